@@ -1,0 +1,134 @@
+"""Pins of the oracle's forward compositing (paper Sec. 3, Eq. 1; Alg. 2 tiled rendering).
+
+Closed forms for one and two Gaussians, brute-force per-pixel depth sorting
+without tiles, tile-shape invariance and the invariants of front-to-back
+compositing."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2506_12727_amd import scenes
+
+Y00 = 0.5 / math.sqrt(math.pi)
+
+
+def _scene(means, scales, quats, opac, rgb):
+    n = len(means)
+    sh = (np.asarray(rgb, np.float64).reshape(n, 1, 3) - 0.5) / Y00
+    return scenes.Scene(np.asarray(means, np.float64), np.asarray(scales, np.float64),
+                        np.asarray(quats, np.float64), np.asarray(opac, np.float64), sh, 0)
+
+
+def _alpha_map(ora, sc, cam, i):
+    """o exp(power) of Gaussian i on every pixel centre, from the oracle's double projection, with
+    the cut test evaluated independently in double precision (power >= max(-4.5, -ln(255 o)))."""
+    m, cov, rgb, _ = ora.project64(sc, [cam], 0)
+    det = cov[i, 0] * cov[i, 2] - cov[i, 1] ** 2
+    a, b, c = cov[i, 2] / det, -cov[i, 1] / det, cov[i, 0] / det
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    dx, dy = xs + 0.5 - m[i, 0], ys + 0.5 - m[i, 1]
+    power = -0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy
+    o = sc.opacities[i]
+    alpha = np.minimum(0.99, o * np.exp(power))
+    keep = power >= max(-4.5, -math.log(255 * o))
+    return np.where(keep, alpha, 0.0), power, max(-4.5, -math.log(255 * o)), rgb[i]
+
+
+def test_single_gaussian_closed_form(ora):
+    cam = scenes.make_camera(48, 40, (0.1, -0.2, -3.0))
+    sc = _scene([[0.05, 0.02, 0.0]], [[0.2, 0.12, 0.08]], [[0.9, 0.1, -0.3, 0.2]], [0.7], [[0.9, 0.4, 0.2]])
+    f = ora.forward(sc, [cam], geom32_mode=False)
+    alpha, power, cut, rgb = _alpha_map(ora, sc, cam, 0)
+    near = np.abs(power - cut) < 1e-5    # cut decided in single precision: skip the knife edge
+    want = rgb[:, None, None] * alpha[None]
+    assert (alpha > 0).sum() > 50
+    assert np.allclose(f["images"][0][:, ~near], want[:, ~near], rtol=1e-12, atol=1e-14)
+    assert np.allclose(f["t_final"][0][~near], (1 - alpha)[~near], rtol=1e-12)
+
+
+def test_two_gaussians_closed_form(ora):
+    cam = scenes.make_camera(40, 40, (0.0, 0.0, -3.0))
+    sc = _scene([[0.0, 0.0, -0.5], [0.03, 0.0, 0.5]], [[0.1] * 3, [0.12] * 3], [[1, 0, 0, 0]] * 2, [0.6, 0.8],
+                [[1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    f = ora.forward(sc, [cam], geom32_mode=False)
+    a1, p1, c1, rgb1 = _alpha_map(ora, sc, cam, 0)   # nearer (z = 2.5)
+    a2, p2, c2, rgb2 = _alpha_map(ora, sc, cam, 1)
+    near = (np.abs(p1 - c1) < 1e-5) | (np.abs(p2 - c2) < 1e-5)
+    want = rgb1[:, None, None] * a1 + rgb2[:, None, None] * a2 * (1 - a1)
+    assert np.allclose(f["images"][0][:, ~near], want[:, ~near], rtol=1e-12, atol=1e-14)
+
+
+def test_brute_force_depth_sort_equals_tiled(ora):
+    sc = scenes.make_scene(3000, 3, log_scale_mean=-3.0)
+    cams = scenes.make_cameras([(61, 47), (32, 32), (50, 70)])
+    ft = ora.forward(sc, cams)
+    fb = ora.forward(sc, cams, brute_force=True)
+    for k in ("images", "t_final", "n_contrib"):
+        for a, b in zip(ft[k], fb[k]):
+            assert np.array_equal(a, b)
+    assert np.array_equal(ft["trace"], fb["trace"])
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (32, 8), (13, 7), (64, 64)])
+def test_tile_shape_invariance(ora, tile):
+    sc = scenes.make_scene(2000, 0, log_scale_mean=-3.0)
+    cams = scenes.make_cameras([(61, 47), (40, 40)])
+    ref = ora.forward(sc, cams, tile=(16, 16))
+    got = ora.forward(sc, cams, tile=tile)
+    for a, b in zip(ref["images"], got["images"]):
+        assert np.array_equal(a, b)
+
+
+def test_compositing_invariants(ora):
+    sc = scenes.make_scene(4000, 0, log_scale_mean=-2.8)
+    cams = scenes.make_cameras([(64, 64), (48, 32)])
+    f = ora.forward(sc, cams)
+    for tf, nc in zip(f["t_final"], f["n_contrib"]):
+        assert np.all(tf >= 1e-4) and np.all(tf <= 1.0)
+        assert np.all(tf[nc == 0] == 1.0)
+    assert (f["t_final"][0] < 0.01).mean() > 0.05   # dense enough to exercise the stop
+    # zero opacity: background only
+    sc0 = scenes.Scene(sc.means, sc.scales, sc.quats, np.zeros_like(sc.opacities), sc.sh, 0)
+    for c in cams:
+        c.bg = np.array([0.2, 0.4, 0.6], np.float32)
+    f0 = ora.forward(sc0, cams)
+    for img in f0["images"]:
+        assert np.allclose(img, np.array([0.2, 0.4, 0.6])[:, None, None], atol=1e-7)
+    # constant colour k: C = k (1 - T_final) + T_final bg
+    k = np.array([0.3, 0.7, 0.1])
+    shk = np.broadcast_to(((k - 0.5) / Y00)[None, None, :], sc.sh.shape).astype(np.float64)
+    sck = scenes.Scene(sc.means, sc.scales, sc.quats, sc.opacities, shk, 0)
+    fk = ora.forward(sck, cams)
+    for img, tf in zip(fk["images"], fk["t_final"]):
+        want = k[:, None, None] * (1 - tf) + tf * np.array([0.2, 0.4, 0.6])[:, None, None]
+        assert np.allclose(img, want, atol=1e-12)
+
+
+def test_gaussians_behind_everything_only_extend_the_walk(ora):
+    """Adding Gaussians strictly behind all others leaves every pixel's front part of the walk
+    unchanged: T_final can only fall, and where none of the new ones is blended the colour and
+    T_final are identical."""
+    sc = scenes.make_scene(1500, 0, log_scale_mean=-3.0)
+    cams = scenes.make_cameras([(48, 48)])
+    f1 = ora.forward(sc, cams)
+    sc2 = scenes.make_scene(1500, 0, log_scale_mean=-3.0, seed=9)
+    fwd = cams[0].R[2].astype(np.float64)
+    m2 = sc2.means.astype(np.float64) + fwd * 10.0     # depths > 11, the first scene's are < 5
+    both = scenes.Scene(np.concatenate([sc.means, m2]), np.concatenate([sc.scales, sc2.scales * 4]),
+                        np.concatenate([sc.quats, sc2.quats]), np.concatenate([sc.opacities, sc2.opacities]),
+                        np.concatenate([sc.sh, sc2.sh]), 0)
+    f2 = ora.forward(both, cams)
+    t1, t2 = f1["t_final"][0], f2["t_final"][0]
+    assert np.all(t2 <= t1)
+    same = f2["n_contrib"][0] == f1["n_contrib"][0]
+    assert (~same).sum() > 100
+    assert np.all(t2[same] == t1[same])
+    assert np.array_equal(f2["images"][0][:, same], f1["images"][0][:, same])
+
+
+def test_gaussian_behind_camera_contributes_nothing(ora):
+    cam = scenes.make_camera(32, 32, (0.0, 0.0, -3.0))
+    sc = _scene([[0.0, 0.0, -4.0]], [[0.5] * 3], [[1, 0, 0, 0]], [0.9], [[1, 1, 1]])
+    f = ora.forward(sc, [cam])
+    assert np.all(f["images"][0] == 0.0) and np.all(f["t_final"][0] == 1.0)
