@@ -1,0 +1,226 @@
+"""Benchmark: multi-view rasterizer training step (forward + loss + backward) on one MI355X.
+
+A step is one pass of the whole hot path over one batch of views: per-view participation and
+projection, the depth and tile sorts, range extraction, the blend forward, the fused loss and its
+image gradient, the blend backward and the preprocessing backward with densification statistics
+when the workload asks for them. Inputs are seeded synthetic scenes resident in HBM before the
+timed region starts.
+
+Prints ONE JSON line. `value` is views/s of the batched path; `one_view_loop` reports the same
+views rendered one view per call; `roofline` is for the kernel that takes the most time, from HIP
+events recorded on the library's stream during the timed region; `cpu_baseline` times the CPU
+oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd views/s, 1M Gaussians, 8-view batch vs 1-view loop; serve p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+# non-packed FP32 vector lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+ALU_PEAK_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# algorithmic lane operations per (pixel, Gaussian) step of the walks
+FWD_OPS_PER_STEP = 18
+BWD_OPS_PER_STEP = 57
+STAGES = ["count", "records", "depth_sort", "emit", "tile_sort", "ranges", "blend_fwd", "loss", "blend_bwd",
+          "preprocess_bwd"]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uneven_1m_8view")
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--no-loop", action="store_true", help="skip the one-view-per-call comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-views", type=int, default=1, help="views of the workload in the CPU sample")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path runs on a single "
+              "MI355X; see DESIGN.md for how it would shard across GPUs).", file=sys.stderr)
+        sys.exit(2)
+    import ctypes as C
+
+    import numpy as np
+    import torch
+
+    from paper_2506_12727_amd import _lib as L
+    from paper_2506_12727_amd import scenes
+    from paper_2506_12727_amd.raster import GaussianTensors, Rasterizer
+
+    torch.cuda.set_device(0)
+    wl = scenes.WORKLOADS[args.workload]
+    tile = tuple(int(x) for x in args.tile.split("x"))
+    scene = wl.scene()
+    cams = wl.cameras()
+    B = len(cams)
+    g = GaussianTensors.from_scene(scene)
+    tg = [torch.from_numpy(t).cuda() for t in scenes.make_targets(cams)]
+    rast = Rasterizer(tile)
+    lib = L.lib()
+    imgs = [torch.empty((3, c.height, c.width), device="cuda") for c in cams]
+    dl = [torch.empty_like(t) for t in imgs]
+    loss = torch.empty(1, device="cuda")
+    grads = dict(means=torch.empty_like(g.means), scales=torch.empty_like(g.scales), quats=torch.empty_like(g.quats),
+                 opacities=torch.empty_like(g.opacities), sh=torch.empty_like(g.sh))
+    dz = None
+    if wl.densify:
+        dz = dict(e1=torch.zeros(g.P, device="cuda"), e2=torch.zeros(g.P, device="cuda"),
+                  count=torch.zeros(g.P, dtype=torch.int32, device="cuda"))
+
+    def step(views, images, dls):
+        _, fr = rast.forward(g, views, images=images)
+        rast.loss(views, images, [tg[cams.index(v)] for v in views] if len(views) != B else tg, wl.w_l1,
+                  wl.w_dssim, out=loss, grads=dls)
+        rast.backward(g, fr, dls, densify=dz, grads=grads)
+        return fr
+
+    def batched():
+        fr = step(cams, imgs, dl)
+        rast.release(fr)
+
+    def loop():
+        for v in range(B):
+            fr = step([cams[v]], [imgs[v]], [dl[v]])
+            rast.release(fr)
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    lib.mvgs_profile_reset(rast.ctx)
+    lib.mvgs_profile_enable(rast.ctx, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batched()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib.mvgs_profile_enable(rast.ctx, 0)
+    ms = (C.c_double * L.MVGS_STAGE_COUNT)()
+    calls = (C.c_int64 * L.MVGS_STAGE_COUNT)()
+    L.check(lib.mvgs_profile_read(rast.ctx, ms, calls), rast.ctx)
+    stage_ms = {STAGES[i]: ms[i] / max(calls[i], 1) for i in range(L.MVGS_STAGE_COUNT)}
+    elapsed = t1 - t0
+    ms_step = 1e3 * elapsed / args.steps
+    views_s = B * args.steps / elapsed
+
+    # frame sizes and walk work of one batched forward (outside the timed region)
+    _, fr = rast.forward(g, cams, images=imgs)
+    info = fr.info()
+    work = torch.zeros(1, dtype=torch.int64, device="cuda")
+    L.check(lib.mvgs_frame_work(rast.ctx, C.c_void_p(torch.cuda.current_stream().cuda_stream), fr.handle,
+                                work.data_ptr()), rast.ctx)
+    torch.cuda.synchronize()
+    steps_walk = int(work.item())
+    rast.release(fr)
+
+    loop_res = None
+    if not args.no_loop:
+        for _ in range(max(1, args.warmup)):
+            loop()
+        torch.cuda.synchronize()
+        lsteps = max(3, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(lsteps):
+            loop()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lv = B * lsteps / (t1 - t0)
+        loop_res = {"value": lv, "unit": "views/s", "ms_per_step": 1e3 * (t1 - t0) / lsteps,
+                    "batched_speedup": views_s / lv}
+
+    # roofline of the dominant kernel
+    dom = max(("blend_fwd", "blend_bwd", "tile_sort", "depth_sort", "emit", "records", "preprocess_bwd"),
+              key=lambda k: stage_ms[k])
+    roof = roofline(dom, stage_ms[dom], info, steps_walk, g, B, cams)
+
+    cpu = None if args.no_cpu else cpu_baseline(scene, cams, tg, wl, tile, args.cpu_views)
+    total_px = sum(c.width * c.height for c in cams)
+    out = {
+        "metric": METRIC,
+        "value": views_s,
+        "unit": "views/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "gaussians": g.P, "sh_degree": wl.sh_degree, "views": B,
+                   "sizes": [[c.width, c.height] for c in cams], "tile": list(tile),
+                   "loss": {"w_l1": wl.w_l1, "w_dssim": wl.w_dssim}, "densify": wl.densify},
+        "gaussian_pixels_per_s": g.P * total_px * args.steps / elapsed,
+        "one_view_loop": loop_res,
+        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "frame": {"records": info["records"], "pairs": info["pairs"], "tiles": info["tiles"],
+                  "walk_steps": steps_walk},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def roofline(stage, ms, info, steps_walk, g, B, cams):
+    """Achieved vs peak for one stage; algorithmic bytes or lane operations per launch."""
+    K, V = info["pairs"], info["records"]
+    npx = sum(c.width * c.height for c in cams)
+    sec = ms / 1e3
+    if stage in ("blend_fwd", "blend_bwd"):
+        ops = steps_walk * (FWD_OPS_PER_STEP if stage == "blend_fwd" else BWD_OPS_PER_STEP)
+        ach = ops / sec / 1e12
+        return {"kernel": stage, "bound": "alu", "achieved": ach, "peak": ALU_PEAK_TLANEOPS, "unit": "Tlane-op/s",
+                "frac": ach / ALU_PEAK_TLANEOPS, "traffic": None,
+                "units": {"walk_steps": steps_walk, "ops_per_step": FWD_OPS_PER_STEP if stage == "blend_fwd"
+                          else BWD_OPS_PER_STEP}}
+    # HBM-bound stages: one read and one write of what the stage must move
+    per = {
+        "tile_sort": 2 * 16.0 * K,              # two 8-bit passes, each reads and writes 8 B per pair
+        "depth_sort": 4 * 16.0 * V,
+        "emit": 8.0 * K + 12.0 * V,
+        "records": (56 + 4 * 3 * (g.sh_degree + 1) ** 2) * g.P + 80.0 * V,
+        "preprocess_bwd": (56 + 12 * (g.sh_degree + 1) ** 2) * g.P + 112.0 * V,
+    }
+    byts = per[stage]
+    ach = byts / sec / 1e9
+    return {"kernel": stage, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "units": {"bytes": byts}}
+
+
+def cpu_baseline(scene, cams, tg, wl, tile, nviews):
+    """The oracle (FP64, OpenMP) on a bounded sample: the first `nviews` views of the workload
+    with the full scene, forward + loss + backward. Value in views/s."""
+    import numpy as np
+
+    import oracle
+    sub = cams[:nviews]
+    tgs = [t.cpu().numpy() for t in tg[:nviews]]
+    t0 = time.perf_counter()
+    f = oracle.forward(scene, sub, tile)
+    _, gl = oracle.loss(sub, f["images"], tgs, wl.w_l1, wl.w_dssim)
+    oracle.backward(scene, sub, gl, tile)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {"value": nviews / dt, "unit": "views/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nviews} view(s) {sub[0].width}x{sub[0].height} of {wl.name}, all {scene.P} Gaussians, "
+                      f"forward+loss+backward, {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * mvgs: multi-view differentiable Gaussian-splatting rasterizer for MI355X (gfx950).
+ *
+ * C ABI of libmvgs.so. Every call enqueues work on the caller's HIP stream and
+ * returns without waiting, except where a call says it synchronizes. All
+ * device buffers are owned by the caller unless stated otherwise; the library
+ * owns its frames and workspace. Arguments are validated before any HIP call;
+ * an invalid call returns MVGS_EINVAL and touches no device state.
+ *
+ * Paper: "Efficient multi-view training for 3D Gaussian Splatting".
+ *   Sec. 3 (Preliminary): a Gaussian has mean mu, scale S, rotation R, colour c
+ *     and opacity o; Sigma = R S S^T R^T is projected to a 2D mean mu' and
+ *     covariance Sigma'; Eq. 1 alpha-composites the depth-sorted Gaussians
+ *     responsible for each pixel; the rasterizer preprocesses (cull, project,
+ *     organise) and renders tile by tile.
+ *   Appendix "Rasterization in multi-view training": per-view participation is
+ *     decided before memory is sized; projected Gaussians are duplicated per
+ *     covered tile and sorted by a 64-bit key holding tile, view and depth; one
+ *     block renders each (tile, view).
+ *   Sec. 5.2, Eqs. 13-14: densification statistics accumulated per Gaussian
+ *     from positional gradients taken in each view's own screen space.
+ *
+ * Conventions (the paper leaves them open): x_c = R x_w + t with camera axes
+ * x right, y down, z forward; pixel (x, y) has its centre at (x+0.5, y+0.5);
+ * parameters arrive activated (scales > 0, opacities in (0,1), quaternions
+ * (w,x,y,z) of any non-zero length); colour is real spherical harmonics of
+ * degree <= 3 on the direction camera centre -> mean, plus 0.5, clamped at 0;
+ * near plane z > 0.2; +0.3 px^2 on the 2D covariance diagonal; a Gaussian
+ * covers a pixel iff power >= max(-4.5, -ln(255 o)) (3-sigma ellipse and
+ * alpha >= 1/255); alpha = min(0.99, o exp(power)); compositing stops before
+ * the transmittance would fall below 1e-4; background added as T_final * bg.
+ */
+#ifndef MVGS_H
+#define MVGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. 0 is success; failures are negative. */
+#define MVGS_OK 0
+#define MVGS_EINVAL (-1)    /* invalid argument; nothing was enqueued */
+#define MVGS_ENOMEM (-2)    /* device or host allocation failed */
+#define MVGS_ECAPACITY (-3) /* a size limit of the format was exceeded (see mvgs_forward) */
+#define MVGS_EHIP (-4)      /* a HIP runtime call failed; mvgs_last_error has the text */
+
+#define MVGS_MAX_VIEWS 65535
+#define MVGS_MAX_TILES_PER_VIEW 65536
+
+typedef struct mvgs_context mvgs_context;
+typedef struct mvgs_frame mvgs_frame;
+
+/* One pinhole camera (host memory). R row-major world->camera rotation, t its
+ * translation, fx/fy/cx/cy in pixels, bg the background colour. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    float bg[3];
+} mvgs_camera;
+
+/* Gaussian parameters, all float32 device pointers, row-major and contiguous:
+ * means [P,3], scales [P,3], quats [P,4] (w,x,y,z), opacities [P],
+ * sh [P,(sh_degree+1)^2,3] (coefficient-major, RGB innermost). */
+typedef struct {
+    int64_t P;
+    int32_t sh_degree;
+    const float* means;
+    const float* scales;
+    const float* quats;
+    const float* opacities;
+    const float* sh;
+} mvgs_gaussians;
+
+/* Parameter gradients (device, same shapes as mvgs_gaussians), overwritten. */
+typedef struct {
+    float* means;
+    float* scales;
+    float* quats;
+    float* opacities;
+    float* sh;
+} mvgs_grads;
+
+/* Densification statistics (device, [P] each), accumulated with +=:
+ * e1 += sum_v sum_{p in v} ||dL_p/dmu'_ndc||, e2 += sum_v ||sum_{p in v} dL_p/dmu'_ndc||,
+ * count += number of views the Gaussian took part in (Sec. 5.2, Eqs. 13-14; the
+ * positional gradient is taken in normalised device coordinates, i.e. the pixel
+ * gradient times (W/2, H/2)). */
+typedef struct {
+    float* e1;
+    float* e2;
+    int32_t* count;
+} mvgs_densify;
+
+/* Context options. tile_w, tile_h in {8, 16, 32} (0 selects 16). */
+typedef struct {
+    int32_t tile_w;
+    int32_t tile_h;
+    int32_t reserved[6];
+} mvgs_options;
+
+/* Create a context on the current HIP device. `opt` may be NULL (defaults).
+ * A context's workspace serves one stream at a time: calls on one context must
+ * not overlap on different streams. Returns MVGS_EINVAL for a bad tile shape. */
+int mvgs_create(mvgs_context** out, const mvgs_options* opt);
+
+/* Destroy a context and every frame it still owns (waits for the device). */
+void mvgs_destroy(mvgs_context* ctx);
+
+/* Forward pass over a batch of B views (paper Sec. 3 and the multi-view
+ * appendix): per-view participation and projection, duplication per covered
+ * tile, sort by (view, tile, depth) with ties by Gaussian index, per-(view,
+ * tile) ranges, and front-to-back blending of every pixel of every view in one
+ * launch per stage.
+ *   cams    host array of B cameras, 1 <= B <= 65535; each view at most
+ *           65536 tiles; width, height >= 1; fx, fy > 0.
+ *   images  host array of B device pointers; view v receives float32
+ *           [3, height_v, width_v] (planar RGB).
+ *   frame   receives a new frame that keeps what the backward needs (records,
+ *           sorted lists, ranges, final transmittance, last contributor per
+ *           pixel); release it with mvgs_frame_release.
+ * Synchronizes the stream once to read the number of (Gaussian, tile) pairs,
+ * which sizes the sort. Returns MVGS_ECAPACITY if that number reaches 2^32. */
+int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_camera* cams, int32_t B,
+                 float* const* images, mvgs_frame** frame);
+
+/* Photometric loss (paper Sec. 3; D-SSIM of Sec. 5.1.2, Eqs. 7-10):
+ *   L = w_l1 * mean|I - T| + w_dssim * (1 - mean SSIM(I, T))
+ * means over every (view, channel, row, column); SSIM with an 11x11 Gaussian
+ * window (sigma 1.5, normalised to sum 1, zero outside the image), C1 = 0.01^2,
+ * C2 = 0.03^2. Writes the scalar loss to loss_dev (device float) and dL/dI to
+ * dl_dimages (B device pointers, [3,H,W] each; overwritten). images and
+ * targets are B device pointers of the same shapes. */
+int mvgs_loss(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t B, const float* const* images,
+              const float* const* targets, float w_l1, float w_dssim, float* loss_dev, float* const* dl_dimages);
+
+/* Backward pass: from dL/dimage (B device pointers [3,H,W]) to parameter
+ * gradients (overwritten) and, when `densify` is not NULL, the densification
+ * statistics (accumulated). `g` must hold the same parameters the frame was
+ * rendered from. Blend state is recomputed from the frame's final
+ * transmittance and last contributor, not stored per pixel and Gaussian. */
+int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_frame* frame,
+                  const float* const* dl_dimages, mvgs_grads* grads, mvgs_densify* densify);
+
+/* Return a frame's memory to its context. The frame must not be in use by
+ * work still pending on a stream other than the one it was created on. */
+int mvgs_frame_release(mvgs_context* ctx, mvgs_frame* frame);
+
+/* Sizes of a frame: participating (view, Gaussian) records, (Gaussian, tile)
+ * pairs and tiles over all views. Any pointer may be NULL. */
+int mvgs_frame_info(const mvgs_frame* frame, int64_t* n_records, int64_t* n_pairs, int64_t* n_tiles);
+
+/* Test hook: copy a frame's binning to caller device buffers: keys [n_pairs]
+ * (view<<48 | tile<<32 | depth bits), values [n_pairs] (Gaussian index), and
+ * ranges [n_tiles][2] ([start,end) per (view, tile), view-major, row-major
+ * tiles; empty tiles give [0,0)). Any output may be NULL. */
+int mvgs_export_binning(mvgs_context* ctx, void* stream, const mvgs_frame* frame, uint64_t* keys,
+                        uint32_t* values, uint32_t* ranges);
+
+/* Test hook: copy each view's final transmittance to B device pointers
+ * ([H,W] float32 each). */
+int mvgs_export_transmittance(mvgs_context* ctx, void* stream, const mvgs_frame* frame, float* const* t_final);
+
+/* Stage timing (opt-in). When enabled, every call records a pair of HIP events on its stream
+ * around each stage below; mvgs_profile_read waits for them and adds their elapsed times.
+ * Stages: 0 count (participation, record/pair totals), 1 records (projection + SH),
+ * 2 depth_sort, 3 emit (pair emission in depth order), 4 tile_sort, 5 ranges,
+ * 6 blend_fwd, 7 loss, 8 blend_bwd, 9 preprocess_bwd. */
+#define MVGS_STAGE_COUNT 10
+int mvgs_profile_enable(mvgs_context* ctx, int enable);
+/* Accumulated milliseconds and launch counts per stage since the last reset (host arrays of
+ * MVGS_STAGE_COUNT; either may be NULL). Waits for the recorded events. */
+int mvgs_profile_read(mvgs_context* ctx, double* ms, int64_t* calls);
+int mvgs_profile_reset(mvgs_context* ctx);
+const char* mvgs_stage_name(int stage);
+
+/* Work of a frame's front-to-back walks: writes to steps_dev (device uint64) the sum over all
+ * pixels of the number of list entries from the start of the pixel's (view, tile) list up to its
+ * last blended Gaussian -- the (pixel, Gaussian) steps the reverse walk of the backward takes and
+ * a lower bound of the forward's (Alg. 2: each thread walks its tile's sorted list). */
+int mvgs_frame_work(mvgs_context* ctx, void* stream, const mvgs_frame* frame, uint64_t* steps_dev);
+
+/* Human-readable text of a status code (static storage). */
+const char* mvgs_status_string(int status);
+
+/* Text of the last error recorded on a context (empty if none). */
+const char* mvgs_last_error(const mvgs_context* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MVGS_H */

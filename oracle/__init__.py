@@ -60,6 +60,8 @@ def lib():
         L.ora_forward.argtypes = [vp, vp, i32, i32, d, vp, vp, vp, vp, vp]
         L.ora_backward.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.ora_project64.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+        L.ora_render_pixels.argtypes = [vp, vp, i32, i32, d, i64, vp, vp, vp, vp, vp]
+        L.ora_count_pairs.argtypes = [vp, vp, vp, vp]
         L.ora_loss.argtypes = [vp, vp, vp, d, d, vp, vp]
         L.ora_ssim_map.argtypes = [i32, i32, vp, vp, vp]
         L.ora_sh_basis.argtypes = [C.c_int, vp, vp, vp]
@@ -208,3 +210,25 @@ def sh_basis(degree: int, d) -> tuple:
     dY = np.zeros((K, 3))
     lib().ora_sh_basis(degree, _ptr(d), _ptr(Y), _ptr(dY))
     return Y, dY
+
+
+def render_pixels(scene, cams, v: int, xs, ys, geom32_mode=True, margin=1e-4):
+    """Colour [n,3], final transmittance [n] and flags [n] of chosen pixels of view v, each by a walk
+    over every participating Gaussian in depth order (usable at any scene size)."""
+    s, c = OScene(scene), OCams(cams)
+    xs = np.ascontiguousarray(xs, np.int32); ys = np.ascontiguousarray(ys, np.int32)
+    n = len(xs)
+    rgb = np.zeros((n, 3)); tf = np.zeros(n); fl = np.zeros(n, np.uint8)
+    ss, cs = s.struct(), c.struct()
+    lib().ora_render_pixels(C.byref(ss), C.byref(cs), v, int(geom32_mode), float(margin), n, _ptr(xs), _ptr(ys),
+                            _ptr(rgb), _ptr(tf), _ptr(fl))
+    return rgb, tf, fl
+
+
+def count_pairs(scene, cams, tile=(16, 16)):
+    """(participating records, (Gaussian, tile) pairs) over the whole batch, without sorting."""
+    s, c = OScene(scene), OCams(cams, tile)
+    r = np.zeros(1, np.int64); p = np.zeros(1, np.int64)
+    ss, cs = s.struct(), c.struct()
+    lib().ora_count_pairs(C.byref(ss), C.byref(cs), _ptr(r), _ptr(p))
+    return int(r[0]), int(p[0])

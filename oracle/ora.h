@@ -97,6 +97,9 @@ int ora_backward(const ora_scene* s, const ora_cams* c, int32_t geom32_mode,
                  const double* const* dl_dimg, double* g_means, double* g_scales, double* g_quats,
                  double* g_opac, double* g_sh, double* e1, double* e2, int32_t* count,
                  double* g_mean2d /* [B][P][2] or NULL */, double* e_old /* [P] or NULL */);
+int ora_render_pixels(const ora_scene* s, const ora_cams* c, int32_t v, int32_t geom32_mode, double margin,
+                      int64_t n, const int32_t* xs, const int32_t* ys, double* rgb, double* t_final, uint8_t* flags);
+int ora_count_pairs(const ora_scene* s, const ora_cams* c, int64_t* records, int64_t* pairs);
 int ora_project64(const ora_scene* s, const ora_cams* c, int32_t v, double* mean2d, double* cov2d,
                   double* rgb, double* depth);
 

@@ -709,3 +709,66 @@ int ora_backward(const ora_scene* s, const ora_cams* c, int32_t geom32_mode, con
     free(pg);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* sampled pixels at any size                                                */
+/* ------------------------------------------------------------------------- */
+
+/* Colour, final transmittance and flags of n chosen pixels of view v, each by walking every
+ * participating Gaussian of the view in (depth bits, g) order (no tiles), as the brute-force
+ * path does; used where rendering the whole batch would take too long. */
+int ora_render_pixels(const ora_scene* s, const ora_cams* c, int32_t v, int32_t geom32_mode, double margin,
+                      int64_t n, const int32_t* xs, const int32_t* ys, double* rgb, double* t_final, uint8_t* flags)
+{
+    if (v < 0 || v >= c->B) return -1;
+    const int64_t P = s->P;
+    ora_g32* g32 = (ora_g32*)malloc(sizeof(ora_g32) * (size_t)(P > 0 ? P : 1));
+    pix_g* pg = (pix_g*)malloc(sizeof(pix_g) * (size_t)(P > 0 ? P : 1));
+    prepare_view(s, c, v, geom32_mode, g32, pg);
+    int64_t n_order = 0;
+    uint32_t* order = depth_order(g32, P, &n_order);
+    const double* bg = c->bg + 3 * v;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < n; ++k) {
+        const int x = xs[k], y = ys[k];
+        double T = 1.0, C[3] = {0, 0, 0};
+        int flag = 0;
+        for (int64_t i = 0; i < n_order; ++i) {
+            const uint32_t g = order[i];
+            step_info st;
+            int r = walk_step(&g32[g], &pg[g], x, y, T, margin, &flag, &st);
+            if (r == 0) continue;
+            if (r == 2) break;
+            for (int q = 0; q < 3; ++q) C[q] += pg[g].rgb[q] * st.alpha * T;
+            T = T * (1.0 - st.alpha);
+        }
+        for (int q = 0; q < 3; ++q) rgb[3 * k + q] = C[q] + T * bg[q];
+        t_final[k] = T;
+        flags[k] = (uint8_t)flag;
+    }
+    free(order);
+    free(g32);
+    free(pg);
+    return 0;
+}
+
+/* Number of (Gaussian, tile) pairs of every view and of participating (view, Gaussian) records,
+ * counted from the decision geometry without sorting. */
+int ora_count_pairs(const ora_scene* s, const ora_cams* c, int64_t* records, int64_t* pairs)
+{
+    ora_g32* g32 = (ora_g32*)malloc(sizeof(ora_g32) * (size_t)(s->P > 0 ? s->P : 1));
+    int64_t nr = 0, np = 0;
+    for (int v = 0; v < c->B; ++v) {
+        ora_geom32_view(s, c, v, g32);
+        for (int64_t g = 0; g < s->P; ++g) {
+            const ora_g32* q = &g32[g];
+            if (!q->participates) continue;
+            nr += 1;
+            np += (int64_t)(q->x1 / c->tile_w - q->x0 / c->tile_w + 1) * (q->y1 / c->tile_h - q->y0 / c->tile_h + 1);
+        }
+    }
+    free(g32);
+    *records = nr;
+    *pairs = np;
+    return 0;
+}

@@ -1,0 +1,703 @@
+// Host runtime of libmvgs: contexts, frames, argument validation, workspace and the
+// launch sequence of each public call (see include/mvgs.h for the contract).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mvgs.h"
+#include "mvgs_kernels.h"
+
+using namespace mvgs;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+// Grow-only device buffer. Growing frees the old allocation (hipFree waits for the device).
+hipError_t ensure(DevBuf& b, size_t bytes) {
+    if (bytes <= b.cap && b.p) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t n = std::max<size_t>(bytes, 256);
+    n = std::max(n, b.cap + b.cap / 4);
+    n = (n + 4095) & ~(size_t)4095;
+    hipError_t e = hipMalloc(&b.p, n);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return e;
+    }
+    b.cap = n;
+    return hipSuccess;
+}
+
+void release(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+template <typename T>
+T* as(DevBuf& b) { return reinterpret_cast<T*>(b.p); }
+
+int bits_for(uint64_t n) {  // bits needed to hold values 0..n-1
+    int b = 0;
+    while (b < 64 && ((uint64_t)1 << b) < n) ++b;
+    return b;
+}
+
+// Pinned host staging with device twins, used round-robin; a slot is reused only after
+// the event recorded behind its last consumer has completed.
+struct UploadRing {
+    static constexpr int kSlots = 16;
+    struct Slot {
+        void* host = nullptr;
+        DevBuf dev;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+    };
+    Slot slots[kSlots];
+    int next = 0;
+    std::vector<int> used;
+
+    hipError_t put(const void* src, size_t bytes, hipStream_t s, void** dev_out) {
+        Slot& sl = slots[next];
+        const int idx = next;
+        next = (next + 1) % kSlots;
+        if (sl.pending) {
+            hipError_t e = hipEventSynchronize(sl.ev);
+            if (e != hipSuccess) return e;
+            sl.pending = false;
+        }
+        if (!sl.ev) {
+            hipError_t e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        if (sl.cap < bytes) {
+            if (sl.host) (void)hipHostFree(sl.host);
+            sl.host = nullptr;
+            size_t n = std::max<size_t>(bytes, 4096);
+            hipError_t e = hipHostMalloc(&sl.host, n, hipHostMallocDefault);
+            if (e != hipSuccess) return e;
+            sl.cap = n;
+        }
+        hipError_t e = ensure(sl.dev, bytes);
+        if (e != hipSuccess) return e;
+        memcpy(sl.host, src, bytes);
+        e = hipMemcpyAsync(sl.dev.p, sl.host, bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return e;
+        used.push_back(idx);
+        *dev_out = sl.dev.p;
+        return hipSuccess;
+    }
+    // record completion behind everything enqueued so far on `s` for the slots used by this call
+    hipError_t seal(hipStream_t s) {
+        hipError_t r = hipSuccess;
+        for (int idx : used) {
+            hipError_t e = hipEventRecord(slots[idx].ev, s);
+            if (e != hipSuccess) r = e;
+            else slots[idx].pending = true;
+        }
+        used.clear();
+        return r;
+    }
+    void destroy() {
+        for (auto& sl : slots) {
+            if (sl.pending) (void)hipEventSynchronize(sl.ev);
+            if (sl.ev) (void)hipEventDestroy(sl.ev);
+            if (sl.host) (void)hipHostFree(sl.host);
+            release(sl.dev);
+        }
+    }
+};
+
+}  // namespace
+
+struct mvgs_frame {
+    mvgs_context* ctx = nullptr;
+    bool in_use = false;
+    int B = 0;
+    std::vector<DevCam> hcams;
+    uint32_t n_tiles = 0, n_pixels = 0;
+    int64_t P = 0;
+    int sh_degree = 0;
+    uint32_t V = 0;
+    uint64_t K = 0;
+    int final_buf = 0;
+    DevBuf cams, recs, rec_off, keys[2], vals[2], ranges, t_final, n_last;
+};
+
+struct mvgs_context {
+    int device = 0;
+    int tw = 16, th = 16;
+    std::string err;
+    std::vector<mvgs_frame*> frames;
+    DevBuf nrec, ntiles, totals, scan_scratch, depth_key[2], rec_vals[2], tile_rect, pair_counts, pair_off;
+    DevBuf sort_scratch, acc, loss_scratch, ssim_maps;
+    uint64_t* pinned_totals = nullptr;
+    bool device_used = false;
+    UploadRing ring;
+
+    // opt-in stage timing
+    struct Mark {
+        int stage;
+        hipEvent_t a, b;
+    };
+    bool prof = false;
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> ev_pool;
+    double prof_ms[MVGS_STAGE_COUNT] = {0};
+    int64_t prof_calls[MVGS_STAGE_COUNT] = {0};
+    DevBuf work;
+
+    hipEvent_t take_event() {
+        if (!ev_pool.empty()) {
+            hipEvent_t e = ev_pool.back();
+            ev_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    // returns a mark index (or -1 when profiling is off)
+    int stage_begin(int stage, hipStream_t s) {
+        if (!prof) return -1;
+        Mark m{stage, take_event(), take_event()};
+        if (!m.a || !m.b || hipEventRecord(m.a, s) != hipSuccess) return -1;
+        marks.push_back(m);
+        return (int)marks.size() - 1;
+    }
+    void stage_end(int idx, hipStream_t s) {
+        if (idx >= 0) (void)hipEventRecord(marks[idx].b, s);
+    }
+
+    // first device use: remember the device, allocate the pinned readback slot
+    hipError_t bind_device() {
+        if (device_used) return hipSuccess;
+        hipError_t e = hipGetDevice(&device);
+        if (e != hipSuccess) return e;
+        e = hipHostMalloc((void**)&pinned_totals, 4 * sizeof(uint64_t), hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        device_used = true;
+        return hipSuccess;
+    }
+
+    int fail(int code, const char* fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+    int hip_fail(hipError_t e, const char* what) {
+        return fail(e == hipErrorOutOfMemory ? MVGS_ENOMEM : MVGS_EHIP, "%s: %s", what, hipGetErrorString(e));
+    }
+};
+
+#define HIPCHK(ctx, call)                                     \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return (ctx)->hip_fail(e_, #call); \
+    } while (0)
+
+#define LAUNCHCHK(ctx, what)                                  \
+    do {                                                      \
+        hipError_t e_ = hipGetLastError();                    \
+        if (e_ != hipSuccess) return (ctx)->hip_fail(e_, what); \
+    } while (0)
+
+namespace {
+
+int validate_cams(mvgs_context* ctx, const mvgs_camera* cams, int32_t B, int tw, int th, uint32_t* n_tiles,
+                  uint32_t* n_pixels) {
+    if (!cams) return ctx->fail(MVGS_EINVAL, "cams is NULL");
+    if (B < 1 || B > MVGS_MAX_VIEWS) return ctx->fail(MVGS_EINVAL, "B=%d outside [1, %d]", B, MVGS_MAX_VIEWS);
+    uint64_t tiles = 0, pix = 0;
+    for (int v = 0; v < B; ++v) {
+        const mvgs_camera& c = cams[v];
+        if (c.width < 1 || c.height < 1 || c.width > 65535 || c.height > 65535)
+            return ctx->fail(MVGS_EINVAL, "view %d: size %dx%d outside [1, 65535]", v, c.width, c.height);
+        if (!(c.fx > 0.0f) || !(c.fy > 0.0f) || !std::isfinite(c.fx) || !std::isfinite(c.fy))
+            return ctx->fail(MVGS_EINVAL, "view %d: focal lengths must be finite and > 0", v);
+        const uint64_t t = (uint64_t)((c.width + tw - 1) / tw) * (uint64_t)((c.height + th - 1) / th);
+        if (t > MVGS_MAX_TILES_PER_VIEW)
+            return ctx->fail(MVGS_EINVAL, "view %d: %llu tiles exceed %d", v, (unsigned long long)t,
+                             MVGS_MAX_TILES_PER_VIEW);
+        tiles += t;
+        pix += (uint64_t)c.width * c.height;
+    }
+    if (pix >= (1ull << 32)) return ctx->fail(MVGS_EINVAL, "total pixels %llu reach 2^32", (unsigned long long)pix);
+    if (tiles >= (1ull << 32)) return ctx->fail(MVGS_EINVAL, "total tiles reach 2^32");
+    *n_tiles = (uint32_t)tiles;
+    *n_pixels = (uint32_t)pix;
+    return MVGS_OK;
+}
+
+int validate_gaussians(mvgs_context* ctx, const mvgs_gaussians* g) {
+    if (!g) return ctx->fail(MVGS_EINVAL, "gaussians is NULL");
+    if (g->P < 0 || g->P >= (1ll << 31)) return ctx->fail(MVGS_EINVAL, "P=%lld outside [0, 2^31)", (long long)g->P);
+    if (g->sh_degree < 0 || g->sh_degree > 3) return ctx->fail(MVGS_EINVAL, "sh_degree=%d outside [0, 3]", g->sh_degree);
+    if (g->P > 0 && (!g->means || !g->scales || !g->quats || !g->opacities || !g->sh))
+        return ctx->fail(MVGS_EINVAL, "a Gaussian parameter pointer is NULL");
+    return MVGS_OK;
+}
+
+GaussianArgs gargs(const mvgs_gaussians* g) {
+    GaussianArgs a;
+    a.means = g->means;
+    a.scales = g->scales;
+    a.quats = g->quats;
+    a.opac = g->opacities;
+    a.sh = g->sh;
+    a.P = g->P;
+    a.sh_degree = g->sh_degree;
+    return a;
+}
+
+void build_cams(const mvgs_camera* cams, int B, int tw, int th, std::vector<DevCam>& out) {
+    out.resize(B);
+    uint32_t tb = 0, pb = 0;
+    for (int v = 0; v < B; ++v) {
+        const mvgs_camera& c = cams[v];
+        DevCam& d = out[v];
+        memcpy(d.R, c.R, sizeof(d.R));
+        memcpy(d.t, c.t, sizeof(d.t));
+        d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+        memcpy(d.bg, c.bg, sizeof(d.bg));
+        for (int i = 0; i < 3; ++i) {
+            const double p = -((double)c.R[i] * c.t[0] + (double)c.R[3 + i] * c.t[1] + (double)c.R[6 + i] * c.t[2]);
+            d.campos[i] = (float)p;
+        }
+        d.W = c.width;
+        d.H = c.height;
+        d.tiles_x = (c.width + tw - 1) / tw;
+        d.tiles_y = (c.height + th - 1) / th;
+        d.tile_base = tb;
+        d.pix_base = pb;
+        tb += (uint32_t)(d.tiles_x * d.tiles_y);
+        pb += (uint32_t)(c.width * c.height);
+    }
+}
+
+mvgs_frame* acquire_frame(mvgs_context* ctx) {
+    for (mvgs_frame* f : ctx->frames)
+        if (!f->in_use) {
+            f->in_use = true;
+            return f;
+        }
+    mvgs_frame* f = new (std::nothrow) mvgs_frame();
+    if (!f) return nullptr;
+    f->ctx = ctx;
+    f->in_use = true;
+    ctx->frames.push_back(f);
+    return f;
+}
+
+void free_frame(mvgs_frame* f) {
+    DevBuf* bufs[] = {&f->cams, &f->recs, &f->rec_off, &f->keys[0], &f->keys[1], &f->vals[0], &f->vals[1],
+                      &f->ranges, &f->t_final, &f->n_last};
+    for (DevBuf* b : bufs) release(*b);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mvgs_status_string(int status) {
+    switch (status) {
+        case MVGS_OK: return "ok";
+        case MVGS_EINVAL: return "invalid argument";
+        case MVGS_ENOMEM: return "out of memory";
+        case MVGS_ECAPACITY: return "size limit exceeded";
+        case MVGS_EHIP: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+const char* mvgs_last_error(const mvgs_context* ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+
+int mvgs_create(mvgs_context** out, const mvgs_options* opt) {
+    if (!out) return MVGS_EINVAL;
+    *out = nullptr;
+    int tw = 16, th = 16;
+    if (opt) {
+        if (opt->tile_w) tw = opt->tile_w;
+        if (opt->tile_h) th = opt->tile_h;
+    }
+    if (!blend_supported(tw, th)) return MVGS_EINVAL;
+    mvgs_context* ctx = new (std::nothrow) mvgs_context();
+    if (!ctx) return MVGS_ENOMEM;
+    ctx->tw = tw;
+    ctx->th = th;
+    // no HIP call here: device resources are created by the first call that needs them
+    *out = ctx;
+    return MVGS_OK;
+}
+
+void mvgs_destroy(mvgs_context* ctx) {
+    if (!ctx) return;
+    if (ctx->device_used) (void)hipDeviceSynchronize();
+    for (mvgs_frame* f : ctx->frames) {
+        free_frame(f);
+        delete f;
+    }
+    DevBuf* bufs[] = {&ctx->nrec, &ctx->ntiles, &ctx->totals, &ctx->scan_scratch, &ctx->depth_key[0],
+                      &ctx->depth_key[1], &ctx->rec_vals[0], &ctx->rec_vals[1], &ctx->tile_rect,
+                      &ctx->pair_counts, &ctx->pair_off, &ctx->sort_scratch, &ctx->acc, &ctx->loss_scratch,
+                      &ctx->ssim_maps};
+    for (DevBuf* b : bufs) release(*b);
+    ctx->ring.destroy();
+    for (auto& m : ctx->marks) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    release(ctx->work);
+    if (ctx->pinned_totals) (void)hipHostFree(ctx->pinned_totals);
+    delete ctx;
+}
+
+int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_camera* cams, int32_t B,
+                 float* const* images, mvgs_frame** frame) {
+    if (!ctx) return MVGS_EINVAL;
+    if (!frame) return ctx->fail(MVGS_EINVAL, "frame output is NULL");
+    *frame = nullptr;
+    int st = validate_gaussians(ctx, g);
+    if (st) return st;
+    uint32_t n_tiles = 0, n_pixels = 0;
+    st = validate_cams(ctx, cams, B, ctx->tw, ctx->th, &n_tiles, &n_pixels);
+    if (st) return st;
+    if (!images) return ctx->fail(MVGS_EINVAL, "images is NULL");
+    for (int v = 0; v < B; ++v)
+        if (!images[v]) return ctx->fail(MVGS_EINVAL, "images[%d] is NULL", v);
+
+    hipStream_t s = (hipStream_t)stream;
+    const int tw = ctx->tw, th = ctx->th;
+    HIPCHK(ctx, ctx->bind_device());
+    mvgs_frame* f = acquire_frame(ctx);
+    if (!f) return ctx->fail(MVGS_ENOMEM, "frame allocation failed");
+    f->B = B;
+    f->P = g->P;
+    f->sh_degree = g->sh_degree;
+    f->n_tiles = n_tiles;
+    f->n_pixels = n_pixels;
+    build_cams(cams, B, tw, th, f->hcams);
+    const GaussianArgs ga = gargs(g);
+    const size_t P = (size_t)g->P;
+
+    auto bail = [&](int code) {
+        f->in_use = false;
+        return code;
+    };
+#define FCHK(call)                                                   \
+    do {                                                             \
+        hipError_t e_ = (call);                                      \
+        if (e_ != hipSuccess) return bail(ctx->hip_fail(e_, #call)); \
+    } while (0)
+
+    FCHK(ensure(f->cams, sizeof(DevCam) * B));
+    void* img_ptrs = nullptr;
+    {
+        void* dcams = nullptr;
+        FCHK(ctx->ring.put(f->hcams.data(), sizeof(DevCam) * B, s, &dcams));
+        FCHK(hipMemcpyAsync(f->cams.p, dcams, sizeof(DevCam) * B, hipMemcpyDeviceToDevice, s));
+        FCHK(ctx->ring.put(images, sizeof(float*) * B, s, &img_ptrs));
+    }
+    const DevCam* dcam = as<DevCam>(f->cams);
+
+    // participation and sizes
+    FCHK(ensure(ctx->nrec, sizeof(uint32_t) * (P + 1)));
+    FCHK(ensure(ctx->ntiles, sizeof(uint32_t) * (P + 1)));
+    FCHK(ensure(ctx->totals, sizeof(uint64_t) * 4));
+    FCHK(ensure(f->rec_off, sizeof(uint32_t) * (P + 1)));
+    FCHK(ensure(ctx->scan_scratch, scan_scratch_bytes(P + 1)));
+    int mk = ctx->stage_begin(0, s);
+    fill_u32(as<uint32_t>(ctx->nrec) + P, 1, 0u, s);
+    launch_count(ga, dcam, B, tw, th, as<uint32_t>(ctx->nrec), as<uint32_t>(ctx->ntiles), s);
+    scan_exclusive_u32(as<uint32_t>(ctx->nrec), as<uint32_t>(f->rec_off), P + 1, as<uint64_t>(ctx->totals),
+                       ctx->scan_scratch.p, s);
+    reduce_sum_u32(as<uint32_t>(ctx->ntiles), P, as<uint64_t>(ctx->totals) + 1, nullptr, s);
+    ctx->stage_end(mk, s);
+    FCHK(hipGetLastError());
+    FCHK(hipMemcpyAsync(ctx->pinned_totals, ctx->totals.p, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    FCHK(hipStreamSynchronize(s));
+    const uint64_t V64 = ctx->pinned_totals[0], K64 = ctx->pinned_totals[1];
+    if (V64 >= (1ull << 32) || K64 >= (1ull << 32)) {
+        (void)ctx->ring.seal(s);
+        return bail(ctx->fail(MVGS_ECAPACITY, "records %llu or pairs %llu reach 2^32", (unsigned long long)V64,
+                              (unsigned long long)K64));
+    }
+    const uint32_t V = (uint32_t)V64, K = (uint32_t)K64;
+    f->V = V;
+    f->K = K;
+
+    // records and the depth sort
+    FCHK(ensure(f->recs, sizeof(BlendRec) * std::max<uint32_t>(V, 1)));
+    FCHK(ensure(ctx->depth_key[0], sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
+    FCHK(ensure(ctx->depth_key[1], sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
+    FCHK(ensure(ctx->rec_vals[0], sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
+    FCHK(ensure(ctx->rec_vals[1], sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
+    FCHK(ensure(ctx->tile_rect, sizeof(uint2) * std::max<uint32_t>(V, 1)));
+    FCHK(ensure(ctx->pair_counts, sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
+    FCHK(ensure(ctx->pair_off, sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
+    FCHK(ensure(f->keys[0], sizeof(uint32_t) * std::max<uint32_t>(K, 1)));
+    FCHK(ensure(f->keys[1], sizeof(uint32_t) * std::max<uint32_t>(K, 1)));
+    FCHK(ensure(f->vals[0], sizeof(uint32_t) * std::max<uint32_t>(K, 1)));
+    FCHK(ensure(f->vals[1], sizeof(uint32_t) * std::max<uint32_t>(K, 1)));
+    FCHK(ensure(f->ranges, sizeof(uint2) * std::max<uint32_t>(n_tiles, 1)));
+    FCHK(ensure(f->t_final, sizeof(float) * n_pixels));
+    FCHK(ensure(f->n_last, sizeof(uint32_t) * n_pixels));
+    FCHK(ensure(ctx->sort_scratch, std::max(radix_scratch_bytes(std::max<size_t>(V, K)), scan_scratch_bytes(V))));
+
+    mk = ctx->stage_begin(1, s);
+    launch_records(ga, dcam, B, tw, th, as<uint32_t>(f->rec_off), as<BlendRec>(f->recs),
+                   as<uint32_t>(ctx->depth_key[0]), as<uint2>(ctx->tile_rect), s);
+    ctx->stage_end(mk, s);
+    mk = ctx->stage_begin(2, s);
+    uint32_t* dk[2] = {as<uint32_t>(ctx->depth_key[0]), as<uint32_t>(ctx->depth_key[1])};
+    uint32_t* dv[2] = {as<uint32_t>(ctx->rec_vals[0]), as<uint32_t>(ctx->rec_vals[1])};
+    const int dcur = radix_sort_u32(dk, dv, true, V, 32, ctx->sort_scratch.p, s);
+    const uint32_t* sorted_rec = dv[dcur];
+    ctx->stage_end(mk, s);
+
+    // pairs in depth order, then a stable sort by global tile id
+    mk = ctx->stage_begin(3, s);
+    launch_gather_tile_counts(sorted_rec, as<uint2>(ctx->tile_rect), V, as<uint32_t>(ctx->pair_counts), s);
+    scan_exclusive_u32(as<uint32_t>(ctx->pair_counts), as<uint32_t>(ctx->pair_off), V, nullptr,
+                       ctx->sort_scratch.p, s);
+    launch_emit_pairs(sorted_rec, as<uint2>(ctx->tile_rect), as<BlendRec>(f->recs), dcam,
+                      as<uint32_t>(ctx->pair_off), V, K, as<uint32_t>(f->keys[0]), as<uint32_t>(f->vals[0]), s);
+    ctx->stage_end(mk, s);
+    mk = ctx->stage_begin(4, s);
+    uint32_t* pk[2] = {as<uint32_t>(f->keys[0]), as<uint32_t>(f->keys[1])};
+    uint32_t* pv[2] = {as<uint32_t>(f->vals[0]), as<uint32_t>(f->vals[1])};
+    f->final_buf = radix_sort_u32(pk, pv, false, K, bits_for(n_tiles), ctx->sort_scratch.p, s);
+    ctx->stage_end(mk, s);
+    mk = ctx->stage_begin(5, s);
+    fill_u32(as<uint32_t>(f->ranges), 2 * (size_t)n_tiles, 0u, s);
+    launch_ranges(pk[f->final_buf], K, as<uint2>(f->ranges), s);
+    ctx->stage_end(mk, s);
+
+    // blend every pixel of every view
+    BlendFwdArgs a;
+    a.cams = dcam;
+    a.B = B;
+    a.n_tiles = n_tiles;
+    a.ranges = as<uint2>(f->ranges);
+    a.vals = pv[f->final_buf];
+    a.recs = as<BlendRec>(f->recs);
+    a.images = (float* const*)img_ptrs;
+    a.t_final = as<float>(f->t_final);
+    a.n_last = as<uint32_t>(f->n_last);
+    mk = ctx->stage_begin(6, s);
+    launch_blend_fwd(a, tw, th, s);
+    ctx->stage_end(mk, s);
+    FCHK(hipGetLastError());
+    FCHK(ctx->ring.seal(s));
+    *frame = f;
+    return MVGS_OK;
+#undef FCHK
+}
+
+int mvgs_loss(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t B, const float* const* images,
+              const float* const* targets, float w_l1, float w_dssim, float* loss_dev, float* const* dl_dimages) {
+    if (!ctx) return MVGS_EINVAL;
+    uint32_t n_tiles = 0, n_pixels = 0;
+    int st = validate_cams(ctx, cams, B, ctx->tw, ctx->th, &n_tiles, &n_pixels);
+    if (st) return st;
+    if (!images || !targets || !dl_dimages || !loss_dev) return ctx->fail(MVGS_EINVAL, "a loss buffer is NULL");
+    if (!std::isfinite(w_l1) || !std::isfinite(w_dssim)) return ctx->fail(MVGS_EINVAL, "loss weights must be finite");
+    std::vector<LossView> lv(B);
+    uint32_t pb = 0, max_hw = 0;
+    for (int v = 0; v < B; ++v) {
+        if (!images[v] || !targets[v] || !dl_dimages[v]) return ctx->fail(MVGS_EINVAL, "view %d: NULL image", v);
+        lv[v].img = images[v];
+        lv[v].tgt = targets[v];
+        lv[v].grad = dl_dimages[v];
+        lv[v].W = cams[v].width;
+        lv[v].H = cams[v].height;
+        lv[v].pix_base = pb;
+        lv[v].pad = 0;
+        const uint32_t hw = (uint32_t)(cams[v].width * cams[v].height);
+        pb += hw;
+        max_hw = std::max(max_hw, hw);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(ctx, ctx->bind_device());
+    HIPCHK(ctx, ensure(ctx->loss_scratch, loss_scratch_bytes(n_pixels, B)));
+    if (w_dssim != 0.0f) HIPCHK(ctx, ensure(ctx->ssim_maps, ssim_map_bytes(max_hw)));
+    void* dviews = nullptr;
+    HIPCHK(ctx, ctx->ring.put(lv.data(), sizeof(LossView) * B, s, &dviews));
+    const int mk = ctx->stage_begin(7, s);
+    launch_loss((const LossView*)dviews, lv.data(), B, n_pixels, w_l1, w_dssim, loss_dev, ctx->loss_scratch.p,
+                ctx->ssim_maps.p, s);
+    ctx->stage_end(mk, s);
+    LAUNCHCHK(ctx, "loss kernels");
+    HIPCHK(ctx, ctx->ring.seal(s));
+    return MVGS_OK;
+}
+
+int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_frame* frame,
+                  const float* const* dl_dimages, mvgs_grads* grads, mvgs_densify* densify) {
+    if (!ctx) return MVGS_EINVAL;
+    int st = validate_gaussians(ctx, g);
+    if (st) return st;
+    if (!frame || frame->ctx != ctx || !frame->in_use) return ctx->fail(MVGS_EINVAL, "frame is not live on this context");
+    if (frame->P != g->P || frame->sh_degree != g->sh_degree)
+        return ctx->fail(MVGS_EINVAL, "gaussians do not match the frame (P or sh_degree)");
+    if (!dl_dimages || !grads) return ctx->fail(MVGS_EINVAL, "dl_dimages or grads is NULL");
+    for (int v = 0; v < frame->B; ++v)
+        if (!dl_dimages[v]) return ctx->fail(MVGS_EINVAL, "dl_dimages[%d] is NULL", v);
+    if (g->P > 0 && (!grads->means || !grads->scales || !grads->quats || !grads->opacities || !grads->sh))
+        return ctx->fail(MVGS_EINVAL, "a gradient pointer is NULL");
+    if (densify && (!densify->e1 || !densify->e2 || !densify->count))
+        return ctx->fail(MVGS_EINVAL, "a densify pointer is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    mvgs_frame* f = const_cast<mvgs_frame*>(frame);
+    const uint32_t V = f->V;
+    HIPCHK(ctx, ensure(ctx->acc, sizeof(float) * kAccStride * std::max<uint32_t>(V, 1)));
+    fill_u32(as<uint32_t>(ctx->acc), (size_t)kAccStride * V, 0u, s);
+    void* dptrs = nullptr;
+    HIPCHK(ctx, ctx->ring.put(dl_dimages, sizeof(float*) * f->B, s, &dptrs));
+    BlendBwdArgs a;
+    a.cams = as<DevCam>(f->cams);
+    a.B = f->B;
+    a.n_tiles = f->n_tiles;
+    a.ranges = as<uint2>(f->ranges);
+    a.vals = as<uint32_t>(f->vals[f->final_buf]);
+    a.recs = as<BlendRec>(f->recs);
+    a.dl_dimg = (const float* const*)dptrs;
+    a.t_final = as<float>(f->t_final);
+    a.n_last = as<uint32_t>(f->n_last);
+    a.acc = as<float>(ctx->acc);
+    a.want_e1 = densify != nullptr;
+    int mk = ctx->stage_begin(8, s);
+    launch_blend_bwd(a, ctx->tw, ctx->th, s);
+    ctx->stage_end(mk, s);
+    GradArgs gr;
+    gr.means = grads->means;
+    gr.scales = grads->scales;
+    gr.quats = grads->quats;
+    gr.opac = grads->opacities;
+    gr.sh = grads->sh;
+    gr.e1 = densify ? densify->e1 : nullptr;
+    gr.e2 = densify ? densify->e2 : nullptr;
+    gr.count = densify ? densify->count : nullptr;
+    mk = ctx->stage_begin(9, s);
+    launch_preprocess_bwd(gargs(g), as<DevCam>(f->cams), as<uint32_t>(f->rec_off), as<BlendRec>(f->recs),
+                          as<float>(ctx->acc), gr, s);
+    ctx->stage_end(mk, s);
+    LAUNCHCHK(ctx, "backward kernels");
+    HIPCHK(ctx, ctx->ring.seal(s));
+    return MVGS_OK;
+}
+
+int mvgs_frame_release(mvgs_context* ctx, mvgs_frame* frame) {
+    if (!ctx || !frame || frame->ctx != ctx) return MVGS_EINVAL;
+    frame->in_use = false;
+    return MVGS_OK;
+}
+
+int mvgs_frame_info(const mvgs_frame* frame, int64_t* n_records, int64_t* n_pairs, int64_t* n_tiles) {
+    if (!frame) return MVGS_EINVAL;
+    if (n_records) *n_records = frame->V;
+    if (n_pairs) *n_pairs = (int64_t)frame->K;
+    if (n_tiles) *n_tiles = frame->n_tiles;
+    return MVGS_OK;
+}
+
+int mvgs_export_binning(mvgs_context* ctx, void* stream, const mvgs_frame* frame, uint64_t* keys, uint32_t* values,
+                        uint32_t* ranges) {
+    if (!ctx || !frame || frame->ctx != ctx || !frame->in_use) return MVGS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    mvgs_frame* f = const_cast<mvgs_frame*>(frame);
+    if (keys || values)
+        launch_export_keys(as<uint32_t>(f->keys[f->final_buf]), as<uint32_t>(f->vals[f->final_buf]),
+                           as<BlendRec>(f->recs), as<DevCam>(f->cams), f->B, (uint32_t)f->K, keys, values, s);
+    if (ranges && f->n_tiles)
+        HIPCHK(ctx, hipMemcpyAsync(ranges, f->ranges.p, sizeof(uint2) * f->n_tiles, hipMemcpyDeviceToDevice, s));
+    LAUNCHCHK(ctx, "export binning");
+    return MVGS_OK;
+}
+
+int mvgs_export_transmittance(mvgs_context* ctx, void* stream, const mvgs_frame* frame, float* const* t_final) {
+    if (!ctx || !frame || frame->ctx != ctx || !frame->in_use || !t_final) return MVGS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    mvgs_frame* f = const_cast<mvgs_frame*>(frame);
+    for (int v = 0; v < f->B; ++v) {
+        if (!t_final[v]) return ctx->fail(MVGS_EINVAL, "t_final[%d] is NULL", v);
+        const DevCam& c = f->hcams[v];
+        HIPCHK(ctx, hipMemcpyAsync(t_final[v], as<float>(f->t_final) + c.pix_base, sizeof(float) * c.W * c.H,
+                                   hipMemcpyDeviceToDevice, s));
+    }
+    return MVGS_OK;
+}
+
+static const char* kStageNames[MVGS_STAGE_COUNT] = {"count", "records", "depth_sort", "emit", "tile_sort",
+                                                     "ranges", "blend_fwd", "loss", "blend_bwd", "preprocess_bwd"};
+
+const char* mvgs_stage_name(int stage) {
+    return (stage >= 0 && stage < MVGS_STAGE_COUNT) ? kStageNames[stage] : "unknown";
+}
+
+int mvgs_profile_enable(mvgs_context* ctx, int enable) {
+    if (!ctx) return MVGS_EINVAL;
+    ctx->prof = enable != 0;
+    return MVGS_OK;
+}
+
+int mvgs_profile_read(mvgs_context* ctx, double* ms, int64_t* calls) {
+    if (!ctx) return MVGS_EINVAL;
+    for (auto& m : ctx->marks) {
+        HIPCHK(ctx, hipEventSynchronize(m.b));
+        float t = 0.0f;
+        HIPCHK(ctx, hipEventElapsedTime(&t, m.a, m.b));
+        ctx->prof_ms[m.stage] += t;
+        ctx->prof_calls[m.stage] += 1;
+        ctx->ev_pool.push_back(m.a);
+        ctx->ev_pool.push_back(m.b);
+    }
+    ctx->marks.clear();
+    for (int i = 0; i < MVGS_STAGE_COUNT; ++i) {
+        if (ms) ms[i] = ctx->prof_ms[i];
+        if (calls) calls[i] = ctx->prof_calls[i];
+    }
+    return MVGS_OK;
+}
+
+int mvgs_profile_reset(mvgs_context* ctx) {
+    if (!ctx) return MVGS_EINVAL;
+    int st = mvgs_profile_read(ctx, nullptr, nullptr);
+    for (int i = 0; i < MVGS_STAGE_COUNT; ++i) {
+        ctx->prof_ms[i] = 0.0;
+        ctx->prof_calls[i] = 0;
+    }
+    return st;
+}
+
+int mvgs_frame_work(mvgs_context* ctx, void* stream, const mvgs_frame* frame, uint64_t* steps_dev) {
+    if (!ctx || !frame || frame->ctx != ctx || !frame->in_use || !steps_dev) return MVGS_EINVAL;
+    mvgs_frame* f = const_cast<mvgs_frame*>(frame);
+    launch_frame_work(as<DevCam>(f->cams), f->B, as<uint2>(f->ranges), as<uint32_t>(f->n_last), f->n_pixels,
+                      ctx->tw, ctx->th, steps_dev, (hipStream_t)stream);
+    LAUNCHCHK(ctx, "frame work");
+    return MVGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,311 @@
+// Per-Gaussian preprocessing kernels: participation count, record emission, and the
+// backward chain from 2D quantities to the parameters (paper Sec. 3; multi-view
+// appendix: participation is decided per view before memory is sized).
+//
+// One thread per Gaussian loops over all views of the batch, so each Gaussian's
+// parameters are read from HBM once per step whatever the number of views; the
+// cameras are uniform across the wave and come in through the scalar cache.
+#include "mvgs_kernels.h"
+
+namespace mvgs {
+
+__device__ __forceinline__ void load_gaussian(const float* __restrict__ means, const float* __restrict__ scales,
+                                              const float* __restrict__ quats, const float* __restrict__ opac,
+                                              int64_t g, float mu[3], float s[3], float q[4], float& o) {
+    mu[0] = means[3 * g]; mu[1] = means[3 * g + 1]; mu[2] = means[3 * g + 2];
+    s[0] = scales[3 * g]; s[1] = scales[3 * g + 1]; s[2] = scales[3 * g + 2];
+    const float4 qq = *reinterpret_cast<const float4*>(quats + 4 * g);
+    q[0] = qq.x; q[1] = qq.y; q[2] = qq.z; q[3] = qq.w;
+    o = opac[g];
+}
+
+// Number of participating views and of covered tiles (summed over views) per Gaussian.
+__global__ void __launch_bounds__(256) k_count(const float* __restrict__ means, const float* __restrict__ scales,
+                                               const float* __restrict__ quats, const float* __restrict__ opac,
+                                               int64_t P, const DevCam* __restrict__ cams, int B, int tile_w,
+                                               int tile_h, uint32_t* __restrict__ nrec,
+                                               uint32_t* __restrict__ ntiles) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= P) return;
+    float mu[3], s[3], q[4], o;
+    load_gaussian(means, scales, quats, opac, g, mu, s, q, o);
+    uint32_t n = 0, nt = 0;
+    for (int v = 0; v < B; ++v) {
+        ProjState st;
+        const ProjOut p = project(mu, s, q, o, cams[v], st);
+        if (p.ok) {
+            n += 1;
+            nt += (uint32_t)((p.x1 / tile_w - p.x0 / tile_w + 1) * (p.y1 / tile_h - p.y0 / tile_h + 1));
+        }
+    }
+    nrec[g] = n;
+    ntiles[g] = nt;
+}
+
+// Records of every participating (view, Gaussian), written in (Gaussian, view) order at
+// rec_off[g]. Also the depth sort key and the covered-tile rectangle of each record.
+template <int D>
+__global__ void __launch_bounds__(256) k_records(const float* __restrict__ means, const float* __restrict__ scales,
+                                                 const float* __restrict__ quats, const float* __restrict__ opac,
+                                                 const float* __restrict__ sh, int64_t P,
+                                                 const DevCam* __restrict__ cams, int B, int tile_w, int tile_h,
+                                                 const uint32_t* __restrict__ rec_off, BlendRec* __restrict__ recs,
+                                                 uint32_t* __restrict__ depth_key, uint2* __restrict__ tile_rect) {
+    constexpr int K = (D + 1) * (D + 1);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= P) return;
+    float mu[3], s[3], q[4], o;
+    load_gaussian(means, scales, quats, opac, g, mu, s, q, o);
+    float coef[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) coef[k][ch] = sh[(g * K + k) * 3 + ch];
+    uint32_t out = rec_off[g];
+    const uint32_t out_end = rec_off[g + 1];
+    for (int v = 0; v < B && out < out_end; ++v) {
+        const DevCam& c = cams[v];
+        ProjState st;
+        const ProjOut p = project(mu, s, q, o, c, st);
+        if (!p.ok) continue;
+        float dx = mu[0] - c.campos[0], dy = mu[1] - c.campos[1], dz = mu[2] - c.campos[2];
+        const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+        dx *= il; dy *= il; dz *= il;
+        float Y[16];
+        sh_basis<D>(dx, dy, dz, Y);
+        float rgb[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float a = 0.5f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) a = __builtin_fmaf(coef[k][ch], Y[k], a);
+            rgb[ch] = a > 0.0f ? a : 0.0f;
+        }
+        BlendRec r;
+        r.boxx = (uint32_t)p.x0 | ((uint32_t)p.x1 << 16);
+        r.boxy = (uint32_t)p.y0 | ((uint32_t)p.y1 << 16);
+        r.mx = p.mx; r.my = p.my;
+        r.hca = p.hca; r.nb = p.nb; r.hcc = p.hcc; r.o = o;
+        r.cut = p.cut; r.hi = p.hi; r.r = rgb[0]; r.g = rgb[1];
+        r.b = rgb[2];
+        r.gid = (uint32_t)g;
+        r.view = (uint32_t)v;
+        r.depth_bits = f2u(p.depth);
+        recs[out] = r;
+        depth_key[out] = f2u(p.depth);
+        tile_rect[out] = make_uint2((uint32_t)(p.x0 / tile_w) | ((uint32_t)(p.x1 / tile_w) << 16),
+                                    (uint32_t)(p.y0 / tile_h) | ((uint32_t)(p.y1 / tile_h) << 16));
+        ++out;
+    }
+}
+
+// Backward chain per Gaussian over its records (2D gradients -> parameters), summed over
+// views; densification statistics in each view's normalised device coordinates.
+template <int D>
+__global__ void __launch_bounds__(256) k_preprocess_bwd(
+    const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
+    const float* __restrict__ opac, const float* __restrict__ sh, int64_t P, const DevCam* __restrict__ cams,
+    const uint32_t* __restrict__ rec_off, const BlendRec* __restrict__ recs, const float* __restrict__ acc,
+    float* __restrict__ g_means, float* __restrict__ g_scales, float* __restrict__ g_quats,
+    float* __restrict__ g_opac, float* __restrict__ g_sh, float* __restrict__ e1, float* __restrict__ e2,
+    int32_t* __restrict__ count) {
+    constexpr int K = (D + 1) * (D + 1);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= P) return;
+    float mu[3], s[3], q[4], o;
+    load_gaussian(means, scales, quats, opac, g, mu, s, q, o);
+    float coef[K][3], dcoef[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            coef[k][ch] = sh[(g * K + k) * 3 + ch];
+            dcoef[k][ch] = 0.0f;
+        }
+    float dmu[3] = {0, 0, 0}, ds[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dop = 0.0f;
+    float se1 = 0.0f, se2 = 0.0f;
+    const uint32_t r0 = rec_off[g], r1 = rec_off[g + 1];
+    for (uint32_t ri = r0; ri < r1; ++ri) {
+        const uint32_t v = recs[ri].view;
+        const DevCam& c = cams[v];
+        const float4 a0 = *reinterpret_cast<const float4*>(acc + (size_t)ri * kAccStride);
+        const float4 a1 = *reinterpret_cast<const float4*>(acc + (size_t)ri * kAccStride + 4);
+        const float4 a2 = *reinterpret_cast<const float4*>(acc + (size_t)ri * kAccStride + 8);
+        const float gmx = a0.x, gmy = a0.y, gca = a0.z, gcb = a0.w;
+        const float gcc = a1.x, gop = a1.y, gr = a1.z, gg = a1.w;
+        const float gb = a2.x, ge1 = a2.y;
+        ProjState st;
+        (void)project(mu, s, q, o, c, st);
+        dop += gop;
+        // statistics (NDC = pixel gradient times (W/2, H/2))
+        const float nx = gmx * 0.5f * (float)c.W, ny = gmy * 0.5f * (float)c.H;
+        se2 += sqrtf(nx * nx + ny * ny);
+        se1 += ge1;
+
+        // conic -> Sigma': dL/dSigma' = -Q G Q with G = [[gca, gcb/2], [gcb/2, gcc]]
+        const float Q00 = st.ca, Q01 = st.cb, Q11 = st.cc;
+        const float G00 = gca, G01 = 0.5f * gcb, G11 = gcc;
+        const float QG00 = Q00 * G00 + Q01 * G01, QG01 = Q00 * G01 + Q01 * G11;
+        const float QG10 = Q01 * G00 + Q11 * G01, QG11 = Q01 * G01 + Q11 * G11;
+        const float Gs00 = -(QG00 * Q00 + QG01 * Q01);
+        const float Gs01 = -(QG00 * Q01 + QG01 * Q11);
+        const float Gs11 = -(QG10 * Q01 + QG11 * Q11);
+        // Sigma' = T Sigma T^T + 0.3 I: dT = 2 Gs T Sigma, dSigma = T^T Gs T
+        const float Sm[9] = {st.S[0], st.S[1], st.S[2], st.S[1], st.S[3], st.S[4], st.S[2], st.S[4], st.S[5]};
+        float TS0[3], TS1[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            TS0[k] = st.T0[0] * Sm[k] + st.T0[1] * Sm[3 + k] + st.T0[2] * Sm[6 + k];
+            TS1[k] = st.T1[0] * Sm[k] + st.T1[1] * Sm[3 + k] + st.T1[2] * Sm[6 + k];
+        }
+        float dT0[3], dT1[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            dT0[k] = 2.0f * (Gs00 * TS0[k] + Gs01 * TS1[k]);
+            dT1[k] = 2.0f * (Gs01 * TS0[k] + Gs11 * TS1[k]);
+        }
+        float dSig[9];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+                dSig[3 * k + m] = st.T0[k] * (Gs00 * st.T0[m] + Gs01 * st.T1[m]) +
+                                  st.T1[k] * (Gs01 * st.T0[m] + Gs11 * st.T1[m]);
+        // T = J W with J = [[j00, 0, j02], [0, j11, j12]]
+        float dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            dJ00 += dT0[k] * c.R[k];
+            dJ02 += dT0[k] * c.R[6 + k];
+            dJ11 += dT1[k] * c.R[3 + k];
+            dJ12 += dT1[k] * c.R[6 + k];
+        }
+        const float iz = st.iz, iz2 = iz * iz, iz3 = iz2 * iz;
+        const float x = st.tx, y = st.ty;
+        float dtc[3];
+        dtc[0] = gmx * c.fx * iz - dJ02 * c.fx * iz2;
+        dtc[1] = gmy * c.fy * iz - dJ12 * c.fy * iz2;
+        dtc[2] = -gmx * c.fx * x * iz2 - gmy * c.fy * y * iz2 - dJ00 * c.fx * iz2 + dJ02 * 2.0f * c.fx * x * iz3 -
+                 dJ11 * c.fy * iz2 + dJ12 * 2.0f * c.fy * y * iz3;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dmu[k] += c.R[k] * dtc[0] + c.R[3 + k] * dtc[1] + c.R[6 + k] * dtc[2];
+        // Sigma = M M^T, M = rot diag(s): dM = 2 dSigma_sym M
+        float M[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) M[3 * i + j] = st.rot[3 * i + j] * s[j];
+        float drot[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                float v_ = 0.0f;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) v_ += (dSig[3 * i + k] + dSig[3 * k + i]) * M[3 * k + j];
+                ds[j] += v_ * st.rot[3 * i + j];
+                drot[3 * i + j] = v_ * s[j];
+            }
+        const float w = st.qw, qx = st.qx, qy = st.qy, qz = st.qz;
+        float dqn[4];
+        dqn[0] = -2 * qz * drot[1] + 2 * qy * drot[2] + 2 * qz * drot[3] - 2 * qx * drot[5] - 2 * qy * drot[6] +
+                 2 * qx * drot[7];
+        dqn[1] = 2 * qy * drot[1] + 2 * qz * drot[2] + 2 * qy * drot[3] - 4 * qx * drot[4] - 2 * w * drot[5] +
+                 2 * qz * drot[6] + 2 * w * drot[7] - 4 * qx * drot[8];
+        dqn[2] = -4 * qy * drot[0] + 2 * qx * drot[1] + 2 * w * drot[2] + 2 * qx * drot[3] + 2 * qz * drot[5] -
+                 2 * w * drot[6] + 2 * qz * drot[7] - 4 * qy * drot[8];
+        dqn[3] = -4 * qz * drot[0] - 2 * w * drot[1] + 2 * qx * drot[2] + 2 * w * drot[3] - 4 * qz * drot[4] +
+                 2 * qy * drot[5] + 2 * qx * drot[6] + 2 * qy * drot[7];
+        const float qd = w * dqn[0] + qx * dqn[1] + qy * dqn[2] + qz * dqn[3];
+        dq[0] += (dqn[0] - w * qd) * st.qinv;
+        dq[1] += (dqn[1] - qx * qd) * st.qinv;
+        dq[2] += (dqn[2] - qy * qd) * st.qinv;
+        dq[3] += (dqn[3] - qz * qd) * st.qinv;
+        // colour
+        float ex = mu[0] - c.campos[0], ey = mu[1] - c.campos[1], ez = mu[2] - c.campos[2];
+        const float il = 1.0f / sqrtf(ex * ex + ey * ey + ez * ez);
+        ex *= il; ey *= il; ez *= il;
+        float Y[16], dY[16][3];
+        sh_basis<D>(ex, ey, ez, Y);
+        sh_basis_grad<D>(ex, ey, ez, dY);
+        const float grgb[3] = {gr, gg, gb};
+        float dd[3] = {0, 0, 0};
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float raw = 0.5f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) raw = __builtin_fmaf(coef[k][ch], Y[k], raw);
+            const float gch = raw > 0.0f ? grgb[ch] : 0.0f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                dcoef[k][ch] += gch * Y[k];
+                dd[0] += gch * coef[k][ch] * dY[k][0];
+                dd[1] += gch * coef[k][ch] * dY[k][1];
+                dd[2] += gch * coef[k][ch] * dY[k][2];
+            }
+        }
+        const float ddot = dd[0] * ex + dd[1] * ey + dd[2] * ez;
+        dmu[0] += (dd[0] - ex * ddot) * il;
+        dmu[1] += (dd[1] - ey * ddot) * il;
+        dmu[2] += (dd[2] - ez * ddot) * il;
+    }
+    g_means[3 * g] = dmu[0]; g_means[3 * g + 1] = dmu[1]; g_means[3 * g + 2] = dmu[2];
+    g_scales[3 * g] = ds[0]; g_scales[3 * g + 1] = ds[1]; g_scales[3 * g + 2] = ds[2];
+    *reinterpret_cast<float4*>(g_quats + 4 * g) = make_float4(dq[0], dq[1], dq[2], dq[3]);
+    g_opac[g] = dop;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) g_sh[(g * K + k) * 3 + ch] = dcoef[k][ch];
+    if (e1) {
+        e1[g] += se1;
+        e2[g] += se2;
+        count[g] += (int32_t)(r1 - r0);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------------
+void launch_count(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, uint32_t* nrec,
+                  uint32_t* ntiles, hipStream_t s) {
+    const unsigned blocks = (unsigned)((ga.P + 255) / 256);
+    if (!blocks) return;
+    hipLaunchKernelGGL(k_count, dim3(blocks), dim3(256), 0, s, ga.means, ga.scales, ga.quats, ga.opac, ga.P, cams,
+                       B, tw, th, nrec, ntiles);
+}
+
+void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,
+                    BlendRec* recs, uint32_t* depth_key, uint2* tile_rect, hipStream_t s) {
+    const unsigned blocks = (unsigned)((ga.P + 255) / 256);
+    if (!blocks) return;
+#define MVGS_REC(D)                                                                                             \
+    hipLaunchKernelGGL(k_records<D>, dim3(blocks), dim3(256), 0, s, ga.means, ga.scales, ga.quats, ga.opac,     \
+                       ga.sh, ga.P, cams, B, tw, th, rec_off, recs, depth_key, tile_rect)
+    switch (ga.sh_degree) {
+        case 0: MVGS_REC(0); break;
+        case 1: MVGS_REC(1); break;
+        case 2: MVGS_REC(2); break;
+        default: MVGS_REC(3); break;
+    }
+#undef MVGS_REC
+}
+
+void launch_preprocess_bwd(const GaussianArgs& ga, const DevCam* cams, const uint32_t* rec_off,
+                           const BlendRec* recs, const float* acc, const GradArgs& gr, hipStream_t s) {
+    const unsigned blocks = (unsigned)((ga.P + 255) / 256);
+    if (!blocks) return;
+#define MVGS_PB(D)                                                                                              \
+    hipLaunchKernelGGL(k_preprocess_bwd<D>, dim3(blocks), dim3(256), 0, s, ga.means, ga.scales, ga.quats,       \
+                       ga.opac, ga.sh, ga.P, cams, rec_off, recs, acc, gr.means, gr.scales, gr.quats, gr.opac,  \
+                       gr.sh, gr.e1, gr.e2, gr.count)
+    switch (ga.sh_degree) {
+        case 0: MVGS_PB(0); break;
+        case 1: MVGS_PB(1); break;
+        case 2: MVGS_PB(2); break;
+        default: MVGS_PB(3); break;
+    }
+#undef MVGS_PB
+}
+
+}  // namespace mvgs

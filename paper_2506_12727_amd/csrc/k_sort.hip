@@ -1,0 +1,380 @@
+// Scans, the stable LSD radix sort, and the (view, tile, depth) binning built on them.
+//
+// The multi-view appendix of the paper sorts one 64-bit key per (Gaussian, tile) pair holding
+// tile, view and depth. The same order -- by (view, tile), then depth, then Gaussian index --
+// is reached here in two cheaper stable sorts: the participating (view, Gaussian) records are
+// sorted by their 32-bit depth key (one item per record), pairs are then emitted in that depth
+// order and sorted stably by their global tile id (view-major, so (view, tile) in one integer of
+// ceil(log2(total tiles)) bits). Ties in depth keep the (Gaussian, view) emission order of the
+// records, i.e. ascending Gaussian index within a view.
+//
+// Radix sort: 8-bit digits, 4096 items per workgroup (4 wavefronts x 16 rounds x 64 lanes).
+// Each pass is an upsweep (per-workgroup digit histogram), an exclusive scan of the digit-major
+// histogram table and a downsweep that ranks items stably within the workgroup with wave64
+// ballots, stages them in LDS in digit order and writes them out in contiguous runs.
+#include <algorithm>
+
+#include "mvgs_kernels.h"
+
+namespace mvgs {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 4096
+
+constexpr int kSortWaves = 4;
+constexpr int kSortRounds = 16;
+constexpr int kSortThreads = kSortWaves * 64;
+constexpr int kSortTile = kSortWaves * kSortRounds * 64;  // 4096
+constexpr int kRadix = 256;
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t* __restrict__ p, size_t n, uint64_t v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// exclusive scan of 256 values held one per thread; returns the exclusive prefix, sets *total
+__device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_t* lds, uint32_t* total) {
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+#pragma unroll
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t add = (t >= off) ? lds[t - off] : 0u;
+        __syncthreads();
+        lds[t] += add;
+        __syncthreads();
+    }
+    const uint32_t incl = lds[t];
+    *total = lds[255];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t* __restrict__ in, size_t n,
+                                                              uint32_t* __restrict__ block_sums) {
+    __shared__ uint32_t lds[256];
+    const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) s += in[base + k];
+    uint32_t total;
+    (void)block_exclusive_scan_256(s, lds, &total);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t* in, uint32_t* out, size_t n,
+                                                             const uint32_t* __restrict__ block_off) {
+    __shared__ uint32_t lds[256];
+    const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+    uint32_t vals[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        vals[k] = (base + k < n) ? in[base + k] : 0u;
+        s += vals[k];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan_256(s, lds, &total) + (block_off ? block_off[blockIdx.x] : 0u);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += vals[k];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_reduce64(const uint32_t* __restrict__ in, size_t n,
+                                                  unsigned long long* __restrict__ total) {
+    __shared__ unsigned long long part[256];
+    unsigned long long s = 0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) s += in[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(total, part[0]);
+}
+
+static size_t div_up(size_t a, size_t b) { return (a + b - 1) / b; }
+
+size_t scan_scratch_bytes(size_t n) {
+    size_t bytes = 256;
+    size_t m = n;
+    while (m > (size_t)kScanTile) {
+        m = div_up(m, kScanTile);
+        bytes += m * sizeof(uint32_t) + 256;
+    }
+    return bytes;
+}
+
+static void fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, p, n, v);
+}
+
+void reduce_sum_u32(const uint32_t* in, size_t n, uint64_t* total64, void* scratch, hipStream_t s) {
+    (void)scratch;
+    fill_u64(total64, 1, 0, s);
+    if (n == 0) return;
+    const unsigned blocks = (unsigned)std::min<size_t>(div_up(n, 256), 2048);
+    hipLaunchKernelGGL(k_reduce64, dim3(blocks), dim3(256), 0, s, in, n, (unsigned long long*)total64);
+}
+
+static void scan_rec(const uint32_t* in, uint32_t* out, size_t n, uint8_t* scratch, hipStream_t s) {
+    const size_t blocks = div_up(n, kScanTile);
+    if (blocks <= 1) {
+        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanThreads), 0, s, in, out, n, (const uint32_t*)nullptr);
+        return;
+    }
+    uint32_t* sums = (uint32_t*)scratch;
+    uint8_t* next = scratch + ((blocks * sizeof(uint32_t) + 255) / 256) * 256;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)blocks), dim3(kScanThreads), 0, s, in, n, sums);
+    scan_rec(sums, sums, blocks, next, s);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)blocks), dim3(kScanThreads), 0, s, in, out, n,
+                       (const uint32_t*)sums);
+}
+
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* total64, void* scratch,
+                        hipStream_t s) {
+    if (total64) reduce_sum_u32(in, n, total64, nullptr, s);
+    if (n == 0) return;
+    scan_rec(in, out, n, (uint8_t*)scratch, s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// radix sort
+// ---------------------------------------------------------------------------------------------
+
+// lanes of this wave holding the same 8-bit digit (among `valid` lanes)
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+    uint64_t peers = ballot64(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = ballot64(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(const uint32_t* __restrict__ keys, size_t n,
+                                                                int shift, int nblocks,
+                                                                uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[kRadix];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const size_t base = (size_t)blockIdx.x * kSortTile + (size_t)wave * kSortRounds * 64;
+    for (int r = 0; r < kSortRounds; ++r) {
+        const size_t i = base + (size_t)r * 64 + lane;
+        const bool valid = i < n;
+        const uint32_t d = valid ? (keys[i] >> shift) & 0xffu : 0u;
+        const uint64_t peers = digit_peers(d, valid);
+        if (valid && rank_below(peers) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out, size_t n, int shift, int nblocks, const uint32_t* __restrict__ hist_scan) {
+    __shared__ uint32_t wcount[kSortWaves][kRadix];
+    __shared__ uint32_t dstart[kRadix];
+    __shared__ uint32_t gbase[kRadix];
+    __shared__ uint32_t scan_tmp[kRadix];
+    __shared__ uint32_t skey[kSortTile];
+    __shared__ uint32_t sval[kSortTile];
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortThreads) (&wcount[0][0])[d] = 0;
+    __syncthreads();
+
+    const size_t base = (size_t)blockIdx.x * kSortTile + (size_t)wave * kSortRounds * 64;
+    uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        const size_t i = base + (size_t)r * 64 + lane;
+        const bool valid = i < n;
+        key[r] = valid ? keys_in[i] : 0xffffffffu;
+        val[r] = valid ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        const size_t i = base + (size_t)r * 64 + lane;
+        const bool valid = i < n;
+        const uint32_t d = (key[r] >> shift) & 0xffu;
+        const uint64_t peers = digit_peers(d, valid);
+        const uint32_t below = (uint32_t)rank_below(peers);
+        const uint32_t before = wcount[wave][d];
+        rank[r] = before + below;
+        wave_lds_sync();
+        if (valid && below == 0) wcount[wave][d] = before + (uint32_t)__popcll(peers);
+        wave_lds_sync();
+    }
+    __syncthreads();
+    // per digit: prefix over waves, block total, and the block's global base
+    {
+        const int d = threadIdx.x;
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) {
+            const uint32_t c = wcount[w][d];
+            wcount[w][d] = run;
+            run += c;
+        }
+        uint32_t total;
+        const uint32_t start = block_exclusive_scan_256(run, scan_tmp, &total);
+        dstart[d] = start;
+        gbase[d] = hist_scan[(size_t)d * nblocks + blockIdx.x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        const size_t i = base + (size_t)r * 64 + lane;
+        if (i < n) {
+            const uint32_t d = (key[r] >> shift) & 0xffu;
+            const uint32_t pos = dstart[d] + wcount[wave][d] + rank[r];
+            skey[pos] = key[r];
+            sval[pos] = val[r];
+        }
+    }
+    __syncthreads();
+    const size_t tile_n = std::min<size_t>((size_t)kSortTile, n - (size_t)blockIdx.x * kSortTile);
+    for (int j = threadIdx.x; j < (int)tile_n; j += kSortThreads) {
+        const uint32_t k = skey[j];
+        const uint32_t d = (k >> shift) & 0xffu;
+        const size_t dst = (size_t)gbase[d] + (uint32_t)(j - dstart[d]);
+        keys_out[dst] = k;
+        vals_out[dst] = sval[j];
+    }
+}
+
+size_t radix_scratch_bytes(size_t n) {
+    const size_t blocks = std::max<size_t>(1, div_up(n, kSortTile));
+    const size_t hist = blocks * kRadix * sizeof(uint32_t);
+    return ((hist + 255) / 256) * 256 * 2 + scan_scratch_bytes(blocks * kRadix);
+}
+
+int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
+                   hipStream_t s) {
+    int cur = 0;
+    if (n == 0 || bits <= 0) return cur;
+    const size_t blocks = div_up(n, kSortTile);
+    const size_t hist_n = blocks * kRadix;
+    uint8_t* p = (uint8_t*)scratch;
+    uint32_t* hist = (uint32_t*)p;
+    p += ((hist_n * sizeof(uint32_t) + 255) / 256) * 256;
+    uint32_t* hist_scan = (uint32_t*)p;
+    p += ((hist_n * sizeof(uint32_t) + 255) / 256) * 256;
+    for (int shift = 0; shift < bits; shift += 8) {
+        const uint32_t* vin = (shift == 0 && identity_values) ? nullptr : vals[cur];
+        hipLaunchKernelGGL(k_radix_upsweep, dim3((unsigned)blocks), dim3(kSortThreads), 0, s, keys[cur], n, shift,
+                           (int)blocks, hist);
+        scan_exclusive_u32(hist, hist_scan, hist_n, nullptr, p, s);
+        hipLaunchKernelGGL(k_radix_downsweep, dim3((unsigned)blocks), dim3(kSortThreads), 0, s, keys[cur], vin,
+                           keys[cur ^ 1], vals[cur ^ 1], n, shift, (int)blocks, (const uint32_t*)hist_scan);
+        cur ^= 1;
+    }
+    return cur;
+}
+
+// ---------------------------------------------------------------------------------------------
+// binning
+// ---------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t rect_tiles(uint2 r) {
+    const uint32_t tx0 = r.x & 0xffffu, tx1 = r.x >> 16, ty0 = r.y & 0xffffu, ty1 = r.y >> 16;
+    return (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+}
+
+__global__ void k_gather_tile_counts(const uint32_t* __restrict__ sorted_rec, const uint2* __restrict__ rect,
+                                     uint32_t n, uint32_t* __restrict__ counts) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) counts[i] = rect_tiles(rect[sorted_rec[i]]);
+}
+
+__global__ void k_emit_pairs(const uint32_t* __restrict__ sorted_rec, const uint2* __restrict__ rect,
+                             const BlendRec* __restrict__ recs, const DevCam* __restrict__ cams,
+                             const uint32_t* __restrict__ pair_off, uint32_t n, uint32_t K,
+                             uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t r = sorted_rec[i];
+    const uint2 rc = rect[r];
+    const uint32_t v = recs[r].view;
+    const uint32_t tb = cams[v].tile_base;
+    const uint32_t tx_n = (uint32_t)cams[v].tiles_x;
+    const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu, ty1 = rc.y >> 16;
+    uint32_t o = pair_off[i];
+    for (uint32_t ty = ty0; ty <= ty1; ++ty)
+        for (uint32_t tx = tx0; tx <= tx1; ++tx) {
+            if (o >= K) return;
+            keys[o] = tb + ty * tx_n + tx;
+            vals[o] = r;
+            ++o;
+        }
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ keys, uint32_t K, uint2* __restrict__ ranges) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= K) return;
+    const uint32_t t = keys[i];
+    if (i == 0 || keys[i - 1] != t) ranges[t].x = i;
+    if (i == K - 1 || keys[i + 1] != t) ranges[t].y = i + 1;
+}
+
+__global__ void k_export_keys(const uint32_t* __restrict__ tile_keys, const uint32_t* __restrict__ vals,
+                              const BlendRec* __restrict__ recs, const DevCam* __restrict__ cams, uint32_t K,
+                              uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= K) return;
+    const uint32_t r = vals[i];
+    const BlendRec& rec = recs[r];
+    const uint32_t local = tile_keys[i] - cams[rec.view].tile_base;
+    if (keys_out) keys_out[i] = ((uint64_t)rec.view << 48) | ((uint64_t)local << 32) | (uint64_t)rec.depth_bits;
+    if (vals_out) vals_out[i] = rec.gid;
+}
+
+void launch_gather_tile_counts(const uint32_t* sorted_rec, const uint2* tile_rect, uint32_t n, uint32_t* counts,
+                               hipStream_t s) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_gather_tile_counts, dim3((n + 255) / 256), dim3(256), 0, s, sorted_rec, tile_rect, n,
+                       counts);
+}
+
+void launch_emit_pairs(const uint32_t* sorted_rec, const uint2* tile_rect, const BlendRec* recs,
+                       const DevCam* cams, const uint32_t* pair_off, uint32_t n, uint32_t K, uint32_t* keys,
+                       uint32_t* vals, hipStream_t s) {
+    if (!n || !K) return;
+    hipLaunchKernelGGL(k_emit_pairs, dim3((n + 255) / 256), dim3(256), 0, s, sorted_rec, tile_rect, recs, cams,
+                       pair_off, n, K, keys, vals);
+}
+
+void launch_ranges(const uint32_t* keys, uint32_t K, uint2* ranges, hipStream_t s) {
+    if (!K) return;
+    hipLaunchKernelGGL(k_ranges, dim3((K + 255) / 256), dim3(256), 0, s, keys, K, ranges);
+}
+
+void launch_export_keys(const uint32_t* tile_keys, const uint32_t* vals, const BlendRec* recs,
+                        const DevCam* cams, int B, uint32_t K, uint64_t* keys_out, uint32_t* vals_out,
+                        hipStream_t s) {
+    (void)B;
+    if (!K) return;
+    hipLaunchKernelGGL(k_export_keys, dim3((K + 255) / 256), dim3(256), 0, s, tile_keys, vals, recs, cams, K,
+                       keys_out, vals_out);
+}
+
+void fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, p, n, v);
+}
+
+}  // namespace mvgs

@@ -1,0 +1,119 @@
+// Launch interfaces of the mvgs kernels (host side, internal to libmvgs).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mvgs_device.h"
+
+namespace mvgs {
+
+// Per-record accumulator stride (floats) of the blend backward:
+// dmx, dmy, dca, dcb, dcc, dopacity, dr, dg, db, E1 term, 2 spare.
+constexpr int kAccStride = 12;
+
+struct GaussianArgs {
+    const float* means;
+    const float* scales;
+    const float* quats;
+    const float* opac;
+    const float* sh;
+    int64_t P;
+    int sh_degree;
+};
+
+struct GradArgs {
+    float* means;
+    float* scales;
+    float* quats;
+    float* opac;
+    float* sh;
+    float* e1;       // may be null (then e2, count are ignored)
+    float* e2;
+    int32_t* count;
+};
+
+// k_preprocess.hip
+void launch_count(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, uint32_t* nrec,
+                  uint32_t* ntiles, hipStream_t s);
+void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,
+                    BlendRec* recs, uint32_t* depth_key, uint2* tile_rect, hipStream_t s);
+void launch_preprocess_bwd(const GaussianArgs& ga, const DevCam* cams, const uint32_t* rec_off,
+                           const BlendRec* recs, const float* acc, const GradArgs& gr, hipStream_t s);
+
+// k_sort.hip
+// Exclusive scan of n u32 values (in may equal out). The total is written to *total64 (device).
+// `scratch` must hold scan_scratch_bytes(n) bytes.
+size_t scan_scratch_bytes(size_t n);
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* total64, void* scratch,
+                        hipStream_t s);
+// Sum of n u32 values as u64 into *total64 (device).
+void reduce_sum_u32(const uint32_t* in, size_t n, uint64_t* total64, void* scratch, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) u32 pairs on bits [0, bits). The input is in keys[0] and
+// vals[0] (or, with identity_values, the values are 0..n-1 and vals[0] is only used as
+// ping-pong space); passes alternate between buffers 0 and 1. Returns the index of the buffer
+// holding the sorted result.
+size_t radix_scratch_bytes(size_t n);
+int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
+                   hipStream_t s);
+
+void fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+
+// Pair emission in depth order: count per sorted record, then (global tile, record) pairs.
+void launch_gather_tile_counts(const uint32_t* sorted_rec, const uint2* tile_rect, uint32_t n, uint32_t* counts,
+                               hipStream_t s);
+void launch_emit_pairs(const uint32_t* sorted_rec, const uint2* tile_rect, const BlendRec* recs,
+                       const DevCam* cams, const uint32_t* pair_off, uint32_t n, uint32_t K, uint32_t* keys,
+                       uint32_t* vals, hipStream_t s);
+void launch_ranges(const uint32_t* keys, uint32_t K, uint2* ranges, hipStream_t s);
+void launch_export_keys(const uint32_t* tile_keys, const uint32_t* vals, const BlendRec* recs,
+                        const DevCam* cams, int B, uint32_t K, uint64_t* keys_out, uint32_t* vals_out,
+                        hipStream_t s);
+
+// k_blend.hip
+struct BlendFwdArgs {
+    const DevCam* cams;
+    int B;
+    uint32_t n_tiles;
+    const uint2* ranges;
+    const uint32_t* vals;
+    const BlendRec* recs;
+    float* const* images;   // device array of B device pointers
+    float* t_final;         // [total pixels]
+    uint32_t* n_last;       // [total pixels]
+};
+struct BlendBwdArgs {
+    const DevCam* cams;
+    int B;
+    uint32_t n_tiles;
+    const uint2* ranges;
+    const uint32_t* vals;
+    const BlendRec* recs;
+    const float* const* dl_dimg;  // device array of B device pointers
+    const float* t_final;
+    const uint32_t* n_last;
+    float* acc;             // [V][kAccStride]
+    int want_e1;
+};
+bool blend_supported(int tw, int th);
+void launch_frame_work(const DevCam* cams, int B, const uint2* ranges, const uint32_t* n_last, uint32_t n_pixels,
+                       int tw, int th, uint64_t* steps, hipStream_t s);
+void launch_blend_fwd(const BlendFwdArgs& a, int tw, int th, hipStream_t s);
+void launch_blend_bwd(const BlendBwdArgs& a, int tw, int th, hipStream_t s);
+
+// k_loss.hip
+struct LossView {
+    const float* img;
+    const float* tgt;
+    float* grad;
+    int32_t W, H;
+    uint32_t pix_base;
+    uint32_t pad;
+};
+size_t loss_scratch_bytes(uint32_t total_pixels, int B);
+size_t ssim_map_bytes(uint32_t max_view_pixels);
+void launch_loss(const LossView* views_dev, const LossView* views_host, int B, uint32_t total_pixels, float w_l1,
+                 float w_dssim, float* loss_out, void* scratch, void* maps, hipStream_t s);
+
+}  // namespace mvgs

@@ -1,0 +1,224 @@
+"""Torch-facing API over the mvgs C ABI: a Rasterizer holding one library context, frames,
+the fused loss, and the autograd.Function that makes the rasterizer differentiable.
+
+PyTorch provides device memory and the HIP stream (torch's current stream); every step of the
+forward, loss and backward runs in libmvgs's kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+@dataclass
+class GaussianTensors:
+    """Activated parameters on the GPU: float32, contiguous."""
+    means: torch.Tensor
+    scales: torch.Tensor
+    quats: torch.Tensor
+    opacities: torch.Tensor
+    sh: torch.Tensor
+    sh_degree: int
+
+    @property
+    def P(self) -> int:
+        return int(self.means.shape[0])
+
+    @staticmethod
+    def from_scene(scene, device="cuda") -> "GaussianTensors":
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32).to(device).contiguous()
+        return GaussianTensors(f(scene.means), f(scene.scales), f(scene.quats), f(scene.opacities).reshape(-1),
+                               f(scene.sh), int(scene.sh_degree))
+
+    def check(self):
+        P = self.P
+        K = (self.sh_degree + 1) ** 2
+        shapes = {"means": (P, 3), "scales": (P, 3), "quats": (P, 4), "opacities": (P,), "sh": (P, K, 3)}
+        for n, shp in shapes.items():
+            t = getattr(self, n)
+            if tuple(t.shape) != shp or t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"{n}: expected contiguous float32 cuda tensor of shape {shp}, got "
+                                 f"{tuple(t.shape)} {t.dtype} on {t.device}")
+
+
+class Frame:
+    """Saved forward state (library-owned) for one batch of views."""
+
+    def __init__(self, rast: "Rasterizer", handle: C.c_void_p, cams):
+        self.rast, self.handle, self.cams = rast, handle, list(cams)
+        self.released = False
+
+    def info(self):
+        V, K, T = C.c_int64(), C.c_int64(), C.c_int64()
+        L.check(L.lib().mvgs_frame_info(self.handle, C.byref(V), C.byref(K), C.byref(T)))
+        return dict(records=V.value, pairs=K.value, tiles=T.value)
+
+    def release(self):
+        if not self.released:
+            self.rast.release(self)
+
+
+class Rasterizer:
+    def __init__(self, tile=(16, 16)):
+        self.lib = L.lib()
+        opt = L.mvgs_options()
+        opt.tile_w, opt.tile_h = int(tile[0]), int(tile[1])
+        self.ctx = C.c_void_p()
+        L.check(self.lib.mvgs_create(C.byref(self.ctx), C.byref(opt)))
+        self.tile = (opt.tile_w, opt.tile_h)
+
+    def close(self):
+        if self.ctx:
+            self.lib.mvgs_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _gauss(g: GaussianTensors) -> L.mvgs_gaussians:
+        s = L.mvgs_gaussians()
+        s.P, s.sh_degree = g.P, g.sh_degree
+        s.means, s.scales, s.quats = g.means.data_ptr(), g.scales.data_ptr(), g.quats.data_ptr()
+        s.opacities, s.sh = g.opacities.data_ptr(), g.sh.data_ptr()
+        return s
+
+    def forward(self, g: GaussianTensors, cams, images: Optional[List[torch.Tensor]] = None):
+        """Render every view of `cams`; returns ([3,H,W] float32 images, Frame)."""
+        g.check()
+        dev = g.means.device
+        if images is None:
+            images = [torch.empty((3, c.height, c.width), dtype=torch.float32, device=dev) for c in cams]
+        ca = L.camera_array(cams)
+        gs = self._gauss(g)
+        fr = C.c_void_p()
+        st = self.lib.mvgs_forward(self.ctx, _stream(), C.byref(gs), ca, len(cams),
+                                   L.ptr_array([t.data_ptr() for t in images]), C.byref(fr))
+        L.check(st, self.ctx)
+        return images, Frame(self, fr, cams)
+
+    def loss(self, cams, images, targets, w_l1=1.0, w_dssim=0.0, out=None, grads=None):
+        """Fused L1 + D-SSIM: returns (loss [1] tensor on the GPU, list of dL/dimage)."""
+        dev = images[0].device
+        if out is None:
+            out = torch.empty(1, dtype=torch.float32, device=dev)
+        if grads is None:
+            grads = [torch.empty_like(t) for t in images]
+        ca = L.camera_array(cams)
+        st = self.lib.mvgs_loss(self.ctx, _stream(), ca, len(cams),
+                                L.ptr_array([t.data_ptr() for t in images]),
+                                L.ptr_array([t.data_ptr() for t in targets]), float(w_l1), float(w_dssim),
+                                out.data_ptr(), L.ptr_array([t.data_ptr() for t in grads]))
+        L.check(st, self.ctx)
+        return out, grads
+
+    def backward(self, g: GaussianTensors, frame: Frame, dl_dimages, densify=None, grads=None):
+        """Parameter gradients (overwritten) and, if `densify` = dict(e1, e2, count) tensors, the
+        densification statistics (accumulated)."""
+        g.check()
+        if grads is None:
+            grads = dict(means=torch.empty_like(g.means), scales=torch.empty_like(g.scales),
+                         quats=torch.empty_like(g.quats), opacities=torch.empty_like(g.opacities),
+                         sh=torch.empty_like(g.sh))
+        gr = L.mvgs_grads()
+        gr.means, gr.scales, gr.quats = grads["means"].data_ptr(), grads["scales"].data_ptr(), grads["quats"].data_ptr()
+        gr.opacities, gr.sh = grads["opacities"].data_ptr(), grads["sh"].data_ptr()
+        dz = None
+        if densify is not None:
+            dz = L.mvgs_densify()
+            dz.e1, dz.e2, dz.count = densify["e1"].data_ptr(), densify["e2"].data_ptr(), densify["count"].data_ptr()
+        gs = self._gauss(g)
+        dl = [t.contiguous() for t in dl_dimages]
+        st = self.lib.mvgs_backward(self.ctx, _stream(), C.byref(gs), frame.handle,
+                                    L.ptr_array([t.data_ptr() for t in dl]), C.byref(gr),
+                                    C.byref(dz) if dz is not None else None)
+        L.check(st, self.ctx)
+        return grads
+
+    def release(self, frame: Frame):
+        if not frame.released:
+            L.check(self.lib.mvgs_frame_release(self.ctx, frame.handle), self.ctx)
+            frame.released = True
+
+    def export_binning(self, frame: Frame):
+        """(keys int64 [K] holding the uint64 keys, values int32 [K], ranges int32 [tiles, 2]) on the GPU."""
+        info = frame.info()
+        dev = torch.device("cuda")
+        K, T = max(info["pairs"], 1), max(info["tiles"], 1)
+        keys = torch.empty(K, dtype=torch.int64, device=dev)
+        vals = torch.empty(K, dtype=torch.int32, device=dev)
+        ranges = torch.empty((T, 2), dtype=torch.int32, device=dev)
+        L.check(self.lib.mvgs_export_binning(self.ctx, _stream(), frame.handle, keys.data_ptr(), vals.data_ptr(),
+                                             ranges.data_ptr()), self.ctx)
+        return keys[:info["pairs"]], vals[:info["pairs"]], ranges[:info["tiles"]]
+
+    def export_transmittance(self, frame: Frame):
+        outs = [torch.empty((c.height, c.width), dtype=torch.float32, device="cuda") for c in frame.cams]
+        L.check(self.lib.mvgs_export_transmittance(self.ctx, _stream(), frame.handle,
+                                                   L.ptr_array([t.data_ptr() for t in outs])), self.ctx)
+        return outs
+
+
+class MVGSRasterize(torch.autograd.Function):
+    """images = rasterize(means, scales, quats, opacities, sh) for a fixed camera batch.
+
+    The backward recomputes blend state from the frame's final transmittance and last contributor;
+    if `densify` (dict of e1, e2, count tensors) is given, the statistics are accumulated into it."""
+
+    @staticmethod
+    def forward(ctx, rast: Rasterizer, cams, sh_degree: int, densify, means, scales, quats, opacities, sh):
+        g = GaussianTensors(means.contiguous(), scales.contiguous(), quats.contiguous(), opacities.contiguous(),
+                            sh.contiguous(), sh_degree)
+        images, frame = rast.forward(g, cams)
+        ctx.rast, ctx.frame, ctx.sh_degree, ctx.densify = rast, frame, sh_degree, densify
+        ctx.save_for_backward(g.means, g.scales, g.quats, g.opacities, g.sh)
+        return tuple(images)
+
+    @staticmethod
+    def backward(ctx, *grad_images):
+        means, scales, quats, opacities, sh = ctx.saved_tensors
+        g = GaussianTensors(means, scales, quats, opacities, sh, ctx.sh_degree)
+        dl = [gi if gi is not None else torch.zeros((3, c.height, c.width), device=means.device)
+              for gi, c in zip(grad_images, ctx.frame.cams)]
+        grads = ctx.rast.backward(g, ctx.frame, dl, densify=ctx.densify)
+        ctx.rast.release(ctx.frame)
+        return (None, None, None, None, grads["means"], grads["scales"], grads["quats"], grads["opacities"],
+                grads["sh"])
+
+
+def rasterize(rast: Rasterizer, cams, g: GaussianTensors, densify=None):
+    return MVGSRasterize.apply(rast, cams, g.sh_degree, densify, g.means, g.scales, g.quats, g.opacities, g.sh)
+
+
+class FusedLoss(torch.autograd.Function):
+    """L = w_l1 L1 + w_dssim D-SSIM over a batch of views, image gradients from the fused kernel."""
+
+    @staticmethod
+    def forward(ctx, rast: Rasterizer, cams, targets, w_l1: float, w_dssim: float, *images):
+        loss, grads = rast.loss(cams, [i.contiguous() for i in images], targets, w_l1, w_dssim)
+        ctx.grads = grads
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, gl):
+        return (None, None, None, None, None) + tuple(g * gl for g in ctx.grads)
+
+
+def fused_loss(rast: Rasterizer, cams, images: Sequence[torch.Tensor], targets, w_l1=1.0, w_dssim=0.0):
+    return FusedLoss.apply(rast, cams, targets, float(w_l1), float(w_dssim), *images)

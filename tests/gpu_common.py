@@ -1,0 +1,64 @@
+"""Helpers shared by the GPU parity tests: run the HIP path on seeded inputs and bring results
+back as numpy arrays for comparison with the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2506_12727_amd import scenes
+from paper_2506_12727_amd.raster import GaussianTensors, Rasterizer
+
+# tolerances (images: 1e-5 relative + 1e-6 absolute; gradients: 1e-3 relative)
+IMG_RTOL, IMG_ATOL = 1e-5, 1e-6
+GRAD_RTOL, GRAD_INF = 1e-3, 1e-4
+GRAD_L2 = 1e-3
+
+
+def needs_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def run_forward(scene, cams, tile=(16, 16), rast=None):
+    r = rast or Rasterizer(tile)
+    g = GaussianTensors.from_scene(scene)
+    imgs, fr = r.forward(g, cams)
+    torch.cuda.synchronize()
+    return r, g, imgs, fr
+
+
+def to_np(ts):
+    return [t.detach().cpu().numpy().astype(np.float64) for t in ts]
+
+
+def compare_images(gpu, ora, flags, rtol=IMG_RTOL, atol=IMG_ATOL):
+    """Element-wise image check outside flagged pixels; returns the flagged fraction."""
+    nflag = ntot = 0
+    for a, b, f in zip(gpu, ora, flags):
+        ok = f == 0
+        nflag += int((~ok).sum())
+        ntot += ok.size
+        err = np.abs(a - b)
+        lim = rtol * np.abs(b) + atol
+        bad = (err > lim) & ok[None] if a.ndim == 3 else (err > lim) & ok
+        if bad.any():
+            idx = np.argwhere(bad)[:5]
+            raise AssertionError(f"{int(bad.sum())} elements out of tolerance, e.g. {idx.tolist()}: "
+                                 f"gpu {a[tuple(idx[0])]} oracle {b[tuple(idx[0])]}")
+    return nflag / max(ntot, 1)
+
+
+def compare_grad(name, gpu, ora, rtol=GRAD_RTOL, inf=GRAD_INF, l2=GRAD_L2, mask=None):
+    gpu = np.asarray(gpu, np.float64).reshape(ora.shape)
+    if mask is not None:
+        gpu, ora = gpu[mask], ora[mask]
+    scale = np.abs(ora).max()
+    assert scale > 0, f"{name}: oracle gradient is all zero"
+    err = np.abs(gpu - ora)
+    lim = rtol * np.abs(ora) + inf * scale
+    bad = err > lim
+    frac_bad = bad.mean()
+    rel_l2 = np.linalg.norm(gpu - ora) / np.linalg.norm(ora)
+    assert rel_l2 <= l2, f"{name}: relative L2 error {rel_l2:.3e}"
+    assert not bad.any(), (f"{name}: {int(bad.sum())} of {bad.size} elements out of tolerance; worst "
+                           f"{err.max():.3e} vs scale {scale:.3e}")
+    return rel_l2

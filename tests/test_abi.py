@@ -1,0 +1,123 @@
+"""The C ABI without a GPU: the library loads, exports every call include/mvgs.h declares, and
+rejects invalid arguments with MVGS_EINVAL before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2506_12727_amd import _lib as L
+from paper_2506_12727_amd import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mvgs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mvgs_\w+)\s*\(", src)))
+
+
+def test_header_declarations_are_exported():
+    lib = L.lib()
+    names = _declared()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTED)
+
+
+def test_status_strings():
+    lib = L.lib()
+    for code in (L.MVGS_OK, L.MVGS_EINVAL, L.MVGS_ENOMEM, L.MVGS_ECAPACITY, L.MVGS_EHIP):
+        assert lib.mvgs_status_string(code)
+    assert lib.mvgs_status_string(-99) == b"unknown status"
+
+
+@pytest.fixture()
+def ctx():
+    lib = L.lib()
+    h = C.c_void_p()
+    assert lib.mvgs_create(C.byref(h), None) == L.MVGS_OK
+    yield h
+    lib.mvgs_destroy(h)
+
+
+def test_create_rejects_bad_tiles():
+    lib = L.lib()
+    for tw, th in [(4, 16), (16, 12), (64, 16), (-8, 8)]:
+        o = L.mvgs_options()
+        o.tile_w, o.tile_h = tw, th
+        h = C.c_void_p()
+        assert lib.mvgs_create(C.byref(h), C.byref(o)) == L.MVGS_EINVAL
+    assert lib.mvgs_create(None, None) == L.MVGS_EINVAL
+
+
+def _gauss(P=10, deg=0, ptr=0x1000):
+    g = L.mvgs_gaussians()
+    g.P, g.sh_degree = P, deg
+    g.means = g.scales = g.quats = g.opacities = g.sh = ptr
+    return g
+
+
+def _fwd(ctx, g, cams, images="auto"):
+    lib = L.lib()
+    ca = L.camera_array(cams) if cams is not None else None
+    n = len(cams) if cams is not None else 0
+    if images == "auto":
+        images = L.ptr_array([0x2000] * max(n, 1))
+    fr = C.c_void_p()
+    return lib.mvgs_forward(ctx, None, C.byref(g) if g is not None else None, ca, n, images, C.byref(fr))
+
+
+def _err(ctx):
+    return L.lib().mvgs_last_error(ctx).decode()
+
+
+def test_forward_argument_validation(ctx):
+    cams = scenes.make_cameras([(64, 48), (32, 32)])
+    assert _fwd(ctx, None, cams) == L.MVGS_EINVAL
+    assert _fwd(ctx, _gauss(deg=4), cams) == L.MVGS_EINVAL and "sh_degree" in _err(ctx)
+    assert _fwd(ctx, _gauss(P=-1), cams) == L.MVGS_EINVAL
+    assert _fwd(ctx, _gauss(P=5, ptr=0), cams) == L.MVGS_EINVAL and "NULL" in _err(ctx)
+    assert _fwd(ctx, _gauss(), []) == L.MVGS_EINVAL                       # B = 0
+    assert _fwd(ctx, _gauss(), cams, images=None) == L.MVGS_EINVAL
+    assert _fwd(ctx, _gauss(), cams, images=L.ptr_array([0x2000, 0])) == L.MVGS_EINVAL
+    bad = scenes.make_cameras([(64, 48)])
+    bad[0].fx = 0.0
+    assert _fwd(ctx, _gauss(), bad) == L.MVGS_EINVAL and "focal" in _err(ctx)
+    bad = scenes.make_cameras([(0, 48)])
+    assert _fwd(ctx, _gauss(), bad) == L.MVGS_EINVAL
+    # 4096 x 4096 at 16x16 is exactly 65536 tiles (allowed); one more column of tiles is not
+    big = scenes.make_cameras([(4097, 4096)])
+    assert _fwd(ctx, _gauss(), big) == L.MVGS_EINVAL and "tiles" in _err(ctx)
+    lib = L.lib()
+    assert lib.mvgs_forward(ctx, None, C.byref(_gauss()), L.camera_array(cams), 2,
+                            L.ptr_array([0x2000] * 2), None) == L.MVGS_EINVAL
+    assert lib.mvgs_forward(None, None, None, None, 0, None, None) == L.MVGS_EINVAL
+
+
+def test_loss_and_backward_validation(ctx):
+    lib = L.lib()
+    cams = scenes.make_cameras([(16, 16)])
+    ca = L.camera_array(cams)
+    p = L.ptr_array([0x2000])
+    assert lib.mvgs_loss(ctx, None, ca, 0, p, p, 1.0, 0.0, 0x3000, p) == L.MVGS_EINVAL
+    assert lib.mvgs_loss(ctx, None, ca, 1, None, p, 1.0, 0.0, 0x3000, p) == L.MVGS_EINVAL
+    assert lib.mvgs_loss(ctx, None, ca, 1, p, p, float("nan"), 0.0, 0x3000, p) == L.MVGS_EINVAL
+    gr = L.mvgs_grads()
+    assert lib.mvgs_backward(ctx, None, C.byref(_gauss()), None, p, C.byref(gr), None) == L.MVGS_EINVAL
+    assert lib.mvgs_frame_release(ctx, None) == L.MVGS_EINVAL
+    assert lib.mvgs_frame_info(None, None, None, None) == L.MVGS_EINVAL
+    assert lib.mvgs_export_binning(ctx, None, None, None, None, None) == L.MVGS_EINVAL
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The GPU package never imports the oracle (the oracle is test infrastructure)."""
+    pkg = os.path.join(ROOT, "paper_2506_12727_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src and "liboracle" not in src, f

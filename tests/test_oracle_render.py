@@ -132,3 +132,19 @@ def test_gaussian_behind_camera_contributes_nothing(ora):
     sc = _scene([[0.0, 0.0, -4.0]], [[0.5] * 3], [[1, 0, 0, 0]], [0.9], [[1, 1, 1]])
     f = ora.forward(sc, [cam])
     assert np.all(f["images"][0] == 0.0) and np.all(f["t_final"][0] == 1.0)
+
+
+def test_sampled_pixels_equal_full_render(ora):
+    sc = scenes.make_scene(2500, 1, log_scale_mean=-3.0)
+    cams = scenes.make_cameras([(61, 47), (40, 33)])
+    f = ora.forward(sc, cams)
+    rng = np.random.default_rng(0)
+    for v, c in enumerate(cams):
+        xs, ys = rng.integers(0, c.width, 40), rng.integers(0, c.height, 40)
+        rgb, tf, fl = ora.render_pixels(sc, cams, v, xs, ys)
+        assert np.array_equal(rgb, f["images"][v][:, ys, xs].T)
+        assert np.array_equal(tf, f["t_final"][v][ys, xs])
+        assert np.array_equal(fl, f["flags"][v][ys, xs])
+    recs, pairs = ora.count_pairs(sc, cams)
+    assert pairs == len(ora.binning(sc, cams)[0])
+    assert recs == sum(int(ora.geom32(sc, cams, v)["participates"].sum()) for v in range(2))
