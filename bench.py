@@ -43,7 +43,9 @@ def parse():
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--no-loop", action="store_true", help="skip the one-view-per-call comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-views", type=int, default=1, help="views of the workload in the CPU sample")
+    ap.add_argument("--cpu-views", type=int, default=2, help="views of the workload in the CPU sample")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -82,22 +84,29 @@ def main():
         dz = dict(e1=torch.zeros(g.P, device="cuda"), e2=torch.zeros(g.P, device="cuda"),
                   count=torch.zeros(g.P, dtype=torch.int32, device="cuda"))
 
-    def step(views, images, dls):
+    def step(idx):
+        views = [cams[i] for i in idx]
+        images = [imgs[i] for i in idx]
+        dls = [dl[i] for i in idx]
         _, fr = rast.forward(g, views, images=images)
-        rast.loss(views, images, [tg[cams.index(v)] for v in views] if len(views) != B else tg, wl.w_l1,
-                  wl.w_dssim, out=loss, grads=dls)
+        rast.loss(views, images, [tg[i] for i in idx], wl.w_l1, wl.w_dssim, out=loss, grads=dls)
         rast.backward(g, fr, dls, densify=dz, grads=grads)
         return fr
 
     def batched():
-        fr = step(cams, imgs, dl)
-        rast.release(fr)
+        rast.release(step(list(range(B))))
 
     def loop():
         for v in range(B):
-            fr = step([cams[v]], [imgs[v]], [dl[v]])
-            rast.release(fr)
+            rast.release(step([v]))
 
+    if args.copy_mib:
+        src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         batched()
     torch.cuda.synchronize()
