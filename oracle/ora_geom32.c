@@ -14,10 +14,12 @@
  * covariance); Appendix "Rasterization in multi-view training" (frustum culling,
  * duplication per covered tile, depth in the sort key). The paper gives no
  * formulas for culling, radius or cut; the readings used are: near plane
- * z > 0.2, dilation +0.3 px^2 on the 2D covariance diagonal, radius
- * ceil(3 sqrt(lambda_max)), pixel centres at (x+0.5, y+0.5), a pixel is covered
- * iff power >= -4.5 (inside the 3-sigma ellipse), and alpha < 1/255 is skipped,
- * tested as power < -ln(255 o) so that no exponential is needed for the decision.
+ * z > 0.2, dilation +0.3 px^2 on the 2D covariance diagonal,
+ * pixel centres at (x+0.5, y+0.5), a pixel is covered iff power >= cut with
+ * cut = max(-4.5, -ln(255 o)) (inside the 3-sigma ellipse and alpha >= 1/255,
+ * the latter tested in the power domain so that no exponential enters the
+ * decision), and the footprint is the pixel box of the per-axis extents of
+ * that cut ellipse.
  */
 #include <math.h>
 #include <stdint.h>
@@ -146,16 +148,20 @@ void ora_geom32_eval(const float mu[3], const float s[3], const float q[4], floa
     g->nb = -g->cb;
     g->hcc = -0.5f * g->cc;
 
-    /* radius from the larger eigenvalue of Sigma' */
-    float mid = 0.5f * (a + c);
-    float disc = fmaf(mid, mid, -det);
-    float lam = mid + sqrtf(disc > 0.0f ? disc : 0.0f);
-    float rad = ceilf(3.0f * sqrtf(lam));
-    g->radius = rad;
+    /* opacity thresholds in the power domain */
+    float lc = -ora_ln32(255.0f * o);
+    const float cut = (lc > -4.5f) ? lc : -4.5f;
 
-    /* inclusive pixel box of the square [m - r, m + r], clipped to the image */
-    float x0 = floorf(mx - rad), x1 = floorf(mx + rad);
-    float y0 = floorf(my - rad), y1 = floorf(my + rad);
+    /* footprint: per-axis half-extents of the cut ellipse {d : -0.5 d^T conic d >= cut}, i.e.
+     * sqrt(-2 cut Sigma'_xx) and sqrt(-2 cut Sigma'_yy), rounded up to whole pixels */
+    float nc = -2.0f * cut;
+    float rx = ceilf(sqrtf(nc * a));
+    float ry = ceilf(sqrtf(nc * c));
+    g->radius = rx > ry ? rx : ry;
+
+    /* inclusive pixel box of [mx - rx, mx + rx] x [my - ry, my + ry], clipped to the image */
+    float x0 = floorf(mx - rx), x1 = floorf(mx + rx);
+    float y0 = floorf(my - ry), y1 = floorf(my + ry);
     float wmax = (float)(W - 1), hmax = (float)(H - 1);
     if (x0 < 0.0f) x0 = 0.0f;
     if (y0 < 0.0f) y0 = 0.0f;
@@ -167,9 +173,7 @@ void ora_geom32_eval(const float mu[3], const float s[3], const float q[4], floa
     g->y0 = (int32_t)y0;
     g->y1 = (int32_t)y1;
 
-    /* opacity thresholds in the power domain */
-    float lc = -ora_ln32(255.0f * o);
-    g->cut = (lc > -4.5f) ? lc : -4.5f;
+    g->cut = cut;
     g->hi = ora_ln32(0.99f / o);
     g->participates = 1;
 }

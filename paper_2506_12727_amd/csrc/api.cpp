@@ -490,8 +490,7 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     f->final_buf = radix_sort_u32(pk, pv, false, K, bits_for(n_tiles), ctx->sort_scratch.p, s);
     ctx->stage_end(mk, s);
     mk = ctx->stage_begin(5, s);
-    fill_u32(as<uint32_t>(f->ranges), 2 * (size_t)n_tiles, 0u, s);
-    launch_ranges(pk[f->final_buf], K, as<uint2>(f->ranges), s);
+    launch_ranges(pk[f->final_buf], K, n_tiles, as<uint2>(f->ranges), s);
     ctx->stage_end(mk, s);
 
     // blend every pixel of every view

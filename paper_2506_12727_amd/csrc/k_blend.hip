@@ -38,6 +38,64 @@ __device__ __forceinline__ bool box_misses(uint32_t bx, uint32_t by, int sx0, in
 
 __device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
 
+// Wavefront-uniform copy of the fields the walks use.
+struct RecS {
+    float mx, my, hca, nb, hcc, o, cut, hi, r, g, b;
+};
+
+__device__ __forceinline__ RecS load_rec(const BlendRec* __restrict__ recs, uint32_t r) {
+    const BlendRec* R = recs + r;
+    RecS s;
+    s.mx = R->mx; s.my = R->my; s.hca = R->hca; s.nb = R->nb; s.hcc = R->hcc; s.o = R->o;
+    s.cut = R->cut; s.hi = R->hi; s.r = R->r; s.g = R->g; s.b = R->b;
+    return s;
+}
+
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t v, int lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+// Candidate window: lane k looks at list entry base + k, loads its record index and pixel box with
+// one vector load each, and the ballot keeps the entries whose box meets the wavefront's sub-tile.
+__device__ __forceinline__ uint64_t window_mask(const uint32_t* __restrict__ vals, const BlendRec* __restrict__ recs,
+                                                uint32_t base, uint32_t end, int lane, int sx0, int sx1, int sy0,
+                                                int sy1, uint32_t& rl) {
+    const uint32_t idx = base + (uint32_t)lane;
+    bool keep = false;
+    rl = 0;
+    if (idx < end) {
+        rl = vals[idx];
+        const uint2 bx = *reinterpret_cast<const uint2*>(recs + rl);
+        keep = !box_misses(bx.x, bx.y, sx0, sx1, sy0, sy1);
+    }
+    return ballot64(keep);
+}
+
+struct FwdState {
+    float T, C0, C1, C2;
+    uint32_t last;
+    bool done;
+};
+
+__device__ __forceinline__ void blend_step(FwdState& st, const RecS& q, float px, float py, uint32_t pos) {
+    if (st.done) return;
+    const float power = pixel_power(px, py, q.mx, q.my, q.hca, q.nb, q.hcc);
+    if (power >= q.cut) {
+        const float alpha = (power > q.hi) ? kAlphaMax : q.o * fast_exp(power);
+        const float Tn = __builtin_fmaf(-st.T, alpha, st.T);
+        if (Tn < kTStop) {
+            st.done = true;
+        } else {
+            const float w = alpha * st.T;
+            st.C0 = __builtin_fmaf(q.r, w, st.C0);
+            st.C1 = __builtin_fmaf(q.g, w, st.C1);
+            st.C2 = __builtin_fmaf(q.b, w, st.C2);
+            st.T = Tn;
+            st.last = pos + 1;
+        }
+    }
+}
+
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH) k_blend_fwd(const DevCam* __restrict__ cams, int B, uint32_t n_tiles,
                                                        const uint2* __restrict__ ranges,
@@ -62,42 +120,43 @@ __global__ void __launch_bounds__(TW * TH) k_blend_fwd(const DevCam* __restrict_
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     const uint2 rg = ranges[tile];
 
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    uint32_t last = 0;
-    bool done = !valid;
-    for (uint32_t i = rg.x; i < rg.y; ++i) {
-        if (ballot64(!done) == 0) break;
-        const BlendRec* R = recs + vals[i];
-        if (box_misses(R->boxx, R->boxy, sx0, sx1, sy0, sy1)) continue;
-        const float mx = R->mx, my = R->my, hca = R->hca, nb = R->nb, hcc = R->hcc, o = R->o;
-        const float cut = R->cut, hi = R->hi, cr = R->r, cg = R->g, cb = R->b;
-        if (!done) {
-            const float power = pixel_power(px, py, mx, my, hca, nb, hcc);
-            if (power >= cut) {
-                const float alpha = (power > hi) ? kAlphaMax : o * fast_exp(power);
-                const float Tn = __builtin_fmaf(-T, alpha, T);
-                if (Tn < kTStop) {
-                    done = true;
-                } else {
-                    const float w = alpha * T;
-                    C0 = __builtin_fmaf(cr, w, C0);
-                    C1 = __builtin_fmaf(cg, w, C1);
-                    C2 = __builtin_fmaf(cb, w, C2);
-                    T = Tn;
-                    last = i + 1;
-                }
-            }
+    FwdState st{1.0f, 0.0f, 0.0f, 0.0f, 0u, !valid};
+    for (uint32_t base = rg.x; base < rg.y; base += 64) {
+        if (ballot64(!st.done) == 0) break;
+        uint32_t rl;
+        uint64_t m = window_mask(vals, recs, base, rg.y, lane, sx0, sx1, sy0, sy1, rl);
+        while (m) {
+            // up to four records per round trip through the scalar cache
+            const int j0 = __builtin_ctzll(m);
+            m &= m - 1;
+            const int j1 = m ? __builtin_ctzll(m) : j0;
+            if (m) m &= m - 1;
+            const bool h1 = j1 != j0;
+            const int j2 = m ? __builtin_ctzll(m) : j0;
+            if (m) m &= m - 1;
+            const bool h2 = j2 != j0;
+            const int j3 = m ? __builtin_ctzll(m) : j0;
+            if (m) m &= m - 1;
+            const bool h3 = j3 != j0;
+            const RecS q0 = load_rec(recs, readlane_u32(rl, j0));
+            const RecS q1 = load_rec(recs, readlane_u32(rl, j1));
+            const RecS q2 = load_rec(recs, readlane_u32(rl, j2));
+            const RecS q3 = load_rec(recs, readlane_u32(rl, j3));
+            blend_step(st, q0, px, py, base + (uint32_t)j0);
+            if (h1) blend_step(st, q1, px, py, base + (uint32_t)j1);
+            if (h2) blend_step(st, q2, px, py, base + (uint32_t)j2);
+            if (h3) blend_step(st, q3, px, py, base + (uint32_t)j3);
         }
     }
     if (valid) {
         const size_t hw = (size_t)c.W * c.H;
         const size_t pix = (size_t)y * c.W + x;
         float* img = images[v];
-        img[pix] = __builtin_fmaf(T, c.bg[0], C0);
-        img[hw + pix] = __builtin_fmaf(T, c.bg[1], C1);
-        img[2 * hw + pix] = __builtin_fmaf(T, c.bg[2], C2);
-        t_final[c.pix_base + pix] = T;
-        n_last[c.pix_base + pix] = last;
+        img[pix] = __builtin_fmaf(st.T, c.bg[0], st.C0);
+        img[hw + pix] = __builtin_fmaf(st.T, c.bg[1], st.C1);
+        img[2 * hw + pix] = __builtin_fmaf(st.T, c.bg[2], st.C2);
+        t_final[c.pix_base + pix] = st.T;
+        n_last[c.pix_base + pix] = st.last;
     }
 }
 
@@ -108,6 +167,71 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
         v = v > o ? v : o;
     }
     return v;
+}
+
+struct BwdState {
+    float T, dC0, dC1, dC2, Rb0, Rb1, Rb2;
+    uint32_t last;
+};
+
+// One Gaussian of the reverse walk: this lane's contributions, summed over the wavefront and
+// added to the record's accumulators.
+template <bool E1>
+__device__ __forceinline__ void unblend_step(BwdState& st, const RecS& q, uint32_t r, uint32_t pos, float px,
+                                             float py, float half_w, float half_h, int lane,
+                                             float* __restrict__ acc) {
+    float g_mx = 0.f, g_my = 0.f, g_ca = 0.f, g_cb = 0.f, g_cc = 0.f, g_o = 0.f;
+    float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_e1 = 0.f;
+    bool contrib = false;
+    if (pos < st.last) {
+        const float dx = px - q.mx, dy = py - q.my;
+        const float power = pixel_power(px, py, q.mx, q.my, q.hca, q.nb, q.hcc);
+        if (power >= q.cut) {
+            contrib = true;
+            const bool clamped = power > q.hi;
+            const float G = fast_exp(power);
+            const float alpha = clamped ? kAlphaMax : q.o * G;
+            st.T = st.T * __builtin_amdgcn_rcpf(1.0f - alpha);   // transmittance in front of this Gaussian
+            const float w = alpha * st.T;
+            g_r = st.dC0 * w;
+            g_g = st.dC1 * w;
+            g_b = st.dC2 * w;
+            const float dalpha = st.T * (st.dC0 * (q.r - st.Rb0) + st.dC1 * (q.g - st.Rb1) + st.dC2 * (q.b - st.Rb2));
+            st.Rb0 = __builtin_fmaf(q.r - st.Rb0, alpha, st.Rb0);
+            st.Rb1 = __builtin_fmaf(q.g - st.Rb1, alpha, st.Rb1);
+            st.Rb2 = __builtin_fmaf(q.b - st.Rb2, alpha, st.Rb2);
+            if (!clamped) {
+                g_o = dalpha * G;
+                const float dpow = dalpha * alpha;
+                const float ca = -2.0f * q.hca, cbq = -q.nb, cc = -2.0f * q.hcc;
+                g_mx = dpow * (ca * dx + cbq * dy);
+                g_my = dpow * (cbq * dx + cc * dy);
+                g_ca = -0.5f * dpow * dx * dx;
+                g_cb = -dpow * dx * dy;
+                g_cc = -0.5f * dpow * dy * dy;
+                if (E1) {
+                    const float nx = g_mx * half_w, ny = g_my * half_h;
+                    g_e1 = sqrtf(nx * nx + ny * ny);
+                }
+            }
+        }
+    }
+    if (ballot64(contrib) == 0) return;
+    const float s0 = wave_sum(g_mx), s1 = wave_sum(g_my), s2 = wave_sum(g_ca), s3 = wave_sum(g_cb);
+    const float s4 = wave_sum(g_cc), s5 = wave_sum(g_o), s6 = wave_sum(g_r), s7 = wave_sum(g_g);
+    const float s8 = wave_sum(g_b);
+    const float s9 = E1 ? wave_sum(g_e1) : 0.0f;
+    float val = s0;
+    val = lane == 1 ? s1 : val;
+    val = lane == 2 ? s2 : val;
+    val = lane == 3 ? s3 : val;
+    val = lane == 4 ? s4 : val;
+    val = lane == 5 ? s5 : val;
+    val = lane == 6 ? s6 : val;
+    val = lane == 7 ? s7 : val;
+    val = lane == 8 ? s8 : val;
+    val = lane == 9 ? s9 : val;
+    if (lane < (E1 ? 10 : 9)) unsafeAtomicAdd(acc + (size_t)r * kAccStride + lane, val);
 }
 
 template <int TW, int TH, bool E1>
@@ -137,80 +261,48 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(const DevCam* __restrict_
     const uint2 rg = ranges[tile];
     const float half_w = 0.5f * (float)c.W, half_h = 0.5f * (float)c.H;
 
-    float T = 1.0f, dC0 = 0.0f, dC1 = 0.0f, dC2 = 0.0f;
-    uint32_t last = 0;
+    BwdState st{1.0f, 0.0f, 0.0f, 0.0f, c.bg[0], c.bg[1], c.bg[2], 0u};
     if (valid) {
         const size_t hw = (size_t)c.W * c.H;
         const size_t pix = (size_t)y * c.W + x;
         const float* g = dl_dimg[v];
-        dC0 = g[pix];
-        dC1 = g[hw + pix];
-        dC2 = g[2 * hw + pix];
-        T = t_final[c.pix_base + pix];
-        last = n_last[c.pix_base + pix];
+        st.dC0 = g[pix];
+        st.dC1 = g[hw + pix];
+        st.dC2 = g[2 * hw + pix];
+        st.T = t_final[c.pix_base + pix];
+        st.last = n_last[c.pix_base + pix];
     }
-    float Rb0 = c.bg[0], Rb1 = c.bg[1], Rb2 = c.bg[2];
-    const uint32_t hi_end = __builtin_amdgcn_readfirstlane(wave_max_u32(last));
+    const uint32_t hi_end = __builtin_amdgcn_readfirstlane(wave_max_u32(st.last));
 
-    for (uint32_t i = hi_end; i > rg.x;) {
-        --i;
-        const uint32_t r = vals[i];
-        const BlendRec* R = recs + r;
-        if (box_misses(R->boxx, R->boxy, sx0, sx1, sy0, sy1)) continue;
-        const float mx = R->mx, my = R->my, hca = R->hca, nb = R->nb, hcc = R->hcc, o = R->o;
-        const float cut = R->cut, hi = R->hi, cr = R->r, cg = R->g, cb = R->b;
-        float g_mx = 0.f, g_my = 0.f, g_ca = 0.f, g_cb = 0.f, g_cc = 0.f, g_o = 0.f;
-        float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_e1 = 0.f;
-        bool contrib = false;
-        if (i < last) {
-            const float dx = px - mx, dy = py - my;
-            const float power = pixel_power(px, py, mx, my, hca, nb, hcc);
-            if (power >= cut) {
-                contrib = true;
-                const bool clamped = power > hi;
-                const float G = fast_exp(power);
-                const float alpha = clamped ? kAlphaMax : o * G;
-                T = T * __builtin_amdgcn_rcpf(1.0f - alpha);   // transmittance in front of this Gaussian
-                const float w = alpha * T;
-                g_r = dC0 * w;
-                g_g = dC1 * w;
-                g_b = dC2 * w;
-                const float dalpha = T * (dC0 * (cr - Rb0) + dC1 * (cg - Rb1) + dC2 * (cb - Rb2));
-                Rb0 = __builtin_fmaf(cr - Rb0, alpha, Rb0);
-                Rb1 = __builtin_fmaf(cg - Rb1, alpha, Rb1);
-                Rb2 = __builtin_fmaf(cb - Rb2, alpha, Rb2);
-                if (!clamped) {
-                    g_o = dalpha * G;
-                    const float dpow = dalpha * alpha;
-                    const float ca = -2.0f * hca, cbq = -nb, cc = -2.0f * hcc;
-                    g_mx = dpow * (ca * dx + cbq * dy);
-                    g_my = dpow * (cbq * dx + cc * dy);
-                    g_ca = -0.5f * dpow * dx * dx;
-                    g_cb = -dpow * dx * dy;
-                    g_cc = -0.5f * dpow * dy * dy;
-                    if (E1) {
-                        const float nx = g_mx * half_w, ny = g_my * half_h;
-                        g_e1 = sqrtf(nx * nx + ny * ny);
-                    }
-                }
-            }
+    for (uint32_t top = hi_end; top > rg.x;) {
+        const uint32_t base = top - rg.x > 64u ? top - 64u : rg.x;
+        uint32_t rl;
+        uint64_t m = window_mask(vals, recs, base, top, lane, sx0, sx1, sy0, sy1, rl);
+        top = base;
+        while (m) {
+            // highest list position first; up to four records per round trip
+            const int j0 = 63 - __builtin_clzll(m);
+            m &= ~(1ull << j0);
+            const int j1 = m ? 63 - __builtin_clzll(m) : j0;
+            if (m) m &= ~(1ull << j1);
+            const bool h1 = j1 != j0;
+            const int j2 = m ? 63 - __builtin_clzll(m) : j0;
+            if (m) m &= ~(1ull << j2);
+            const bool h2 = j2 != j0;
+            const int j3 = m ? 63 - __builtin_clzll(m) : j0;
+            if (m) m &= ~(1ull << j3);
+            const bool h3 = j3 != j0;
+            const uint32_t r0 = readlane_u32(rl, j0), r1 = readlane_u32(rl, j1);
+            const uint32_t r2 = readlane_u32(rl, j2), r3 = readlane_u32(rl, j3);
+            const RecS q0 = load_rec(recs, r0);
+            const RecS q1 = load_rec(recs, r1);
+            const RecS q2 = load_rec(recs, r2);
+            const RecS q3 = load_rec(recs, r3);
+            unblend_step<E1>(st, q0, r0, base + (uint32_t)j0, px, py, half_w, half_h, lane, acc);
+            if (h1) unblend_step<E1>(st, q1, r1, base + (uint32_t)j1, px, py, half_w, half_h, lane, acc);
+            if (h2) unblend_step<E1>(st, q2, r2, base + (uint32_t)j2, px, py, half_w, half_h, lane, acc);
+            if (h3) unblend_step<E1>(st, q3, r3, base + (uint32_t)j3, px, py, half_w, half_h, lane, acc);
         }
-        if (ballot64(contrib) == 0) continue;
-        const float s0 = wave_sum(g_mx), s1 = wave_sum(g_my), s2 = wave_sum(g_ca), s3 = wave_sum(g_cb);
-        const float s4 = wave_sum(g_cc), s5 = wave_sum(g_o), s6 = wave_sum(g_r), s7 = wave_sum(g_g);
-        const float s8 = wave_sum(g_b);
-        const float s9 = E1 ? wave_sum(g_e1) : 0.0f;
-        float val = s0;
-        val = lane == 1 ? s1 : val;
-        val = lane == 2 ? s2 : val;
-        val = lane == 3 ? s3 : val;
-        val = lane == 4 ? s4 : val;
-        val = lane == 5 ? s5 : val;
-        val = lane == 6 ? s6 : val;
-        val = lane == 7 ? s7 : val;
-        val = lane == 8 ? s8 : val;
-        val = lane == 9 ? s9 : val;
-        if (lane < (E1 ? 10 : 9)) unsafeAtomicAdd(acc + (size_t)r * kAccStride + lane, val);
     }
 }
 

@@ -301,34 +301,81 @@ __global__ void k_gather_tile_counts(const uint32_t* __restrict__ sorted_rec, co
     if (i < n) counts[i] = rect_tiles(rect[sorted_rec[i]]);
 }
 
-__global__ void k_emit_pairs(const uint32_t* __restrict__ sorted_rec, const uint2* __restrict__ rect,
-                             const BlendRec* __restrict__ recs, const DevCam* __restrict__ cams,
-                             const uint32_t* __restrict__ pair_off, uint32_t n, uint32_t K,
-                             uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t r = sorted_rec[i];
-    const uint2 rc = rect[r];
-    const uint32_t v = recs[r].view;
-    const uint32_t tb = cams[v].tile_base;
-    const uint32_t tx_n = (uint32_t)cams[v].tiles_x;
-    const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu, ty1 = rc.y >> 16;
-    uint32_t o = pair_off[i];
-    for (uint32_t ty = ty0; ty <= ty1; ++ty)
-        for (uint32_t tx = tx0; tx <= tx1; ++tx) {
-            if (o >= K) return;
-            keys[o] = tb + ty * tx_n + tx;
-            vals[o] = r;
-            ++o;
+// Load-balanced emission: a workgroup takes 256 consecutive records of the depth order; their
+// pairs are contiguous in the output, so the workgroup's lanes walk those pairs in order (each
+// store is coalesced across the wavefront) and find their record by binary search over the
+// workgroup's prefix sums in LDS. Pair j of a record with a w-tile-wide rectangle is tile
+// (tx0 + j mod w, ty0 + j / w), row-major, as a per-record loop would emit them.
+constexpr int kEmitThreads = 256;
+
+__global__ void __launch_bounds__(kEmitThreads) k_emit_pairs(const uint32_t* __restrict__ sorted_rec,
+                                                             const uint2* __restrict__ rect,
+                                                             const BlendRec* __restrict__ recs,
+                                                             const DevCam* __restrict__ cams,
+                                                             const uint32_t* __restrict__ pair_off, uint32_t n,
+                                                             uint32_t K, uint32_t* __restrict__ keys,
+                                                             uint32_t* __restrict__ vals) {
+    __shared__ uint32_t s_off[kEmitThreads + 1];   // local exclusive offsets (+ total)
+    __shared__ uint32_t s_rec[kEmitThreads];
+    __shared__ uint32_t s_x[kEmitThreads];         // tx0 | w << 16
+    __shared__ uint32_t s_base[kEmitThreads];      // tile id of (tx0, ty0)
+    __shared__ uint32_t s_stride[kEmitThreads];    // tiles_x of the record's view
+    const uint32_t i0 = blockIdx.x * kEmitThreads;
+    const uint32_t i = i0 + threadIdx.x;
+    const uint32_t base_out = pair_off[i0];
+    if (i < n) {
+        const uint32_t r = sorted_rec[i];
+        const uint2 rc = rect[r];
+        const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
+        const DevCam& c = cams[recs[r].view];
+        s_rec[threadIdx.x] = r;
+        s_x[threadIdx.x] = tx0 | ((tx1 - tx0 + 1) << 16);
+        s_base[threadIdx.x] = c.tile_base + ty0 * (uint32_t)c.tiles_x + tx0;
+        s_stride[threadIdx.x] = (uint32_t)c.tiles_x;
+        s_off[threadIdx.x] = pair_off[i] - base_out;
+    }
+    const uint32_t last = min(n - i0, (uint32_t)kEmitThreads);
+    if (threadIdx.x == 0) s_off[last] = (i0 + last < n ? pair_off[i0 + last] : K) - base_out;
+    __syncthreads();
+    const uint32_t total = s_off[last];
+    for (uint32_t j = threadIdx.x; j < total; j += kEmitThreads) {
+        // record k with s_off[k] <= j < s_off[k + 1]
+        uint32_t lo = 0, hi = last;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_off[mid] <= j) lo = mid;
+            else hi = mid;
         }
+        const uint32_t t = j - s_off[lo];
+        const uint32_t w = s_x[lo] >> 16;
+        // t < 65536, so (t + 0.5) / w in float32 is never within rounding of an integer
+        const uint32_t row = (uint32_t)floorf(((float)t + 0.5f) * __builtin_amdgcn_rcpf((float)w));
+        const uint32_t col = t - row * w;
+        const uint32_t o = base_out + j;
+        if (o >= K) break;
+        keys[o] = s_base[lo] + row * s_stride[lo] + col;
+        vals[o] = s_rec[lo];
+    }
 }
 
-__global__ void k_ranges(const uint32_t* __restrict__ keys, uint32_t K, uint2* __restrict__ ranges) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= K) return;
-    const uint32_t t = keys[i];
-    if (i == 0 || keys[i - 1] != t) ranges[t].x = i;
-    if (i == K - 1 || keys[i + 1] != t) ranges[t].y = i + 1;
+// [start, end) of each global tile's run in the sorted pair keys, by binary search
+__global__ void __launch_bounds__(256) k_ranges_search(const uint32_t* __restrict__ keys, uint32_t K,
+                                                       uint32_t n_tiles, uint2* __restrict__ ranges) {
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_tiles) return;
+    uint32_t lo = 0, hi = K;  // first index with keys[i] >= t
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (keys[mid] < t) lo = mid + 1;
+        else hi = mid;
+    }
+    uint32_t lo2 = lo, hi2 = K;  // first index with keys[i] > t
+    while (lo2 < hi2) {
+        const uint32_t mid = lo2 + ((hi2 - lo2) >> 1);
+        if (keys[mid] <= t) lo2 = mid + 1;
+        else hi2 = mid;
+    }
+    ranges[t] = lo2 > lo ? make_uint2(lo, lo2) : make_uint2(0u, 0u);
 }
 
 __global__ void k_export_keys(const uint32_t* __restrict__ tile_keys, const uint32_t* __restrict__ vals,
@@ -354,13 +401,13 @@ void launch_emit_pairs(const uint32_t* sorted_rec, const uint2* tile_rect, const
                        const DevCam* cams, const uint32_t* pair_off, uint32_t n, uint32_t K, uint32_t* keys,
                        uint32_t* vals, hipStream_t s) {
     if (!n || !K) return;
-    hipLaunchKernelGGL(k_emit_pairs, dim3((n + 255) / 256), dim3(256), 0, s, sorted_rec, tile_rect, recs, cams,
-                       pair_off, n, K, keys, vals);
+    hipLaunchKernelGGL(k_emit_pairs, dim3((n + kEmitThreads - 1) / kEmitThreads), dim3(kEmitThreads), 0, s,
+                       sorted_rec, tile_rect, recs, cams, pair_off, n, K, keys, vals);
 }
 
-void launch_ranges(const uint32_t* keys, uint32_t K, uint2* ranges, hipStream_t s) {
-    if (!K) return;
-    hipLaunchKernelGGL(k_ranges, dim3((K + 255) / 256), dim3(256), 0, s, keys, K, ranges);
+void launch_ranges(const uint32_t* keys, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s) {
+    if (!n_tiles) return;
+    hipLaunchKernelGGL(k_ranges_search, dim3((n_tiles + 255) / 256), dim3(256), 0, s, keys, K, n_tiles, ranges);
 }
 
 void launch_export_keys(const uint32_t* tile_keys, const uint32_t* vals, const BlendRec* recs,

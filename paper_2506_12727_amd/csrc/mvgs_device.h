@@ -180,13 +180,18 @@ __device__ __forceinline__ ProjOut project(const float mu[3], const float s[3], 
     out.nb = -cb;
     out.hcc = -0.5f * cc;
 
-    const float mid = 0.5f * (a + cq);
-    const float disc = __builtin_fmaf(mid, mid, -det);
-    const float lam = mid + sqrtf(disc > 0.0f ? disc : 0.0f);
-    const float rad = ceilf(3.0f * sqrtf(lam));
+    const float lc = -ln_threshold(kAlphaMin * o);
+    out.cut = (lc > kPowerFloor) ? lc : kPowerFloor;
+    out.hi = ln_threshold(kAlphaMax / o);
 
-    float x0 = floorf(out.mx - rad), x1 = floorf(out.mx + rad);
-    float y0 = floorf(out.my - rad), y1 = floorf(out.my + rad);
+    // footprint: per-axis half-extents of the cut ellipse {d : -0.5 d^T conic d >= cut},
+    // sqrt(-2 cut Sigma'_xx) and sqrt(-2 cut Sigma'_yy), in whole pixels
+    const float nc = -2.0f * out.cut;
+    const float rx = ceilf(sqrtf(nc * a));
+    const float ry = ceilf(sqrtf(nc * cq));
+
+    float x0 = floorf(out.mx - rx), x1 = floorf(out.mx + rx);
+    float y0 = floorf(out.my - ry), y1 = floorf(out.my + ry);
     const float wmax = (float)(c.W - 1), hmax = (float)(c.H - 1);
     if (x0 < 0.0f) x0 = 0.0f;
     if (y0 < 0.0f) y0 = 0.0f;
@@ -197,10 +202,6 @@ __device__ __forceinline__ ProjOut project(const float mu[3], const float s[3], 
     out.x1 = (int32_t)x1;
     out.y0 = (int32_t)y0;
     out.y1 = (int32_t)y1;
-
-    const float lc = -ln_threshold(kAlphaMin * o);
-    out.cut = (lc > kPowerFloor) ? lc : kPowerFloor;
-    out.hi = ln_threshold(kAlphaMax / o);
     out.ok = true;
     return out;
 }

@@ -66,7 +66,7 @@ void launch_gather_tile_counts(const uint32_t* sorted_rec, const uint2* tile_rec
 void launch_emit_pairs(const uint32_t* sorted_rec, const uint2* tile_rect, const BlendRec* recs,
                        const DevCam* cams, const uint32_t* pair_off, uint32_t n, uint32_t K, uint32_t* keys,
                        uint32_t* vals, hipStream_t s);
-void launch_ranges(const uint32_t* keys, uint32_t K, uint2* ranges, hipStream_t s);
+void launch_ranges(const uint32_t* keys, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s);
 void launch_export_keys(const uint32_t* tile_keys, const uint32_t* vals, const BlendRec* recs,
                         const DevCam* cams, int B, uint32_t K, uint64_t* keys_out, uint32_t* vals_out,
                         hipStream_t s);

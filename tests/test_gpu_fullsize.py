@@ -1,0 +1,125 @@
+"""Parity at the benchmark workloads' full sizes, in the launch configuration bench.py times
+(16x16 tiles, all views in one batch).
+
+The whole oracle render is too slow here, so the checks use what it can compute at any size:
+record and pair counts, the exact sorted list of sampled (view, tile)s, sampled pixels walked one by
+one over every participating Gaussian in depth order, the participation counts of the statistics,
+and the loss of one full-resolution view.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2506_12727_amd import scenes
+from paper_2506_12727_amd.raster import GaussianTensors, Rasterizer
+
+from gpu_common import needs_gpu
+
+pytestmark = pytest.mark.gpu
+
+_CACHE = {}
+
+
+def _setup(name):
+    if name not in _CACHE:
+        wl = scenes.WORKLOADS[name]
+        _CACHE[name] = (wl, wl.scene(), wl.cameras())
+    return _CACHE[name]
+
+
+def _tile_list_oracle(g32, cam, tile_xy, tile=(16, 16)):
+    """Gaussians of one view whose tile rectangle covers tile (tx, ty), in (depth bits, index) order."""
+    tx, ty = tile_xy
+    p = g32["participates"] == 1
+    cover = p & (g32["x0"] // tile[0] <= tx) & (g32["x1"] // tile[0] >= tx) & \
+        (g32["y0"] // tile[1] <= ty) & (g32["y1"] // tile[1] >= ty)
+    idx = np.nonzero(cover)[0]
+    order = np.lexsort((idx, g32["depth_bits"][idx]))
+    return idx[order].astype(np.uint32), g32["depth_bits"][idx][order]
+
+
+@pytest.mark.parametrize("name,views_checked", [("uneven_1m_8view", 8), ("train_300k_4x1600x1064_dssim", 4),
+                                                ("large_3m_16x1280x840", 3)])
+def test_fullsize_binning_and_sampled_pixels(name, views_checked):
+    needs_gpu()
+    wl, sc, cams = _setup(name)
+    r = Rasterizer((16, 16))
+    g = GaussianTensors.from_scene(sc)
+    imgs, fr = r.forward(g, cams)
+    info = fr.info()
+    recs, pairs = oracle.count_pairs(sc, cams)
+    assert (info["records"], info["pairs"]) == (recs, pairs)
+    keys, vals, ranges = r.export_binning(fr)
+    assert bool((keys[1:] >= keys[:-1]).all())
+    kn = keys.cpu().numpy().view(np.uint64)
+    vn = vals.cpu().numpy().view(np.uint32)
+    rn = ranges.cpu().numpy().view(np.uint32)
+    rng = np.random.default_rng(11)
+    tile_base = 0
+    n_flag = n_pix = 0
+    for v, c in enumerate(cams):
+        tx_n, ty_n = (c.width + 15) // 16, (c.height + 15) // 16
+        if v < views_checked:
+            g32 = oracle.geom32(sc, cams, v)
+            for _ in range(6):
+                tx, ty = int(rng.integers(tx_n)), int(rng.integers(ty_n))
+                want_g, want_d = _tile_list_oracle(g32, c, (tx, ty))
+                a, b = rn[tile_base + ty * tx_n + tx]
+                assert b - a == len(want_g)
+                assert np.array_equal(vn[a:b], want_g)
+                key = (np.uint64(v) << np.uint64(48)) | (np.uint64(ty * tx_n + tx) << np.uint64(32)) | \
+                    want_d.astype(np.uint64)
+                assert np.array_equal(kn[a:b], key)
+            xs, ys = rng.integers(0, c.width, 48), rng.integers(0, c.height, 48)
+            rgb, tf, fl = oracle.render_pixels(sc, cams, v, xs, ys)
+            got = imgs[v].cpu().numpy().astype(np.float64)[:, ys, xs].T
+            ok = fl == 0
+            n_flag += int((~ok).sum())
+            n_pix += len(xs)
+            err = np.abs(got - rgb)
+            assert np.all(err[ok] <= 1e-5 * np.abs(rgb[ok]) + 1e-6), (v, float(err[ok].max()))
+        tile_base += tx_n * ty_n
+    assert n_flag <= max(1, n_pix // 100)
+    r.release(fr)
+
+
+def test_fullsize_statistics_and_gradients():
+    """1M Gaussians x 8 views with densification statistics: count equals the number of views each
+    Gaussian takes part in (exact), E2 <= E1, gradients finite and not all zero."""
+    needs_gpu()
+    wl, sc, cams = _setup("uneven_1m_8view")
+    r = Rasterizer((16, 16))
+    g = GaussianTensors.from_scene(sc)
+    imgs, fr = r.forward(g, cams)
+    tg = [torch.from_numpy(t).cuda() for t in scenes.make_targets(cams)]
+    _, dl = r.loss(cams, imgs, tg, 1.0, 0.0)
+    dz = dict(e1=torch.zeros(g.P, device="cuda"), e2=torch.zeros(g.P, device="cuda"),
+              count=torch.zeros(g.P, dtype=torch.int32, device="cuda"))
+    grads = r.backward(g, fr, dl, densify=dz)
+    torch.cuda.synchronize()
+    want = np.zeros(g.P, np.int64)
+    for v in range(len(cams)):
+        want += oracle.geom32(sc, cams, v)["participates"]
+    assert np.array_equal(dz["count"].cpu().numpy(), want)
+    assert bool((dz["e2"] <= dz["e1"] * (1 + 1e-4) + 1e-12).all())
+    for n, t in grads.items():
+        assert bool(torch.isfinite(t).all()), n
+        assert float(t.abs().max()) > 0, n
+    r.release(fr)
+
+
+def test_fullsize_dssim_loss_one_view():
+    needs_gpu()
+    wl, sc, cams = _setup("train_300k_4x1600x1064_dssim")
+    cam = cams[:1]
+    r = Rasterizer((16, 16))
+    g = GaussianTensors.from_scene(sc)
+    imgs, fr = r.forward(g, cam)
+    tg = scenes.make_targets(cam)
+    loss, dl = r.loss(cam, imgs, [torch.from_numpy(t).cuda() for t in tg], wl.w_l1, wl.w_dssim)
+    lo, go = oracle.loss(cam, [i.cpu().numpy() for i in imgs], tg, wl.w_l1, wl.w_dssim)
+    assert abs(float(loss.item()) - lo) <= 1e-5 * abs(lo)
+    gd = dl[0].cpu().numpy().astype(np.float64)
+    assert np.allclose(gd, go[0], rtol=1e-4, atol=1e-5 * np.abs(go[0]).max())
+    r.release(fr)

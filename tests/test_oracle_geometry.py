@@ -128,25 +128,41 @@ def test_participation_rules(ora):
         assert ora.geom32(sc, [cam], 0)[0]["participates"] == want
 
 
-def test_box_contains_three_sigma_ellipse(ora):
-    """Every pixel whose power (double precision) is >= -4.5 lies inside the clipped pixel box,
-    so tiles are only a conservative accelerator."""
+def test_box_contains_cut_ellipse(ora):
+    """Every pixel whose power (double precision) is >= the cut lies inside the clipped pixel box,
+    so tiles are only a conservative accelerator; and the box is the per-axis extent of that
+    ellipse rounded up to whole pixels (touching it within a pixel on at least one side)."""
     sc = scenes.make_scene(400, 0, log_scale_mean=-2.5)
     cams = scenes.make_cameras([(96, 80)])
     g = ora.geom32(sc, cams, 0)
     m, cov, _, _ = ora.project64(sc, cams, 0)
     ys, xs = np.mgrid[0:80, 0:96]
     px, py = xs + 0.5, ys + 0.5
+    n_checked = 0
     for i in np.nonzero(g["participates"])[0]:
         det = cov[i, 0] * cov[i, 2] - cov[i, 1] ** 2
         a, b, c = cov[i, 2] / det, -cov[i, 1] / det, cov[i, 0] / det
         dx, dy = px - m[i, 0], py - m[i, 1]
         power = -0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy
-        inside = power >= -4.5 + 1e-6
+        cut = max(-4.5, -math.log(255.0 * float(sc.opacities[i])))
+        inside = power >= cut + 1e-6
         if inside.any():
             yy, xx = np.nonzero(inside)
             assert xx.min() >= g["x0"][i] and xx.max() <= g["x1"][i]
             assert yy.min() >= g["y0"][i] and yy.max() <= g["y1"][i]
+            n_checked += 1
+        rx = math.ceil(math.sqrt(-2 * cut * cov[i, 0]) - 1e-5)
+        ry = math.ceil(math.sqrt(-2 * cut * cov[i, 2]) - 1e-5)
+        assert g["radius"][i] in (max(rx, ry), max(rx, ry) + 1)
+    assert n_checked > 50
+
+
+def test_transparent_gaussians_do_not_take_part(ora):
+    """opacity < 1/255 can never give alpha >= 1/255: the cut ellipse is empty."""
+    cam = _cam()
+    for o, want in [(0.5 / 255, 0), (2.0 / 255, 1), (0.9, 1)]:
+        sc = _one((0, 0, 0), (0.05,) * 3, (1, 0, 0, 0), opac=o)
+        assert ora.geom32(sc, [cam], 0)[0]["participates"] == want
 
 
 def test_cut_thresholds(ora):
