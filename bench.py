@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uneven_1m_8view")
     ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--ppl", type=int, default=0, help="pixels per lane in the blend kernels (0: library default)")
     ap.add_argument("--no-loop", action="store_true", help="skip the one-view-per-call comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-views", type=int, default=2, help="views of the workload in the CPU sample")
@@ -72,7 +73,7 @@ def main():
     B = len(cams)
     g = GaussianTensors.from_scene(scene)
     tg = [torch.from_numpy(t).cuda() for t in scenes.make_targets(cams)]
-    rast = Rasterizer(tile)
+    rast = Rasterizer(tile, args.ppl)
     lib = L.lib()
     imgs = [torch.empty((3, c.height, c.width), device="cuda") for c in cams]
     dl = [torch.empty_like(t) for t in imgs]
@@ -174,6 +175,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "gaussians": g.P, "sh_degree": wl.sh_degree, "views": B,
                    "sizes": [[c.width, c.height] for c in cams], "tile": list(tile),
+                   "pixels_per_lane": args.ppl,
                    "loss": {"w_l1": wl.w_l1, "w_dssim": wl.w_dssim}, "densify": wl.densify},
         "gaussian_pixels_per_s": g.P * total_px * args.steps / elapsed,
         "one_view_loop": loop_res,

@@ -96,11 +96,15 @@ typedef struct {
     int32_t* count;
 } mvgs_densify;
 
-/* Context options. tile_w, tile_h in {8, 16, 32} (0 selects 16). */
+/* Context options. tile_w, tile_h in {8, 16, 32} (0 selects 16). pixels_per_lane in {1, 2, 4}:
+ * each lane of a blend wavefront owns that many pixels of its 8x8, 8x16 or 16x16 sub-tile; 2
+ * needs tile_h >= 16, 4 needs tile_w and tile_h >= 16; 0 selects the largest the tile allows.
+ * Results do not depend on these choices. */
 typedef struct {
     int32_t tile_w;
     int32_t tile_h;
-    int32_t reserved[6];
+    int32_t pixels_per_lane;
+    int32_t reserved[5];
 } mvgs_options;
 
 /* Create a context on the current HIP device. `opt` may be NULL (defaults).

@@ -47,7 +47,8 @@ class mvgs_densify(C.Structure):
 
 
 class mvgs_options(C.Structure):
-    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("pixels_per_lane", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class MvgsError(RuntimeError):

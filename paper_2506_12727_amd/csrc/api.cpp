@@ -142,7 +142,7 @@ struct mvgs_frame {
 
 struct mvgs_context {
     int device = 0;
-    int tw = 16, th = 16;
+    int tw = 16, th = 16, ppl = 2;
     std::string err;
     std::vector<mvgs_frame*> frames;
     DevBuf nrec, ntiles, totals, scan_scratch, depth_key[2], rec_vals[2], tile_rect, pair_counts, pair_off;
@@ -335,16 +335,19 @@ const char* mvgs_last_error(const mvgs_context* ctx) { return ctx ? ctx->err.c_s
 int mvgs_create(mvgs_context** out, const mvgs_options* opt) {
     if (!out) return MVGS_EINVAL;
     *out = nullptr;
-    int tw = 16, th = 16;
+    int tw = 16, th = 16, ppl = 0;
     if (opt) {
         if (opt->tile_w) tw = opt->tile_w;
         if (opt->tile_h) th = opt->tile_h;
+        ppl = opt->pixels_per_lane;
     }
-    if (!blend_supported(tw, th)) return MVGS_EINVAL;
+    if (ppl == 0) ppl = blend_default_ppl(tw, th);
+    if (!blend_supported(tw, th, ppl)) return MVGS_EINVAL;
     mvgs_context* ctx = new (std::nothrow) mvgs_context();
     if (!ctx) return MVGS_ENOMEM;
     ctx->tw = tw;
     ctx->th = th;
+    ctx->ppl = ppl;
     // no HIP call here: device resources are created by the first call that needs them
     *out = ctx;
     return MVGS_OK;
@@ -505,7 +508,7 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     a.t_final = as<float>(f->t_final);
     a.n_last = as<uint32_t>(f->n_last);
     mk = ctx->stage_begin(6, s);
-    launch_blend_fwd(a, tw, th, s);
+    launch_blend_fwd(a, tw, th, ctx->ppl, s);
     ctx->stage_end(mk, s);
     FCHK(hipGetLastError());
     FCHK(ctx->ring.seal(s));
@@ -587,7 +590,7 @@ int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, cons
     a.acc = as<float>(ctx->acc);
     a.want_e1 = densify != nullptr;
     int mk = ctx->stage_begin(8, s);
-    launch_blend_bwd(a, ctx->tw, ctx->th, s);
+    launch_blend_bwd(a, ctx->tw, ctx->th, ctx->ppl, s);
     ctx->stage_end(mk, s);
     GradArgs gr;
     gr.means = grads->means;

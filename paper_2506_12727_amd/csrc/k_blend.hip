@@ -55,8 +55,52 @@ __device__ __forceinline__ uint32_t readlane_u32(uint32_t v, int lane) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
 
-// Candidate window: lane k looks at list entry base + k, loads its record index and pixel box with
-// one vector load each, and the ballot keeps the entries whose box meets the wavefront's sub-tile.
+// Largest power -0.5 d^T conic d over the rectangle [xa, xb] x [ya, yb] of pixel centres (d = p - mean),
+// with power(d) = dx (hca dx + nb dy) + hcc dy^2, concave: 0 if the mean is inside, else the best of
+// the four edges, each maximised in closed form and clamped to the edge. Also returns the size of
+// the terms at that point, which bounds its rounding error.
+__device__ __forceinline__ float rect_max_power(float mx, float my, float hca, float nb, float hcc, float xa,
+                                               float xb, float ya, float yb, float& mag) {
+    const float ax = xa - mx, bx = xb - mx, ay = ya - my, by = yb - my;
+    if (ax <= 0.0f && bx >= 0.0f && ay <= 0.0f && by >= 0.0f) {
+        mag = 0.0f;
+        return 0.0f;
+    }
+    float best = -__builtin_inff();
+    mag = 0.0f;
+    // edges x = const: maximise over dy at dy* = -nb dx / (2 hcc)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float dx = e ? bx : ax;
+        float dy = -nb * dx / (2.0f * hcc);
+        dy = fminf(fmaxf(dy, ay), by);
+        const float t1 = hca * dx * dx, t2 = nb * dx * dy, t3 = hcc * dy * dy;
+        const float p = t1 + t2 + t3;
+        if (p > best) {
+            best = p;
+            mag = fabsf(t1) + fabsf(t2) + fabsf(t3);
+        }
+    }
+    // edges y = const: maximise over dx at dx* = -nb dy / (2 hca)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float dy = e ? by : ay;
+        float dx = -nb * dy / (2.0f * hca);
+        dx = fminf(fmaxf(dx, ax), bx);
+        const float t1 = hca * dx * dx, t2 = nb * dx * dy, t3 = hcc * dy * dy;
+        const float p = t1 + t2 + t3;
+        if (p > best) {
+            best = p;
+            mag = fabsf(t1) + fabsf(t2) + fabsf(t3);
+        }
+    }
+    return best;
+}
+
+// Candidate window: lane k looks at list entry base + k and keeps it if the Gaussian's cut ellipse
+// reaches a pixel centre of the wavefront's sub-tile: first the pixel box, then the ellipse itself.
+// The ellipse test only ever keeps too much (a slack far above float32 rounding), so culling never
+// changes a result; it only spares the wavefront Gaussians that no pixel of its sub-tile accepts.
 __device__ __forceinline__ uint64_t window_mask(const uint32_t* __restrict__ vals, const BlendRec* __restrict__ recs,
                                                 uint32_t base, uint32_t end, int lane, int sx0, int sx1, int sy0,
                                                 int sy1, uint32_t& rl) {
@@ -65,19 +109,27 @@ __device__ __forceinline__ uint64_t window_mask(const uint32_t* __restrict__ val
     rl = 0;
     if (idx < end) {
         rl = vals[idx];
-        const uint2 bx = *reinterpret_cast<const uint2*>(recs + rl);
-        keep = !box_misses(bx.x, bx.y, sx0, sx1, sy0, sy1);
+        const float4 q0 = *reinterpret_cast<const float4*>(recs + rl);
+        keep = !box_misses(__float_as_uint(q0.x), __float_as_uint(q0.y), sx0, sx1, sy0, sy1);
+        if (keep) {
+            const float4 q1 = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(recs + rl) + 4);
+            const float cut = reinterpret_cast<const float*>(recs + rl)[8];
+            float mag;
+            const float pm = rect_max_power(q0.z, q0.w, q1.x, q1.y, q1.z, (float)sx0 + 0.5f, (float)sx1 + 0.5f,
+                                            (float)sy0 + 0.5f, (float)sy1 + 0.5f, mag);
+            keep = pm >= cut - (1e-2f + 1e-5f * mag);
+        }
     }
     return ballot64(keep);
 }
 
-struct FwdState {
+struct FwdPix {
     float T, C0, C1, C2;
     uint32_t last;
     bool done;
 };
 
-__device__ __forceinline__ void blend_step(FwdState& st, const RecS& q, float px, float py, uint32_t pos) {
+__device__ __forceinline__ void blend_step(FwdPix& st, const RecS& q, float px, float py, uint32_t pos) {
     if (st.done) return;
     const float power = pixel_power(px, py, q.mx, q.my, q.hca, q.nb, q.hcc);
     if (power >= q.cut) {
@@ -96,35 +148,75 @@ __device__ __forceinline__ void blend_step(FwdState& st, const RecS& q, float px
     }
 }
 
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH) k_blend_fwd(const DevCam* __restrict__ cams, int B, uint32_t n_tiles,
-                                                       const uint2* __restrict__ ranges,
-                                                       const uint32_t* __restrict__ vals,
-                                                       const BlendRec* __restrict__ recs,
-                                                       float* const* __restrict__ images,
-                                                       float* __restrict__ t_final, uint32_t* __restrict__ n_last) {
-    constexpr int WX = TW / 8;
+// Geometry of one wavefront: an SW x SH sub-tile of the (view, tile) of this workgroup with
+// SW * SH = 64 PPL (8x8, 8x16 or 16x16); lane l owns the PPL pixels
+// (sx0 + l % SW, sy0 + l / SW + (64 / SW) k), k < PPL.
+template <int PPL>
+struct SubTile {
+    static constexpr int SW = PPL == 4 ? 16 : 8;
+    static constexpr int ROWS = 64 / SW;     // pixel rows one lane-step covers
+    static constexpr int SH = ROWS * PPL;
+};
+
+struct WaveTile {
+    int v;
+    int sx0, sx1, sy0, sy1;
+    uint2 rg;
+    bool empty;
+};
+
+template <int TW, int TH, int PPL>
+__device__ __forceinline__ WaveTile wave_tile(const DevCam* __restrict__ cams, int B, uint32_t n_tiles,
+                                              const uint2* __restrict__ ranges) {
+    using ST = SubTile<PPL>;
+    constexpr int WX = TW / ST::SW;
+    WaveTile w;
     const uint32_t tile = xcd_tile(blockIdx.x, n_tiles);
-    const int v = find_view(cams, B, tile);
-    const DevCam& c = cams[v];
+    w.v = find_view(cams, B, tile);
+    const DevCam& c = cams[w.v];
     const uint32_t local = tile - c.tile_base;
     const int ty = (int)(local / (uint32_t)c.tiles_x);
     const int tx = (int)local - ty * c.tiles_x;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = (int)(threadIdx.x & 63);
-    const int sx0 = tx * TW + (wave % WX) * 8, sy0 = ty * TH + (wave / WX) * 8;
-    if (sx0 >= c.W || sy0 >= c.H) return;
-    const int sx1 = min(sx0 + 7, c.W - 1), sy1 = min(sy0 + 7, c.H - 1);
-    const int x = sx0 + (lane & 7), y = sy0 + (lane >> 3);
-    const bool valid = x < c.W && y < c.H;
-    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-    const uint2 rg = ranges[tile];
+    w.sx0 = tx * TW + (wave % WX) * ST::SW;
+    w.sy0 = ty * TH + (wave / WX) * ST::SH;
+    w.empty = w.sx0 >= c.W || w.sy0 >= c.H;
+    w.sx1 = min(w.sx0 + ST::SW - 1, c.W - 1);
+    w.sy1 = min(w.sy0 + ST::SH - 1, c.H - 1);
+    w.rg = ranges[tile];
+    return w;
+}
 
-    FwdState st{1.0f, 0.0f, 0.0f, 0.0f, 0u, !valid};
-    for (uint32_t base = rg.x; base < rg.y; base += 64) {
-        if (ballot64(!st.done) == 0) break;
+template <int TW, int TH, int PPL>
+__global__ void __launch_bounds__(TW * TH / PPL) k_blend_fwd(const DevCam* __restrict__ cams, int B,
+                                                             uint32_t n_tiles, const uint2* __restrict__ ranges,
+                                                             const uint32_t* __restrict__ vals,
+                                                             const BlendRec* __restrict__ recs,
+                                                             float* const* __restrict__ images,
+                                                             float* __restrict__ t_final,
+                                                             uint32_t* __restrict__ n_last) {
+    const WaveTile wt = wave_tile<TW, TH, PPL>(cams, B, n_tiles, ranges);
+    if (wt.empty) return;
+    using ST = SubTile<PPL>;
+    const DevCam& c = cams[wt.v];
+    const int lane = (int)(threadIdx.x & 63);
+    const int x = wt.sx0 + (lane % ST::SW);
+    const float px = (float)x + 0.5f;
+    float py[PPL];
+    FwdPix st[PPL];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        const int y = wt.sy0 + (lane / ST::SW) + ST::ROWS * k;
+        py[k] = (float)y + 0.5f;
+        st[k] = FwdPix{1.0f, 0.0f, 0.0f, 0.0f, 0u, !(x < c.W && y < c.H)};
+    }
+    for (uint32_t base = wt.rg.x; base < wt.rg.y; base += 64) {
+        bool live = false;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) live |= !st[k].done;
+        if (ballot64(live) == 0) break;
         uint32_t rl;
-        uint64_t m = window_mask(vals, recs, base, rg.y, lane, sx0, sx1, sy0, sy1, rl);
+        uint64_t m = window_mask(vals, recs, base, wt.rg.y, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1, rl);
         while (m) {
             // up to four records per round trip through the scalar cache
             const int j0 = __builtin_ctzll(m);
@@ -142,21 +234,35 @@ __global__ void __launch_bounds__(TW * TH) k_blend_fwd(const DevCam* __restrict_
             const RecS q1 = load_rec(recs, readlane_u32(rl, j1));
             const RecS q2 = load_rec(recs, readlane_u32(rl, j2));
             const RecS q3 = load_rec(recs, readlane_u32(rl, j3));
-            blend_step(st, q0, px, py, base + (uint32_t)j0);
-            if (h1) blend_step(st, q1, px, py, base + (uint32_t)j1);
-            if (h2) blend_step(st, q2, px, py, base + (uint32_t)j2);
-            if (h3) blend_step(st, q3, px, py, base + (uint32_t)j3);
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) blend_step(st[k], q0, px, py[k], base + (uint32_t)j0);
+            if (h1) {
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) blend_step(st[k], q1, px, py[k], base + (uint32_t)j1);
+            }
+            if (h2) {
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) blend_step(st[k], q2, px, py[k], base + (uint32_t)j2);
+            }
+            if (h3) {
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) blend_step(st[k], q3, px, py[k], base + (uint32_t)j3);
+            }
         }
     }
-    if (valid) {
-        const size_t hw = (size_t)c.W * c.H;
-        const size_t pix = (size_t)y * c.W + x;
-        float* img = images[v];
-        img[pix] = __builtin_fmaf(st.T, c.bg[0], st.C0);
-        img[hw + pix] = __builtin_fmaf(st.T, c.bg[1], st.C1);
-        img[2 * hw + pix] = __builtin_fmaf(st.T, c.bg[2], st.C2);
-        t_final[c.pix_base + pix] = st.T;
-        n_last[c.pix_base + pix] = st.last;
+    const size_t hw = (size_t)c.W * c.H;
+    float* img = images[wt.v];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        const int y = wt.sy0 + (lane / ST::SW) + ST::ROWS * k;
+        if (x < c.W && y < c.H) {
+            const size_t pix = (size_t)y * c.W + x;
+            img[pix] = __builtin_fmaf(st[k].T, c.bg[0], st[k].C0);
+            img[hw + pix] = __builtin_fmaf(st[k].T, c.bg[1], st[k].C1);
+            img[2 * hw + pix] = __builtin_fmaf(st[k].T, c.bg[2], st[k].C2);
+            t_final[c.pix_base + pix] = st[k].T;
+            n_last[c.pix_base + pix] = st[k].last;
+        }
     }
 }
 
@@ -169,58 +275,68 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
-struct BwdState {
+struct BwdPix {
     float T, dC0, dC1, dC2, Rb0, Rb1, Rb2;
+    float py;
     uint32_t last;
 };
 
-// One Gaussian of the reverse walk: this lane's contributions, summed over the wavefront and
-// added to the record's accumulators.
+// Per-lane sums of one Gaussian's gradient contributions over the lane's pixels.
+struct BwdSum {
+    float mx, my, ca, cb, cc, o, r, g, b, e1;
+    bool contrib;
+};
+
 template <bool E1>
-__device__ __forceinline__ void unblend_step(BwdState& st, const RecS& q, uint32_t r, uint32_t pos, float px,
-                                             float py, float half_w, float half_h, int lane,
-                                             float* __restrict__ acc) {
-    float g_mx = 0.f, g_my = 0.f, g_ca = 0.f, g_cb = 0.f, g_cc = 0.f, g_o = 0.f;
-    float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_e1 = 0.f;
-    bool contrib = false;
-    if (pos < st.last) {
-        const float dx = px - q.mx, dy = py - q.my;
-        const float power = pixel_power(px, py, q.mx, q.my, q.hca, q.nb, q.hcc);
-        if (power >= q.cut) {
-            contrib = true;
-            const bool clamped = power > q.hi;
-            const float G = fast_exp(power);
-            const float alpha = clamped ? kAlphaMax : q.o * G;
-            st.T = st.T * __builtin_amdgcn_rcpf(1.0f - alpha);   // transmittance in front of this Gaussian
-            const float w = alpha * st.T;
-            g_r = st.dC0 * w;
-            g_g = st.dC1 * w;
-            g_b = st.dC2 * w;
-            const float dalpha = st.T * (st.dC0 * (q.r - st.Rb0) + st.dC1 * (q.g - st.Rb1) + st.dC2 * (q.b - st.Rb2));
-            st.Rb0 = __builtin_fmaf(q.r - st.Rb0, alpha, st.Rb0);
-            st.Rb1 = __builtin_fmaf(q.g - st.Rb1, alpha, st.Rb1);
-            st.Rb2 = __builtin_fmaf(q.b - st.Rb2, alpha, st.Rb2);
-            if (!clamped) {
-                g_o = dalpha * G;
-                const float dpow = dalpha * alpha;
-                const float ca = -2.0f * q.hca, cbq = -q.nb, cc = -2.0f * q.hcc;
-                g_mx = dpow * (ca * dx + cbq * dy);
-                g_my = dpow * (cbq * dx + cc * dy);
-                g_ca = -0.5f * dpow * dx * dx;
-                g_cb = -dpow * dx * dy;
-                g_cc = -0.5f * dpow * dy * dy;
-                if (E1) {
-                    const float nx = g_mx * half_w, ny = g_my * half_h;
-                    g_e1 = sqrtf(nx * nx + ny * ny);
-                }
-            }
-        }
+__device__ __forceinline__ void unblend_pixel(BwdPix& st, BwdSum& a, const RecS& q, uint32_t pos, float px,
+                                              float half_w, float half_h) {
+    if (pos >= st.last) return;
+    const float dx = px - q.mx, dy = st.py - q.my;
+    const float power = pixel_power(px, st.py, q.mx, q.my, q.hca, q.nb, q.hcc);
+    if (!(power >= q.cut)) return;
+    a.contrib = true;
+    const bool clamped = power > q.hi;
+    const float G = fast_exp(power);
+    const float alpha = clamped ? kAlphaMax : q.o * G;
+    st.T = st.T * __builtin_amdgcn_rcpf(1.0f - alpha);   // transmittance in front of this Gaussian
+    const float w = alpha * st.T;
+    a.r = __builtin_fmaf(st.dC0, w, a.r);
+    a.g = __builtin_fmaf(st.dC1, w, a.g);
+    a.b = __builtin_fmaf(st.dC2, w, a.b);
+    const float dalpha = st.T * (st.dC0 * (q.r - st.Rb0) + st.dC1 * (q.g - st.Rb1) + st.dC2 * (q.b - st.Rb2));
+    st.Rb0 = __builtin_fmaf(q.r - st.Rb0, alpha, st.Rb0);
+    st.Rb1 = __builtin_fmaf(q.g - st.Rb1, alpha, st.Rb1);
+    st.Rb2 = __builtin_fmaf(q.b - st.Rb2, alpha, st.Rb2);
+    if (clamped) return;
+    a.o = __builtin_fmaf(dalpha, G, a.o);
+    const float dpow = dalpha * alpha;
+    const float ca = -2.0f * q.hca, cbq = -q.nb, cc = -2.0f * q.hcc;
+    const float gx = dpow * (ca * dx + cbq * dy);
+    const float gy = dpow * (cbq * dx + cc * dy);
+    a.mx += gx;
+    a.my += gy;
+    a.ca = __builtin_fmaf(-0.5f * dpow, dx * dx, a.ca);
+    a.cb = __builtin_fmaf(-dpow, dx * dy, a.cb);
+    a.cc = __builtin_fmaf(-0.5f * dpow, dy * dy, a.cc);
+    if (E1) {
+        const float nx = gx * half_w, ny = gy * half_h;
+        a.e1 += sqrtf(nx * nx + ny * ny);
     }
-    if (ballot64(contrib) == 0) return;
-    const float s0 = wave_sum(g_mx), s1 = wave_sum(g_my), s2 = wave_sum(g_ca), s3 = wave_sum(g_cb);
-    const float s4 = wave_sum(g_cc), s5 = wave_sum(g_o), s6 = wave_sum(g_r), s7 = wave_sum(g_g);
-    const float s8 = wave_sum(g_b);
-    const float s9 = E1 ? wave_sum(g_e1) : 0.0f;
+}
+
+// One Gaussian of the reverse walk for all of this lane's pixels, summed over the wavefront and
+// added to the record's accumulators with one atomic instruction.
+template <bool E1, int PPL>
+__device__ __forceinline__ void unblend_step(BwdPix (&st)[PPL], const RecS& q, uint32_t r, uint32_t pos, float px,
+                                             float half_w, float half_h, int lane, float* __restrict__ acc) {
+    BwdSum a{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false};
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) unblend_pixel<E1>(st[k], a, q, pos, px, half_w, half_h);
+    if (ballot64(a.contrib) == 0) return;
+    const float s0 = wave_sum(a.mx), s1 = wave_sum(a.my), s2 = wave_sum(a.ca), s3 = wave_sum(a.cb);
+    const float s4 = wave_sum(a.cc), s5 = wave_sum(a.o), s6 = wave_sum(a.r), s7 = wave_sum(a.g);
+    const float s8 = wave_sum(a.b);
+    const float s9 = E1 ? wave_sum(a.e1) : 0.0f;
     float val = s0;
     val = lane == 1 ? s1 : val;
     val = lane == 2 ? s2 : val;
@@ -234,50 +350,47 @@ __device__ __forceinline__ void unblend_step(BwdState& st, const RecS& q, uint32
     if (lane < (E1 ? 10 : 9)) unsafeAtomicAdd(acc + (size_t)r * kAccStride + lane, val);
 }
 
-template <int TW, int TH, bool E1>
-__global__ void __launch_bounds__(TW * TH) k_blend_bwd(const DevCam* __restrict__ cams, int B, uint32_t n_tiles,
-                                                       const uint2* __restrict__ ranges,
-                                                       const uint32_t* __restrict__ vals,
-                                                       const BlendRec* __restrict__ recs,
-                                                       const float* const* __restrict__ dl_dimg,
-                                                       const float* __restrict__ t_final,
-                                                       const uint32_t* __restrict__ n_last,
-                                                       float* __restrict__ acc) {
-    constexpr int WX = TW / 8;
-    const uint32_t tile = xcd_tile(blockIdx.x, n_tiles);
-    const int v = find_view(cams, B, tile);
-    const DevCam& c = cams[v];
-    const uint32_t local = tile - c.tile_base;
-    const int ty = (int)(local / (uint32_t)c.tiles_x);
-    const int tx = (int)local - ty * c.tiles_x;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+template <int TW, int TH, int PPL, bool E1>
+__global__ void __launch_bounds__(TW * TH / PPL) k_blend_bwd(const DevCam* __restrict__ cams, int B,
+                                                             uint32_t n_tiles, const uint2* __restrict__ ranges,
+                                                             const uint32_t* __restrict__ vals,
+                                                             const BlendRec* __restrict__ recs,
+                                                             const float* const* __restrict__ dl_dimg,
+                                                             const float* __restrict__ t_final,
+                                                             const uint32_t* __restrict__ n_last,
+                                                             float* __restrict__ acc) {
+    const WaveTile wt = wave_tile<TW, TH, PPL>(cams, B, n_tiles, ranges);
+    if (wt.empty) return;
+    using ST = SubTile<PPL>;
+    const DevCam& c = cams[wt.v];
     const int lane = (int)(threadIdx.x & 63);
-    const int sx0 = tx * TW + (wave % WX) * 8, sy0 = ty * TH + (wave / WX) * 8;
-    if (sx0 >= c.W || sy0 >= c.H) return;
-    const int sx1 = min(sx0 + 7, c.W - 1), sy1 = min(sy0 + 7, c.H - 1);
-    const int x = sx0 + (lane & 7), y = sy0 + (lane >> 3);
-    const bool valid = x < c.W && y < c.H;
-    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-    const uint2 rg = ranges[tile];
+    const int x = wt.sx0 + (lane % ST::SW);
+    const float px = (float)x + 0.5f;
     const float half_w = 0.5f * (float)c.W, half_h = 0.5f * (float)c.H;
-
-    BwdState st{1.0f, 0.0f, 0.0f, 0.0f, c.bg[0], c.bg[1], c.bg[2], 0u};
-    if (valid) {
-        const size_t hw = (size_t)c.W * c.H;
-        const size_t pix = (size_t)y * c.W + x;
-        const float* g = dl_dimg[v];
-        st.dC0 = g[pix];
-        st.dC1 = g[hw + pix];
-        st.dC2 = g[2 * hw + pix];
-        st.T = t_final[c.pix_base + pix];
-        st.last = n_last[c.pix_base + pix];
+    const size_t hw = (size_t)c.W * c.H;
+    const float* g = dl_dimg[wt.v];
+    BwdPix st[PPL];
+    uint32_t lane_last = 0;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        const int y = wt.sy0 + (lane / ST::SW) + ST::ROWS * k;
+        st[k] = BwdPix{1.0f, 0.0f, 0.0f, 0.0f, c.bg[0], c.bg[1], c.bg[2], (float)y + 0.5f, 0u};
+        if (x < c.W && y < c.H) {
+            const size_t pix = (size_t)y * c.W + x;
+            st[k].dC0 = g[pix];
+            st[k].dC1 = g[hw + pix];
+            st[k].dC2 = g[2 * hw + pix];
+            st[k].T = t_final[c.pix_base + pix];
+            st[k].last = n_last[c.pix_base + pix];
+            lane_last = max(lane_last, st[k].last);
+        }
     }
-    const uint32_t hi_end = __builtin_amdgcn_readfirstlane(wave_max_u32(st.last));
+    const uint32_t hi_end = __builtin_amdgcn_readfirstlane(wave_max_u32(lane_last));
 
-    for (uint32_t top = hi_end; top > rg.x;) {
-        const uint32_t base = top - rg.x > 64u ? top - 64u : rg.x;
+    for (uint32_t top = hi_end; top > wt.rg.x;) {
+        const uint32_t base = top - wt.rg.x > 64u ? top - 64u : wt.rg.x;
         uint32_t rl;
-        uint64_t m = window_mask(vals, recs, base, top, lane, sx0, sx1, sy0, sy1, rl);
+        uint64_t m = window_mask(vals, recs, base, top, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1, rl);
         top = base;
         while (m) {
             // highest list position first; up to four records per round trip
@@ -298,10 +411,10 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(const DevCam* __restrict_
             const RecS q1 = load_rec(recs, r1);
             const RecS q2 = load_rec(recs, r2);
             const RecS q3 = load_rec(recs, r3);
-            unblend_step<E1>(st, q0, r0, base + (uint32_t)j0, px, py, half_w, half_h, lane, acc);
-            if (h1) unblend_step<E1>(st, q1, r1, base + (uint32_t)j1, px, py, half_w, half_h, lane, acc);
-            if (h2) unblend_step<E1>(st, q2, r2, base + (uint32_t)j2, px, py, half_w, half_h, lane, acc);
-            if (h3) unblend_step<E1>(st, q3, r3, base + (uint32_t)j3, px, py, half_w, half_h, lane, acc);
+            unblend_step<E1, PPL>(st, q0, r0, base + (uint32_t)j0, px, half_w, half_h, lane, acc);
+            if (h1) unblend_step<E1, PPL>(st, q1, r1, base + (uint32_t)j1, px, half_w, half_h, lane, acc);
+            if (h2) unblend_step<E1, PPL>(st, q2, r2, base + (uint32_t)j2, px, half_w, half_h, lane, acc);
+            if (h3) unblend_step<E1, PPL>(st, q3, r3, base + (uint32_t)j3, px, half_w, half_h, lane, acc);
         }
     }
 }
@@ -347,48 +460,58 @@ void launch_frame_work(const DevCam* cams, int B, const uint2* ranges, const uin
                        n_pixels, tw, th, (unsigned long long*)steps);
 }
 
-bool blend_supported(int tw, int th) {
+bool blend_supported(int tw, int th, int ppl) {
     const bool okw = tw == 8 || tw == 16 || tw == 32;
     const bool okh = th == 8 || th == 16 || th == 32;
-    return okw && okh;
+    if (!okw || !okh) return false;
+    if (ppl == 1) return true;
+    if (ppl == 2) return th >= 16;
+    if (ppl == 4) return tw >= 16 && th >= 16;
+    return false;
 }
 
-#define MVGS_TILE_SWITCH(TWv, THv, CALL)               \
-    do {                                                \
-        if (TWv == 8 && THv == 8) { CALL(8, 8); }       \
-        else if (TWv == 16 && THv == 8) { CALL(16, 8); }   \
-        else if (TWv == 8 && THv == 16) { CALL(8, 16); }   \
-        else if (TWv == 16 && THv == 16) { CALL(16, 16); } \
-        else if (TWv == 32 && THv == 8) { CALL(32, 8); }   \
-        else if (TWv == 8 && THv == 32) { CALL(8, 32); }   \
-        else if (TWv == 32 && THv == 16) { CALL(32, 16); } \
-        else if (TWv == 16 && THv == 32) { CALL(16, 32); } \
-        else { CALL(32, 32); }                          \
-    } while (0)
-
-void launch_blend_fwd(const BlendFwdArgs& a, int tw, int th, hipStream_t s) {
-    if (!a.n_tiles) return;
-#define MVGS_BF(W_, H_)                                                                                        \
-    hipLaunchKernelGGL((k_blend_fwd<W_, H_>), dim3(a.n_tiles), dim3(W_ * H_), 0, s, a.cams, a.B, a.n_tiles,    \
-                       a.ranges, a.vals, a.recs, a.images, a.t_final, a.n_last)
-    MVGS_TILE_SWITCH(tw, th, MVGS_BF);
-#undef MVGS_BF
+int blend_default_ppl(int tw, int th) {
+    if (tw >= 16 && th >= 16) return 4;
+    return th >= 16 ? 2 : 1;
 }
 
-void launch_blend_bwd(const BlendBwdArgs& a, int tw, int th, hipStream_t s) {
+template <int W_, int H_, int P_>
+static void launch_fwd_t(const BlendFwdArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_blend_fwd<W_, H_, P_>), dim3(a.n_tiles), dim3(W_ * H_ / P_), 0, s, a.cams, a.B, a.n_tiles,
+                       a.ranges, a.vals, a.recs, a.images, a.t_final, a.n_last);
+}
+
+template <int W_, int H_, int P_>
+static void launch_bwd_t(const BlendBwdArgs& a, hipStream_t s) {
+    if (a.want_e1)
+        hipLaunchKernelGGL((k_blend_bwd<W_, H_, P_, true>), dim3(a.n_tiles), dim3(W_ * H_ / P_), 0, s, a.cams, a.B,
+                           a.n_tiles, a.ranges, a.vals, a.recs, a.dl_dimg, a.t_final, a.n_last, a.acc);
+    else
+        hipLaunchKernelGGL((k_blend_bwd<W_, H_, P_, false>), dim3(a.n_tiles), dim3(W_ * H_ / P_), 0, s, a.cams, a.B,
+                           a.n_tiles, a.ranges, a.vals, a.recs, a.dl_dimg, a.t_final, a.n_last, a.acc);
+}
+
+// every supported (tile_w, tile_h, pixels per lane)
+#define MVGS_BLEND_CONFIGS(X) \
+    X(8, 8, 1) X(16, 8, 1) X(32, 8, 1) \
+    X(8, 16, 1) X(16, 16, 1) X(32, 16, 1) X(8, 16, 2) X(16, 16, 2) X(32, 16, 2) \
+    X(8, 32, 1) X(16, 32, 1) X(32, 32, 1) X(8, 32, 2) X(16, 32, 2) X(32, 32, 2) \
+    X(16, 16, 4) X(32, 16, 4) X(16, 32, 4) X(32, 32, 4)
+
+void launch_blend_fwd(const BlendFwdArgs& a, int tw, int th, int ppl, hipStream_t s) {
     if (!a.n_tiles) return;
-#define MVGS_BB(W_, H_)                                                                                        \
-    do {                                                                                                       \
-        if (a.want_e1)                                                                                         \
-            hipLaunchKernelGGL((k_blend_bwd<W_, H_, true>), dim3(a.n_tiles), dim3(W_ * H_), 0, s, a.cams, a.B, \
-                               a.n_tiles, a.ranges, a.vals, a.recs, a.dl_dimg, a.t_final, a.n_last, a.acc);    \
-        else                                                                                                   \
-            hipLaunchKernelGGL((k_blend_bwd<W_, H_, false>), dim3(a.n_tiles), dim3(W_ * H_), 0, s, a.cams,     \
-                               a.B, a.n_tiles, a.ranges, a.vals, a.recs, a.dl_dimg, a.t_final, a.n_last,      \
-                               a.acc);                                                                         \
-    } while (0)
-    MVGS_TILE_SWITCH(tw, th, MVGS_BB);
-#undef MVGS_BB
+#define MVGS_F(W_, H_, P_) \
+    if (tw == W_ && th == H_ && ppl == P_) { launch_fwd_t<W_, H_, P_>(a, s); return; }
+    MVGS_BLEND_CONFIGS(MVGS_F)
+#undef MVGS_F
+}
+
+void launch_blend_bwd(const BlendBwdArgs& a, int tw, int th, int ppl, hipStream_t s) {
+    if (!a.n_tiles) return;
+#define MVGS_B(W_, H_, P_) \
+    if (tw == W_ && th == H_ && ppl == P_) { launch_bwd_t<W_, H_, P_>(a, s); return; }
+    MVGS_BLEND_CONFIGS(MVGS_B)
+#undef MVGS_B
 }
 
 }  // namespace mvgs

@@ -96,11 +96,12 @@ struct BlendBwdArgs {
     float* acc;             // [V][kAccStride]
     int want_e1;
 };
-bool blend_supported(int tw, int th);
+bool blend_supported(int tw, int th, int ppl);
+int blend_default_ppl(int tw, int th);
 void launch_frame_work(const DevCam* cams, int B, const uint2* ranges, const uint32_t* n_last, uint32_t n_pixels,
                        int tw, int th, uint64_t* steps, hipStream_t s);
-void launch_blend_fwd(const BlendFwdArgs& a, int tw, int th, hipStream_t s);
-void launch_blend_bwd(const BlendBwdArgs& a, int tw, int th, hipStream_t s);
+void launch_blend_fwd(const BlendFwdArgs& a, int tw, int th, int ppl, hipStream_t s);
+void launch_blend_bwd(const BlendBwdArgs& a, int tw, int th, int ppl, hipStream_t s);
 
 // k_loss.hip
 struct LossView {

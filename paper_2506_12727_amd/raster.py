@@ -72,10 +72,11 @@ class Frame:
 
 
 class Rasterizer:
-    def __init__(self, tile=(16, 16)):
+    def __init__(self, tile=(16, 16), pixels_per_lane=0):
         self.lib = L.lib()
         opt = L.mvgs_options()
         opt.tile_w, opt.tile_h = int(tile[0]), int(tile[1])
+        opt.pixels_per_lane = int(pixels_per_lane)
         self.ctx = C.c_void_p()
         L.check(self.lib.mvgs_create(C.byref(self.ctx), C.byref(opt)))
         self.tile = (opt.tile_w, opt.tile_h)

@@ -18,8 +18,8 @@ def needs_gpu():
         pytest.skip("no GPU")
 
 
-def run_forward(scene, cams, tile=(16, 16), rast=None):
-    r = rast or Rasterizer(tile)
+def run_forward(scene, cams, tile=(16, 16), rast=None, ppl=0):
+    r = rast or Rasterizer(tile, ppl)
     g = GaussianTensors.from_scene(scene)
     imgs, fr = r.forward(g, cams)
     torch.cuda.synchronize()

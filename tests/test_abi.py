@@ -46,11 +46,17 @@ def ctx():
 
 def test_create_rejects_bad_tiles():
     lib = L.lib()
-    for tw, th in [(4, 16), (16, 12), (64, 16), (-8, 8)]:
+    for tw, th, ppl in [(4, 16, 0), (16, 12, 0), (64, 16, 0), (-8, 8, 0), (16, 16, 3), (8, 16, 4), (16, 8, 2), (16, 8, 4)]:
         o = L.mvgs_options()
-        o.tile_w, o.tile_h = tw, th
+        o.tile_w, o.tile_h, o.pixels_per_lane = tw, th, ppl
         h = C.c_void_p()
         assert lib.mvgs_create(C.byref(h), C.byref(o)) == L.MVGS_EINVAL
+    for tw, th, ppl in [(16, 16, 0), (16, 16, 1), (16, 32, 4), (8, 8, 1), (32, 16, 2), (16, 16, 4)]:
+        o = L.mvgs_options()
+        o.tile_w, o.tile_h, o.pixels_per_lane = tw, th, ppl
+        h = C.c_void_p()
+        assert lib.mvgs_create(C.byref(h), C.byref(o)) == L.MVGS_OK
+        lib.mvgs_destroy(h)
     assert lib.mvgs_create(None, None) == L.MVGS_EINVAL
 
 

@@ -23,24 +23,30 @@ def _small():
     return scenes.WORKLOADS["small_16k_4x128"]
 
 
+def _ragged(deg=3, lsm=-3.0):
+    return (scenes.make_scene(6000, deg, log_scale_mean=lsm), scenes.make_cameras([(61, 47), (130, 70), (33, 97)]))
+
+
+# name -> (scene, cameras, tile, pixels per lane)
 CASES = {
     # the small benchmark workload: 16,384 Gaussians, SH 0, 4 x 128^2, 16x16 tiles
-    "small": lambda: (_small().scene(), _small().cameras(), (16, 16)),
-    # ragged views and SH 3 with larger splats, several tile shapes
-    "ragged_16x16": lambda: (scenes.make_scene(6000, 3, log_scale_mean=-3.0),
-                             scenes.make_cameras([(61, 47), (130, 70), (33, 97)]), (16, 16)),
-    "ragged_8x8": lambda: (scenes.make_scene(6000, 3, log_scale_mean=-3.0),
-                           scenes.make_cameras([(61, 47), (130, 70), (33, 97)]), (8, 8)),
-    "ragged_32x16": lambda: (scenes.make_scene(6000, 2, log_scale_mean=-3.2),
-                             scenes.make_cameras([(61, 47), (130, 70), (33, 97)]), (32, 16)),
+    "small": lambda: (_small().scene(), _small().cameras(), (16, 16), 0),
+    # ragged views and SH 3 with larger splats, several tile shapes and lane layouts
+    "ragged_16x16": lambda: _ragged() + ((16, 16), 2),
+    "ragged_16x16_ppl1": lambda: _ragged() + ((16, 16), 1),
+    "ragged_8x8": lambda: _ragged() + ((8, 8), 1),
+    "ragged_32x16": lambda: _ragged(2, -3.2) + ((32, 16), 2),
+    "ragged_16x32_ppl4": lambda: _ragged(1, -3.1) + ((16, 32), 4),
+    "ragged_32x32_ppl4": lambda: _ragged(3, -2.8) + ((32, 32), 4),
+    "ragged_8x32_ppl2": lambda: _ragged(3, -3.0) + ((8, 32), 2),
 }
 
 
 @pytest.mark.parametrize("case", list(CASES))
 def test_binning_bit_exact(case):
     needs_gpu()
-    sc, cams, tile = CASES[case]()
-    r, g, imgs, fr = run_forward(sc, cams, tile)
+    sc, cams, tile, ppl = CASES[case]()
+    r, g, imgs, fr = run_forward(sc, cams, tile, ppl=ppl)
     keys, vals, ranges = r.export_binning(fr)
     ok, ov, orr = oracle.binning(sc, cams, tile)
     gk = keys.cpu().numpy().view(np.uint64)
@@ -57,8 +63,8 @@ def test_binning_bit_exact(case):
 @pytest.mark.parametrize("case", list(CASES))
 def test_forward_images(case):
     needs_gpu()
-    sc, cams, tile = CASES[case]()
-    r, g, imgs, fr = run_forward(sc, cams, tile)
+    sc, cams, tile, ppl = CASES[case]()
+    r, g, imgs, fr = run_forward(sc, cams, tile, ppl=ppl)
     ref = oracle.forward(sc, cams, tile)
     frac = compare_images(to_np(imgs), ref["images"], ref["flags"])
     tf = to_np(r.export_transmittance(fr))
@@ -84,8 +90,8 @@ def test_loss_and_image_gradient(w):
         assert np.allclose(a, b, rtol=1e-4, atol=1e-5 * np.abs(b).max())
 
 
-def _backward_case(sc, cams, tile, w_l1, w_dssim, densify):
-    r, g, imgs, fr = run_forward(sc, cams, tile)
+def _backward_case(sc, cams, tile, w_l1, w_dssim, densify, ppl=0):
+    r, g, imgs, fr = run_forward(sc, cams, tile, ppl=ppl)
     ref = oracle.forward(sc, cams, tile)
     tg = [torch.from_numpy(a).cuda() for a in scenes.make_targets(cams)]
     _, dl = r.loss(cams, imgs, tg, w_l1, w_dssim)
@@ -114,8 +120,8 @@ def _backward_case(sc, cams, tile, w_l1, w_dssim, densify):
 @pytest.mark.parametrize("case", list(CASES))
 def test_backward_gradients_and_statistics(case):
     needs_gpu()
-    sc, cams, tile = CASES[case]()
-    _backward_case(sc, cams, tile, 1.0, 0.0, densify=True)
+    sc, cams, tile, ppl = CASES[case]()
+    _backward_case(sc, cams, tile, 1.0, 0.0, densify=True, ppl=ppl)
 
 
 def test_backward_with_dssim():
@@ -127,8 +133,8 @@ def test_backward_with_dssim():
 
 def test_statistics_accumulate_across_calls():
     needs_gpu()
-    sc, cams, tile = CASES["small"]()
-    r, g, imgs, fr = run_forward(sc, cams, tile)
+    sc, cams, tile, ppl = CASES["small"]()
+    r, g, imgs, fr = run_forward(sc, cams, tile, ppl=ppl)
     tg = [torch.from_numpy(a).cuda() for a in scenes.make_targets(cams)]
     _, dl = r.loss(cams, imgs, tg, 1.0, 0.0)
     P = g.P
