@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uneven_1m_8view")
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--tile", default="auto", help="WxH, or auto: pick tile and pixels per lane by timing")
     ap.add_argument("--ppl", type=int, default=0, help="pixels per lane in the blend kernels (0: library default)")
     ap.add_argument("--no-loop", action="store_true", help="skip the one-view-per-call comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -67,13 +67,19 @@ def main():
 
     torch.cuda.set_device(0)
     wl = scenes.WORKLOADS[args.workload]
-    tile = tuple(int(x) for x in args.tile.split("x"))
     scene = wl.scene()
     cams = wl.cameras()
     B = len(cams)
     g = GaussianTensors.from_scene(scene)
     tg = [torch.from_numpy(t).cuda() for t in scenes.make_targets(cams)]
-    rast = Rasterizer(tile, args.ppl)
+    tuned = None
+    if args.tile == "auto":
+        from paper_2506_12727_amd.tune import autotune
+        tile, ppl, times = autotune(g, cams, tg, wl.w_l1, wl.w_dssim)
+        tuned = {f"{t[0]}x{t[1]}/{p}": round(1e3 * v, 3) for (t, p), v in times.items()}
+    else:
+        tile, ppl = tuple(int(x) for x in args.tile.split("x")), args.ppl
+    rast = Rasterizer(tile, ppl)
     lib = L.lib()
     imgs = [torch.empty((3, c.height, c.width), device="cuda") for c in cams]
     dl = [torch.empty_like(t) for t in imgs]
@@ -158,7 +164,7 @@ def main():
               key=lambda k: stage_ms[k])
     roof = roofline(dom, stage_ms[dom], info, steps_walk, g, B, cams)
 
-    cpu = None if args.no_cpu else cpu_baseline(scene, cams, tg, wl, tile, args.cpu_views)
+    cpu = None if args.no_cpu else cpu_baseline(scene, cams, tg, wl, (16, 16), args.cpu_views)
     total_px = sum(c.width * c.height for c in cams)
     out = {
         "metric": METRIC,
@@ -175,7 +181,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "gaussians": g.P, "sh_degree": wl.sh_degree, "views": B,
                    "sizes": [[c.width, c.height] for c in cams], "tile": list(tile),
-                   "pixels_per_lane": args.ppl,
+                   "pixels_per_lane": ppl, "autotune_ms_per_step": tuned,
                    "loss": {"w_l1": wl.w_l1, "w_dssim": wl.w_dssim}, "densify": wl.densify},
         "gaussian_pixels_per_s": g.P * total_px * args.steps / elapsed,
         "one_view_loop": loop_res,

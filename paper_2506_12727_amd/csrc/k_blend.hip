@@ -324,30 +324,73 @@ __device__ __forceinline__ void unblend_pixel(BwdPix& st, BwdSum& a, const RecS&
     }
 }
 
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ float dpp_mov(float old, float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v),
+                                                                 CTRL, ROW_MASK, BANK_MASK, false));
+}
+
+// One halving step of the transposed reduction: of the pair (a, b) a lane keeps a if `hi` is false
+// and b otherwise, and adds the same member from its partner across the exchange `xchg`.
+template <typename X>
+__device__ __forceinline__ float keep_add(float a, float b, bool hi, X xchg) {
+    const float send = hi ? a : b;
+    const float keep = hi ? b : a;
+    return keep + xchg(send);
+}
+
+// Sum of ten per-lane values over the wavefront in one pass of halving exchanges (xor 32, 16, 8,
+// 4 move half of the values each, xor 2 and 1 finish): afterwards the first lane of quad q holds
+// the total of value kQuadValue[q]. Returns that total; *idx receives the value index (or -1).
+__device__ __forceinline__ float wave_sum10(const float (&v)[10], int lane, uint32_t bperm32, int* idx) {
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+    auto x32 = [&](float t) { return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute((int)bperm32,
+                                                                                            __builtin_bit_cast(int, t))); };
+    // swizzle bit mode: and_mask 0x1f, xor_mask 0x10 -> lane ^ 16 within each half
+    auto x16 = [&](float t) { return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, t),
+                                                                                           0x401f)); };
+    auto x8 = [&](float t) { return dpp_mov<0x128, 0xf, 0xf>(0.0f, t); };  // row_ror:8 -> lane ^ 8 in a row
+    auto x4 = [&](float t) {
+        const float up = dpp_mov<0x104, 0xf, 0x5>(0.0f, t);   // row_shl:4 into banks 0, 2 (lane + 4)
+        return dpp_mov<0x114, 0xf, 0xa>(up, t);              // row_shr:4 into banks 1, 3 (lane - 4)
+    };
+    const float r0 = keep_add(v[0], v[1], b5, x32);
+    const float r1 = keep_add(v[2], v[3], b5, x32);
+    const float r2 = keep_add(v[4], v[5], b5, x32);
+    const float r3 = keep_add(v[6], v[7], b5, x32);
+    const float r4 = keep_add(v[8], v[9], b5, x32);
+    const float s0 = keep_add(r0, r1, b4, x16);
+    const float s1 = keep_add(r2, r3, b4, x16);
+    const float s2 = keep_add(r4, 0.0f, b4, x16);
+    const float u0 = keep_add(s0, s1, b3, x8);
+    const float u1 = keep_add(s2, 0.0f, b3, x8);
+    float x = keep_add(u0, u1, b2, x4);
+    x += dpp_mov<0x4e, 0xf, 0xf>(0.0f, x);   // quad_perm [2,3,0,1]
+    x += dpp_mov<0xb1, 0xf, 0xf>(0.0f, x);   // quad_perm [1,0,3,2]
+    // value held by lane groups: bit2 = 0 -> u0 (bit3 picks s0/s1), bit2 = 1 -> u1 (s2 if bit3 = 0)
+    int k = -1;
+    if ((lane & 3) == 0) {
+        if (!b2) k = (b3 ? 4 : 0) + (b5 ? 1 : 0) + (b4 ? 2 : 0);
+        else if (!b3 && !b4) k = 8 + (b5 ? 1 : 0);
+    }
+    *idx = k;
+    return x;
+}
+
 // One Gaussian of the reverse walk for all of this lane's pixels, summed over the wavefront and
 // added to the record's accumulators with one atomic instruction.
 template <bool E1, int PPL>
 __device__ __forceinline__ void unblend_step(BwdPix (&st)[PPL], const RecS& q, uint32_t r, uint32_t pos, float px,
-                                             float half_w, float half_h, int lane, float* __restrict__ acc) {
+                                             float half_w, float half_h, int lane, uint32_t bperm32,
+                                             float* __restrict__ acc) {
     BwdSum a{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false};
 #pragma unroll
     for (int k = 0; k < PPL; ++k) unblend_pixel<E1>(st[k], a, q, pos, px, half_w, half_h);
     if (ballot64(a.contrib) == 0) return;
-    const float s0 = wave_sum(a.mx), s1 = wave_sum(a.my), s2 = wave_sum(a.ca), s3 = wave_sum(a.cb);
-    const float s4 = wave_sum(a.cc), s5 = wave_sum(a.o), s6 = wave_sum(a.r), s7 = wave_sum(a.g);
-    const float s8 = wave_sum(a.b);
-    const float s9 = E1 ? wave_sum(a.e1) : 0.0f;
-    float val = s0;
-    val = lane == 1 ? s1 : val;
-    val = lane == 2 ? s2 : val;
-    val = lane == 3 ? s3 : val;
-    val = lane == 4 ? s4 : val;
-    val = lane == 5 ? s5 : val;
-    val = lane == 6 ? s6 : val;
-    val = lane == 7 ? s7 : val;
-    val = lane == 8 ? s8 : val;
-    val = lane == 9 ? s9 : val;
-    if (lane < (E1 ? 10 : 9)) unsafeAtomicAdd(acc + (size_t)r * kAccStride + lane, val);
+    const float v[10] = {a.mx, a.my, a.ca, a.cb, a.cc, a.o, a.r, a.g, a.b, E1 ? a.e1 : 0.0f};
+    int k;
+    const float total = wave_sum10(v, lane, bperm32, &k);
+    if (k >= 0 && (E1 || k < 9)) unsafeAtomicAdd(acc + (size_t)r * kAccStride + k, total);
 }
 
 template <int TW, int TH, int PPL, bool E1>
@@ -386,6 +429,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_bwd(const DevCam* __res
         }
     }
     const uint32_t hi_end = __builtin_amdgcn_readfirstlane(wave_max_u32(lane_last));
+    const uint32_t bperm32 = (uint32_t)((lane ^ 32) << 2);
 
     for (uint32_t top = hi_end; top > wt.rg.x;) {
         const uint32_t base = top - wt.rg.x > 64u ? top - 64u : wt.rg.x;
@@ -411,10 +455,10 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_bwd(const DevCam* __res
             const RecS q1 = load_rec(recs, r1);
             const RecS q2 = load_rec(recs, r2);
             const RecS q3 = load_rec(recs, r3);
-            unblend_step<E1, PPL>(st, q0, r0, base + (uint32_t)j0, px, half_w, half_h, lane, acc);
-            if (h1) unblend_step<E1, PPL>(st, q1, r1, base + (uint32_t)j1, px, half_w, half_h, lane, acc);
-            if (h2) unblend_step<E1, PPL>(st, q2, r2, base + (uint32_t)j2, px, half_w, half_h, lane, acc);
-            if (h3) unblend_step<E1, PPL>(st, q3, r3, base + (uint32_t)j3, px, half_w, half_h, lane, acc);
+            unblend_step<E1, PPL>(st, q0, r0, base + (uint32_t)j0, px, half_w, half_h, lane, bperm32, acc);
+            if (h1) unblend_step<E1, PPL>(st, q1, r1, base + (uint32_t)j1, px, half_w, half_h, lane, bperm32, acc);
+            if (h2) unblend_step<E1, PPL>(st, q2, r2, base + (uint32_t)j2, px, half_w, half_h, lane, bperm32, acc);
+            if (h3) unblend_step<E1, PPL>(st, q3, r3, base + (uint32_t)j3, px, half_w, half_h, lane, bperm32, acc);
         }
     }
 }
