@@ -27,7 +27,7 @@ METRIC = "fwd+bwd views/s, 1M Gaussians, 8-view batch vs 1-view loop; serve p50/
 HBM_PEAK_GBS = 8000.0
 # non-packed FP32 vector lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 ALU_PEAK_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# algorithmic lane operations per (pixel, Gaussian) step of the walks
+# algorithmic lane operations per blended (pixel, Gaussian) pair
 FWD_OPS_PER_STEP = 18
 BWD_OPS_PER_STEP = 57
 STAGES = ["count", "records", "depth_sort", "emit", "tile_sort", "ranges", "blend_fwd", "loss", "blend_bwd",
@@ -137,11 +137,11 @@ def main():
     # frame sizes and walk work of one batched forward (outside the timed region)
     _, fr = rast.forward(g, cams, images=imgs)
     info = fr.info()
-    work = torch.zeros(1, dtype=torch.int64, device="cuda")
+    work = torch.zeros(2, dtype=torch.int64, device="cuda")
     L.check(lib.mvgs_frame_work(rast.ctx, C.c_void_p(torch.cuda.current_stream().cuda_stream), fr.handle,
                                 work.data_ptr()), rast.ctx)
     torch.cuda.synchronize()
-    steps_walk = int(work.item())
+    steps_walk, blended = (int(x) for x in work.cpu().tolist())
     rast.release(fr)
 
     loop_res = None
@@ -162,7 +162,7 @@ def main():
     # roofline of the dominant kernel
     dom = max(("blend_fwd", "blend_bwd", "tile_sort", "depth_sort", "emit", "records", "preprocess_bwd"),
               key=lambda k: stage_ms[k])
-    roof = roofline(dom, stage_ms[dom], info, steps_walk, g, B, cams)
+    roof = roofline(dom, stage_ms[dom], info, blended, g, B, cams)
 
     cpu = None if args.no_cpu else cpu_baseline(scene, cams, tg, wl, (16, 16), args.cpu_views)
     total_px = sum(c.width * c.height for c in cams)
@@ -187,25 +187,26 @@ def main():
         "one_view_loop": loop_res,
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "frame": {"records": info["records"], "pairs": info["pairs"], "tiles": info["tiles"],
-                  "walk_steps": steps_walk},
+                  "walk_steps": steps_walk, "blended_pairs": blended},
+        "blend_rooflines": {k: roofline(k, stage_ms[k], info, blended, g, B, cams)
+                            for k in ("blend_fwd", "blend_bwd")},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
 
-def roofline(stage, ms, info, steps_walk, g, B, cams):
+def roofline(stage, ms, info, blended, g, B, cams):
     """Achieved vs peak for one stage; algorithmic bytes or lane operations per launch."""
     K, V = info["pairs"], info["records"]
     npx = sum(c.width * c.height for c in cams)
     sec = ms / 1e3
     if stage in ("blend_fwd", "blend_bwd"):
-        ops = steps_walk * (FWD_OPS_PER_STEP if stage == "blend_fwd" else BWD_OPS_PER_STEP)
-        ach = ops / sec / 1e12
+        per = FWD_OPS_PER_STEP if stage == "blend_fwd" else BWD_OPS_PER_STEP
+        ach = blended * per / sec / 1e12
         return {"kernel": stage, "bound": "alu", "achieved": ach, "peak": ALU_PEAK_TLANEOPS, "unit": "Tlane-op/s",
                 "frac": ach / ALU_PEAK_TLANEOPS, "traffic": None,
-                "units": {"walk_steps": steps_walk, "ops_per_step": FWD_OPS_PER_STEP if stage == "blend_fwd"
-                          else BWD_OPS_PER_STEP}}
+                "units": {"blended_pairs": blended, "ops_per_pair": per}}
     # HBM-bound stages: one read and one write of what the stage must move
     per = {
         "tile_sort": 2 * 16.0 * K,              # two 8-bit passes, each reads and writes 8 B per pair

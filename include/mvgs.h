@@ -182,11 +182,12 @@ int mvgs_profile_read(mvgs_context* ctx, double* ms, int64_t* calls);
 int mvgs_profile_reset(mvgs_context* ctx);
 const char* mvgs_stage_name(int stage);
 
-/* Work of a frame's front-to-back walks: writes to steps_dev (device uint64) the sum over all
- * pixels of the number of list entries from the start of the pixel's (view, tile) list up to its
- * last blended Gaussian -- the (pixel, Gaussian) steps the reverse walk of the backward takes and
- * a lower bound of the forward's (Alg. 2: each thread walks its tile's sorted list). */
-int mvgs_frame_work(mvgs_context* ctx, void* stream, const mvgs_frame* frame, uint64_t* steps_dev);
+/* Work of a frame's walks (for rooflines; it walks every pixel's list again, so it costs about a
+ * forward). Writes two device uint64 to work_dev: [0] the sum over pixels of the list entries from
+ * the start of the pixel's (view, tile) list up to its last blended Gaussian (what Alg. 2's
+ * per-thread loop visits), [1] the number of (pixel, Gaussian) pairs blended by Eq. 1, which
+ * does not depend on the tile shape. */
+int mvgs_frame_work(mvgs_context* ctx, void* stream, const mvgs_frame* frame, uint64_t* work_dev);
 
 /* Human-readable text of a status code (static storage). */
 const char* mvgs_status_string(int status);

@@ -137,7 +137,7 @@ struct mvgs_frame {
     uint32_t V = 0;
     uint64_t K = 0;
     int final_buf = 0;
-    DevBuf cams, recs, rec_off, keys[2], vals[2], ranges, t_final, n_last;
+    DevBuf cams, recs, rec_off, rec_view, keys[2], vals[2], ranges, t_final, n_last;
 };
 
 struct mvgs_context {
@@ -310,8 +310,8 @@ mvgs_frame* acquire_frame(mvgs_context* ctx) {
 }
 
 void free_frame(mvgs_frame* f) {
-    DevBuf* bufs[] = {&f->cams, &f->recs, &f->rec_off, &f->keys[0], &f->keys[1], &f->vals[0], &f->vals[1],
-                      &f->ranges, &f->t_final, &f->n_last};
+    DevBuf* bufs[] = {&f->cams, &f->recs, &f->rec_off, &f->rec_view, &f->keys[0], &f->keys[1], &f->vals[0],
+                      &f->vals[1], &f->ranges, &f->t_final, &f->n_last};
     for (DevBuf* b : bufs) release(*b);
 }
 
@@ -427,7 +427,10 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     // participation and sizes
     FCHK(ensure(ctx->nrec, sizeof(uint32_t) * (P + 1)));
     FCHK(ensure(ctx->ntiles, sizeof(uint32_t) * (P + 1)));
-    FCHK(ensure(ctx->totals, sizeof(uint64_t) * 4));
+    if (!ctx->totals.p) {
+        FCHK(ensure(ctx->totals, sizeof(uint64_t) * 4));
+        fill_u32(as<uint32_t>(ctx->totals), 8, 0u, s);
+    }
     FCHK(ensure(f->rec_off, sizeof(uint32_t) * (P + 1)));
     FCHK(ensure(ctx->scan_scratch, scan_scratch_bytes(P + 1)));
     int mk = ctx->stage_begin(0, s);
@@ -438,9 +441,15 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     reduce_sum_u32(as<uint32_t>(ctx->ntiles), P, as<uint64_t>(ctx->totals) + 1, nullptr, s);
     ctx->stage_end(mk, s);
     FCHK(hipGetLastError());
-    FCHK(hipMemcpyAsync(ctx->pinned_totals, ctx->totals.p, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    FCHK(hipMemcpyAsync(ctx->pinned_totals, ctx->totals.p, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     FCHK(hipStreamSynchronize(s));
     const uint64_t V64 = ctx->pinned_totals[0], K64 = ctx->pinned_totals[1];
+    if (ctx->pinned_totals[2] != 0) {
+        // a sort of an earlier call on this context timed out in its look-back (never expected)
+        fill_u32(reinterpret_cast<uint32_t*>(as<uint64_t>(ctx->totals) + 2), 2, 0u, s);
+        (void)ctx->ring.seal(s);
+        return bail(ctx->fail(MVGS_EHIP, "radix sort look-back timed out in an earlier call on this context"));
+    }
     if (V64 >= (1ull << 32) || K64 >= (1ull << 32)) {
         (void)ctx->ring.seal(s);
         return bail(ctx->fail(MVGS_ECAPACITY, "records %llu or pairs %llu reach 2^32", (unsigned long long)V64,
@@ -452,11 +461,12 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
 
     // records and the depth sort
     FCHK(ensure(f->recs, sizeof(BlendRec) * std::max<uint32_t>(V, 1)));
+    FCHK(ensure(f->rec_view, sizeof(uint16_t) * std::max<uint32_t>(V, 1)));
     FCHK(ensure(ctx->depth_key[0], sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
     FCHK(ensure(ctx->depth_key[1], sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
     FCHK(ensure(ctx->rec_vals[0], sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
     FCHK(ensure(ctx->rec_vals[1], sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
-    FCHK(ensure(ctx->tile_rect, sizeof(uint2) * std::max<uint32_t>(V, 1)));
+    FCHK(ensure(ctx->tile_rect, sizeof(uint4) * std::max<uint32_t>(V, 1)));
     FCHK(ensure(ctx->pair_counts, sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
     FCHK(ensure(ctx->pair_off, sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
     FCHK(ensure(f->keys[0], sizeof(uint32_t) * std::max<uint32_t>(K, 1)));
@@ -470,27 +480,28 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
 
     mk = ctx->stage_begin(1, s);
     launch_records(ga, dcam, B, tw, th, as<uint32_t>(f->rec_off), as<BlendRec>(f->recs),
-                   as<uint32_t>(ctx->depth_key[0]), as<uint2>(ctx->tile_rect), s);
+                   as<uint32_t>(ctx->depth_key[0]), as<uint4>(ctx->tile_rect), as<uint16_t>(f->rec_view), s);
     ctx->stage_end(mk, s);
     mk = ctx->stage_begin(2, s);
     uint32_t* dk[2] = {as<uint32_t>(ctx->depth_key[0]), as<uint32_t>(ctx->depth_key[1])};
     uint32_t* dv[2] = {as<uint32_t>(ctx->rec_vals[0]), as<uint32_t>(ctx->rec_vals[1])};
-    const int dcur = radix_sort_u32(dk, dv, true, V, 32, ctx->sort_scratch.p, s);
+    uint32_t* sort_err = reinterpret_cast<uint32_t*>(as<uint64_t>(ctx->totals) + 2);
+    const int dcur = radix_sort_u32(dk, dv, true, V, 32, ctx->sort_scratch.p, sort_err, s);
     const uint32_t* sorted_rec = dv[dcur];
     ctx->stage_end(mk, s);
 
     // pairs in depth order, then a stable sort by global tile id
     mk = ctx->stage_begin(3, s);
-    launch_gather_tile_counts(sorted_rec, as<uint2>(ctx->tile_rect), V, as<uint32_t>(ctx->pair_counts), s);
+    launch_gather_tile_counts(sorted_rec, as<uint4>(ctx->tile_rect), V, as<uint32_t>(ctx->pair_counts), s);
     scan_exclusive_u32(as<uint32_t>(ctx->pair_counts), as<uint32_t>(ctx->pair_off), V, nullptr,
                        ctx->sort_scratch.p, s);
-    launch_emit_pairs(sorted_rec, as<uint2>(ctx->tile_rect), as<BlendRec>(f->recs), dcam,
+    launch_emit_pairs(sorted_rec, as<uint4>(ctx->tile_rect),
                       as<uint32_t>(ctx->pair_off), V, K, as<uint32_t>(f->keys[0]), as<uint32_t>(f->vals[0]), s);
     ctx->stage_end(mk, s);
     mk = ctx->stage_begin(4, s);
     uint32_t* pk[2] = {as<uint32_t>(f->keys[0]), as<uint32_t>(f->keys[1])};
     uint32_t* pv[2] = {as<uint32_t>(f->vals[0]), as<uint32_t>(f->vals[1])};
-    f->final_buf = radix_sort_u32(pk, pv, false, K, bits_for(n_tiles), ctx->sort_scratch.p, s);
+    f->final_buf = radix_sort_u32(pk, pv, false, K, bits_for(n_tiles), ctx->sort_scratch.p, sort_err, s);
     ctx->stage_end(mk, s);
     mk = ctx->stage_begin(5, s);
     launch_ranges(pk[f->final_buf], K, n_tiles, as<uint2>(f->ranges), s);
@@ -602,7 +613,7 @@ int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, cons
     gr.e2 = densify ? densify->e2 : nullptr;
     gr.count = densify ? densify->count : nullptr;
     mk = ctx->stage_begin(9, s);
-    launch_preprocess_bwd(gargs(g), as<DevCam>(f->cams), as<uint32_t>(f->rec_off), as<BlendRec>(f->recs),
+    launch_preprocess_bwd(gargs(g), as<DevCam>(f->cams), as<uint32_t>(f->rec_off), as<uint16_t>(f->rec_view),
                           as<float>(ctx->acc), gr, s);
     ctx->stage_end(mk, s);
     LAUNCHCHK(ctx, "backward kernels");
@@ -693,11 +704,12 @@ int mvgs_profile_reset(mvgs_context* ctx) {
     return st;
 }
 
-int mvgs_frame_work(mvgs_context* ctx, void* stream, const mvgs_frame* frame, uint64_t* steps_dev) {
-    if (!ctx || !frame || frame->ctx != ctx || !frame->in_use || !steps_dev) return MVGS_EINVAL;
+int mvgs_frame_work(mvgs_context* ctx, void* stream, const mvgs_frame* frame, uint64_t* work_dev) {
+    if (!ctx || !frame || frame->ctx != ctx || !frame->in_use || !work_dev) return MVGS_EINVAL;
     mvgs_frame* f = const_cast<mvgs_frame*>(frame);
-    launch_frame_work(as<DevCam>(f->cams), f->B, as<uint2>(f->ranges), as<uint32_t>(f->n_last), f->n_pixels,
-                      ctx->tw, ctx->th, steps_dev, (hipStream_t)stream);
+    launch_frame_work(as<DevCam>(f->cams), f->B, as<uint2>(f->ranges), as<uint32_t>(f->vals[f->final_buf]),
+                      as<BlendRec>(f->recs), as<uint32_t>(f->n_last), f->n_pixels, ctx->tw, ctx->th, work_dev,
+                      (hipStream_t)stream);
     LAUNCHCHK(ctx, "frame work");
     return MVGS_OK;
 }

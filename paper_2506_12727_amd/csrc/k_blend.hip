@@ -463,14 +463,18 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_bwd(const DevCam* __res
     }
 }
 
-// sum over pixels of (last blended list position + 1 - list start): the reverse walk's steps
+// Work of a frame's walks, one thread per pixel: out[0] += list entries from the start of the pixel's
+// (view, tile) list to its last blended Gaussian; out[1] += Gaussians blended into the pixel (entries
+// before the last blended one that pass the cut test at the pixel, walked again here).
 __global__ void __launch_bounds__(256) k_frame_work(const DevCam* __restrict__ cams, int B,
                                                     const uint2* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ vals,
+                                                    const BlendRec* __restrict__ recs,
                                                     const uint32_t* __restrict__ n_last, uint32_t n_pixels, int tw,
-                                                    int th, unsigned long long* __restrict__ steps) {
-    __shared__ unsigned long long red[256];
+                                                    int th, unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long red[2][256];
     const uint32_t p = blockIdx.x * 256 + threadIdx.x;
-    unsigned long long w = 0;
+    unsigned long long steps = 0, blended = 0;
     if (p < n_pixels) {
         int lo = 0, hi = B;
         while (hi - lo > 1) {
@@ -483,25 +487,42 @@ __global__ void __launch_bounds__(256) k_frame_work(const DevCam* __restrict__ c
         const int y = (int)(i / (uint32_t)c.W), x = (int)(i - (uint32_t)y * c.W);
         const uint32_t tile = c.tile_base + (uint32_t)((y / th) * c.tiles_x + x / tw);
         const uint32_t start = ranges[tile].x, nl = n_last[p];
-        w = nl > start ? (unsigned long long)(nl - start) : 0ull;
+        if (nl > start) {
+            steps = nl - start;
+            const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+            for (uint32_t j = start; j < nl; ++j) {
+                const BlendRec& R = recs[vals[j]];
+                if (pixel_power(px, py, R.mx, R.my, R.hca, R.nb, R.hcc) >= R.cut) ++blended;
+            }
+        }
     }
-    red[threadIdx.x] = w;
+    red[0][threadIdx.x] = steps;
+    red[1][threadIdx.x] = blended;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        if ((int)threadIdx.x < off) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + off];
+            red[1][threadIdx.x] += red[1][threadIdx.x + off];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicAdd(steps, red[0]);
+    if (threadIdx.x == 0) {
+        atomicAdd(out, red[0][0]);
+        atomicAdd(out + 1, red[1][0]);
+    }
 }
 
-__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+__global__ void k_zero_u64x2(unsigned long long* p) {
+    p[0] = 0ull;
+    p[1] = 0ull;
+}
 
-void launch_frame_work(const DevCam* cams, int B, const uint2* ranges, const uint32_t* n_last, uint32_t n_pixels,
-                       int tw, int th, uint64_t* steps, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, (unsigned long long*)steps);
+void launch_frame_work(const DevCam* cams, int B, const uint2* ranges, const uint32_t* vals, const BlendRec* recs,
+                       const uint32_t* n_last, uint32_t n_pixels, int tw, int th, uint64_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u64x2, dim3(1), dim3(1), 0, s, (unsigned long long*)out);
     if (!n_pixels) return;
-    hipLaunchKernelGGL(k_frame_work, dim3((n_pixels + 255) / 256), dim3(256), 0, s, cams, B, ranges, n_last,
-                       n_pixels, tw, th, (unsigned long long*)steps);
+    hipLaunchKernelGGL(k_frame_work, dim3((n_pixels + 255) / 256), dim3(256), 0, s, cams, B, ranges, vals, recs,
+                       n_last, n_pixels, tw, th, (unsigned long long*)out);
 }
 
 bool blend_supported(int tw, int th, int ppl) {

@@ -50,7 +50,8 @@ __global__ void __launch_bounds__(256) k_records(const float* __restrict__ means
                                                  const float* __restrict__ sh, int64_t P,
                                                  const DevCam* __restrict__ cams, int B, int tile_w, int tile_h,
                                                  const uint32_t* __restrict__ rec_off, BlendRec* __restrict__ recs,
-                                                 uint32_t* __restrict__ depth_key, uint2* __restrict__ tile_rect) {
+                                                 uint32_t* __restrict__ depth_key, uint4* __restrict__ tile_rect,
+                                                 uint16_t* __restrict__ rec_view) {
     constexpr int K = (D + 1) * (D + 1);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= P) return;
@@ -92,9 +93,13 @@ __global__ void __launch_bounds__(256) k_records(const float* __restrict__ means
         r.view = (uint32_t)v;
         r.depth_bits = f2u(p.depth);
         recs[out] = r;
+        rec_view[out] = (uint16_t)v;
         depth_key[out] = f2u(p.depth);
-        tile_rect[out] = make_uint2((uint32_t)(p.x0 / tile_w) | ((uint32_t)(p.x1 / tile_w) << 16),
-                                    (uint32_t)(p.y0 / tile_h) | ((uint32_t)(p.y1 / tile_h) << 16));
+        // covered tiles: first global tile id, width | height << 16, the view's tiles per row
+        const uint32_t tx0 = (uint32_t)(p.x0 / tile_w), ty0 = (uint32_t)(p.y0 / tile_h);
+        const uint32_t tw_n = (uint32_t)(p.x1 / tile_w) - tx0 + 1, th_n = (uint32_t)(p.y1 / tile_h) - ty0 + 1;
+        tile_rect[out] = make_uint4(c.tile_base + ty0 * (uint32_t)c.tiles_x + tx0, tw_n | (th_n << 16),
+                                    (uint32_t)c.tiles_x, 0u);
         ++out;
     }
 }
@@ -105,7 +110,7 @@ template <int D>
 __global__ void __launch_bounds__(256) k_preprocess_bwd(
     const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
     const float* __restrict__ opac, const float* __restrict__ sh, int64_t P, const DevCam* __restrict__ cams,
-    const uint32_t* __restrict__ rec_off, const BlendRec* __restrict__ recs, const float* __restrict__ acc,
+    const uint32_t* __restrict__ rec_off, const uint16_t* __restrict__ rec_view, const float* __restrict__ acc,
     float* __restrict__ g_means, float* __restrict__ g_scales, float* __restrict__ g_quats,
     float* __restrict__ g_opac, float* __restrict__ g_sh, float* __restrict__ e1, float* __restrict__ e2,
     int32_t* __restrict__ count) {
@@ -126,7 +131,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(
     float se1 = 0.0f, se2 = 0.0f;
     const uint32_t r0 = rec_off[g], r1 = rec_off[g + 1];
     for (uint32_t ri = r0; ri < r1; ++ri) {
-        const uint32_t v = recs[ri].view;
+        const uint32_t v = rec_view[ri];
         const DevCam& c = cams[v];
         const float4 a0 = *reinterpret_cast<const float4*>(acc + (size_t)ri * kAccStride);
         const float4 a1 = *reinterpret_cast<const float4*>(acc + (size_t)ri * kAccStride + 4);
@@ -276,12 +281,12 @@ void launch_count(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int
 }
 
 void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,
-                    BlendRec* recs, uint32_t* depth_key, uint2* tile_rect, hipStream_t s) {
+                    BlendRec* recs, uint32_t* depth_key, uint4* tile_rect, uint16_t* rec_view, hipStream_t s) {
     const unsigned blocks = (unsigned)((ga.P + 255) / 256);
     if (!blocks) return;
 #define MVGS_REC(D)                                                                                             \
     hipLaunchKernelGGL(k_records<D>, dim3(blocks), dim3(256), 0, s, ga.means, ga.scales, ga.quats, ga.opac,     \
-                       ga.sh, ga.P, cams, B, tw, th, rec_off, recs, depth_key, tile_rect)
+                       ga.sh, ga.P, cams, B, tw, th, rec_off, recs, depth_key, tile_rect, rec_view)
     switch (ga.sh_degree) {
         case 0: MVGS_REC(0); break;
         case 1: MVGS_REC(1); break;
@@ -292,12 +297,12 @@ void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, i
 }
 
 void launch_preprocess_bwd(const GaussianArgs& ga, const DevCam* cams, const uint32_t* rec_off,
-                           const BlendRec* recs, const float* acc, const GradArgs& gr, hipStream_t s) {
+                           const uint16_t* rec_view, const float* acc, const GradArgs& gr, hipStream_t s) {
     const unsigned blocks = (unsigned)((ga.P + 255) / 256);
     if (!blocks) return;
 #define MVGS_PB(D)                                                                                              \
     hipLaunchKernelGGL(k_preprocess_bwd<D>, dim3(blocks), dim3(256), 0, s, ga.means, ga.scales, ga.quats,       \
-                       ga.opac, ga.sh, ga.P, cams, rec_off, recs, acc, gr.means, gr.scales, gr.quats, gr.opac,  \
+                       ga.opac, ga.sh, ga.P, cams, rec_off, rec_view, acc, gr.means, gr.scales, gr.quats, gr.opac,  \
                        gr.sh, gr.e1, gr.e2, gr.count)
     switch (ga.sh_degree) {
         case 0: MVGS_PB(0); break;

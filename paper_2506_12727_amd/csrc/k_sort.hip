@@ -105,6 +105,8 @@ __global__ void __launch_bounds__(256) k_reduce64(const uint32_t* __restrict__ i
 
 static size_t div_up(size_t a, size_t b) { return (a + b - 1) / b; }
 
+void fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+
 size_t scan_scratch_bytes(size_t n) {
     size_t bytes = 256;
     size_t m = n;
@@ -164,40 +166,67 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
     return peers;
 }
 
-__global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(const uint32_t* __restrict__ keys, size_t n,
-                                                                int shift, int nblocks,
-                                                                uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[kRadix];
-    h[threadIdx.x] = 0;
+// Digit histograms of every pass in one read of the keys: per-workgroup LDS counters, then one
+// global atomic per (pass, digit, workgroup). hist[p * 256 + d] counts digit d (dbits wide) of pass p.
+__global__ void __launch_bounds__(256) k_radix_hist_all(const uint32_t* __restrict__ keys, size_t n, int passes,
+                                                        int dbits, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[4][kRadix];
+    for (int i = threadIdx.x; i < 4 * kRadix; i += 256) (&h[0][0])[i] = 0;
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const size_t base = (size_t)blockIdx.x * kSortTile + (size_t)wave * kSortRounds * 64;
-    for (int r = 0; r < kSortRounds; ++r) {
-        const size_t i = base + (size_t)r * 64 + lane;
-        const bool valid = i < n;
-        const uint32_t d = valid ? (keys[i] >> shift) & 0xffu : 0u;
-        const uint64_t peers = digit_peers(d, valid);
-        if (valid && rank_below(peers) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const uint32_t k = keys[i];
+        const uint32_t mask = (1u << dbits) - 1u;
+        for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(k >> (dbits * p)) & mask], 1u);
     }
     __syncthreads();
-    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t c = h[p][threadIdx.x];
+        if (c) atomicAdd(&hist[p * kRadix + threadIdx.x], c);
+    }
 }
 
-__global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
+// Exclusive scan of each pass's 256 digit counts, in place (one workgroup of 256 threads).
+__global__ void __launch_bounds__(256) k_radix_hist_scan(uint32_t* __restrict__ hist, int passes) {
+    __shared__ uint32_t tmp[kRadix];
+    for (int p = 0; p < passes; ++p) {
+        uint32_t total;
+        const uint32_t v = hist[p * kRadix + threadIdx.x];
+        const uint32_t ex = block_exclusive_scan_256(v, tmp, &total);
+        hist[p * kRadix + threadIdx.x] = ex;
+    }
+}
+
+// Status word of (partition, digit) in the look-back: bits 63-62 flag, bits 31-0 count.
+constexpr uint64_t kFlagAggregate = 1ull << 62;   // this partition's own count
+constexpr uint64_t kFlagPrefix = 2ull << 62;      // count of this and all earlier partitions
+constexpr uint64_t kFlagMask = 3ull << 62;
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+// One stable pass: workgroups take partitions of 4096 items in launch order from an atomic counter,
+// rank their items by digit with wave64 ballots, publish per-digit counts, add up the counts of the
+// earlier partitions (decoupled look-back: stop at the first published prefix), and scatter through
+// LDS in digit order. Each status word carries its count itself, so relaxed device-scope atomics
+// (coherent loads and stores, no cache-wide write-back or invalidate) are enough. A partition never waits on a later one, so the pass always drains; the wait is
+// bounded nevertheless and a timeout is recorded in *err instead of hanging.
+__global__ void __launch_bounds__(kSortThreads) k_radix_onesweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, size_t n, int shift, int nblocks, const uint32_t* __restrict__ hist_scan) {
+    uint32_t* __restrict__ vals_out, size_t n, int shift, uint32_t mask, const uint32_t* __restrict__ digit_base,
+    uint64_t* __restrict__ status, uint32_t* __restrict__ part_counter, uint32_t* __restrict__ err) {
     __shared__ uint32_t wcount[kSortWaves][kRadix];
     __shared__ uint32_t dstart[kRadix];
     __shared__ uint32_t gbase[kRadix];
     __shared__ uint32_t scan_tmp[kRadix];
     __shared__ uint32_t skey[kSortTile];
     __shared__ uint32_t sval[kSortTile];
+    __shared__ uint32_t s_part;
 
+    if (threadIdx.x == 0) s_part = atomicAdd(part_counter, 1u);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortThreads) (&wcount[0][0])[d] = 0;
     __syncthreads();
+    const uint32_t part = s_part;
 
-    const size_t base = (size_t)blockIdx.x * kSortTile + (size_t)wave * kSortRounds * 64;
+    const size_t base = (size_t)part * kSortTile + (size_t)wave * kSortRounds * 64;
     uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
@@ -210,7 +239,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     for (int r = 0; r < kSortRounds; ++r) {
         const size_t i = base + (size_t)r * 64 + lane;
         const bool valid = i < n;
-        const uint32_t d = (key[r] >> shift) & 0xffu;
+        const uint32_t d = (key[r] >> shift) & mask;
         const uint64_t peers = digit_peers(d, valid);
         const uint32_t below = (uint32_t)rank_below(peers);
         const uint32_t before = wcount[wave][d];
@@ -220,7 +249,6 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
         wave_lds_sync();
     }
     __syncthreads();
-    // per digit: prefix over waves, block total, and the block's global base
     {
         const int d = threadIdx.x;
         uint32_t run = 0;
@@ -231,56 +259,98 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
             run += c;
         }
         uint32_t total;
-        const uint32_t start = block_exclusive_scan_256(run, scan_tmp, &total);
-        dstart[d] = start;
-        gbase[d] = hist_scan[(size_t)d * nblocks + blockIdx.x];
+        dstart[d] = block_exclusive_scan_256(run, scan_tmp, &total);
+        // publish, look back, publish the inclusive prefix
+        uint64_t* my = status + (size_t)part * kRadix + d;
+        if (part == 0) {
+            __hip_atomic_store(my, kFlagPrefix | run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            gbase[d] = digit_base[d];
+        } else {
+            __hip_atomic_store(my, kFlagAggregate | run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t excl = 0;
+            int64_t j = (int64_t)part - 1;
+            uint32_t spins = 0;
+            while (j >= 0) {
+                const uint64_t st = __hip_atomic_load(status + (size_t)j * kRadix + d, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t f = st & kFlagMask;
+                if (f == kFlagPrefix) {
+                    excl += (uint32_t)st;
+                    break;
+                }
+                if (f == kFlagAggregate) {
+                    excl += (uint32_t)st;
+                    --j;
+                    continue;
+                }
+                if (++spins > kSpinLimit) {
+                    atomicOr(err, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __hip_atomic_store(my, kFlagPrefix | (excl + run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            gbase[d] = digit_base[d] + excl;
+        }
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
         const size_t i = base + (size_t)r * 64 + lane;
         if (i < n) {
-            const uint32_t d = (key[r] >> shift) & 0xffu;
+            const uint32_t d = (key[r] >> shift) & mask;
             const uint32_t pos = dstart[d] + wcount[wave][d] + rank[r];
             skey[pos] = key[r];
             sval[pos] = val[r];
         }
     }
     __syncthreads();
-    const size_t tile_n = std::min<size_t>((size_t)kSortTile, n - (size_t)blockIdx.x * kSortTile);
+    const size_t tile_n = std::min<size_t>((size_t)kSortTile, n - (size_t)part * kSortTile);
     for (int j = threadIdx.x; j < (int)tile_n; j += kSortThreads) {
         const uint32_t k = skey[j];
-        const uint32_t d = (k >> shift) & 0xffu;
+        const uint32_t d = (k >> shift) & mask;
         const size_t dst = (size_t)gbase[d] + (uint32_t)(j - dstart[d]);
         keys_out[dst] = k;
         vals_out[dst] = sval[j];
     }
 }
 
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 size_t radix_scratch_bytes(size_t n) {
-    const size_t blocks = std::max<size_t>(1, div_up(n, kSortTile));
-    const size_t hist = blocks * kRadix * sizeof(uint32_t);
-    return ((hist + 255) / 256) * 256 * 2 + scan_scratch_bytes(blocks * kRadix);
+    const size_t parts = std::max<size_t>(1, div_up(n, kSortTile));
+    return align256(4 * kRadix * sizeof(uint32_t)) + align256(parts * kRadix * sizeof(uint64_t)) +
+           align256(8 * sizeof(uint32_t));
 }
 
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
-                   hipStream_t s) {
+                   uint32_t* err, hipStream_t s) {
     int cur = 0;
     if (n == 0 || bits <= 0) return cur;
-    const size_t blocks = div_up(n, kSortTile);
-    const size_t hist_n = blocks * kRadix;
+    // fewest 8-bit passes, digits spread evenly over them (fewer distinct digits per workgroup
+    // give longer runs of consecutive stores)
+    const int passes = (bits + 7) / 8;
+    const int dbits = (bits + passes - 1) / passes;
+    const uint32_t mask = (1u << dbits) - 1u;
+    const size_t parts = div_up(n, kSortTile);
     uint8_t* p = (uint8_t*)scratch;
     uint32_t* hist = (uint32_t*)p;
-    p += ((hist_n * sizeof(uint32_t) + 255) / 256) * 256;
-    uint32_t* hist_scan = (uint32_t*)p;
-    p += ((hist_n * sizeof(uint32_t) + 255) / 256) * 256;
-    for (int shift = 0; shift < bits; shift += 8) {
-        const uint32_t* vin = (shift == 0 && identity_values) ? nullptr : vals[cur];
-        hipLaunchKernelGGL(k_radix_upsweep, dim3((unsigned)blocks), dim3(kSortThreads), 0, s, keys[cur], n, shift,
-                           (int)blocks, hist);
-        scan_exclusive_u32(hist, hist_scan, hist_n, nullptr, p, s);
-        hipLaunchKernelGGL(k_radix_downsweep, dim3((unsigned)blocks), dim3(kSortThreads), 0, s, keys[cur], vin,
-                           keys[cur ^ 1], vals[cur ^ 1], n, shift, (int)blocks, (const uint32_t*)hist_scan);
+    p += align256(4 * kRadix * sizeof(uint32_t));
+    uint64_t* status = (uint64_t*)p;
+    p += align256(parts * kRadix * sizeof(uint64_t));
+    uint32_t* counters = (uint32_t*)p;
+    fill_u32(hist, (size_t)passes * kRadix, 0u, s);
+    fill_u32(counters, (size_t)passes, 0u, s);
+    const unsigned hblocks = (unsigned)std::min<size_t>(div_up(n, 256 * 16), 4096);
+    hipLaunchKernelGGL(k_radix_hist_all, dim3(hblocks), dim3(256), 0, s, keys[0], n, passes, dbits, hist);
+    hipLaunchKernelGGL(k_radix_hist_scan, dim3(1), dim3(256), 0, s, hist, passes);
+    for (int pass = 0; pass < passes; ++pass) {
+        const uint32_t* vin = (pass == 0 && identity_values) ? nullptr : vals[cur];
+        hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)div_up(parts * kRadix, 256)), dim3(256), 0, s, status,
+                           parts * kRadix, (uint64_t)0);
+        hipLaunchKernelGGL(k_radix_onesweep, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys[cur], vin,
+                           keys[cur ^ 1], vals[cur ^ 1], n, dbits * pass, mask, (const uint32_t*)(hist + pass * kRadix), status,
+                           counters + pass, err);
         cur ^= 1;
     }
     return cur;
@@ -290,12 +360,9 @@ int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, s
 // binning
 // ---------------------------------------------------------------------------------------------
 
-__device__ __forceinline__ uint32_t rect_tiles(uint2 r) {
-    const uint32_t tx0 = r.x & 0xffffu, tx1 = r.x >> 16, ty0 = r.y & 0xffffu, ty1 = r.y >> 16;
-    return (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-}
+__device__ __forceinline__ uint32_t rect_tiles(uint4 r) { return (r.y & 0xffffu) * (r.y >> 16); }
 
-__global__ void k_gather_tile_counts(const uint32_t* __restrict__ sorted_rec, const uint2* __restrict__ rect,
+__global__ void k_gather_tile_counts(const uint32_t* __restrict__ sorted_rec, const uint4* __restrict__ rect,
                                      uint32_t n, uint32_t* __restrict__ counts) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) counts[i] = rect_tiles(rect[sorted_rec[i]]);
@@ -309,29 +376,25 @@ __global__ void k_gather_tile_counts(const uint32_t* __restrict__ sorted_rec, co
 constexpr int kEmitThreads = 256;
 
 __global__ void __launch_bounds__(kEmitThreads) k_emit_pairs(const uint32_t* __restrict__ sorted_rec,
-                                                             const uint2* __restrict__ rect,
-                                                             const BlendRec* __restrict__ recs,
-                                                             const DevCam* __restrict__ cams,
+                                                             const uint4* __restrict__ rect,
                                                              const uint32_t* __restrict__ pair_off, uint32_t n,
                                                              uint32_t K, uint32_t* __restrict__ keys,
                                                              uint32_t* __restrict__ vals) {
     __shared__ uint32_t s_off[kEmitThreads + 1];   // local exclusive offsets (+ total)
     __shared__ uint32_t s_rec[kEmitThreads];
-    __shared__ uint32_t s_x[kEmitThreads];         // tx0 | w << 16
-    __shared__ uint32_t s_base[kEmitThreads];      // tile id of (tx0, ty0)
-    __shared__ uint32_t s_stride[kEmitThreads];    // tiles_x of the record's view
+    __shared__ uint32_t s_x[kEmitThreads];         // width in tiles
+    __shared__ uint32_t s_base[kEmitThreads];      // global tile id of the first covered tile
+    __shared__ uint32_t s_stride[kEmitThreads];    // tiles per row of the record's view
     const uint32_t i0 = blockIdx.x * kEmitThreads;
     const uint32_t i = i0 + threadIdx.x;
     const uint32_t base_out = pair_off[i0];
     if (i < n) {
         const uint32_t r = sorted_rec[i];
-        const uint2 rc = rect[r];
-        const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
-        const DevCam& c = cams[recs[r].view];
+        const uint4 rc = rect[r];
         s_rec[threadIdx.x] = r;
-        s_x[threadIdx.x] = tx0 | ((tx1 - tx0 + 1) << 16);
-        s_base[threadIdx.x] = c.tile_base + ty0 * (uint32_t)c.tiles_x + tx0;
-        s_stride[threadIdx.x] = (uint32_t)c.tiles_x;
+        s_x[threadIdx.x] = rc.y & 0xffffu;
+        s_base[threadIdx.x] = rc.x;
+        s_stride[threadIdx.x] = rc.z;
         s_off[threadIdx.x] = pair_off[i] - base_out;
     }
     const uint32_t last = min(n - i0, (uint32_t)kEmitThreads);
@@ -347,7 +410,7 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_pairs(const uint32_t* __r
             else hi = mid;
         }
         const uint32_t t = j - s_off[lo];
-        const uint32_t w = s_x[lo] >> 16;
+        const uint32_t w = s_x[lo];
         // t < 65536, so (t + 0.5) / w in float32 is never within rounding of an integer
         const uint32_t row = (uint32_t)floorf(((float)t + 0.5f) * __builtin_amdgcn_rcpf((float)w));
         const uint32_t col = t - row * w;
@@ -390,19 +453,18 @@ __global__ void k_export_keys(const uint32_t* __restrict__ tile_keys, const uint
     if (vals_out) vals_out[i] = rec.gid;
 }
 
-void launch_gather_tile_counts(const uint32_t* sorted_rec, const uint2* tile_rect, uint32_t n, uint32_t* counts,
+void launch_gather_tile_counts(const uint32_t* sorted_rec, const uint4* tile_rect, uint32_t n, uint32_t* counts,
                                hipStream_t s) {
     if (!n) return;
     hipLaunchKernelGGL(k_gather_tile_counts, dim3((n + 255) / 256), dim3(256), 0, s, sorted_rec, tile_rect, n,
                        counts);
 }
 
-void launch_emit_pairs(const uint32_t* sorted_rec, const uint2* tile_rect, const BlendRec* recs,
-                       const DevCam* cams, const uint32_t* pair_off, uint32_t n, uint32_t K, uint32_t* keys,
-                       uint32_t* vals, hipStream_t s) {
+void launch_emit_pairs(const uint32_t* sorted_rec, const uint4* tile_rect, const uint32_t* pair_off, uint32_t n,
+                       uint32_t K, uint32_t* keys, uint32_t* vals, hipStream_t s) {
     if (!n || !K) return;
     hipLaunchKernelGGL(k_emit_pairs, dim3((n + kEmitThreads - 1) / kEmitThreads), dim3(kEmitThreads), 0, s,
-                       sorted_rec, tile_rect, recs, cams, pair_off, n, K, keys, vals);
+                       sorted_rec, tile_rect, pair_off, n, K, keys, vals);
 }
 
 void launch_ranges(const uint32_t* keys, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s) {

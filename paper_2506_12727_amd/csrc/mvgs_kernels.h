@@ -37,9 +37,9 @@ struct GradArgs {
 void launch_count(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, uint32_t* nrec,
                   uint32_t* ntiles, hipStream_t s);
 void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,
-                    BlendRec* recs, uint32_t* depth_key, uint2* tile_rect, hipStream_t s);
+                    BlendRec* recs, uint32_t* depth_key, uint4* tile_rect, uint16_t* rec_view, hipStream_t s);
 void launch_preprocess_bwd(const GaussianArgs& ga, const DevCam* cams, const uint32_t* rec_off,
-                           const BlendRec* recs, const float* acc, const GradArgs& gr, hipStream_t s);
+                           const uint16_t* rec_view, const float* acc, const GradArgs& gr, hipStream_t s);
 
 // k_sort.hip
 // Exclusive scan of n u32 values (in may equal out). The total is written to *total64 (device).
@@ -50,22 +50,22 @@ void scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* t
 // Sum of n u32 values as u64 into *total64 (device).
 void reduce_sum_u32(const uint32_t* in, size_t n, uint64_t* total64, void* scratch, hipStream_t s);
 
-// Stable LSD radix sort of (key, value) u32 pairs on bits [0, bits). The input is in keys[0] and
-// vals[0] (or, with identity_values, the values are 0..n-1 and vals[0] is only used as
-// ping-pong space); passes alternate between buffers 0 and 1. Returns the index of the buffer
-// holding the sorted result.
+// Stable LSD radix sort of (key, value) u32 pairs on bits [0, bits), 8 bits per pass, one read
+// and one write of keys and values per pass. The input is in keys[0] and vals[0] (or, with
+// identity_values, the values are 0..n-1 and vals[0] is only ping-pong space); passes alternate
+// between buffers 0 and 1. Returns the index of the buffer holding the result. A look-back wait
+// that times out sets *err (device) to a non-zero value instead of hanging.
 size_t radix_scratch_bytes(size_t n);
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
-                   hipStream_t s);
+                   uint32_t* err, hipStream_t s);
 
 void fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 
 // Pair emission in depth order: count per sorted record, then (global tile, record) pairs.
-void launch_gather_tile_counts(const uint32_t* sorted_rec, const uint2* tile_rect, uint32_t n, uint32_t* counts,
+void launch_gather_tile_counts(const uint32_t* sorted_rec, const uint4* tile_rect, uint32_t n, uint32_t* counts,
                                hipStream_t s);
-void launch_emit_pairs(const uint32_t* sorted_rec, const uint2* tile_rect, const BlendRec* recs,
-                       const DevCam* cams, const uint32_t* pair_off, uint32_t n, uint32_t K, uint32_t* keys,
-                       uint32_t* vals, hipStream_t s);
+void launch_emit_pairs(const uint32_t* sorted_rec, const uint4* tile_rect, const uint32_t* pair_off, uint32_t n,
+                       uint32_t K, uint32_t* keys, uint32_t* vals, hipStream_t s);
 void launch_ranges(const uint32_t* keys, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s);
 void launch_export_keys(const uint32_t* tile_keys, const uint32_t* vals, const BlendRec* recs,
                         const DevCam* cams, int B, uint32_t K, uint64_t* keys_out, uint32_t* vals_out,
@@ -98,8 +98,8 @@ struct BlendBwdArgs {
 };
 bool blend_supported(int tw, int th, int ppl);
 int blend_default_ppl(int tw, int th);
-void launch_frame_work(const DevCam* cams, int B, const uint2* ranges, const uint32_t* n_last, uint32_t n_pixels,
-                       int tw, int th, uint64_t* steps, hipStream_t s);
+void launch_frame_work(const DevCam* cams, int B, const uint2* ranges, const uint32_t* vals, const BlendRec* recs,
+                       const uint32_t* n_last, uint32_t n_pixels, int tw, int th, uint64_t* out, hipStream_t s);
 void launch_blend_fwd(const BlendFwdArgs& a, int tw, int th, int ppl, hipStream_t s);
 void launch_blend_bwd(const BlendBwdArgs& a, int tw, int th, int ppl, hipStream_t s);
 
