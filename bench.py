@@ -45,6 +45,12 @@ def parse():
     ap.add_argument("--no-loop", action="store_true", help="skip the one-view-per-call comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-views", type=int, default=2, help="views of the workload in the CPU sample")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="measured serving requests (0: skip)")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="serving requests before the measured ones")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of serving requests (1/s)")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-batch", type=int, default=8)
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -164,6 +170,14 @@ def main():
               key=lambda k: stage_ms[k])
     roof = roofline(dom, stage_ms[dom], info, blended, g, B, cams)
 
+    serve = None
+    if args.serve_requests > 0:
+        rast.close()
+        del imgs, dl, grads
+        torch.cuda.synchronize()
+        serve = serve_bench(args, g if (wl.P, wl.sh_degree) == (1_000_000, 3) and wl.log_scale_mean == -4.0 else None,
+                            tile, ppl)
+
     cpu = None if args.no_cpu else cpu_baseline(scene, cams, tg, wl, (16, 16), args.cpu_views)
     total_px = sum(c.width * c.height for c in cams)
     out = {
@@ -191,9 +205,47 @@ def main():
         "blend_rooflines": {k: roofline(k, stage_ms[k], info, blended, g, B, cams)
                             for k in ("blend_fwd", "blend_bwd")},
         "roofline": roof,
+        "serve": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def serve_bench(args, g, tile, ppl):
+    """Serving loop over a resident 1M-Gaussian SH-3 scene: Poisson arrivals, resolutions uniform
+    over the serving set, poses on a radius-3 sphere; then the same loop with every request
+    arriving at once, which measures throughput at saturation."""
+    import math
+
+    from paper_2506_12727_amd import scenes
+    from paper_2506_12727_amd.raster import GaussianTensors
+    from paper_2506_12727_amd.serve import Server
+
+    if g is None:
+        g = GaussianTensors.from_scene(scenes.make_scene(1_000_000, 3))
+    n = args.serve_warmup + args.serve_requests
+    arr, cams = scenes.make_requests(n, rate_hz=args.serve_rate)
+    budget = int(args.serve_budget_gib * (1 << 30))
+    srv = Server(g, n_slots=args.serve_slots, budget_bytes=budget, max_batch=args.serve_batch, tile=tile,
+                 pixels_per_lane=ppl)
+    try:
+        st = srv.run(arr, cams, measure_from=args.serve_warmup)
+        n_sat = min(n, 600)
+        arr2, cams2 = scenes.make_requests(n_sat, rate_hz=math.inf, seed=scenes.SEED_REQUESTS + 100)
+        sat = srv.run(arr2, cams2)
+    finally:
+        srv.close()
+    out = {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+           "views_per_s": st["views_per_s"], "offered_per_s": args.serve_rate, "requests": st["requests"],
+           "warmup_requests": args.serve_warmup, "rejected": st["rejected"],
+           "mean_batch": st["mean_batch"], "slot_overlap": st["overlap"],
+           "peak_budget_gib": st["peak_budget_bytes"] / (1 << 30), "budget_gib": args.serve_budget_gib,
+           "refused_batches": st["refused_batches"], "slots": args.serve_slots, "max_batch": args.serve_batch,
+           "saturated": {"requests": sat["requests"], "views_per_s": sat["views_per_s"],
+                         "pixels_per_s": sat["pixels_per_s"], "mean_batch": sat["mean_batch"],
+                         "slot_overlap": sat["overlap"]},
+           "resolutions": [list(r) for r in scenes.SERVE_RESOLUTIONS], "gaussians": g.P}
+    return out
 
 
 def roofline(stage, ms, info, blended, g, B, cams):

@@ -99,12 +99,18 @@ typedef struct {
 /* Context options. tile_w, tile_h in {8, 16, 32} (0 selects 16). pixels_per_lane in {1, 2, 4}:
  * each lane of a blend wavefront owns that many pixels of its 8x8, 8x16 or 16x16 sub-tile; 2
  * needs tile_h >= 16, 4 needs tile_w and tile_h >= 16; 0 selects the largest the tile allows.
- * Results do not depend on these choices. */
+ * Results do not depend on these choices.
+ * workspace_limit: 0 for none, else the most device bytes the context may hold (workspace,
+ * upload staging and all its frames, as mvgs_memory_held counts them). A call that would grow
+ * past it allocates nothing and returns MVGS_ECAPACITY; a serving loop admits work against an
+ * HBM budget this way. Must be >= 0. reserved must be zero. */
 typedef struct {
     int32_t tile_w;
     int32_t tile_h;
     int32_t pixels_per_lane;
-    int32_t reserved[5];
+    int32_t reserved0;
+    int64_t workspace_limit;
+    int64_t reserved[2];
 } mvgs_options;
 
 /* Create a context on the current HIP device. `opt` may be NULL (defaults).
@@ -128,7 +134,8 @@ void mvgs_destroy(mvgs_context* ctx);
  *           sorted lists, ranges, final transmittance, last contributor per
  *           pixel); release it with mvgs_frame_release.
  * Synchronizes the stream once to read the number of (Gaussian, tile) pairs,
- * which sizes the sort. Returns MVGS_ECAPACITY if that number reaches 2^32. */
+ * which sizes the sort. Returns MVGS_ECAPACITY if that number reaches 2^32 or
+ * the workspace would exceed the context's limit (no frame is made then). */
 int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_camera* cams, int32_t B,
                  float* const* images, mvgs_frame** frame);
 
@@ -153,6 +160,17 @@ int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, cons
 /* Return a frame's memory to its context. The frame must not be in use by
  * work still pending on a stream other than the one it was created on. */
 int mvgs_frame_release(mvgs_context* ctx, mvgs_frame* frame);
+
+/* Change a context's workspace limit (bytes, 0 for none; see mvgs_options). Memory already held
+ * is kept: the limit applies to later growth. No device work. */
+int mvgs_set_workspace_limit(mvgs_context* ctx, int64_t bytes);
+
+/* Device bytes the context holds now (workspace, staging, frames live or pooled). Host only. */
+int mvgs_memory_held(mvgs_context* ctx, int64_t* bytes);
+
+/* Device bytes the forward that made this frame asked for at exact sizes (its own buffers plus
+ * the context workspace it used), without the growth slack of the context's allocator. */
+int mvgs_frame_workspace(const mvgs_frame* frame, int64_t* bytes);
 
 /* Sizes of a frame: participating (view, Gaussian) records, (Gaussian, tile)
  * pairs and tiles over all views. Any pointer may be NULL. */

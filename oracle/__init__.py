@@ -232,3 +232,35 @@ def count_pairs(scene, cams, tile=(16, 16)):
     ss, cs = s.struct(), c.struct()
     lib().ora_count_pairs(C.byref(ss), C.byref(cs), _ptr(r), _ptr(p))
     return int(r[0]), int(p[0])
+
+
+def subsample_tiles(width: int, height: int, B: int, tile, keys):
+    """Index array of thread-efficient partial rendering (Alg. 3; Sec. 4.1.1) for B views of one
+    size: each tile's pixel positions are shared out among the B views so that the views together
+    cover the image plane once and each renders about N/B pixels of every tile (N pixels per tile).
+
+    The sub-sampling draws one random key per pixel position (`keys`, [height*width] or
+    [height, width], passed in): a tile's positions are ranked by (key, position index) and the
+    position of rank r goes to view r mod B. Returns (offsets, pixels): segment
+    [offsets[s], offsets[s+1]) of `pixels` lists, in rank order, the pixel indices y*width + x of
+    view v in tile t, with s = v * tiles_per_view + t (tiles row-major within a view).
+    Plain loops, one tile at a time."""
+    tw, th = int(tile[0]), int(tile[1])
+    W, H = int(width), int(height)
+    keys = np.asarray(keys, dtype=np.uint32).reshape(-1)
+    assert keys.size == W * H
+    txn, tyn = (W + tw - 1) // tw, (H + th - 1) // th
+    T = txn * tyn
+    segs = [[] for _ in range(B * T)]
+    for ty in range(tyn):
+        for tx in range(txn):
+            t = ty * txn + tx
+            pos = [y * W + x for y in range(ty * th, min(H, ty * th + th))
+                   for x in range(tx * tw, min(W, tx * tw + tw))]
+            ranked = sorted(pos, key=lambda p: (int(keys[p]), p))
+            for r, p in enumerate(ranked):
+                segs[(r % B) * T + t].append(p)
+    offsets = np.zeros(B * T + 1, np.uint32)
+    offsets[1:] = np.cumsum([len(s) for s in segs])
+    pixels = np.array([p for s in segs for p in s], dtype=np.uint32)
+    return offsets, pixels

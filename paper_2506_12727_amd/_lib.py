@@ -22,7 +22,8 @@ MVGS_MAX_TILES_PER_VIEW = 65536
 EXPORTED = ["mvgs_create", "mvgs_destroy", "mvgs_forward", "mvgs_loss", "mvgs_backward", "mvgs_frame_release",
             "mvgs_frame_info", "mvgs_export_binning", "mvgs_export_transmittance", "mvgs_status_string",
             "mvgs_last_error", "mvgs_profile_enable", "mvgs_profile_read", "mvgs_profile_reset",
-            "mvgs_stage_name", "mvgs_frame_work"]
+            "mvgs_stage_name", "mvgs_frame_work", "mvgs_set_workspace_limit", "mvgs_memory_held",
+            "mvgs_frame_workspace"]
 MVGS_STAGE_COUNT = 10
 
 
@@ -48,7 +49,7 @@ class mvgs_densify(C.Structure):
 
 class mvgs_options(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("pixels_per_lane", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("reserved0", C.c_int32), ("workspace_limit", C.c_int64), ("reserved", C.c_int64 * 2)]
 
 
 class MvgsError(RuntimeError):
@@ -103,6 +104,12 @@ def lib():
     L.mvgs_stage_name.restype = C.c_char_p
     L.mvgs_frame_work.argtypes = [vp, vp, vp, vp]
     L.mvgs_frame_work.restype = C.c_int
+    L.mvgs_set_workspace_limit.argtypes = [vp, i64]
+    L.mvgs_set_workspace_limit.restype = C.c_int
+    L.mvgs_memory_held.argtypes = [vp, C.POINTER(i64)]
+    L.mvgs_memory_held.restype = C.c_int
+    L.mvgs_frame_workspace.argtypes = [vp, C.POINTER(i64)]
+    L.mvgs_frame_workspace.restype = C.c_int
     _LIB = L
     return L
 

@@ -22,18 +22,25 @@ struct DevBuf {
     size_t cap = 0;
 };
 
+// Capacity a grow-only buffer has after it is asked for `bytes`: unchanged if it already fits,
+// else at least a quarter more than before, in whole 4 KiB pages.
+size_t grown_capacity(const DevBuf& b, size_t bytes) {
+    if (bytes <= b.cap && b.p) return b.cap;
+    size_t n = std::max<size_t>(bytes, 256);
+    n = std::max(n, b.cap + b.cap / 4);
+    return (n + 4095) & ~(size_t)4095;
+}
+
 // Grow-only device buffer. Growing frees the old allocation (hipFree waits for the device).
 hipError_t ensure(DevBuf& b, size_t bytes) {
     if (bytes <= b.cap && b.p) return hipSuccess;
+    const size_t n = grown_capacity(b, bytes);
     if (b.p) {
         hipError_t e = hipFree(b.p);
         if (e != hipSuccess) return e;
         b.p = nullptr;
         b.cap = 0;
     }
-    size_t n = std::max<size_t>(bytes, 256);
-    n = std::max(n, b.cap + b.cap / 4);
-    n = (n + 4095) & ~(size_t)4095;
     hipError_t e = hipMalloc(&b.p, n);
     if (e != hipSuccess) {
         b.p = nullptr;
@@ -137,7 +144,15 @@ struct mvgs_frame {
     uint32_t V = 0;
     uint64_t K = 0;
     int final_buf = 0;
+    size_t need_bytes = 0;  // device bytes the forward that made this frame asked for
     DevBuf cams, recs, rec_off, rec_view, keys[2], vals[2], ranges, t_final, n_last;
+
+    template <typename Fn>
+    void each_buffer(Fn fn) {
+        DevBuf* bufs[] = {&cams, &recs, &rec_off, &rec_view, &keys[0], &keys[1], &vals[0], &vals[1],
+                          &ranges, &t_final, &n_last};
+        for (DevBuf* b : bufs) fn(*b);
+    }
 };
 
 struct mvgs_context {
@@ -147,6 +162,7 @@ struct mvgs_context {
     std::vector<mvgs_frame*> frames;
     DevBuf nrec, ntiles, totals, scan_scratch, depth_key[2], rec_vals[2], tile_rect, pair_counts, pair_off;
     DevBuf sort_scratch, acc, loss_scratch, ssim_maps;
+    size_t limit = 0;  // 0: no workspace limit
     uint64_t* pinned_totals = nullptr;
     bool device_used = false;
     UploadRing ring;
@@ -162,6 +178,22 @@ struct mvgs_context {
     double prof_ms[MVGS_STAGE_COUNT] = {0};
     int64_t prof_calls[MVGS_STAGE_COUNT] = {0};
     DevBuf work;
+
+    template <typename Fn>
+    void each_buffer(Fn fn) {
+        DevBuf* bufs[] = {&nrec, &ntiles, &totals, &scan_scratch, &depth_key[0], &depth_key[1], &rec_vals[0],
+                          &rec_vals[1], &tile_rect, &pair_counts, &pair_off, &sort_scratch, &acc,
+                          &loss_scratch, &ssim_maps, &work};
+        for (DevBuf* b : bufs) fn(*b);
+        for (auto& sl : ring.slots) fn(sl.dev);
+        for (mvgs_frame* f : frames) f->each_buffer(fn);
+    }
+    // device bytes held now: workspace, upload staging and every frame, live or pooled
+    size_t held() {
+        size_t n = 0;
+        each_buffer([&](DevBuf& b) { n += b.cap; });
+        return n;
+    }
 
     hipEvent_t take_event() {
         if (!ev_pool.empty()) {
@@ -209,6 +241,38 @@ struct mvgs_context {
         return fail(e == hipErrorOutOfMemory ? MVGS_ENOMEM : MVGS_EHIP, "%s: %s", what, hipGetErrorString(e));
     }
 };
+
+namespace {
+
+struct Need {
+    DevBuf* buf;
+    size_t bytes;
+};
+
+// Grows every listed buffer (each listed once) to its size, unless the context would then hold
+// more than its workspace limit: then nothing is allocated and MVGS_ECAPACITY is returned.
+int grow_all(mvgs_context* ctx, const Need* need, int count) {
+    if (ctx->limit) {
+        size_t planned = ctx->held();
+        for (int i = 0; i < count; ++i) planned += grown_capacity(*need[i].buf, need[i].bytes) - need[i].buf->cap;
+        if (planned > ctx->limit)
+            return ctx->fail(MVGS_ECAPACITY, "the call needs the context to hold %zu device bytes; its limit is %zu",
+                             planned, ctx->limit);
+    }
+    for (int i = 0; i < count; ++i) {
+        hipError_t e = ensure(*need[i].buf, need[i].bytes);
+        if (e != hipSuccess) return ctx->hip_fail(e, "workspace allocation");
+    }
+    return MVGS_OK;
+}
+
+size_t need_sum(const Need* need, int count) {
+    size_t n = 0;
+    for (int i = 0; i < count; ++i) n += need[i].bytes;
+    return n;
+}
+
+}  // namespace
 
 #define HIPCHK(ctx, call)                                     \
     do {                                                      \
@@ -309,11 +373,6 @@ mvgs_frame* acquire_frame(mvgs_context* ctx) {
     return f;
 }
 
-void free_frame(mvgs_frame* f) {
-    DevBuf* bufs[] = {&f->cams, &f->recs, &f->rec_off, &f->rec_view, &f->keys[0], &f->keys[1], &f->vals[0],
-                      &f->vals[1], &f->ranges, &f->t_final, &f->n_last};
-    for (DevBuf* b : bufs) release(*b);
-}
 
 }  // namespace
 
@@ -336,11 +395,15 @@ int mvgs_create(mvgs_context** out, const mvgs_options* opt) {
     if (!out) return MVGS_EINVAL;
     *out = nullptr;
     int tw = 16, th = 16, ppl = 0;
+    int64_t limit = 0;
     if (opt) {
         if (opt->tile_w) tw = opt->tile_w;
         if (opt->tile_h) th = opt->tile_h;
         ppl = opt->pixels_per_lane;
+        limit = opt->workspace_limit;
+        if (opt->reserved0 || opt->reserved[0] || opt->reserved[1]) return MVGS_EINVAL;
     }
+    if (limit < 0) return MVGS_EINVAL;
     if (ppl == 0) ppl = blend_default_ppl(tw, th);
     if (!blend_supported(tw, th, ppl)) return MVGS_EINVAL;
     mvgs_context* ctx = new (std::nothrow) mvgs_context();
@@ -348,6 +411,7 @@ int mvgs_create(mvgs_context** out, const mvgs_options* opt) {
     ctx->tw = tw;
     ctx->th = th;
     ctx->ppl = ppl;
+    ctx->limit = (size_t)limit;
     // no HIP call here: device resources are created by the first call that needs them
     *out = ctx;
     return MVGS_OK;
@@ -356,22 +420,14 @@ int mvgs_create(mvgs_context** out, const mvgs_options* opt) {
 void mvgs_destroy(mvgs_context* ctx) {
     if (!ctx) return;
     if (ctx->device_used) (void)hipDeviceSynchronize();
-    for (mvgs_frame* f : ctx->frames) {
-        free_frame(f);
-        delete f;
-    }
-    DevBuf* bufs[] = {&ctx->nrec, &ctx->ntiles, &ctx->totals, &ctx->scan_scratch, &ctx->depth_key[0],
-                      &ctx->depth_key[1], &ctx->rec_vals[0], &ctx->rec_vals[1], &ctx->tile_rect,
-                      &ctx->pair_counts, &ctx->pair_off, &ctx->sort_scratch, &ctx->acc, &ctx->loss_scratch,
-                      &ctx->ssim_maps};
-    for (DevBuf* b : bufs) release(*b);
     ctx->ring.destroy();
+    ctx->each_buffer([](DevBuf& b) { release(b); });
+    for (mvgs_frame* f : ctx->frames) delete f;
     for (auto& m : ctx->marks) {
         (void)hipEventDestroy(m.a);
         (void)hipEventDestroy(m.b);
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-    release(ctx->work);
     if (ctx->pinned_totals) (void)hipHostFree(ctx->pinned_totals);
     delete ctx;
 }
@@ -414,7 +470,16 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
         if (e_ != hipSuccess) return bail(ctx->hip_fail(e_, #call)); \
     } while (0)
 
-    FCHK(ensure(f->cams, sizeof(DevCam) * B));
+    const bool fresh_totals = !ctx->totals.p;
+    const Need need1[] = {{&f->cams, sizeof(DevCam) * B},
+                          {&ctx->nrec, sizeof(uint32_t) * (P + 1)},
+                          {&ctx->ntiles, sizeof(uint32_t) * (P + 1)},
+                          {&ctx->totals, sizeof(uint64_t) * 4},
+                          {&f->rec_off, sizeof(uint32_t) * (P + 1)},
+                          {&ctx->scan_scratch, scan_scratch_bytes(P + 1)}};
+    st = grow_all(ctx, need1, 6);
+    if (st) return bail(st);
+    if (fresh_totals) fill_u32(as<uint32_t>(ctx->totals), 8, 0u, s);
     void* img_ptrs = nullptr;
     {
         void* dcams = nullptr;
@@ -425,14 +490,6 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     const DevCam* dcam = as<DevCam>(f->cams);
 
     // participation and sizes
-    FCHK(ensure(ctx->nrec, sizeof(uint32_t) * (P + 1)));
-    FCHK(ensure(ctx->ntiles, sizeof(uint32_t) * (P + 1)));
-    if (!ctx->totals.p) {
-        FCHK(ensure(ctx->totals, sizeof(uint64_t) * 4));
-        fill_u32(as<uint32_t>(ctx->totals), 8, 0u, s);
-    }
-    FCHK(ensure(f->rec_off, sizeof(uint32_t) * (P + 1)));
-    FCHK(ensure(ctx->scan_scratch, scan_scratch_bytes(P + 1)));
     int mk = ctx->stage_begin(0, s);
     fill_u32(as<uint32_t>(ctx->nrec) + P, 1, 0u, s);
     launch_count(ga, dcam, B, tw, th, as<uint32_t>(ctx->nrec), as<uint32_t>(ctx->ntiles), s);
@@ -460,23 +517,32 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     f->K = K;
 
     // records and the depth sort
-    FCHK(ensure(f->recs, sizeof(BlendRec) * std::max<uint32_t>(V, 1)));
-    FCHK(ensure(f->rec_view, sizeof(uint16_t) * std::max<uint32_t>(V, 1)));
-    FCHK(ensure(ctx->depth_key[0], sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
-    FCHK(ensure(ctx->depth_key[1], sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
-    FCHK(ensure(ctx->rec_vals[0], sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
-    FCHK(ensure(ctx->rec_vals[1], sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
-    FCHK(ensure(ctx->tile_rect, sizeof(uint4) * std::max<uint32_t>(V, 1)));
-    FCHK(ensure(ctx->pair_counts, sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
-    FCHK(ensure(ctx->pair_off, sizeof(uint32_t) * std::max<uint32_t>(V, 1)));
-    FCHK(ensure(f->keys[0], sizeof(uint32_t) * std::max<uint32_t>(K, 1)));
-    FCHK(ensure(f->keys[1], sizeof(uint32_t) * std::max<uint32_t>(K, 1)));
-    FCHK(ensure(f->vals[0], sizeof(uint32_t) * std::max<uint32_t>(K, 1)));
-    FCHK(ensure(f->vals[1], sizeof(uint32_t) * std::max<uint32_t>(K, 1)));
-    FCHK(ensure(f->ranges, sizeof(uint2) * std::max<uint32_t>(n_tiles, 1)));
-    FCHK(ensure(f->t_final, sizeof(float) * n_pixels));
-    FCHK(ensure(f->n_last, sizeof(uint32_t) * n_pixels));
-    FCHK(ensure(ctx->sort_scratch, std::max(radix_scratch_bytes(std::max<size_t>(V, K)), scan_scratch_bytes(V))));
+    const size_t V1 = std::max<uint32_t>(V, 1), K1 = std::max<uint32_t>(K, 1);
+    const Need need2[] = {{&f->recs, sizeof(BlendRec) * V1},
+                          {&f->rec_view, sizeof(uint16_t) * V1},
+                          {&ctx->depth_key[0], sizeof(uint32_t) * V1},
+                          {&ctx->depth_key[1], sizeof(uint32_t) * V1},
+                          {&ctx->rec_vals[0], sizeof(uint32_t) * V1},
+                          {&ctx->rec_vals[1], sizeof(uint32_t) * V1},
+                          {&ctx->tile_rect, sizeof(uint4) * V1},
+                          {&ctx->pair_counts, sizeof(uint32_t) * V1},
+                          {&ctx->pair_off, sizeof(uint32_t) * V1},
+                          {&f->keys[0], sizeof(uint32_t) * K1},
+                          {&f->keys[1], sizeof(uint32_t) * K1},
+                          {&f->vals[0], sizeof(uint32_t) * K1},
+                          {&f->vals[1], sizeof(uint32_t) * K1},
+                          {&f->ranges, sizeof(uint2) * std::max<uint32_t>(n_tiles, 1)},
+                          {&f->t_final, sizeof(float) * n_pixels},
+                          {&f->n_last, sizeof(uint32_t) * n_pixels},
+                          {&ctx->sort_scratch,
+                           std::max(radix_scratch_bytes(std::max<size_t>(V, K)), scan_scratch_bytes(V))}};
+    const int n_need2 = (int)(sizeof(need2) / sizeof(need2[0]));
+    st = grow_all(ctx, need2, n_need2);
+    if (st) {
+        (void)ctx->ring.seal(s);
+        return bail(st);
+    }
+    f->need_bytes = need_sum(need1, 6) + need_sum(need2, n_need2);
 
     mk = ctx->stage_begin(1, s);
     launch_records(ga, dcam, B, tw, th, as<uint32_t>(f->rec_off), as<BlendRec>(f->recs),
@@ -553,8 +619,10 @@ int mvgs_loss(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t 
     }
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(ctx, ctx->bind_device());
-    HIPCHK(ctx, ensure(ctx->loss_scratch, loss_scratch_bytes(n_pixels, B)));
-    if (w_dssim != 0.0f) HIPCHK(ctx, ensure(ctx->ssim_maps, ssim_map_bytes(max_hw)));
+    const Need need[] = {{&ctx->loss_scratch, loss_scratch_bytes(n_pixels, B)},
+                         {&ctx->ssim_maps, w_dssim != 0.0f ? ssim_map_bytes(max_hw) : 0}};
+    st = grow_all(ctx, need, w_dssim != 0.0f ? 2 : 1);
+    if (st) return st;
     void* dviews = nullptr;
     HIPCHK(ctx, ctx->ring.put(lv.data(), sizeof(LossView) * B, s, &dviews));
     const int mk = ctx->stage_begin(7, s);
@@ -584,7 +652,9 @@ int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, cons
     hipStream_t s = (hipStream_t)stream;
     mvgs_frame* f = const_cast<mvgs_frame*>(frame);
     const uint32_t V = f->V;
-    HIPCHK(ctx, ensure(ctx->acc, sizeof(float) * kAccStride * std::max<uint32_t>(V, 1)));
+    const Need need[] = {{&ctx->acc, sizeof(float) * kAccStride * std::max<uint32_t>(V, 1)}};
+    st = grow_all(ctx, need, 1);
+    if (st) return st;
     fill_u32(as<uint32_t>(ctx->acc), (size_t)kAccStride * V, 0u, s);
     void* dptrs = nullptr;
     HIPCHK(ctx, ctx->ring.put(dl_dimages, sizeof(float*) * f->B, s, &dptrs));
@@ -624,6 +694,24 @@ int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, cons
 int mvgs_frame_release(mvgs_context* ctx, mvgs_frame* frame) {
     if (!ctx || !frame || frame->ctx != ctx) return MVGS_EINVAL;
     frame->in_use = false;
+    return MVGS_OK;
+}
+
+int mvgs_set_workspace_limit(mvgs_context* ctx, int64_t bytes) {
+    if (!ctx || bytes < 0) return MVGS_EINVAL;
+    ctx->limit = (size_t)bytes;
+    return MVGS_OK;
+}
+
+int mvgs_memory_held(mvgs_context* ctx, int64_t* bytes) {
+    if (!ctx || !bytes) return MVGS_EINVAL;
+    *bytes = (int64_t)ctx->held();
+    return MVGS_OK;
+}
+
+int mvgs_frame_workspace(const mvgs_frame* frame, int64_t* bytes) {
+    if (!frame || !bytes) return MVGS_EINVAL;
+    *bytes = (int64_t)frame->need_bytes;
     return MVGS_OK;
 }
 

@@ -61,6 +61,12 @@ class Frame:
         self.rast, self.handle, self.cams = rast, handle, list(cams)
         self.released = False
 
+    def workspace(self) -> int:
+        """Device bytes the forward that made this frame asked for (exact sizes)."""
+        b = C.c_int64()
+        L.check(L.lib().mvgs_frame_workspace(self.handle, C.byref(b)))
+        return int(b.value)
+
     def info(self):
         V, K, T = C.c_int64(), C.c_int64(), C.c_int64()
         L.check(L.lib().mvgs_frame_info(self.handle, C.byref(V), C.byref(K), C.byref(T)))
@@ -72,14 +78,24 @@ class Frame:
 
 
 class Rasterizer:
-    def __init__(self, tile=(16, 16), pixels_per_lane=0):
+    def __init__(self, tile=(16, 16), pixels_per_lane=0, workspace_limit=0):
         self.lib = L.lib()
         opt = L.mvgs_options()
         opt.tile_w, opt.tile_h = int(tile[0]), int(tile[1])
         opt.pixels_per_lane = int(pixels_per_lane)
+        opt.workspace_limit = int(workspace_limit)
         self.ctx = C.c_void_p()
         L.check(self.lib.mvgs_create(C.byref(self.ctx), C.byref(opt)))
         self.tile = (opt.tile_w, opt.tile_h)
+
+    def set_workspace_limit(self, nbytes: int):
+        """Most device bytes this context may hold from now on (0: no limit)."""
+        L.check(self.lib.mvgs_set_workspace_limit(self.ctx, int(nbytes)), self.ctx)
+
+    def memory_held(self) -> int:
+        b = C.c_int64()
+        L.check(self.lib.mvgs_memory_held(self.ctx, C.byref(b)), self.ctx)
+        return int(b.value)
 
     def close(self):
         if self.ctx:

@@ -179,3 +179,24 @@ WORKLOADS = {
 }
 
 SERVE_RESOLUTIONS = [(256, 256), (640, 480), (1280, 720), (1920, 1080)]
+
+
+def make_requests(n: int, rate_hz: float = 200.0, seed: int = SEED_REQUESTS,
+                  resolutions: Sequence[Tuple[int, int]] = SERVE_RESOLUTIONS, radius: float = 3.0):
+    """A seeded stream of `n` render requests: Poisson arrivals at `rate_hz` (exponential gaps,
+    first arrival after one gap; rate 0 or inf puts every arrival at 0), a resolution drawn
+    uniformly from `resolutions`, and a camera on a sphere of `radius` looking at the origin.
+    Returns (arrival seconds [n] float64, list of Camera)."""
+    rng = _rng(seed)
+    if rate_hz and math.isfinite(rate_hz):
+        arrivals = np.cumsum(rng.exponential(1.0 / rate_hz, size=n))
+    else:
+        arrivals = np.zeros(n)
+    which = rng.integers(0, len(resolutions), size=n)
+    cams = []
+    for i in range(n):
+        d = rng.normal(0.0, 1.0, size=3)
+        d /= np.linalg.norm(d)
+        w, h = resolutions[int(which[i])]
+        cams.append(make_camera(w, h, d * radius))
+    return arrivals, cams

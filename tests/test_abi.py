@@ -127,3 +127,26 @@ def test_product_path_has_no_oracle_dependency():
             if f.endswith((".py", ".hip", ".cpp", ".h")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src and "liboracle" not in src, f
+
+
+def test_workspace_limit_options_and_memory_queries():
+    lib = L.lib()
+    o = L.mvgs_options()
+    o.workspace_limit = -1
+    h = C.c_void_p()
+    assert lib.mvgs_create(C.byref(h), C.byref(o)) == L.MVGS_EINVAL
+    o = L.mvgs_options()
+    o.reserved[1] = 5
+    assert lib.mvgs_create(C.byref(h), C.byref(o)) == L.MVGS_EINVAL
+    o = L.mvgs_options()
+    o.workspace_limit = 1 << 30
+    assert lib.mvgs_create(C.byref(h), C.byref(o)) == L.MVGS_OK
+    held = C.c_int64(-1)
+    # a fresh context holds no device memory; the query makes no HIP call
+    assert lib.mvgs_memory_held(h, C.byref(held)) == L.MVGS_OK and held.value == 0
+    assert lib.mvgs_memory_held(h, None) == L.MVGS_EINVAL
+    assert lib.mvgs_set_workspace_limit(h, -5) == L.MVGS_EINVAL
+    assert lib.mvgs_set_workspace_limit(h, 0) == L.MVGS_OK
+    assert lib.mvgs_set_workspace_limit(None, 0) == L.MVGS_EINVAL
+    assert lib.mvgs_frame_workspace(None, C.byref(held)) == L.MVGS_EINVAL
+    lib.mvgs_destroy(h)

@@ -1,5 +1,5 @@
-"""Parity at the benchmark workloads' full sizes, in the launch configuration bench.py times
-(16x16 tiles, all views in one batch).
+"""Parity at the benchmark workloads' full sizes, all views in one batch, with 16x16 tiles and,
+for the 1M-Gaussian 8-view batch, every launch shape the autotuner may pick for bench.py.
 
 The whole oracle render is too slow here, so the checks use what it can compute at any size:
 record and pair counts, the exact sorted list of sampled (view, tile)s, sampled pixels walked one by
@@ -13,6 +13,8 @@ import torch
 import oracle
 from paper_2506_12727_amd import scenes
 from paper_2506_12727_amd.raster import GaussianTensors, Rasterizer
+
+from paper_2506_12727_amd.tune import CANDIDATES
 
 from gpu_common import needs_gpu
 
@@ -28,6 +30,24 @@ def _setup(name):
     return _CACHE[name]
 
 
+def _geom(name, sc, cams, v):
+    key = ("geom", name, v)
+    if key not in _CACHE:
+        _CACHE[key] = oracle.geom32(sc, cams, v)
+    return _CACHE[key]
+
+
+def _pixels(name, sc, cams, v):
+    """48 seeded pixels of view v and the oracle's walk over every participating Gaussian."""
+    key = ("pix", name, v)
+    if key not in _CACHE:
+        c = cams[v]
+        rng = np.random.default_rng(100 + v)
+        xs, ys = rng.integers(0, c.width, 48), rng.integers(0, c.height, 48)
+        _CACHE[key] = (xs, ys) + tuple(oracle.render_pixels(sc, cams, v, xs, ys))
+    return _CACHE[key]
+
+
 def _tile_list_oracle(g32, cam, tile_xy, tile=(16, 16)):
     """Gaussians of one view whose tile rectangle covers tile (tx, ty), in (depth bits, index) order."""
     tx, ty = tile_xy
@@ -39,16 +59,21 @@ def _tile_list_oracle(g32, cam, tile_xy, tile=(16, 16)):
     return idx[order].astype(np.uint32), g32["depth_bits"][idx][order]
 
 
-@pytest.mark.parametrize("name,views_checked", [("uneven_1m_8view", 8), ("train_300k_4x1600x1064_dssim", 4),
-                                                ("large_3m_16x1280x840", 3)])
-def test_fullsize_binning_and_sampled_pixels(name, views_checked):
+FULL = [("uneven_1m_8view", 8, (16, 16), 0)] + \
+    [("uneven_1m_8view", 8, t, p) for t, p in CANDIDATES if (t, p) != ((16, 16), 0)] + \
+    [("train_300k_4x1600x1064_dssim", 4, (16, 16), 0), ("large_3m_16x1280x840", 3, (16, 16), 0)]
+
+
+@pytest.mark.parametrize("name,views_checked,tile,ppl", FULL)
+def test_fullsize_binning_and_sampled_pixels(name, views_checked, tile, ppl):
     needs_gpu()
     wl, sc, cams = _setup(name)
-    r = Rasterizer((16, 16))
+    r = Rasterizer(tile, ppl)
+    tw, th = tile
     g = GaussianTensors.from_scene(sc)
     imgs, fr = r.forward(g, cams)
     info = fr.info()
-    recs, pairs = oracle.count_pairs(sc, cams)
+    recs, pairs = oracle.count_pairs(sc, cams, tile)
     assert (info["records"], info["pairs"]) == (recs, pairs)
     keys, vals, ranges = r.export_binning(fr)
     assert bool((keys[1:] >= keys[:-1]).all())
@@ -59,20 +84,19 @@ def test_fullsize_binning_and_sampled_pixels(name, views_checked):
     tile_base = 0
     n_flag = n_pix = 0
     for v, c in enumerate(cams):
-        tx_n, ty_n = (c.width + 15) // 16, (c.height + 15) // 16
+        tx_n, ty_n = (c.width + tw - 1) // tw, (c.height + th - 1) // th
         if v < views_checked:
-            g32 = oracle.geom32(sc, cams, v)
+            g32 = _geom(name, sc, cams, v)
             for _ in range(6):
                 tx, ty = int(rng.integers(tx_n)), int(rng.integers(ty_n))
-                want_g, want_d = _tile_list_oracle(g32, c, (tx, ty))
+                want_g, want_d = _tile_list_oracle(g32, c, (tx, ty), tile)
                 a, b = rn[tile_base + ty * tx_n + tx]
                 assert b - a == len(want_g)
                 assert np.array_equal(vn[a:b], want_g)
                 key = (np.uint64(v) << np.uint64(48)) | (np.uint64(ty * tx_n + tx) << np.uint64(32)) | \
                     want_d.astype(np.uint64)
                 assert np.array_equal(kn[a:b], key)
-            xs, ys = rng.integers(0, c.width, 48), rng.integers(0, c.height, 48)
-            rgb, tf, fl = oracle.render_pixels(sc, cams, v, xs, ys)
+            xs, ys, rgb, tf, fl = _pixels(name, sc, cams, v)
             got = imgs[v].cpu().numpy().astype(np.float64)[:, ys, xs].T
             ok = fl == 0
             n_flag += int((~ok).sum())
