@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--no-partial", action="store_true", help="skip the partial-rendering comparison")
+    ap.add_argument("--partial-views", type=int, default=8)
+    ap.add_argument("--partial-size", default="1280x720")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -170,6 +173,10 @@ def main():
               key=lambda k: stage_ms[k])
     roof = roofline(dom, stage_ms[dom], info, blended, g, B, cams)
 
+    partial = None
+    if not args.no_partial:
+        partial = partial_bench(args, g, wl, tile, ppl)
+
     serve = None
     if args.serve_requests > 0:
         rast.close()
@@ -205,10 +212,85 @@ def main():
         "blend_rooflines": {k: roofline(k, stage_ms[k], info, blended, g, B, cams)
                             for k in ("blend_fwd", "blend_bwd")},
         "roofline": roof,
+        "partial": partial,
         "serve": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def partial_bench(args, g, wl, tile, ppl):
+    """Thread-efficient partial rendering (Alg. 3) against its baselines on B views of one size
+    (the scene of the main workload): every step renders the batch, takes an L1 loss and runs the
+    backward. full = every pixel of every view; masked = the binary-mask baseline; compact = the
+    thread-efficient scheme; single = one view, every pixel. In the partial modes each tile's pixels
+    are shared out among the views (fresh random keys every step), so the batch renders one image
+    plane's worth of pixels, written as one merged image."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2506_12727_amd import _lib as L
+    from paper_2506_12727_amd import scenes
+    from paper_2506_12727_amd.raster import Rasterizer
+
+    W, H = (int(x) for x in args.partial_size.split("x"))
+    B = args.partial_views
+    cams = scenes.make_cameras([(W, H)] * B, radius=wl.radius)
+    tg = [torch.from_numpy(t).cuda() for t in scenes.make_targets(cams)]
+    keys_tg = torch.from_numpy(scenes.make_targets(cams[:1], seed=scenes.SEED_TARGETS + 1)[0]).cuda()
+    rast = Rasterizer(tile, ppl)
+    lib = L.lib()
+    imgs = [torch.empty((3, H, W), device="cuda") for _ in range(B)]
+    dl = [torch.empty_like(t) for t in imgs]
+    merged, merged_dl = torch.empty((3, H, W), device="cuda"), torch.empty((3, H, W), device="cuda")
+    loss = torch.empty(1, device="cuda")
+    grads = dict(means=torch.empty_like(g.means), scales=torch.empty_like(g.scales), quats=torch.empty_like(g.quats),
+                 opacities=torch.empty_like(g.opacities), sh=torch.empty_like(g.sh))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(scenes.SEED_REQUESTS)
+
+    def full_step(n):
+        v = cams[:n]
+        _, fr = rast.forward(g, v, images=imgs[:n])
+        rast.loss(v, imgs[:n], tg[:n], 1.0, 0.0, out=loss, grads=dl[:n])
+        rast.backward(g, fr, dl[:n], grads=grads)
+        rast.release(fr)
+
+    def partial_step(mode):
+        keys = torch.randint(-2 ** 31, 2 ** 31 - 1, (W * H,), dtype=torch.int32, device="cuda", generator=gen)
+        off, pix = rast.subsample(cams, keys)
+        _, fr = rast.forward_partial(g, cams, off, pix, mode, images=[merged] * B)
+        rast.loss(cams[:1], [merged], [keys_tg], 1.0, 0.0, out=loss, grads=[merged_dl])
+        rast.backward(g, fr, [merged_dl] * B, grads=grads)
+        rast.release(fr)
+
+    runs = {"full": lambda: full_step(B), "masked": lambda: partial_step(L.MVGS_PARTIAL_MASKED),
+            "compact": lambda: partial_step(L.MVGS_PARTIAL_COMPACT), "single": lambda: full_step(1)}
+    out = {"views": B, "size": [W, H], "tile": list(tile), "pixels_per_lane": ppl}
+    steps = max(5, args.steps // 2)
+    ms = (C.c_double * L.MVGS_STAGE_COUNT)()
+    calls = (C.c_int64 * L.MVGS_STAGE_COUNT)()
+    for name, fn in runs.items():
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        lib.mvgs_profile_reset(rast.ctx)
+        lib.mvgs_profile_enable(rast.ctx, 1)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        lib.mvgs_profile_enable(rast.ctx, 0)
+        L.check(lib.mvgs_profile_read(rast.ctx, ms, calls), rast.ctx)
+        out[name] = {"ms_per_step": 1e3 * dt,
+                     "blend_fwd_ms": ms[6] / max(calls[6], 1), "blend_bwd_ms": ms[8] / max(calls[8], 1)}
+    out["compact_vs_full_speedup"] = out["full"]["ms_per_step"] / out["compact"]["ms_per_step"]
+    out["compact_vs_masked_speedup"] = out["masked"]["ms_per_step"] / out["compact"]["ms_per_step"]
+    out["compact_vs_single_view_overhead"] = out["compact"]["ms_per_step"] / out["single"]["ms_per_step"]
+    rast.close()
+    return out
 
 
 def serve_bench(args, g, tile, ppl):

@@ -139,6 +139,41 @@ void mvgs_destroy(mvgs_context* ctx);
 int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_camera* cams, int32_t B,
                  float* const* images, mvgs_frame** frame);
 
+/* Partial rendering (paper Sec. 4.1.1, "Thread-efficient partial rendering", and Alg. 3): each view
+ * renders only a selection of its pixels, the paper's index array. The selection is given per
+ * (view, tile) of the batch, in the order of the ranges (view-major; tiles of tile_w x tile_h of
+ * this context, row-major):
+ *   sel_offsets  device uint32 [n_tiles + 1], rising from 0 to n_sel; segment s of the selection is
+ *                [sel_offsets[s], sel_offsets[s+1]), s = tile_base(v) + ty * tiles_x(v) + tx
+ *   sel_pixels   device uint32 [n_sel], pixel indices y * width_v + x inside the segment's tile,
+ *                each pixel at most once, in any order
+ * Modes: MVGS_PARTIAL_COMPACT is the paper's thread-efficient scheme, one wavefront per 64 selected
+ * pixels of a segment so that no lane idles; MVGS_PARTIAL_MASKED is its binary-mask baseline, the
+ * full-tile launch with the lanes of unselected pixels idle. Both give bit-identical values, equal to
+ * the full forward's at the selected pixels. Only selected pixels of images[v] are written (the
+ * others keep their contents), so passing one buffer for all views of a sub-sampled batch yields
+ * the merged image. The selection is copied into the frame and checked on the device before any
+ * blending: a bad selection returns MVGS_EINVAL (after the stream synchronization the forward does
+ * anyway). mvgs_backward on such a frame reads dL/dimage at the selected pixels only;
+ * mvgs_export_transmittance writes the selected pixels only (masked mode: every pixel, 1 where
+ * unselected). Otherwise as mvgs_forward. */
+#define MVGS_PARTIAL_COMPACT 0
+#define MVGS_PARTIAL_MASKED 1
+int mvgs_forward_partial(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_camera* cams,
+                         int32_t B, const uint32_t* sel_offsets, const uint32_t* sel_pixels, int64_t n_sel,
+                         int32_t mode, float* const* images, mvgs_frame** frame);
+
+/* Pixel sub-sampling for partial rendering of B views of one size (paper Sec. 4.1.1: pixels of every
+ * tile are sub-sampled per view): the positions of each tile (of this context's tile shape) are
+ * ranked by keys[y * width + x] (device uint32 [height * width], random numbers drawn by the
+ * caller), ties by position, and the position of rank r goes to view r mod B. The views thus share
+ * every tile out evenly (ceil or floor of N/B pixels each) and together cover the image plane once.
+ * Writes the selection in mvgs_forward_partial's format: sel_offsets [B * tiles + 1], sel_pixels
+ * [height * width] (caller-owned device buffers), each segment in rank order. MVGS_EINVAL if the
+ * views differ in size. */
+int mvgs_subsample(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t B, const uint32_t* keys,
+                   uint32_t* sel_offsets, uint32_t* sel_pixels);
+
 /* Photometric loss (paper Sec. 3; D-SSIM of Sec. 5.1.2, Eqs. 7-10):
  *   L = w_l1 * mean|I - T| + w_dssim * (1 - mean SSIM(I, T))
  * means over every (view, channel, row, column); SSIM with an 11x11 Gaussian

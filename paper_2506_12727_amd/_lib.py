@@ -23,7 +23,9 @@ EXPORTED = ["mvgs_create", "mvgs_destroy", "mvgs_forward", "mvgs_loss", "mvgs_ba
             "mvgs_frame_info", "mvgs_export_binning", "mvgs_export_transmittance", "mvgs_status_string",
             "mvgs_last_error", "mvgs_profile_enable", "mvgs_profile_read", "mvgs_profile_reset",
             "mvgs_stage_name", "mvgs_frame_work", "mvgs_set_workspace_limit", "mvgs_memory_held",
-            "mvgs_frame_workspace"]
+            "mvgs_frame_workspace", "mvgs_forward_partial", "mvgs_subsample"]
+MVGS_PARTIAL_COMPACT = 0
+MVGS_PARTIAL_MASKED = 1
 MVGS_STAGE_COUNT = 10
 
 
@@ -110,6 +112,11 @@ def lib():
     L.mvgs_memory_held.restype = C.c_int
     L.mvgs_frame_workspace.argtypes = [vp, C.POINTER(i64)]
     L.mvgs_frame_workspace.restype = C.c_int
+    L.mvgs_forward_partial.argtypes = [vp, vp, C.POINTER(mvgs_gaussians), C.POINTER(mvgs_camera), i32, vp, vp, i64,
+                                       i32, vp, C.POINTER(vp)]
+    L.mvgs_forward_partial.restype = C.c_int
+    L.mvgs_subsample.argtypes = [vp, vp, C.POINTER(mvgs_camera), i32, vp, vp, vp]
+    L.mvgs_subsample.restype = C.c_int
     _LIB = L
     return L
 

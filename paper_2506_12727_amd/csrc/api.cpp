@@ -133,6 +133,8 @@ struct UploadRing {
 
 }  // namespace
 
+constexpr int kModeFull = -1;  // otherwise MVGS_PARTIAL_COMPACT or MVGS_PARTIAL_MASKED
+
 struct mvgs_frame {
     mvgs_context* ctx = nullptr;
     bool in_use = false;
@@ -145,12 +147,17 @@ struct mvgs_frame {
     uint64_t K = 0;
     int final_buf = 0;
     size_t need_bytes = 0;  // device bytes the forward that made this frame asked for
+    // partial rendering: kModeFull renders every pixel; the others a selection (t_final and
+    // n_last then hold one entry per selected pixel in thread-efficient mode)
+    int mode = kModeFull;
+    uint32_t n_sel = 0, n_tasks = 0;
     DevBuf cams, recs, rec_off, rec_view, keys[2], vals[2], ranges, t_final, n_last;
+    DevBuf sel_off, sel_pix, mask, task_n, task_off, tasks;
 
     template <typename Fn>
     void each_buffer(Fn fn) {
-        DevBuf* bufs[] = {&cams, &recs, &rec_off, &rec_view, &keys[0], &keys[1], &vals[0], &vals[1],
-                          &ranges, &t_final, &n_last};
+        DevBuf* bufs[] = {&cams, &recs, &rec_off, &rec_view, &keys[0], &keys[1], &vals[0], &vals[1], &ranges,
+                          &t_final, &n_last, &sel_off, &sel_pix, &mask, &task_n, &task_off, &tasks};
         for (DevBuf* b : bufs) fn(*b);
     }
 };
@@ -432,8 +439,35 @@ void mvgs_destroy(mvgs_context* ctx) {
     delete ctx;
 }
 
-int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_camera* cams, int32_t B,
-                 float* const* images, mvgs_frame** frame) {
+}  // extern "C"
+
+namespace {
+
+SelBlendArgs sel_args(mvgs_frame* f) {
+    SelBlendArgs sa{};
+    sa.cams = as<DevCam>(f->cams);
+    sa.B = f->B;
+    sa.ranges = as<uint2>(f->ranges);
+    sa.vals = as<uint32_t>(f->vals[f->final_buf]);
+    sa.recs = as<BlendRec>(f->recs);
+    sa.sel_off = as<uint32_t>(f->sel_off);
+    sa.sel_pix = as<uint32_t>(f->sel_pix);
+    sa.tasks = as<uint2>(f->tasks);
+    sa.n_tasks = f->n_tasks;
+    sa.t_sel = as<float>(f->t_final);
+    sa.last_sel = as<uint32_t>(f->n_last);
+    return sa;
+}
+
+struct SelIn {
+    const uint32_t* off;
+    const uint32_t* pix;
+    uint32_t n_sel;
+    int mode;
+};
+
+int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_camera* cams, int32_t B,
+                 float* const* images, mvgs_frame** frame, const SelIn* sel) {
     if (!ctx) return MVGS_EINVAL;
     if (!frame) return ctx->fail(MVGS_EINVAL, "frame output is NULL");
     *frame = nullptr;
@@ -456,6 +490,9 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     f->sh_degree = g->sh_degree;
     f->n_tiles = n_tiles;
     f->n_pixels = n_pixels;
+    f->mode = sel ? sel->mode : kModeFull;
+    f->n_sel = sel ? sel->n_sel : 0;
+    f->n_tasks = 0;
     build_cams(cams, B, tw, th, f->hcams);
     const GaussianArgs ga = gargs(g);
     const size_t P = (size_t)g->P;
@@ -471,13 +508,23 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     } while (0)
 
     const bool fresh_totals = !ctx->totals.p;
+    // tasks of thread-efficient partial rendering: at most one per segment plus one per 64 pixels
+    const size_t task_cap = sel ? (size_t)n_tiles + sel->n_sel / 64 + 1 : 0;
+    const size_t mask_words = ((size_t)n_pixels + 31) / 32;
     const Need need1[] = {{&f->cams, sizeof(DevCam) * B},
                           {&ctx->nrec, sizeof(uint32_t) * (P + 1)},
                           {&ctx->ntiles, sizeof(uint32_t) * (P + 1)},
                           {&ctx->totals, sizeof(uint64_t) * 4},
                           {&f->rec_off, sizeof(uint32_t) * (P + 1)},
-                          {&ctx->scan_scratch, scan_scratch_bytes(P + 1)}};
-    st = grow_all(ctx, need1, 6);
+                          {&ctx->scan_scratch, scan_scratch_bytes(std::max<size_t>(P + 1, n_tiles))},
+                          {&f->sel_off, sel ? sizeof(uint32_t) * ((size_t)n_tiles + 1) : 0},
+                          {&f->sel_pix, sel ? sizeof(uint32_t) * std::max<size_t>(sel->n_sel, 1) : 0},
+                          {&f->mask, sel ? sizeof(uint32_t) * mask_words : 0},
+                          {&f->task_n, sel ? sizeof(uint32_t) * n_tiles : 0},
+                          {&f->task_off, sel ? sizeof(uint32_t) * n_tiles : 0},
+                          {&f->tasks, sel ? sizeof(uint2) * task_cap : 0}};
+    const int n_need1 = sel ? 12 : 6;
+    st = grow_all(ctx, need1, n_need1);
     if (st) return bail(st);
     if (fresh_totals) fill_u32(as<uint32_t>(ctx->totals), 8, 0u, s);
     void* img_ptrs = nullptr;
@@ -496,18 +543,55 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     scan_exclusive_u32(as<uint32_t>(ctx->nrec), as<uint32_t>(f->rec_off), P + 1, as<uint64_t>(ctx->totals),
                        ctx->scan_scratch.p, s);
     reduce_sum_u32(as<uint32_t>(ctx->ntiles), P, as<uint64_t>(ctx->totals) + 1, nullptr, s);
+    uint32_t* sel_err = reinterpret_cast<uint32_t*>(as<uint64_t>(ctx->totals) + 2) + 1;
+    if (sel) {
+        // the selection: private copy, checks, pixel mask, wavefront tasks
+        if (n_tiles) FCHK(hipMemcpyAsync(f->sel_off.p, sel->off, sizeof(uint32_t) * ((size_t)n_tiles + 1),
+                                         hipMemcpyDeviceToDevice, s));
+        if (sel->n_sel) FCHK(hipMemcpyAsync(f->sel_pix.p, sel->pix, sizeof(uint32_t) * sel->n_sel,
+                                            hipMemcpyDeviceToDevice, s));
+        fill_u32(as<uint32_t>(f->mask), mask_words, 0u, s);
+        fill_u32(sel_err, 1, 0u, s);
+        fill_u32(reinterpret_cast<uint32_t*>(as<uint64_t>(ctx->totals) + 3), 2, 0u, s);
+        if (n_tiles) {
+            launch_sel_check(dcam, B, n_tiles, tw, th, as<uint32_t>(f->sel_off), as<uint32_t>(f->sel_pix),
+                             sel->n_sel, as<uint32_t>(f->mask), as<uint32_t>(f->task_n), sel_err, s);
+            scan_exclusive_u32(as<uint32_t>(f->task_n), as<uint32_t>(f->task_off), n_tiles,
+                               as<uint64_t>(ctx->totals) + 3, ctx->scan_scratch.p, s);
+            launch_sel_tasks(n_tiles, as<uint32_t>(f->task_n), as<uint32_t>(f->task_off), (uint32_t)task_cap,
+                             as<uint2>(f->tasks), s);
+        }
+    }
     ctx->stage_end(mk, s);
     FCHK(hipGetLastError());
-    FCHK(hipMemcpyAsync(ctx->pinned_totals, ctx->totals.p, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    FCHK(hipMemcpyAsync(ctx->pinned_totals, ctx->totals.p, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     FCHK(hipStreamSynchronize(s));
     const uint64_t V64 = ctx->pinned_totals[0], K64 = ctx->pinned_totals[1];
-    if (ctx->pinned_totals[2] != 0) {
+    if (sel) {
+        const uint32_t e = (uint32_t)(ctx->pinned_totals[2] >> 32);
+        if (e) {
+            (void)ctx->ring.seal(s);
+            return bail(ctx->fail(MVGS_EINVAL, "pixel selection rejected:%s%s%s%s",
+                                  (e & kSelBadOffsets) ? " offsets do not rise from 0 to n_sel;" : "",
+                                  (e & kSelTooLong) ? " a segment holds more pixels than a tile;" : "",
+                                  (e & kSelOutside) ? " a pixel lies outside its (view, tile);" : "",
+                                  (e & kSelDuplicate) ? " a pixel is selected twice;" : ""));
+        }
+        const uint64_t nt = ctx->pinned_totals[3];
+        if (nt > task_cap) {
+            (void)ctx->ring.seal(s);
+            return bail(ctx->fail(MVGS_EHIP, "selection tasks %llu exceed their bound", (unsigned long long)nt));
+        }
+        f->n_tasks = (uint32_t)nt;
+    }
+    if ((uint32_t)ctx->pinned_totals[2] != 0) {
         // a sort of an earlier call on this context timed out in its look-back (never expected)
         fill_u32(reinterpret_cast<uint32_t*>(as<uint64_t>(ctx->totals) + 2), 2, 0u, s);
         (void)ctx->ring.seal(s);
         return bail(ctx->fail(MVGS_EHIP, "radix sort look-back timed out in an earlier call on this context"));
     }
     if (V64 >= (1ull << 32) || K64 >= (1ull << 32)) {
+        // (unreachable for the selection checks above: they ran first)
         (void)ctx->ring.seal(s);
         return bail(ctx->fail(MVGS_ECAPACITY, "records %llu or pairs %llu reach 2^32", (unsigned long long)V64,
                               (unsigned long long)K64));
@@ -518,6 +602,8 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
 
     // records and the depth sort
     const size_t V1 = std::max<uint32_t>(V, 1), K1 = std::max<uint32_t>(K, 1);
+    // per-pixel blend state: every pixel, or every selected pixel in thread-efficient mode
+    const size_t n_px_state = (sel && sel->mode == MVGS_PARTIAL_COMPACT) ? sel->n_sel : n_pixels;
     const Need need2[] = {{&f->recs, sizeof(BlendRec) * V1},
                           {&f->rec_view, sizeof(uint16_t) * V1},
                           {&ctx->depth_key[0], sizeof(uint32_t) * V1},
@@ -532,8 +618,8 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
                           {&f->vals[0], sizeof(uint32_t) * K1},
                           {&f->vals[1], sizeof(uint32_t) * K1},
                           {&f->ranges, sizeof(uint2) * std::max<uint32_t>(n_tiles, 1)},
-                          {&f->t_final, sizeof(float) * n_pixels},
-                          {&f->n_last, sizeof(uint32_t) * n_pixels},
+                          {&f->t_final, sizeof(float) * std::max<size_t>(n_px_state, 1)},
+                          {&f->n_last, sizeof(uint32_t) * std::max<size_t>(n_px_state, 1)},
                           {&ctx->sort_scratch,
                            std::max(radix_scratch_bytes(std::max<size_t>(V, K)), scan_scratch_bytes(V))}};
     const int n_need2 = (int)(sizeof(need2) / sizeof(need2[0]));
@@ -542,7 +628,7 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
         (void)ctx->ring.seal(s);
         return bail(st);
     }
-    f->need_bytes = need_sum(need1, 6) + need_sum(need2, n_need2);
+    f->need_bytes = need_sum(need1, n_need1) + need_sum(need2, n_need2);
 
     mk = ctx->stage_begin(1, s);
     launch_records(ga, dcam, B, tw, th, as<uint32_t>(f->rec_off), as<BlendRec>(f->recs),
@@ -584,14 +670,64 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     a.images = (float* const*)img_ptrs;
     a.t_final = as<float>(f->t_final);
     a.n_last = as<uint32_t>(f->n_last);
+    a.mask = f->mode == MVGS_PARTIAL_MASKED ? as<uint32_t>(f->mask) : nullptr;
     mk = ctx->stage_begin(6, s);
-    launch_blend_fwd(a, tw, th, ctx->ppl, s);
+    if (f->mode == MVGS_PARTIAL_COMPACT) {
+        SelBlendArgs sa = sel_args(f);
+        sa.images = a.images;
+        launch_blend_fwd_sel(sa, s);
+    } else {
+        launch_blend_fwd(a, tw, th, ctx->ppl, s);
+    }
     ctx->stage_end(mk, s);
     FCHK(hipGetLastError());
     FCHK(ctx->ring.seal(s));
     *frame = f;
     return MVGS_OK;
 #undef FCHK
+}
+
+}  // namespace
+
+extern "C" {
+
+int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_camera* cams, int32_t B,
+                 float* const* images, mvgs_frame** frame) {
+    return forward_impl(ctx, stream, g, cams, B, images, frame, nullptr);
+}
+
+int mvgs_forward_partial(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_camera* cams,
+                         int32_t B, const uint32_t* sel_offsets, const uint32_t* sel_pixels, int64_t n_sel,
+                         int32_t mode, float* const* images, mvgs_frame** frame) {
+    if (!ctx) return MVGS_EINVAL;
+    if (mode != MVGS_PARTIAL_COMPACT && mode != MVGS_PARTIAL_MASKED)
+        return ctx->fail(MVGS_EINVAL, "mode %d is not MVGS_PARTIAL_COMPACT or MVGS_PARTIAL_MASKED", mode);
+    if (n_sel < 0 || n_sel >= (1ll << 32)) return ctx->fail(MVGS_EINVAL, "n_sel=%lld outside [0, 2^32)", (long long)n_sel);
+    if (!sel_offsets || (n_sel > 0 && !sel_pixels)) return ctx->fail(MVGS_EINVAL, "selection array is NULL");
+    const SelIn sel{sel_offsets, sel_pixels, (uint32_t)n_sel, mode};
+    return forward_impl(ctx, stream, g, cams, B, images, frame, &sel);
+}
+
+int mvgs_subsample(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t B, const uint32_t* keys,
+                   uint32_t* sel_offsets, uint32_t* sel_pixels) {
+    if (!ctx) return MVGS_EINVAL;
+    uint32_t n_tiles = 0, n_pixels = 0;
+    int st = validate_cams(ctx, cams, B, ctx->tw, ctx->th, &n_tiles, &n_pixels);
+    if (st) return st;
+    for (int v = 1; v < B; ++v)
+        if (cams[v].width != cams[0].width || cams[v].height != cams[0].height)
+            return ctx->fail(MVGS_EINVAL, "view %d is %dx%d, view 0 is %dx%d: sub-sampling needs one size", v,
+                             cams[v].width, cams[v].height, cams[0].width, cams[0].height);
+    if (!keys || !sel_offsets || !sel_pixels) return ctx->fail(MVGS_EINVAL, "a sub-sampling buffer is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(ctx, ctx->bind_device());
+    const Need need[] = {{&ctx->scan_scratch, scan_scratch_bytes(n_tiles)}};
+    st = grow_all(ctx, need, 1);
+    if (st) return st;
+    launch_subsample(keys, cams[0].width, cams[0].height, B, ctx->tw, ctx->th, sel_offsets, sel_pixels,
+                     ctx->scan_scratch.p, s);
+    LAUNCHCHK(ctx, "sub-sampling kernels");
+    return MVGS_OK;
 }
 
 int mvgs_loss(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t B, const float* const* images,
@@ -670,8 +806,17 @@ int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, cons
     a.n_last = as<uint32_t>(f->n_last);
     a.acc = as<float>(ctx->acc);
     a.want_e1 = densify != nullptr;
+    a.mask = f->mode == MVGS_PARTIAL_MASKED ? as<uint32_t>(f->mask) : nullptr;
     int mk = ctx->stage_begin(8, s);
-    launch_blend_bwd(a, ctx->tw, ctx->th, ctx->ppl, s);
+    if (f->mode == MVGS_PARTIAL_COMPACT) {
+        SelBlendArgs sa = sel_args(f);
+        sa.dl_dimg = a.dl_dimg;
+        sa.acc = a.acc;
+        sa.want_e1 = a.want_e1;
+        launch_blend_bwd_sel(sa, s);
+    } else {
+        launch_blend_bwd(a, ctx->tw, ctx->th, ctx->ppl, s);
+    }
     ctx->stage_end(mk, s);
     GradArgs gr;
     gr.means = grads->means;
@@ -741,8 +886,18 @@ int mvgs_export_transmittance(mvgs_context* ctx, void* stream, const mvgs_frame*
     if (!ctx || !frame || frame->ctx != ctx || !frame->in_use || !t_final) return MVGS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     mvgs_frame* f = const_cast<mvgs_frame*>(frame);
-    for (int v = 0; v < f->B; ++v) {
+    for (int v = 0; v < f->B; ++v)
         if (!t_final[v]) return ctx->fail(MVGS_EINVAL, "t_final[%d] is NULL", v);
+    if (f->mode == MVGS_PARTIAL_COMPACT) {
+        void* dptrs = nullptr;
+        HIPCHK(ctx, ctx->ring.put(t_final, sizeof(float*) * f->B, s, &dptrs));
+        launch_sel_scatter_t(as<DevCam>(f->cams), f->B, f->n_tiles, as<uint32_t>(f->sel_off),
+                             as<uint32_t>(f->sel_pix), as<float>(f->t_final), (float* const*)dptrs, s);
+        LAUNCHCHK(ctx, "transmittance scatter");
+        HIPCHK(ctx, ctx->ring.seal(s));
+        return MVGS_OK;
+    }
+    for (int v = 0; v < f->B; ++v) {
         const DevCam& c = f->hcams[v];
         HIPCHK(ctx, hipMemcpyAsync(t_final[v], as<float>(f->t_final) + c.pix_base, sizeof(float) * c.W * c.H,
                                    hipMemcpyDeviceToDevice, s));
@@ -795,9 +950,14 @@ int mvgs_profile_reset(mvgs_context* ctx) {
 int mvgs_frame_work(mvgs_context* ctx, void* stream, const mvgs_frame* frame, uint64_t* work_dev) {
     if (!ctx || !frame || frame->ctx != ctx || !frame->in_use || !work_dev) return MVGS_EINVAL;
     mvgs_frame* f = const_cast<mvgs_frame*>(frame);
-    launch_frame_work(as<DevCam>(f->cams), f->B, as<uint2>(f->ranges), as<uint32_t>(f->vals[f->final_buf]),
-                      as<BlendRec>(f->recs), as<uint32_t>(f->n_last), f->n_pixels, ctx->tw, ctx->th, work_dev,
-                      (hipStream_t)stream);
+    if (f->mode == MVGS_PARTIAL_COMPACT)
+        launch_frame_work_sel(as<DevCam>(f->cams), f->B, f->n_tiles, as<uint2>(f->ranges),
+                              as<uint32_t>(f->vals[f->final_buf]), as<BlendRec>(f->recs), as<uint32_t>(f->sel_off),
+                              as<uint32_t>(f->sel_pix), as<uint32_t>(f->n_last), work_dev, (hipStream_t)stream);
+    else
+        launch_frame_work(as<DevCam>(f->cams), f->B, as<uint2>(f->ranges), as<uint32_t>(f->vals[f->final_buf]),
+                          as<BlendRec>(f->recs), as<uint32_t>(f->n_last), f->n_pixels, ctx->tw, ctx->th, work_dev,
+                          (hipStream_t)stream);
     LAUNCHCHK(ctx, "frame work");
     return MVGS_OK;
 }

@@ -9,144 +9,9 @@
 // no block barrier: each wavefront walks its tile's sorted list on its own, skips Gaussians whose
 // pixel box misses its sub-tile (a scalar test), and leaves as soon as all of its pixels have
 // stopped. Workgroups are mapped so that each XCD receives a contiguous run of tiles.
-#include "mvgs_kernels.h"
+#include "blend_device.h"
 
 namespace mvgs {
-
-constexpr float kLog2e = 1.4426950408889634f;
-
-// Contiguous tile runs per XCD: block b is dispatched to XCD b % 8.
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
-    const uint32_t x = b & 7u, k = b >> 3;
-    const uint32_t q = n >> 3, rem = n & 7u;
-    return x * q + (x < rem ? x : rem) + k;
-}
-
-__device__ __forceinline__ int find_view(const DevCam* __restrict__ cams, int B, uint32_t tile) {
-    int lo = 0, hi = B;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (cams[mid].tile_base <= tile) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ bool box_misses(uint32_t bx, uint32_t by, int sx0, int sx1, int sy0, int sy1) {
-    return (int)(bx & 0xffffu) > sx1 || (int)(bx >> 16) < sx0 || (int)(by & 0xffffu) > sy1 || (int)(by >> 16) < sy0;
-}
-
-__device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
-
-// Wavefront-uniform copy of the fields the walks use.
-struct RecS {
-    float mx, my, hca, nb, hcc, o, cut, hi, r, g, b;
-};
-
-__device__ __forceinline__ RecS load_rec(const BlendRec* __restrict__ recs, uint32_t r) {
-    const BlendRec* R = recs + r;
-    RecS s;
-    s.mx = R->mx; s.my = R->my; s.hca = R->hca; s.nb = R->nb; s.hcc = R->hcc; s.o = R->o;
-    s.cut = R->cut; s.hi = R->hi; s.r = R->r; s.g = R->g; s.b = R->b;
-    return s;
-}
-
-__device__ __forceinline__ uint32_t readlane_u32(uint32_t v, int lane) {
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
-}
-
-// Largest power -0.5 d^T conic d over the rectangle [xa, xb] x [ya, yb] of pixel centres (d = p - mean),
-// with power(d) = dx (hca dx + nb dy) + hcc dy^2, concave: 0 if the mean is inside, else the best of
-// the four edges, each maximised in closed form and clamped to the edge. Also returns the size of
-// the terms at that point, which bounds its rounding error.
-__device__ __forceinline__ float rect_max_power(float mx, float my, float hca, float nb, float hcc, float xa,
-                                               float xb, float ya, float yb, float& mag) {
-    const float ax = xa - mx, bx = xb - mx, ay = ya - my, by = yb - my;
-    if (ax <= 0.0f && bx >= 0.0f && ay <= 0.0f && by >= 0.0f) {
-        mag = 0.0f;
-        return 0.0f;
-    }
-    float best = -__builtin_inff();
-    mag = 0.0f;
-    // edges x = const: maximise over dy at dy* = -nb dx / (2 hcc)
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const float dx = e ? bx : ax;
-        float dy = -nb * dx / (2.0f * hcc);
-        dy = fminf(fmaxf(dy, ay), by);
-        const float t1 = hca * dx * dx, t2 = nb * dx * dy, t3 = hcc * dy * dy;
-        const float p = t1 + t2 + t3;
-        if (p > best) {
-            best = p;
-            mag = fabsf(t1) + fabsf(t2) + fabsf(t3);
-        }
-    }
-    // edges y = const: maximise over dx at dx* = -nb dy / (2 hca)
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const float dy = e ? by : ay;
-        float dx = -nb * dy / (2.0f * hca);
-        dx = fminf(fmaxf(dx, ax), bx);
-        const float t1 = hca * dx * dx, t2 = nb * dx * dy, t3 = hcc * dy * dy;
-        const float p = t1 + t2 + t3;
-        if (p > best) {
-            best = p;
-            mag = fabsf(t1) + fabsf(t2) + fabsf(t3);
-        }
-    }
-    return best;
-}
-
-// Candidate window: lane k looks at list entry base + k and keeps it if the Gaussian's cut ellipse
-// reaches a pixel centre of the wavefront's sub-tile: first the pixel box, then the ellipse itself.
-// The ellipse test only ever keeps too much (a slack far above float32 rounding), so culling never
-// changes a result; it only spares the wavefront Gaussians that no pixel of its sub-tile accepts.
-__device__ __forceinline__ uint64_t window_mask(const uint32_t* __restrict__ vals, const BlendRec* __restrict__ recs,
-                                                uint32_t base, uint32_t end, int lane, int sx0, int sx1, int sy0,
-                                                int sy1, uint32_t& rl) {
-    const uint32_t idx = base + (uint32_t)lane;
-    bool keep = false;
-    rl = 0;
-    if (idx < end) {
-        rl = vals[idx];
-        const float4 q0 = *reinterpret_cast<const float4*>(recs + rl);
-        keep = !box_misses(__float_as_uint(q0.x), __float_as_uint(q0.y), sx0, sx1, sy0, sy1);
-        if (keep) {
-            const float4 q1 = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(recs + rl) + 4);
-            const float cut = reinterpret_cast<const float*>(recs + rl)[8];
-            float mag;
-            const float pm = rect_max_power(q0.z, q0.w, q1.x, q1.y, q1.z, (float)sx0 + 0.5f, (float)sx1 + 0.5f,
-                                            (float)sy0 + 0.5f, (float)sy1 + 0.5f, mag);
-            keep = pm >= cut - (1e-2f + 1e-5f * mag);
-        }
-    }
-    return ballot64(keep);
-}
-
-struct FwdPix {
-    float T, C0, C1, C2;
-    uint32_t last;
-    bool done;
-};
-
-__device__ __forceinline__ void blend_step(FwdPix& st, const RecS& q, float px, float py, uint32_t pos) {
-    if (st.done) return;
-    const float power = pixel_power(px, py, q.mx, q.my, q.hca, q.nb, q.hcc);
-    if (power >= q.cut) {
-        const float alpha = (power > q.hi) ? kAlphaMax : q.o * fast_exp(power);
-        const float Tn = __builtin_fmaf(-st.T, alpha, st.T);
-        if (Tn < kTStop) {
-            st.done = true;
-        } else {
-            const float w = alpha * st.T;
-            st.C0 = __builtin_fmaf(q.r, w, st.C0);
-            st.C1 = __builtin_fmaf(q.g, w, st.C1);
-            st.C2 = __builtin_fmaf(q.b, w, st.C2);
-            st.T = Tn;
-            st.last = pos + 1;
-        }
-    }
-}
 
 // Geometry of one wavefront: an SW x SH sub-tile of the (view, tile) of this workgroup with
 // SW * SH = 64 PPL (8x8, 8x16 or 16x16); lane l owns the PPL pixels
@@ -187,6 +52,15 @@ __device__ __forceinline__ WaveTile wave_tile(const DevCam* __restrict__ cams, i
     return w;
 }
 
+// Whether pixel (x, y) of view c is rendered: inside the image and, when a selection mask (one bit
+// per pixel of the batch, at pix_base + y W + x) is given, selected.
+__device__ __forceinline__ bool pixel_selected(const DevCam& c, int x, int y, const uint32_t* __restrict__ mask) {
+    if (!(x < c.W && y < c.H)) return false;
+    if (!mask) return true;
+    const uint32_t gp = c.pix_base + (uint32_t)y * (uint32_t)c.W + (uint32_t)x;
+    return (mask[gp >> 5] >> (gp & 31u)) & 1u;
+}
+
 template <int TW, int TH, int PPL>
 __global__ void __launch_bounds__(TW * TH / PPL) k_blend_fwd(const DevCam* __restrict__ cams, int B,
                                                              uint32_t n_tiles, const uint2* __restrict__ ranges,
@@ -194,7 +68,8 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_fwd(const DevCam* __res
                                                              const BlendRec* __restrict__ recs,
                                                              float* const* __restrict__ images,
                                                              float* __restrict__ t_final,
-                                                             uint32_t* __restrict__ n_last) {
+                                                             uint32_t* __restrict__ n_last,
+                                                             const uint32_t* __restrict__ mask) {
     const WaveTile wt = wave_tile<TW, TH, PPL>(cams, B, n_tiles, ranges);
     if (wt.empty) return;
     using ST = SubTile<PPL>;
@@ -204,52 +79,15 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_fwd(const DevCam* __res
     const float px = (float)x + 0.5f;
     float py[PPL];
     FwdPix st[PPL];
+    bool sel[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int y = wt.sy0 + (lane / ST::SW) + ST::ROWS * k;
         py[k] = (float)y + 0.5f;
-        st[k] = FwdPix{1.0f, 0.0f, 0.0f, 0.0f, 0u, !(x < c.W && y < c.H)};
+        sel[k] = pixel_selected(c, x, y, mask);
+        st[k] = FwdPix{1.0f, 0.0f, 0.0f, 0.0f, 0u, !sel[k]};
     }
-    for (uint32_t base = wt.rg.x; base < wt.rg.y; base += 64) {
-        bool live = false;
-#pragma unroll
-        for (int k = 0; k < PPL; ++k) live |= !st[k].done;
-        if (ballot64(live) == 0) break;
-        uint32_t rl;
-        uint64_t m = window_mask(vals, recs, base, wt.rg.y, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1, rl);
-        while (m) {
-            // up to four records per round trip through the scalar cache
-            const int j0 = __builtin_ctzll(m);
-            m &= m - 1;
-            const int j1 = m ? __builtin_ctzll(m) : j0;
-            if (m) m &= m - 1;
-            const bool h1 = j1 != j0;
-            const int j2 = m ? __builtin_ctzll(m) : j0;
-            if (m) m &= m - 1;
-            const bool h2 = j2 != j0;
-            const int j3 = m ? __builtin_ctzll(m) : j0;
-            if (m) m &= m - 1;
-            const bool h3 = j3 != j0;
-            const RecS q0 = load_rec(recs, readlane_u32(rl, j0));
-            const RecS q1 = load_rec(recs, readlane_u32(rl, j1));
-            const RecS q2 = load_rec(recs, readlane_u32(rl, j2));
-            const RecS q3 = load_rec(recs, readlane_u32(rl, j3));
-#pragma unroll
-            for (int k = 0; k < PPL; ++k) blend_step(st[k], q0, px, py[k], base + (uint32_t)j0);
-            if (h1) {
-#pragma unroll
-                for (int k = 0; k < PPL; ++k) blend_step(st[k], q1, px, py[k], base + (uint32_t)j1);
-            }
-            if (h2) {
-#pragma unroll
-                for (int k = 0; k < PPL; ++k) blend_step(st[k], q2, px, py[k], base + (uint32_t)j2);
-            }
-            if (h3) {
-#pragma unroll
-                for (int k = 0; k < PPL; ++k) blend_step(st[k], q3, px, py[k], base + (uint32_t)j3);
-            }
-        }
-    }
+    walk_forward<PPL>(st, px, py, wt.rg, vals, recs, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1);
     const size_t hw = (size_t)c.W * c.H;
     float* img = images[wt.v];
 #pragma unroll
@@ -257,140 +95,15 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_fwd(const DevCam* __res
         const int y = wt.sy0 + (lane / ST::SW) + ST::ROWS * k;
         if (x < c.W && y < c.H) {
             const size_t pix = (size_t)y * c.W + x;
-            img[pix] = __builtin_fmaf(st[k].T, c.bg[0], st[k].C0);
-            img[hw + pix] = __builtin_fmaf(st[k].T, c.bg[1], st[k].C1);
-            img[2 * hw + pix] = __builtin_fmaf(st[k].T, c.bg[2], st[k].C2);
+            if (sel[k]) {
+                img[pix] = __builtin_fmaf(st[k].T, c.bg[0], st[k].C0);
+                img[hw + pix] = __builtin_fmaf(st[k].T, c.bg[1], st[k].C1);
+                img[2 * hw + pix] = __builtin_fmaf(st[k].T, c.bg[2], st[k].C2);
+            }
             t_final[c.pix_base + pix] = st[k].T;
             n_last[c.pix_base + pix] = st[k].last;
         }
     }
-}
-
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint32_t o = (uint32_t)__shfl_xor((int)v, off, 64);
-        v = v > o ? v : o;
-    }
-    return v;
-}
-
-struct BwdPix {
-    float T, dC0, dC1, dC2, Rb0, Rb1, Rb2;
-    float py;
-    uint32_t last;
-};
-
-// Per-lane sums of one Gaussian's gradient contributions over the lane's pixels.
-struct BwdSum {
-    float mx, my, ca, cb, cc, o, r, g, b, e1;
-    bool contrib;
-};
-
-template <bool E1>
-__device__ __forceinline__ void unblend_pixel(BwdPix& st, BwdSum& a, const RecS& q, uint32_t pos, float px,
-                                              float half_w, float half_h) {
-    if (pos >= st.last) return;
-    const float dx = px - q.mx, dy = st.py - q.my;
-    const float power = pixel_power(px, st.py, q.mx, q.my, q.hca, q.nb, q.hcc);
-    if (!(power >= q.cut)) return;
-    a.contrib = true;
-    const bool clamped = power > q.hi;
-    const float G = fast_exp(power);
-    const float alpha = clamped ? kAlphaMax : q.o * G;
-    st.T = st.T * __builtin_amdgcn_rcpf(1.0f - alpha);   // transmittance in front of this Gaussian
-    const float w = alpha * st.T;
-    a.r = __builtin_fmaf(st.dC0, w, a.r);
-    a.g = __builtin_fmaf(st.dC1, w, a.g);
-    a.b = __builtin_fmaf(st.dC2, w, a.b);
-    const float dalpha = st.T * (st.dC0 * (q.r - st.Rb0) + st.dC1 * (q.g - st.Rb1) + st.dC2 * (q.b - st.Rb2));
-    st.Rb0 = __builtin_fmaf(q.r - st.Rb0, alpha, st.Rb0);
-    st.Rb1 = __builtin_fmaf(q.g - st.Rb1, alpha, st.Rb1);
-    st.Rb2 = __builtin_fmaf(q.b - st.Rb2, alpha, st.Rb2);
-    if (clamped) return;
-    a.o = __builtin_fmaf(dalpha, G, a.o);
-    const float dpow = dalpha * alpha;
-    const float ca = -2.0f * q.hca, cbq = -q.nb, cc = -2.0f * q.hcc;
-    const float gx = dpow * (ca * dx + cbq * dy);
-    const float gy = dpow * (cbq * dx + cc * dy);
-    a.mx += gx;
-    a.my += gy;
-    a.ca = __builtin_fmaf(-0.5f * dpow, dx * dx, a.ca);
-    a.cb = __builtin_fmaf(-dpow, dx * dy, a.cb);
-    a.cc = __builtin_fmaf(-0.5f * dpow, dy * dy, a.cc);
-    if (E1) {
-        const float nx = gx * half_w, ny = gy * half_h;
-        a.e1 += sqrtf(nx * nx + ny * ny);
-    }
-}
-
-template <int CTRL, int ROW_MASK, int BANK_MASK>
-__device__ __forceinline__ float dpp_mov(float old, float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v),
-                                                                 CTRL, ROW_MASK, BANK_MASK, false));
-}
-
-// One halving step of the transposed reduction: of the pair (a, b) a lane keeps a if `hi` is false
-// and b otherwise, and adds the same member from its partner across the exchange `xchg`.
-template <typename X>
-__device__ __forceinline__ float keep_add(float a, float b, bool hi, X xchg) {
-    const float send = hi ? a : b;
-    const float keep = hi ? b : a;
-    return keep + xchg(send);
-}
-
-// Sum of ten per-lane values over the wavefront in one pass of halving exchanges (xor 32, 16, 8,
-// 4 move half of the values each, xor 2 and 1 finish): afterwards the first lane of quad q holds
-// the total of value kQuadValue[q]. Returns that total; *idx receives the value index (or -1).
-__device__ __forceinline__ float wave_sum10(const float (&v)[10], int lane, uint32_t bperm32, int* idx) {
-    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
-    auto x32 = [&](float t) { return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute((int)bperm32,
-                                                                                            __builtin_bit_cast(int, t))); };
-    // swizzle bit mode: and_mask 0x1f, xor_mask 0x10 -> lane ^ 16 within each half
-    auto x16 = [&](float t) { return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, t),
-                                                                                           0x401f)); };
-    auto x8 = [&](float t) { return dpp_mov<0x128, 0xf, 0xf>(0.0f, t); };  // row_ror:8 -> lane ^ 8 in a row
-    auto x4 = [&](float t) {
-        const float up = dpp_mov<0x104, 0xf, 0x5>(0.0f, t);   // row_shl:4 into banks 0, 2 (lane + 4)
-        return dpp_mov<0x114, 0xf, 0xa>(up, t);              // row_shr:4 into banks 1, 3 (lane - 4)
-    };
-    const float r0 = keep_add(v[0], v[1], b5, x32);
-    const float r1 = keep_add(v[2], v[3], b5, x32);
-    const float r2 = keep_add(v[4], v[5], b5, x32);
-    const float r3 = keep_add(v[6], v[7], b5, x32);
-    const float r4 = keep_add(v[8], v[9], b5, x32);
-    const float s0 = keep_add(r0, r1, b4, x16);
-    const float s1 = keep_add(r2, r3, b4, x16);
-    const float s2 = keep_add(r4, 0.0f, b4, x16);
-    const float u0 = keep_add(s0, s1, b3, x8);
-    const float u1 = keep_add(s2, 0.0f, b3, x8);
-    float x = keep_add(u0, u1, b2, x4);
-    x += dpp_mov<0x4e, 0xf, 0xf>(0.0f, x);   // quad_perm [2,3,0,1]
-    x += dpp_mov<0xb1, 0xf, 0xf>(0.0f, x);   // quad_perm [1,0,3,2]
-    // value held by lane groups: bit2 = 0 -> u0 (bit3 picks s0/s1), bit2 = 1 -> u1 (s2 if bit3 = 0)
-    int k = -1;
-    if ((lane & 3) == 0) {
-        if (!b2) k = (b3 ? 4 : 0) + (b5 ? 1 : 0) + (b4 ? 2 : 0);
-        else if (!b3 && !b4) k = 8 + (b5 ? 1 : 0);
-    }
-    *idx = k;
-    return x;
-}
-
-// One Gaussian of the reverse walk for all of this lane's pixels, summed over the wavefront and
-// added to the record's accumulators with one atomic instruction.
-template <bool E1, int PPL>
-__device__ __forceinline__ void unblend_step(BwdPix (&st)[PPL], const RecS& q, uint32_t r, uint32_t pos, float px,
-                                             float half_w, float half_h, int lane, uint32_t bperm32,
-                                             float* __restrict__ acc) {
-    BwdSum a{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false};
-#pragma unroll
-    for (int k = 0; k < PPL; ++k) unblend_pixel<E1>(st[k], a, q, pos, px, half_w, half_h);
-    if (ballot64(a.contrib) == 0) return;
-    const float v[10] = {a.mx, a.my, a.ca, a.cb, a.cc, a.o, a.r, a.g, a.b, E1 ? a.e1 : 0.0f};
-    int k;
-    const float total = wave_sum10(v, lane, bperm32, &k);
-    if (k >= 0 && (E1 || k < 9)) unsafeAtomicAdd(acc + (size_t)r * kAccStride + k, total);
 }
 
 template <int TW, int TH, int PPL, bool E1>
@@ -401,7 +114,8 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_bwd(const DevCam* __res
                                                              const float* const* __restrict__ dl_dimg,
                                                              const float* __restrict__ t_final,
                                                              const uint32_t* __restrict__ n_last,
-                                                             float* __restrict__ acc) {
+                                                             float* __restrict__ acc,
+                                                             const uint32_t* __restrict__ mask) {
     const WaveTile wt = wave_tile<TW, TH, PPL>(cams, B, n_tiles, ranges);
     if (wt.empty) return;
     using ST = SubTile<PPL>;
@@ -418,7 +132,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_bwd(const DevCam* __res
     for (int k = 0; k < PPL; ++k) {
         const int y = wt.sy0 + (lane / ST::SW) + ST::ROWS * k;
         st[k] = BwdPix{1.0f, 0.0f, 0.0f, 0.0f, c.bg[0], c.bg[1], c.bg[2], (float)y + 0.5f, 0u};
-        if (x < c.W && y < c.H) {
+        if (pixel_selected(c, x, y, mask)) {
             const size_t pix = (size_t)y * c.W + x;
             st[k].dC0 = g[pix];
             st[k].dC1 = g[hw + pix];
@@ -429,38 +143,8 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_bwd(const DevCam* __res
         }
     }
     const uint32_t hi_end = __builtin_amdgcn_readfirstlane(wave_max_u32(lane_last));
-    const uint32_t bperm32 = (uint32_t)((lane ^ 32) << 2);
-
-    for (uint32_t top = hi_end; top > wt.rg.x;) {
-        const uint32_t base = top - wt.rg.x > 64u ? top - 64u : wt.rg.x;
-        uint32_t rl;
-        uint64_t m = window_mask(vals, recs, base, top, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1, rl);
-        top = base;
-        while (m) {
-            // highest list position first; up to four records per round trip
-            const int j0 = 63 - __builtin_clzll(m);
-            m &= ~(1ull << j0);
-            const int j1 = m ? 63 - __builtin_clzll(m) : j0;
-            if (m) m &= ~(1ull << j1);
-            const bool h1 = j1 != j0;
-            const int j2 = m ? 63 - __builtin_clzll(m) : j0;
-            if (m) m &= ~(1ull << j2);
-            const bool h2 = j2 != j0;
-            const int j3 = m ? 63 - __builtin_clzll(m) : j0;
-            if (m) m &= ~(1ull << j3);
-            const bool h3 = j3 != j0;
-            const uint32_t r0 = readlane_u32(rl, j0), r1 = readlane_u32(rl, j1);
-            const uint32_t r2 = readlane_u32(rl, j2), r3 = readlane_u32(rl, j3);
-            const RecS q0 = load_rec(recs, r0);
-            const RecS q1 = load_rec(recs, r1);
-            const RecS q2 = load_rec(recs, r2);
-            const RecS q3 = load_rec(recs, r3);
-            unblend_step<E1, PPL>(st, q0, r0, base + (uint32_t)j0, px, half_w, half_h, lane, bperm32, acc);
-            if (h1) unblend_step<E1, PPL>(st, q1, r1, base + (uint32_t)j1, px, half_w, half_h, lane, bperm32, acc);
-            if (h2) unblend_step<E1, PPL>(st, q2, r2, base + (uint32_t)j2, px, half_w, half_h, lane, bperm32, acc);
-            if (h3) unblend_step<E1, PPL>(st, q3, r3, base + (uint32_t)j3, px, half_w, half_h, lane, bperm32, acc);
-        }
-    }
+    walk_backward<E1, PPL>(st, px, hi_end, wt.rg, vals, recs, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1, half_w, half_h,
+                           acc);
 }
 
 // Work of a frame's walks, one thread per pixel: out[0] += list entries from the start of the pixel's
@@ -543,17 +227,17 @@ int blend_default_ppl(int tw, int th) {
 template <int W_, int H_, int P_>
 static void launch_fwd_t(const BlendFwdArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_blend_fwd<W_, H_, P_>), dim3(a.n_tiles), dim3(W_ * H_ / P_), 0, s, a.cams, a.B, a.n_tiles,
-                       a.ranges, a.vals, a.recs, a.images, a.t_final, a.n_last);
+                       a.ranges, a.vals, a.recs, a.images, a.t_final, a.n_last, a.mask);
 }
 
 template <int W_, int H_, int P_>
 static void launch_bwd_t(const BlendBwdArgs& a, hipStream_t s) {
     if (a.want_e1)
         hipLaunchKernelGGL((k_blend_bwd<W_, H_, P_, true>), dim3(a.n_tiles), dim3(W_ * H_ / P_), 0, s, a.cams, a.B,
-                           a.n_tiles, a.ranges, a.vals, a.recs, a.dl_dimg, a.t_final, a.n_last, a.acc);
+                           a.n_tiles, a.ranges, a.vals, a.recs, a.dl_dimg, a.t_final, a.n_last, a.acc, a.mask);
     else
         hipLaunchKernelGGL((k_blend_bwd<W_, H_, P_, false>), dim3(a.n_tiles), dim3(W_ * H_ / P_), 0, s, a.cams, a.B,
-                           a.n_tiles, a.ranges, a.vals, a.recs, a.dl_dimg, a.t_final, a.n_last, a.acc);
+                           a.n_tiles, a.ranges, a.vals, a.recs, a.dl_dimg, a.t_final, a.n_last, a.acc, a.mask);
 }
 
 // every supported (tile_w, tile_h, pixels per lane)

@@ -82,6 +82,7 @@ struct BlendFwdArgs {
     float* const* images;   // device array of B device pointers
     float* t_final;         // [total pixels]
     uint32_t* n_last;       // [total pixels]
+    const uint32_t* mask;   // null, or one bit per pixel of the batch: render only the set ones
 };
 struct BlendBwdArgs {
     const DevCam* cams;
@@ -95,6 +96,7 @@ struct BlendBwdArgs {
     const uint32_t* n_last;
     float* acc;             // [V][kAccStride]
     int want_e1;
+    const uint32_t* mask;   // as in BlendFwdArgs
 };
 bool blend_supported(int tw, int th, int ppl);
 int blend_default_ppl(int tw, int th);
@@ -102,6 +104,40 @@ void launch_frame_work(const DevCam* cams, int B, const uint2* ranges, const uin
                        const uint32_t* n_last, uint32_t n_pixels, int tw, int th, uint64_t* out, hipStream_t s);
 void launch_blend_fwd(const BlendFwdArgs& a, int tw, int th, int ppl, hipStream_t s);
 void launch_blend_bwd(const BlendBwdArgs& a, int tw, int th, int ppl, hipStream_t s);
+
+// k_partial.hip: partial rendering over a pixel selection (see the file comment)
+constexpr uint32_t kSelBadOffsets = 1, kSelOutside = 2, kSelDuplicate = 4, kSelTooLong = 8;
+struct SelBlendArgs {
+    const DevCam* cams;
+    int B;
+    const uint2* ranges;
+    const uint32_t* vals;
+    const BlendRec* recs;
+    const uint32_t* sel_off;    // [n_tiles + 1]
+    const uint32_t* sel_pix;    // [n_sel]
+    const uint2* tasks;         // (segment, chunk of 64) per wavefront
+    uint32_t n_tasks;
+    float* const* images;       // forward: device array of B device pointers
+    float* t_sel;               // [n_sel]
+    uint32_t* last_sel;         // [n_sel]
+    const float* const* dl_dimg;  // backward
+    float* acc;
+    int want_e1;
+};
+void launch_sel_check(const DevCam* cams, int B, uint32_t n_tiles, int tw, int th, const uint32_t* sel_off,
+                      const uint32_t* sel_pix, uint32_t n_sel, uint32_t* mask, uint32_t* n_tasks, uint32_t* err,
+                      hipStream_t s);
+void launch_sel_tasks(uint32_t n_tiles, const uint32_t* n_tasks, const uint32_t* task_off, uint32_t cap,
+                      uint2* tasks, hipStream_t s);
+void launch_blend_fwd_sel(const SelBlendArgs& a, hipStream_t s);
+void launch_blend_bwd_sel(const SelBlendArgs& a, hipStream_t s);
+void launch_subsample(const uint32_t* keys, int W, int H, int B, int tw, int th, uint32_t* sel_off,
+                      uint32_t* sel_pix, void* scan_scratch, hipStream_t s);
+void launch_sel_scatter_t(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off,
+                          const uint32_t* sel_pix, const float* t_sel, float* const* out, hipStream_t s);
+void launch_frame_work_sel(const DevCam* cams, int B, uint32_t n_tiles, const uint2* ranges, const uint32_t* vals,
+                           const BlendRec* recs, const uint32_t* sel_off, const uint32_t* sel_pix,
+                           const uint32_t* last_sel, uint64_t* out, hipStream_t s);
 
 // k_loss.hip
 struct LossView {

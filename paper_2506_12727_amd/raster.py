@@ -130,6 +130,35 @@ class Rasterizer:
         L.check(st, self.ctx)
         return images, Frame(self, fr, cams)
 
+    def subsample(self, cams, keys: torch.Tensor):
+        """Alg. 3's index array for views of one size from one random uint32 key per pixel position
+        (int32 tensor [H*W] on the GPU holding the key bits): (sel_offsets, sel_pixels) int32 tensors."""
+        W, H = int(cams[0].width), int(cams[0].height)
+        tiles = ((W + self.tile[0] - 1) // self.tile[0]) * ((H + self.tile[1] - 1) // self.tile[1])
+        off = torch.empty(len(cams) * tiles + 1, dtype=torch.int32, device=keys.device)
+        pix = torch.empty(W * H, dtype=torch.int32, device=keys.device)
+        keys = keys.contiguous()
+        L.check(self.lib.mvgs_subsample(self.ctx, _stream(), L.camera_array(cams), len(cams), keys.data_ptr(),
+                                        off.data_ptr(), pix.data_ptr()), self.ctx)
+        return off, pix
+
+    def forward_partial(self, g: GaussianTensors, cams, sel_offsets: torch.Tensor, sel_pixels: torch.Tensor,
+                        mode: int = L.MVGS_PARTIAL_COMPACT, images: Optional[List[torch.Tensor]] = None):
+        """Render only the selected pixels (Alg. 3). `images` (default: zero-filled) receive the
+        selected pixels; pass the same tensor for every view to get the merged image."""
+        g.check()
+        dev = g.means.device
+        if images is None:
+            images = [torch.zeros((3, c.height, c.width), dtype=torch.float32, device=dev) for c in cams]
+        sel_offsets, sel_pixels = sel_offsets.contiguous(), sel_pixels.contiguous()
+        fr = C.c_void_p()
+        st = self.lib.mvgs_forward_partial(self.ctx, _stream(), C.byref(self._gauss(g)), L.camera_array(cams),
+                                           len(cams), sel_offsets.data_ptr(), sel_pixels.data_ptr(),
+                                           int(sel_pixels.numel()), int(mode),
+                                           L.ptr_array([t.data_ptr() for t in images]), C.byref(fr))
+        L.check(st, self.ctx)
+        return images, Frame(self, fr, cams)
+
     def loss(self, cams, images, targets, w_l1=1.0, w_dssim=0.0, out=None, grads=None):
         """Fused L1 + D-SSIM: returns (loss [1] tensor on the GPU, list of dL/dimage)."""
         dev = images[0].device

@@ -58,13 +58,14 @@ class Admission:
     images       bytes of output images of requests in flight
     """
 
-    def __init__(self, budget: int, n_slots: int, max_batch: int, fixed_bytes: int = 0,
+    def __init__(self, budget: int, n_slots: int, max_batch: int, fixed_bytes: int = 0, view_bytes: int = 0,
                  bytes_per_pixel: float = 256.0, slack: float = 1.3, miss_growth: float = 1.5):
         if budget <= 0 or n_slots < 1 or max_batch < 1:
             raise ValueError("budget, n_slots and max_batch must be positive")
         self.budget = int(budget)
         self.max_batch = int(max_batch)
         self.fixed = int(fixed_bytes)
+        self.view_bytes = int(view_bytes)
         self.bpp = float(bytes_per_pixel)
         self.slack = float(slack)            # the context's allocator grows buffers with headroom
         self.miss_growth = float(miss_growth)
@@ -79,15 +80,17 @@ class Admission:
     def used(self) -> int:
         return sum(self.reserved) + self.images
 
-    def workspace_estimate(self, pixels: int) -> int:
-        return int(self.fixed + self.bpp * pixels)
+    def workspace_estimate(self, views: int, pixels: int) -> int:
+        """Workspace of a batch: a part per batch, a bound per view (records, one per Gaussian that
+        takes part, at most P) and a learned part per pixel (pairs and per-pixel blend state)."""
+        return int(self.fixed + self.view_bytes * views + self.bpp * pixels)
 
-    def _need(self, slot: int, pixels: int, image_bytes: int) -> int:
-        return max(self.held[slot], int(self.slack * self.workspace_estimate(pixels))) + image_bytes
+    def _need(self, slot: int, views: int, pixels: int, image_bytes: int) -> int:
+        return max(self.held[slot], int(self.slack * self.workspace_estimate(views, pixels))) + image_bytes
 
     def fits_alone(self, req: Request) -> bool:
         """Whether the request could run with every other slot empty."""
-        return int(self.slack * self.workspace_estimate(req.pixels)) + req.image_bytes <= self.budget
+        return int(self.slack * self.workspace_estimate(1, req.pixels)) + req.image_bytes <= self.budget
 
     def take(self, slot: int, queue: deque) -> List[Request]:
         """Pop the longest admissible prefix of `queue` for an idle `slot` and reserve its memory.
@@ -95,7 +98,7 @@ class Admission:
         avail = self.budget - (self.used() - self.reserved[slot])
         n = pix = img = 0
         for r in queue:
-            if n == self.max_batch or self._need(slot, pix + r.pixels, img + r.image_bytes) > avail:
+            if n == self.max_batch or self._need(slot, n + 1, pix + r.pixels, img + r.image_bytes) > avail:
                 break
             n += 1
             pix += r.pixels
@@ -104,7 +107,7 @@ class Admission:
             return []
         batch = [queue.popleft() for _ in range(n)]
         self.taken_gen[slot] = self.gen
-        self.reserved[slot] = max(self.held[slot], int(self.slack * self.workspace_estimate(pix)))
+        self.reserved[slot] = max(self.held[slot], int(self.slack * self.workspace_estimate(n, pix)))
         self.images += img
         self.peak = max(self.peak, self.used())
         return batch
@@ -116,7 +119,7 @@ class Admission:
         self.held[slot] = self.reserved[slot] = int(held_after)
         pix = sum(r.pixels for r in batch)
         if workspace is not None and pix > 0:
-            self.bpp = max(self.bpp, (workspace - self.fixed) / pix)
+            self.bpp = max(self.bpp, (workspace - self.fixed - self.view_bytes * len(batch)) / pix)
 
     def refused(self, slot: int, batch: Sequence[Request], held_after: int):
         """The library refused the batch under its reservation: release, and estimate higher unless
@@ -205,21 +208,27 @@ class _Slot:
                 srv.cond.notify_all()
 
 
+# Device bytes per participating (view, Gaussian) record in a forward: the 64-byte blend record, its
+# view (2), depth keys and record indices double-buffered (16), tile rectangle (16), pair count and
+# offset (8).
+RECORD_BYTES = 106
+
+
 class Server:
     """Continuous-batching render server over a resident scene (GaussianTensors on the GPU)."""
 
     def __init__(self, g, n_slots: int = 4, budget_bytes: int = 16 << 30, max_batch: int = 8,
                  tile=(16, 16), pixels_per_lane: int = 0, keep_images: bool = False,
-                 bytes_per_pixel: float = 256.0):
+                 bytes_per_pixel: float = 64.0):
         import torch
         g.check()
         self.g, self.device = g, g.means.device
         self.tile, self.ppl = tuple(tile), int(pixels_per_lane)
         self.keep_images = keep_images
-        # per-batch workspace that does not scale with pixels: Gaussian-sized counters and offsets,
-        # upload staging and page rounding
+        # per batch: Gaussian-sized counters and offsets, upload staging, page rounding; per view: at
+        # most P records of RECORD_BYTES each
         self.adm = Admission(budget_bytes, n_slots, max_batch, fixed_bytes=16 * (g.P + 1) + (256 << 10),
-                             bytes_per_pixel=bytes_per_pixel)
+                             view_bytes=RECORD_BYTES * g.P, bytes_per_pixel=bytes_per_pixel)
         self.cond = threading.Condition()
         self.queue: deque = deque()
         self.done: List[Request] = []

@@ -150,3 +150,33 @@ def test_workspace_limit_options_and_memory_queries():
     assert lib.mvgs_set_workspace_limit(None, 0) == L.MVGS_EINVAL
     assert lib.mvgs_frame_workspace(None, C.byref(held)) == L.MVGS_EINVAL
     lib.mvgs_destroy(h)
+
+
+def test_partial_and_subsample_validation(ctx):
+    lib = L.lib()
+    g = _gauss()
+    cams = scenes.make_cameras([(32, 32), (32, 32)])
+    ca = L.camera_array(cams)
+    imgs = L.ptr_array([0x2000, 0x2000])
+    fr = C.c_void_p()
+
+    def part(off, pix, n, mode):
+        return lib.mvgs_forward_partial(ctx, None, C.byref(g), ca, 2, off, pix, n, mode, imgs, C.byref(fr))
+
+    assert part(0x3000, 0x4000, 10, 7) == L.MVGS_EINVAL
+    assert "mode" in _err(ctx)
+    assert part(0x3000, 0x4000, -1, 0) == L.MVGS_EINVAL
+    assert part(0x3000, 0x4000, 1 << 32, 0) == L.MVGS_EINVAL
+    assert part(None, 0x4000, 10, 0) == L.MVGS_EINVAL
+    assert part(0x3000, None, 10, 1) == L.MVGS_EINVAL
+    assert "NULL" in _err(ctx)
+    # camera validation applies as in the full forward
+    bad = L.camera_array(scenes.make_cameras([(0, 32)]))
+    assert lib.mvgs_forward_partial(ctx, None, C.byref(g), bad, 1, 0x3000, 0x4000, 1, 0, imgs,
+                                    C.byref(fr)) == L.MVGS_EINVAL
+    # sub-sampling needs views of one size and non-NULL buffers
+    mixed = L.camera_array(scenes.make_cameras([(32, 32), (33, 32)]))
+    assert lib.mvgs_subsample(ctx, None, mixed, 2, 0x1000, 0x2000, 0x3000) == L.MVGS_EINVAL
+    assert "one size" in _err(ctx)
+    assert lib.mvgs_subsample(ctx, None, ca, 2, None, 0x2000, 0x3000) == L.MVGS_EINVAL
+    assert lib.mvgs_subsample(ctx, None, ca, 0, 0x1000, 0x2000, 0x3000) == L.MVGS_EINVAL

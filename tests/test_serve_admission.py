@@ -139,3 +139,19 @@ def test_request_stream_is_seeded_poisson():
         assert abs(np.linalg.norm(pos) - 3.0) < 1e-4
     a0, _ = scenes.make_requests(10, rate_hz=math.inf)
     assert np.all(a0 == 0.0)
+
+
+def test_per_view_bound_limits_batches_and_is_not_learned_per_pixel():
+    # 100 px requests; per view 1000 B of records, 1 B/px; slack 1
+    adm = Admission(budget=3000, n_slots=1, max_batch=8, view_bytes=1000, bytes_per_pixel=1.0, slack=1.0)
+    q = _reqs([(10, 10)] * 4)
+    b = adm.take(0, q)
+    # k views need 1100 k + 1200 k (images) <= 3000 -> 1
+    assert len(b) == 1 and adm.reserved[0] == 1100
+    # a finished batch whose workspace is mostly records does not inflate the per-pixel estimate
+    adm.finish(0, b, held_after=1050, workspace=1050)
+    assert adm.bpp == 1.0
+    adm.finish(0, [], held_after=1050, workspace=None)
+    b = adm.take(0, q)
+    adm.finish(0, b, held_after=1300, workspace=1300)
+    assert adm.bpp == 3.0
