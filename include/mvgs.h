@@ -139,7 +139,7 @@ void mvgs_destroy(mvgs_context* ctx);
 int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_camera* cams, int32_t B,
                  float* const* images, mvgs_frame** frame);
 
-/* Partial rendering (paper Sec. 4.1.1, "Thread-efficient partial rendering", and Alg. 3): each view
+/* Partial rendering (paper Sec. 5.1.1, "Thread-efficient partial rendering", and Alg. 3): each view
  * renders only a selection of its pixels, the paper's index array. The selection is given per
  * (view, tile) of the batch, in the order of the ranges (view-major; tiles of tile_w x tile_h of
  * this context, row-major):
@@ -163,7 +163,7 @@ int mvgs_forward_partial(mvgs_context* ctx, void* stream, const mvgs_gaussians* 
                          int32_t B, const uint32_t* sel_offsets, const uint32_t* sel_pixels, int64_t n_sel,
                          int32_t mode, float* const* images, mvgs_frame** frame);
 
-/* Pixel sub-sampling for partial rendering of B views of one size (paper Sec. 4.1.1: pixels of every
+/* Pixel sub-sampling for partial rendering of B views of one size (paper Sec. 5.1.1: pixels of every
  * tile are sub-sampled per view): the positions of each tile (of this context's tile shape) are
  * ranked by keys[y * width + x] (device uint32 [height * width], random numbers drawn by the
  * caller), ties by position, and the position of rank r goes to view r mod B. The views thus share

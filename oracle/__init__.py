@@ -235,7 +235,7 @@ def count_pairs(scene, cams, tile=(16, 16)):
 
 
 def subsample_tiles(width: int, height: int, B: int, tile, keys):
-    """Index array of thread-efficient partial rendering (Alg. 3; Sec. 4.1.1) for B views of one
+    """Index array of thread-efficient partial rendering (Alg. 3; Sec. 5.1.1) for B views of one
     size: each tile's pixel positions are shared out among the B views so that the views together
     cover the image plane once and each renders about N/B pixels of every tile (N pixels per tile).
 

@@ -1,4 +1,4 @@
-// Partial rendering (Sec. 4.1.1, Alg. 3): each view of the batch renders only a selection of its
+// Partial rendering (Sec. 5.1.1, Alg. 3): each view of the batch renders only a selection of its
 // pixels, so that a batch of views costs about one view's worth of blending.
 //
 // The selection is the paper's index array. For every (view, tile) of the batch, in the global

@@ -8,10 +8,14 @@
 // ceil(log2(total tiles)) bits). Ties in depth keep the (Gaussian, view) emission order of the
 // records, i.e. ascending Gaussian index within a view.
 //
-// Radix sort: 8-bit digits, 4096 items per workgroup (4 wavefronts x 16 rounds x 64 lanes).
-// Each pass is an upsweep (per-workgroup digit histogram), an exclusive scan of the digit-major
-// histogram table and a downsweep that ranks items stably within the workgroup with wave64
-// ballots, stages them in LDS in digit order and writes them out in contiguous runs.
+// Radix sort: LSD, digits of at most 8 bits spread evenly over the passes, 4096 items per
+// partition (4 wavefronts x 16 rounds x 64 lanes). One read of the keys builds the digit
+// histograms of every pass at once; then each pass is a single sweep: a workgroup takes the next
+// partition from an atomic counter, ranks its items stably with wave64 ballots, publishes its
+// per-digit counts, finds the exclusive prefix of each digit by looking back over earlier
+// partitions (decoupled look-back, relaxed device-scope atomics, stopping at the first published
+// inclusive prefix), stages the items in LDS in digit order and writes them out in contiguous
+// runs. A look-back wait is bounded: on time-out it raises an error word instead of hanging.
 #include <algorithm>
 
 #include "mvgs_kernels.h"
