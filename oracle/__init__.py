@@ -57,10 +57,10 @@ def lib():
         L.ora_total_tiles.argtypes = [vp]
         L.ora_binning.restype = i64
         L.ora_binning.argtypes = [vp, vp, vp, vp, i64, vp]
-        L.ora_forward.argtypes = [vp, vp, i32, i32, d, vp, vp, vp, vp, vp]
+        L.ora_forward.argtypes = [vp, vp, i32, i32, d, vp, vp, vp, vp, vp, vp]
         L.ora_backward.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.ora_project64.argtypes = [vp, vp, i32, vp, vp, vp, vp]
-        L.ora_render_pixels.argtypes = [vp, vp, i32, i32, d, i64, vp, vp, vp, vp, vp]
+        L.ora_render_pixels.argtypes = [vp, vp, i32, i32, d, i64, vp, vp, vp, vp, vp, vp]
         L.ora_count_pairs.argtypes = [vp, vp, vp, vp]
         L.ora_loss.argtypes = [vp, vp, vp, d, d, vp, vp]
         L.ora_ssim_map.argtypes = [i32, i32, vp, vp, vp]
@@ -149,19 +149,21 @@ def binning(scene, cams, tile=(16, 16)):
 
 
 def forward(scene, cams, tile=(16, 16), geom32_mode=True, brute_force=False, margin=1e-4):
-    """Images [3,H,W] (float64), T_final [H,W], contributor counts, per-pixel flags
-    (bit 0: the transmittance stop is within `margin` relative of its threshold) and a per-view
-    hash of every discrete decision taken."""
+    """Images [3,H,W] (float64), T_final [H,W], blended depth [H,W] (sum of z alpha T over the
+    blended Gaussians, z camera-space depth), contributor counts, per-pixel flags (bit 0: the
+    transmittance stop is within `margin` relative of its threshold) and a per-view hash of every
+    discrete decision taken."""
     s, c = OScene(scene), OCams(cams, tile)
     imgs = [np.zeros((3, h, w)) for (w, h) in c.sizes]
     tf = [np.zeros((h, w)) for (w, h) in c.sizes]
+    dp = [np.zeros((h, w)) for (w, h) in c.sizes]
     nc = [np.zeros((h, w), np.int32) for (w, h) in c.sizes]
     fl = [np.zeros((h, w), np.uint8) for (w, h) in c.sizes]
     th = np.zeros(c.B, np.uint64)
     ss, cs = s.struct(), c.struct()
     lib().ora_forward(C.byref(ss), C.byref(cs), int(geom32_mode), int(brute_force), float(margin),
-                      _ptrs(imgs), _ptrs(tf), _ptrs(nc), _ptrs(fl), _ptr(th))
-    return dict(images=imgs, t_final=tf, n_contrib=nc, flags=fl, trace=th)
+                      _ptrs(imgs), _ptrs(tf), _ptrs(dp), _ptrs(nc), _ptrs(fl), _ptr(th))
+    return dict(images=imgs, t_final=tf, depth=dp, n_contrib=nc, flags=fl, trace=th)
 
 
 def loss(cams, images, targets, w_l1=1.0, w_dssim=0.0):
@@ -212,16 +214,19 @@ def sh_basis(degree: int, d) -> tuple:
     return Y, dY
 
 
-def render_pixels(scene, cams, v: int, xs, ys, geom32_mode=True, margin=1e-4):
-    """Colour [n,3], final transmittance [n] and flags [n] of chosen pixels of view v, each by a walk
-    over every participating Gaussian in depth order (usable at any scene size)."""
+def render_pixels(scene, cams, v: int, xs, ys, geom32_mode=True, margin=1e-4, with_depth=False):
+    """Colour [n,3], final transmittance [n] and flags [n] (and, with_depth, the blended depth [n]
+    after them) of chosen pixels of view v, each by a walk over every participating Gaussian in
+    depth order (usable at any scene size)."""
     s, c = OScene(scene), OCams(cams)
     xs = np.ascontiguousarray(xs, np.int32); ys = np.ascontiguousarray(ys, np.int32)
     n = len(xs)
-    rgb = np.zeros((n, 3)); tf = np.zeros(n); fl = np.zeros(n, np.uint8)
+    rgb = np.zeros((n, 3)); tf = np.zeros(n); dp = np.zeros(n); fl = np.zeros(n, np.uint8)
     ss, cs = s.struct(), c.struct()
     lib().ora_render_pixels(C.byref(ss), C.byref(cs), v, int(geom32_mode), float(margin), n, _ptr(xs), _ptr(ys),
-                            _ptr(rgb), _ptr(tf), _ptr(fl))
+                            _ptr(rgb), _ptr(tf), _ptr(dp), _ptr(fl))
+    if with_depth:
+        return rgb, tf, fl, dp
     return rgb, tf, fl
 
 
@@ -264,3 +269,108 @@ def subsample_tiles(width: int, height: int, B: int, tile, keys):
     offsets[1:] = np.cumsum([len(s) for s in segs])
     pixels = np.array([p for s in segs for p in s], dtype=np.uint32)
     return offsets, pixels
+
+
+# ---------------------------------------------------------------------------------------------
+# 3D distance-aware D-SSIM (Sec. 5.1.2, Eqs. 7-11), on the merged image plane of partial rendering
+# ---------------------------------------------------------------------------------------------
+
+SSIM3D_SIGMA_PX = 1.5     # the window's sigma in pixels, as in the 2D D-SSIM
+SSIM3D_RADIUS = 5         # 11 x 11 window
+SSIM_C1, SSIM_C2 = 0.01 ** 2, 0.03 ** 2
+
+
+def surface_points(cams, view_map, depth, t_final):
+    """World-space surface point of every pixel of a merged image plane.
+
+    Pixel (x, y) was rendered from view view_map[y, x]. Its surface depth is the blended depth over
+    the blended opacity, zbar = depth / (1 - T_final), defined where something was blended
+    (T_final < 1); the point is R^T (zbar * ((x + 0.5 - cx) / fx, (y + 0.5 - cy) / fy, 1) - t), the
+    pixel-to-world map of the 3D kernel's definition. Also returns the kernel's width at the point:
+    1.5 pixels at depth zbar in world units, 1.5 zbar / fx (0 where there is no point).
+    Returns (points [H, W, 3], scale [H, W])."""
+    view_map = np.asarray(view_map)
+    H, W = view_map.shape
+    P = np.zeros((H, W, 3))
+    S = np.zeros((H, W))
+    for y in range(H):
+        for x in range(W):
+            c = cams[int(view_map[y, x])]
+            a = 1.0 - float(t_final[y, x])
+            if not a > 0.0:
+                continue
+            z = float(depth[y, x]) / a
+            ray = np.array([(x + 0.5 - c.cx) / c.fx, (y + 0.5 - c.cy) / c.fy, 1.0])
+            R = np.asarray(c.R, np.float64).reshape(3, 3)
+            t = np.asarray(c.t, np.float64).reshape(3)
+            P[y, x] = R.T @ (z * ray - t)
+            S[y, x] = SSIM3D_SIGMA_PX * z / c.fx
+    return P, S
+
+
+def _kernel3d(points, scale, du, dv):
+    """Weights w[c] of the window offset (du, dv) for every centre c: exp(-|P(c + d) - P(c)|^2 /
+    (2 scale(c)^2)) where both pixels have points and c + d is inside the plane; a centre without a
+    point keeps only itself. Returns (w [H, W], q index arrays (qy, qx) clipped, inside mask)."""
+    H, W = scale.shape
+    ys, xs = np.mgrid[0:H, 0:W]
+    qy, qx = ys + dv, xs + du
+    inside = (qy >= 0) & (qy < H) & (qx >= 0) & (qx < W)
+    qyc, qxc = np.clip(qy, 0, H - 1), np.clip(qx, 0, W - 1)
+    has_c = scale > 0
+    has_q = scale[qyc, qxc] > 0
+    d2 = ((points[qyc, qxc] - points) ** 2).sum(-1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        w = np.where(has_c & has_q, np.exp(-d2 / (2.0 * np.where(has_c, scale, 1.0) ** 2)), 0.0)
+    if du == 0 and dv == 0:
+        w = np.where(has_c, w, 1.0)
+    return np.where(inside, w, 0.0), qyc, qxc
+
+
+def loss3d(image, target, points, scale, w_l1=1.0, w_dssim=0.0):
+    """L = w_l1 mean|I - T| + w_dssim (1 - mean SSIM*) over one merged plane [3, H, W], where
+    SSIM* is Eqs. 7-10 with the window replaced by the 3D distance-aware kernel (Eq. 11) around each
+    centre, normalised to sum 1 over the in-plane window. The kernel's weights are constants (the
+    rendered depth passes no gradient). Returns (loss, dL/dimage [3, H, W])."""
+    I1 = np.asarray(image, np.float64)
+    I2 = np.asarray(target, np.float64)
+    _, H, W = I1.shape
+    N = I1.size
+    r = SSIM3D_RADIUS
+    offs = [(du, dv) for dv in range(-r, r + 1) for du in range(-r, r + 1)]
+    Wc = np.zeros((H, W))
+    m1 = np.zeros_like(I1); m2 = np.zeros_like(I1)
+    e11 = np.zeros_like(I1); e22 = np.zeros_like(I1); e12 = np.zeros_like(I1)
+    for du, dv in offs:
+        w, qy, qx = _kernel3d(points, scale, du, dv)
+        a, b = I1[:, qy, qx], I2[:, qy, qx]
+        Wc += w
+        m1 += w * a; m2 += w * b
+        e11 += w * a * a; e22 += w * b * b; e12 += w * a * b
+    mu1, mu2 = m1 / Wc, m2 / Wc
+    s11 = e11 / Wc - mu1 * mu1
+    s22 = e22 / Wc - mu2 * mu2
+    s12 = e12 / Wc - mu1 * mu2
+    A = 2 * mu1 * mu2 + SSIM_C1
+    Bn = 2 * s12 + SSIM_C2
+    Cn = mu1 * mu1 + mu2 * mu2 + SSIM_C1
+    Dn = s11 + s22 + SSIM_C2
+    S = A * Bn / (Cn * Dn)
+    L1 = np.abs(I1 - I2).mean()
+    loss = w_l1 * L1 + w_dssim * (1.0 - S.mean())
+    # dS(c)/dI1(q) = w_cq / W_c * (dS/dmu1 + dS/ds11 * 2 (I1(q) - mu1) + dS/ds12 * (I2(q) - mu2))
+    dmu = 2 * mu2 * Bn / (Cn * Dn) - S * 2 * mu1 / Cn
+    ds11 = -S / Dn
+    ds12 = 2 * A / (Cn * Dn)
+    ca = (dmu - 2 * mu1 * ds11 - mu2 * ds12) / Wc
+    cb = 2 * ds11 / Wc
+    cd = ds12 / Wc
+    dS = np.zeros_like(I1)
+    ys, xs = np.mgrid[0:H, 0:W]
+    for du, dv in offs:
+        w, qy, qx = _kernel3d(points, scale, du, dv)
+        contrib = w * (ca + cb * I1[:, qy, qx] + cd * I2[:, qy, qx])
+        inside = w > 0
+        np.add.at(dS, (slice(None), qy[inside], qx[inside]), contrib[:, inside])
+    grad = w_l1 * np.sign(I1 - I2) / N - w_dssim * dS / N
+    return loss, grad, S

@@ -90,15 +90,18 @@ int64_t ora_total_tiles(const ora_cams* c);
 int ora_geom32_view(const ora_scene* s, const ora_cams* c, int32_t v, ora_g32* out /* [P] */);
 int64_t ora_binning(const ora_scene* s, const ora_cams* c, uint64_t* keys, uint32_t* vals,
                     int64_t cap, uint32_t* ranges /* [2*total_tiles] or NULL */);
+/* depth: per view [H,W], the camera-space depth blended with the colour weights,
+ * sum_i z_i alpha_i T_i (may be NULL) */
 int ora_forward(const ora_scene* s, const ora_cams* c, int32_t geom32_mode, int32_t brute_force,
-                double margin, double* const* images, double* const* t_final,
+                double margin, double* const* images, double* const* t_final, double* const* depth,
                 int32_t* const* n_contrib, uint8_t* const* flags, uint64_t* trace_hash /* [B] or NULL */);
 int ora_backward(const ora_scene* s, const ora_cams* c, int32_t geom32_mode,
                  const double* const* dl_dimg, double* g_means, double* g_scales, double* g_quats,
                  double* g_opac, double* g_sh, double* e1, double* e2, int32_t* count,
                  double* g_mean2d /* [B][P][2] or NULL */, double* e_old /* [P] or NULL */);
 int ora_render_pixels(const ora_scene* s, const ora_cams* c, int32_t v, int32_t geom32_mode, double margin,
-                      int64_t n, const int32_t* xs, const int32_t* ys, double* rgb, double* t_final, uint8_t* flags);
+                      int64_t n, const int32_t* xs, const int32_t* ys, double* rgb, double* t_final, double* depth,
+                      uint8_t* flags);
 int ora_count_pairs(const ora_scene* s, const ora_cams* c, int64_t* records, int64_t* pairs);
 int ora_project64(const ora_scene* s, const ora_cams* c, int32_t v, double* mean2d, double* cov2d,
                   double* rgb, double* depth);

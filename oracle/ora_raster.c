@@ -299,6 +299,7 @@ int64_t ora_binning(const ora_scene* s, const ora_cams* c, uint64_t* keys, uint3
 /* What the pixel loop needs per Gaussian of one view. */
 typedef struct {
     double mx, my, ca, cb, cc, o, rgb[3];
+    double z; /* camera-space depth */
     int clamp_bits;
 } pix_g;
 
@@ -322,9 +323,11 @@ static void prepare_view(const ora_scene* s, const ora_cams* c, int v, int geom3
         if (geom32_mode) {
             q->mx = g32[g].mx; q->my = g32[g].my;
             q->ca = g32[g].ca; q->cb = g32[g].cb; q->cc = g32[g].cc;
+            q->z = g32[g].depth;
         } else {
             q->mx = p.mean2d[0]; q->my = p.mean2d[1];
             q->ca = p.conic[0]; q->cb = p.conic[1]; q->cc = p.conic[2];
+            q->z = p.tc[2];
         }
         q->o = s->opac[g];
         q->clamp_bits = 0;
@@ -387,7 +390,7 @@ static uint32_t* depth_order(const ora_g32* g32, int64_t P, int64_t* n_out)
 }
 
 int ora_forward(const ora_scene* s, const ora_cams* c, int32_t geom32_mode, int32_t brute_force, double margin,
-                double* const* images, double* const* t_final, int32_t* const* n_contrib,
+                double* const* images, double* const* t_final, double* const* depth, int32_t* const* n_contrib,
                 uint8_t* const* flags, uint64_t* trace_hash)
 {
     const int64_t P = s->P;
@@ -408,7 +411,7 @@ int ora_forward(const ora_scene* s, const ora_cams* c, int32_t geom32_mode, int3
         for (int y = 0; y < H; ++y) {
             for (int x = 0; x < W; ++x) {
                 const int64_t pix = (int64_t)y * W + x;
-                double T = 1.0, C[3] = {0, 0, 0};
+                double T = 1.0, C[3] = {0, 0, 0}, Dz = 0.0;
                 int flag = 0, n = 0;
                 uint64_t h = mix64((uint64_t)pix);
                 const uint32_t* list;
@@ -434,12 +437,14 @@ int ora_forward(const ora_scene* s, const ora_cams* c, int32_t geom32_mode, int3
                         break;
                     }
                     for (int k = 0; k < 3; ++k) C[k] += pg[g].rgb[k] * st.alpha * T;
+                    Dz += pg[g].z * st.alpha * T;
                     T = T * (1.0 - st.alpha);
                     ++n;
                     h = mix64(h ^ ((uint64_t)g << 2) ^ (uint64_t)st.clamped);
                 }
                 for (int k = 0; k < 3; ++k) images[v][(int64_t)k * H * W + pix] = C[k] + T * bg[k];
                 if (t_final) t_final[v][pix] = T;
+                if (depth) depth[v][pix] = Dz;
                 if (n_contrib) n_contrib[v][pix] = n;
                 if (flags) flags[v][pix] = (uint8_t)flag;
                 hsum += h;
@@ -718,7 +723,8 @@ int ora_backward(const ora_scene* s, const ora_cams* c, int32_t geom32_mode, con
  * participating Gaussian of the view in (depth bits, g) order (no tiles), as the brute-force
  * path does; used where rendering the whole batch would take too long. */
 int ora_render_pixels(const ora_scene* s, const ora_cams* c, int32_t v, int32_t geom32_mode, double margin,
-                      int64_t n, const int32_t* xs, const int32_t* ys, double* rgb, double* t_final, uint8_t* flags)
+                      int64_t n, const int32_t* xs, const int32_t* ys, double* rgb, double* t_final, double* depth,
+                      uint8_t* flags)
 {
     if (v < 0 || v >= c->B) return -1;
     const int64_t P = s->P;
@@ -731,7 +737,7 @@ int ora_render_pixels(const ora_scene* s, const ora_cams* c, int32_t v, int32_t 
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t k = 0; k < n; ++k) {
         const int x = xs[k], y = ys[k];
-        double T = 1.0, C[3] = {0, 0, 0};
+        double T = 1.0, C[3] = {0, 0, 0}, Dz = 0.0;
         int flag = 0;
         for (int64_t i = 0; i < n_order; ++i) {
             const uint32_t g = order[i];
@@ -740,10 +746,12 @@ int ora_render_pixels(const ora_scene* s, const ora_cams* c, int32_t v, int32_t 
             if (r == 0) continue;
             if (r == 2) break;
             for (int q = 0; q < 3; ++q) C[q] += pg[g].rgb[q] * st.alpha * T;
+            Dz += pg[g].z * st.alpha * T;
             T = T * (1.0 - st.alpha);
         }
         for (int q = 0; q < 3; ++q) rgb[3 * k + q] = C[q] + T * bg[q];
         t_final[k] = T;
+        if (depth) depth[k] = Dz;
         flags[k] = (uint8_t)flag;
     }
     free(order);
