@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--no-graph", action="store_true", help="time eager calls only (no HIP-graph replay)")
     ap.add_argument("--no-partial", action="store_true", help="skip the partial-rendering comparison")
     ap.add_argument("--partial-views", type=int, default=8)
     ap.add_argument("--partial-size", default="1280x720")
@@ -153,6 +154,25 @@ def main():
     steps_walk, blended = (int(x) for x in work.cpu().tolist())
     rast.release(fr)
 
+    # the same step captured into a HIP graph (capacity mode: no host synchronization in the step)
+    graph_res = None
+    if not args.no_graph:
+        from paper_2506_12727_amd.graph import CapturedStep
+        capacity = (int(info["records"] * 1.02) + 1024, int(info["pairs"] * 1.02) + 4096)
+        gstep = CapturedStep(g, cams, tg, wl.w_l1, wl.w_dssim, tile=tile, ppl=ppl, capacity=capacity, densify=dz)
+        for _ in range(args.warmup):
+            gstep.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            gstep.replay()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gstep.check()
+        graph_res = {"ms_per_step": 1e3 * (t1 - t0) / args.steps, "views_per_s": B * args.steps / (t1 - t0),
+                     "capacity": {"records": capacity[0], "pairs": capacity[1]}}
+        gstep.close()
+
     loop_res = None
     if not args.no_loop:
         for _ in range(max(1, args.warmup)):
@@ -187,14 +207,20 @@ def main():
 
     cpu = None if args.no_cpu else cpu_baseline(scene, cams, tg, wl, (16, 16), args.cpu_views)
     total_px = sum(c.width * c.height for c in cams)
+    # the headline is the graph-replayed step when it ran (same work; no host gaps between kernels)
+    value, ms_value = views_s, ms_step
+    if graph_res is not None:
+        value, ms_value = graph_res["views_per_s"], graph_res["ms_per_step"]
+    if loop_res is not None:
+        loop_res["batched_speedup"] = value / loop_res["value"]
     out = {
         "metric": METRIC,
-        "value": views_s,
+        "value": value,
         "unit": "views/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": ms_value,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -204,7 +230,10 @@ def main():
                    "sizes": [[c.width, c.height] for c in cams], "tile": list(tile),
                    "pixels_per_lane": ppl, "autotune_ms_per_step": tuned,
                    "loss": {"w_l1": wl.w_l1, "w_dssim": wl.w_dssim}, "densify": wl.densify},
-        "gaussian_pixels_per_s": g.P * total_px * args.steps / elapsed,
+        "gaussian_pixels_per_s": g.P * total_px / (ms_value / 1e3),
+        "value_source": "hip graph replay" if graph_res is not None else "eager calls",
+        "eager": {"ms_per_step": ms_step, "views_per_s": views_s},
+        "graph": graph_res,
         "one_view_loop": loop_res,
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "frame": {"records": info["records"], "pairs": info["pairs"], "tiles": info["tiles"],
@@ -225,7 +254,8 @@ def partial_bench(args, g, wl, tile, ppl):
     backward. full = every pixel of every view; masked = the binary-mask baseline; compact = the
     thread-efficient scheme; single = one view, every pixel. In the partial modes each tile's pixels
     are shared out among the views (fresh random keys every step), so the batch renders one image
-    plane's worth of pixels, written as one merged image."""
+    plane's worth of pixels, written as one merged image. full and single use the main workload's
+    launch shape; each partial mode is timed with every candidate tile and reports its fastest."""
     import ctypes as C
 
     import torch
@@ -239,7 +269,6 @@ def partial_bench(args, g, wl, tile, ppl):
     cams = scenes.make_cameras([(W, H)] * B, radius=wl.radius)
     tg = [torch.from_numpy(t).cuda() for t in scenes.make_targets(cams)]
     keys_tg = torch.from_numpy(scenes.make_targets(cams[:1], seed=scenes.SEED_TARGETS + 1)[0]).cuda()
-    rast = Rasterizer(tile, ppl)
     lib = L.lib()
     imgs = [torch.empty((3, H, W), device="cuda") for _ in range(B)]
     dl = [torch.empty_like(t) for t in imgs]
@@ -250,14 +279,14 @@ def partial_bench(args, g, wl, tile, ppl):
     gen = torch.Generator(device="cuda")
     gen.manual_seed(scenes.SEED_REQUESTS)
 
-    def full_step(n):
+    def full_step(rast, n):
         v = cams[:n]
         _, fr = rast.forward(g, v, images=imgs[:n])
         rast.loss(v, imgs[:n], tg[:n], 1.0, 0.0, out=loss, grads=dl[:n])
         rast.backward(g, fr, dl[:n], grads=grads)
         rast.release(fr)
 
-    def partial_step(mode):
+    def partial_step(rast, mode):
         keys = torch.randint(-2 ** 31, 2 ** 31 - 1, (W * H,), dtype=torch.int32, device="cuda", generator=gen)
         off, pix = rast.subsample(cams, keys)
         _, fr = rast.forward_partial(g, cams, off, pix, mode, images=[merged] * B)
@@ -265,13 +294,11 @@ def partial_bench(args, g, wl, tile, ppl):
         rast.backward(g, fr, [merged_dl] * B, grads=grads)
         rast.release(fr)
 
-    runs = {"full": lambda: full_step(B), "masked": lambda: partial_step(L.MVGS_PARTIAL_MASKED),
-            "compact": lambda: partial_step(L.MVGS_PARTIAL_COMPACT), "single": lambda: full_step(1)}
-    out = {"views": B, "size": [W, H], "tile": list(tile), "pixels_per_lane": ppl}
     steps = max(5, args.steps // 2)
     ms = (C.c_double * L.MVGS_STAGE_COUNT)()
     calls = (C.c_int64 * L.MVGS_STAGE_COUNT)()
-    for name, fn in runs.items():
+
+    def timed(rast, fn):
         for _ in range(2):
             fn()
         torch.cuda.synchronize()
@@ -284,12 +311,26 @@ def partial_bench(args, g, wl, tile, ppl):
         dt = (time.perf_counter() - t0) / steps
         lib.mvgs_profile_enable(rast.ctx, 0)
         L.check(lib.mvgs_profile_read(rast.ctx, ms, calls), rast.ctx)
-        out[name] = {"ms_per_step": 1e3 * dt,
-                     "blend_fwd_ms": ms[6] / max(calls[6], 1), "blend_bwd_ms": ms[8] / max(calls[8], 1)}
+        return {"ms_per_step": 1e3 * dt, "blend_fwd_ms": ms[6] / max(calls[6], 1),
+                "blend_bwd_ms": ms[8] / max(calls[8], 1)}
+
+    out = {"views": B, "size": [W, H]}
+    rast = Rasterizer(tile, ppl)
+    out["full"] = dict(timed(rast, lambda: full_step(rast, B)), tile=list(tile), pixels_per_lane=ppl)
+    out["single"] = dict(timed(rast, lambda: full_step(rast, 1)), tile=list(tile), pixels_per_lane=ppl)
+    rast.close()
+    for name, mode in (("masked", L.MVGS_PARTIAL_MASKED), ("compact", L.MVGS_PARTIAL_COMPACT)):
+        best = None
+        for t in ((16, 16), (32, 16), (32, 32)):
+            r = Rasterizer(t)
+            res = dict(timed(r, lambda: partial_step(r, mode)), tile=list(t))
+            r.close()
+            if best is None or res["ms_per_step"] < best["ms_per_step"]:
+                best = res
+        out[name] = best
     out["compact_vs_full_speedup"] = out["full"]["ms_per_step"] / out["compact"]["ms_per_step"]
     out["compact_vs_masked_speedup"] = out["masked"]["ms_per_step"] / out["compact"]["ms_per_step"]
     out["compact_vs_single_view_overhead"] = out["compact"]["ms_per_step"] / out["single"]["ms_per_step"]
-    rast.close()
     return out
 
 

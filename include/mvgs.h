@@ -103,14 +103,23 @@ typedef struct {
  * workspace_limit: 0 for none, else the most device bytes the context may hold (workspace,
  * upload staging and all its frames, as mvgs_memory_held counts them). A call that would grow
  * past it allocates nothing and returns MVGS_ECAPACITY; a serving loop admits work against an
- * HBM budget this way. Must be >= 0. reserved must be zero. */
+ * HBM budget this way. Must be >= 0. reserved0 must be zero.
+ * capacity_records, capacity_pairs: both 0 (sizes found per call: the forward synchronizes once),
+ * or both in [1, 2^32): capacity mode. The forward then makes no host synchronization: buffers are
+ * sized once by the capacities, every kernel reads the actual counts from device memory, and a
+ * call whose participating (view, Gaussian) records or (Gaussian, tile) pairs exceed them does no
+ * work (images get the background) and is reported by mvgs_frame_check. Such a forward, with the
+ * loss and backward on its frame, can be captured into a HIP graph (the stream in capture mode),
+ * after one call of each with the same shapes outside the capture; partial rendering is not
+ * available in capacity mode. */
 typedef struct {
     int32_t tile_w;
     int32_t tile_h;
     int32_t pixels_per_lane;
     int32_t reserved0;
     int64_t workspace_limit;
-    int64_t reserved[2];
+    int64_t capacity_records;
+    int64_t capacity_pairs;
 } mvgs_options;
 
 /* Create a context on the current HIP device. `opt` may be NULL (defaults).
@@ -134,8 +143,9 @@ void mvgs_destroy(mvgs_context* ctx);
  *           sorted lists, ranges, final transmittance, last contributor per
  *           pixel); release it with mvgs_frame_release.
  * Synchronizes the stream once to read the number of (Gaussian, tile) pairs,
- * which sizes the sort. Returns MVGS_ECAPACITY if that number reaches 2^32 or
- * the workspace would exceed the context's limit (no frame is made then). */
+ * which sizes the sort (not in capacity mode: see mvgs_options). Returns
+ * MVGS_ECAPACITY if that number reaches 2^32 or the workspace would exceed the
+ * context's limit (no frame is made then). */
 int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_camera* cams, int32_t B,
                  float* const* images, mvgs_frame** frame);
 
@@ -169,8 +179,8 @@ int mvgs_forward_partial(mvgs_context* ctx, void* stream, const mvgs_gaussians* 
  * caller), ties by position, and the position of rank r goes to view r mod B. The views thus share
  * every tile out evenly (ceil or floor of N/B pixels each) and together cover the image plane once.
  * Writes the selection in mvgs_forward_partial's format: sel_offsets [B * tiles + 1], sel_pixels
- * [height * width] (caller-owned device buffers), each segment in rank order. MVGS_EINVAL if the
- * views differ in size. */
+ * [height * width] (caller-owned device buffers), each segment in ascending pixel index (compact
+ * bands per wavefront). MVGS_EINVAL if the views differ in size. */
 int mvgs_subsample(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t B, const uint32_t* keys,
                    uint32_t* sel_offsets, uint32_t* sel_pixels);
 
@@ -184,6 +194,25 @@ int mvgs_subsample(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int
 int mvgs_loss(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t B, const float* const* images,
               const float* const* targets, float w_l1, float w_dssim, float* loss_dev, float* const* dl_dimages);
 
+/* L1 + 3D distance-aware D-SSIM (paper Sec. 5.1.2, Eqs. 7-11) on the merged image plane of a
+ * thread-efficient partial frame whose selection covers the views' common image plane once (as
+ * mvgs_subsample makes). Pixel (x, y) of the plane was rendered from one view; its surface point is
+ * the blended depth over the blended opacity, zbar = D / (1 - T_final), along that view's camera
+ * ray, in world space (no point where nothing was blended). The SSIM window (11 x 11) around each
+ * centre weighs a neighbour by exp(-|P(q) - P(c)|^2 / (2 s_c^2)), s_c = 1.5 zbar_c / fx (1.5
+ * pixels at the centre's depth), normalised over the in-plane window; a centre without a point
+ * keeps only itself; the weights are constants of the loss (no gradient reaches the depth).
+ *   L = w_l1 * mean|I - T| + w_dssim * (1 - mean SSIM*)   over (channel, row, column)
+ * image, target: device [3, H, W] merged planes; writes the loss to loss_dev and dL/dI to
+ * dl_dimage ([3, H, W], overwritten). Pass dl_dimage for every view to mvgs_backward. */
+int mvgs_loss_3d(mvgs_context* ctx, void* stream, const mvgs_frame* frame, const float* image, const float* target,
+                 float w_l1, float w_dssim, float* loss_dev, float* dl_dimage);
+
+/* Test hook: the blended depth (sum of z alpha T over the blended Gaussians, z the camera-space
+ * depth) of a thread-efficient partial frame's selected pixels into B device [H, W] planes (other
+ * pixels untouched). */
+int mvgs_export_depth(mvgs_context* ctx, void* stream, const mvgs_frame* frame, float* const* depth);
+
 /* Backward pass: from dL/dimage (B device pointers [3,H,W]) to parameter
  * gradients (overwritten) and, when `densify` is not NULL, the densification
  * statistics (accumulated). `g` must hold the same parameters the frame was
@@ -195,6 +224,18 @@ int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, cons
 /* Return a frame's memory to its context. The frame must not be in use by
  * work still pending on a stream other than the one it was created on. */
 int mvgs_frame_release(mvgs_context* ctx, mvgs_frame* frame);
+
+/* Capacity mode: wait for the frame's forward and report whether it fitted the capacities
+ * (MVGS_ECAPACITY if not: its images and any backward on it are void; make a context with larger
+ * capacities). Sets the sizes mvgs_frame_info and mvgs_export_binning use. Synchronizes the
+ * stream; not capturable. Returns MVGS_OK at once for frames not made in capacity mode. */
+int mvgs_frame_check(mvgs_context* ctx, void* stream, mvgs_frame* frame);
+
+/* For a frame made by a forward captured into a graph: replace its cameras (same count and image
+ * sizes; poses, intrinsics and background may change). Host-only: it rewrites the staging memory
+ * the graph's upload node reads, so the next replay renders the new cameras. No replay that
+ * reads this frame may be in flight. */
+int mvgs_frame_set_cameras(mvgs_context* ctx, mvgs_frame* frame, const mvgs_camera* cams, int32_t B);
 
 /* Change a context's workspace limit (bytes, 0 for none; see mvgs_options). Memory already held
  * is kept: the limit applies to later growth. No device work. */

@@ -247,9 +247,10 @@ def subsample_tiles(width: int, height: int, B: int, tile, keys):
     The sub-sampling draws one random key per pixel position (`keys`, [height*width] or
     [height, width], passed in): a tile's positions are ranked by (key, position index) and the
     position of rank r goes to view r mod B. Returns (offsets, pixels): segment
-    [offsets[s], offsets[s+1]) of `pixels` lists, in rank order, the pixel indices y*width + x of
-    view v in tile t, with s = v * tiles_per_view + t (tiles row-major within a view).
-    Plain loops, one tile at a time."""
+    [offsets[s], offsets[s+1]) of `pixels` lists, in ascending position, the pixel indices
+    y*width + x of view v in tile t, with s = v * tiles_per_view + t (tiles row-major within a
+    view). (The order inside a segment does not change what is rendered.) Plain loops, one tile at
+    a time."""
     tw, th = int(tile[0]), int(tile[1])
     W, H = int(width), int(height)
     keys = np.asarray(keys, dtype=np.uint32).reshape(-1)
@@ -265,6 +266,8 @@ def subsample_tiles(width: int, height: int, B: int, tile, keys):
             ranked = sorted(pos, key=lambda p: (int(keys[p]), p))
             for r, p in enumerate(ranked):
                 segs[(r % B) * T + t].append(p)
+            for v in range(B):
+                segs[v * T + t].sort()
     offsets = np.zeros(B * T + 1, np.uint32)
     offsets[1:] = np.cumsum([len(s) for s in segs])
     pixels = np.array([p for s in segs for p in s], dtype=np.uint32)

@@ -23,7 +23,8 @@ EXPORTED = ["mvgs_create", "mvgs_destroy", "mvgs_forward", "mvgs_loss", "mvgs_ba
             "mvgs_frame_info", "mvgs_export_binning", "mvgs_export_transmittance", "mvgs_status_string",
             "mvgs_last_error", "mvgs_profile_enable", "mvgs_profile_read", "mvgs_profile_reset",
             "mvgs_stage_name", "mvgs_frame_work", "mvgs_set_workspace_limit", "mvgs_memory_held",
-            "mvgs_frame_workspace", "mvgs_forward_partial", "mvgs_subsample"]
+            "mvgs_frame_workspace", "mvgs_forward_partial", "mvgs_subsample", "mvgs_frame_check",
+            "mvgs_frame_set_cameras", "mvgs_loss_3d", "mvgs_export_depth"]
 MVGS_PARTIAL_COMPACT = 0
 MVGS_PARTIAL_MASKED = 1
 MVGS_STAGE_COUNT = 10
@@ -51,7 +52,8 @@ class mvgs_densify(C.Structure):
 
 class mvgs_options(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("pixels_per_lane", C.c_int32),
-                ("reserved0", C.c_int32), ("workspace_limit", C.c_int64), ("reserved", C.c_int64 * 2)]
+                ("reserved0", C.c_int32), ("workspace_limit", C.c_int64), ("capacity_records", C.c_int64),
+                ("capacity_pairs", C.c_int64)]
 
 
 class MvgsError(RuntimeError):
@@ -117,6 +119,14 @@ def lib():
     L.mvgs_forward_partial.restype = C.c_int
     L.mvgs_subsample.argtypes = [vp, vp, C.POINTER(mvgs_camera), i32, vp, vp, vp]
     L.mvgs_subsample.restype = C.c_int
+    L.mvgs_frame_check.argtypes = [vp, vp, vp]
+    L.mvgs_frame_check.restype = C.c_int
+    L.mvgs_frame_set_cameras.argtypes = [vp, vp, C.POINTER(mvgs_camera), i32]
+    L.mvgs_frame_set_cameras.restype = C.c_int
+    L.mvgs_loss_3d.argtypes = [vp, vp, vp, vp, vp, f32, f32, vp, vp]
+    L.mvgs_loss_3d.restype = C.c_int
+    L.mvgs_export_depth.argtypes = [vp, vp, vp, vp]
+    L.mvgs_export_depth.restype = C.c_int
     _LIB = L
     return L
 

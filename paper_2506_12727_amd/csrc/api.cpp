@@ -79,8 +79,43 @@ struct UploadRing {
     Slot slots[kSlots];
     int next = 0;
     std::vector<int> used;
+    // Staging recorded into a stream capture: one dedicated buffer pair per upload, kept until the
+    // context is destroyed, so that every replay of the graph copies the same host memory.
+    struct Sticky {
+        void* host = nullptr;
+        void* dev = nullptr;
+        size_t bytes = 0;
+    };
+    std::vector<Sticky> sticky;
 
-    hipError_t put(const void* src, size_t bytes, hipStream_t s, void** dev_out) {
+    hipError_t put_sticky(const void* src, size_t bytes, hipStream_t s, void** dev_out, void** host_out) {
+        Sticky st;
+        st.bytes = std::max<size_t>(bytes, 256);
+        // allocations are not stream work; let them through the capture like a caching allocator does
+        hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+        hipError_t e = hipThreadExchangeStreamCaptureMode(&mode);
+        if (e != hipSuccess) return e;
+        e = hipHostMalloc(&st.host, st.bytes, hipHostMallocDefault);
+        if (e == hipSuccess) {
+            e = hipMalloc(&st.dev, st.bytes);
+            if (e != hipSuccess) (void)hipHostFree(st.host);
+        }
+        hipStreamCaptureMode back = mode;
+        (void)hipThreadExchangeStreamCaptureMode(&back);
+        if (e != hipSuccess) return e;
+        sticky.push_back(st);
+        memcpy(st.host, src, bytes);
+        e = hipMemcpyAsync(st.dev, st.host, bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return e;
+        *dev_out = st.dev;
+        if (host_out) *host_out = st.host;
+        return hipSuccess;
+    }
+
+    hipError_t put(const void* src, size_t bytes, hipStream_t s, void** dev_out, bool capturing = false,
+                   void** host_out = nullptr) {
+        if (capturing) return put_sticky(src, bytes, s, dev_out, host_out);
+        if (host_out) *host_out = nullptr;
         Slot& sl = slots[next];
         const int idx = next;
         next = (next + 1) % kSlots;
@@ -122,6 +157,11 @@ struct UploadRing {
         return r;
     }
     void destroy() {
+        for (auto& st : sticky) {
+            if (st.host) (void)hipHostFree(st.host);
+            if (st.dev) (void)hipFree(st.dev);
+        }
+        sticky.clear();
         for (auto& sl : slots) {
             if (sl.pending) (void)hipEventSynchronize(sl.ev);
             if (sl.ev) (void)hipEventDestroy(sl.ev);
@@ -151,13 +191,22 @@ struct mvgs_frame {
     // n_last then hold one entry per selected pixel in thread-efficient mode)
     int mode = kModeFull;
     uint32_t n_sel = 0, n_tasks = 0;
+    // capacity mode: sizes are known on the host only after mvgs_frame_check; dtot holds the
+    // call's totals (u64 records, pairs, error words) and at byte 32 the clamped counts and the
+    // overflow word
+    bool capacity = false, checked = true;
+    void* cam_stage = nullptr;   // host staging of the cameras when the forward was captured
+    // thread-efficient partial frames: whether the selection covers the views' common image plane
+    // once (then the merged plane has a 3D loss), and the blended depth per selected pixel
+    bool partition = false;
     DevBuf cams, recs, rec_off, rec_view, keys[2], vals[2], ranges, t_final, n_last;
-    DevBuf sel_off, sel_pix, mask, task_n, task_off, tasks;
+    DevBuf sel_off, sel_pix, mask, task_n, task_off, tasks, dtot, depth, plane_mask;
 
     template <typename Fn>
     void each_buffer(Fn fn) {
         DevBuf* bufs[] = {&cams, &recs, &rec_off, &rec_view, &keys[0], &keys[1], &vals[0], &vals[1], &ranges,
-                          &t_final, &n_last, &sel_off, &sel_pix, &mask, &task_n, &task_off, &tasks};
+                          &t_final, &n_last, &sel_off, &sel_pix, &mask, &task_n, &task_off, &tasks, &dtot, &depth,
+                          &plane_mask};
         for (DevBuf* b : bufs) fn(*b);
     }
 };
@@ -168,8 +217,10 @@ struct mvgs_context {
     std::string err;
     std::vector<mvgs_frame*> frames;
     DevBuf nrec, ntiles, totals, scan_scratch, depth_key[2], rec_vals[2], tile_rect, pair_counts, pair_off;
-    DevBuf sort_scratch, acc, loss_scratch, ssim_maps;
+    DevBuf sort_scratch, acc, loss_scratch, ssim_maps, loss3d_scratch;
     size_t limit = 0;  // 0: no workspace limit
+    uint64_t cap_v = 0, cap_k = 0;  // capacity mode when non-zero
+    bool capturing = false;         // the current call's stream is being captured into a graph
     uint64_t* pinned_totals = nullptr;
     bool device_used = false;
     UploadRing ring;
@@ -190,7 +241,7 @@ struct mvgs_context {
     void each_buffer(Fn fn) {
         DevBuf* bufs[] = {&nrec, &ntiles, &totals, &scan_scratch, &depth_key[0], &depth_key[1], &rec_vals[0],
                           &rec_vals[1], &tile_rect, &pair_counts, &pair_off, &sort_scratch, &acc,
-                          &loss_scratch, &ssim_maps, &work};
+                          &loss_scratch, &ssim_maps, &loss3d_scratch, &work};
         for (DevBuf* b : bufs) fn(*b);
         for (auto& sl : ring.slots) fn(sl.dev);
         for (mvgs_frame* f : frames) f->each_buffer(fn);
@@ -214,7 +265,7 @@ struct mvgs_context {
     }
     // returns a mark index (or -1 when profiling is off)
     int stage_begin(int stage, hipStream_t s) {
-        if (!prof) return -1;
+        if (!prof || capturing) return -1;
         Mark m{stage, take_event(), take_event()};
         if (!m.a || !m.b || hipEventRecord(m.a, s) != hipSuccess) return -1;
         marks.push_back(m);
@@ -224,12 +275,19 @@ struct mvgs_context {
         if (idx >= 0) (void)hipEventRecord(marks[idx].b, s);
     }
 
+    // called first by every call that enqueues work: notes whether the stream is being captured
+    bool begin(hipStream_t s) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        capturing = hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
+        return capturing;
+    }
+
     // first device use: remember the device, allocate the pinned readback slot
     hipError_t bind_device() {
         if (device_used) return hipSuccess;
         hipError_t e = hipGetDevice(&device);
         if (e != hipSuccess) return e;
-        e = hipHostMalloc((void**)&pinned_totals, 4 * sizeof(uint64_t), hipHostMallocDefault);
+        e = hipHostMalloc((void**)&pinned_totals, 8 * sizeof(uint64_t), hipHostMallocDefault);
         if (e != hipSuccess) return e;
         device_used = true;
         return hipSuccess;
@@ -259,14 +317,23 @@ struct Need {
 // Grows every listed buffer (each listed once) to its size, unless the context would then hold
 // more than its workspace limit: then nothing is allocated and MVGS_ECAPACITY is returned.
 int grow_all(mvgs_context* ctx, const Need* need, int count) {
+    if (ctx->capturing) {
+        for (int i = 0; i < count; ++i)
+            if (need[i].bytes && grown_capacity(*need[i].buf, need[i].bytes) != need[i].buf->cap)
+                return ctx->fail(MVGS_ECAPACITY, "the call would allocate device memory during stream capture: "
+                                                 "make the same call once before capturing");
+        return MVGS_OK;
+    }
     if (ctx->limit) {
         size_t planned = ctx->held();
-        for (int i = 0; i < count; ++i) planned += grown_capacity(*need[i].buf, need[i].bytes) - need[i].buf->cap;
+        for (int i = 0; i < count; ++i)
+            if (need[i].bytes) planned += grown_capacity(*need[i].buf, need[i].bytes) - need[i].buf->cap;
         if (planned > ctx->limit)
             return ctx->fail(MVGS_ECAPACITY, "the call needs the context to hold %zu device bytes; its limit is %zu",
                              planned, ctx->limit);
     }
     for (int i = 0; i < count; ++i) {
+        if (!need[i].bytes) continue;
         hipError_t e = ensure(*need[i].buf, need[i].bytes);
         if (e != hipSuccess) return ctx->hip_fail(e, "workspace allocation");
     }
@@ -402,15 +469,19 @@ int mvgs_create(mvgs_context** out, const mvgs_options* opt) {
     if (!out) return MVGS_EINVAL;
     *out = nullptr;
     int tw = 16, th = 16, ppl = 0;
-    int64_t limit = 0;
+    int64_t limit = 0, cap_v = 0, cap_k = 0;
     if (opt) {
         if (opt->tile_w) tw = opt->tile_w;
         if (opt->tile_h) th = opt->tile_h;
         ppl = opt->pixels_per_lane;
         limit = opt->workspace_limit;
-        if (opt->reserved0 || opt->reserved[0] || opt->reserved[1]) return MVGS_EINVAL;
+        cap_v = opt->capacity_records;
+        cap_k = opt->capacity_pairs;
+        if (opt->reserved0) return MVGS_EINVAL;
     }
-    if (limit < 0) return MVGS_EINVAL;
+    if (limit < 0 || cap_v < 0 || cap_k < 0 || (cap_v == 0) != (cap_k == 0) || cap_v >= (1ll << 32) ||
+        cap_k >= (1ll << 32))
+        return MVGS_EINVAL;
     if (ppl == 0) ppl = blend_default_ppl(tw, th);
     if (!blend_supported(tw, th, ppl)) return MVGS_EINVAL;
     mvgs_context* ctx = new (std::nothrow) mvgs_context();
@@ -419,6 +490,8 @@ int mvgs_create(mvgs_context** out, const mvgs_options* opt) {
     ctx->th = th;
     ctx->ppl = ppl;
     ctx->limit = (size_t)limit;
+    ctx->cap_v = (uint64_t)cap_v;
+    ctx->cap_k = (uint64_t)cap_k;
     // no HIP call here: device resources are created by the first call that needs them
     *out = ctx;
     return MVGS_OK;
@@ -456,6 +529,7 @@ SelBlendArgs sel_args(mvgs_frame* f) {
     sa.n_tasks = f->n_tasks;
     sa.t_sel = as<float>(f->t_final);
     sa.last_sel = as<uint32_t>(f->n_last);
+    sa.depth_sel = as<float>(f->depth);
     return sa;
 }
 
@@ -482,6 +556,11 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
 
     hipStream_t s = (hipStream_t)stream;
     const int tw = ctx->tw, th = ctx->th;
+    const bool cap = ctx->cap_v > 0;
+    if (cap && sel) return ctx->fail(MVGS_EINVAL, "partial rendering needs a context without capacities");
+    if (ctx->begin(s) && (!cap || !ctx->device_used))
+        return ctx->fail(MVGS_EINVAL, "a forward can be captured only on a context with capacities, after one "
+                                      "call outside the capture");
     HIPCHK(ctx, ctx->bind_device());
     mvgs_frame* f = acquire_frame(ctx);
     if (!f) return ctx->fail(MVGS_ENOMEM, "frame allocation failed");
@@ -493,6 +572,10 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     f->mode = sel ? sel->mode : kModeFull;
     f->n_sel = sel ? sel->n_sel : 0;
     f->n_tasks = 0;
+    f->partition = false;
+    f->capacity = cap;
+    f->checked = !cap;
+    f->cam_stage = nullptr;
     build_cams(cams, B, tw, th, f->hcams);
     const GaussianArgs ga = gargs(g);
     const size_t P = (size_t)g->P;
@@ -511,10 +594,16 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     // tasks of thread-efficient partial rendering: at most one per segment plus one per 64 pixels
     const size_t task_cap = sel ? (size_t)n_tiles + sel->n_sel / 64 + 1 : 0;
     const size_t mask_words = ((size_t)n_pixels + 31) / 32;
+    bool same_size = true;
+    for (int v = 1; v < B; ++v)
+        same_size = same_size && cams[v].width == cams[0].width && cams[v].height == cams[0].height;
+    const size_t plane_words = ((size_t)cams[0].width * cams[0].height + 31) / 32;
+    const bool want_plane = sel && same_size;
     const Need need1[] = {{&f->cams, sizeof(DevCam) * B},
                           {&ctx->nrec, sizeof(uint32_t) * (P + 1)},
                           {&ctx->ntiles, sizeof(uint32_t) * (P + 1)},
                           {&ctx->totals, sizeof(uint64_t) * 4},
+                          {&f->dtot, cap ? (size_t)64 : (size_t)0},
                           {&f->rec_off, sizeof(uint32_t) * (P + 1)},
                           {&ctx->scan_scratch, scan_scratch_bytes(std::max<size_t>(P + 1, n_tiles))},
                           {&f->sel_off, sel ? sizeof(uint32_t) * ((size_t)n_tiles + 1) : 0},
@@ -522,17 +611,18 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
                           {&f->mask, sel ? sizeof(uint32_t) * mask_words : 0},
                           {&f->task_n, sel ? sizeof(uint32_t) * n_tiles : 0},
                           {&f->task_off, sel ? sizeof(uint32_t) * n_tiles : 0},
-                          {&f->tasks, sel ? sizeof(uint2) * task_cap : 0}};
-    const int n_need1 = sel ? 12 : 6;
+                          {&f->tasks, sel ? sizeof(uint2) * task_cap : 0},
+                          {&f->plane_mask, want_plane ? sizeof(uint32_t) * plane_words : 0}};
+    const int n_need1 = 14;
     st = grow_all(ctx, need1, n_need1);
     if (st) return bail(st);
     if (fresh_totals) fill_u32(as<uint32_t>(ctx->totals), 8, 0u, s);
     void* img_ptrs = nullptr;
     {
         void* dcams = nullptr;
-        FCHK(ctx->ring.put(f->hcams.data(), sizeof(DevCam) * B, s, &dcams));
+        FCHK(ctx->ring.put(f->hcams.data(), sizeof(DevCam) * B, s, &dcams, ctx->capturing, &f->cam_stage));
         FCHK(hipMemcpyAsync(f->cams.p, dcams, sizeof(DevCam) * B, hipMemcpyDeviceToDevice, s));
-        FCHK(ctx->ring.put(images, sizeof(float*) * B, s, &img_ptrs));
+        FCHK(ctx->ring.put(images, sizeof(float*) * B, s, &img_ptrs, ctx->capturing));
     }
     const DevCam* dcam = as<DevCam>(f->cams);
 
@@ -551,11 +641,13 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
         if (sel->n_sel) FCHK(hipMemcpyAsync(f->sel_pix.p, sel->pix, sizeof(uint32_t) * sel->n_sel,
                                             hipMemcpyDeviceToDevice, s));
         fill_u32(as<uint32_t>(f->mask), mask_words, 0u, s);
+        if (want_plane) fill_u32(as<uint32_t>(f->plane_mask), plane_words, 0u, s);
         fill_u32(sel_err, 1, 0u, s);
         fill_u32(reinterpret_cast<uint32_t*>(as<uint64_t>(ctx->totals) + 3), 2, 0u, s);
         if (n_tiles) {
             launch_sel_check(dcam, B, n_tiles, tw, th, as<uint32_t>(f->sel_off), as<uint32_t>(f->sel_pix),
-                             sel->n_sel, as<uint32_t>(f->mask), as<uint32_t>(f->task_n), sel_err, s);
+                             sel->n_sel, as<uint32_t>(f->mask), want_plane ? as<uint32_t>(f->plane_mask) : nullptr,
+                             as<uint32_t>(f->task_n), sel_err, s);
             scan_exclusive_u32(as<uint32_t>(f->task_n), as<uint32_t>(f->task_off), n_tiles,
                                as<uint64_t>(ctx->totals) + 3, ctx->scan_scratch.p, s);
             launch_sel_tasks(n_tiles, as<uint32_t>(f->task_n), as<uint32_t>(f->task_off), (uint32_t)task_cap,
@@ -564,41 +656,57 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     }
     ctx->stage_end(mk, s);
     FCHK(hipGetLastError());
-    FCHK(hipMemcpyAsync(ctx->pinned_totals, ctx->totals.p, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    FCHK(hipStreamSynchronize(s));
-    const uint64_t V64 = ctx->pinned_totals[0], K64 = ctx->pinned_totals[1];
-    if (sel) {
-        const uint32_t e = (uint32_t)(ctx->pinned_totals[2] >> 32);
-        if (e) {
-            (void)ctx->ring.seal(s);
-            return bail(ctx->fail(MVGS_EINVAL, "pixel selection rejected:%s%s%s%s",
-                                  (e & kSelBadOffsets) ? " offsets do not rise from 0 to n_sel;" : "",
-                                  (e & kSelTooLong) ? " a segment holds more pixels than a tile;" : "",
-                                  (e & kSelOutside) ? " a pixel lies outside its (view, tile);" : "",
-                                  (e & kSelDuplicate) ? " a pixel is selected twice;" : ""));
+    uint64_t V64 = ctx->cap_v, K64 = ctx->cap_k;
+    const uint32_t* eff = nullptr;   // capacity mode: device (records, pairs) of this call
+    const uint32_t* ovf = nullptr;   // capacity mode: device overflow word
+    if (cap) {
+        uint32_t* e32 = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(f->dtot.p) + 32);
+        launch_capacity_clamp(as<uint64_t>(ctx->totals), ctx->cap_v, ctx->cap_k, e32, e32 + 2, s);
+        eff = e32;
+        ovf = e32 + 2;
+        f->V = 0;
+        f->K = 0;
+    } else {
+        FCHK(hipMemcpyAsync(ctx->pinned_totals, ctx->totals.p, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        FCHK(hipStreamSynchronize(s));
+        V64 = ctx->pinned_totals[0];
+        K64 = ctx->pinned_totals[1];
+        if (sel) {
+            const uint32_t e = (uint32_t)(ctx->pinned_totals[2] >> 32);
+            f->partition = want_plane && !(e & kSelPlaneOverlap) &&
+                           (uint64_t)sel->n_sel == (uint64_t)cams[0].width * (uint64_t)cams[0].height;
+            if (e & kSelErrors) {
+                (void)ctx->ring.seal(s);
+                return bail(ctx->fail(MVGS_EINVAL, "pixel selection rejected:%s%s%s%s",
+                                      (e & kSelBadOffsets) ? " offsets do not rise from 0 to n_sel;" : "",
+                                      (e & kSelTooLong) ? " a segment holds more pixels than a tile;" : "",
+                                      (e & kSelOutside) ? " a pixel lies outside its (view, tile);" : "",
+                                      (e & kSelDuplicate) ? " a pixel is selected twice;" : ""));
+            }
+            const uint64_t nt = ctx->pinned_totals[3];
+            if (nt > task_cap) {
+                (void)ctx->ring.seal(s);
+                return bail(ctx->fail(MVGS_EHIP, "selection tasks %llu exceed their bound", (unsigned long long)nt));
+            }
+            f->n_tasks = (uint32_t)nt;
         }
-        const uint64_t nt = ctx->pinned_totals[3];
-        if (nt > task_cap) {
+        if ((uint32_t)ctx->pinned_totals[2] != 0) {
+            // a sort of an earlier call on this context timed out in its look-back (never expected)
+            fill_u32(reinterpret_cast<uint32_t*>(as<uint64_t>(ctx->totals) + 2), 2, 0u, s);
             (void)ctx->ring.seal(s);
-            return bail(ctx->fail(MVGS_EHIP, "selection tasks %llu exceed their bound", (unsigned long long)nt));
+            return bail(ctx->fail(MVGS_EHIP, "radix sort look-back timed out in an earlier call on this context"));
         }
-        f->n_tasks = (uint32_t)nt;
+        if (V64 >= (1ull << 32) || K64 >= (1ull << 32)) {
+            (void)ctx->ring.seal(s);
+            return bail(ctx->fail(MVGS_ECAPACITY, "records %llu or pairs %llu reach 2^32", (unsigned long long)V64,
+                                  (unsigned long long)K64));
+        }
+        f->V = (uint32_t)V64;
+        f->K = (uint32_t)K64;
     }
-    if ((uint32_t)ctx->pinned_totals[2] != 0) {
-        // a sort of an earlier call on this context timed out in its look-back (never expected)
-        fill_u32(reinterpret_cast<uint32_t*>(as<uint64_t>(ctx->totals) + 2), 2, 0u, s);
-        (void)ctx->ring.seal(s);
-        return bail(ctx->fail(MVGS_EHIP, "radix sort look-back timed out in an earlier call on this context"));
-    }
-    if (V64 >= (1ull << 32) || K64 >= (1ull << 32)) {
-        // (unreachable for the selection checks above: they ran first)
-        (void)ctx->ring.seal(s);
-        return bail(ctx->fail(MVGS_ECAPACITY, "records %llu or pairs %llu reach 2^32", (unsigned long long)V64,
-                              (unsigned long long)K64));
-    }
+    // exact sizes, or in capacity mode the capacities (grids are then sized by them and the
+    // kernels read the actual counts from eff)
     const uint32_t V = (uint32_t)V64, K = (uint32_t)K64;
-    f->V = V;
-    f->K = K;
 
     // records and the depth sort
     const size_t V1 = std::max<uint32_t>(V, 1), K1 = std::max<uint32_t>(K, 1);
@@ -620,6 +728,8 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
                           {&f->ranges, sizeof(uint2) * std::max<uint32_t>(n_tiles, 1)},
                           {&f->t_final, sizeof(float) * std::max<size_t>(n_px_state, 1)},
                           {&f->n_last, sizeof(uint32_t) * std::max<size_t>(n_px_state, 1)},
+                          {&f->depth, (sel && sel->mode == MVGS_PARTIAL_COMPACT)
+                                          ? sizeof(float) * std::max<size_t>(sel->n_sel, 1) : (size_t)0},
                           {&ctx->sort_scratch,
                            std::max(radix_scratch_bytes(std::max<size_t>(V, K)), scan_scratch_bytes(V))}};
     const int n_need2 = (int)(sizeof(need2) / sizeof(need2[0]));
@@ -632,31 +742,32 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
 
     mk = ctx->stage_begin(1, s);
     launch_records(ga, dcam, B, tw, th, as<uint32_t>(f->rec_off), as<BlendRec>(f->recs),
-                   as<uint32_t>(ctx->depth_key[0]), as<uint4>(ctx->tile_rect), as<uint16_t>(f->rec_view), s);
+                   as<uint32_t>(ctx->depth_key[0]), as<uint4>(ctx->tile_rect), as<uint16_t>(f->rec_view), s, ovf);
     ctx->stage_end(mk, s);
     mk = ctx->stage_begin(2, s);
     uint32_t* dk[2] = {as<uint32_t>(ctx->depth_key[0]), as<uint32_t>(ctx->depth_key[1])};
     uint32_t* dv[2] = {as<uint32_t>(ctx->rec_vals[0]), as<uint32_t>(ctx->rec_vals[1])};
     uint32_t* sort_err = reinterpret_cast<uint32_t*>(as<uint64_t>(ctx->totals) + 2);
-    const int dcur = radix_sort_u32(dk, dv, true, V, 32, ctx->sort_scratch.p, sort_err, s);
+    const int dcur = radix_sort_u32(dk, dv, true, V, 32, ctx->sort_scratch.p, sort_err, s, eff);
     const uint32_t* sorted_rec = dv[dcur];
     ctx->stage_end(mk, s);
 
     // pairs in depth order, then a stable sort by global tile id
     mk = ctx->stage_begin(3, s);
-    launch_gather_tile_counts(sorted_rec, as<uint4>(ctx->tile_rect), V, as<uint32_t>(ctx->pair_counts), s);
+    launch_gather_tile_counts(sorted_rec, as<uint4>(ctx->tile_rect), V, as<uint32_t>(ctx->pair_counts), s, eff);
     scan_exclusive_u32(as<uint32_t>(ctx->pair_counts), as<uint32_t>(ctx->pair_off), V, nullptr,
-                       ctx->sort_scratch.p, s);
-    launch_emit_pairs(sorted_rec, as<uint4>(ctx->tile_rect),
-                      as<uint32_t>(ctx->pair_off), V, K, as<uint32_t>(f->keys[0]), as<uint32_t>(f->vals[0]), s);
+                       ctx->sort_scratch.p, s, eff);
+    launch_emit_pairs(sorted_rec, as<uint4>(ctx->tile_rect), as<uint32_t>(ctx->pair_off), V, K,
+                      as<uint32_t>(f->keys[0]), as<uint32_t>(f->vals[0]), s, eff);
     ctx->stage_end(mk, s);
     mk = ctx->stage_begin(4, s);
     uint32_t* pk[2] = {as<uint32_t>(f->keys[0]), as<uint32_t>(f->keys[1])};
     uint32_t* pv[2] = {as<uint32_t>(f->vals[0]), as<uint32_t>(f->vals[1])};
-    f->final_buf = radix_sort_u32(pk, pv, false, K, bits_for(n_tiles), ctx->sort_scratch.p, sort_err, s);
+    f->final_buf = radix_sort_u32(pk, pv, false, K, bits_for(n_tiles), ctx->sort_scratch.p, sort_err, s,
+                                  eff ? eff + 1 : nullptr);
     ctx->stage_end(mk, s);
     mk = ctx->stage_begin(5, s);
-    launch_ranges(pk[f->final_buf], K, n_tiles, as<uint2>(f->ranges), s);
+    launch_ranges(pk[f->final_buf], K, n_tiles, as<uint2>(f->ranges), s, eff ? eff + 1 : nullptr);
     ctx->stage_end(mk, s);
 
     // blend every pixel of every view
@@ -680,6 +791,8 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
         launch_blend_fwd(a, tw, th, ctx->ppl, s);
     }
     ctx->stage_end(mk, s);
+    if (cap)  // this call's totals and error words, for mvgs_frame_check
+        FCHK(hipMemcpyAsync(f->dtot.p, ctx->totals.p, 3 * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
     FCHK(hipGetLastError());
     FCHK(ctx->ring.seal(s));
     *frame = f;
@@ -720,6 +833,7 @@ int mvgs_subsample(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int
                              cams[v].width, cams[v].height, cams[0].width, cams[0].height);
     if (!keys || !sel_offsets || !sel_pixels) return ctx->fail(MVGS_EINVAL, "a sub-sampling buffer is NULL");
     hipStream_t s = (hipStream_t)stream;
+    ctx->begin(s);
     HIPCHK(ctx, ctx->bind_device());
     const Need need[] = {{&ctx->scan_scratch, scan_scratch_bytes(n_tiles)}};
     st = grow_all(ctx, need, 1);
@@ -754,18 +868,63 @@ int mvgs_loss(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t 
         max_hw = std::max(max_hw, hw);
     }
     hipStream_t s = (hipStream_t)stream;
+    if (ctx->begin(s) && !ctx->device_used)
+        return ctx->fail(MVGS_EINVAL, "make the call once before capturing it");
     HIPCHK(ctx, ctx->bind_device());
     const Need need[] = {{&ctx->loss_scratch, loss_scratch_bytes(n_pixels, B)},
                          {&ctx->ssim_maps, w_dssim != 0.0f ? ssim_map_bytes(max_hw) : 0}};
     st = grow_all(ctx, need, w_dssim != 0.0f ? 2 : 1);
     if (st) return st;
     void* dviews = nullptr;
-    HIPCHK(ctx, ctx->ring.put(lv.data(), sizeof(LossView) * B, s, &dviews));
+    HIPCHK(ctx, ctx->ring.put(lv.data(), sizeof(LossView) * B, s, &dviews, ctx->capturing));
     const int mk = ctx->stage_begin(7, s);
     launch_loss((const LossView*)dviews, lv.data(), B, n_pixels, w_l1, w_dssim, loss_dev, ctx->loss_scratch.p,
                 ctx->ssim_maps.p, s);
     ctx->stage_end(mk, s);
     LAUNCHCHK(ctx, "loss kernels");
+    HIPCHK(ctx, ctx->ring.seal(s));
+    return MVGS_OK;
+}
+
+int mvgs_loss_3d(mvgs_context* ctx, void* stream, const mvgs_frame* frame, const float* image, const float* target,
+                 float w_l1, float w_dssim, float* loss_dev, float* dl_dimage) {
+    if (!ctx) return MVGS_EINVAL;
+    if (!frame || frame->ctx != ctx || !frame->in_use) return ctx->fail(MVGS_EINVAL, "frame is not live on this context");
+    if (frame->mode != MVGS_PARTIAL_COMPACT || !frame->partition)
+        return ctx->fail(MVGS_EINVAL, "the 3D loss needs a thread-efficient partial frame whose selection covers the "
+                                      "views' image plane once (as mvgs_subsample makes)");
+    if (!image || !target || !loss_dev || !dl_dimage) return ctx->fail(MVGS_EINVAL, "a loss buffer is NULL");
+    if (!std::isfinite(w_l1) || !std::isfinite(w_dssim)) return ctx->fail(MVGS_EINVAL, "loss weights must be finite");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->begin(s);
+    mvgs_frame* f = const_cast<mvgs_frame*>(frame);
+    const int W = f->hcams[0].W, H = f->hcams[0].H;
+    const Need need[] = {{&ctx->loss3d_scratch, loss3d_scratch_bytes(W, H)}};
+    int st = grow_all(ctx, need, 1);
+    if (st) return st;
+    const int mk = ctx->stage_begin(7, s);
+    launch_loss3d(as<DevCam>(f->cams), f->B, f->n_tiles, as<uint32_t>(f->sel_off), as<uint32_t>(f->sel_pix),
+                  as<float>(f->t_final), as<float>(f->depth), W, H, image, target, w_l1, w_dssim, loss_dev, dl_dimage,
+                  ctx->loss3d_scratch.p, s);
+    ctx->stage_end(mk, s);
+    LAUNCHCHK(ctx, "3D loss kernels");
+    return MVGS_OK;
+}
+
+int mvgs_export_depth(mvgs_context* ctx, void* stream, const mvgs_frame* frame, float* const* depth) {
+    if (!ctx || !frame || frame->ctx != ctx || !frame->in_use || !depth) return MVGS_EINVAL;
+    if (frame->mode != MVGS_PARTIAL_COMPACT)
+        return ctx->fail(MVGS_EINVAL, "depth is rendered by thread-efficient partial frames only");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->begin(s);
+    mvgs_frame* f = const_cast<mvgs_frame*>(frame);
+    for (int v = 0; v < f->B; ++v)
+        if (!depth[v]) return ctx->fail(MVGS_EINVAL, "depth[%d] is NULL", v);
+    void* dptrs = nullptr;
+    HIPCHK(ctx, ctx->ring.put(depth, sizeof(float*) * f->B, s, &dptrs, ctx->capturing));
+    launch_sel_scatter(as<DevCam>(f->cams), f->B, f->n_tiles, as<uint32_t>(f->sel_off), as<uint32_t>(f->sel_pix),
+                       as<float>(f->depth), (float* const*)dptrs, s);
+    LAUNCHCHK(ctx, "depth scatter");
     HIPCHK(ctx, ctx->ring.seal(s));
     return MVGS_OK;
 }
@@ -786,14 +945,19 @@ int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, cons
     if (densify && (!densify->e1 || !densify->e2 || !densify->count))
         return ctx->fail(MVGS_EINVAL, "a densify pointer is NULL");
     hipStream_t s = (hipStream_t)stream;
+    ctx->begin(s);
     mvgs_frame* f = const_cast<mvgs_frame*>(frame);
-    const uint32_t V = f->V;
+    // records: exact, or in capacity mode bounded by the capacity with the count on the device
+    const uint32_t V = f->capacity ? (uint32_t)ctx->cap_v : f->V;
+    const uint32_t* eff = f->capacity ? reinterpret_cast<const uint32_t*>(static_cast<uint8_t*>(f->dtot.p) + 32)
+                                      : nullptr;
+    const uint32_t* ovf = eff ? eff + 2 : nullptr;
     const Need need[] = {{&ctx->acc, sizeof(float) * kAccStride * std::max<uint32_t>(V, 1)}};
     st = grow_all(ctx, need, 1);
     if (st) return st;
-    fill_u32(as<uint32_t>(ctx->acc), (size_t)kAccStride * V, 0u, s);
+    fill_u32_count(as<uint32_t>(ctx->acc), V, eff, kAccStride, 0u, s);
     void* dptrs = nullptr;
-    HIPCHK(ctx, ctx->ring.put(dl_dimages, sizeof(float*) * f->B, s, &dptrs));
+    HIPCHK(ctx, ctx->ring.put(dl_dimages, sizeof(float*) * f->B, s, &dptrs, ctx->capturing));
     BlendBwdArgs a;
     a.cams = as<DevCam>(f->cams);
     a.B = f->B;
@@ -829,7 +993,7 @@ int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, cons
     gr.count = densify ? densify->count : nullptr;
     mk = ctx->stage_begin(9, s);
     launch_preprocess_bwd(gargs(g), as<DevCam>(f->cams), as<uint32_t>(f->rec_off), as<uint16_t>(f->rec_view),
-                          as<float>(ctx->acc), gr, s);
+                          as<float>(ctx->acc), gr, s, ovf);
     ctx->stage_end(mk, s);
     LAUNCHCHK(ctx, "backward kernels");
     HIPCHK(ctx, ctx->ring.seal(s));
@@ -860,6 +1024,46 @@ int mvgs_frame_workspace(const mvgs_frame* frame, int64_t* bytes) {
     return MVGS_OK;
 }
 
+int mvgs_frame_check(mvgs_context* ctx, void* stream, mvgs_frame* frame) {
+    if (!ctx || !frame || frame->ctx != ctx || !frame->in_use) return MVGS_EINVAL;
+    if (!frame->capacity) return MVGS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (ctx->begin(s)) return ctx->fail(MVGS_EINVAL, "mvgs_frame_check synchronizes and cannot be captured");
+    HIPCHK(ctx, hipMemcpyAsync(ctx->pinned_totals, frame->dtot.p, 48, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    const uint64_t V = ctx->pinned_totals[0], K = ctx->pinned_totals[1];
+    const uint32_t* e32 = reinterpret_cast<const uint32_t*>(ctx->pinned_totals + 4);
+    if ((uint32_t)ctx->pinned_totals[2] != 0) {
+        fill_u32(reinterpret_cast<uint32_t*>(as<uint64_t>(ctx->totals) + 2), 2, 0u, s);
+        return ctx->fail(MVGS_EHIP, "radix sort look-back timed out");
+    }
+    if (e32[2]) {
+        frame->checked = false;
+        return ctx->fail(MVGS_ECAPACITY, "%llu records and %llu pairs exceed the capacities %llu and %llu",
+                         (unsigned long long)V, (unsigned long long)K, (unsigned long long)ctx->cap_v,
+                         (unsigned long long)ctx->cap_k);
+    }
+    frame->V = (uint32_t)V;
+    frame->K = (uint32_t)K;
+    frame->checked = true;
+    return MVGS_OK;
+}
+
+int mvgs_frame_set_cameras(mvgs_context* ctx, mvgs_frame* frame, const mvgs_camera* cams, int32_t B) {
+    if (!ctx || !frame || frame->ctx != ctx || !frame->in_use) return MVGS_EINVAL;
+    if (!frame->cam_stage) return ctx->fail(MVGS_EINVAL, "the frame was not made under stream capture");
+    if (!cams || B != frame->B) return ctx->fail(MVGS_EINVAL, "expected %d cameras", frame->B);
+    uint32_t n_tiles = 0, n_pixels = 0;
+    int st = validate_cams(ctx, cams, B, ctx->tw, ctx->th, &n_tiles, &n_pixels);
+    if (st) return st;
+    for (int v = 0; v < B; ++v)
+        if (cams[v].width != frame->hcams[v].W || cams[v].height != frame->hcams[v].H)
+            return ctx->fail(MVGS_EINVAL, "view %d changes size: a captured graph keeps its sizes", v);
+    build_cams(cams, B, ctx->tw, ctx->th, frame->hcams);
+    memcpy(frame->cam_stage, frame->hcams.data(), sizeof(DevCam) * B);
+    return MVGS_OK;
+}
+
 int mvgs_frame_info(const mvgs_frame* frame, int64_t* n_records, int64_t* n_pairs, int64_t* n_tiles) {
     if (!frame) return MVGS_EINVAL;
     if (n_records) *n_records = frame->V;
@@ -871,6 +1075,7 @@ int mvgs_frame_info(const mvgs_frame* frame, int64_t* n_records, int64_t* n_pair
 int mvgs_export_binning(mvgs_context* ctx, void* stream, const mvgs_frame* frame, uint64_t* keys, uint32_t* values,
                         uint32_t* ranges) {
     if (!ctx || !frame || frame->ctx != ctx || !frame->in_use) return MVGS_EINVAL;
+    if (!frame->checked) return ctx->fail(MVGS_EINVAL, "call mvgs_frame_check on a capacity-mode frame first");
     hipStream_t s = (hipStream_t)stream;
     mvgs_frame* f = const_cast<mvgs_frame*>(frame);
     if (keys || values)
@@ -891,7 +1096,7 @@ int mvgs_export_transmittance(mvgs_context* ctx, void* stream, const mvgs_frame*
     if (f->mode == MVGS_PARTIAL_COMPACT) {
         void* dptrs = nullptr;
         HIPCHK(ctx, ctx->ring.put(t_final, sizeof(float*) * f->B, s, &dptrs));
-        launch_sel_scatter_t(as<DevCam>(f->cams), f->B, f->n_tiles, as<uint32_t>(f->sel_off),
+        launch_sel_scatter(as<DevCam>(f->cams), f->B, f->n_tiles, as<uint32_t>(f->sel_off),
                              as<uint32_t>(f->sel_pix), as<float>(f->t_final), (float* const*)dptrs, s);
         LAUNCHCHK(ctx, "transmittance scatter");
         HIPCHK(ctx, ctx->ring.seal(s));

@@ -35,7 +35,7 @@ __device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp
 
 // Wavefront-uniform copy of the fields the walks use.
 struct RecS {
-    float mx, my, hca, nb, hcc, o, cut, hi, r, g, b;
+    float mx, my, hca, nb, hcc, o, cut, hi, r, g, b, z;
 };
 
 __device__ __forceinline__ RecS load_rec(const BlendRec* __restrict__ recs, uint32_t r) {
@@ -43,6 +43,7 @@ __device__ __forceinline__ RecS load_rec(const BlendRec* __restrict__ recs, uint
     RecS s;
     s.mx = R->mx; s.my = R->my; s.hca = R->hca; s.nb = R->nb; s.hcc = R->hcc; s.o = R->o;
     s.cut = R->cut; s.hi = R->hi; s.r = R->r; s.g = R->g; s.b = R->b;
+    s.z = __uint_as_float(R->depth_bits);
     return s;
 }
 
@@ -122,8 +123,12 @@ struct FwdPix {
     float T, C0, C1, C2;
     uint32_t last;
     bool done;
+    float D;   // blended camera-space depth (accumulated only where asked for)
 };
 
+// One Gaussian of Eq. 1 for one pixel (skipped when the pixel has stopped or the cut test fails;
+// the branches cost less than computing every step for every lane).
+template <bool DEPTH>
 __device__ __forceinline__ void blend_step(FwdPix& st, const RecS& q, float px, float py, uint32_t pos) {
     if (st.done) return;
     const float power = pixel_power(px, py, q.mx, q.my, q.hca, q.nb, q.hcc);
@@ -137,6 +142,7 @@ __device__ __forceinline__ void blend_step(FwdPix& st, const RecS& q, float px, 
             st.C0 = __builtin_fmaf(q.r, w, st.C0);
             st.C1 = __builtin_fmaf(q.g, w, st.C1);
             st.C2 = __builtin_fmaf(q.b, w, st.C2);
+            if (DEPTH) st.D = __builtin_fmaf(q.z, w, st.D);
             st.T = Tn;
             st.last = pos + 1;
         }
@@ -274,7 +280,7 @@ __device__ __forceinline__ void unblend_step(BwdPix (&st)[PPL], const RecS& q, u
 // Front-to-back walk of one wavefront over the sorted list [rg.x, rg.y) of its (view, tile): each
 // lane blends its PPL pixels (px, py[k]); candidates are culled against the pixel rectangle
 // [sx0, sx1] x [sy0, sy1] that holds every pixel of the wavefront. Ends when all lanes stopped.
-template <int PPL>
+template <int PPL, bool DEPTH = false>
 __device__ __forceinline__ void walk_forward(FwdPix (&st)[PPL], float px, const float (&py)[PPL], uint2 rg,
                                              const uint32_t* __restrict__ vals, const BlendRec* __restrict__ recs,
                                              int lane, int sx0, int sx1, int sy0, int sy1) {
@@ -303,18 +309,18 @@ __device__ __forceinline__ void walk_forward(FwdPix (&st)[PPL], float px, const 
             const RecS q2 = load_rec(recs, readlane_u32(rl, j2));
             const RecS q3 = load_rec(recs, readlane_u32(rl, j3));
 #pragma unroll
-            for (int k = 0; k < PPL; ++k) blend_step(st[k], q0, px, py[k], base + (uint32_t)j0);
+            for (int k = 0; k < PPL; ++k) blend_step<DEPTH>(st[k], q0, px, py[k], base + (uint32_t)j0);
             if (h1) {
 #pragma unroll
-                for (int k = 0; k < PPL; ++k) blend_step(st[k], q1, px, py[k], base + (uint32_t)j1);
+                for (int k = 0; k < PPL; ++k) blend_step<DEPTH>(st[k], q1, px, py[k], base + (uint32_t)j1);
             }
             if (h2) {
 #pragma unroll
-                for (int k = 0; k < PPL; ++k) blend_step(st[k], q2, px, py[k], base + (uint32_t)j2);
+                for (int k = 0; k < PPL; ++k) blend_step<DEPTH>(st[k], q2, px, py[k], base + (uint32_t)j2);
             }
             if (h3) {
 #pragma unroll
-                for (int k = 0; k < PPL; ++k) blend_step(st[k], q3, px, py[k], base + (uint32_t)j3);
+                for (int k = 0; k < PPL; ++k) blend_step<DEPTH>(st[k], q3, px, py[k], base + (uint32_t)j3);
             }
         }
     }

@@ -52,6 +52,8 @@ __device__ __forceinline__ WaveTile wave_tile(const DevCam* __restrict__ cams, i
     return w;
 }
 
+constexpr uint32_t kUnselected = 0xffffffffu;
+
 // Whether pixel (x, y) of view c is rendered: inside the image and, when a selection mask (one bit
 // per pixel of the batch, at pix_base + y W + x) is given, selected.
 __device__ __forceinline__ bool pixel_selected(const DevCam& c, int x, int y, const uint32_t* __restrict__ mask) {
@@ -79,15 +81,57 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_fwd(const DevCam* __res
     const float px = (float)x + 0.5f;
     float py[PPL];
     FwdPix st[PPL];
-    bool sel[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int y = wt.sy0 + (lane / ST::SW) + ST::ROWS * k;
         py[k] = (float)y + 0.5f;
-        sel[k] = pixel_selected(c, x, y, mask);
-        st[k] = FwdPix{1.0f, 0.0f, 0.0f, 0.0f, 0u, !sel[k]};
+        // an unselected pixel starts stopped, marked by an impossible last contributor, so the
+        // mask is not needed again after the walk (it would hold scalar registers the walk uses)
+        const bool sel = pixel_selected(c, x, y, mask);
+        st[k] = FwdPix{1.0f, 0.0f, 0.0f, 0.0f, sel ? 0u : kUnselected, !sel, 0.0f};
     }
-    walk_forward<PPL>(st, px, py, wt.rg, vals, recs, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1);
+    // The walk of walk_forward, written out here: with the call, the compiler optimises the loop
+    // apart from this kernel and the kernel runs out of scalar registers.
+    for (uint32_t base = wt.rg.x; base < wt.rg.y; base += 64) {
+        bool live = false;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) live |= !st[k].done;
+        if (ballot64(live) == 0) break;
+        uint32_t rl;
+        uint64_t m = window_mask(vals, recs, base, wt.rg.y, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1, rl);
+        while (m) {
+            // up to four records per round trip through the scalar cache
+            const int j0 = __builtin_ctzll(m);
+            m &= m - 1;
+            const int j1 = m ? __builtin_ctzll(m) : j0;
+            if (m) m &= m - 1;
+            const bool h1 = j1 != j0;
+            const int j2 = m ? __builtin_ctzll(m) : j0;
+            if (m) m &= m - 1;
+            const bool h2 = j2 != j0;
+            const int j3 = m ? __builtin_ctzll(m) : j0;
+            if (m) m &= m - 1;
+            const bool h3 = j3 != j0;
+            const RecS q0 = load_rec(recs, readlane_u32(rl, j0));
+            const RecS q1 = load_rec(recs, readlane_u32(rl, j1));
+            const RecS q2 = load_rec(recs, readlane_u32(rl, j2));
+            const RecS q3 = load_rec(recs, readlane_u32(rl, j3));
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) blend_step<false>(st[k], q0, px, py[k], base + (uint32_t)j0);
+            if (h1) {
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) blend_step<false>(st[k], q1, px, py[k], base + (uint32_t)j1);
+            }
+            if (h2) {
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) blend_step<false>(st[k], q2, px, py[k], base + (uint32_t)j2);
+            }
+            if (h3) {
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) blend_step<false>(st[k], q3, px, py[k], base + (uint32_t)j3);
+            }
+        }
+    }
     const size_t hw = (size_t)c.W * c.H;
     float* img = images[wt.v];
 #pragma unroll
@@ -95,13 +139,14 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_fwd(const DevCam* __res
         const int y = wt.sy0 + (lane / ST::SW) + ST::ROWS * k;
         if (x < c.W && y < c.H) {
             const size_t pix = (size_t)y * c.W + x;
-            if (sel[k]) {
+            const bool sel = st[k].last != kUnselected;
+            if (sel) {
                 img[pix] = __builtin_fmaf(st[k].T, c.bg[0], st[k].C0);
                 img[hw + pix] = __builtin_fmaf(st[k].T, c.bg[1], st[k].C1);
                 img[2 * hw + pix] = __builtin_fmaf(st[k].T, c.bg[2], st[k].C2);
             }
             t_final[c.pix_base + pix] = st[k].T;
-            n_last[c.pix_base + pix] = st[k].last;
+            n_last[c.pix_base + pix] = sel ? st[k].last : 0u;
         }
     }
 }

@@ -18,12 +18,13 @@ namespace mvgs {
 
 // One thread per segment (plus one for the closing offset): offsets must rise from 0 to n_sel,
 // a segment holds at most one tile of pixels, every pixel lies in its (view, tile) and appears
-// once. Marks the pixels in `mask` (zeroed by the caller) and counts the segment's tasks.
+// once. Marks the pixels in `mask` (zeroed by the caller) and counts the segment's tasks. With
+// plane_mask (views of one size, zeroed), also notes whether two views take the same position.
 __global__ void __launch_bounds__(256) k_sel_check(const DevCam* __restrict__ cams, int B, uint32_t n_tiles,
                                                    int tw, int th, const uint32_t* __restrict__ sel_off,
                                                    const uint32_t* __restrict__ sel_pix, uint32_t n_sel,
-                                                   uint32_t* __restrict__ mask, uint32_t* __restrict__ n_tasks,
-                                                   uint32_t* __restrict__ err) {
+                                                   uint32_t* __restrict__ mask, uint32_t* __restrict__ plane_mask,
+                                                   uint32_t* __restrict__ n_tasks, uint32_t* __restrict__ err) {
     const uint32_t t = blockIdx.x * 256u + threadIdx.x;
     if (t > n_tiles) return;
     if (t == n_tiles) {
@@ -61,6 +62,11 @@ __global__ void __launch_bounds__(256) k_sel_check(const DevCam* __restrict__ ca
         }
         const uint32_t gp = c.pix_base + p, bit = 1u << (gp & 31u);
         if (atomicOr(mask + (gp >> 5), bit) & bit) bad |= kSelDuplicate;
+        // views of one size: is each position of the shared image plane taken by one view only?
+        if (plane_mask) {
+            const uint32_t pb = 1u << (p & 31u);
+            if (atomicOr(plane_mask + (p >> 5), pb) & pb) bad |= kSelPlaneOverlap;
+        }
     }
     if (bad) atomicOr(err, bad);
     n_tasks[t] = (cnt + 63u) / 64u;
@@ -118,14 +124,14 @@ __global__ void __launch_bounds__(64) k_blend_fwd_sel(const DevCam* __restrict__
                                                       const uint32_t* __restrict__ sel_pix,
                                                       const uint2* __restrict__ tasks, uint32_t n_tasks,
                                                       float* const* __restrict__ images, float* __restrict__ t_sel,
-                                                      uint32_t* __restrict__ last_sel) {
+                                                      uint32_t* __restrict__ last_sel, float* __restrict__ depth_sel) {
     const int lane = (int)threadIdx.x;
     const SelWave w = sel_wave(cams, B, ranges, sel_off, sel_pix, tasks, n_tasks, lane);
     const DevCam& c = cams[w.v];
     const float px = (float)w.x + 0.5f;
     const float py[1] = {(float)w.y + 0.5f};
-    FwdPix st[1] = {FwdPix{1.0f, 0.0f, 0.0f, 0.0f, 0u, !w.valid}};
-    walk_forward<1>(st, px, py, w.rg, vals, recs, lane, w.bx0, w.bx1, w.by0, w.by1);
+    FwdPix st[1] = {FwdPix{1.0f, 0.0f, 0.0f, 0.0f, 0u, !w.valid, 0.0f}};
+    walk_forward<1, true>(st, px, py, w.rg, vals, recs, lane, w.bx0, w.bx1, w.by0, w.by1);
     if (w.valid) {
         const size_t hw = (size_t)c.W * c.H, pix = (size_t)w.y * c.W + w.x;
         float* img = images[w.v];
@@ -134,6 +140,7 @@ __global__ void __launch_bounds__(64) k_blend_fwd_sel(const DevCam* __restrict__
         img[2 * hw + pix] = __builtin_fmaf(st[0].T, c.bg[2], st[0].C2);
         t_sel[w.i] = st[0].T;
         last_sel[w.i] = st[0].last;
+        depth_sel[w.i] = st[0].D;
     }
 }
 
@@ -181,13 +188,15 @@ __global__ void __launch_bounds__(256) k_subsample_counts(int W, int H, int B, i
 }
 
 // Sub-sampling, step 2: one workgroup per tile ranks the tile's positions by (key, position) in
-// LDS and writes position of rank r to entry r / B of view (r mod B)'s segment.
+// LDS; the position of rank r goes to view r mod B, and each view's positions are written in
+// ascending order (so the wavefronts of a segment cover compact bands of the tile).
 __global__ void __launch_bounds__(256) k_subsample_scatter(const uint32_t* __restrict__ keys, int W, int H, int B,
                                                            int tw, int th, int tiles_x, uint32_t tiles_per_view,
                                                            const uint32_t* __restrict__ sel_off,
                                                            uint32_t* __restrict__ sel_pix) {
     __shared__ uint32_t k_s[1024];
     __shared__ uint32_t p_s[1024];
+    __shared__ uint32_t v_s[1024];
     const uint32_t t = blockIdx.x;
     const int ty = (int)(t / (uint32_t)tiles_x), tx = (int)t - ty * tiles_x;
     const int x0 = tx * tw, y0 = ty * th;
@@ -206,20 +215,17 @@ __global__ void __launch_bounds__(256) k_subsample_scatter(const uint32_t* __res
             const uint32_t km = k_s[m];
             r += (km < kj || (km == kj && p_s[m] < pj)) ? 1u : 0u;
         }
-        const uint32_t v = r % (uint32_t)B;
-        sel_pix[sel_off[v * tiles_per_view + t] + r / (uint32_t)B] = pj;
+        v_s[j] = r % (uint32_t)B;
     }
-}
-
-// Final transmittance of selected pixels into per-view [H, W] planes (other pixels untouched).
-__global__ void __launch_bounds__(256) k_sel_scatter_t(const DevCam* __restrict__ cams, int B, uint32_t n_tiles,
-                                                       const uint32_t* __restrict__ sel_off,
-                                                       const uint32_t* __restrict__ sel_pix,
-                                                       const float* __restrict__ t_sel, float* const* __restrict__ out) {
-    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
-    if (t >= n_tiles) return;
-    float* o = out[find_view(cams, B, t)];
-    for (uint32_t i = sel_off[t]; i < sel_off[t + 1]; ++i) o[sel_pix[i]] = t_sel[i];
+    __syncthreads();
+    // positions j are in ascending order (row-major inside the tile): the entry of j in its view's
+    // segment is the number of earlier positions of the same view
+    for (int j = (int)threadIdx.x; j < n; j += 256) {
+        const uint32_t v = v_s[j];
+        uint32_t e = 0;
+        for (int m = 0; m < j; ++m) e += v_s[m] == v ? 1u : 0u;
+        sel_pix[sel_off[v * tiles_per_view + t] + e] = p_s[j];
+    }
 }
 
 // Walk work of a thread-efficient frame (as k_frame_work), one thread per segment.
@@ -258,10 +264,22 @@ __global__ void k_zero_pair(unsigned long long* p) {
 }
 
 void launch_sel_check(const DevCam* cams, int B, uint32_t n_tiles, int tw, int th, const uint32_t* sel_off,
-                      const uint32_t* sel_pix, uint32_t n_sel, uint32_t* mask, uint32_t* n_tasks, uint32_t* err,
-                      hipStream_t s) {
+                      const uint32_t* sel_pix, uint32_t n_sel, uint32_t* mask, uint32_t* plane_mask, uint32_t* n_tasks,
+                      uint32_t* err, hipStream_t s) {
     hipLaunchKernelGGL(k_sel_check, dim3((n_tiles + 1 + 255) / 256), dim3(256), 0, s, cams, B, n_tiles, tw, th,
-                       sel_off, sel_pix, n_sel, mask, n_tasks, err);
+                       sel_off, sel_pix, n_sel, mask, plane_mask, n_tasks, err);
+}
+
+// Per-selected-pixel values (final transmittance, depth) into per-view [H, W] planes; other pixels
+// are left untouched.
+__global__ void __launch_bounds__(256) k_sel_scatter_f(const DevCam* __restrict__ cams, int B, uint32_t n_tiles,
+                                                       const uint32_t* __restrict__ sel_off,
+                                                       const uint32_t* __restrict__ sel_pix,
+                                                       const float* __restrict__ v_sel, float* const* __restrict__ out) {
+    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    if (t >= n_tiles) return;
+    float* o = out[find_view(cams, B, t)];
+    for (uint32_t i = sel_off[t]; i < sel_off[t + 1]; ++i) o[sel_pix[i]] = v_sel[i];
 }
 
 void launch_sel_tasks(uint32_t n_tiles, const uint32_t* n_tasks, const uint32_t* task_off, uint32_t cap,
@@ -274,7 +292,7 @@ void launch_sel_tasks(uint32_t n_tiles, const uint32_t* n_tasks, const uint32_t*
 void launch_blend_fwd_sel(const SelBlendArgs& a, hipStream_t s) {
     if (!a.n_tasks) return;
     hipLaunchKernelGGL(k_blend_fwd_sel, dim3(a.n_tasks), dim3(64), 0, s, a.cams, a.B, a.ranges, a.vals, a.recs,
-                       a.sel_off, a.sel_pix, a.tasks, a.n_tasks, a.images, a.t_sel, a.last_sel);
+                       a.sel_off, a.sel_pix, a.tasks, a.n_tasks, a.images, a.t_sel, a.last_sel, a.depth_sel);
 }
 
 void launch_blend_bwd_sel(const SelBlendArgs& a, hipStream_t s) {
@@ -301,11 +319,11 @@ void launch_subsample(const uint32_t* keys, int W, int H, int B, int tw, int th,
                        sel_pix);
 }
 
-void launch_sel_scatter_t(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off,
-                          const uint32_t* sel_pix, const float* t_sel, float* const* out, hipStream_t s) {
+void launch_sel_scatter(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off, const uint32_t* sel_pix,
+                        const float* v_sel, float* const* out, hipStream_t s) {
     if (!n_tiles) return;
-    hipLaunchKernelGGL(k_sel_scatter_t, dim3((n_tiles + 255) / 256), dim3(256), 0, s, cams, B, n_tiles, sel_off,
-                       sel_pix, t_sel, out);
+    hipLaunchKernelGGL(k_sel_scatter_f, dim3((n_tiles + 255) / 256), dim3(256), 0, s, cams, B, n_tiles, sel_off,
+                       sel_pix, v_sel, out);
 }
 
 void launch_frame_work_sel(const DevCam* cams, int B, uint32_t n_tiles, const uint2* ranges, const uint32_t* vals,

@@ -51,10 +51,11 @@ __global__ void __launch_bounds__(256) k_records(const float* __restrict__ means
                                                  const DevCam* __restrict__ cams, int B, int tile_w, int tile_h,
                                                  const uint32_t* __restrict__ rec_off, BlendRec* __restrict__ recs,
                                                  uint32_t* __restrict__ depth_key, uint4* __restrict__ tile_rect,
-                                                 uint16_t* __restrict__ rec_view) {
+                                                 uint16_t* __restrict__ rec_view,
+                                                 const uint32_t* __restrict__ overflow) {
     constexpr int K = (D + 1) * (D + 1);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= P) return;
+    if (g >= P || (overflow && *overflow)) return;
     float mu[3], s[3], q[4], o;
     load_gaussian(means, scales, quats, opac, g, mu, s, q, o);
     float coef[K][3];
@@ -113,7 +114,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(
     const uint32_t* __restrict__ rec_off, const uint16_t* __restrict__ rec_view, const float* __restrict__ acc,
     float* __restrict__ g_means, float* __restrict__ g_scales, float* __restrict__ g_quats,
     float* __restrict__ g_opac, float* __restrict__ g_sh, float* __restrict__ e1, float* __restrict__ e2,
-    int32_t* __restrict__ count) {
+    int32_t* __restrict__ count, const uint32_t* __restrict__ overflow) {
     constexpr int K = (D + 1) * (D + 1);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= P) return;
@@ -129,7 +130,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(
         }
     float dmu[3] = {0, 0, 0}, ds[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dop = 0.0f;
     float se1 = 0.0f, se2 = 0.0f;
-    const uint32_t r0 = rec_off[g], r1 = rec_off[g + 1];
+    const uint32_t r0 = rec_off[g], r1 = (overflow && *overflow) ? r0 : rec_off[g + 1];
     for (uint32_t ri = r0; ri < r1; ++ri) {
         const uint32_t v = rec_view[ri];
         const DevCam& c = cams[v];
@@ -281,12 +282,13 @@ void launch_count(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int
 }
 
 void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,
-                    BlendRec* recs, uint32_t* depth_key, uint4* tile_rect, uint16_t* rec_view, hipStream_t s) {
+                    BlendRec* recs, uint32_t* depth_key, uint4* tile_rect, uint16_t* rec_view, hipStream_t s,
+                    const uint32_t* overflow) {
     const unsigned blocks = (unsigned)((ga.P + 255) / 256);
     if (!blocks) return;
 #define MVGS_REC(D)                                                                                             \
     hipLaunchKernelGGL(k_records<D>, dim3(blocks), dim3(256), 0, s, ga.means, ga.scales, ga.quats, ga.opac,     \
-                       ga.sh, ga.P, cams, B, tw, th, rec_off, recs, depth_key, tile_rect, rec_view)
+                       ga.sh, ga.P, cams, B, tw, th, rec_off, recs, depth_key, tile_rect, rec_view, overflow)
     switch (ga.sh_degree) {
         case 0: MVGS_REC(0); break;
         case 1: MVGS_REC(1); break;
@@ -297,13 +299,14 @@ void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, i
 }
 
 void launch_preprocess_bwd(const GaussianArgs& ga, const DevCam* cams, const uint32_t* rec_off,
-                           const uint16_t* rec_view, const float* acc, const GradArgs& gr, hipStream_t s) {
+                           const uint16_t* rec_view, const float* acc, const GradArgs& gr, hipStream_t s,
+                           const uint32_t* overflow) {
     const unsigned blocks = (unsigned)((ga.P + 255) / 256);
     if (!blocks) return;
 #define MVGS_PB(D)                                                                                              \
     hipLaunchKernelGGL(k_preprocess_bwd<D>, dim3(blocks), dim3(256), 0, s, ga.means, ga.scales, ga.quats,       \
                        ga.opac, ga.sh, ga.P, cams, rec_off, rec_view, acc, gr.means, gr.scales, gr.quats, gr.opac,  \
-                       gr.sh, gr.e1, gr.e2, gr.count)
+                       gr.sh, gr.e1, gr.e2, gr.count, overflow)
     switch (ga.sh_degree) {
         case 0: MVGS_PB(0); break;
         case 1: MVGS_PB(1); break;

@@ -61,8 +61,10 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_
 }
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t* __restrict__ in, size_t n,
+                                                              const uint32_t* __restrict__ n_dev,
                                                               uint32_t* __restrict__ block_sums) {
     __shared__ uint32_t lds[256];
+    n = count_of(n, n_dev);
     const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
     uint32_t s = 0;
 #pragma unroll
@@ -74,8 +76,10 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t* __
 }
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t* in, uint32_t* out, size_t n,
+                                                             const uint32_t* __restrict__ n_dev,
                                                              const uint32_t* __restrict__ block_off) {
     __shared__ uint32_t lds[256];
+    n = count_of(n, n_dev);
     const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
     uint32_t vals[kScanItems];
     uint32_t s = 0;
@@ -133,25 +137,28 @@ void reduce_sum_u32(const uint32_t* in, size_t n, uint64_t* total64, void* scrat
     hipLaunchKernelGGL(k_reduce64, dim3(blocks), dim3(256), 0, s, in, n, (unsigned long long*)total64);
 }
 
-static void scan_rec(const uint32_t* in, uint32_t* out, size_t n, uint8_t* scratch, hipStream_t s) {
+// n is the bound that sizes the grids; n_dev (device, may be null) the count actually scanned.
+static void scan_rec(const uint32_t* in, uint32_t* out, size_t n, const uint32_t* n_dev, uint8_t* scratch,
+                     hipStream_t s) {
     const size_t blocks = div_up(n, kScanTile);
     if (blocks <= 1) {
-        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanThreads), 0, s, in, out, n, (const uint32_t*)nullptr);
+        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanThreads), 0, s, in, out, n, n_dev,
+                           (const uint32_t*)nullptr);
         return;
     }
     uint32_t* sums = (uint32_t*)scratch;
     uint8_t* next = scratch + ((blocks * sizeof(uint32_t) + 255) / 256) * 256;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)blocks), dim3(kScanThreads), 0, s, in, n, sums);
-    scan_rec(sums, sums, blocks, next, s);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)blocks), dim3(kScanThreads), 0, s, in, out, n,
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)blocks), dim3(kScanThreads), 0, s, in, n, n_dev, sums);
+    scan_rec(sums, sums, blocks, nullptr, next, s);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)blocks), dim3(kScanThreads), 0, s, in, out, n, n_dev,
                        (const uint32_t*)sums);
 }
 
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* total64, void* scratch,
-                        hipStream_t s) {
+                        hipStream_t s, const uint32_t* n_dev) {
     if (total64) reduce_sum_u32(in, n, total64, nullptr, s);
     if (n == 0) return;
-    scan_rec(in, out, n, (uint8_t*)scratch, s);
+    scan_rec(in, out, n, n_dev, (uint8_t*)scratch, s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -172,9 +179,11 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 
 // Digit histograms of every pass in one read of the keys: per-workgroup LDS counters, then one
 // global atomic per (pass, digit, workgroup). hist[p * 256 + d] counts digit d (dbits wide) of pass p.
-__global__ void __launch_bounds__(256) k_radix_hist_all(const uint32_t* __restrict__ keys, size_t n, int passes,
+__global__ void __launch_bounds__(256) k_radix_hist_all(const uint32_t* __restrict__ keys, size_t n,
+                                                        const uint32_t* __restrict__ n_dev, int passes,
                                                         int dbits, uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[4][kRadix];
+    n = count_of(n, n_dev);
     for (int i = threadIdx.x; i < 4 * kRadix; i += 256) (&h[0][0])[i] = 0;
     __syncthreads();
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
@@ -214,8 +223,9 @@ constexpr uint32_t kSpinLimit = 1u << 24;
 // bounded nevertheless and a timeout is recorded in *err instead of hanging.
 __global__ void __launch_bounds__(kSortThreads) k_radix_onesweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, size_t n, int shift, uint32_t mask, const uint32_t* __restrict__ digit_base,
-    uint64_t* __restrict__ status, uint32_t* __restrict__ part_counter, uint32_t* __restrict__ err) {
+    uint32_t* __restrict__ vals_out, size_t n, const uint32_t* __restrict__ n_dev, int shift, uint32_t mask,
+    const uint32_t* __restrict__ digit_base, uint64_t* __restrict__ status, uint32_t* __restrict__ part_counter,
+    uint32_t* __restrict__ err) {
     __shared__ uint32_t wcount[kSortWaves][kRadix];
     __shared__ uint32_t dstart[kRadix];
     __shared__ uint32_t gbase[kRadix];
@@ -229,6 +239,9 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_onesweep(
     for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortThreads) (&wcount[0][0])[d] = 0;
     __syncthreads();
     const uint32_t part = s_part;
+    // partitions are handed out in order, so those past the actual count are the last ones taken
+    n = count_of(n, n_dev);
+    if ((size_t)part * kSortTile >= n) return;
 
     const size_t base = (size_t)part * kSortTile + (size_t)wave * kSortRounds * 64;
     uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
@@ -328,7 +341,7 @@ size_t radix_scratch_bytes(size_t n) {
 }
 
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
-                   uint32_t* err, hipStream_t s) {
+                   uint32_t* err, hipStream_t s, const uint32_t* n_dev) {
     int cur = 0;
     if (n == 0 || bits <= 0) return cur;
     // fewest 8-bit passes, digits spread evenly over them (fewer distinct digits per workgroup
@@ -346,15 +359,15 @@ int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, s
     fill_u32(hist, (size_t)passes * kRadix, 0u, s);
     fill_u32(counters, (size_t)passes, 0u, s);
     const unsigned hblocks = (unsigned)std::min<size_t>(div_up(n, 256 * 16), 4096);
-    hipLaunchKernelGGL(k_radix_hist_all, dim3(hblocks), dim3(256), 0, s, keys[0], n, passes, dbits, hist);
+    hipLaunchKernelGGL(k_radix_hist_all, dim3(hblocks), dim3(256), 0, s, keys[0], n, n_dev, passes, dbits, hist);
     hipLaunchKernelGGL(k_radix_hist_scan, dim3(1), dim3(256), 0, s, hist, passes);
     for (int pass = 0; pass < passes; ++pass) {
         const uint32_t* vin = (pass == 0 && identity_values) ? nullptr : vals[cur];
         hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)div_up(parts * kRadix, 256)), dim3(256), 0, s, status,
                            parts * kRadix, (uint64_t)0);
         hipLaunchKernelGGL(k_radix_onesweep, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys[cur], vin,
-                           keys[cur ^ 1], vals[cur ^ 1], n, dbits * pass, mask, (const uint32_t*)(hist + pass * kRadix), status,
-                           counters + pass, err);
+                           keys[cur ^ 1], vals[cur ^ 1], n, n_dev, dbits * pass, mask,
+                           (const uint32_t*)(hist + pass * kRadix), status, counters + pass, err);
         cur ^= 1;
     }
     return cur;
@@ -367,9 +380,9 @@ int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, s
 __device__ __forceinline__ uint32_t rect_tiles(uint4 r) { return (r.y & 0xffffu) * (r.y >> 16); }
 
 __global__ void k_gather_tile_counts(const uint32_t* __restrict__ sorted_rec, const uint4* __restrict__ rect,
-                                     uint32_t n, uint32_t* __restrict__ counts) {
+                                     uint32_t n, const uint32_t* __restrict__ n_dev, uint32_t* __restrict__ counts) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) counts[i] = rect_tiles(rect[sorted_rec[i]]);
+    if (i < (uint32_t)count_of(n, n_dev)) counts[i] = rect_tiles(rect[sorted_rec[i]]);
 }
 
 // Load-balanced emission: a workgroup takes 256 consecutive records of the depth order; their
@@ -382,14 +395,21 @@ constexpr int kEmitThreads = 256;
 __global__ void __launch_bounds__(kEmitThreads) k_emit_pairs(const uint32_t* __restrict__ sorted_rec,
                                                              const uint4* __restrict__ rect,
                                                              const uint32_t* __restrict__ pair_off, uint32_t n,
-                                                             uint32_t K, uint32_t* __restrict__ keys,
+                                                             uint32_t K, const uint32_t* __restrict__ counts_dev,
+                                                             uint32_t* __restrict__ keys,
                                                              uint32_t* __restrict__ vals) {
     __shared__ uint32_t s_off[kEmitThreads + 1];   // local exclusive offsets (+ total)
     __shared__ uint32_t s_rec[kEmitThreads];
     __shared__ uint32_t s_x[kEmitThreads];         // width in tiles
     __shared__ uint32_t s_base[kEmitThreads];      // global tile id of the first covered tile
     __shared__ uint32_t s_stride[kEmitThreads];    // tiles per row of the record's view
+    // counts_dev: (records, pairs) actually present, when the grid is sized by bounds
+    if (counts_dev) {
+        n = (uint32_t)count_of(n, counts_dev);
+        K = (uint32_t)count_of(K, counts_dev + 1);
+    }
     const uint32_t i0 = blockIdx.x * kEmitThreads;
+    if (i0 >= n) return;
     const uint32_t i = i0 + threadIdx.x;
     const uint32_t base_out = pair_off[i0];
     if (i < n) {
@@ -427,9 +447,11 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_pairs(const uint32_t* __r
 
 // [start, end) of each global tile's run in the sorted pair keys, by binary search
 __global__ void __launch_bounds__(256) k_ranges_search(const uint32_t* __restrict__ keys, uint32_t K,
-                                                       uint32_t n_tiles, uint2* __restrict__ ranges) {
+                                                       const uint32_t* __restrict__ K_dev, uint32_t n_tiles,
+                                                       uint2* __restrict__ ranges) {
     const uint32_t t = blockIdx.x * 256 + threadIdx.x;
     if (t >= n_tiles) return;
+    K = (uint32_t)count_of(K, K_dev);
     uint32_t lo = 0, hi = K;  // first index with keys[i] >= t
     while (lo < hi) {
         const uint32_t mid = lo + ((hi - lo) >> 1);
@@ -458,22 +480,24 @@ __global__ void k_export_keys(const uint32_t* __restrict__ tile_keys, const uint
 }
 
 void launch_gather_tile_counts(const uint32_t* sorted_rec, const uint4* tile_rect, uint32_t n, uint32_t* counts,
-                               hipStream_t s) {
+                               hipStream_t s, const uint32_t* n_dev) {
     if (!n) return;
     hipLaunchKernelGGL(k_gather_tile_counts, dim3((n + 255) / 256), dim3(256), 0, s, sorted_rec, tile_rect, n,
-                       counts);
+                       n_dev, counts);
 }
 
 void launch_emit_pairs(const uint32_t* sorted_rec, const uint4* tile_rect, const uint32_t* pair_off, uint32_t n,
-                       uint32_t K, uint32_t* keys, uint32_t* vals, hipStream_t s) {
+                       uint32_t K, uint32_t* keys, uint32_t* vals, hipStream_t s, const uint32_t* counts_dev) {
     if (!n || !K) return;
     hipLaunchKernelGGL(k_emit_pairs, dim3((n + kEmitThreads - 1) / kEmitThreads), dim3(kEmitThreads), 0, s,
-                       sorted_rec, tile_rect, pair_off, n, K, keys, vals);
+                       sorted_rec, tile_rect, pair_off, n, K, counts_dev, keys, vals);
 }
 
-void launch_ranges(const uint32_t* keys, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s) {
+void launch_ranges(const uint32_t* keys, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s,
+                   const uint32_t* K_dev) {
     if (!n_tiles) return;
-    hipLaunchKernelGGL(k_ranges_search, dim3((n_tiles + 255) / 256), dim3(256), 0, s, keys, K, n_tiles, ranges);
+    hipLaunchKernelGGL(k_ranges_search, dim3((n_tiles + 255) / 256), dim3(256), 0, s, keys, K, K_dev, n_tiles,
+                       ranges);
 }
 
 void launch_export_keys(const uint32_t* tile_keys, const uint32_t* vals, const BlendRec* recs,
@@ -488,6 +512,35 @@ void launch_export_keys(const uint32_t* tile_keys, const uint32_t* vals, const B
 void fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
     if (!n) return;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, p, n, v);
+}
+
+__global__ void k_fill_u32_count(uint32_t* __restrict__ p, size_t n, const uint32_t* __restrict__ n_dev, uint32_t per,
+                                 uint32_t v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (size_t)per * count_of(n, n_dev)) p[i] = v;
+}
+
+void fill_u32_count(uint32_t* p, size_t n, const uint32_t* n_dev, uint32_t per, uint32_t v, hipStream_t s) {
+    if (!n || !per) return;
+    hipLaunchKernelGGL(k_fill_u32_count, dim3((unsigned)div_up(n * per, 256)), dim3(256), 0, s, p, n, n_dev, per, v);
+}
+
+// Capacity mode: the records and pairs of this call against the buffers' capacities. Within them,
+// eff = (V, K); beyond either, eff = (0, 0) and the overflow word is set, so every later kernel
+// does no work and stays inside its buffers.
+__global__ void k_capacity_clamp(const unsigned long long* __restrict__ totals, uint64_t cap_v, uint64_t cap_k,
+                                 uint32_t* __restrict__ eff, uint32_t* __restrict__ overflow) {
+    const uint64_t V = totals[0], K = totals[1];
+    const bool over = V > cap_v || K > cap_k;
+    eff[0] = over ? 0u : (uint32_t)V;
+    eff[1] = over ? 0u : (uint32_t)K;
+    overflow[0] = over ? 1u : 0u;
+}
+
+void launch_capacity_clamp(const uint64_t* totals, uint64_t cap_v, uint64_t cap_k, uint32_t* eff, uint32_t* overflow,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_capacity_clamp, dim3(1), dim3(1), 0, s, (const unsigned long long*)totals, cap_v, cap_k, eff,
+                       overflow);
 }
 
 }  // namespace mvgs

@@ -36,17 +36,29 @@ struct GradArgs {
 // k_preprocess.hip
 void launch_count(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, uint32_t* nrec,
                   uint32_t* ntiles, hipStream_t s);
+// overflow: null, or a device word that, when non-zero, makes the kernel write nothing
 void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,
-                    BlendRec* recs, uint32_t* depth_key, uint4* tile_rect, uint16_t* rec_view, hipStream_t s);
+                    BlendRec* recs, uint32_t* depth_key, uint4* tile_rect, uint16_t* rec_view, hipStream_t s,
+                    const uint32_t* overflow = nullptr);
+// overflow: as above; when set, every Gaussian is treated as taking part in no view
 void launch_preprocess_bwd(const GaussianArgs& ga, const DevCam* cams, const uint32_t* rec_off,
-                           const uint16_t* rec_view, const float* acc, const GradArgs& gr, hipStream_t s);
+                           const uint16_t* rec_view, const float* acc, const GradArgs& gr, hipStream_t s,
+                           const uint32_t* overflow = nullptr);
 
 // k_sort.hip
+// Counts in capacity mode: a launch is sized by a host bound n and, when n_dev is not null, works
+// on the first min(*n_dev, n) items only (n_dev is written by earlier kernels on the stream).
+__device__ __forceinline__ size_t count_of(size_t bound, const uint32_t* n_dev) {
+    if (!n_dev) return bound;
+    const size_t d = *n_dev;
+    return d < bound ? d : bound;
+}
+
 // Exclusive scan of n u32 values (in may equal out). The total is written to *total64 (device).
 // `scratch` must hold scan_scratch_bytes(n) bytes.
 size_t scan_scratch_bytes(size_t n);
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* total64, void* scratch,
-                        hipStream_t s);
+                        hipStream_t s, const uint32_t* n_dev = nullptr);
 // Sum of n u32 values as u64 into *total64 (device).
 void reduce_sum_u32(const uint32_t* in, size_t n, uint64_t* total64, void* scratch, hipStream_t s);
 
@@ -57,16 +69,23 @@ void reduce_sum_u32(const uint32_t* in, size_t n, uint64_t* total64, void* scrat
 // that times out sets *err (device) to a non-zero value instead of hanging.
 size_t radix_scratch_bytes(size_t n);
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
-                   uint32_t* err, hipStream_t s);
+                   uint32_t* err, hipStream_t s, const uint32_t* n_dev = nullptr);
 
 void fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+// per * min(*n_dev, n) values (all per * n when n_dev is null)
+void fill_u32_count(uint32_t* p, size_t n, const uint32_t* n_dev, uint32_t per, uint32_t v, hipStream_t s);
+void launch_capacity_clamp(const uint64_t* totals, uint64_t cap_v, uint64_t cap_k, uint32_t* eff, uint32_t* overflow,
+                           hipStream_t s);
 
 // Pair emission in depth order: count per sorted record, then (global tile, record) pairs.
 void launch_gather_tile_counts(const uint32_t* sorted_rec, const uint4* tile_rect, uint32_t n, uint32_t* counts,
-                               hipStream_t s);
+                               hipStream_t s, const uint32_t* n_dev = nullptr);
+// counts_dev: null, or device (records, pairs) actually present when n and K are bounds
 void launch_emit_pairs(const uint32_t* sorted_rec, const uint4* tile_rect, const uint32_t* pair_off, uint32_t n,
-                       uint32_t K, uint32_t* keys, uint32_t* vals, hipStream_t s);
-void launch_ranges(const uint32_t* keys, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s);
+                       uint32_t K, uint32_t* keys, uint32_t* vals, hipStream_t s,
+                       const uint32_t* counts_dev = nullptr);
+void launch_ranges(const uint32_t* keys, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s,
+                   const uint32_t* K_dev = nullptr);
 void launch_export_keys(const uint32_t* tile_keys, const uint32_t* vals, const BlendRec* recs,
                         const DevCam* cams, int B, uint32_t K, uint64_t* keys_out, uint32_t* vals_out,
                         hipStream_t s);
@@ -107,6 +126,8 @@ void launch_blend_bwd(const BlendBwdArgs& a, int tw, int th, int ppl, hipStream_
 
 // k_partial.hip: partial rendering over a pixel selection (see the file comment)
 constexpr uint32_t kSelBadOffsets = 1, kSelOutside = 2, kSelDuplicate = 4, kSelTooLong = 8;
+constexpr uint32_t kSelErrors = 15;
+constexpr uint32_t kSelPlaneOverlap = 16;   // not an error: two views share a plane position
 struct SelBlendArgs {
     const DevCam* cams;
     int B;
@@ -120,24 +141,32 @@ struct SelBlendArgs {
     float* const* images;       // forward: device array of B device pointers
     float* t_sel;               // [n_sel]
     uint32_t* last_sel;         // [n_sel]
+    float* depth_sel;           // [n_sel] blended depth (forward)
     const float* const* dl_dimg;  // backward
     float* acc;
     int want_e1;
 };
 void launch_sel_check(const DevCam* cams, int B, uint32_t n_tiles, int tw, int th, const uint32_t* sel_off,
-                      const uint32_t* sel_pix, uint32_t n_sel, uint32_t* mask, uint32_t* n_tasks, uint32_t* err,
-                      hipStream_t s);
+                      const uint32_t* sel_pix, uint32_t n_sel, uint32_t* mask, uint32_t* plane_mask, uint32_t* n_tasks,
+                      uint32_t* err, hipStream_t s);
 void launch_sel_tasks(uint32_t n_tiles, const uint32_t* n_tasks, const uint32_t* task_off, uint32_t cap,
                       uint2* tasks, hipStream_t s);
 void launch_blend_fwd_sel(const SelBlendArgs& a, hipStream_t s);
 void launch_blend_bwd_sel(const SelBlendArgs& a, hipStream_t s);
 void launch_subsample(const uint32_t* keys, int W, int H, int B, int tw, int th, uint32_t* sel_off,
                       uint32_t* sel_pix, void* scan_scratch, hipStream_t s);
-void launch_sel_scatter_t(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off,
-                          const uint32_t* sel_pix, const float* t_sel, float* const* out, hipStream_t s);
+void launch_sel_scatter(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off, const uint32_t* sel_pix,
+                        const float* v_sel, float* const* out, hipStream_t s);
 void launch_frame_work_sel(const DevCam* cams, int B, uint32_t n_tiles, const uint2* ranges, const uint32_t* vals,
                            const BlendRec* recs, const uint32_t* sel_off, const uint32_t* sel_pix,
                            const uint32_t* last_sel, uint64_t* out, hipStream_t s);
+
+// k_loss3d.hip: L1 + 3D distance-aware D-SSIM on the merged plane of a thread-efficient partial
+// frame whose selection covers the plane once
+size_t loss3d_scratch_bytes(int W, int H);
+void launch_loss3d(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off, const uint32_t* sel_pix,
+                   const float* t_sel, const float* depth_sel, int W, int H, const float* img, const float* tgt,
+                   float w_l1, float w_dssim, float* loss_out, float* grad, void* scratch, hipStream_t s);
 
 // k_loss.hip
 struct LossView {

@@ -1,0 +1,84 @@
+"""A training step captured into a HIP graph.
+
+The step (forward over a batch of views, fused loss, backward with optional densification
+statistics) runs in capacity mode, where the library's forward needs no host synchronization, so
+the whole step is one graph: a replay launches every kernel of the step with no host work between
+them. The graph keeps its tensors: write new targets into `targets` before a replay, and change the
+batch's poses with `set_cameras` (same image sizes). Each replay overwrites `images`, `loss`,
+`dl` and `grads` and adds to the statistics. `check()` waits and raises if the last replay's
+records or pairs exceeded the capacities (its results are then void).
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import torch
+
+from .raster import GaussianTensors, Rasterizer
+
+
+def measure_capacity(g: GaussianTensors, cams, tile=(16, 16), ppl=0, headroom: float = 1.25):
+    """Records and pairs of one eager forward of this batch, times `headroom`."""
+    r = Rasterizer(tile, ppl)
+    try:
+        _, fr = r.forward(g, cams)
+        info = fr.info()
+        r.release(fr)
+    finally:
+        r.close()
+    return (max(1, int(math.ceil(info["records"] * headroom))), max(1, int(math.ceil(info["pairs"] * headroom))))
+
+
+class CapturedStep:
+    def __init__(self, g: GaussianTensors, cams, targets, w_l1=1.0, w_dssim=0.0, tile=(16, 16), ppl=0,
+                 capacity=None, densify: Optional[dict] = None):
+        g.check()
+        self.g, self.cams = g, list(cams)
+        self.w_l1, self.w_dssim = float(w_l1), float(w_dssim)
+        if capacity is None:
+            capacity = measure_capacity(g, cams, tile, ppl)
+        self.rast = Rasterizer(tile, ppl, capacity=capacity)
+        dev = g.means.device
+        self.images = [torch.empty((3, c.height, c.width), device=dev) for c in cams]
+        self.targets = [t.contiguous() for t in targets]
+        self.dl = [torch.empty_like(t) for t in self.images]
+        self.loss = torch.empty(1, device=dev)
+        self.grads = dict(means=torch.empty_like(g.means), scales=torch.empty_like(g.scales),
+                          quats=torch.empty_like(g.quats), opacities=torch.empty_like(g.opacities),
+                          sh=torch.empty_like(g.sh))
+        self.densify = densify
+        # one step outside the capture sizes every buffer; its frame returns to the pool
+        fr = self._step()
+        fr.check()
+        self.rast.release(fr)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.frame = self._step()
+        torch.cuda.synchronize()
+
+    def _step(self):
+        r = self.rast
+        _, fr = r.forward(self.g, self.cams, images=self.images)
+        r.loss(self.cams, self.images, self.targets, self.w_l1, self.w_dssim, out=self.loss, grads=self.dl)
+        r.backward(self.g, fr, self.dl, densify=self.densify, grads=self.grads)
+        return fr
+
+    def replay(self):
+        self.graph.replay()
+
+    def set_cameras(self, cams):
+        """New poses for the next replays (same sizes). No replay may be in flight."""
+        self.frame.set_cameras(cams)
+        self.cams = list(cams)
+
+    def check(self):
+        self.frame.check()
+
+    def close(self):
+        self.graph = None
+        if self.frame is not None:
+            self.rast.release(self.frame)
+            self.frame = None
+        self.rast.close()

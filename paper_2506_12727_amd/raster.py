@@ -61,6 +61,17 @@ class Frame:
         self.rast, self.handle, self.cams = rast, handle, list(cams)
         self.released = False
 
+    def check(self):
+        """Capacity mode: wait for the forward and raise MvgsError (MVGS_ECAPACITY) if its records or
+        pairs exceeded the context's capacities. No-op otherwise."""
+        L.check(L.lib().mvgs_frame_check(self.rast.ctx, _stream(), self.handle), self.rast.ctx)
+
+    def set_cameras(self, cams):
+        """For a frame made under graph capture: the cameras the next replay renders (same sizes)."""
+        L.check(L.lib().mvgs_frame_set_cameras(self.rast.ctx, self.handle, L.camera_array(cams), len(cams)),
+                self.rast.ctx)
+        self.cams = list(cams)
+
     def workspace(self) -> int:
         """Device bytes the forward that made this frame asked for (exact sizes)."""
         b = C.c_int64()
@@ -78,12 +89,17 @@ class Frame:
 
 
 class Rasterizer:
-    def __init__(self, tile=(16, 16), pixels_per_lane=0, workspace_limit=0):
+    def __init__(self, tile=(16, 16), pixels_per_lane=0, workspace_limit=0, capacity=None):
+        """capacity: None, or (records, pairs) for capacity mode (no host synchronization in the
+        forward; capturable into a HIP graph)."""
         self.lib = L.lib()
         opt = L.mvgs_options()
         opt.tile_w, opt.tile_h = int(tile[0]), int(tile[1])
         opt.pixels_per_lane = int(pixels_per_lane)
         opt.workspace_limit = int(workspace_limit)
+        if capacity is not None:
+            opt.capacity_records, opt.capacity_pairs = int(capacity[0]), int(capacity[1])
+        self.capacity = capacity
         self.ctx = C.c_void_p()
         L.check(self.lib.mvgs_create(C.byref(self.ctx), C.byref(opt)))
         self.tile = (opt.tile_w, opt.tile_h)
@@ -213,6 +229,26 @@ class Rasterizer:
         L.check(self.lib.mvgs_export_binning(self.ctx, _stream(), frame.handle, keys.data_ptr(), vals.data_ptr(),
                                              ranges.data_ptr()), self.ctx)
         return keys[:info["pairs"]], vals[:info["pairs"]], ranges[:info["tiles"]]
+
+    def loss_3d(self, frame: Frame, image: torch.Tensor, target: torch.Tensor, w_l1=1.0, w_dssim=0.0, out=None,
+                grad=None):
+        """L1 + 3D distance-aware D-SSIM on the merged plane of a thread-efficient partial frame:
+        (loss [1] on the GPU, dL/dimage [3,H,W]). Pass the gradient for every view to backward."""
+        if out is None:
+            out = torch.empty(1, dtype=torch.float32, device=image.device)
+        if grad is None:
+            grad = torch.empty_like(image)
+        L.check(self.lib.mvgs_loss_3d(self.ctx, _stream(), frame.handle, image.contiguous().data_ptr(),
+                                      target.contiguous().data_ptr(), float(w_l1), float(w_dssim), out.data_ptr(),
+                                      grad.data_ptr()), self.ctx)
+        return out, grad
+
+    def export_depth(self, frame: Frame, outs=None):
+        if outs is None:
+            outs = [torch.zeros((c.height, c.width), dtype=torch.float32, device="cuda") for c in frame.cams]
+        L.check(self.lib.mvgs_export_depth(self.ctx, _stream(), frame.handle,
+                                           L.ptr_array([t.data_ptr() for t in outs])), self.ctx)
+        return outs
 
     def export_transmittance(self, frame: Frame):
         outs = [torch.empty((c.height, c.width), dtype=torch.float32, device="cuda") for c in frame.cams]

@@ -112,6 +112,16 @@ class Admission:
         self.peak = max(self.peak, self.used())
         return batch
 
+    def take_forced(self, slot: int, queue: deque) -> List[Request]:
+        """The head alone, reserving everything the budget has left (used when every slot is idle
+        and holds nothing, yet the estimate says the head does not fit: the library decides)."""
+        r = queue.popleft()
+        self.taken_gen[slot] = self.gen
+        self.reserved[slot] = max(self.held[slot], self.budget - (self.used() - self.reserved[slot]) - r.image_bytes)
+        self.images += r.image_bytes
+        self.peak = max(self.peak, self.used())
+        return [r]
+
     def finish(self, slot: int, batch: Sequence[Request], held_after: int, workspace: Optional[int]):
         """The batch is done: its images leave the in-flight count (the caller owns them now), the
         reservation falls back to what the context holds, and the estimate learns."""
@@ -145,6 +155,7 @@ class _Slot:
         self.stream = torch.cuda.Stream()          # default priority
         self.batch: Optional[List[Request]] = None
         self.limit = 0
+        self.forced = False   # the batch was admitted with the whole remaining budget
         self.busy_intervals = []
         self.thread = threading.Thread(target=self._loop, name=f"mvgs-slot-{index}", daemon=True)
         self.thread.start()
@@ -182,7 +193,7 @@ class _Slot:
                     srv.cond.wait()
                 if srv.stopping:
                     return
-                batch, limit = self.batch, self.limit
+                batch, limit, forced = self.batch, self.limit, self.forced
             t0 = srv.clock()
             try:
                 imgs, ws = self._render(batch, limit)
@@ -197,7 +208,13 @@ class _Slot:
                     srv.error = err
                 elif imgs is None:
                     srv.adm.refused(self.index, batch, held)
-                    srv.queue.extendleft(reversed(batch))
+                    if forced:
+                        # refused with every byte the budget has: the request cannot be served
+                        for r in batch:
+                            r.error = "request exceeds the memory budget"
+                            srv.rejected.append(r)
+                    else:
+                        srv.queue.extendleft(reversed(batch))
                 else:
                     srv.adm.finish(self.index, batch, held, ws)
                     for r, im in zip(batch, imgs):
@@ -264,28 +281,29 @@ class Server:
             for s in idle:
                 batch = self.adm.take(s.index, self.queue)
                 if batch:
-                    for r in batch:
-                        r.batch = len(self.batches)
-                    self.batches.append((s.index, len(batch)))
-                    s.batch, s.limit = batch, self.adm.reserved[s.index]
+                    self._launch(s, batch, forced=False)
                     launched = True
                     break
             if launched:
-                self.cond.notify_all()
                 continue
-            head = self.queue[0]
-            if not self.adm.fits_alone(head):
-                head.error = "request exceeds the memory budget"
-                self.rejected.append(self.queue.popleft())
-                continue
-            if len(idle) == len(self.slots):
-                # every slot idle and memory held by idle contexts blocks the head: free the largest
-                big = idle[0]
+            if len(idle) < len(self.slots):
+                return   # wait for a busy slot to finish
+            # every slot idle, yet the head does not fit the estimate: free idle contexts' memory,
+            # then let the library decide with the whole budget
+            big = idle[0]
+            if self.adm.held[big.index] > 0:
                 big.recycle()
                 self.adm.recycled(big.index)
                 self.recycles += 1
                 continue
-            return   # wait for a busy slot to finish
+            self._launch(big, self.adm.take_forced(big.index, self.queue), forced=True)
+
+    def _launch(self, s, batch, forced):
+        for r in batch:
+            r.batch = len(self.batches)
+        self.batches.append((s.index, len(batch)))
+        s.batch, s.limit, s.forced = batch, self.adm.reserved[s.index], forced
+        self.cond.notify_all()
 
     def run(self, arrivals: Sequence[float], cams: Sequence, measure_from: int = 0) -> dict:
         """Serve requests arriving at `arrivals` (seconds from now, ascending). Returns statistics

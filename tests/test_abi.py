@@ -136,8 +136,20 @@ def test_workspace_limit_options_and_memory_queries():
     h = C.c_void_p()
     assert lib.mvgs_create(C.byref(h), C.byref(o)) == L.MVGS_EINVAL
     o = L.mvgs_options()
-    o.reserved[1] = 5
+    o.reserved0 = 5
     assert lib.mvgs_create(C.byref(h), C.byref(o)) == L.MVGS_EINVAL
+    # capacities: both or neither, non-negative, below 2^32
+    for cv, ck in [(10, 0), (0, 10), (-1, -1), (1 << 32, 10), (10, 1 << 32)]:
+        o = L.mvgs_options()
+        o.capacity_records, o.capacity_pairs = cv, ck
+        assert lib.mvgs_create(C.byref(h), C.byref(o)) == L.MVGS_EINVAL, (cv, ck)
+    o = L.mvgs_options()
+    o.capacity_records, o.capacity_pairs = 1000, 5000
+    assert lib.mvgs_create(C.byref(h), C.byref(o)) == L.MVGS_OK
+    assert lib.mvgs_frame_check(h, None, None) == L.MVGS_EINVAL
+    assert lib.mvgs_frame_check(None, None, None) == L.MVGS_EINVAL
+    assert lib.mvgs_frame_set_cameras(h, None, None, 1) == L.MVGS_EINVAL
+    lib.mvgs_destroy(h)
     o = L.mvgs_options()
     o.workspace_limit = 1 << 30
     assert lib.mvgs_create(C.byref(h), C.byref(o)) == L.MVGS_OK

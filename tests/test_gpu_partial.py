@@ -223,3 +223,96 @@ def test_bad_selections_are_refused():
     with pytest.raises(L.MvgsError):
         r.subsample(scenes.make_cameras([(40, 20), (41, 20)]), kt)
     r.close()
+
+
+def _merged_setup(tile=(16, 16), B=3, size=(48, 40), seed=21):
+    sc = scenes.make_scene(6000, 3, log_scale_mean=-3.0)
+    cams = scenes.make_cameras([size] * B, seed=seed)
+    kn, kt = _keys(size[0], size[1], seed)
+    return sc, cams, kt
+
+
+def test_partial_depth_matches_oracle():
+    needs_gpu()
+    tile = (16, 16)
+    sc, cams, kt = _merged_setup(tile, B=4, size=(61, 47))
+    r = Rasterizer(tile)
+    g = GaussianTensors.from_scene(sc)
+    off, pix = r.subsample(cams, kt)
+    _, fr = r.forward_partial(g, cams, off, pix, L.MVGS_PARTIAL_COMPACT)
+    dep = r.export_depth(fr)
+    torch.cuda.synchronize()
+    sel = _sel_lists(off, pix, cams, tile)
+    for v, c in enumerate(cams):
+        xs, ys = sel[v] % c.width, sel[v] // c.width
+        rgb, tf, fl, dz = oracle.render_pixels(sc, cams, v, xs, ys, with_depth=True)
+        got = dep[v].cpu().numpy().astype(np.float64)[ys, xs]
+        ok = fl == 0
+        assert np.all(np.abs(got - dz)[ok] <= 1e-5 * np.abs(dz)[ok] + 1e-6), v
+    # depth is rendered by thread-efficient frames only
+    _, fm = r.forward_partial(g, cams, off, pix, L.MVGS_PARTIAL_MASKED)
+    with pytest.raises(L.MvgsError):
+        r.export_depth(fm)
+    r.release(fm)
+    r.release(fr)
+    r.close()
+
+
+@pytest.mark.parametrize("w", [(0.8, 0.2), (0.0, 1.0)])
+def test_loss3d_matches_oracle(w):
+    needs_gpu()
+    tile = (16, 16)
+    sc, cams, kt = _merged_setup(tile)
+    W, H = cams[0].width, cams[0].height
+    r = Rasterizer(tile)
+    g = GaussianTensors.from_scene(sc)
+    off, pix = r.subsample(cams, kt)
+    merged = torch.zeros((3, H, W), device="cuda")
+    _, fr = r.forward_partial(g, cams, off, pix, L.MVGS_PARTIAL_COMPACT, images=[merged] * len(cams))
+    target = torch.rand((3, H, W), device="cuda", generator=torch.Generator(device="cuda").manual_seed(5))
+    loss, grad = r.loss_3d(fr, merged, target, *w)
+    # the oracle takes the same inputs: merged image, target, and points from the rendered depth and T
+    plane_t = torch.ones((H, W), device="cuda")
+    plane_d = torch.zeros((H, W), device="cuda")
+    L.check(r.lib.mvgs_export_transmittance(r.ctx, None, fr.handle, L.ptr_array([plane_t.data_ptr()] * len(cams))),
+            r.ctx)
+    r.export_depth(fr, outs=[plane_d] * len(cams))
+    torch.cuda.synchronize()
+    sel = _sel_lists(off, pix, cams, tile)
+    vm = np.zeros(W * H, int)
+    for v in range(len(cams)):
+        vm[sel[v]] = v
+    P, S = oracle.surface_points(cams, vm.reshape(H, W), plane_d.cpu().numpy().astype(np.float64),
+                                 plane_t.cpu().numpy().astype(np.float64))
+    assert (S > 0).mean() > 0.5
+    lo, go, _ = oracle.loss3d(merged.cpu().numpy(), target.cpu().numpy(), P, S, *w)
+    assert abs(float(loss.item()) - lo) <= 1e-5 * abs(lo) + 1e-7
+    gd = grad.cpu().numpy().astype(np.float64)
+    assert np.allclose(gd, go, rtol=1e-4, atol=1e-5 * np.abs(go).max())
+    # the gradient drives the backward like any image gradient (one plane for every view)
+    grads = r.backward(g, fr, [grad] * len(cams))
+    torch.cuda.synchronize()
+    assert all(bool(torch.isfinite(t).all()) for t in grads.values())
+    r.release(fr)
+    r.close()
+
+
+def test_loss3d_needs_a_plane_partition():
+    needs_gpu()
+    tile = (32, 32)
+    sc = scenes.make_scene(3000, 1, log_scale_mean=-3.1)
+    cams = scenes.make_cameras([(61, 47), (61, 47)])
+    r = Rasterizer(tile, 4)
+    g = GaussianTensors.from_scene(sc)
+    off, pix = _uneven_selection(cams, tile, 3)
+    img = torch.zeros((3, 47, 61), device="cuda")
+    _, fr = r.forward_partial(g, cams, off, pix, L.MVGS_PARTIAL_COMPACT)
+    with pytest.raises(L.MvgsError) as ei:
+        r.loss_3d(fr, img, img)
+    assert ei.value.status == L.MVGS_EINVAL
+    r.release(fr)
+    _, ff = r.forward(g, cams)
+    with pytest.raises(L.MvgsError):
+        r.loss_3d(ff, img, img)
+    r.release(ff)
+    r.close()

@@ -17,7 +17,10 @@ def test_partition_hand_worked_fixture():
     f = json.load(open(GOLDEN))
     off, pix = oracle.subsample_tiles(f["width"], f["height"], f["views"], f["tile"], f["keys"])
     segs = [list(pix[off[s]:off[s + 1]]) for s in range(len(off) - 1)]
-    assert segs == f["segments"]
+    assert segs == f["segments_in_position_order"]
+    # the ranking itself: rank r goes to view r mod 3
+    for r, p in enumerate(f["ranked_positions"]):
+        assert p in segs[r % 3]
 
 
 def _check_partition(W, H, B, tile, keys):
@@ -37,10 +40,12 @@ def _check_partition(W, H, B, tile, keys):
             seg = pix[off[v * T + t]:off[v * T + t + 1]]
             # balanced: view v gets the ranks v, v + B, v + 2B, ...
             assert len(seg) == max(0, -(-(n - v) // B))
+            assert np.all(np.diff(seg.astype(np.int64)) > 0)   # ascending position
             xs, ys = seg % W, seg // W
             assert np.all(xs // tw == tx) and np.all(ys // th == ty)
-            ranked.append(seg)
-        # interleaving the views' segments gives the tile's positions in (key, position) order
+            # in (key, position) order, the segment's pixels are the ranks v, v + B, ...
+            ranked.append(sorted(seg.tolist(), key=lambda p: (int(k[p]), p)))
+        # interleaving the views' ranked pixels gives the tile's positions in (key, position) order
         order = [ranked[r % B][r // B] for r in range(n)]
         kk = [(int(k[p]), int(p)) for p in order]
         assert kk == sorted(kk)
@@ -60,7 +65,8 @@ def test_partition_invariants_ragged():
 def test_more_views_than_pixels_in_a_tile():
     keys = np.arange(6, dtype=np.uint32)[::-1].copy()
     off, pix = _check_partition(3, 2, 8, (8, 8), keys)
-    # six pixels, eight views: views 6 and 7 get nothing; rank order is descending position
+    # six pixels, eight views: views 6 and 7 get nothing; the keys fall with position, so view v
+    # gets the position of rank v, 5 - v
     assert [len(pix[off[v]:off[v + 1]]) for v in range(8)] == [1, 1, 1, 1, 1, 1, 0, 0]
     assert list(pix) == [5, 4, 3, 2, 1, 0]
 

@@ -155,3 +155,15 @@ def test_per_view_bound_limits_batches_and_is_not_learned_per_pixel():
     b = adm.take(0, q)
     adm.finish(0, b, held_after=1300, workspace=1300)
     assert adm.bpp == 3.0
+
+
+def test_forced_admission_reserves_what_the_budget_has_left():
+    adm = Admission(budget=10_000, n_slots=2, max_batch=4, bytes_per_pixel=100.0, slack=1.0)
+    q = _reqs([(10, 10)])            # estimate 10,000 + 1,200 image bytes: over the budget
+    assert adm.take(0, q) == []
+    b = adm.take_forced(0, q)
+    assert len(b) == 1 and not q
+    assert adm.reserved[0] == 10_000 - 1_200 and adm.images == 1_200
+    assert adm.used() <= adm.budget
+    adm.refused(0, b, held_after=0)
+    assert adm.used() == 0
