@@ -191,7 +191,7 @@ def main():
     # roofline of the dominant kernel
     dom = max(("blend_fwd", "blend_bwd", "tile_sort", "depth_sort", "emit", "records", "preprocess_bwd"),
               key=lambda k: stage_ms[k])
-    roof = roofline(dom, stage_ms[dom], info, blended, g, B, cams)
+    roof = roofline(dom, stage_ms[dom], info, blended, g, B, cams, measured_traffic(dom, wl.name, tile, ppl))
 
     partial = None
     if not args.no_partial:
@@ -238,7 +238,8 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "frame": {"records": info["records"], "pairs": info["pairs"], "tiles": info["tiles"],
                   "walk_steps": steps_walk, "blended_pairs": blended},
-        "blend_rooflines": {k: roofline(k, stage_ms[k], info, blended, g, B, cams)
+        "blend_rooflines": {k: roofline(k, stage_ms[k], info, blended, g, B, cams,
+                                        measured_traffic(k, wl.name, tile, ppl))
                             for k in ("blend_fwd", "blend_bwd")},
         "roofline": roof,
         "partial": partial,
@@ -371,8 +372,28 @@ def serve_bench(args, g, tile, ppl):
     return out
 
 
-def roofline(stage, ms, info, blended, g, B, cams):
-    """Achieved vs peak for one stage; algorithmic bytes or lane operations per launch."""
+def measured_traffic(stage, workload, tile, ppl):
+    """HBM bytes per launch of a blend kernel from the rocprofv3 counter runs recorded in
+    profiles/blend_traffic.json, or None when that record is for another launch shape or workload,
+    or its kernels' sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "blend_traffic.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for p in rec["sources"]:
+            h.update(open(os.path.join(ROOT, p), "rb").read())
+    except (OSError, ValueError, KeyError):
+        return None
+    if (h.hexdigest() != rec["sources_sha256"] or rec["workload"] != workload or list(rec["tile"]) != list(tile)
+            or rec["pixels_per_lane"] != ppl):
+        return None
+    return rec["bytes_per_launch"].get(stage)
+
+
+def roofline(stage, ms, info, blended, g, B, cams, traffic=None):
+    """Achieved vs peak for one stage; algorithmic bytes or lane operations per launch; traffic is
+    the measured HBM bytes per launch when known."""
     K, V = info["pairs"], info["records"]
     npx = sum(c.width * c.height for c in cams)
     sec = ms / 1e3
@@ -380,7 +401,9 @@ def roofline(stage, ms, info, blended, g, B, cams):
         per = FWD_OPS_PER_STEP if stage == "blend_fwd" else BWD_OPS_PER_STEP
         ach = blended * per / sec / 1e12
         return {"kernel": stage, "bound": "alu", "achieved": ach, "peak": ALU_PEAK_TLANEOPS, "unit": "Tlane-op/s",
-                "frac": ach / ALU_PEAK_TLANEOPS, "traffic": None,
+                "frac": ach / ALU_PEAK_TLANEOPS, "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE, WRITE_SIZE, calibrated)",
+                "traffic_TBps": None if traffic is None else traffic / sec / 1e12,
                 "units": {"blended_pairs": blended, "ops_per_pair": per}}
     # HBM-bound stages: one read and one write of what the stage must move
     per = {
