@@ -216,7 +216,8 @@ struct mvgs_context {
     int tw = 16, th = 16, ppl = 2;
     std::string err;
     std::vector<mvgs_frame*> frames;
-    DevBuf nrec, ntiles, totals, scan_scratch, depth_key[2], rec_vals[2], tile_rect, pair_counts, pair_off;
+    DevBuf nrec, ntiles, totals, scan_scratch, depth_key[2], rec_vals[2], tile_rect, sorted_rect, pair_counts,
+        pair_off;
     DevBuf sort_scratch, acc, loss_scratch, ssim_maps, loss3d_scratch;
     size_t limit = 0;  // 0: no workspace limit
     uint64_t cap_v = 0, cap_k = 0;  // capacity mode when non-zero
@@ -240,7 +241,7 @@ struct mvgs_context {
     template <typename Fn>
     void each_buffer(Fn fn) {
         DevBuf* bufs[] = {&nrec, &ntiles, &totals, &scan_scratch, &depth_key[0], &depth_key[1], &rec_vals[0],
-                          &rec_vals[1], &tile_rect, &pair_counts, &pair_off, &sort_scratch, &acc,
+                          &rec_vals[1], &tile_rect, &sorted_rect, &pair_counts, &pair_off, &sort_scratch, &acc,
                           &loss_scratch, &ssim_maps, &loss3d_scratch, &work};
         for (DevBuf* b : bufs) fn(*b);
         for (auto& sl : ring.slots) fn(sl.dev);
@@ -719,6 +720,7 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
                           {&ctx->rec_vals[0], sizeof(uint32_t) * V1},
                           {&ctx->rec_vals[1], sizeof(uint32_t) * V1},
                           {&ctx->tile_rect, sizeof(uint4) * V1},
+                          {&ctx->sorted_rect, sizeof(uint4) * V1},
                           {&ctx->pair_counts, sizeof(uint32_t) * V1},
                           {&ctx->pair_off, sizeof(uint32_t) * V1},
                           {&f->keys[0], sizeof(uint32_t) * K1},
@@ -754,10 +756,11 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
 
     // pairs in depth order, then a stable sort by global tile id
     mk = ctx->stage_begin(3, s);
-    launch_gather_tile_counts(sorted_rec, as<uint4>(ctx->tile_rect), V, as<uint32_t>(ctx->pair_counts), s, eff);
+    launch_gather_tile_counts(sorted_rec, as<uint4>(ctx->tile_rect), V, as<uint32_t>(ctx->pair_counts),
+                              as<uint4>(ctx->sorted_rect), s, eff);
     scan_exclusive_u32(as<uint32_t>(ctx->pair_counts), as<uint32_t>(ctx->pair_off), V, nullptr,
                        ctx->sort_scratch.p, s, eff);
-    launch_emit_pairs(sorted_rec, as<uint4>(ctx->tile_rect), as<uint32_t>(ctx->pair_off), V, K,
+    launch_emit_pairs(sorted_rec, as<uint4>(ctx->sorted_rect), as<uint32_t>(ctx->pair_off), V, K,
                       as<uint32_t>(f->keys[0]), as<uint32_t>(f->vals[0]), s, eff);
     ctx->stage_end(mk, s);
     mk = ctx->stage_begin(4, s);

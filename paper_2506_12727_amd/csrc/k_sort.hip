@@ -379,10 +379,17 @@ int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, s
 
 __device__ __forceinline__ uint32_t rect_tiles(uint4 r) { return (r.y & 0xffffu) * (r.y >> 16); }
 
+// The one gather of the records' tile rectangles in depth order: pair counts, and the rectangles
+// themselves in that order so that pair emission reads them sequentially.
 __global__ void k_gather_tile_counts(const uint32_t* __restrict__ sorted_rec, const uint4* __restrict__ rect,
-                                     uint32_t n, const uint32_t* __restrict__ n_dev, uint32_t* __restrict__ counts) {
+                                     uint32_t n, const uint32_t* __restrict__ n_dev, uint32_t* __restrict__ counts,
+                                     uint4* __restrict__ sorted_rect) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < (uint32_t)count_of(n, n_dev)) counts[i] = rect_tiles(rect[sorted_rec[i]]);
+    if (i < (uint32_t)count_of(n, n_dev)) {
+        const uint4 r = rect[sorted_rec[i]];
+        counts[i] = rect_tiles(r);
+        sorted_rect[i] = r;
+    }
 }
 
 // Load-balanced emission: a workgroup takes 256 consecutive records of the depth order; their
@@ -393,7 +400,7 @@ __global__ void k_gather_tile_counts(const uint32_t* __restrict__ sorted_rec, co
 constexpr int kEmitThreads = 256;
 
 __global__ void __launch_bounds__(kEmitThreads) k_emit_pairs(const uint32_t* __restrict__ sorted_rec,
-                                                             const uint4* __restrict__ rect,
+                                                             const uint4* __restrict__ sorted_rect,
                                                              const uint32_t* __restrict__ pair_off, uint32_t n,
                                                              uint32_t K, const uint32_t* __restrict__ counts_dev,
                                                              uint32_t* __restrict__ keys,
@@ -414,7 +421,7 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_pairs(const uint32_t* __r
     const uint32_t base_out = pair_off[i0];
     if (i < n) {
         const uint32_t r = sorted_rec[i];
-        const uint4 rc = rect[r];
+        const uint4 rc = sorted_rect[i];
         s_rec[threadIdx.x] = r;
         s_x[threadIdx.x] = rc.y & 0xffffu;
         s_base[threadIdx.x] = rc.x;
@@ -480,17 +487,17 @@ __global__ void k_export_keys(const uint32_t* __restrict__ tile_keys, const uint
 }
 
 void launch_gather_tile_counts(const uint32_t* sorted_rec, const uint4* tile_rect, uint32_t n, uint32_t* counts,
-                               hipStream_t s, const uint32_t* n_dev) {
+                               uint4* sorted_rect, hipStream_t s, const uint32_t* n_dev) {
     if (!n) return;
     hipLaunchKernelGGL(k_gather_tile_counts, dim3((n + 255) / 256), dim3(256), 0, s, sorted_rec, tile_rect, n,
-                       n_dev, counts);
+                       n_dev, counts, sorted_rect);
 }
 
-void launch_emit_pairs(const uint32_t* sorted_rec, const uint4* tile_rect, const uint32_t* pair_off, uint32_t n,
+void launch_emit_pairs(const uint32_t* sorted_rec, const uint4* sorted_rect, const uint32_t* pair_off, uint32_t n,
                        uint32_t K, uint32_t* keys, uint32_t* vals, hipStream_t s, const uint32_t* counts_dev) {
     if (!n || !K) return;
     hipLaunchKernelGGL(k_emit_pairs, dim3((n + kEmitThreads - 1) / kEmitThreads), dim3(kEmitThreads), 0, s,
-                       sorted_rec, tile_rect, pair_off, n, K, counts_dev, keys, vals);
+                       sorted_rec, sorted_rect, pair_off, n, K, counts_dev, keys, vals);
 }
 
 void launch_ranges(const uint32_t* keys, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s,

@@ -13,6 +13,10 @@
 
 namespace mvgs {
 
+// Per-record accumulator stride (floats) of the blend backward:
+// dmx, dmy, dca, dcb, dcc, dopacity, dr, dg, db, E1 term, 2 spare.
+constexpr int kAccStride = 12;
+
 constexpr float kNear = 0.2f;          // near plane (camera-space z)
 constexpr float kDilation = 0.3f;      // px^2 added to the 2D covariance diagonal
 constexpr float kPowerFloor = -4.5f;   // 3-sigma ellipse: power = -0.5 d^T conic d >= -4.5

@@ -8,10 +8,6 @@
 
 namespace mvgs {
 
-// Per-record accumulator stride (floats) of the blend backward:
-// dmx, dmy, dca, dcb, dcc, dopacity, dr, dg, db, E1 term, 2 spare.
-constexpr int kAccStride = 12;
-
 struct GaussianArgs {
     const float* means;
     const float* scales;
@@ -78,10 +74,11 @@ void launch_capacity_clamp(const uint64_t* totals, uint64_t cap_v, uint64_t cap_
                            hipStream_t s);
 
 // Pair emission in depth order: count per sorted record, then (global tile, record) pairs.
+// Pair counts of the records in depth order, and their tile rectangles gathered into that order.
 void launch_gather_tile_counts(const uint32_t* sorted_rec, const uint4* tile_rect, uint32_t n, uint32_t* counts,
-                               hipStream_t s, const uint32_t* n_dev = nullptr);
+                               uint4* sorted_rect, hipStream_t s, const uint32_t* n_dev = nullptr);
 // counts_dev: null, or device (records, pairs) actually present when n and K are bounds
-void launch_emit_pairs(const uint32_t* sorted_rec, const uint4* tile_rect, const uint32_t* pair_off, uint32_t n,
+void launch_emit_pairs(const uint32_t* sorted_rec, const uint4* sorted_rect, const uint32_t* pair_off, uint32_t n,
                        uint32_t K, uint32_t* keys, uint32_t* vals, hipStream_t s,
                        const uint32_t* counts_dev = nullptr);
 void launch_ranges(const uint32_t* keys, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s,

@@ -226,9 +226,9 @@ class _Slot:
 
 
 # Device bytes per participating (view, Gaussian) record in a forward: the 64-byte blend record, its
-# view (2), depth keys and record indices double-buffered (16), tile rectangle (16), pair count and
-# offset (8).
-RECORD_BYTES = 106
+# view (2), depth keys and record indices double-buffered (16), tile rectangle in record and in depth
+# order (32), pair count and offset (8).
+RECORD_BYTES = 122
 
 
 class Server:
