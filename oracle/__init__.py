@@ -377,3 +377,59 @@ def loss3d(image, target, points, scale, w_l1=1.0, w_dssim=0.0):
         np.add.at(dS, (slice(None), qy[inside], qx[inside]), contrib[:, inside])
     grad = w_l1 * np.sign(I1 - I2) / N - w_dssim * dS / N
     return loss, grad, S
+
+
+# ---------------------------------------------------------------------------------------------
+# Multi-view adaptive density control (Sec. 5.2.2 with the statistics of Eqs. 13-14)
+# ---------------------------------------------------------------------------------------------
+
+def densify(means, scales, quats, opacities, sh, e1, e2, count, normals, split_threshold, clone_threshold,
+            dense_scale, min_opacity):
+    """One densification step over activated parameters. Per Gaussian g with count[g] > 0:
+    mean E1 = e1/count above split_threshold and largest scale above dense_scale -> split into two
+    children drawn from the Gaussian itself (means mu + R (s * z_k) with z_k = normals[g, k], the
+    normalised quaternion's rotation R, scales s / 1.6, other parameters copied); mean E2 =
+    e2/count above clone_threshold and largest scale at most dense_scale -> clone (the original
+    and an identical copy). A Gaussian with opacity below min_opacity is pruned with all it would
+    produce. Outputs keep the order of the originals (each original's outputs in a row: itself,
+    its copy, or its two children). The decisions are compared in single precision; the children's
+    means in double. Returns (means, scales, quats, opacities, sh, src) with src the original index
+    of each output."""
+    P = len(means)
+    out = {k: [] for k in ("means", "scales", "quats", "opacities", "sh", "src")}
+
+    def emit(g, mu, s):
+        out["means"].append(np.asarray(mu, np.float64))
+        out["scales"].append(np.asarray(s, np.float64))
+        out["quats"].append(np.asarray(quats[g], np.float64))
+        out["opacities"].append(float(opacities[g]))
+        out["sh"].append(np.asarray(sh[g], np.float64))
+        out["src"].append(g)
+
+    f32 = np.float32
+    for g in range(P):
+        # the decisions are taken in single precision, as the kernels take them
+        if f32(opacities[g]) < f32(min_opacity):
+            continue
+        s = np.asarray(scales[g], np.float64)
+        big = f32(np.max(np.asarray(scales[g], f32))) > f32(dense_scale)
+        c = int(count[g])
+        m1 = f32(f32(e1[g]) / f32(c)) if c > 0 else f32(0.0)
+        m2 = f32(f32(e2[g]) / f32(c)) if c > 0 else f32(0.0)
+        if big and m1 > f32(split_threshold):
+            w, x, y, z = np.asarray(quats[g], np.float64) / np.linalg.norm(np.asarray(quats[g], np.float64))
+            R = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                          [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                          [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+            for k in range(2):
+                emit(g, np.asarray(means[g], np.float64) + R @ (s * np.asarray(normals[g][k], np.float64)), s / 1.6)
+        elif (not big) and m2 > f32(clone_threshold):
+            emit(g, means[g], s)
+            emit(g, means[g], s)
+        else:
+            emit(g, means[g], s)
+    res = [np.array(out[k]) for k in ("means", "scales", "quats")]
+    res.append(np.array(out["opacities"]))
+    res.append(np.array(out["sh"]).reshape((-1,) + np.asarray(sh).shape[1:]))
+    res.append(np.array(out["src"], np.int64))
+    return tuple(res)
