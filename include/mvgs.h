@@ -213,6 +213,40 @@ int mvgs_loss_3d(mvgs_context* ctx, void* stream, const mvgs_frame* frame, const
  * pixels untouched). */
 int mvgs_export_depth(mvgs_context* ctx, void* stream, const mvgs_frame* frame, float* const* depth);
 
+/* Multi-view adaptive density control (paper Sec. 5.2.2): per Gaussian, with the per-view mean
+ * statistics m1 = e1 / count and m2 = e2 / count (0 where count is 0), compared in single precision:
+ *   opacity < min_opacity                                 -> pruned (no output)
+ *   largest scale > dense_scale and m1 > split_threshold  -> split into two children,
+ *       means mu + R (s * z_k) (R the normalised quaternion's rotation, z_k = normals[6g + 3k ..]),
+ *       scales s / 1.6, other parameters copied
+ *   largest scale <= dense_scale and m2 > clone_threshold -> cloned (itself and an identical copy)
+ *   otherwise                                             -> kept.
+ * The paper splits on E1 and clones on E2 and scales the pruning threshold by the number of views
+ * per batch (pass min_opacity already scaled). Outputs keep the originals' order, each original's
+ * outputs in a row; src (device int32 [n_out], may be NULL) receives the original of each output,
+ * to carry other per-Gaussian state along. normals: device float [P, 2, 3] standard normal draws
+ * (the caller's random numbers). out: device buffers for `capacity` Gaussians (the input's SH
+ * degree). Synchronizes the stream once to read n_out; MVGS_ECAPACITY (nothing written) if the
+ * result exceeds capacity (2 P always suffices). */
+typedef struct {
+    float split_threshold;
+    float clone_threshold;
+    float dense_scale;
+    float min_opacity;
+} mvgs_adc_params;
+
+typedef struct {
+    float* means;
+    float* scales;
+    float* quats;
+    float* opacities;
+    float* sh;
+} mvgs_gaussians_out;
+
+int mvgs_adapt_density(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const float* e1, const float* e2,
+                       const int32_t* count, const float* normals, const mvgs_adc_params* prm,
+                       const mvgs_gaussians_out* out, int32_t* src, int64_t capacity, int64_t* n_out);
+
 /* Backward pass: from dL/dimage (B device pointers [3,H,W]) to parameter
  * gradients (overwritten) and, when `densify` is not NULL, the densification
  * statistics (accumulated). `g` must hold the same parameters the frame was

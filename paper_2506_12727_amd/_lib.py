@@ -24,7 +24,7 @@ EXPORTED = ["mvgs_create", "mvgs_destroy", "mvgs_forward", "mvgs_loss", "mvgs_ba
             "mvgs_last_error", "mvgs_profile_enable", "mvgs_profile_read", "mvgs_profile_reset",
             "mvgs_stage_name", "mvgs_frame_work", "mvgs_set_workspace_limit", "mvgs_memory_held",
             "mvgs_frame_workspace", "mvgs_forward_partial", "mvgs_subsample", "mvgs_frame_check",
-            "mvgs_frame_set_cameras", "mvgs_loss_3d", "mvgs_export_depth"]
+            "mvgs_frame_set_cameras", "mvgs_loss_3d", "mvgs_export_depth", "mvgs_adapt_density"]
 MVGS_PARTIAL_COMPACT = 0
 MVGS_PARTIAL_MASKED = 1
 MVGS_STAGE_COUNT = 10
@@ -54,6 +54,16 @@ class mvgs_options(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("pixels_per_lane", C.c_int32),
                 ("reserved0", C.c_int32), ("workspace_limit", C.c_int64), ("capacity_records", C.c_int64),
                 ("capacity_pairs", C.c_int64)]
+
+
+class mvgs_adc_params(C.Structure):
+    _fields_ = [("split_threshold", C.c_float), ("clone_threshold", C.c_float), ("dense_scale", C.c_float),
+                ("min_opacity", C.c_float)]
+
+
+class mvgs_gaussians_out(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p), ("opacities", C.c_void_p),
+                ("sh", C.c_void_p)]
 
 
 class MvgsError(RuntimeError):
@@ -127,6 +137,9 @@ def lib():
     L.mvgs_loss_3d.restype = C.c_int
     L.mvgs_export_depth.argtypes = [vp, vp, vp, vp]
     L.mvgs_export_depth.restype = C.c_int
+    L.mvgs_adapt_density.argtypes = [vp, vp, C.POINTER(mvgs_gaussians), vp, vp, vp, vp, C.POINTER(mvgs_adc_params),
+                               C.POINTER(mvgs_gaussians_out), vp, i64, C.POINTER(i64)]
+    L.mvgs_adapt_density.restype = C.c_int
     _LIB = L
     return L
 

@@ -218,7 +218,7 @@ struct mvgs_context {
     std::vector<mvgs_frame*> frames;
     DevBuf nrec, ntiles, totals, scan_scratch, depth_key[2], rec_vals[2], tile_rect, sorted_rect, pair_counts,
         pair_off;
-    DevBuf sort_scratch, acc, loss_scratch, ssim_maps, loss3d_scratch;
+    DevBuf sort_scratch, acc, loss_scratch, ssim_maps, loss3d_scratch, adc_n, adc_off, adc_act;
     size_t limit = 0;  // 0: no workspace limit
     uint64_t cap_v = 0, cap_k = 0;  // capacity mode when non-zero
     bool capturing = false;         // the current call's stream is being captured into a graph
@@ -242,7 +242,7 @@ struct mvgs_context {
     void each_buffer(Fn fn) {
         DevBuf* bufs[] = {&nrec, &ntiles, &totals, &scan_scratch, &depth_key[0], &depth_key[1], &rec_vals[0],
                           &rec_vals[1], &tile_rect, &sorted_rect, &pair_counts, &pair_off, &sort_scratch, &acc,
-                          &loss_scratch, &ssim_maps, &loss3d_scratch, &work};
+                          &loss_scratch, &ssim_maps, &loss3d_scratch, &adc_n, &adc_off, &adc_act, &work};
         for (DevBuf* b : bufs) fn(*b);
         for (auto& sl : ring.slots) fn(sl.dev);
         for (mvgs_frame* f : frames) f->each_buffer(fn);
@@ -603,7 +603,7 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     const Need need1[] = {{&f->cams, sizeof(DevCam) * B},
                           {&ctx->nrec, sizeof(uint32_t) * (P + 1)},
                           {&ctx->ntiles, sizeof(uint32_t) * (P + 1)},
-                          {&ctx->totals, sizeof(uint64_t) * 4},
+                          {&ctx->totals, sizeof(uint64_t) * 8},
                           {&f->dtot, cap ? (size_t)64 : (size_t)0},
                           {&f->rec_off, sizeof(uint32_t) * (P + 1)},
                           {&ctx->scan_scratch, scan_scratch_bytes(std::max<size_t>(P + 1, n_tiles))},
@@ -617,7 +617,7 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     const int n_need1 = 14;
     st = grow_all(ctx, need1, n_need1);
     if (st) return bail(st);
-    if (fresh_totals) fill_u32(as<uint32_t>(ctx->totals), 8, 0u, s);
+    if (fresh_totals) fill_u32(as<uint32_t>(ctx->totals), 16, 0u, s);
     void* img_ptrs = nullptr;
     {
         void* dcams = nullptr;
@@ -886,6 +886,58 @@ int mvgs_loss(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t 
     ctx->stage_end(mk, s);
     LAUNCHCHK(ctx, "loss kernels");
     HIPCHK(ctx, ctx->ring.seal(s));
+    return MVGS_OK;
+}
+
+int mvgs_adapt_density(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const float* e1, const float* e2,
+                       const int32_t* count, const float* normals, const mvgs_adc_params* prm,
+                       const mvgs_gaussians_out* out, int32_t* src, int64_t capacity, int64_t* n_out) {
+    if (!ctx) return MVGS_EINVAL;
+    int st = validate_gaussians(ctx, g);
+    if (st) return st;
+    if (!prm || !out || !n_out) return ctx->fail(MVGS_EINVAL, "params, outputs or n_out is NULL");
+    if (g->P > 0 && (!e1 || !e2 || !count || !normals))
+        return ctx->fail(MVGS_EINVAL, "statistics or normals are NULL");
+    if (capacity < 0) return ctx->fail(MVGS_EINVAL, "capacity < 0");
+    if (!(prm->dense_scale >= 0.0f) || !std::isfinite(prm->split_threshold) || !std::isfinite(prm->clone_threshold) ||
+        !std::isfinite(prm->min_opacity))
+        return ctx->fail(MVGS_EINVAL, "densification parameters must be finite (dense_scale >= 0)");
+    *n_out = 0;
+    hipStream_t s = (hipStream_t)stream;
+    if (ctx->begin(s)) return ctx->fail(MVGS_EINVAL, "mvgs_adapt_density synchronizes and cannot be captured");
+    HIPCHK(ctx, ctx->bind_device());
+    const size_t P = (size_t)g->P;
+    const Need need[] = {{&ctx->adc_n, sizeof(uint32_t) * (P + 1)},
+                         {&ctx->adc_off, sizeof(uint32_t) * (P + 1)},
+                         {&ctx->adc_act, std::max<size_t>(P, 1)},
+                         {&ctx->totals, sizeof(uint64_t) * 8},
+                         {&ctx->scan_scratch, scan_scratch_bytes(P + 1)}};
+    const bool fresh_totals = !ctx->totals.p;
+    st = grow_all(ctx, need, 5);
+    if (st) return st;
+    if (fresh_totals) fill_u32(as<uint32_t>(ctx->totals), 16, 0u, s);
+    AdcParams ap{prm->split_threshold, prm->clone_threshold, prm->dense_scale, prm->min_opacity};
+    const GaussianArgs ga = gargs(g);
+    uint64_t* total = as<uint64_t>(ctx->totals) + 4;
+    if (P) {
+        launch_adc_classify(ga, e1, e2, count, ap, as<uint32_t>(ctx->adc_n), as<uint8_t>(ctx->adc_act), s);
+        scan_exclusive_u32(as<uint32_t>(ctx->adc_n), as<uint32_t>(ctx->adc_off), P, total, ctx->scan_scratch.p, s);
+    } else {
+        fill_u32(reinterpret_cast<uint32_t*>(total), 2, 0u, s);
+    }
+    LAUNCHCHK(ctx, "densification classify");
+    HIPCHK(ctx, hipMemcpyAsync(ctx->pinned_totals, total, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    const int64_t n = (int64_t)ctx->pinned_totals[0];
+    *n_out = n;
+    if (n > capacity)
+        return ctx->fail(MVGS_ECAPACITY, "densification makes %lld Gaussians; the outputs hold %lld", (long long)n,
+                         (long long)capacity);
+    if (n > 0 && (!out->means || !out->scales || !out->quats || !out->opacities || !out->sh))
+        return ctx->fail(MVGS_EINVAL, "an output pointer is NULL");
+    launch_adc_write(ga, normals, as<uint8_t>(ctx->adc_act), as<uint32_t>(ctx->adc_off), out->means, out->scales,
+                     out->quats, out->opacities, out->sh, src, s);
+    LAUNCHCHK(ctx, "densification write");
     return MVGS_OK;
 }
 

@@ -158,6 +158,15 @@ void launch_frame_work_sel(const DevCam* cams, int B, uint32_t n_tiles, const ui
                            const BlendRec* recs, const uint32_t* sel_off, const uint32_t* sel_pix,
                            const uint32_t* last_sel, uint64_t* out, hipStream_t s);
 
+// k_densify.hip: multi-view adaptive density control
+struct AdcParams {
+    float split_threshold, clone_threshold, dense_scale, min_opacity;
+};
+void launch_adc_classify(const GaussianArgs& ga, const float* e1, const float* e2, const int32_t* count,
+                         const AdcParams& prm, uint32_t* n_out, uint8_t* action, hipStream_t s);
+void launch_adc_write(const GaussianArgs& ga, const float* normals, const uint8_t* action, const uint32_t* off,
+                      float* means, float* scales, float* quats, float* opac, float* sh, int32_t* src, hipStream_t s);
+
 // k_loss3d.hip: L1 + 3D distance-aware D-SSIM on the merged plane of a thread-efficient partial
 // frame whose selection covers the plane once
 size_t loss3d_scratch_bytes(int W, int H);

@@ -250,6 +250,33 @@ class Rasterizer:
                                            L.ptr_array([t.data_ptr() for t in outs])), self.ctx)
         return outs
 
+    def adapt_density(self, g: GaussianTensors, stats: dict, normals: torch.Tensor, split_threshold=2e-4,
+                clone_threshold=2e-4, dense_scale=0.01, min_opacity=0.005):
+        """Multi-view adaptive density control from the statistics dict(e1, e2, count): returns the new
+        GaussianTensors and the original index of each new Gaussian (int32). normals: [P, 2, 3]
+        standard normal draws for the split children."""
+        g.check()
+        P = g.P
+        K = (g.sh_degree + 1) ** 2
+        dev = g.means.device
+        cap = max(2 * P, 1)
+        out = GaussianTensors(torch.empty((cap, 3), device=dev), torch.empty((cap, 3), device=dev),
+                              torch.empty((cap, 4), device=dev), torch.empty(cap, device=dev),
+                              torch.empty((cap, K, 3), device=dev), g.sh_degree)
+        src = torch.empty(cap, dtype=torch.int32, device=dev)
+        prm = L.mvgs_adc_params(float(split_threshold), float(clone_threshold), float(dense_scale), float(min_opacity))
+        o = L.mvgs_gaussians_out(out.means.data_ptr(), out.scales.data_ptr(), out.quats.data_ptr(),
+                                 out.opacities.data_ptr(), out.sh.data_ptr())
+        n = C.c_int64()
+        normals = normals.contiguous()
+        L.check(self.lib.mvgs_adapt_density(self.ctx, _stream(), C.byref(self._gauss(g)), stats["e1"].data_ptr(),
+                                      stats["e2"].data_ptr(), stats["count"].data_ptr(), normals.data_ptr(),
+                                      C.byref(prm), C.byref(o), src.data_ptr(), cap, C.byref(n)), self.ctx)
+        m = int(n.value)
+        res = GaussianTensors(out.means[:m].contiguous(), out.scales[:m].contiguous(), out.quats[:m].contiguous(),
+                              out.opacities[:m].contiguous(), out.sh[:m].contiguous(), g.sh_degree)
+        return res, src[:m]
+
     def export_transmittance(self, frame: Frame):
         outs = [torch.empty((c.height, c.width), dtype=torch.float32, device="cuda") for c in frame.cams]
         L.check(self.lib.mvgs_export_transmittance(self.ctx, _stream(), frame.handle,

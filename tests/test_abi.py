@@ -192,3 +192,29 @@ def test_partial_and_subsample_validation(ctx):
     assert "one size" in _err(ctx)
     assert lib.mvgs_subsample(ctx, None, ca, 2, None, 0x2000, 0x3000) == L.MVGS_EINVAL
     assert lib.mvgs_subsample(ctx, None, ca, 0, 0x1000, 0x2000, 0x3000) == L.MVGS_EINVAL
+
+
+def test_adapt_density_validation(ctx):
+    lib = L.lib()
+    g = _gauss()
+    prm = L.mvgs_adc_params(2e-4, 2e-4, 0.01, 0.005)
+    out = L.mvgs_gaussians_out(0x5000, 0x5000, 0x5000, 0x5000, 0x5000)
+    n = C.c_int64(-7)
+
+    def call(g=g, e1=0x1000, normals=0x4000, prm=prm, out=out, cap=20, n=n):
+        return lib.mvgs_adapt_density(ctx, None, C.byref(g) if g is not None else None, e1, 0x2000, 0x3000, normals,
+                                      C.byref(prm) if prm is not None else None,
+                                      C.byref(out) if out is not None else None, 0x6000, cap,
+                                      C.byref(n) if n is not None else None)
+
+    assert call(g=None) == L.MVGS_EINVAL
+    assert call(g=_gauss(deg=4)) == L.MVGS_EINVAL
+    assert call(e1=None) == L.MVGS_EINVAL and "NULL" in _err(ctx)
+    assert call(normals=None) == L.MVGS_EINVAL
+    assert call(prm=None) == L.MVGS_EINVAL
+    assert call(out=None) == L.MVGS_EINVAL
+    assert call(n=None) == L.MVGS_EINVAL
+    assert call(cap=-1) == L.MVGS_EINVAL and "capacity" in _err(ctx)
+    assert call(prm=L.mvgs_adc_params(float("nan"), 2e-4, 0.01, 0.005)) == L.MVGS_EINVAL
+    assert call(prm=L.mvgs_adc_params(2e-4, 2e-4, -1.0, 0.005)) == L.MVGS_EINVAL and "finite" in _err(ctx)
+    assert lib.mvgs_adapt_density(None, None, None, None, None, None, None, None, None, None, 0, None) == L.MVGS_EINVAL
