@@ -247,6 +247,49 @@ int mvgs_adapt_density(mvgs_context* ctx, void* stream, const mvgs_gaussians* g,
                        const int32_t* count, const float* normals, const mvgs_adc_params* prm,
                        const mvgs_gaussians_out* out, int32_t* src, int64_t capacity, int64_t* n_out);
 
+/* One Adam step (the optimiser 3DGS trains with) of the activated parameters, in place. Scales
+ * and opacities move in their unconstrained coordinates, log-scale and opacity logit: their
+ * gradients are taken through exp and the sigmoid and the step is applied as s * exp(-step) and
+ * sigmoid(logit(o) - step) (opacities of exactly 0 or 1 stay). Per element, with the gradient g
+ * in those coordinates: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * step = lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), t = prm->step >= 1.
+ * params: device float, the layout of mvgs_gaussians. grads: the gradients mvgs_backward wrote
+ * (statistics pointers unused). moments: device float [P, 11 + 3K, 2] (m, v interleaved; per
+ * Gaussian the elements of means, scales, quats, opacity, SH in that order), zero before the
+ * first step. The SH learning rate is lr_sh_dc for the first coefficient, lr_sh_rest for the
+ * others. Launches one kernel, no synchronization (may be captured). */
+typedef struct {
+    float lr_means, lr_scales, lr_quats, lr_opacities, lr_sh_dc, lr_sh_rest;
+    float beta1, beta2, eps;
+    int32_t step;
+} mvgs_adam_params;
+
+int mvgs_adam_step(mvgs_context* ctx, void* stream, int64_t P, int32_t sh_degree, const mvgs_gaussians_out* params,
+                   const mvgs_grads* grads, float* moments, const mvgs_adam_params* prm);
+
+/* out[r, :] = in[src[r], :] for r < n over float rows of `width` (device): carries per-Gaussian
+ * state such as the optimiser moments through mvgs_adapt_density's src map. in and out must not
+ * overlap; src entries must index rows of in (not checked on the device). */
+int mvgs_gather_rows(mvgs_context* ctx, void* stream, const int32_t* src, int64_t n, int64_t width, const float* in,
+                     float* out);
+
+/* Running moments of mini-batch gradients for the Monte Carlo variance estimate of Sec. 3.2 (the
+ * mean squared norm minus the squared norm of the mean). The gradient vector is the
+ * concatenation means | scales | quats | opacities | SH of one backward's grads (n = P (11 + 3K)
+ * elements). Adds it to sum (device double [n]); adds its squared norm to acc[0] and sets acc[1]
+ * (device double [2]) to the squared norm of the updated sum. After k calls:
+ * variance = acc[0] / k - acc[1] / k^2. No synchronization (may be captured). */
+int mvgs_grad_moments(mvgs_context* ctx, void* stream, int64_t P, int32_t sh_degree, const mvgs_grads* grads,
+                      double* sum, double* acc);
+
+/* Merges per-view planes into the image plane of a partial frame (Alg. 3: each pixel of the plane
+ * belongs to the view that selected it), e.g. the views' targets into the target of the merged
+ * render. planes: B device pointers to [channels, H, W] float (the views must share one size);
+ * out: device [channels, H, W]; each selected pixel of view v takes planes[v]'s value there, other
+ * pixels of out are left alone. MVGS_EINVAL for a full (unselected) frame. */
+int mvgs_frame_merge(mvgs_context* ctx, void* stream, const mvgs_frame* frame, const float* const* planes,
+                     int32_t channels, float* out);
+
 /* Backward pass: from dL/dimage (B device pointers [3,H,W]) to parameter
  * gradients (overwritten) and, when `densify` is not NULL, the densification
  * statistics (accumulated). `g` must hold the same parameters the frame was

@@ -433,3 +433,83 @@ def densify(means, scales, quats, opacities, sh, e1, e2, count, normals, split_t
     res.append(np.array(out["sh"]).reshape((-1,) + np.asarray(sh).shape[1:]))
     res.append(np.array(out["src"], np.int64))
     return tuple(res)
+
+
+def adam_step(params, grads, moments, step, lr, beta1=0.9, beta2=0.999, eps=1e-15):
+    """One Adam step (Kingma and Ba; the optimiser 3DGS trains with) of activated parameters, in
+    double precision, returning new (params, moments). params and grads: dicts of means [P,3],
+    scales [P,3], quats [P,4], opacities [P], sh [P,K,3] (grads with respect to the activated
+    values). Scales and opacities move in log-scale and logit coordinates: their gradients pass
+    through exp and the sigmoid, the step is applied there and mapped back (opacities of exactly
+    0 or 1 stay). moments: [P, 11 + 3K, 2] (m, v), per Gaussian in the order means, scales,
+    quats, opacity, SH. lr: dict(means, scales, quats, opacities, sh_dc, sh_rest)."""
+    P = len(params["means"])
+    K = np.asarray(params["sh"]).shape[1]
+    d = lambda a: np.asarray(a, np.float64)
+    s, o = d(params["scales"]), d(params["opacities"]).reshape(P)
+    # gradient in the optimised coordinates, per Gaussian in the moment order
+    gvec = np.concatenate([d(grads["means"]).reshape(P, 3), (d(grads["scales"]) * s).reshape(P, 3),
+                           d(grads["quats"]).reshape(P, 4), (d(grads["opacities"]).reshape(P) * o * (1 - o))[:, None],
+                           d(grads["sh"]).reshape(P, 3 * K)], axis=1)
+    lrs = np.concatenate([np.full(3, lr["means"]), np.full(3, lr["scales"]), np.full(4, lr["quats"]),
+                          [lr["opacities"]], np.full(3, lr["sh_dc"]), np.full(3 * K - 3, lr["sh_rest"])])
+    mom = d(moments).copy()
+    m = beta1 * mom[..., 0] + (1 - beta1) * gvec
+    v = beta2 * mom[..., 1] + (1 - beta2) * gvec * gvec
+    mom[..., 0], mom[..., 1] = m, v
+    stepv = lrs[None, :] * (m / (1 - beta1 ** step)) / (np.sqrt(v / (1 - beta2 ** step)) + eps)
+    out = dict(means=d(params["means"]) - stepv[:, 0:3], scales=s * np.exp(-stepv[:, 3:6]),
+               quats=d(params["quats"]) - stepv[:, 6:10], sh=(d(params["sh"]).reshape(P, 3 * K) - stepv[:, 11:])
+               .reshape(P, K, 3))
+    inner = (o > 0) & (o < 1)
+    logit = np.log(np.where(inner, o, 0.5)) - np.log1p(-np.where(inner, o, 0.5))
+    out["opacities"] = np.where(inner, 1.0 / (1.0 + np.exp(-(logit - stepv[:, 10]))), o)
+    return out, mom
+
+
+def flatten_grads(g) -> np.ndarray:
+    """The gradient vector of Sec. 3.2's variance: means | scales | quats | opacities | SH."""
+    return np.concatenate([np.asarray(g[k], np.float64).reshape(-1)
+                           for k in ("means", "scales", "quats", "opacities", "sh")])
+
+
+def minibatch_variance(vectors) -> float:
+    """Monte Carlo estimate of the variance of mini-batch gradients (Sec. 3.2): the mean squared
+    norm of the sampled mini-batch gradients minus the squared norm of their mean."""
+    x = np.asarray(vectors, np.float64)
+    return float(np.mean(np.sum(x * x, axis=1)) - np.sum(np.mean(x, axis=0) ** 2))
+
+
+def batch_gradient(scene, cams, targets, views, w_l1=1.0, tile=(16, 16)):
+    """Gradient of the mini-batch loss formed by the listed views: the mean over those views of
+    each view's mean L1 loss (the loss whose expectation over uniformly drawn views is the loss
+    over the whole set)."""
+    sub = [cams[v] for v in views]
+    imgs = forward(scene, sub, tile)["images"]
+    dl = []
+    for img, v in zip(imgs, views):
+        t = np.asarray(targets[v], np.float64)
+        n = t.size
+        dl.append(w_l1 * np.sign(img - t) / (n * len(views)))
+    return backward(scene, sub, dl, tile)
+
+
+def partial_batch_gradient(scene, cams, targets, views, keys, tile=(16, 16)):
+    """Gradient of the L1 loss of one partial-rendering mini-batch (Alg. 3): the listed views (of
+    one size) share the image plane by the sub-sampling of `keys`; each pixel of the plane is
+    rendered from the view that took it and compared with that view's target; the loss is the
+    mean over the plane's (channel, row, column)."""
+    sub = [cams[v] for v in views]
+    W, H = sub[0].width, sub[0].height
+    off, pix = subsample_tiles(W, H, len(views), tile, keys)
+    T = (len(off) - 1) // len(views)
+    imgs = forward(scene, sub, tile)["images"]
+    dl = []
+    for j, v in enumerate(views):
+        sel = pix[off[j * T]:off[(j + 1) * T]]
+        ys, xs = sel // W, sel % W
+        d = np.zeros((3, H, W))
+        diff = imgs[j][:, ys, xs] - np.asarray(targets[v], np.float64)[:, ys, xs]
+        d[:, ys, xs] = np.sign(diff) / (3 * W * H)
+        dl.append(d)
+    return backward(scene, sub, dl, tile)

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmvgs.so")
 SOURCES = ["k_preprocess.hip", "k_sort.hip", "k_blend.hip", "k_partial.hip", "k_loss.hip", "k_loss3d.hip",
-           "k_densify.hip", "api.cpp"]
+           "k_densify.hip", "k_train.hip", "api.cpp"]
 ARCH = os.environ.get("MVGS_OFFLOAD_ARCH", "gfx950")
 
 CFLAGS = ["-x", "hip", "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

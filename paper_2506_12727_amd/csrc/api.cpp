@@ -941,6 +941,78 @@ int mvgs_adapt_density(mvgs_context* ctx, void* stream, const mvgs_gaussians* g,
     return MVGS_OK;
 }
 
+static int grads_present(const mvgs_grads* gr, int64_t P) {
+    return gr && (P == 0 || (gr->means && gr->scales && gr->quats && gr->opacities && gr->sh));
+}
+
+int mvgs_adam_step(mvgs_context* ctx, void* stream, int64_t P, int32_t sh_degree, const mvgs_gaussians_out* params,
+                   const mvgs_grads* grads, float* moments, const mvgs_adam_params* prm) {
+    if (!ctx) return MVGS_EINVAL;
+    if (P < 0 || P >= (1ll << 31)) return ctx->fail(MVGS_EINVAL, "P=%lld outside [0, 2^31)", (long long)P);
+    if (sh_degree < 0 || sh_degree > 3) return ctx->fail(MVGS_EINVAL, "sh_degree=%d outside [0, 3]", sh_degree);
+    if (!params || !prm || !grads_present(grads, P))
+        return ctx->fail(MVGS_EINVAL, "params, grads or adam parameters are NULL");
+    if (P > 0 && (!params->means || !params->scales || !params->quats || !params->opacities || !params->sh ||
+                  !moments))
+        return ctx->fail(MVGS_EINVAL, "a parameter or moment pointer is NULL");
+    if (prm->step < 1) return ctx->fail(MVGS_EINVAL, "step=%d must be >= 1", prm->step);
+    if (!(prm->beta1 >= 0.0f && prm->beta1 < 1.0f && prm->beta2 >= 0.0f && prm->beta2 < 1.0f && prm->eps >= 0.0f))
+        return ctx->fail(MVGS_EINVAL, "betas must lie in [0, 1) and eps >= 0");
+    const float lrs[6] = {prm->lr_means, prm->lr_scales, prm->lr_quats, prm->lr_opacities, prm->lr_sh_dc,
+                          prm->lr_sh_rest};
+    for (float l : lrs)
+        if (!std::isfinite(l)) return ctx->fail(MVGS_EINVAL, "learning rates must be finite");
+    AdamArgs a{lrs[0], lrs[1], lrs[2], lrs[3], lrs[4], lrs[5], prm->beta1, prm->beta2, prm->eps,
+               (float)(1.0 - std::pow((double)prm->beta1, prm->step)),
+               (float)(1.0 - std::pow((double)prm->beta2, prm->step))};
+    if (!(a.bc1 > 0.0f) || !(a.bc2 > 0.0f)) return ctx->fail(MVGS_EINVAL, "a bias correction is zero");
+    GradArgs gr{};
+    gr.means = grads->means;
+    gr.scales = grads->scales;
+    gr.quats = grads->quats;
+    gr.opac = grads->opacities;
+    gr.sh = grads->sh;
+    HIPCHK(ctx, ctx->bind_device());
+    launch_adam(params->means, params->scales, params->quats, params->opacities, params->sh, gr, moments, P, sh_degree,
+                a, (hipStream_t)stream);
+    LAUNCHCHK(ctx, "adam step");
+    return MVGS_OK;
+}
+
+int mvgs_gather_rows(mvgs_context* ctx, void* stream, const int32_t* src, int64_t n, int64_t width, const float* in,
+                     float* out) {
+    if (!ctx) return MVGS_EINVAL;
+    if (n < 0 || width < 0 || (width > 0 && n > (int64_t(1) << 40) / width))
+        return ctx->fail(MVGS_EINVAL, "n=%lld, width=%lld out of range", (long long)n, (long long)width);
+    if (n > 0 && width > 0 && (!src || !in || !out)) return ctx->fail(MVGS_EINVAL, "src, in or out is NULL");
+    HIPCHK(ctx, ctx->bind_device());
+    launch_gather_rows(src, n, width, in, out, (hipStream_t)stream);
+    LAUNCHCHK(ctx, "row gather");
+    return MVGS_OK;
+}
+
+int mvgs_grad_moments(mvgs_context* ctx, void* stream, int64_t P, int32_t sh_degree, const mvgs_grads* grads,
+                      double* sum, double* acc) {
+    if (!ctx) return MVGS_EINVAL;
+    if (P < 0 || P >= (1ll << 31)) return ctx->fail(MVGS_EINVAL, "P=%lld outside [0, 2^31)", (long long)P);
+    if (sh_degree < 0 || sh_degree > 3) return ctx->fail(MVGS_EINVAL, "sh_degree=%d outside [0, 3]", sh_degree);
+    if (!grads_present(grads, P) || !acc || (P > 0 && !sum))
+        return ctx->fail(MVGS_EINVAL, "grads, sum or acc is NULL");
+    HIPCHK(ctx, ctx->bind_device());
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t K = (int64_t)(sh_degree + 1) * (sh_degree + 1);
+    fill_f64(acc + 1, 1, 0.0, s);
+    const float* seg[5] = {grads->means, grads->scales, grads->quats, grads->opacities, grads->sh};
+    const int64_t width[5] = {3, 3, 4, 1, 3 * K};
+    int64_t at = 0;
+    for (int k = 0; k < 5; ++k) {
+        launch_grad_moments(seg[k], P * width[k], sum + at, acc, s);
+        at += P * width[k];
+    }
+    LAUNCHCHK(ctx, "gradient moments");
+    return MVGS_OK;
+}
+
 int mvgs_loss_3d(mvgs_context* ctx, void* stream, const mvgs_frame* frame, const float* image, const float* target,
                  float w_l1, float w_dssim, float* loss_dev, float* dl_dimage) {
     if (!ctx) return MVGS_EINVAL;
@@ -1162,6 +1234,29 @@ int mvgs_export_transmittance(mvgs_context* ctx, void* stream, const mvgs_frame*
         HIPCHK(ctx, hipMemcpyAsync(t_final[v], as<float>(f->t_final) + c.pix_base, sizeof(float) * c.W * c.H,
                                    hipMemcpyDeviceToDevice, s));
     }
+    return MVGS_OK;
+}
+
+int mvgs_frame_merge(mvgs_context* ctx, void* stream, const mvgs_frame* frame, const float* const* planes,
+                     int32_t channels, float* out) {
+    if (!ctx) return MVGS_EINVAL;
+    if (!frame || frame->ctx != ctx || !frame->in_use) return ctx->fail(MVGS_EINVAL, "not a live frame");
+    mvgs_frame* f = const_cast<mvgs_frame*>(frame);
+    if (f->mode == kModeFull) return ctx->fail(MVGS_EINVAL, "the frame has no pixel selection");
+    if (channels < 1 || channels > 64) return ctx->fail(MVGS_EINVAL, "channels=%d outside [1, 64]", channels);
+    if (!planes || !out) return ctx->fail(MVGS_EINVAL, "planes or out is NULL");
+    for (int v = 0; v < f->B; ++v) {
+        if (!planes[v]) return ctx->fail(MVGS_EINVAL, "planes[%d] is NULL", v);
+        if (f->hcams[v].W != f->hcams[0].W || f->hcams[v].H != f->hcams[0].H)
+            return ctx->fail(MVGS_EINVAL, "merging needs views of one size");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    void* dptrs = nullptr;
+    HIPCHK(ctx, ctx->ring.put(planes, sizeof(float*) * f->B, s, &dptrs));
+    launch_sel_merge(as<DevCam>(f->cams), f->B, f->n_tiles, as<uint32_t>(f->sel_off), as<uint32_t>(f->sel_pix),
+                     (const float* const*)dptrs, channels, (uint32_t)(f->hcams[0].W * f->hcams[0].H), out, s);
+    LAUNCHCHK(ctx, "selection merge");
+    HIPCHK(ctx, ctx->ring.seal(s));
     return MVGS_OK;
 }
 

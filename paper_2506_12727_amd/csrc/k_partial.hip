@@ -282,6 +282,29 @@ __global__ void __launch_bounds__(256) k_sel_scatter_f(const DevCam* __restrict_
     for (uint32_t i = sel_off[t]; i < sel_off[t + 1]; ++i) o[sel_pix[i]] = v_sel[i];
 }
 
+// Per-view [C, H, W] planes of one size merged into one plane: each selected pixel takes the value
+// of the view that selected it; other pixels are left untouched.
+__global__ void __launch_bounds__(256) k_sel_merge(const DevCam* __restrict__ cams, int B, uint32_t n_tiles,
+                                                   const uint32_t* __restrict__ sel_off,
+                                                   const uint32_t* __restrict__ sel_pix,
+                                                   const float* const* __restrict__ planes, int C, uint32_t plane_px,
+                                                   float* __restrict__ out) {
+    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    if (t >= n_tiles) return;
+    const float* in = planes[find_view(cams, B, t)];
+    for (uint32_t i = sel_off[t]; i < sel_off[t + 1]; ++i) {
+        const uint32_t p = sel_pix[i];
+        for (int c = 0; c < C; ++c) out[(size_t)c * plane_px + p] = in[(size_t)c * plane_px + p];
+    }
+}
+
+void launch_sel_merge(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off, const uint32_t* sel_pix,
+                      const float* const* planes, int C, uint32_t plane_px, float* out, hipStream_t s) {
+    if (!n_tiles) return;
+    hipLaunchKernelGGL(k_sel_merge, dim3((n_tiles + 255) / 256), dim3(256), 0, s, cams, B, n_tiles, sel_off, sel_pix,
+                       planes, C, plane_px, out);
+}
+
 void launch_sel_tasks(uint32_t n_tiles, const uint32_t* n_tasks, const uint32_t* task_off, uint32_t cap,
                       uint2* tasks, hipStream_t s) {
     if (!n_tiles) return;

@@ -1,0 +1,132 @@
+// Kernels of the synthetic training loop around the rasterizer: one Adam update of the activated
+// parameters, the row gather that carries per-Gaussian optimiser state through densification, and
+// the running moments of mini-batch gradients used to estimate their variance (Sec. 3.2).
+//
+// The parameters are kept activated (the rasterizer's inputs). Scales and opacities are optimised
+// in their unconstrained coordinates, log-scale and opacity logit, as 3DGS does; those coordinates
+// are implied by the activated values: the gradient is taken through the activation and the step
+// is applied as s * exp(-step) and sigmoid(logit(o) - step) = 1 / (1 + (1 - o) / o * exp(step)).
+#include "mvgs_kernels.h"
+
+namespace mvgs {
+
+// One element per thread over [P][D] with D = 11 + 3K: means 3, scales 3, quats 4, opacity 1, SH 3K.
+__global__ void __launch_bounds__(256) k_adam(float* __restrict__ means, float* __restrict__ scales,
+                                              float* __restrict__ quats, float* __restrict__ opac,
+                                              float* __restrict__ sh, const float* __restrict__ g_means,
+                                              const float* __restrict__ g_scales, const float* __restrict__ g_quats,
+                                              const float* __restrict__ g_opac, const float* __restrict__ g_sh,
+                                              float2* __restrict__ mom, int64_t P, int K, AdamArgs a) {
+    const int D = 11 + 3 * K;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= P * D) return;
+    const int64_t g = i / D;
+    const int d = (int)(i - g * D);
+    float* p;
+    float grad, lr;
+    float x = 0.0f;   // scale or opacity before the step
+    if (d < 3) {
+        p = means + 3 * g + d;
+        grad = g_means[3 * g + d];
+        lr = a.lr_means;
+    } else if (d < 6) {
+        p = scales + 3 * g + (d - 3);
+        x = *p;
+        grad = g_scales[3 * g + (d - 3)] * x;   // d/d log s
+        lr = a.lr_scales;
+    } else if (d < 10) {
+        p = quats + 4 * g + (d - 6);
+        grad = g_quats[4 * g + (d - 6)];
+        lr = a.lr_quats;
+    } else if (d == 10) {
+        p = opac + g;
+        x = *p;
+        grad = g_opac[g] * (x * (1.0f - x));     // d/d logit o
+        lr = a.lr_opacities;
+    } else {
+        const int e = d - 11;
+        p = sh + (int64_t)3 * K * g + e;
+        grad = g_sh[(int64_t)3 * K * g + e];
+        lr = e < 3 ? a.lr_sh_dc : a.lr_sh_rest;
+    }
+    float2 mv = mom[i];
+    mv.x = a.beta1 * mv.x + (1.0f - a.beta1) * grad;
+    mv.y = a.beta2 * mv.y + (1.0f - a.beta2) * (grad * grad);
+    mom[i] = mv;
+    const float step = lr * (mv.x / a.bc1) / (sqrtf(mv.y / a.bc2) + a.eps);
+    if (d >= 3 && d < 6) {
+        *p = x * expf(-step);
+    } else if (d == 10) {
+        // 0 and 1 are fixed points of the logit step (and would give 0 * inf here)
+        if (x > 0.0f && x < 1.0f) *p = 1.0f / (1.0f + (1.0f - x) / x * expf(step));
+    } else {
+        *p = *p - step;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_gather_rows(const int32_t* __restrict__ src, int64_t n, int64_t width,
+                                                     const float* __restrict__ in, float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n * width) return;
+    const int64_t r = i / width;
+    out[i] = in[(int64_t)src[r] * width + (i - r * width)];
+}
+
+// sum += x; acc[0] += ||x||^2; acc[1] += ||sum after the update||^2 (acc[1] cleared by the caller).
+__global__ void __launch_bounds__(256) k_grad_moments(const float* __restrict__ x, int64_t n,
+                                                      double* __restrict__ sum, double* __restrict__ acc) {
+    __shared__ double red[2][4];
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double v = (double)x[i];
+        const double s = sum[i] + v;
+        sum[i] = s;
+        a0 += v * v;
+        a1 += s * s;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a0 += __shfl_down(a0, o, 64);
+        a1 += __shfl_down(a1, o, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = a0;
+        red[1][w] = a1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(acc, red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+        atomicAdd(acc + 1, red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+    }
+}
+
+__global__ void k_fill_f64(double* p, int n, double v) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = v;
+}
+
+void launch_adam(float* means, float* scales, float* quats, float* opac, float* sh, const GradArgs& gr, float* mom,
+                 int64_t P, int sh_degree, const AdamArgs& a, hipStream_t s) {
+    const int K = (sh_degree + 1) * (sh_degree + 1);
+    const int64_t n = P * (11 + 3 * K);
+    if (!n) return;
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, means, scales, quats, opac, sh,
+                       gr.means, gr.scales, gr.quats, gr.opac, gr.sh, reinterpret_cast<float2*>(mom), P, K, a);
+}
+
+void launch_gather_rows(const int32_t* src, int64_t n, int64_t width, const float* in, float* out, hipStream_t s) {
+    if (!n || !width) return;
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((n * width + 255) / 256)), dim3(256), 0, s, src, n, width, in,
+                       out);
+}
+
+void launch_grad_moments(const float* x, int64_t n, double* sum, double* acc, hipStream_t s) {
+    if (!n) return;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_grad_moments, dim3((unsigned)blocks), dim3(256), 0, s, x, n, sum, acc);
+}
+
+void fill_f64(double* p, int n, double v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, p, n, v);
+}
+
+}  // namespace mvgs

@@ -152,6 +152,8 @@ void launch_blend_fwd_sel(const SelBlendArgs& a, hipStream_t s);
 void launch_blend_bwd_sel(const SelBlendArgs& a, hipStream_t s);
 void launch_subsample(const uint32_t* keys, int W, int H, int B, int tw, int th, uint32_t* sel_off,
                       uint32_t* sel_pix, void* scan_scratch, hipStream_t s);
+void launch_sel_merge(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off, const uint32_t* sel_pix,
+                      const float* const* planes, int C, uint32_t plane_px, float* out, hipStream_t s);
 void launch_sel_scatter(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off, const uint32_t* sel_pix,
                         const float* v_sel, float* const* out, hipStream_t s);
 void launch_frame_work_sel(const DevCam* cams, int B, uint32_t n_tiles, const uint2* ranges, const uint32_t* vals,
@@ -166,6 +168,18 @@ void launch_adc_classify(const GaussianArgs& ga, const float* e1, const float* e
                          const AdcParams& prm, uint32_t* n_out, uint8_t* action, hipStream_t s);
 void launch_adc_write(const GaussianArgs& ga, const float* normals, const uint8_t* action, const uint32_t* off,
                       float* means, float* scales, float* quats, float* opac, float* sh, int32_t* src, hipStream_t s);
+
+// k_train.hip: optimiser step, state gather and gradient moments of the training loop
+struct AdamArgs {
+    float lr_means, lr_scales, lr_quats, lr_opacities, lr_sh_dc, lr_sh_rest;
+    float beta1, beta2, eps;
+    float bc1, bc2;   // bias corrections 1 - beta^step
+};
+void launch_adam(float* means, float* scales, float* quats, float* opac, float* sh, const GradArgs& gr, float* mom,
+                 int64_t P, int sh_degree, const AdamArgs& a, hipStream_t s);
+void launch_gather_rows(const int32_t* src, int64_t n, int64_t width, const float* in, float* out, hipStream_t s);
+void launch_grad_moments(const float* x, int64_t n, double* sum, double* acc, hipStream_t s);
+void fill_f64(double* p, int n, double v, hipStream_t s);
 
 // k_loss3d.hip: L1 + 3D distance-aware D-SSIM on the merged plane of a thread-efficient partial
 // frame whose selection covers the plane once

@@ -7,6 +7,7 @@ forward, loss and backward runs in libmvgs's kernels.
 from __future__ import annotations
 
 import ctypes as C
+import math
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -52,6 +53,13 @@ class GaussianTensors:
             if tuple(t.shape) != shp or t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
                 raise ValueError(f"{n}: expected contiguous float32 cuda tensor of shape {shp}, got "
                                  f"{tuple(t.shape)} {t.dtype} on {t.device}")
+
+
+def _check_grads(g: GaussianTensors, grads: dict):
+    for name in ("means", "scales", "quats", "opacities", "sh"):
+        t = grads[name]
+        if t.shape != getattr(g, name).shape or t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError(f"grads[{name!r}] does not match the Gaussians")
 
 
 class Frame:
@@ -198,9 +206,7 @@ class Rasterizer:
             grads = dict(means=torch.empty_like(g.means), scales=torch.empty_like(g.scales),
                          quats=torch.empty_like(g.quats), opacities=torch.empty_like(g.opacities),
                          sh=torch.empty_like(g.sh))
-        gr = L.mvgs_grads()
-        gr.means, gr.scales, gr.quats = grads["means"].data_ptr(), grads["scales"].data_ptr(), grads["quats"].data_ptr()
-        gr.opacities, gr.sh = grads["opacities"].data_ptr(), grads["sh"].data_ptr()
+        gr = self._grads(grads)
         dz = None
         if densify is not None:
             dz = L.mvgs_densify()
@@ -243,6 +249,25 @@ class Rasterizer:
                                       grad.data_ptr()), self.ctx)
         return out, grad
 
+    def merge(self, frame: Frame, planes, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Per-view [C,H,W] planes merged into the partial frame's image plane (selected pixels of
+        each view from that view's plane; others of `out`, zero if it is new, are kept)."""
+        planes = [p.contiguous() for p in planes]
+        c0 = frame.cams[0]
+        if len(planes) != len(frame.cams):
+            raise ValueError(f"{len(planes)} planes for {len(frame.cams)} views")
+        for p in planes:
+            if p.dim() != 3 or tuple(p.shape[1:]) != (c0.height, c0.width) or p.shape[0] != planes[0].shape[0] \
+                    or p.dtype != torch.float32 or not p.is_cuda:
+                raise ValueError(f"planes: expected float32 cuda [C, {c0.height}, {c0.width}] tensors")
+        if out is None:
+            out = torch.zeros_like(planes[0])
+        elif tuple(out.shape) != tuple(planes[0].shape) or out.dtype != torch.float32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor shaped like the planes")
+        L.check(self.lib.mvgs_frame_merge(self.ctx, _stream(), frame.handle, L.ptr_array([p.data_ptr() for p in planes]),
+                                          int(planes[0].shape[0]), out.data_ptr()), self.ctx)
+        return out
+
     def export_depth(self, frame: Frame, outs=None):
         if outs is None:
             outs = [torch.zeros((c.height, c.width), dtype=torch.float32, device="cuda") for c in frame.cams]
@@ -259,6 +284,12 @@ class Rasterizer:
         P = g.P
         K = (g.sh_degree + 1) ** 2
         dev = g.means.device
+        for name, dt in (("e1", torch.float32), ("e2", torch.float32), ("count", torch.int32)):
+            t = stats[name]
+            if tuple(t.shape) != (P,) or t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name}: expected contiguous {dt} cuda tensor of shape ({P},)")
+        if tuple(normals.shape) != (P, 2, 3) or normals.dtype != torch.float32 or not normals.is_cuda:
+            raise ValueError(f"normals: expected float32 cuda tensor of shape ({P}, 2, 3)")
         cap = max(2 * P, 1)
         out = GaussianTensors(torch.empty((cap, 3), device=dev), torch.empty((cap, 3), device=dev),
                               torch.empty((cap, 4), device=dev), torch.empty(cap, device=dev),
@@ -276,6 +307,54 @@ class Rasterizer:
         res = GaussianTensors(out.means[:m].contiguous(), out.scales[:m].contiguous(), out.quats[:m].contiguous(),
                               out.opacities[:m].contiguous(), out.sh[:m].contiguous(), g.sh_degree)
         return res, src[:m]
+
+    @staticmethod
+    def _grads(grads: dict) -> L.mvgs_grads:
+        gr = L.mvgs_grads()
+        gr.means, gr.scales, gr.quats = grads["means"].data_ptr(), grads["scales"].data_ptr(), grads["quats"].data_ptr()
+        gr.opacities, gr.sh = grads["opacities"].data_ptr(), grads["sh"].data_ptr()
+        return gr
+
+    def adam_step(self, g: GaussianTensors, grads: dict, moments: torch.Tensor, step: int, lr: dict,
+                  beta1=0.9, beta2=0.999, eps=1e-15):
+        """One in-place Adam step of the activated parameters g (log-scale and opacity-logit
+        coordinates for scales and opacities); moments: float32 [P, 11 + 3K, 2], zero at first.
+        lr: dict(means, scales, quats, opacities, sh_dc, sh_rest)."""
+        g.check()
+        K = (g.sh_degree + 1) ** 2
+        _check_grads(g, grads)
+        if tuple(moments.shape) != (g.P, 11 + 3 * K, 2) or moments.dtype != torch.float32 or \
+                not moments.is_contiguous() or not moments.is_cuda:
+            raise ValueError(f"moments: expected float32 {(g.P, 11 + 3 * K, 2)}, got {tuple(moments.shape)}")
+        o = L.mvgs_gaussians_out(g.means.data_ptr(), g.scales.data_ptr(), g.quats.data_ptr(), g.opacities.data_ptr(),
+                                 g.sh.data_ptr())
+        prm = L.mvgs_adam_params(lr["means"], lr["scales"], lr["quats"], lr["opacities"], lr["sh_dc"], lr["sh_rest"],
+                                 beta1, beta2, eps, int(step))
+        L.check(self.lib.mvgs_adam_step(self.ctx, _stream(), g.P, g.sh_degree, C.byref(o),
+                                        C.byref(self._grads(grads)), moments.data_ptr(), C.byref(prm)), self.ctx)
+
+    def gather_rows(self, src: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+        """x[src] for a float32 tensor whose first axis indexes Gaussians, on the GPU."""
+        x = x.contiguous()
+        n = int(src.numel())
+        width = math.prod(int(d) for d in x.shape[1:])
+        out = torch.empty((n,) + tuple(x.shape[1:]), dtype=x.dtype, device=x.device)
+        if x.dtype != torch.float32 or src.dtype != torch.int32:
+            raise ValueError("gather_rows takes float32 rows and int32 indices")
+        L.check(self.lib.mvgs_gather_rows(self.ctx, _stream(), src.data_ptr(), n, width, x.data_ptr(),
+                                          out.data_ptr()), self.ctx)
+        return out
+
+    def grad_moments(self, g: GaussianTensors, grads: dict, sum_: torch.Tensor, acc: torch.Tensor):
+        """Adds one mini-batch gradient to the running moments (sum float64 [P (11 + 3K)], acc
+        float64 [2]) of the Monte Carlo variance estimate."""
+        n = g.P * (11 + 3 * (g.sh_degree + 1) ** 2)
+        for t, want in ((sum_, n), (acc, 2)):
+            if t.dtype != torch.float64 or t.numel() != want or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"moment buffer: expected contiguous float64 cuda tensor of {want} elements")
+        _check_grads(g, grads)
+        L.check(self.lib.mvgs_grad_moments(self.ctx, _stream(), g.P, g.sh_degree, C.byref(self._grads(grads)),
+                                           sum_.data_ptr(), acc.data_ptr()), self.ctx)
 
     def export_transmittance(self, frame: Frame):
         outs = [torch.empty((c.height, c.width), dtype=torch.float32, device="cuda") for c in frame.cams]
