@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-partial", action="store_true", help="skip the partial-rendering comparison")
     ap.add_argument("--partial-views", type=int, default=8)
     ap.add_argument("--partial-size", default="1280x720")
+    ap.add_argument("--no-variance", action="store_true", help="skip the mini-batch gradient variance measurement")
+    ap.add_argument("--variance-batches", type=int, default=24)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -197,6 +199,8 @@ def main():
     if not args.no_partial:
         partial = partial_bench(args, g, wl, tile, ppl)
 
+    variance = None if args.no_variance else variance_bench(args, tile, ppl)
+
     serve = None
     if args.serve_requests > 0:
         rast.close()
@@ -243,6 +247,7 @@ def main():
                             for k in ("blend_fwd", "blend_bwd")},
         "roofline": roof,
         "partial": partial,
+        "grad_variance": variance,
         "serve": serve,
         "cpu_baseline": cpu,
     }
@@ -332,6 +337,48 @@ def partial_bench(args, g, wl, tile, ppl):
     out["compact_vs_full_speedup"] = out["full"]["ms_per_step"] / out["compact"]["ms_per_step"]
     out["compact_vs_masked_speedup"] = out["masked"]["ms_per_step"] / out["compact"]["ms_per_step"]
     out["compact_vs_single_view_overhead"] = out["compact"]["ms_per_step"] / out["single"]["ms_per_step"]
+    return out
+
+
+def variance_bench(args, tile, ppl):
+    """Variance of mini-batch gradients (Sec. 3.2) on the 300k-Gaussian SH-3 scene with 16 views
+    of 1600x1064: one whole view per batch, four whole views, and four views sharing one image
+    plane by partial rendering (Alg. 3, as many pixels as one view). L1 loss, seeded batches."""
+    import numpy as np
+    import torch
+
+    from paper_2506_12727_amd import scenes
+    from paper_2506_12727_amd.raster import GaussianTensors, Rasterizer
+    from paper_2506_12727_amd.train import variance_partial, variance_views
+
+    wl = scenes.WORKLOADS["train_300k_4x1600x1064_dssim"]
+    N, B, K = 16, 4, args.variance_batches
+    g = GaussianTensors.from_scene(wl.scene())
+    cams = scenes.make_cameras([(1600, 1064)] * N, seed=41)
+    tg = [torch.from_numpy(t).cuda() for t in scenes.make_targets(cams, seed=42)]
+    rng = np.random.default_rng(43)
+    singles = [[int(rng.integers(N))] for _ in range(K)]
+    multis = [[int(v) for v in rng.choice(N, size=B, replace=False)] for _ in range(K)]
+    keys = [torch.from_numpy(rng.integers(0, 2 ** 32, size=1600 * 1064, dtype=np.uint64).astype(np.uint32)
+                             .view(np.int32)).cuda() for _ in range(K)]
+    r = Rasterizer(tile, ppl)
+    out = {"scene": "300k Gaussians, SH 3", "views": N, "size": [1600, 1064], "batch_views": B, "batches": K,
+           "loss": "L1"}
+    variance_views(r, g, cams, tg, singles[:2])          # warm-up
+    for name, fn in (("single_view", lambda: variance_views(r, g, cams, tg, singles)),
+                     ("multi_view", lambda: variance_views(r, g, cams, tg, multis)),
+                     ("partial", lambda: variance_partial(r, g, cams, tg, multis, keys))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = fn()
+        torch.cuda.synchronize()
+        res["ms_per_batch"] = 1e3 * (time.perf_counter() - t0) / K
+        out[name] = res
+    r.close()
+    v1 = out["single_view"]["variance"]
+    out["ratio_multi_to_single"] = out["multi_view"]["variance"] / v1
+    out["ratio_partial_to_single"] = out["partial"]["variance"] / v1
+    out["sampling_law_ratio"] = (N - B) / (B * (N - 1))
     return out
 
 

@@ -56,13 +56,41 @@ __global__ void __launch_bounds__(256) k_points3d(const DevCam* __restrict__ cam
     }
 }
 
-// weight of neighbour q in the window of centre c
-__device__ __forceinline__ float weight3d(const double4& pc, const double4& pq, bool self) {
-    if (!(pc.w > 0.0)) return self ? 1.0f : 0.0f;
-    if (!(pq.w > 0.0)) return 0.0f;
-    const double dx = pq.x - pc.x, dy = pq.y - pc.y, dz = pq.z - pc.z;
-    const double e = (dx * dx + dy * dy + dz * dz) / (2.0 * pc.w * pc.w);
-    return __builtin_expf(-(float)e);
+// The two window passes work on 16 x 16 pixels per workgroup with the 26 x 26 neighbourhood
+// (5-pixel halo) staged in LDS: points as double (their differences are taken in double, then
+// rounded), the exponent factor k = log2(e) / (2 s^2) of each pixel's own sigma (kNoPoint where
+// nothing was blended, kOutside beyond the image), and the colours or the coefficients.
+// The weight of neighbour q in the window of centre c is exp2(-|P(q) - P(c)|^2 k_c); a centre
+// without a point keeps only itself, a neighbour without a point has no weight.
+constexpr int kT = 16, kHalo = kT + 2 * kWin, kHN = kHalo * kHalo;
+constexpr float kNoPoint = -1.0f, kOutside = -2.0f;
+constexpr double kLog2e = 1.4426950408889634;
+
+struct HaloPoints {
+    double px[kHN], py[kHN], pz[kHN];
+    float k[kHN];
+};
+
+__device__ __forceinline__ void stage_points(const double4* __restrict__ pts, int W, int H, int x0, int y0,
+                                             HaloPoints& h) {
+    for (int i = threadIdx.x; i < kHN; i += 256) {
+        const int gx = x0 - kWin + i % kHalo, gy = y0 - kWin + i / kHalo;
+        double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
+        float k = kOutside;
+        if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+            p = pts[(size_t)gy * W + gx];
+            k = p.w > 0.0 ? (float)(kLog2e / (2.0 * p.w * p.w)) : kNoPoint;
+        }
+        h.px[i] = p.x;
+        h.py[i] = p.y;
+        h.pz[i] = p.z;
+        h.k[i] = k;
+    }
+}
+
+__device__ __forceinline__ float pair_weight(const HaloPoints& h, int c, int q, float kc) {
+    const float dx = (float)(h.px[q] - h.px[c]), dy = (float)(h.py[q] - h.py[c]), dz = (float)(h.pz[q] - h.pz[c]);
+    return __builtin_amdgcn_exp2f(-(dx * dx + dy * dy + dz * dz) * kc);
 }
 
 // Per centre: weighted moments over the window, SSIM per channel, loss partial sums (per
@@ -71,28 +99,47 @@ __device__ __forceinline__ float weight3d(const double4& pc, const double4& pq, 
 __global__ void __launch_bounds__(256) k_ssim3d_fwd(const float* __restrict__ img, const float* __restrict__ tgt,
                                                     const double4* __restrict__ pts, int W, int H,
                                                     float* __restrict__ coef, double* __restrict__ partial) {
-    __shared__ double red[2][256];
-    const int x = blockIdx.x * 16 + (threadIdx.x & 15), y = blockIdx.y * 16 + (threadIdx.x >> 4);
+    __shared__ HaloPoints h;
+    __shared__ float col[6][kHN];
+    __shared__ double red[2][4];
+    const int x0 = blockIdx.x * kT, y0 = blockIdx.y * kT;
     const size_t hw = (size_t)W * H;
+    stage_points(pts, W, H, x0, y0, h);
+    for (int i = threadIdx.x; i < kHN; i += 256) {
+        const int gx = x0 - kWin + i % kHalo, gy = y0 - kWin + i / kHalo;
+        const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const size_t g = in ? (size_t)gy * W + gx : 0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            col[ch][i] = in ? img[ch * hw + g] : 0.0f;
+            col[3 + ch][i] = in ? tgt[ch * hw + g] : 0.0f;
+        }
+    }
+    __syncthreads();
+    const int lx = threadIdx.x & 15, ly = threadIdx.x >> 4;
+    const int x = x0 + lx, y = y0 + ly;
     double s_ssim = 0.0, s_l1 = 0.0;
     if (x < W && y < H) {
-        const size_t c = (size_t)y * W + x;
-        const double4 pc = pts[c];
+        const int ci = (ly + kWin) * kHalo + lx + kWin;
+        const float kc = h.k[ci];
         float sw = 0.0f, m1[3] = {0, 0, 0}, m2[3] = {0, 0, 0}, e11[3] = {0, 0, 0}, e22[3] = {0, 0, 0},
               e12[3] = {0, 0, 0};
         for (int dy = -kWin; dy <= kWin; ++dy) {
-            const int qy = y + dy;
-            if (qy < 0 || qy >= H) continue;
+            const int row = ci + dy * kHalo;
             for (int dx = -kWin; dx <= kWin; ++dx) {
-                const int qx = x + dx;
-                if (qx < 0 || qx >= W) continue;
-                const size_t q = (size_t)qy * W + qx;
-                const float w = weight3d(pc, pts[q], dx == 0 && dy == 0);
+                const int q = row + dx;
+                float w;
+                if (kc < 0.0f) {
+                    w = q == ci ? 1.0f : 0.0f;
+                } else {
+                    if (h.k[q] < 0.0f) continue;
+                    w = pair_weight(h, ci, q, kc);
+                }
                 if (w == 0.0f) continue;
                 sw += w;
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
-                    const float a = img[ch * hw + q], b = tgt[ch * hw + q];
+                    const float a = col[ch][q], b = col[3 + ch][q];
                     const float wa = w * a, wb = w * b;
                     m1[ch] += wa;
                     m2[ch] += wb;
@@ -102,6 +149,7 @@ __global__ void __launch_bounds__(256) k_ssim3d_fwd(const float* __restrict__ im
                 }
             }
         }
+        const size_t c = (size_t)y * W + x;
         const float inv = 1.0f / sw;
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
@@ -118,23 +166,22 @@ __global__ void __launch_bounds__(256) k_ssim3d_fwd(const float* __restrict__ im
             coef[(size_t)(3 * ch + 1) * hw + c] = 2.0f * ds11 * inv;
             coef[(size_t)(3 * ch + 2) * hw + c] = ds12 * inv;
             s_ssim += (double)S;
-            s_l1 += (double)fabsf(img[ch * hw + c] - tgt[ch * hw + c]);
+            s_l1 += (double)fabsf(col[ch][ci] - col[3 + ch][ci]);
         }
     }
-    red[0][threadIdx.x] = s_ssim;
-    red[1][threadIdx.x] = s_l1;
+    for (int o = 32; o > 0; o >>= 1) {
+        s_ssim += __shfl_down(s_ssim, o, 64);
+        s_l1 += __shfl_down(s_l1, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = s_ssim;
+        red[1][threadIdx.x >> 6] = s_l1;
+    }
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + off];
-            red[1][threadIdx.x] += red[1][threadIdx.x + off];
-        }
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
         const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-        partial[2 * b] = red[0][0];
-        partial[2 * b + 1] = red[1][0];
+        partial[2 * b] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        partial[2 * b + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
     }
 }
 
@@ -144,30 +191,48 @@ __global__ void __launch_bounds__(256) k_ssim3d_bwd(const float* __restrict__ im
                                                     const double4* __restrict__ pts, const float* __restrict__ coef,
                                                     int W, int H, float w_l1, float w_dssim,
                                                     float* __restrict__ grad) {
-    const int x = blockIdx.x * 16 + (threadIdx.x & 15), y = blockIdx.y * 16 + (threadIdx.x >> 4);
+    __shared__ HaloPoints h;
+    __shared__ float cf[9][kHN];
+    const int x0 = blockIdx.x * kT, y0 = blockIdx.y * kT;
+    const size_t hw = (size_t)W * H;
+    stage_points(pts, W, H, x0, y0, h);
+    for (int i = threadIdx.x; i < kHN; i += 256) {
+        const int gx = x0 - kWin + i % kHalo, gy = y0 - kWin + i / kHalo;
+        const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const size_t g = in ? (size_t)gy * W + gx : 0;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) cf[j][i] = in ? coef[(size_t)j * hw + g] : 0.0f;
+    }
+    __syncthreads();
+    const int lx = threadIdx.x & 15, ly = threadIdx.x >> 4;
+    const int x = x0 + lx, y = y0 + ly;
     if (x >= W || y >= H) return;
-    const size_t hw = (size_t)W * H, q = (size_t)y * W + x;
-    const double4 pq = pts[q];
+    const size_t q = (size_t)y * W + x;
+    const int qi = (ly + kWin) * kHalo + lx + kWin;
     float a[3], b[3], acc[3] = {0, 0, 0};
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         a[ch] = img[ch * hw + q];
         b[ch] = tgt[ch * hw + q];
     }
-    for (int dy = -kWin; dy <= kWin; ++dy) {
-        const int cy = y + dy;
-        if (cy < 0 || cy >= H) continue;
-        for (int dx = -kWin; dx <= kWin; ++dx) {
-            const int cx = x + dx;
-            if (cx < 0 || cx >= W) continue;
-            const size_t c = (size_t)cy * W + cx;
-            const float w = weight3d(pts[c], pq, dx == 0 && dy == 0);
-            if (w == 0.0f) continue;
+    if (h.k[qi] < 0.0f) {
+        // no point here: only its own window holds it (with weight 1)
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const float t = coef[(size_t)(3 * ch) * hw + c] + coef[(size_t)(3 * ch + 1) * hw + c] * a[ch] +
-                                coef[(size_t)(3 * ch + 2) * hw + c] * b[ch];
-                acc[ch] = __builtin_fmaf(w, t, acc[ch]);
+        for (int ch = 0; ch < 3; ++ch) acc[ch] = cf[3 * ch][qi] + cf[3 * ch + 1][qi] * a[ch] + cf[3 * ch + 2][qi] * b[ch];
+    } else {
+        for (int dy = -kWin; dy <= kWin; ++dy) {
+            const int row = qi + dy * kHalo;
+            for (int dx = -kWin; dx <= kWin; ++dx) {
+                const int c = row + dx;
+                const float kc = h.k[c];
+                if (kc < 0.0f) continue;
+                const float w = pair_weight(h, c, qi, kc);
+                if (w == 0.0f) continue;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float t = cf[3 * ch][c] + cf[3 * ch + 1][c] * a[ch] + cf[3 * ch + 2][c] * b[ch];
+                    acc[ch] = __builtin_fmaf(w, t, acc[ch]);
+                }
             }
         }
     }
