@@ -20,14 +20,14 @@ constexpr int kWin = 5;                 // window radius: 11 x 11
 constexpr float kSigmaPx = 1.5f;
 constexpr float kC1 = 0.01f * 0.01f, kC2 = 0.03f * 0.03f;
 
-// One thread per selection segment: the surface point of each of its pixels, stored at the
+// One wavefront per selection segment: the surface point of each of its pixels, stored at the
 // pixel's plane position as (x, y, z, scale); scale 0 marks a pixel where nothing was blended.
 __global__ void __launch_bounds__(256) k_points3d(const DevCam* __restrict__ cams, int B, uint32_t n_tiles,
                                                   const uint32_t* __restrict__ sel_off,
                                                   const uint32_t* __restrict__ sel_pix,
                                                   const float* __restrict__ t_sel, const float* __restrict__ depth_sel,
                                                   double4* __restrict__ pts) {
-    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t t = blockIdx.x * 4u + (threadIdx.x >> 6);
     if (t >= n_tiles) return;
     int lo = 0, hi = B;
     while (hi - lo > 1) {
@@ -36,7 +36,7 @@ __global__ void __launch_bounds__(256) k_points3d(const DevCam* __restrict__ cam
         else hi = mid;
     }
     const DevCam& c = cams[lo];
-    for (uint32_t i = sel_off[t]; i < sel_off[t + 1]; ++i) {
+    for (uint32_t i = sel_off[t] + (threadIdx.x & 63u); i < sel_off[t + 1]; i += 64u) {
         const uint32_t p = sel_pix[i];
         const double a = 1.0 - (double)t_sel[i];
         double4 out = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -286,7 +286,7 @@ void launch_loss3d(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* 
     double* partial = (double*)p;
     const dim3 grid((W + 15) / 16, (H + 15) / 16);
     const int blocks = (int)(grid.x * grid.y);
-    hipLaunchKernelGGL(k_points3d, dim3((n_tiles + 255) / 256), dim3(256), 0, s, cams, B, n_tiles, sel_off, sel_pix,
+    hipLaunchKernelGGL(k_points3d, dim3((n_tiles + 3) / 4), dim3(256), 0, s, cams, B, n_tiles, sel_off, sel_pix,
                        t_sel, depth_sel, pts);
     hipLaunchKernelGGL(k_ssim3d_fwd, grid, dim3(256), 0, s, img, tgt, pts, W, H, coef, partial);
     hipLaunchKernelGGL(k_ssim3d_bwd, grid, dim3(256), 0, s, img, tgt, pts, coef, W, H, w_l1, w_dssim, grad);

@@ -16,7 +16,7 @@
 
 namespace mvgs {
 
-// One thread per segment (plus one for the closing offset): offsets must rise from 0 to n_sel,
+// One wavefront per segment (plus one for the closing offset): offsets must rise from 0 to n_sel,
 // a segment holds at most one tile of pixels, every pixel lies in its (view, tile) and appears
 // once. Marks the pixels in `mask` (zeroed by the caller) and counts the segment's tasks. With
 // plane_mask (views of one size, zeroed), also notes whether two views take the same position.
@@ -25,21 +25,28 @@ __global__ void __launch_bounds__(256) k_sel_check(const DevCam* __restrict__ ca
                                                    const uint32_t* __restrict__ sel_pix, uint32_t n_sel,
                                                    uint32_t* __restrict__ mask, uint32_t* __restrict__ plane_mask,
                                                    uint32_t* __restrict__ n_tasks, uint32_t* __restrict__ err) {
-    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    // one wavefront per segment, its lanes over the segment's entries
+    const uint32_t t = blockIdx.x * 4u + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
     if (t > n_tiles) return;
     if (t == n_tiles) {
-        if (sel_off[n_tiles] != n_sel) atomicOr(err, kSelBadOffsets);
+        if (lane == 0 && sel_off[n_tiles] != n_sel) atomicOr(err, kSelBadOffsets);
         return;
     }
-    n_tasks[t] = 0;
     const uint32_t a = sel_off[t], b = sel_off[t + 1];
     if ((t == 0 && a != 0) || a > b || b > n_sel) {
-        atomicOr(err, kSelBadOffsets);
+        if (lane == 0) {
+            n_tasks[t] = 0;
+            atomicOr(err, kSelBadOffsets);
+        }
         return;
     }
     const uint32_t cnt = b - a;
     if (cnt > (uint32_t)(tw * th)) {
-        atomicOr(err, kSelTooLong);
+        if (lane == 0) {
+            n_tasks[t] = 0;
+            atomicOr(err, kSelTooLong);
+        }
         return;
     }
     const DevCam& c = cams[find_view(cams, B, t)];
@@ -49,7 +56,7 @@ __global__ void __launch_bounds__(256) k_sel_check(const DevCam* __restrict__ ca
     const int x1 = min(x0 + tw, c.W), y1 = min(y0 + th, c.H);
     const uint32_t hw = (uint32_t)c.W * (uint32_t)c.H;
     uint32_t bad = 0;
-    for (uint32_t i = a; i < b; ++i) {
+    for (uint32_t i = a + lane; i < b; i += 64u) {
         const uint32_t p = sel_pix[i];
         if (p >= hw) {
             bad |= kSelOutside;
@@ -69,7 +76,7 @@ __global__ void __launch_bounds__(256) k_sel_check(const DevCam* __restrict__ ca
         }
     }
     if (bad) atomicOr(err, bad);
-    n_tasks[t] = (cnt + 63u) / 64u;
+    if (lane == 0) n_tasks[t] = (cnt + 63u) / 64u;
 }
 
 // Task table: task task_off[t] + j is chunk j of segment t. Writes past `cap` (possible only for
@@ -266,7 +273,7 @@ __global__ void k_zero_pair(unsigned long long* p) {
 void launch_sel_check(const DevCam* cams, int B, uint32_t n_tiles, int tw, int th, const uint32_t* sel_off,
                       const uint32_t* sel_pix, uint32_t n_sel, uint32_t* mask, uint32_t* plane_mask, uint32_t* n_tasks,
                       uint32_t* err, hipStream_t s) {
-    hipLaunchKernelGGL(k_sel_check, dim3((n_tiles + 1 + 255) / 256), dim3(256), 0, s, cams, B, n_tiles, tw, th,
+    hipLaunchKernelGGL(k_sel_check, dim3((n_tiles + 1 + 3) / 4), dim3(256), 0, s, cams, B, n_tiles, tw, th,
                        sel_off, sel_pix, n_sel, mask, plane_mask, n_tasks, err);
 }
 
@@ -276,10 +283,10 @@ __global__ void __launch_bounds__(256) k_sel_scatter_f(const DevCam* __restrict_
                                                        const uint32_t* __restrict__ sel_off,
                                                        const uint32_t* __restrict__ sel_pix,
                                                        const float* __restrict__ v_sel, float* const* __restrict__ out) {
-    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t t = blockIdx.x * 4u + (threadIdx.x >> 6);   // one wavefront per segment
     if (t >= n_tiles) return;
     float* o = out[find_view(cams, B, t)];
-    for (uint32_t i = sel_off[t]; i < sel_off[t + 1]; ++i) o[sel_pix[i]] = v_sel[i];
+    for (uint32_t i = sel_off[t] + (threadIdx.x & 63u); i < sel_off[t + 1]; i += 64u) o[sel_pix[i]] = v_sel[i];
 }
 
 // Per-view [C, H, W] planes of one size merged into one plane: each selected pixel takes the value
@@ -289,10 +296,10 @@ __global__ void __launch_bounds__(256) k_sel_merge(const DevCam* __restrict__ ca
                                                    const uint32_t* __restrict__ sel_pix,
                                                    const float* const* __restrict__ planes, int C, uint32_t plane_px,
                                                    float* __restrict__ out) {
-    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t t = blockIdx.x * 4u + (threadIdx.x >> 6);   // one wavefront per segment
     if (t >= n_tiles) return;
     const float* in = planes[find_view(cams, B, t)];
-    for (uint32_t i = sel_off[t]; i < sel_off[t + 1]; ++i) {
+    for (uint32_t i = sel_off[t] + (threadIdx.x & 63u); i < sel_off[t + 1]; i += 64u) {
         const uint32_t p = sel_pix[i];
         for (int c = 0; c < C; ++c) out[(size_t)c * plane_px + p] = in[(size_t)c * plane_px + p];
     }
@@ -301,7 +308,7 @@ __global__ void __launch_bounds__(256) k_sel_merge(const DevCam* __restrict__ ca
 void launch_sel_merge(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off, const uint32_t* sel_pix,
                       const float* const* planes, int C, uint32_t plane_px, float* out, hipStream_t s) {
     if (!n_tiles) return;
-    hipLaunchKernelGGL(k_sel_merge, dim3((n_tiles + 255) / 256), dim3(256), 0, s, cams, B, n_tiles, sel_off, sel_pix,
+    hipLaunchKernelGGL(k_sel_merge, dim3((n_tiles + 3) / 4), dim3(256), 0, s, cams, B, n_tiles, sel_off, sel_pix,
                        planes, C, plane_px, out);
 }
 
@@ -345,7 +352,7 @@ void launch_subsample(const uint32_t* keys, int W, int H, int B, int tw, int th,
 void launch_sel_scatter(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off, const uint32_t* sel_pix,
                         const float* v_sel, float* const* out, hipStream_t s) {
     if (!n_tiles) return;
-    hipLaunchKernelGGL(k_sel_scatter_f, dim3((n_tiles + 255) / 256), dim3(256), 0, s, cams, B, n_tiles, sel_off,
+    hipLaunchKernelGGL(k_sel_scatter_f, dim3((n_tiles + 3) / 4), dim3(256), 0, s, cams, B, n_tiles, sel_off,
                        sel_pix, v_sel, out);
 }
 
