@@ -278,7 +278,9 @@ int mvgs_gather_rows(mvgs_context* ctx, void* stream, const int32_t* src, int64_
  * concatenation means | scales | quats | opacities | SH of one backward's grads (n = P (11 + 3K)
  * elements). Adds it to sum (device double [n]); adds its squared norm to acc[0] and sets acc[1]
  * (device double [2]) to the squared norm of the updated sum. After k calls:
- * variance = acc[0] / k - acc[1] / k^2. No synchronization (may be captured). */
+ * variance = acc[0] / k - acc[1] / k^2. The sums are reduced in a fixed order (reproducible). No
+ * synchronization; the first call on a context allocates 16 KiB of partial sums, so capture a
+ * call only after one uncaptured call. */
 int mvgs_grad_moments(mvgs_context* ctx, void* stream, int64_t P, int32_t sh_degree, const mvgs_grads* grads,
                       double* sum, double* acc);
 

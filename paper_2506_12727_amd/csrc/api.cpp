@@ -218,7 +218,7 @@ struct mvgs_context {
     std::vector<mvgs_frame*> frames;
     DevBuf nrec, ntiles, totals, scan_scratch, depth_key[2], rec_vals[2], tile_rect, sorted_rect, pair_counts,
         pair_off;
-    DevBuf sort_scratch, acc, loss_scratch, ssim_maps, loss3d_scratch, adc_n, adc_off, adc_act;
+    DevBuf sort_scratch, acc, loss_scratch, ssim_maps, loss3d_scratch, adc_n, adc_off, adc_act, moment_partials;
     size_t limit = 0;  // 0: no workspace limit
     uint64_t cap_v = 0, cap_k = 0;  // capacity mode when non-zero
     bool capturing = false;         // the current call's stream is being captured into a graph
@@ -242,7 +242,8 @@ struct mvgs_context {
     void each_buffer(Fn fn) {
         DevBuf* bufs[] = {&nrec, &ntiles, &totals, &scan_scratch, &depth_key[0], &depth_key[1], &rec_vals[0],
                           &rec_vals[1], &tile_rect, &sorted_rect, &pair_counts, &pair_off, &sort_scratch, &acc,
-                          &loss_scratch, &ssim_maps, &loss3d_scratch, &adc_n, &adc_off, &adc_act, &work};
+                          &loss_scratch, &ssim_maps, &loss3d_scratch, &adc_n, &adc_off, &adc_act,
+                          &moment_partials, &work};
         for (DevBuf* b : bufs) fn(*b);
         for (auto& sl : ring.slots) fn(sl.dev);
         for (mvgs_frame* f : frames) f->each_buffer(fn);
@@ -1000,15 +1001,21 @@ int mvgs_grad_moments(mvgs_context* ctx, void* stream, int64_t P, int32_t sh_deg
         return ctx->fail(MVGS_EINVAL, "grads, sum or acc is NULL");
     HIPCHK(ctx, ctx->bind_device());
     hipStream_t s = (hipStream_t)stream;
+    ctx->begin(s);
+    const Need need[] = {{&ctx->moment_partials, sizeof(double) * 2 * kMomentBlocks}};
+    int st = grow_all(ctx, need, 1);
+    if (st) return st;
     const int64_t K = (int64_t)(sh_degree + 1) * (sh_degree + 1);
-    fill_f64(acc + 1, 1, 0.0, s);
+    GradSegments gs;
     const float* seg[5] = {grads->means, grads->scales, grads->quats, grads->opacities, grads->sh};
     const int64_t width[5] = {3, 3, 4, 1, 3 * K};
     int64_t at = 0;
     for (int k = 0; k < 5; ++k) {
-        launch_grad_moments(seg[k], P * width[k], sum + at, acc, s);
+        gs.x[k] = seg[k];
         at += P * width[k];
+        gs.end[k] = at;
     }
+    launch_grad_moments(gs, sum, acc, as<double>(ctx->moment_partials), s);
     LAUNCHCHK(ctx, "gradient moments");
     return MVGS_OK;
 }

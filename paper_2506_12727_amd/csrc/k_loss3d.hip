@@ -245,6 +245,36 @@ __global__ void __launch_bounds__(256) k_ssim3d_bwd(const float* __restrict__ im
     }
 }
 
+// L1 alone (w_dssim = 0): the gradient w_l1 sign(I - T) / N and per-workgroup L1 sums, with the
+// same grid and partial layout as the window passes.
+__global__ void __launch_bounds__(256) k_l1_plane(const float* __restrict__ img, const float* __restrict__ tgt,
+                                                  int W, int H, float w_l1, float* __restrict__ grad,
+                                                  double* __restrict__ partial) {
+    __shared__ double red[4];
+    const int x = blockIdx.x * kT + (threadIdx.x & 15), y = blockIdx.y * kT + (threadIdx.x >> 4);
+    const size_t hw = (size_t)W * H;
+    double s_l1 = 0.0;
+    if (x < W && y < H) {
+        const size_t q = (size_t)y * W + x;
+        const float invN = 1.0f / (3.0f * (float)hw);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const float d = img[ch * hw + q] - tgt[ch * hw + q];
+            const float sg = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
+            grad[ch * hw + q] = w_l1 * sg * invN;
+            s_l1 += (double)fabsf(d);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) s_l1 += __shfl_down(s_l1, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s_l1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        partial[2 * b] = 0.0;
+        partial[2 * b + 1] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
 __global__ void k_loss3d_final(const double* __restrict__ partial, int n, double N, float w_l1, float w_dssim,
                                float* __restrict__ out) {
     __shared__ double red[2][256];
@@ -286,10 +316,14 @@ void launch_loss3d(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* 
     double* partial = (double*)p;
     const dim3 grid((W + 15) / 16, (H + 15) / 16);
     const int blocks = (int)(grid.x * grid.y);
-    hipLaunchKernelGGL(k_points3d, dim3((n_tiles + 3) / 4), dim3(256), 0, s, cams, B, n_tiles, sel_off, sel_pix,
-                       t_sel, depth_sel, pts);
-    hipLaunchKernelGGL(k_ssim3d_fwd, grid, dim3(256), 0, s, img, tgt, pts, W, H, coef, partial);
-    hipLaunchKernelGGL(k_ssim3d_bwd, grid, dim3(256), 0, s, img, tgt, pts, coef, W, H, w_l1, w_dssim, grad);
+    if (w_dssim == 0.0f) {
+        hipLaunchKernelGGL(k_l1_plane, grid, dim3(256), 0, s, img, tgt, W, H, w_l1, grad, partial);
+    } else {
+        hipLaunchKernelGGL(k_points3d, dim3((n_tiles + 3) / 4), dim3(256), 0, s, cams, B, n_tiles, sel_off,
+                           sel_pix, t_sel, depth_sel, pts);
+        hipLaunchKernelGGL(k_ssim3d_fwd, grid, dim3(256), 0, s, img, tgt, pts, W, H, coef, partial);
+        hipLaunchKernelGGL(k_ssim3d_bwd, grid, dim3(256), 0, s, img, tgt, pts, coef, W, H, w_l1, w_dssim, grad);
+    }
     hipLaunchKernelGGL(k_loss3d_final, dim3(1), dim3(256), 0, s, partial, blocks, 3.0 * (double)hw, w_l1, w_dssim,
                        loss_out);
 }

@@ -72,13 +72,17 @@ __global__ void __launch_bounds__(256) k_gather_rows(const int32_t* __restrict__
     out[i] = in[(int64_t)src[r] * width + (i - r * width)];
 }
 
-// sum += x; acc[0] += ||x||^2; acc[1] += ||sum after the update||^2 (acc[1] cleared by the caller).
-__global__ void __launch_bounds__(256) k_grad_moments(const float* __restrict__ x, int64_t n,
-                                                      double* __restrict__ sum, double* __restrict__ acc) {
+// sum += x over the concatenation of the five gradient tensors; per workgroup, the partial sums
+// of ||x||^2 and of ||sum after the update||^2 (fixed grid and order: the result is reproducible).
+__global__ void __launch_bounds__(256) k_grad_moments(GradSegments g, double* __restrict__ sum,
+                                                      double* __restrict__ partials) {
     __shared__ double red[2][4];
     double a0 = 0.0, a1 = 0.0;
+    const int64_t n = g.end[4];
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const double v = (double)x[i];
+        int k = 0;
+        while (i >= g.end[k]) ++k;
+        const double v = (double)g.x[k][i - (k ? g.end[k - 1] : 0)];
         const double s = sum[i] + v;
         sum[i] = s;
         a0 += v * v;
@@ -95,13 +99,34 @@ __global__ void __launch_bounds__(256) k_grad_moments(const float* __restrict__ 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        atomicAdd(acc, red[0][0] + red[0][1] + red[0][2] + red[0][3]);
-        atomicAdd(acc + 1, red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+        partials[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        partials[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
     }
 }
 
-__global__ void k_fill_f64(double* p, int n, double v) {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = v;
+// acc[0] += sum of the squared-norm partials; acc[1] = sum of the partials of ||sum||^2.
+__global__ void __launch_bounds__(256) k_grad_moments_final(const double* __restrict__ partials, int blocks,
+                                                            double* __restrict__ acc) {
+    __shared__ double red[2][256];
+    double a0 = 0.0, a1 = 0.0;
+    for (int b = threadIdx.x; b < blocks; b += 256) {
+        a0 += partials[2 * b];
+        a1 += partials[2 * b + 1];
+    }
+    red[0][threadIdx.x] = a0;
+    red[1][threadIdx.x] = a1;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + o];
+            red[1][threadIdx.x] += red[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        acc[0] += red[0][0];
+        acc[1] = red[1][0];
+    }
 }
 
 void launch_adam(float* means, float* scales, float* quats, float* opac, float* sh, const GradArgs& gr, float* mom,
@@ -119,14 +144,11 @@ void launch_gather_rows(const int32_t* src, int64_t n, int64_t width, const floa
                        out);
 }
 
-void launch_grad_moments(const float* x, int64_t n, double* sum, double* acc, hipStream_t s) {
-    if (!n) return;
-    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_grad_moments, dim3((unsigned)blocks), dim3(256), 0, s, x, n, sum, acc);
-}
-
-void fill_f64(double* p, int n, double v, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, p, n, v);
+void launch_grad_moments(const GradSegments& g, double* sum, double* acc, double* partials, hipStream_t s) {
+    const int64_t n = g.end[4];
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 2047) / 2048, kMomentBlocks));
+    if (n) hipLaunchKernelGGL(k_grad_moments, dim3((unsigned)blocks), dim3(256), 0, s, g, sum, partials);
+    hipLaunchKernelGGL(k_grad_moments_final, dim3(1), dim3(256), 0, s, partials, n ? blocks : 0, acc);
 }
 
 }  // namespace mvgs

@@ -178,8 +178,14 @@ struct AdamArgs {
 void launch_adam(float* means, float* scales, float* quats, float* opac, float* sh, const GradArgs& gr, float* mom,
                  int64_t P, int sh_degree, const AdamArgs& a, hipStream_t s);
 void launch_gather_rows(const int32_t* src, int64_t n, int64_t width, const float* in, float* out, hipStream_t s);
-void launch_grad_moments(const float* x, int64_t n, double* sum, double* acc, hipStream_t s);
-void fill_f64(double* p, int n, double v, hipStream_t s);
+// the five gradient tensors (means, scales, quats, opacities, SH) as one vector: x[k] holds
+// elements [end[k-1], end[k]) of it
+struct GradSegments {
+    const float* x[5];
+    int64_t end[5];
+};
+constexpr int kMomentBlocks = 1024;   // workgroups of the moment pass (2 double partials each)
+void launch_grad_moments(const GradSegments& g, double* sum, double* acc, double* partials, hipStream_t s);
 
 // k_loss3d.hip: L1 + 3D distance-aware D-SSIM on the merged plane of a thread-efficient partial
 // frame whose selection covers the plane once

@@ -258,7 +258,7 @@ def test_partial_depth_matches_oracle():
     r.close()
 
 
-@pytest.mark.parametrize("w", [(0.8, 0.2), (0.0, 1.0)])
+@pytest.mark.parametrize("w", [(0.8, 0.2), (0.0, 1.0), (1.0, 0.0)])
 def test_loss3d_matches_oracle(w):
     needs_gpu()
     tile = (16, 16)
