@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--partial-size", default="1280x720")
     ap.add_argument("--no-variance", action="store_true", help="skip the mini-batch gradient variance measurement")
     ap.add_argument("--variance-batches", type=int, default=24)
+    ap.add_argument("--no-train", action="store_true", help="skip the training-iteration comparison")
+    ap.add_argument("--train-steps", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -200,6 +202,7 @@ def main():
         partial = partial_bench(args, g, wl, tile, ppl)
 
     variance = None if args.no_variance else variance_bench(args, tile, ppl)
+    training = None if args.no_train else train_bench(args, tile, ppl)
 
     serve = None
     if args.serve_requests > 0:
@@ -248,6 +251,7 @@ def main():
         "roofline": roof,
         "partial": partial,
         "grad_variance": variance,
+        "training": training,
         "serve": serve,
         "cpu_baseline": cpu,
     }
@@ -379,6 +383,43 @@ def variance_bench(args, tile, ppl):
     out["ratio_multi_to_single"] = out["multi_view"]["variance"] / v1
     out["ratio_partial_to_single"] = out["partial"]["variance"] / v1
     out["sampling_law_ratio"] = (N - B) / (B * (N - 1))
+    return out
+
+
+def train_bench(args, tile, ppl):
+    """Training iterations (forward, fused loss, backward with the densification statistics, one
+    Adam step) on the 300K-Gaussian SH-3 scene with a pool of 16 views of 1600x1064, as in the
+    paper's training-time comparison: one view per iteration, four whole views, and four views
+    sharing one image plane by thread-efficient partial rendering. 0.8 L1 + 0.2 D-SSIM (the 3D
+    distance-aware D-SSIM for the partial batches); targets are renders of a second draw."""
+    import torch
+
+    from paper_2506_12727_amd import scenes
+    from paper_2506_12727_amd.raster import GaussianTensors
+    from paper_2506_12727_amd.train import Trainer
+
+    wl = scenes.WORKLOADS["train_300k_4x1600x1064_dssim"]
+    cams = scenes.make_cameras([(1600, 1064)] * 16, seed=41)
+    gt = GaussianTensors.from_scene(scenes.make_scene(wl.P, wl.sh_degree, seed=7))
+    out = {"scene": "300K Gaussians, SH 3", "views": 16, "size": [1600, 1064], "steps": args.train_steps,
+           "loss": {"w_l1": 0.8, "w_dssim": 0.2}}
+    for name, B, partial in (("single_view", 1, False), ("multi_view", 4, False), ("partial", 4, True)):
+        g = GaussianTensors.from_scene(wl.scene())
+        t = Trainer(g, gt, cams, views_per_step=B, partial=partial, densify_every=0, tile=tile, ppl=ppl, seed=44)
+        for _ in range(3):
+            t.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.train_steps):
+            loss = t.step()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.train_steps
+        out[name] = {"views_per_step": B, "ms_per_step": ms, "views_per_s": 1e3 * B / ms,
+                     "last_loss": float(loss.item())}
+        t.close()
+        del t, g
+    out["partial_over_single_time"] = out["partial"]["ms_per_step"] / out["single_view"]["ms_per_step"]
+    out["multi_over_single_time"] = out["multi_view"]["ms_per_step"] / out["single_view"]["ms_per_step"]
     return out
 
 

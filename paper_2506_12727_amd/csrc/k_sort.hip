@@ -8,8 +8,8 @@
 // ceil(log2(total tiles)) bits). Ties in depth keep the (Gaussian, view) emission order of the
 // records, i.e. ascending Gaussian index within a view.
 //
-// Radix sort: LSD, digits of at most 8 bits spread evenly over the passes, 4096 items per
-// partition (4 wavefronts x 16 rounds x 64 lanes). One read of the keys builds the digit
+// Radix sort: LSD, digits of at most 8 bits spread evenly over the passes, 8192 items per
+// partition (4 wavefronts x 32 rounds x 64 lanes). One read of the keys builds the digit
 // histograms of every pass at once; then each pass is a single sweep: a workgroup takes the next
 // partition from an atomic counter, ranks its items stably with wave64 ballots, publishes its
 // per-digit counts, finds the exclusive prefix of each digit by looking back over earlier
@@ -27,9 +27,9 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;  // 4096
 
 constexpr int kSortWaves = 4;
-constexpr int kSortRounds = 16;
+constexpr int kSortRounds = 32;
 constexpr int kSortThreads = kSortWaves * 64;
-constexpr int kSortTile = kSortWaves * kSortRounds * 64;  // 4096
+constexpr int kSortTile = kSortWaves * kSortRounds * 64;  // 8192
 constexpr int kRadix = 256;
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
@@ -215,7 +215,7 @@ constexpr uint64_t kFlagPrefix = 2ull << 62;      // count of this and all earli
 constexpr uint64_t kFlagMask = 3ull << 62;
 constexpr uint32_t kSpinLimit = 1u << 24;
 
-// One stable pass: workgroups take partitions of 4096 items in launch order from an atomic counter,
+// One stable pass: workgroups take partitions of 8192 items in launch order from an atomic counter,
 // rank their items by digit with wave64 ballots, publish per-digit counts, add up the counts of the
 // earlier partitions (decoupled look-back: stop at the first published prefix), and scatter through
 // LDS in digit order. Each status word carries its count itself, so relaxed device-scope atomics

@@ -49,7 +49,7 @@ class Trainer:
     def __init__(self, g: GaussianTensors, gt: GaussianTensors, cams: Sequence, views_per_step: int = 4,
                  partial: bool = False, w_l1: float = 0.8, w_dssim: float = 0.2, lr: Optional[dict] = None,
                  densify: Optional[dict] = None, densify_from: int = 100, densify_until: int = 1000,
-                 densify_every: int = 100, tile=(16, 16), seed: int = 0):
+                 densify_every: int = 100, tile=(16, 16), ppl: int = 0, seed: int = 0):
         g.check()
         gt.check()
         self.g = g
@@ -64,7 +64,7 @@ class Trainer:
         self.lr = dict(DEFAULT_LR, **(lr or {}))
         self.adc = dict(DEFAULT_ADC, **(densify or {}))
         self.densify_from, self.densify_until, self.densify_every = densify_from, densify_until, densify_every
-        self.rast = Rasterizer(tile)
+        self.rast = Rasterizer(tile, ppl)
         self.dev = g.means.device
         self.gen = torch.Generator(device=self.dev)
         self.gen.manual_seed(seed)
