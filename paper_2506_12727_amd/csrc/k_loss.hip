@@ -182,14 +182,44 @@ __global__ void __launch_bounds__(kLossThreads) k_ssim_bv(const float* __restric
     grad[i] += s[0] + 2.0f * img[i] * s[1] + tgt[i] * s[2];
 }
 
-// Deterministic final reduction: loss = w_l1 * sum(l1 partials) / N + w_dssim * (1 - sum(ssim partials) / N).
-__global__ void __launch_bounds__(256) k_loss_final(const float* __restrict__ l1p, uint32_t n_l1,
-                                                    const float* __restrict__ sp, uint32_t n_s, double inv_n,
-                                                    float w_l1, float w_dssim, float* __restrict__ out) {
+// Deterministic reduction in two stages. First, each workgroup adds kReduceChunk consecutive
+// partials of the concatenation [l1 partials | ssim partials] into two doubles (one per kind).
+constexpr uint32_t kReduceChunk = 4096;
+
+__global__ void __launch_bounds__(256) k_loss_reduce(const float* __restrict__ partials, uint32_t n_l1,
+                                                     uint32_t n, double* __restrict__ out) {
+    __shared__ double red[2][4];
+    double a = 0.0, b = 0.0;
+    const uint32_t c0 = blockIdx.x * kReduceChunk, c1 = min(n, c0 + kReduceChunk);
+    for (uint32_t i = c0 + threadIdx.x; i < c1; i += 256) {
+        const double v = (double)partials[i];
+        if (i < n_l1) a += v;
+        else b += v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_down(a, o, 64);
+        b += __shfl_down(b, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = a;
+        red[1][threadIdx.x >> 6] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        out[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+}
+
+// Then loss = w_l1 * sum(l1 partials) / N + w_dssim * (1 - sum(ssim partials) / N).
+__global__ void __launch_bounds__(256) k_loss_final(const double* __restrict__ chunks, uint32_t n_chunks,
+                                                    double inv_n, float w_l1, float w_dssim, float* __restrict__ out) {
     __shared__ double red[2][256];
     double a = 0.0, b = 0.0;
-    for (uint32_t i = threadIdx.x; i < n_l1; i += 256) a += l1p[i];
-    for (uint32_t i = threadIdx.x; i < n_s; i += 256) b += sp[i];
+    for (uint32_t i = threadIdx.x; i < n_chunks; i += 256) {
+        a += chunks[2 * i];
+        b += chunks[2 * i + 1];
+    }
     red[0][threadIdx.x] = a;
     red[1][threadIdx.x] = b;
     __syncthreads();
@@ -222,8 +252,10 @@ static Win11 gaussian_window() {
 size_t loss_scratch_bytes(uint32_t total_pixels, int B) {
     // partials (l1 + ssim) then, per view in turn, 8 maps per channel of the largest view
     (void)B;
-    size_t n_l1 = (total_pixels + kLossThreads - 1) / kLossThreads;
-    return (n_l1 + 3 * (size_t)total_pixels / kLossThreads + 3 * (size_t)B + 64) * sizeof(float);
+    const size_t n_l1 = (total_pixels + kLossThreads - 1) / kLossThreads;
+    const size_t n_part = n_l1 + 3 * (size_t)total_pixels / kLossThreads + 3 * (size_t)B;
+    // float partials, then (8-byte aligned) two doubles per reduction chunk
+    return (n_part + 64) * sizeof(float) + 2 * sizeof(double) * (n_part / kReduceChunk + 2);
 }
 
 size_t ssim_map_bytes(uint32_t max_view_pixels) { return (size_t)max_view_pixels * 3 * 8 * sizeof(float); }
@@ -257,8 +289,12 @@ void launch_loss(const LossView* views_dev, const LossView* views_host, int B, u
                                lv.W, lv.H, win, lv.grad);
         }
     }
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, (const float*)partial, n_l1, (const float*)sp, n_s,
-                       1.0 / N, w_l1, w_dssim, loss_out);
+    const uint32_t n_part = n_l1 + n_s;
+    const uint32_t n_chunks = (n_part + kReduceChunk - 1) / kReduceChunk;
+    double* chunks = reinterpret_cast<double*>(((uintptr_t)(partial + n_part) + 7) & ~(uintptr_t)7);
+    hipLaunchKernelGGL(k_loss_reduce, dim3(n_chunks), dim3(256), 0, s, (const float*)partial, n_l1, n_part, chunks);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, (const double*)chunks, n_chunks, 1.0 / N, w_l1,
+                       w_dssim, loss_out);
 }
 
 }  // namespace mvgs

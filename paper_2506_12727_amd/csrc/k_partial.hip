@@ -56,23 +56,55 @@ __global__ void __launch_bounds__(256) k_sel_check(const DevCam* __restrict__ ca
     const int x1 = min(x0 + tw, c.W), y1 = min(y0 + th, c.H);
     const uint32_t hw = (uint32_t)c.W * (uint32_t)c.H;
     uint32_t bad = 0;
-    for (uint32_t i = a + lane; i < b; i += 64u) {
-        const uint32_t p = sel_pix[i];
-        if (p >= hw) {
-            bad |= kSelOutside;
-            continue;
+    for (uint32_t i0 = a; i0 < b; i0 += 64u) {   // whole wavefront in every round
+        const uint32_t i = i0 + lane;
+        bool in = false;
+        uint32_t p = 0;
+        if (i < b) {
+            p = sel_pix[i];
+            if (p >= hw) {
+                bad |= kSelOutside;
+            } else {
+                const int y = (int)(p / (uint32_t)c.W), x = (int)(p - (uint32_t)y * (uint32_t)c.W);
+                if (x < x0 || x >= x1 || y < y0 || y >= y1) bad |= kSelOutside;
+                else in = true;
+            }
         }
-        const int y = (int)(p / (uint32_t)c.W), x = (int)(p - (uint32_t)y * (uint32_t)c.W);
-        if (x < x0 || x >= x1 || y < y0 || y >= y1) {
-            bad |= kSelOutside;
-            continue;
-        }
-        const uint32_t gp = c.pix_base + p, bit = 1u << (gp & 31u);
-        if (atomicOr(mask + (gp >> 5), bit) & bit) bad |= kSelDuplicate;
-        // views of one size: is each position of the shared image plane taken by one view only?
-        if (plane_mask) {
-            const uint32_t pb = 1u << (p & 31u);
-            if (atomicOr(plane_mask + (p >> 5), pb) & pb) bad |= kSelPlaneOverlap;
+        const uint32_t gp = c.pix_base + p;
+        // strictly ascending pixels (as sub-sampling writes them): no duplicate inside this round,
+        // and pixels sharing a mask word sit in runs of neighbouring lanes, so each run sets its
+        // bits with one atomic from its last lane
+        // (a rejected pixel would leave a gap inside a run: then every lane takes the plain path)
+        const uint32_t gp_prev = (uint32_t)__shfl_up((int)gp, 1, 64);
+        const bool asc = ballot64((i < b && !in) || (in && lane > 0 && gp <= gp_prev)) == 0;
+        if (asc) {
+            uint32_t wd = in ? gp >> 5 : 0xffffffffu, bits = in ? 1u << (gp & 31u) : 0u;
+            uint32_t pw = in ? p >> 5 : 0xffffffffu, pbits = in ? 1u << (p & 31u) : 0u;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t ob = (uint32_t)__shfl_up((int)bits, off, 64);
+                const uint32_t ow = (uint32_t)__shfl_up((int)wd, off, 64);
+                const uint32_t opb = (uint32_t)__shfl_up((int)pbits, off, 64);
+                const uint32_t opw = (uint32_t)__shfl_up((int)pw, off, 64);
+                if ((int)lane >= off && ow == wd) bits |= ob;
+                if ((int)lane >= off && opw == pw) pbits |= opb;
+            }
+            const uint32_t wd_next = (uint32_t)__shfl_down((int)wd, 1, 64);
+            const uint32_t pw_next = (uint32_t)__shfl_down((int)pw, 1, 64);
+            if (in && (lane == 63 || wd_next != wd)) {
+                if (atomicOr(mask + wd, bits) & bits) bad |= kSelDuplicate;
+            }
+            // views of one size: is each position of the shared image plane taken by one view only?
+            if (plane_mask && in && (lane == 63 || pw_next != pw)) {
+                if (atomicOr(plane_mask + pw, pbits) & pbits) bad |= kSelPlaneOverlap;
+            }
+        } else if (in) {
+            const uint32_t bit = 1u << (gp & 31u);
+            if (atomicOr(mask + (gp >> 5), bit) & bit) bad |= kSelDuplicate;
+            if (plane_mask) {
+                const uint32_t pb = 1u << (p & 31u);
+                if (atomicOr(plane_mask + (p >> 5), pb) & pb) bad |= kSelPlaneOverlap;
+            }
         }
     }
     if (bad) atomicOr(err, bad);
@@ -194,44 +226,61 @@ __global__ void __launch_bounds__(256) k_subsample_counts(int W, int H, int B, i
     counts[s] = n > v ? (n - v + (uint32_t)B - 1u) / (uint32_t)B : 0u;
 }
 
-// Sub-sampling, step 2: one workgroup per tile ranks the tile's positions by (key, position) in
-// LDS; the position of rank r goes to view r mod B, and each view's positions are written in
-// ascending order (so the wavefronts of a segment cover compact bands of the tile).
+// Ascending bitonic sort of m (a power of two, at most 1024) 64-bit values in LDS by 256 threads.
+__device__ __forceinline__ void lds_bitonic_sort(uint64_t* s, int m) {
+    for (int k = 2; k <= m; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = (int)threadIdx.x; i < m; i += 256) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const uint64_t a = s[i], b = s[ixj];
+                    if ((a > b) == ((i & k) == 0)) {
+                        s[i] = b;
+                        s[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Sub-sampling, step 2: one workgroup per tile. The tile's positions (row-major index j) are
+// sorted in LDS by (key, j); the position of rank r goes to view r mod B. A second sort by
+// (view, j) lists each view's positions in ascending order (so the wavefronts of a segment cover
+// compact bands of the tile); view v's run starts at v floor(n / B) + min(v, n mod B).
 __global__ void __launch_bounds__(256) k_subsample_scatter(const uint32_t* __restrict__ keys, int W, int H, int B,
                                                            int tw, int th, int tiles_x, uint32_t tiles_per_view,
                                                            const uint32_t* __restrict__ sel_off,
                                                            uint32_t* __restrict__ sel_pix) {
-    __shared__ uint32_t k_s[1024];
-    __shared__ uint32_t p_s[1024];
-    __shared__ uint32_t v_s[1024];
+    __shared__ uint64_t s[1024];
     const uint32_t t = blockIdx.x;
     const int ty = (int)(t / (uint32_t)tiles_x), tx = (int)t - ty * tiles_x;
     const int x0 = tx * tw, y0 = ty * th;
     const int w = min(W, x0 + tw) - x0, h = min(H, y0 + th) - y0;
     const int n = w * h;
-    for (int j = (int)threadIdx.x; j < n; j += 256) {
-        const uint32_t p = (uint32_t)(y0 + j / w) * (uint32_t)W + (uint32_t)(x0 + j % w);
-        p_s[j] = p;
-        k_s[j] = keys[p];
-    }
-    __syncthreads();
-    for (int j = (int)threadIdx.x; j < n; j += 256) {
-        const uint32_t kj = k_s[j], pj = p_s[j];
-        uint32_t r = 0;
-        for (int m = 0; m < n; ++m) {
-            const uint32_t km = k_s[m];
-            r += (km < kj || (km == kj && p_s[m] < pj)) ? 1u : 0u;
+    int m = 1;
+    while (m < n) m <<= 1;
+    for (int j = (int)threadIdx.x; j < m; j += 256) {
+        uint64_t v = ~0ull;
+        if (j < n) {
+            const uint32_t p = (uint32_t)(y0 + j / w) * (uint32_t)W + (uint32_t)(x0 + j % w);
+            v = ((uint64_t)keys[p] << 32) | (uint32_t)j;
         }
-        v_s[j] = r % (uint32_t)B;
+        s[j] = v;
     }
     __syncthreads();
-    // positions j are in ascending order (row-major inside the tile): the entry of j in its view's
-    // segment is the number of earlier positions of the same view
-    for (int j = (int)threadIdx.x; j < n; j += 256) {
-        const uint32_t v = v_s[j];
-        uint32_t e = 0;
-        for (int m = 0; m < j; ++m) e += v_s[m] == v ? 1u : 0u;
-        sel_pix[sel_off[v * tiles_per_view + t] + e] = p_s[j];
+    lds_bitonic_sort(s, m);
+    for (int r = (int)threadIdx.x; r < n; r += 256)
+        s[r] = ((uint64_t)(uint32_t)(r % B) << 32) | (uint32_t)(s[r] & 0xffffffffu);
+    __syncthreads();
+    lds_bitonic_sort(s, m);
+    const int q = n / B, rem = n - q * B;
+    for (int i = (int)threadIdx.x; i < n; i += 256) {
+        const int v = (int)(s[i] >> 32), j = (int)(s[i] & 0xffffffffu);
+        const int e = i - (v * q + min(v, rem));
+        const uint32_t p = (uint32_t)(y0 + j / w) * (uint32_t)W + (uint32_t)(x0 + j % w);
+        sel_pix[sel_off[(uint32_t)v * tiles_per_view + t] + (uint32_t)e] = p;
     }
 }
 

@@ -204,6 +204,12 @@ def test_bad_selections_are_refused():
     dup[1] = dup[0]
     st, msg = run(o, dup)
     assert st == L.MVGS_EINVAL and "twice" in msg
+    # a repeat in a later round of 64 entries that is itself in ascending order
+    assert o[1] - o[0] > 66
+    dup2 = p.copy()
+    dup2[o[0] + 64] = dup2[o[0] + 63]
+    st, msg = run(o, dup2)
+    assert st == L.MVGS_EINVAL and "twice" in msg
     out = p.copy()
     out[0] = 39   # pixel (39, 0) lies in tile 2, not tile 0
     st, msg = run(o, out)
