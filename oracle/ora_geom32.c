@@ -179,14 +179,14 @@ void ora_geom32_eval(const float mu[3], const float s[3], const float q[4], floa
 }
 
 /* power = -0.5 (d^T conic d), d = pixel centre - projected mean, in the kernel's
- * single-precision operation order. */
+ * single-precision operation order: dy (hcc dy + nb dx) + (hca dx) dx. */
 float ora_power32(const ora_g32* g, int32_t x, int32_t y)
 {
     float px = (float)x + 0.5f;
     float py = (float)y + 0.5f;
     float dx = px - g->mx;
     float dy = py - g->my;
-    float f1 = fmaf(g->hca, dx, g->nb * dy);
-    float m3 = (g->hcc * dy) * dy;
-    return fmaf(dx, f1, m3);
+    float ax = (g->hca * dx) * dx;
+    float bx = g->nb * dx;
+    return fmaf(dy, fmaf(g->hcc, dy, bx), ax);
 }

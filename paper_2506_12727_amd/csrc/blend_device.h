@@ -129,9 +129,9 @@ struct FwdPix {
 // One Gaussian of Eq. 1 for one pixel (skipped when the pixel has stopped or the cut test fails;
 // the branches cost less than computing every step for every lane).
 template <bool DEPTH>
-__device__ __forceinline__ void blend_step(FwdPix& st, const RecS& q, float px, float py, uint32_t pos) {
+__device__ __forceinline__ void blend_step(FwdPix& st, const RecS& q, const PowerX& t, float py, uint32_t pos) {
     if (st.done) return;
-    const float power = pixel_power(px, py, q.mx, q.my, q.hca, q.nb, q.hcc);
+    const float power = power_y(t, py, q.my, q.hcc);
     if (power >= q.cut) {
         const float alpha = (power > q.hi) ? kAlphaMax : q.o * fast_exp(power);
         const float Tn = __builtin_fmaf(-st.T, alpha, st.T);
@@ -172,11 +172,11 @@ struct BwdSum {
 };
 
 template <bool E1>
-__device__ __forceinline__ void unblend_pixel(BwdPix& st, BwdSum& a, const RecS& q, uint32_t pos, float px,
+__device__ __forceinline__ void unblend_pixel(BwdPix& st, BwdSum& a, const RecS& q, uint32_t pos, const PowerX& t,
                                               float half_w, float half_h) {
     if (pos >= st.last) return;
-    const float dx = px - q.mx, dy = st.py - q.my;
-    const float power = pixel_power(px, st.py, q.mx, q.my, q.hca, q.nb, q.hcc);
+    const float dx = t.dx, dy = st.py - q.my;
+    const float power = power_dy(t, dy, q.hcc);
     if (!(power >= q.cut)) return;
     a.contrib = true;
     const bool clamped = power > q.hi;
@@ -268,8 +268,9 @@ __device__ __forceinline__ void unblend_step(BwdPix (&st)[PPL], const RecS& q, u
                                              float half_w, float half_h, int lane, uint32_t bperm32,
                                              float* __restrict__ acc) {
     BwdSum a{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false};
+    const PowerX t = power_x(px, q.mx, q.hca, q.nb);
 #pragma unroll
-    for (int k = 0; k < PPL; ++k) unblend_pixel<E1>(st[k], a, q, pos, px, half_w, half_h);
+    for (int k = 0; k < PPL; ++k) unblend_pixel<E1>(st[k], a, q, pos, t, half_w, half_h);
     if (ballot64(a.contrib) == 0) return;
     const float v[10] = {a.mx, a.my, a.ca, a.cb, a.cc, a.o, a.r, a.g, a.b, E1 ? a.e1 : 0.0f};
     int k;
@@ -308,19 +309,23 @@ __device__ __forceinline__ void walk_forward(FwdPix (&st)[PPL], float px, const 
             const RecS q1 = load_rec(recs, readlane_u32(rl, j1));
             const RecS q2 = load_rec(recs, readlane_u32(rl, j2));
             const RecS q3 = load_rec(recs, readlane_u32(rl, j3));
+            const PowerX t0 = power_x(px, q0.mx, q0.hca, q0.nb);
 #pragma unroll
-            for (int k = 0; k < PPL; ++k) blend_step<DEPTH>(st[k], q0, px, py[k], base + (uint32_t)j0);
+            for (int k = 0; k < PPL; ++k) blend_step<DEPTH>(st[k], q0, t0, py[k], base + (uint32_t)j0);
             if (h1) {
+                const PowerX t1 = power_x(px, q1.mx, q1.hca, q1.nb);
 #pragma unroll
-                for (int k = 0; k < PPL; ++k) blend_step<DEPTH>(st[k], q1, px, py[k], base + (uint32_t)j1);
+                for (int k = 0; k < PPL; ++k) blend_step<DEPTH>(st[k], q1, t1, py[k], base + (uint32_t)j1);
             }
             if (h2) {
+                const PowerX t2 = power_x(px, q2.mx, q2.hca, q2.nb);
 #pragma unroll
-                for (int k = 0; k < PPL; ++k) blend_step<DEPTH>(st[k], q2, px, py[k], base + (uint32_t)j2);
+                for (int k = 0; k < PPL; ++k) blend_step<DEPTH>(st[k], q2, t2, py[k], base + (uint32_t)j2);
             }
             if (h3) {
+                const PowerX t3 = power_x(px, q3.mx, q3.hca, q3.nb);
 #pragma unroll
-                for (int k = 0; k < PPL; ++k) blend_step<DEPTH>(st[k], q3, px, py[k], base + (uint32_t)j3);
+                for (int k = 0; k < PPL; ++k) blend_step<DEPTH>(st[k], q3, t3, py[k], base + (uint32_t)j3);
             }
         }
     }

@@ -116,19 +116,24 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_fwd(const DevCam* __res
             const RecS q1 = load_rec(recs, readlane_u32(rl, j1));
             const RecS q2 = load_rec(recs, readlane_u32(rl, j2));
             const RecS q3 = load_rec(recs, readlane_u32(rl, j3));
+            // the column terms of the power once per lane, shared by its PPL pixels
+            const PowerX t0 = power_x(px, q0.mx, q0.hca, q0.nb);
 #pragma unroll
-            for (int k = 0; k < PPL; ++k) blend_step<false>(st[k], q0, px, py[k], base + (uint32_t)j0);
+            for (int k = 0; k < PPL; ++k) blend_step<false>(st[k], q0, t0, py[k], base + (uint32_t)j0);
             if (h1) {
+                const PowerX t1 = power_x(px, q1.mx, q1.hca, q1.nb);
 #pragma unroll
-                for (int k = 0; k < PPL; ++k) blend_step<false>(st[k], q1, px, py[k], base + (uint32_t)j1);
+                for (int k = 0; k < PPL; ++k) blend_step<false>(st[k], q1, t1, py[k], base + (uint32_t)j1);
             }
             if (h2) {
+                const PowerX t2 = power_x(px, q2.mx, q2.hca, q2.nb);
 #pragma unroll
-                for (int k = 0; k < PPL; ++k) blend_step<false>(st[k], q2, px, py[k], base + (uint32_t)j2);
+                for (int k = 0; k < PPL; ++k) blend_step<false>(st[k], q2, t2, py[k], base + (uint32_t)j2);
             }
             if (h3) {
+                const PowerX t3 = power_x(px, q3.mx, q3.hca, q3.nb);
 #pragma unroll
-                for (int k = 0; k < PPL; ++k) blend_step<false>(st[k], q3, px, py[k], base + (uint32_t)j3);
+                for (int k = 0; k < PPL; ++k) blend_step<false>(st[k], q3, t3, py[k], base + (uint32_t)j3);
             }
         }
     }

@@ -11,17 +11,19 @@
 namespace mvgs {
 
 // One element per thread over [P][D] with D = 11 + 3K: means 3, scales 3, quats 4, opacity 1, SH 3K.
+// Idx is uint32_t when P D fits (a 32-bit division by D instead of a 64-bit one).
+template <typename Idx>
 __global__ void __launch_bounds__(256) k_adam(float* __restrict__ means, float* __restrict__ scales,
                                               float* __restrict__ quats, float* __restrict__ opac,
                                               float* __restrict__ sh, const float* __restrict__ g_means,
                                               const float* __restrict__ g_scales, const float* __restrict__ g_quats,
                                               const float* __restrict__ g_opac, const float* __restrict__ g_sh,
                                               float2* __restrict__ mom, int64_t P, int K, AdamArgs a) {
-    const int D = 11 + 3 * K;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= P * D) return;
-    const int64_t g = i / D;
-    const int d = (int)(i - g * D);
+    const Idx D = (Idx)(11 + 3 * K);
+    const Idx i = (Idx)blockIdx.x * 256u + (Idx)threadIdx.x;
+    if ((int64_t)i >= P * (int64_t)D) return;
+    const int64_t g = (int64_t)(i / D);
+    const int d = (int)(i - (Idx)g * D);
     float* p;
     float grad, lr;
     float x = 0.0f;   // scale or opacity before the step
@@ -64,12 +66,13 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ means, float* 
     }
 }
 
+template <typename Idx>
 __global__ void __launch_bounds__(256) k_gather_rows(const int32_t* __restrict__ src, int64_t n, int64_t width,
                                                      const float* __restrict__ in, float* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n * width) return;
-    const int64_t r = i / width;
-    out[i] = in[(int64_t)src[r] * width + (i - r * width)];
+    const Idx i = (Idx)blockIdx.x * 256u + (Idx)threadIdx.x;
+    if ((int64_t)i >= n * width) return;
+    const Idx r = i / (Idx)width;
+    out[i] = in[(int64_t)src[r] * width + (int64_t)(i - r * (Idx)width)];
 }
 
 // sum += x over the concatenation of the five gradient tensors; per workgroup, the partial sums
@@ -134,14 +137,22 @@ void launch_adam(float* means, float* scales, float* quats, float* opac, float* 
     const int K = (sh_degree + 1) * (sh_degree + 1);
     const int64_t n = P * (11 + 3 * K);
     if (!n) return;
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, means, scales, quats, opac, sh,
-                       gr.means, gr.scales, gr.quats, gr.opac, gr.sh, reinterpret_cast<float2*>(mom), P, K, a);
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (n <= (int64_t(1) << 32) - 256)   // no index of the grid wraps
+        hipLaunchKernelGGL(k_adam<uint32_t>, grid, dim3(256), 0, s, means, scales, quats, opac, sh, gr.means,
+                           gr.scales, gr.quats, gr.opac, gr.sh, reinterpret_cast<float2*>(mom), P, K, a);
+    else
+        hipLaunchKernelGGL(k_adam<uint64_t>, grid, dim3(256), 0, s, means, scales, quats, opac, sh, gr.means,
+                           gr.scales, gr.quats, gr.opac, gr.sh, reinterpret_cast<float2*>(mom), P, K, a);
 }
 
 void launch_gather_rows(const int32_t* src, int64_t n, int64_t width, const float* in, float* out, hipStream_t s) {
     if (!n || !width) return;
-    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((n * width + 255) / 256)), dim3(256), 0, s, src, n, width, in,
-                       out);
+    const dim3 grid((unsigned)((n * width + 255) / 256));
+    if (n * width <= (int64_t(1) << 32) - 256)
+        hipLaunchKernelGGL(k_gather_rows<uint32_t>, grid, dim3(256), 0, s, src, n, width, in, out);
+    else
+        hipLaunchKernelGGL(k_gather_rows<uint64_t>, grid, dim3(256), 0, s, src, n, width, in, out);
 }
 
 void launch_grad_moments(const GradSegments& g, double* sum, double* acc, double* partials, hipStream_t s) {

@@ -210,13 +210,28 @@ __device__ __forceinline__ ProjOut project(const float mu[3], const float s[3], 
     return out;
 }
 
-// power = -0.5 d^T conic d at pixel (px, py), d = pixel centre - mean: the cut test's operand.
-__device__ __forceinline__ float pixel_power(float px, float py, float mx, float my, float hca, float nb, float hcc) {
+// power = -0.5 d^T conic d at pixel (px, py), d = pixel centre - mean: the cut test's operand,
+// evaluated as dy (hcc dy + nb dx) + hca dx dx. The column terms (PowerX) are shared by every
+// pixel of a lane's column.
+struct PowerX {
+    float dx, ax, bx;
+};
+
+__device__ __forceinline__ PowerX power_x(float px, float mx, float hca, float nb) {
     const float dx = px - mx;
-    const float dy = py - my;
-    const float f1 = __builtin_fmaf(hca, dx, nb * dy);
-    const float m3 = (hcc * dy) * dy;
-    return __builtin_fmaf(dx, f1, m3);
+    return PowerX{dx, (hca * dx) * dx, nb * dx};
+}
+
+__device__ __forceinline__ float power_dy(const PowerX& t, float dy, float hcc) {
+    return __builtin_fmaf(dy, __builtin_fmaf(hcc, dy, t.bx), t.ax);
+}
+
+__device__ __forceinline__ float power_y(const PowerX& t, float py, float my, float hcc) {
+    return power_dy(t, py - my, hcc);
+}
+
+__device__ __forceinline__ float pixel_power(float px, float py, float mx, float my, float hca, float nb, float hcc) {
+    return power_y(power_x(px, mx, hca, nb), py, my, hcc);
 }
 
 // ---------------------------------------------------------------------------------------------
