@@ -165,9 +165,12 @@ struct BwdPix {
     uint32_t last;
 };
 
-// Per-lane sums of one Gaussian's gradient contributions over the lane's pixels.
+// Per-lane sums of one Gaussian's gradient contributions over the lane's pixels. Without E1 the
+// mean and conic terms are gathered as s0 = sum dpow, s1 = sum dpow dy, s2 = sum dpow dy^2 (the
+// lane's pixels share dx) and expanded once per lane in unblend_step.
 struct BwdSum {
     float mx, my, ca, cb, cc, o, r, g, b, e1;
+    float s0, s1, s2;
     bool contrib;
 };
 
@@ -194,17 +197,23 @@ __device__ __forceinline__ void unblend_pixel(BwdPix& st, BwdSum& a, const RecS&
     if (clamped) return;
     a.o = __builtin_fmaf(dalpha, G, a.o);
     const float dpow = dalpha * alpha;
-    const float ca = -2.0f * q.hca, cbq = -q.nb, cc = -2.0f * q.hcc;
-    const float gx = dpow * (ca * dx + cbq * dy);
-    const float gy = dpow * (cbq * dx + cc * dy);
-    a.mx += gx;
-    a.my += gy;
-    a.ca = __builtin_fmaf(-0.5f * dpow, dx * dx, a.ca);
-    a.cb = __builtin_fmaf(-dpow, dx * dy, a.cb);
-    a.cc = __builtin_fmaf(-0.5f * dpow, dy * dy, a.cc);
     if (E1) {
+        // the per-pixel positional gradient is needed for its norm
+        const float ca = -2.0f * q.hca, cbq = -q.nb, cc = -2.0f * q.hcc;
+        const float gx = dpow * (ca * dx + cbq * dy);
+        const float gy = dpow * (cbq * dx + cc * dy);
+        a.mx += gx;
+        a.my += gy;
+        a.ca = __builtin_fmaf(-0.5f * dpow, dx * dx, a.ca);
+        a.cb = __builtin_fmaf(-dpow, dx * dy, a.cb);
+        a.cc = __builtin_fmaf(-0.5f * dpow, dy * dy, a.cc);
         const float nx = gx * half_w, ny = gy * half_h;
         a.e1 += sqrtf(nx * nx + ny * ny);
+    } else {
+        const float dpy = dpow * dy;
+        a.s0 += dpow;
+        a.s1 += dpy;
+        a.s2 = __builtin_fmaf(dpy, dy, a.s2);
     }
 }
 
@@ -267,11 +276,22 @@ template <bool E1, int PPL>
 __device__ __forceinline__ void unblend_step(BwdPix (&st)[PPL], const RecS& q, uint32_t r, uint32_t pos, float px,
                                              float half_w, float half_h, int lane, uint32_t bperm32,
                                              float* __restrict__ acc) {
-    BwdSum a{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false};
+    BwdSum a{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false};
     const PowerX t = power_x(px, q.mx, q.hca, q.nb);
 #pragma unroll
     for (int k = 0; k < PPL; ++k) unblend_pixel<E1>(st[k], a, q, pos, t, half_w, half_h);
     if (ballot64(a.contrib) == 0) return;
+    if (!E1) {
+        // sum over the lane's pixels of dpow (ca dx + cb dy, cb dx + cc dy) and -dpow (dx^2 / 2,
+        // dx dy, dy^2 / 2), with ca = -2 hca, cb = -nb, cc = -2 hcc
+        const float dx = t.dx;
+        const float cadx = -2.0f * q.hca * dx, cbdx = -q.nb * dx;
+        a.mx = __builtin_fmaf(cadx, a.s0, -q.nb * a.s1);
+        a.my = __builtin_fmaf(cbdx, a.s0, -2.0f * q.hcc * a.s1);
+        a.ca = -0.5f * dx * dx * a.s0;
+        a.cb = -dx * a.s1;
+        a.cc = -0.5f * a.s2;
+    }
     const float v[10] = {a.mx, a.my, a.ca, a.cb, a.cc, a.o, a.r, a.g, a.b, E1 ? a.e1 : 0.0f};
     int k;
     const float total = wave_sum10(v, lane, bperm32, &k);
