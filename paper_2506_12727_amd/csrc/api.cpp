@@ -692,12 +692,6 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
             }
             f->n_tasks = (uint32_t)nt;
         }
-        if ((uint32_t)ctx->pinned_totals[2] != 0) {
-            // a sort of an earlier call on this context timed out in its look-back (never expected)
-            fill_u32(reinterpret_cast<uint32_t*>(as<uint64_t>(ctx->totals) + 2), 2, 0u, s);
-            (void)ctx->ring.seal(s);
-            return bail(ctx->fail(MVGS_EHIP, "radix sort look-back timed out in an earlier call on this context"));
-        }
         if (V64 >= (1ull << 32) || K64 >= (1ull << 32)) {
             (void)ctx->ring.seal(s);
             return bail(ctx->fail(MVGS_ECAPACITY, "records %llu or pairs %llu reach 2^32", (unsigned long long)V64,
@@ -750,8 +744,7 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     mk = ctx->stage_begin(2, s);
     uint32_t* dk[2] = {as<uint32_t>(ctx->depth_key[0]), as<uint32_t>(ctx->depth_key[1])};
     uint32_t* dv[2] = {as<uint32_t>(ctx->rec_vals[0]), as<uint32_t>(ctx->rec_vals[1])};
-    uint32_t* sort_err = reinterpret_cast<uint32_t*>(as<uint64_t>(ctx->totals) + 2);
-    const int dcur = radix_sort_u32(dk, dv, true, V, 32, ctx->sort_scratch.p, sort_err, s, eff);
+    const int dcur = radix_sort_u32(dk, dv, true, V, 32, ctx->sort_scratch.p, s, eff);
     const uint32_t* sorted_rec = dv[dcur];
     ctx->stage_end(mk, s);
 
@@ -767,7 +760,7 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     mk = ctx->stage_begin(4, s);
     uint32_t* pk[2] = {as<uint32_t>(f->keys[0]), as<uint32_t>(f->keys[1])};
     uint32_t* pv[2] = {as<uint32_t>(f->vals[0]), as<uint32_t>(f->vals[1])};
-    f->final_buf = radix_sort_u32(pk, pv, false, K, bits_for(n_tiles), ctx->sort_scratch.p, sort_err, s,
+    f->final_buf = radix_sort_u32(pk, pv, false, K, bits_for(n_tiles), ctx->sort_scratch.p, s,
                                   eff ? eff + 1 : nullptr);
     ctx->stage_end(mk, s);
     mk = ctx->stage_begin(5, s);
@@ -1167,10 +1160,6 @@ int mvgs_frame_check(mvgs_context* ctx, void* stream, mvgs_frame* frame) {
     HIPCHK(ctx, hipStreamSynchronize(s));
     const uint64_t V = ctx->pinned_totals[0], K = ctx->pinned_totals[1];
     const uint32_t* e32 = reinterpret_cast<const uint32_t*>(ctx->pinned_totals + 4);
-    if ((uint32_t)ctx->pinned_totals[2] != 0) {
-        fill_u32(reinterpret_cast<uint32_t*>(as<uint64_t>(ctx->totals) + 2), 2, 0u, s);
-        return ctx->fail(MVGS_EHIP, "radix sort look-back timed out");
-    }
     if (e32[2]) {
         frame->checked = false;
         return ctx->fail(MVGS_ECAPACITY, "%llu records and %llu pairs exceed the capacities %llu and %llu",

@@ -9,13 +9,13 @@
 // records, i.e. ascending Gaussian index within a view.
 //
 // Radix sort: LSD, digits of at most 8 bits spread evenly over the passes, 8192 items per
-// partition (4 wavefronts x 32 rounds x 64 lanes). One read of the keys builds the digit
-// histograms of every pass at once; then each pass is a single sweep: a workgroup takes the next
-// partition from an atomic counter, ranks its items stably with wave64 ballots, publishes its
-// per-digit counts, finds the exclusive prefix of each digit by looking back over earlier
-// partitions (decoupled look-back, relaxed device-scope atomics, stopping at the first published
-// inclusive prefix), stages the items in LDS in digit order and writes them out in contiguous
-// runs. A look-back wait is bounded: on time-out it raises an error word instead of hanging.
+// partition (4 wavefronts x 32 rounds x 64 lanes). Each pass reduces, scans, then scatters: one
+// workgroup per partition counts its digits (LDS counters) into a digit-major table, one exclusive
+// scan of that table gives every (digit, partition) its output base, and one workgroup per
+// partition ranks its items stably with wave64 ballots, stages them in LDS in digit order and
+// writes them out in contiguous runs. Nothing waits on another workgroup. (A single-sweep pass
+// with decoupled look-back was measured slower on this chip: its device-scope look-back latency
+// across the XCDs cost more than the extra read of the keys.)
 #include <algorithm>
 
 #include "mvgs_kernels.h"
@@ -177,72 +177,56 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
     return peers;
 }
 
-// Digit histograms of every pass in one read of the keys: per-workgroup LDS counters, then one
-// global atomic per (pass, digit, workgroup). hist[p * 256 + d] counts digit d (dbits wide) of pass p.
-__global__ void __launch_bounds__(256) k_radix_hist_all(const uint32_t* __restrict__ keys, size_t n,
-                                                        const uint32_t* __restrict__ n_dev, int passes,
-                                                        int dbits, uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[4][kRadix];
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Reduce-then-scan pass, step 1: per-partition digit counts, digit-major (counts[d * parts + p]),
+// so that one exclusive scan of the whole array gives every (digit, partition) its output base.
+__global__ void __launch_bounds__(256) k_radix_upsweep(const uint32_t* __restrict__ keys, size_t n,
+                                                       const uint32_t* __restrict__ n_dev, int shift, uint32_t mask,
+                                                       uint32_t parts, uint32_t* __restrict__ counts) {
+    __shared__ uint32_t h[kRadix];
+    h[threadIdx.x] = 0;
+    __syncthreads();
     n = count_of(n, n_dev);
-    for (int i = threadIdx.x; i < 4 * kRadix; i += 256) (&h[0][0])[i] = 0;
-    __syncthreads();
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-        const uint32_t k = keys[i];
-        const uint32_t mask = (1u << dbits) - 1u;
-        for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(k >> (dbits * p)) & mask], 1u);
+    const size_t base = (size_t)blockIdx.x * kSortTile;
+    if (base + kSortTile <= n) {
+        const uint4* k4 = reinterpret_cast<const uint4*>(keys + base);
+        for (int j = threadIdx.x; j < kSortTile / 4; j += 256) {
+            const uint4 k = k4[j];
+            atomicAdd(&h[(k.x >> shift) & mask], 1u);
+            atomicAdd(&h[(k.y >> shift) & mask], 1u);
+            atomicAdd(&h[(k.z >> shift) & mask], 1u);
+            atomicAdd(&h[(k.w >> shift) & mask], 1u);
+        }
+    } else {
+        for (int j = threadIdx.x; j < kSortTile; j += 256) {
+            const size_t i = base + j;
+            if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+        }
     }
     __syncthreads();
-    for (int p = 0; p < passes; ++p) {
-        const uint32_t c = h[p][threadIdx.x];
-        if (c) atomicAdd(&hist[p * kRadix + threadIdx.x], c);
-    }
+    counts[(size_t)threadIdx.x * parts + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of each pass's 256 digit counts, in place (one workgroup of 256 threads).
-__global__ void __launch_bounds__(256) k_radix_hist_scan(uint32_t* __restrict__ hist, int passes) {
-    __shared__ uint32_t tmp[kRadix];
-    for (int p = 0; p < passes; ++p) {
-        uint32_t total;
-        const uint32_t v = hist[p * kRadix + threadIdx.x];
-        const uint32_t ex = block_exclusive_scan_256(v, tmp, &total);
-        hist[p * kRadix + threadIdx.x] = ex;
-    }
-}
-
-// Status word of (partition, digit) in the look-back: bits 63-62 flag, bits 31-0 count.
-constexpr uint64_t kFlagAggregate = 1ull << 62;   // this partition's own count
-constexpr uint64_t kFlagPrefix = 2ull << 62;      // count of this and all earlier partitions
-constexpr uint64_t kFlagMask = 3ull << 62;
-constexpr uint32_t kSpinLimit = 1u << 24;
-
-// One stable pass: workgroups take partitions of 8192 items in launch order from an atomic counter,
-// rank their items by digit with wave64 ballots, publish per-digit counts, add up the counts of the
-// earlier partitions (decoupled look-back: stop at the first published prefix), and scatter through
-// LDS in digit order. Each status word carries its count itself, so relaxed device-scope atomics
-// (coherent loads and stores, no cache-wide write-back or invalidate) are enough. A partition never waits on a later one, so the pass always drains; the wait is
-// bounded nevertheless and a timeout is recorded in *err instead of hanging.
-__global__ void __launch_bounds__(kSortThreads) k_radix_onesweep(
+// Step 3: rank each partition's items stably with wave64 ballots and scatter them through LDS in
+// digit order to the bases the scan gave.
+__global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, size_t n, const uint32_t* __restrict__ n_dev, int shift, uint32_t mask,
-    const uint32_t* __restrict__ digit_base, uint64_t* __restrict__ status, uint32_t* __restrict__ part_counter,
-    uint32_t* __restrict__ err) {
+    uint32_t parts, const uint32_t* __restrict__ offsets) {
     __shared__ uint32_t wcount[kSortWaves][kRadix];
     __shared__ uint32_t dstart[kRadix];
     __shared__ uint32_t gbase[kRadix];
     __shared__ uint32_t scan_tmp[kRadix];
     __shared__ uint32_t skey[kSortTile];
     __shared__ uint32_t sval[kSortTile];
-    __shared__ uint32_t s_part;
-
-    if (threadIdx.x == 0) s_part = atomicAdd(part_counter, 1u);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortThreads) (&wcount[0][0])[d] = 0;
-    __syncthreads();
-    const uint32_t part = s_part;
-    // partitions are handed out in order, so those past the actual count are the last ones taken
+    const uint32_t part = blockIdx.x;
     n = count_of(n, n_dev);
     if ((size_t)part * kSortTile >= n) return;
-
+    gbase[threadIdx.x] = offsets[(size_t)threadIdx.x * parts + part];
+    __syncthreads();
     const size_t base = (size_t)part * kSortTile + (size_t)wave * kSortRounds * 64;
     uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
 #pragma unroll
@@ -277,38 +261,6 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_onesweep(
         }
         uint32_t total;
         dstart[d] = block_exclusive_scan_256(run, scan_tmp, &total);
-        // publish, look back, publish the inclusive prefix
-        uint64_t* my = status + (size_t)part * kRadix + d;
-        if (part == 0) {
-            __hip_atomic_store(my, kFlagPrefix | run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            gbase[d] = digit_base[d];
-        } else {
-            __hip_atomic_store(my, kFlagAggregate | run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t excl = 0;
-            int64_t j = (int64_t)part - 1;
-            uint32_t spins = 0;
-            while (j >= 0) {
-                const uint64_t st = __hip_atomic_load(status + (size_t)j * kRadix + d, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                const uint64_t f = st & kFlagMask;
-                if (f == kFlagPrefix) {
-                    excl += (uint32_t)st;
-                    break;
-                }
-                if (f == kFlagAggregate) {
-                    excl += (uint32_t)st;
-                    --j;
-                    continue;
-                }
-                if (++spins > kSpinLimit) {
-                    atomicOr(err, 1u);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-            __hip_atomic_store(my, kFlagPrefix | (excl + run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            gbase[d] = digit_base[d] + excl;
-        }
     }
     __syncthreads();
 #pragma unroll
@@ -332,16 +284,13 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_onesweep(
     }
 }
 
-static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
-
 size_t radix_scratch_bytes(size_t n) {
     const size_t parts = std::max<size_t>(1, div_up(n, kSortTile));
-    return align256(4 * kRadix * sizeof(uint32_t)) + align256(parts * kRadix * sizeof(uint64_t)) +
-           align256(8 * sizeof(uint32_t));
+    return align256(parts * kRadix * sizeof(uint32_t)) + scan_scratch_bytes(parts * kRadix);
 }
 
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
-                   uint32_t* err, hipStream_t s, const uint32_t* n_dev) {
+                   hipStream_t s, const uint32_t* n_dev) {
     int cur = 0;
     if (n == 0 || bits <= 0) return cur;
     // fewest 8-bit passes, digits spread evenly over them (fewer distinct digits per workgroup
@@ -351,23 +300,16 @@ int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, s
     const uint32_t mask = (1u << dbits) - 1u;
     const size_t parts = div_up(n, kSortTile);
     uint8_t* p = (uint8_t*)scratch;
-    uint32_t* hist = (uint32_t*)p;
-    p += align256(4 * kRadix * sizeof(uint32_t));
-    uint64_t* status = (uint64_t*)p;
-    p += align256(parts * kRadix * sizeof(uint64_t));
-    uint32_t* counters = (uint32_t*)p;
-    fill_u32(hist, (size_t)passes * kRadix, 0u, s);
-    fill_u32(counters, (size_t)passes, 0u, s);
-    const unsigned hblocks = (unsigned)std::min<size_t>(div_up(n, 256 * 16), 4096);
-    hipLaunchKernelGGL(k_radix_hist_all, dim3(hblocks), dim3(256), 0, s, keys[0], n, n_dev, passes, dbits, hist);
-    hipLaunchKernelGGL(k_radix_hist_scan, dim3(1), dim3(256), 0, s, hist, passes);
+    uint32_t* counts = (uint32_t*)p;
+    p += align256(parts * kRadix * sizeof(uint32_t));
     for (int pass = 0; pass < passes; ++pass) {
         const uint32_t* vin = (pass == 0 && identity_values) ? nullptr : vals[cur];
-        hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)div_up(parts * kRadix, 256)), dim3(256), 0, s, status,
-                           parts * kRadix, (uint64_t)0);
-        hipLaunchKernelGGL(k_radix_onesweep, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys[cur], vin,
-                           keys[cur ^ 1], vals[cur ^ 1], n, n_dev, dbits * pass, mask,
-                           (const uint32_t*)(hist + pass * kRadix), status, counters + pass, err);
+        hipLaunchKernelGGL(k_radix_upsweep, dim3((unsigned)parts), dim3(256), 0, s, keys[cur], n, n_dev, dbits * pass,
+                           mask, (uint32_t)parts, counts);
+        scan_exclusive_u32(counts, counts, parts * kRadix, nullptr, p, s, nullptr);
+        hipLaunchKernelGGL(k_radix_downsweep, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys[cur], vin,
+                           keys[cur ^ 1], vals[cur ^ 1], n, n_dev, dbits * pass, mask, (uint32_t)parts,
+                           (const uint32_t*)counts);
         cur ^= 1;
     }
     return cur;

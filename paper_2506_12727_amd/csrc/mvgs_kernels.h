@@ -58,14 +58,14 @@ void scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* t
 // Sum of n u32 values as u64 into *total64 (device).
 void reduce_sum_u32(const uint32_t* in, size_t n, uint64_t* total64, void* scratch, hipStream_t s);
 
-// Stable LSD radix sort of (key, value) u32 pairs on bits [0, bits), 8 bits per pass, one read
-// and one write of keys and values per pass. The input is in keys[0] and vals[0] (or, with
-// identity_values, the values are 0..n-1 and vals[0] is only ping-pong space); passes alternate
-// between buffers 0 and 1. Returns the index of the buffer holding the result. A look-back wait
-// that times out sets *err (device) to a non-zero value instead of hanging.
+// Stable LSD radix sort of (key, value) u32 pairs on bits [0, bits), at most 8 bits per pass; a
+// pass reads the keys twice (count, scatter) and writes keys and values once. The input is in
+// keys[0] and vals[0] (or, with identity_values, the values are 0..n-1 and vals[0] is only
+// ping-pong space); passes alternate between buffers 0 and 1. Returns the index of the buffer
+// holding the result.
 size_t radix_scratch_bytes(size_t n);
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
-                   uint32_t* err, hipStream_t s, const uint32_t* n_dev = nullptr);
+                   hipStream_t s, const uint32_t* n_dev = nullptr);
 
 void fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 // per * min(*n_dev, n) values (all per * n when n_dev is null)
