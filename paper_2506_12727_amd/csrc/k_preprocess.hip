@@ -42,67 +42,100 @@ __global__ void __launch_bounds__(256) k_count(const float* __restrict__ means, 
     ntiles[g] = nt;
 }
 
+// The per-record arrays beside the record itself: view, depth key and covered-tile rectangle
+// (first global tile id, width | height << 16, the view's tiles per row).
+__device__ __forceinline__ void record_side(const BlendRec& r, const DevCam* __restrict__ cams, int tile_w,
+                                            int tile_h, uint32_t i, uint32_t* __restrict__ depth_key,
+                                            uint4* __restrict__ tile_rect, uint16_t* __restrict__ rec_view) {
+    const DevCam& c = cams[r.view];
+    const uint32_t x0 = r.boxx & 0xffffu, x1 = r.boxx >> 16, y0 = r.boxy & 0xffffu, y1 = r.boxy >> 16;
+    const uint32_t tx0 = x0 / (uint32_t)tile_w, ty0 = y0 / (uint32_t)tile_h;
+    const uint32_t tw_n = x1 / (uint32_t)tile_w - tx0 + 1, th_n = y1 / (uint32_t)tile_h - ty0 + 1;
+    rec_view[i] = (uint16_t)r.view;
+    depth_key[i] = r.depth_bits;
+    tile_rect[i] = make_uint4(c.tile_base + ty0 * (uint32_t)c.tiles_x + tx0, tw_n | (th_n << 16), (uint32_t)c.tiles_x,
+                              0u);
+}
+
 // Records of every participating (view, Gaussian), written in (Gaussian, view) order at
-// rec_off[g]. Also the depth sort key and the covered-tile rectangle of each record.
+// rec_off[g]. Also the depth sort key and the covered-tile rectangle of each record. One
+// wavefront per workgroup: its 64 Gaussians own one contiguous run of records, which is staged in
+// LDS while the lanes project view after view and then written out by consecutive lanes (each
+// lane's own records lie a Gaussian's worth of views apart, so direct stores would leave lines
+// half written); a run longer than the stage is written directly.
+constexpr uint32_t kRecStage = 512;   // records (32 KiB)
+
 template <int D>
-__global__ void __launch_bounds__(256) k_records(const float* __restrict__ means, const float* __restrict__ scales,
-                                                 const float* __restrict__ quats, const float* __restrict__ opac,
-                                                 const float* __restrict__ sh, int64_t P,
-                                                 const DevCam* __restrict__ cams, int B, int tile_w, int tile_h,
-                                                 const uint32_t* __restrict__ rec_off, BlendRec* __restrict__ recs,
-                                                 uint32_t* __restrict__ depth_key, uint4* __restrict__ tile_rect,
-                                                 uint16_t* __restrict__ rec_view,
-                                                 const uint32_t* __restrict__ overflow) {
+__global__ void __launch_bounds__(64) k_records(const float* __restrict__ means, const float* __restrict__ scales,
+                                                const float* __restrict__ quats, const float* __restrict__ opac,
+                                                const float* __restrict__ sh, int64_t P,
+                                                const DevCam* __restrict__ cams, int B, int tile_w, int tile_h,
+                                                const uint32_t* __restrict__ rec_off, BlendRec* __restrict__ recs,
+                                                uint32_t* __restrict__ depth_key, uint4* __restrict__ tile_rect,
+                                                uint16_t* __restrict__ rec_view,
+                                                const uint32_t* __restrict__ overflow) {
+    __shared__ BlendRec stage[kRecStage];
     constexpr int K = (D + 1) * (D + 1);
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= P || (overflow && *overflow)) return;
-    float mu[3], s[3], q[4], o;
-    load_gaussian(means, scales, quats, opac, g, mu, s, q, o);
-    float coef[K][3];
+    if (overflow && *overflow) return;
+    const int64_t g0 = (int64_t)blockIdx.x * 64;
+    const int64_t g1 = g0 + 64 < P ? g0 + 64 : P;
+    const uint32_t base = rec_off[g0], n_run = rec_off[g1] - base;
+    const bool staged = n_run <= kRecStage;
+    const int64_t g = g0 + threadIdx.x;
+    if (g < P) {
+        float mu[3], s[3], q[4], o;
+        load_gaussian(means, scales, quats, opac, g, mu, s, q, o);
+        float coef[K][3];
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) coef[k][ch] = sh[(g * K + k) * 3 + ch];
-    uint32_t out = rec_off[g];
-    const uint32_t out_end = rec_off[g + 1];
-    for (int v = 0; v < B && out < out_end; ++v) {
-        const DevCam& c = cams[v];
-        ProjState st;
-        const ProjOut p = project(mu, s, q, o, c, st);
-        if (!p.ok) continue;
-        float dx = mu[0] - c.campos[0], dy = mu[1] - c.campos[1], dz = mu[2] - c.campos[2];
-        const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-        dx *= il; dy *= il; dz *= il;
-        float Y[16];
-        sh_basis<D>(dx, dy, dz, Y);
-        float rgb[3];
+            for (int ch = 0; ch < 3; ++ch) coef[k][ch] = sh[(g * K + k) * 3 + ch];
+        uint32_t out = rec_off[g];
+        const uint32_t out_end = rec_off[g + 1];
+        for (int v = 0; v < B && out < out_end; ++v) {
+            const DevCam& c = cams[v];
+            ProjState st;
+            const ProjOut p = project(mu, s, q, o, c, st);
+            if (!p.ok) continue;
+            float dx = mu[0] - c.campos[0], dy = mu[1] - c.campos[1], dz = mu[2] - c.campos[2];
+            const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+            dx *= il; dy *= il; dz *= il;
+            float Y[16];
+            sh_basis<D>(dx, dy, dz, Y);
+            float rgb[3];
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float a = 0.5f;
+            for (int ch = 0; ch < 3; ++ch) {
+                float a = 0.5f;
 #pragma unroll
-            for (int k = 0; k < K; ++k) a = __builtin_fmaf(coef[k][ch], Y[k], a);
-            rgb[ch] = a > 0.0f ? a : 0.0f;
+                for (int k = 0; k < K; ++k) a = __builtin_fmaf(coef[k][ch], Y[k], a);
+                rgb[ch] = a > 0.0f ? a : 0.0f;
+            }
+            BlendRec r;
+            r.boxx = (uint32_t)p.x0 | ((uint32_t)p.x1 << 16);
+            r.boxy = (uint32_t)p.y0 | ((uint32_t)p.y1 << 16);
+            r.mx = p.mx; r.my = p.my;
+            r.hca = p.hca; r.nb = p.nb; r.hcc = p.hcc; r.o = o;
+            r.cut = p.cut; r.hi = p.hi; r.r = rgb[0]; r.g = rgb[1];
+            r.b = rgb[2];
+            r.gid = (uint32_t)g;
+            r.view = (uint32_t)v;
+            r.depth_bits = f2u(p.depth);
+            if (staged) {
+                stage[out - base] = r;
+            } else {
+                recs[out] = r;
+                record_side(r, cams, tile_w, tile_h, out, depth_key, tile_rect, rec_view);
+            }
+            ++out;
         }
-        BlendRec r;
-        r.boxx = (uint32_t)p.x0 | ((uint32_t)p.x1 << 16);
-        r.boxy = (uint32_t)p.y0 | ((uint32_t)p.y1 << 16);
-        r.mx = p.mx; r.my = p.my;
-        r.hca = p.hca; r.nb = p.nb; r.hcc = p.hcc; r.o = o;
-        r.cut = p.cut; r.hi = p.hi; r.r = rgb[0]; r.g = rgb[1];
-        r.b = rgb[2];
-        r.gid = (uint32_t)g;
-        r.view = (uint32_t)v;
-        r.depth_bits = f2u(p.depth);
-        recs[out] = r;
-        rec_view[out] = (uint16_t)v;
-        depth_key[out] = f2u(p.depth);
-        // covered tiles: first global tile id, width | height << 16, the view's tiles per row
-        const uint32_t tx0 = (uint32_t)(p.x0 / tile_w), ty0 = (uint32_t)(p.y0 / tile_h);
-        const uint32_t tw_n = (uint32_t)(p.x1 / tile_w) - tx0 + 1, th_n = (uint32_t)(p.y1 / tile_h) - ty0 + 1;
-        tile_rect[out] = make_uint4(c.tile_base + ty0 * (uint32_t)c.tiles_x + tx0, tw_n | (th_n << 16),
-                                    (uint32_t)c.tiles_x, 0u);
-        ++out;
     }
+    if (!staged) return;
+    __syncthreads();
+    const uint4* src = reinterpret_cast<const uint4*>(stage);
+    uint4* dst = reinterpret_cast<uint4*>(recs + base);
+    for (uint32_t i = threadIdx.x; i < 4 * n_run; i += 64) dst[i] = src[i];
+    for (uint32_t i = threadIdx.x; i < n_run; i += 64)
+        record_side(stage[i], cams, tile_w, tile_h, base + i, depth_key, tile_rect, rec_view);
 }
 
 // Backward chain per Gaussian over its records (2D gradients -> parameters), summed over
@@ -284,10 +317,10 @@ void launch_count(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int
 void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,
                     BlendRec* recs, uint32_t* depth_key, uint4* tile_rect, uint16_t* rec_view, hipStream_t s,
                     const uint32_t* overflow) {
-    const unsigned blocks = (unsigned)((ga.P + 255) / 256);
+    const unsigned blocks = (unsigned)((ga.P + 63) / 64);
     if (!blocks) return;
 #define MVGS_REC(D)                                                                                             \
-    hipLaunchKernelGGL(k_records<D>, dim3(blocks), dim3(256), 0, s, ga.means, ga.scales, ga.quats, ga.opac,     \
+    hipLaunchKernelGGL(k_records<D>, dim3(blocks), dim3(64), 0, s, ga.means, ga.scales, ga.quats, ga.opac,      \
                        ga.sh, ga.P, cams, B, tw, th, rec_off, recs, depth_key, tile_rect, rec_view, overflow)
     switch (ga.sh_degree) {
         case 0: MVGS_REC(0); break;
