@@ -64,11 +64,14 @@ __device__ __forceinline__ float rect_max_power(float mx, float my, float hca, f
     }
     float best = -__builtin_inff();
     mag = 0.0f;
+    // The stationary points only choose where on an edge to evaluate the quadratic; near them it
+    // is flat, so the hardware reciprocal (about 1 ulp) moves the value by far less than the slack.
+    const float ry = -nb * __builtin_amdgcn_rcpf(2.0f * hcc), rx = -nb * __builtin_amdgcn_rcpf(2.0f * hca);
     // edges x = const: maximise over dy at dy* = -nb dx / (2 hcc)
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
         const float dx = e ? bx : ax;
-        float dy = -nb * dx / (2.0f * hcc);
+        float dy = ry * dx;
         dy = fminf(fmaxf(dy, ay), by);
         const float t1 = hca * dx * dx, t2 = nb * dx * dy, t3 = hcc * dy * dy;
         const float p = t1 + t2 + t3;
@@ -81,7 +84,7 @@ __device__ __forceinline__ float rect_max_power(float mx, float my, float hca, f
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
         const float dy = e ? by : ay;
-        float dx = -nb * dy / (2.0f * hca);
+        float dx = rx * dy;
         dx = fminf(fmaxf(dx, ax), bx);
         const float t1 = hca * dx * dx, t2 = nb * dx * dy, t3 = hcc * dy * dy;
         const float p = t1 + t2 + t3;
