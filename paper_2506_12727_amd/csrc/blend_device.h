@@ -122,24 +122,28 @@ __device__ __forceinline__ uint64_t window_mask(const uint32_t* __restrict__ val
     return ballot64(keep);
 }
 
+// T carries the pixel's state in its sign: a stopped (or unselected) pixel holds -T, so one
+// comparison tells a live pixel and no separate flag has to be kept per candidate. Transmittance
+// is |T| (at least 1e-4 while live).
 struct FwdPix {
     float T, C0, C1, C2;
     uint32_t last;
-    bool done;
     float D;   // blended camera-space depth (accumulated only where asked for)
 };
+
+__device__ __forceinline__ bool pix_live(const FwdPix& st) { return st.T > 0.0f; }
 
 // One Gaussian of Eq. 1 for one pixel (skipped when the pixel has stopped or the cut test fails;
 // the branches cost less than computing every step for every lane).
 template <bool DEPTH>
 __device__ __forceinline__ void blend_step(FwdPix& st, const RecS& q, const PowerX& t, float py, uint32_t pos) {
-    if (st.done) return;
+    if (!pix_live(st)) return;
     const float power = power_y(t, py, q.my, q.hcc);
     if (power >= q.cut) {
         const float alpha = (power > q.hi) ? kAlphaMax : q.o * fast_exp(power);
         const float Tn = __builtin_fmaf(-st.T, alpha, st.T);
         if (Tn < kTStop) {
-            st.done = true;
+            st.T = -st.T;
         } else {
             const float w = alpha * st.T;
             st.C0 = __builtin_fmaf(q.r, w, st.C0);
@@ -311,7 +315,7 @@ __device__ __forceinline__ void walk_forward(FwdPix (&st)[PPL], float px, const 
     for (uint32_t base = rg.x; base < rg.y; base += 64) {
         bool live = false;
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) live |= !st[k].done;
+        for (int k = 0; k < PPL; ++k) live |= pix_live(st[k]);
         if (ballot64(live) == 0) break;
         uint32_t rl;
         uint64_t m = window_mask(vals, recs, base, rg.y, lane, sx0, sx1, sy0, sy1, rl);

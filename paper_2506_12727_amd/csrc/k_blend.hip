@@ -88,14 +88,14 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_fwd(const DevCam* __res
         // an unselected pixel starts stopped, marked by an impossible last contributor, so the
         // mask is not needed again after the walk (it would hold scalar registers the walk uses)
         const bool sel = pixel_selected(c, x, y, mask);
-        st[k] = FwdPix{1.0f, 0.0f, 0.0f, 0.0f, sel ? 0u : kUnselected, !sel, 0.0f};
+        st[k] = FwdPix{sel ? 1.0f : -1.0f, 0.0f, 0.0f, 0.0f, sel ? 0u : kUnselected, 0.0f};
     }
     // The walk of walk_forward, written out here: with the call, the compiler optimises the loop
     // apart from this kernel and the kernel runs out of scalar registers.
     for (uint32_t base = wt.rg.x; base < wt.rg.y; base += 64) {
         bool live = false;
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) live |= !st[k].done;
+        for (int k = 0; k < PPL; ++k) live |= pix_live(st[k]);
         if (ballot64(live) == 0) break;
         uint32_t rl;
         uint64_t m = window_mask(vals, recs, base, wt.rg.y, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1, rl);
@@ -145,12 +145,13 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_fwd(const DevCam* __res
         if (x < c.W && y < c.H) {
             const size_t pix = (size_t)y * c.W + x;
             const bool sel = st[k].last != kUnselected;
+            const float T = fabsf(st[k].T);
             if (sel) {
-                img[pix] = __builtin_fmaf(st[k].T, c.bg[0], st[k].C0);
-                img[hw + pix] = __builtin_fmaf(st[k].T, c.bg[1], st[k].C1);
-                img[2 * hw + pix] = __builtin_fmaf(st[k].T, c.bg[2], st[k].C2);
+                img[pix] = __builtin_fmaf(T, c.bg[0], st[k].C0);
+                img[hw + pix] = __builtin_fmaf(T, c.bg[1], st[k].C1);
+                img[2 * hw + pix] = __builtin_fmaf(T, c.bg[2], st[k].C2);
             }
-            t_final[c.pix_base + pix] = st[k].T;
+            t_final[c.pix_base + pix] = T;
             n_last[c.pix_base + pix] = sel ? st[k].last : 0u;
         }
     }

@@ -169,15 +169,16 @@ __global__ void __launch_bounds__(64) k_blend_fwd_sel(const DevCam* __restrict__
     const DevCam& c = cams[w.v];
     const float px = (float)w.x + 0.5f;
     const float py[1] = {(float)w.y + 0.5f};
-    FwdPix st[1] = {FwdPix{1.0f, 0.0f, 0.0f, 0.0f, 0u, !w.valid, 0.0f}};
+    FwdPix st[1] = {FwdPix{w.valid ? 1.0f : -1.0f, 0.0f, 0.0f, 0.0f, 0u, 0.0f}};
     walk_forward<1, true>(st, px, py, w.rg, vals, recs, lane, w.bx0, w.bx1, w.by0, w.by1);
     if (w.valid) {
         const size_t hw = (size_t)c.W * c.H, pix = (size_t)w.y * c.W + w.x;
         float* img = images[w.v];
-        img[pix] = __builtin_fmaf(st[0].T, c.bg[0], st[0].C0);
-        img[hw + pix] = __builtin_fmaf(st[0].T, c.bg[1], st[0].C1);
-        img[2 * hw + pix] = __builtin_fmaf(st[0].T, c.bg[2], st[0].C2);
-        t_sel[w.i] = st[0].T;
+        const float T = fabsf(st[0].T);
+        img[pix] = __builtin_fmaf(T, c.bg[0], st[0].C0);
+        img[hw + pix] = __builtin_fmaf(T, c.bg[1], st[0].C1);
+        img[2 * hw + pix] = __builtin_fmaf(T, c.bg[2], st[0].C2);
+        t_sel[w.i] = T;
         last_sel[w.i] = st[0].last;
         depth_sel[w.i] = st[0].D;
     }
