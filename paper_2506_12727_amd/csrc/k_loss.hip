@@ -31,31 +31,49 @@ __device__ __forceinline__ int find_loss_view(const LossView* __restrict__ v, in
     return lo;
 }
 
-// L1 term: writes grad = w_l1 * sign(I - T) / N and one partial sum of |I - T| per block.
+// L1 term: writes grad = w_l1 * sign(I - T) / N and one partial sum of |I - T| per block. Four
+// consecutive pixels per thread, loaded and stored as float4 where they lie in one view at an
+// aligned offset (one scalar pixel at a time elsewhere).
+__device__ __forceinline__ float l1_sign(float d, float scale) { return d > 0.0f ? scale : (d < 0.0f ? -scale : 0.0f); }
+
 __global__ void __launch_bounds__(kLossThreads) k_l1(const LossView* __restrict__ views, int B, uint32_t total,
                                                      float scale, float* __restrict__ partial) {
-    __shared__ float red[kLossThreads];
-    const uint32_t p = blockIdx.x * kLossThreads + threadIdx.x;
+    __shared__ float red[kLossThreads / 64];
+    const uint32_t p0 = (blockIdx.x * kLossThreads + threadIdx.x) * 4u;
     float s = 0.0f;
-    if (p < total) {
-        const int v = find_loss_view(views, B, p);
+    if (p0 < total) {
+        const int v = find_loss_view(views, B, p0);
         const LossView lv = views[v];
         const size_t hw = (size_t)lv.W * lv.H;
-        const size_t i = p - lv.pix_base;
+        const size_t i = p0 - lv.pix_base;
+        const bool aligned = (((uintptr_t)lv.img | (uintptr_t)lv.tgt | (uintptr_t)lv.grad) & 15u) == 0;
+        if (aligned && (hw & 3u) == 0 && (i & 3u) == 0 && i + 3 < hw) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            const float d = lv.img[ch * hw + i] - lv.tgt[ch * hw + i];
-            s += fabsf(d);
-            lv.grad[ch * hw + i] = d > 0.0f ? scale : (d < 0.0f ? -scale : 0.0f);
+            for (int ch = 0; ch < 3; ++ch) {
+                const float4 a = *reinterpret_cast<const float4*>(lv.img + ch * hw + i);
+                const float4 t = *reinterpret_cast<const float4*>(lv.tgt + ch * hw + i);
+                const float4 d = make_float4(a.x - t.x, a.y - t.y, a.z - t.z, a.w - t.w);
+                s += fabsf(d.x) + fabsf(d.y) + fabsf(d.z) + fabsf(d.w);
+                *reinterpret_cast<float4*>(lv.grad + ch * hw + i) =
+                    make_float4(l1_sign(d.x, scale), l1_sign(d.y, scale), l1_sign(d.z, scale), l1_sign(d.w, scale));
+            }
+        } else {
+            for (uint32_t p = p0; p < p0 + 4u && p < total; ++p) {
+                const LossView lw = views[find_loss_view(views, B, p)];
+                const size_t hw2 = (size_t)lw.W * lw.H, j = p - lw.pix_base;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float d = lw.img[ch * hw2 + j] - lw.tgt[ch * hw2 + j];
+                    s += fabsf(d);
+                    lw.grad[ch * hw2 + j] = l1_sign(d, scale);
+                }
+            }
         }
     }
-    red[threadIdx.x] = s;
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    for (int off = kLossThreads / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 // Horizontal pass: 5 windowed sums (I, T, I^2, T^2, IT) along x. Grid (blocks, 3 channels).
@@ -264,7 +282,7 @@ void launch_loss(const LossView* views_dev, const LossView* views_host, int B, u
                  float w_dssim, float* loss_out, void* scratch, void* maps, hipStream_t s) {
     const double N = 3.0 * (double)total_pixels;
     float* partial = (float*)scratch;
-    const uint32_t n_l1 = (total_pixels + kLossThreads - 1) / kLossThreads;
+    const uint32_t n_l1 = (total_pixels + 4 * kLossThreads - 1) / (4 * kLossThreads);
     hipLaunchKernelGGL(k_l1, dim3(n_l1), dim3(kLossThreads), 0, s, views_dev, B, total_pixels, (float)(w_l1 / N),
                        partial);
     float* sp = partial + n_l1;

@@ -268,20 +268,24 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(
         sh_basis<D>(ex, ey, ez, Y);
         sh_basis_grad<D>(ex, ey, ez, dY);
         const float grgb[3] = {gr, gg, gb};
-        float dd[3] = {0, 0, 0};
+        float gch[3];
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             float raw = 0.5f;
 #pragma unroll
             for (int k = 0; k < K; ++k) raw = __builtin_fmaf(coef[k][ch], Y[k], raw);
-            const float gch = raw > 0.0f ? grgb[ch] : 0.0f;
+            gch[ch] = raw > 0.0f ? grgb[ch] : 0.0f;   // the clamp at 0 passes no gradient
+        }
+        // d colour / d direction: sum over k of (sum over channels gch coef) dY_k
+        float dd[3] = {0, 0, 0};
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                dcoef[k][ch] += gch * Y[k];
-                dd[0] += gch * coef[k][ch] * dY[k][0];
-                dd[1] += gch * coef[k][ch] * dY[k][1];
-                dd[2] += gch * coef[k][ch] * dY[k][2];
-            }
+        for (int k = 0; k < K; ++k) {
+            const float wk = gch[0] * coef[k][0] + gch[1] * coef[k][1] + gch[2] * coef[k][2];
+            dd[0] += wk * dY[k][0];
+            dd[1] += wk * dY[k][1];
+            dd[2] += wk * dY[k][2];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) dcoef[k][ch] += gch[ch] * Y[k];
         }
         const float ddot = dd[0] * ex + dd[1] * ey + dd[2] * ez;
         dmu[0] += (dd[0] - ex * ddot) * il;
