@@ -110,8 +110,10 @@ typedef struct {
  * call whose participating (view, Gaussian) records or (Gaussian, tile) pairs exceed them does no
  * work (images get the background) and is reported by mvgs_frame_check. Such a forward, with the
  * loss and backward on its frame, can be captured into a HIP graph (the stream in capture mode),
- * after one call of each with the same shapes outside the capture; partial rendering is not
- * available in capacity mode. */
+ * after one call of each with the same shapes outside the capture. Partial rendering works in
+ * capacity mode too: its selection kernels are then launched for the bound n_tiles + n_sel / 64 + 1
+ * on tasks and read the count from device memory, and a rejected selection voids the call like an
+ * overflow (mvgs_frame_check reports it); sub-sampling, merge and the 3D loss capture as well. */
 typedef struct {
     int32_t tile_w;
     int32_t tile_h;
@@ -164,7 +166,11 @@ int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
  * others keep their contents), so passing one buffer for all views of a sub-sampled batch yields
  * the merged image. The selection is copied into the frame and checked on the device before any
  * blending: a bad selection returns MVGS_EINVAL (after the stream synchronization the forward does
- * anyway). mvgs_backward on such a frame reads dL/dimage at the selected pixels only;
+ * anyway). In capacity mode the forward does not synchronize: a bad selection (or more tasks than
+ * their bound) makes the call do no work, and mvgs_frame_check returns MVGS_EINVAL for it; a
+ * selection of exactly width * height pixels over views of one size is then taken as a partition
+ * of the plane for mvgs_loss_3d, and mvgs_frame_check also returns MVGS_EINVAL if it selects a
+ * plane position in two views. mvgs_backward on such a frame reads dL/dimage at the selected pixels only;
  * mvgs_export_transmittance writes the selected pixels only (masked mode: every pixel, 1 where
  * unselected). Otherwise as mvgs_forward. */
 #define MVGS_PARTIAL_COMPACT 0
@@ -306,8 +312,11 @@ int mvgs_frame_release(mvgs_context* ctx, mvgs_frame* frame);
 
 /* Capacity mode: wait for the frame's forward and report whether it fitted the capacities
  * (MVGS_ECAPACITY if not: its images and any backward on it are void; make a context with larger
- * capacities). Sets the sizes mvgs_frame_info and mvgs_export_binning use. Synchronizes the
- * stream; not capturable. Returns MVGS_OK at once for frames not made in capacity mode. */
+ * capacities). A partial frame is also void, with MVGS_EINVAL, if its selection was rejected; if
+ * its width * height pixels select a plane position in two views, MVGS_EINVAL says that its 3D
+ * loss and merge are void. Sets the sizes mvgs_frame_info and mvgs_export_binning use.
+ * Synchronizes the stream; not capturable. Returns MVGS_OK at once for frames not made in
+ * capacity mode. */
 int mvgs_frame_check(mvgs_context* ctx, void* stream, mvgs_frame* frame);
 
 /* For a frame made by a forward captured into a graph: replace its cameras (same count and image

@@ -518,6 +518,17 @@ void mvgs_destroy(mvgs_context* ctx) {
 
 namespace {
 
+// Capacity-mode frames keep on the device (dtot, 64 bytes): the call's totals (u64 records, pairs,
+// error words, selection tasks) at [0, 32) and at [32, 44) the clamped record and pair counts and
+// the void word (bit 0 capacity overflow, bit 1 rejected selection, bit 2 tasks over their bound).
+const uint32_t* frame_eff(const mvgs_frame* f) {
+    return f->capacity ? reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(f->dtot.p) + 32) : nullptr;
+}
+const uint32_t* frame_void(const mvgs_frame* f) { return f->capacity ? frame_eff(f) + 2 : nullptr; }
+const uint32_t* frame_tasks(const mvgs_frame* f) {
+    return f->capacity ? reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(f->dtot.p) + 24) : nullptr;
+}
+
 SelBlendArgs sel_args(mvgs_frame* f) {
     SelBlendArgs sa{};
     sa.cams = as<DevCam>(f->cams);
@@ -532,6 +543,10 @@ SelBlendArgs sel_args(mvgs_frame* f) {
     sa.t_sel = as<float>(f->t_final);
     sa.last_sel = as<uint32_t>(f->n_last);
     sa.depth_sel = as<float>(f->depth);
+    if (f->capacity) {
+        sa.n_dev = frame_tasks(f);
+        sa.void_word = frame_void(f);
+    }
     return sa;
 }
 
@@ -559,7 +574,6 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     hipStream_t s = (hipStream_t)stream;
     const int tw = ctx->tw, th = ctx->th;
     const bool cap = ctx->cap_v > 0;
-    if (cap && sel) return ctx->fail(MVGS_EINVAL, "partial rendering needs a context without capacities");
     if (ctx->begin(s) && (!cap || !ctx->device_used))
         return ctx->fail(MVGS_EINVAL, "a forward can be captured only on a context with capacities, after one "
                                       "call outside the capture");
@@ -664,6 +678,16 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     if (cap) {
         uint32_t* e32 = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(f->dtot.p) + 32);
         launch_capacity_clamp(as<uint64_t>(ctx->totals), ctx->cap_v, ctx->cap_k, e32, e32 + 2, s);
+        if (sel) {
+            // the grid of the selection kernels is the task bound; the count stays on the device
+            launch_sel_void(sel_err, as<uint64_t>(ctx->totals) + 3, (uint32_t)task_cap, e32, e32 + 2, s);
+            f->n_tasks = (uint32_t)task_cap;
+            // a selection of W H pixels is taken as a partition of the plane; mvgs_frame_check
+            // reports it if a plane position is selected in two views
+            f->partition = want_plane && (uint64_t)sel->n_sel == (uint64_t)cams[0].width * (uint64_t)cams[0].height;
+        }
+        // this call's totals and error words, for the selection kernels and mvgs_frame_check
+        FCHK(hipMemcpyAsync(f->dtot.p, ctx->totals.p, 4 * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
         eff = e32;
         ovf = e32 + 2;
         f->V = 0;
@@ -788,8 +812,6 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
         launch_blend_fwd(a, tw, th, ctx->ppl, s);
     }
     ctx->stage_end(mk, s);
-    if (cap)  // this call's totals and error words, for mvgs_frame_check
-        FCHK(hipMemcpyAsync(f->dtot.p, ctx->totals.p, 3 * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
     FCHK(hipGetLastError());
     FCHK(ctx->ring.seal(s));
     *frame = f;
@@ -1032,7 +1054,7 @@ int mvgs_loss_3d(mvgs_context* ctx, void* stream, const mvgs_frame* frame, const
     const int mk = ctx->stage_begin(7, s);
     launch_loss3d(as<DevCam>(f->cams), f->B, f->n_tiles, as<uint32_t>(f->sel_off), as<uint32_t>(f->sel_pix),
                   as<float>(f->t_final), as<float>(f->depth), W, H, image, target, w_l1, w_dssim, loss_dev, dl_dimage,
-                  ctx->loss3d_scratch.p, s);
+                  ctx->loss3d_scratch.p, s, frame_void(f));
     ctx->stage_end(mk, s);
     LAUNCHCHK(ctx, "3D loss kernels");
     return MVGS_OK;
@@ -1050,7 +1072,7 @@ int mvgs_export_depth(mvgs_context* ctx, void* stream, const mvgs_frame* frame, 
     void* dptrs = nullptr;
     HIPCHK(ctx, ctx->ring.put(depth, sizeof(float*) * f->B, s, &dptrs, ctx->capturing));
     launch_sel_scatter(as<DevCam>(f->cams), f->B, f->n_tiles, as<uint32_t>(f->sel_off), as<uint32_t>(f->sel_pix),
-                       as<float>(f->depth), (float* const*)dptrs, s);
+                       as<float>(f->depth), (float* const*)dptrs, s, frame_void(f));
     LAUNCHCHK(ctx, "depth scatter");
     HIPCHK(ctx, ctx->ring.seal(s));
     return MVGS_OK;
@@ -1076,9 +1098,8 @@ int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, cons
     mvgs_frame* f = const_cast<mvgs_frame*>(frame);
     // records: exact, or in capacity mode bounded by the capacity with the count on the device
     const uint32_t V = f->capacity ? (uint32_t)ctx->cap_v : f->V;
-    const uint32_t* eff = f->capacity ? reinterpret_cast<const uint32_t*>(static_cast<uint8_t*>(f->dtot.p) + 32)
-                                      : nullptr;
-    const uint32_t* ovf = eff ? eff + 2 : nullptr;
+    const uint32_t* eff = frame_eff(f);
+    const uint32_t* ovf = frame_void(f);
     const Need need[] = {{&ctx->acc, sizeof(float) * kAccStride * std::max<uint32_t>(V, 1)}};
     st = grow_all(ctx, need, 1);
     if (st) return st;
@@ -1160,11 +1181,31 @@ int mvgs_frame_check(mvgs_context* ctx, void* stream, mvgs_frame* frame) {
     HIPCHK(ctx, hipStreamSynchronize(s));
     const uint64_t V = ctx->pinned_totals[0], K = ctx->pinned_totals[1];
     const uint32_t* e32 = reinterpret_cast<const uint32_t*>(ctx->pinned_totals + 4);
+    const uint32_t sel_e = frame->mode == kModeFull ? 0u : (uint32_t)(ctx->pinned_totals[2] >> 32);
+    if (e32[2] & 2u) {
+        frame->checked = false;
+        return ctx->fail(MVGS_EINVAL, "pixel selection rejected:%s%s%s%s",
+                         (sel_e & kSelBadOffsets) ? " offsets do not rise from 0 to n_sel;" : "",
+                         (sel_e & kSelTooLong) ? " a segment holds more pixels than a tile;" : "",
+                         (sel_e & kSelOutside) ? " a pixel lies outside its (view, tile);" : "",
+                         (sel_e & kSelDuplicate) ? " a pixel is selected twice;" : "");
+    }
+    if (e32[2] & 4u) {
+        frame->checked = false;
+        return ctx->fail(MVGS_EHIP, "selection tasks %llu exceed their bound %u",
+                         (unsigned long long)ctx->pinned_totals[3], frame->n_tasks);
+    }
     if (e32[2]) {
         frame->checked = false;
         return ctx->fail(MVGS_ECAPACITY, "%llu records and %llu pairs exceed the capacities %llu and %llu",
                          (unsigned long long)V, (unsigned long long)K, (unsigned long long)ctx->cap_v,
                          (unsigned long long)ctx->cap_k);
+    }
+    if (frame->partition && (sel_e & kSelPlaneOverlap)) {
+        frame->checked = false;
+        return ctx->fail(MVGS_EINVAL, "the selection holds W H pixels but selects a plane position in two views: "
+                                      "it is not a partition of the plane, and the 3D loss and merge of the frame "
+                                      "are void");
     }
     frame->V = (uint32_t)V;
     frame->K = (uint32_t)K;
@@ -1216,11 +1257,12 @@ int mvgs_export_transmittance(mvgs_context* ctx, void* stream, const mvgs_frame*
     mvgs_frame* f = const_cast<mvgs_frame*>(frame);
     for (int v = 0; v < f->B; ++v)
         if (!t_final[v]) return ctx->fail(MVGS_EINVAL, "t_final[%d] is NULL", v);
+    ctx->begin(s);
     if (f->mode == MVGS_PARTIAL_COMPACT) {
         void* dptrs = nullptr;
-        HIPCHK(ctx, ctx->ring.put(t_final, sizeof(float*) * f->B, s, &dptrs));
+        HIPCHK(ctx, ctx->ring.put(t_final, sizeof(float*) * f->B, s, &dptrs, ctx->capturing));
         launch_sel_scatter(as<DevCam>(f->cams), f->B, f->n_tiles, as<uint32_t>(f->sel_off),
-                             as<uint32_t>(f->sel_pix), as<float>(f->t_final), (float* const*)dptrs, s);
+                           as<uint32_t>(f->sel_pix), as<float>(f->t_final), (float* const*)dptrs, s, frame_void(f));
         LAUNCHCHK(ctx, "transmittance scatter");
         HIPCHK(ctx, ctx->ring.seal(s));
         return MVGS_OK;
@@ -1247,10 +1289,12 @@ int mvgs_frame_merge(mvgs_context* ctx, void* stream, const mvgs_frame* frame, c
             return ctx->fail(MVGS_EINVAL, "merging needs views of one size");
     }
     hipStream_t s = (hipStream_t)stream;
+    ctx->begin(s);
     void* dptrs = nullptr;
-    HIPCHK(ctx, ctx->ring.put(planes, sizeof(float*) * f->B, s, &dptrs));
+    HIPCHK(ctx, ctx->ring.put(planes, sizeof(float*) * f->B, s, &dptrs, ctx->capturing));
     launch_sel_merge(as<DevCam>(f->cams), f->B, f->n_tiles, as<uint32_t>(f->sel_off), as<uint32_t>(f->sel_pix),
-                     (const float* const*)dptrs, channels, (uint32_t)(f->hcams[0].W * f->hcams[0].H), out, s);
+                     (const float* const*)dptrs, channels, (uint32_t)(f->hcams[0].W * f->hcams[0].H), out, s,
+                     frame_void(f));
     LAUNCHCHK(ctx, "selection merge");
     HIPCHK(ctx, ctx->ring.seal(s));
     return MVGS_OK;

@@ -26,9 +26,9 @@ __global__ void __launch_bounds__(256) k_points3d(const DevCam* __restrict__ cam
                                                   const uint32_t* __restrict__ sel_off,
                                                   const uint32_t* __restrict__ sel_pix,
                                                   const float* __restrict__ t_sel, const float* __restrict__ depth_sel,
-                                                  double4* __restrict__ pts) {
+                                                  double4* __restrict__ pts, const uint32_t* __restrict__ void_word) {
     const uint32_t t = blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (t >= n_tiles) return;
+    if (t >= n_tiles || (void_word && *void_word)) return;
     int lo = 0, hi = B;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -305,7 +305,8 @@ size_t loss3d_scratch_bytes(int W, int H) {
 
 void launch_loss3d(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off, const uint32_t* sel_pix,
                    const float* t_sel, const float* depth_sel, int W, int H, const float* img, const float* tgt,
-                   float w_l1, float w_dssim, float* loss_out, float* grad, void* scratch, hipStream_t s) {
+                   float w_l1, float w_dssim, float* loss_out, float* grad, void* scratch, hipStream_t s,
+                   const uint32_t* void_word) {
     const size_t hw = (size_t)W * H;
     uint8_t* p = (uint8_t*)scratch;
     double4* pts = (double4*)p;
@@ -320,7 +321,7 @@ void launch_loss3d(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* 
         hipLaunchKernelGGL(k_l1_plane, grid, dim3(256), 0, s, img, tgt, W, H, w_l1, grad, partial);
     } else {
         hipLaunchKernelGGL(k_points3d, dim3((n_tiles + 3) / 4), dim3(256), 0, s, cams, B, n_tiles, sel_off,
-                           sel_pix, t_sel, depth_sel, pts);
+                           sel_pix, t_sel, depth_sel, pts, void_word);
         hipLaunchKernelGGL(k_ssim3d_fwd, grid, dim3(256), 0, s, img, tgt, pts, W, H, coef, partial);
         hipLaunchKernelGGL(k_ssim3d_bwd, grid, dim3(256), 0, s, img, tgt, pts, coef, W, H, w_l1, w_dssim, grad);
     }

@@ -133,12 +133,22 @@ struct SelWave {
     int bx0, bx1, by0, by1;   // bounding rectangle of the task's pixels
 };
 
+// The task of this wavefront: tasks are taken in XCD runs; in capacity mode the grid is a bound
+// and n_dev (device) the count, and a set void word (a rejected selection, or records or pairs over
+// their capacities) leaves every task undone.
+__device__ __forceinline__ bool sel_task(uint32_t n_tasks, const uint32_t* __restrict__ n_dev,
+                                         const uint32_t* __restrict__ void_word, uint32_t* pos) {
+    if (void_word && *void_word) return false;
+    *pos = xcd_tile(blockIdx.x, n_tasks);
+    return !n_dev || *pos < *n_dev;
+}
+
 __device__ __forceinline__ SelWave sel_wave(const DevCam* __restrict__ cams, int B, const uint2* __restrict__ ranges,
                                             const uint32_t* __restrict__ sel_off,
                                             const uint32_t* __restrict__ sel_pix, const uint2* __restrict__ tasks,
-                                            uint32_t n_tasks, int lane) {
+                                            uint32_t pos, int lane) {
     SelWave w;
-    const uint2 tk = tasks[xcd_tile(blockIdx.x, n_tasks)];
+    const uint2 tk = tasks[pos];
     const uint32_t t = tk.x;
     w.v = find_view(cams, B, t);
     const DevCam& c = cams[w.v];
@@ -163,9 +173,13 @@ __global__ void __launch_bounds__(64) k_blend_fwd_sel(const DevCam* __restrict__
                                                       const uint32_t* __restrict__ sel_pix,
                                                       const uint2* __restrict__ tasks, uint32_t n_tasks,
                                                       float* const* __restrict__ images, float* __restrict__ t_sel,
-                                                      uint32_t* __restrict__ last_sel, float* __restrict__ depth_sel) {
+                                                      uint32_t* __restrict__ last_sel, float* __restrict__ depth_sel,
+                                                      const uint32_t* __restrict__ n_dev,
+                                                      const uint32_t* __restrict__ void_word) {
     const int lane = (int)threadIdx.x;
-    const SelWave w = sel_wave(cams, B, ranges, sel_off, sel_pix, tasks, n_tasks, lane);
+    uint32_t pos;
+    if (!sel_task(n_tasks, n_dev, void_word, &pos)) return;
+    const SelWave w = sel_wave(cams, B, ranges, sel_off, sel_pix, tasks, pos, lane);
     const DevCam& c = cams[w.v];
     const float px = (float)w.x + 0.5f;
     const float py[1] = {(float)w.y + 0.5f};
@@ -195,9 +209,12 @@ __global__ void __launch_bounds__(64) k_blend_bwd_sel(const DevCam* __restrict__
                                                       const float* const* __restrict__ dl_dimg,
                                                       const float* __restrict__ t_sel,
                                                       const uint32_t* __restrict__ last_sel,
-                                                      float* __restrict__ acc) {
+                                                      float* __restrict__ acc, const uint32_t* __restrict__ n_dev,
+                                                      const uint32_t* __restrict__ void_word) {
     const int lane = (int)threadIdx.x;
-    const SelWave w = sel_wave(cams, B, ranges, sel_off, sel_pix, tasks, n_tasks, lane);
+    uint32_t pos;
+    if (!sel_task(n_tasks, n_dev, void_word, &pos)) return;
+    const SelWave w = sel_wave(cams, B, ranges, sel_off, sel_pix, tasks, pos, lane);
     const DevCam& c = cams[w.v];
     const float px = (float)w.x + 0.5f;
     BwdPix st[1] = {BwdPix{1.0f, 0.0f, 0.0f, 0.0f, c.bg[0], c.bg[1], c.bg[2], (float)w.y + 0.5f, 0u}};
@@ -332,9 +349,10 @@ void launch_sel_check(const DevCam* cams, int B, uint32_t n_tiles, int tw, int t
 __global__ void __launch_bounds__(256) k_sel_scatter_f(const DevCam* __restrict__ cams, int B, uint32_t n_tiles,
                                                        const uint32_t* __restrict__ sel_off,
                                                        const uint32_t* __restrict__ sel_pix,
-                                                       const float* __restrict__ v_sel, float* const* __restrict__ out) {
+                                                       const float* __restrict__ v_sel, float* const* __restrict__ out,
+                                                       const uint32_t* __restrict__ void_word) {
     const uint32_t t = blockIdx.x * 4u + (threadIdx.x >> 6);   // one wavefront per segment
-    if (t >= n_tiles) return;
+    if (t >= n_tiles || (void_word && *void_word)) return;
     float* o = out[find_view(cams, B, t)];
     for (uint32_t i = sel_off[t] + (threadIdx.x & 63u); i < sel_off[t + 1]; i += 64u) o[sel_pix[i]] = v_sel[i];
 }
@@ -345,9 +363,9 @@ __global__ void __launch_bounds__(256) k_sel_merge(const DevCam* __restrict__ ca
                                                    const uint32_t* __restrict__ sel_off,
                                                    const uint32_t* __restrict__ sel_pix,
                                                    const float* const* __restrict__ planes, int C, uint32_t plane_px,
-                                                   float* __restrict__ out) {
+                                                   float* __restrict__ out, const uint32_t* __restrict__ void_word) {
     const uint32_t t = blockIdx.x * 4u + (threadIdx.x >> 6);   // one wavefront per segment
-    if (t >= n_tiles) return;
+    if (t >= n_tiles || (void_word && *void_word)) return;
     const float* in = planes[find_view(cams, B, t)];
     for (uint32_t i = sel_off[t] + (threadIdx.x & 63u); i < sel_off[t + 1]; i += 64u) {
         const uint32_t p = sel_pix[i];
@@ -356,10 +374,31 @@ __global__ void __launch_bounds__(256) k_sel_merge(const DevCam* __restrict__ ca
 }
 
 void launch_sel_merge(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off, const uint32_t* sel_pix,
-                      const float* const* planes, int C, uint32_t plane_px, float* out, hipStream_t s) {
+                      const float* const* planes, int C, uint32_t plane_px, float* out, hipStream_t s,
+                      const uint32_t* void_word) {
     if (!n_tiles) return;
     hipLaunchKernelGGL(k_sel_merge, dim3((n_tiles + 3) / 4), dim3(256), 0, s, cams, B, n_tiles, sel_off, sel_pix,
-                       planes, C, plane_px, out);
+                       planes, C, plane_px, out, void_word);
+}
+
+// Capacity mode: a rejected selection (bit 1 of the void word) or more tasks than their bound
+// (bit 2) voids the frame like a capacity overflow: the record and pair counts become 0 and no
+// kernel reads the pixel indices.
+__global__ void k_sel_void(const uint32_t* __restrict__ sel_err, const unsigned long long* __restrict__ task_total,
+                           uint32_t task_cap, uint32_t* __restrict__ eff, uint32_t* __restrict__ void_word) {
+    uint32_t bits = (*sel_err & kSelErrors) ? 2u : 0u;
+    if (*task_total > task_cap) bits |= 4u;
+    if (bits) {
+        eff[0] = 0u;
+        eff[1] = 0u;
+        *void_word |= bits;
+    }
+}
+
+void launch_sel_void(const uint32_t* sel_err, const uint64_t* task_total, uint32_t task_cap, uint32_t* eff,
+                     uint32_t* void_word, hipStream_t s) {
+    hipLaunchKernelGGL(k_sel_void, dim3(1), dim3(1), 0, s, sel_err, (const unsigned long long*)task_total, task_cap,
+                       eff, void_word);
 }
 
 void launch_sel_tasks(uint32_t n_tiles, const uint32_t* n_tasks, const uint32_t* task_off, uint32_t cap,
@@ -372,17 +411,20 @@ void launch_sel_tasks(uint32_t n_tiles, const uint32_t* n_tasks, const uint32_t*
 void launch_blend_fwd_sel(const SelBlendArgs& a, hipStream_t s) {
     if (!a.n_tasks) return;
     hipLaunchKernelGGL(k_blend_fwd_sel, dim3(a.n_tasks), dim3(64), 0, s, a.cams, a.B, a.ranges, a.vals, a.recs,
-                       a.sel_off, a.sel_pix, a.tasks, a.n_tasks, a.images, a.t_sel, a.last_sel, a.depth_sel);
+                       a.sel_off, a.sel_pix, a.tasks, a.n_tasks, a.images, a.t_sel, a.last_sel, a.depth_sel, a.n_dev,
+                       a.void_word);
 }
 
 void launch_blend_bwd_sel(const SelBlendArgs& a, hipStream_t s) {
     if (!a.n_tasks) return;
     if (a.want_e1)
         hipLaunchKernelGGL(k_blend_bwd_sel<true>, dim3(a.n_tasks), dim3(64), 0, s, a.cams, a.B, a.ranges, a.vals,
-                           a.recs, a.sel_off, a.sel_pix, a.tasks, a.n_tasks, a.dl_dimg, a.t_sel, a.last_sel, a.acc);
+                           a.recs, a.sel_off, a.sel_pix, a.tasks, a.n_tasks, a.dl_dimg, a.t_sel, a.last_sel, a.acc,
+                           a.n_dev, a.void_word);
     else
         hipLaunchKernelGGL(k_blend_bwd_sel<false>, dim3(a.n_tasks), dim3(64), 0, s, a.cams, a.B, a.ranges, a.vals,
-                           a.recs, a.sel_off, a.sel_pix, a.tasks, a.n_tasks, a.dl_dimg, a.t_sel, a.last_sel, a.acc);
+                           a.recs, a.sel_off, a.sel_pix, a.tasks, a.n_tasks, a.dl_dimg, a.t_sel, a.last_sel, a.acc,
+                           a.n_dev, a.void_word);
 }
 
 void launch_subsample(const uint32_t* keys, int W, int H, int B, int tw, int th, uint32_t* sel_off,
@@ -400,10 +442,10 @@ void launch_subsample(const uint32_t* keys, int W, int H, int B, int tw, int th,
 }
 
 void launch_sel_scatter(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off, const uint32_t* sel_pix,
-                        const float* v_sel, float* const* out, hipStream_t s) {
+                        const float* v_sel, float* const* out, hipStream_t s, const uint32_t* void_word) {
     if (!n_tiles) return;
     hipLaunchKernelGGL(k_sel_scatter_f, dim3((n_tiles + 3) / 4), dim3(256), 0, s, cams, B, n_tiles, sel_off,
-                       sel_pix, v_sel, out);
+                       sel_pix, v_sel, out, void_word);
 }
 
 void launch_frame_work_sel(const DevCam* cams, int B, uint32_t n_tiles, const uint2* ranges, const uint32_t* vals,

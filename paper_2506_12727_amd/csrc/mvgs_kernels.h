@@ -142,7 +142,11 @@ struct SelBlendArgs {
     const float* const* dl_dimg;  // backward
     float* acc;
     int want_e1;
+    const uint32_t* n_dev;      // capacity mode: the task count (device; n_tasks is then the bound)
+    const uint32_t* void_word;  // capacity mode: non-zero voids the frame (nothing is rendered)
 };
+void launch_sel_void(const uint32_t* sel_err, const uint64_t* task_total, uint32_t task_cap, uint32_t* eff,
+                     uint32_t* void_word, hipStream_t s);
 void launch_sel_check(const DevCam* cams, int B, uint32_t n_tiles, int tw, int th, const uint32_t* sel_off,
                       const uint32_t* sel_pix, uint32_t n_sel, uint32_t* mask, uint32_t* plane_mask, uint32_t* n_tasks,
                       uint32_t* err, hipStream_t s);
@@ -153,9 +157,10 @@ void launch_blend_bwd_sel(const SelBlendArgs& a, hipStream_t s);
 void launch_subsample(const uint32_t* keys, int W, int H, int B, int tw, int th, uint32_t* sel_off,
                       uint32_t* sel_pix, void* scan_scratch, hipStream_t s);
 void launch_sel_merge(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off, const uint32_t* sel_pix,
-                      const float* const* planes, int C, uint32_t plane_px, float* out, hipStream_t s);
+                      const float* const* planes, int C, uint32_t plane_px, float* out, hipStream_t s,
+                      const uint32_t* void_word = nullptr);
 void launch_sel_scatter(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off, const uint32_t* sel_pix,
-                        const float* v_sel, float* const* out, hipStream_t s);
+                        const float* v_sel, float* const* out, hipStream_t s, const uint32_t* void_word = nullptr);
 void launch_frame_work_sel(const DevCam* cams, int B, uint32_t n_tiles, const uint2* ranges, const uint32_t* vals,
                            const BlendRec* recs, const uint32_t* sel_off, const uint32_t* sel_pix,
                            const uint32_t* last_sel, uint64_t* out, hipStream_t s);
@@ -192,7 +197,8 @@ void launch_grad_moments(const GradSegments& g, double* sum, double* acc, double
 size_t loss3d_scratch_bytes(int W, int H);
 void launch_loss3d(const DevCam* cams, int B, uint32_t n_tiles, const uint32_t* sel_off, const uint32_t* sel_pix,
                    const float* t_sel, const float* depth_sel, int W, int H, const float* img, const float* tgt,
-                   float w_l1, float w_dssim, float* loss_out, float* grad, void* scratch, hipStream_t s);
+                   float w_l1, float w_dssim, float* loss_out, float* grad, void* scratch, hipStream_t s,
+                   const uint32_t* void_word = nullptr);
 
 // k_loss.hip
 struct LossView {

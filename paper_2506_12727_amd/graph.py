@@ -7,6 +7,12 @@ them. The graph keeps its tensors: write new targets into `targets` before a rep
 batch's poses with `set_cameras` (same image sizes). Each replay overwrites `images`, `loss`,
 `dl` and `grads` and adds to the statistics. `check()` waits and raises if the last replay's
 records or pairs exceeded the capacities (its results are then void).
+
+With `partial=True` the step is the thread-efficient partial rendering of Alg. 3: the views (of
+one size) share one image plane by the per-position keys in `keys` (int32 [H*W]; each replay
+draws new ones into it first unless `fresh_keys=False`, then the caller writes them), the
+targets are merged into `target_plane` by the same selection, and the loss is L1 + the 3D
+distance-aware D-SSIM of Sec. 5.1.2 on the plane (`plane`, its gradient `dl_plane`).
 """
 from __future__ import annotations
 
@@ -32,17 +38,29 @@ def measure_capacity(g: GaussianTensors, cams, tile=(16, 16), ppl=0, headroom: f
 
 class CapturedStep:
     def __init__(self, g: GaussianTensors, cams, targets, w_l1=1.0, w_dssim=0.0, tile=(16, 16), ppl=0,
-                 capacity=None, densify: Optional[dict] = None):
+                 capacity=None, densify: Optional[dict] = None, partial: bool = False, fresh_keys: bool = True):
         g.check()
         self.g, self.cams = g, list(cams)
         self.w_l1, self.w_dssim = float(w_l1), float(w_dssim)
+        self.partial, self.fresh_keys = bool(partial), bool(fresh_keys)
+        if self.partial and len({(c.width, c.height) for c in self.cams}) != 1:
+            raise ValueError("partial rendering shares one image plane: the views must have one size")
         if capacity is None:
             capacity = measure_capacity(g, cams, tile, ppl)
         self.rast = Rasterizer(tile, ppl, capacity=capacity)
         dev = g.means.device
-        self.images = [torch.empty((3, c.height, c.width), device=dev) for c in cams]
         self.targets = [t.contiguous() for t in targets]
-        self.dl = [torch.empty_like(t) for t in self.images]
+        if self.partial:
+            W, H = self.cams[0].width, self.cams[0].height
+            self.keys = torch.randint(-2 ** 31, 2 ** 31, (W * H,), dtype=torch.int32, device=dev)
+            self.plane = torch.zeros((3, H, W), device=dev)
+            self.target_plane = torch.zeros((3, H, W), device=dev)
+            self.dl_plane = torch.empty((3, H, W), device=dev)
+            self.images = [self.plane] * len(self.cams)
+            self.dl = [self.dl_plane] * len(self.cams)
+        else:
+            self.images = [torch.empty((3, c.height, c.width), device=dev) for c in cams]
+            self.dl = [torch.empty_like(t) for t in self.images]
         self.loss = torch.empty(1, device=dev)
         self.grads = dict(means=torch.empty_like(g.means), scales=torch.empty_like(g.scales),
                           quats=torch.empty_like(g.quats), opacities=torch.empty_like(g.opacities),
@@ -60,8 +78,16 @@ class CapturedStep:
 
     def _step(self):
         r = self.rast
-        _, fr = r.forward(self.g, self.cams, images=self.images)
-        r.loss(self.cams, self.images, self.targets, self.w_l1, self.w_dssim, out=self.loss, grads=self.dl)
+        if self.partial:
+            if self.fresh_keys:
+                self.keys.random_(-2 ** 31, 2 ** 31)
+            off, pix = r.subsample(self.cams, self.keys)
+            _, fr = r.forward_partial(self.g, self.cams, off, pix, 0, images=self.images)
+            r.merge(fr, self.targets, out=self.target_plane)
+            r.loss_3d(fr, self.plane, self.target_plane, self.w_l1, self.w_dssim, out=self.loss, grad=self.dl_plane)
+        else:
+            _, fr = r.forward(self.g, self.cams, images=self.images)
+            r.loss(self.cams, self.images, self.targets, self.w_l1, self.w_dssim, out=self.loss, grads=self.dl)
         r.backward(self.g, fr, self.dl, densify=self.densify, grads=self.grads)
         return fr
 

@@ -70,8 +70,10 @@ class Frame:
         self.released = False
 
     def check(self):
-        """Capacity mode: wait for the forward and raise MvgsError (MVGS_ECAPACITY) if its records or
-        pairs exceeded the context's capacities. No-op otherwise."""
+        """Capacity mode: wait for the forward and raise MvgsError if its results are void: records
+        or pairs over the context's capacities (MVGS_ECAPACITY), or for a partial frame a rejected
+        pixel selection, or a selection of W*H pixels that is no partition of the plane
+        (MVGS_EINVAL). No-op otherwise."""
         L.check(L.lib().mvgs_frame_check(self.rast.ctx, _stream(), self.handle), self.rast.ctx)
 
     def set_cameras(self, cams):
@@ -356,8 +358,11 @@ class Rasterizer:
         L.check(self.lib.mvgs_grad_moments(self.ctx, _stream(), g.P, g.sh_degree, C.byref(self._grads(grads)),
                                            sum_.data_ptr(), acc.data_ptr()), self.ctx)
 
-    def export_transmittance(self, frame: Frame):
-        outs = [torch.empty((c.height, c.width), dtype=torch.float32, device="cuda") for c in frame.cams]
+    def export_transmittance(self, frame: Frame, outs=None):
+        """Final transmittance [H,W] of each view (of the selected pixels only for a thread-efficient
+        partial frame: other pixels of `outs` are kept)."""
+        if outs is None:
+            outs = [torch.zeros((c.height, c.width), dtype=torch.float32, device="cuda") for c in frame.cams]
         L.check(self.lib.mvgs_export_transmittance(self.ctx, _stream(), frame.handle,
                                                    L.ptr_array([t.data_ptr() for t in outs])), self.ctx)
         return outs
