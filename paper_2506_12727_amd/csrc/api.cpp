@@ -216,8 +216,7 @@ struct mvgs_context {
     int tw = 16, th = 16, ppl = 2;
     std::string err;
     std::vector<mvgs_frame*> frames;
-    DevBuf nrec, ntiles, totals, scan_scratch, depth_key[2], rec_vals[2], tile_rect, sorted_rect, pair_counts,
-        pair_off;
+    DevBuf nrec, ntiles, totals, scan_scratch, depth_key[2], rec_vals[2], tile_rect, sorted_rect;
     DevBuf sort_scratch, acc, loss_scratch, ssim_maps, loss3d_scratch, adc_n, adc_off, adc_act, moment_partials;
     size_t limit = 0;  // 0: no workspace limit
     uint64_t cap_v = 0, cap_k = 0;  // capacity mode when non-zero
@@ -241,7 +240,7 @@ struct mvgs_context {
     template <typename Fn>
     void each_buffer(Fn fn) {
         DevBuf* bufs[] = {&nrec, &ntiles, &totals, &scan_scratch, &depth_key[0], &depth_key[1], &rec_vals[0],
-                          &rec_vals[1], &tile_rect, &sorted_rect, &pair_counts, &pair_off, &sort_scratch, &acc,
+                          &rec_vals[1], &tile_rect, &sorted_rect, &sort_scratch, &acc,
                           &loss_scratch, &ssim_maps, &loss3d_scratch, &adc_n, &adc_off, &adc_act,
                           &moment_partials, &work};
         for (DevBuf* b : bufs) fn(*b);
@@ -740,8 +739,6 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
                           {&ctx->rec_vals[1], sizeof(uint32_t) * V1},
                           {&ctx->tile_rect, sizeof(uint4) * V1},
                           {&ctx->sorted_rect, sizeof(uint4) * V1},
-                          {&ctx->pair_counts, sizeof(uint32_t) * V1},
-                          {&ctx->pair_off, sizeof(uint32_t) * V1},
                           {&f->keys[0], sizeof(uint32_t) * K1},
                           {&f->keys[1], sizeof(uint32_t) * K1},
                           {&f->vals[0], sizeof(uint32_t) * K1},
@@ -752,7 +749,7 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
                           {&f->depth, (sel && sel->mode == MVGS_PARTIAL_COMPACT)
                                           ? sizeof(float) * std::max<size_t>(sel->n_sel, 1) : (size_t)0},
                           {&ctx->sort_scratch,
-                           std::max(radix_scratch_bytes(std::max<size_t>(V, K)), scan_scratch_bytes(V))}};
+                           std::max(radix_scratch_bytes(V), emit_sort_scratch_bytes(V, K))}};
     const int n_need2 = (int)(sizeof(need2) / sizeof(need2[0]));
     st = grow_all(ctx, need2, n_need2);
     if (st) {
@@ -772,20 +769,18 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     const uint32_t* sorted_rec = dv[dcur];
     ctx->stage_end(mk, s);
 
-    // pairs in depth order, then a stable sort by global tile id
+    // pairs in depth order, emitted into their places after the first pass of the stable sort by
+    // global tile id, then the other passes
     mk = ctx->stage_begin(3, s);
-    launch_gather_tile_counts(sorted_rec, as<uint4>(ctx->tile_rect), V, as<uint32_t>(ctx->pair_counts),
-                              as<uint4>(ctx->sorted_rect), s, eff);
-    scan_exclusive_u32(as<uint32_t>(ctx->pair_counts), as<uint32_t>(ctx->pair_off), V, nullptr,
-                       ctx->sort_scratch.p, s, eff);
-    launch_emit_pairs(sorted_rec, as<uint4>(ctx->sorted_rect), as<uint32_t>(ctx->pair_off), V, K,
-                      as<uint32_t>(f->keys[0]), as<uint32_t>(f->vals[0]), s, eff);
+    const int tile_bits = bits_for(n_tiles);
+    emit_pairs_first_pass(sorted_rec, as<uint4>(ctx->tile_rect), as<uint4>(ctx->sorted_rect), V, eff,
+                          as<uint32_t>(f->keys[0]), as<uint32_t>(f->vals[0]), K, eff ? eff + 1 : nullptr, tile_bits,
+                          ctx->sort_scratch.p, s);
     ctx->stage_end(mk, s);
     mk = ctx->stage_begin(4, s);
     uint32_t* pk[2] = {as<uint32_t>(f->keys[0]), as<uint32_t>(f->keys[1])};
     uint32_t* pv[2] = {as<uint32_t>(f->vals[0]), as<uint32_t>(f->vals[1])};
-    f->final_buf = radix_sort_u32(pk, pv, false, K, bits_for(n_tiles), ctx->sort_scratch.p, s,
-                                  eff ? eff + 1 : nullptr);
+    f->final_buf = sort_pairs_rest(pk, pv, K, eff ? eff + 1 : nullptr, tile_bits, ctx->sort_scratch.p, s);
     ctx->stage_end(mk, s);
     mk = ctx->stage_begin(5, s);
     launch_ranges(pk[f->final_buf], K, n_tiles, as<uint2>(f->ranges), s, eff ? eff + 1 : nullptr);

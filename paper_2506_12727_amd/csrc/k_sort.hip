@@ -42,22 +42,24 @@ __global__ void k_fill_u64(uint64_t* __restrict__ p, size_t n, uint64_t v) {
     if (i < n) p[i] = v;
 }
 
-// exclusive scan of 256 values held one per thread; returns the exclusive prefix, sets *total
+// exclusive scan of 256 values held one per thread (a workgroup of 256): each wavefront scans its
+// 64 values with shuffles, then the four wavefront totals are combined through LDS (lds: at least
+// 4 words). Returns the exclusive prefix and sets *total; lds may be reused on return.
 __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_t* lds, uint32_t* total) {
-    const int t = threadIdx.x;
-    lds[t] = v;
-    __syncthreads();
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t x = v;
 #pragma unroll
-    for (int off = 1; off < 256; off <<= 1) {
-        const uint32_t add = (t >= off) ? lds[t - off] : 0u;
-        __syncthreads();
-        lds[t] += add;
-        __syncthreads();
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, off, 64);
+        if (lane >= off) x += y;
     }
-    const uint32_t incl = lds[t];
-    *total = lds[255];
+    if (lane == 63) lds[wave] = x;
     __syncthreads();
-    return incl - v;
+    const uint32_t w0 = lds[0], w1 = lds[1], w2 = lds[2], w3 = lds[3];
+    __syncthreads();
+    *total = w0 + w1 + w2 + w3;
+    const uint32_t before = (wave > 0 ? w0 : 0u) + (wave > 1 ? w1 : 0u) + (wave > 2 ? w2 : 0u);
+    return before + x - v;
 }
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t* __restrict__ in, size_t n,
@@ -165,22 +167,27 @@ void scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* t
 // radix sort
 // ---------------------------------------------------------------------------------------------
 
-// lanes of this wave holding the same 8-bit digit (among `valid` lanes)
+// lanes of this wave holding the same 8-bit digit (among `valid` lanes): per bit, the lane's bit
+// spread over a word (0 or ~0) is both the ballot's predicate and the mask that keeps the ballot
+// or its complement, so the update is one three-input logic op per half of the peer mask
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
-    uint64_t peers = ballot64(valid);
+    const uint64_t v = ballot64(valid);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t m = ballot64(bit);
-        peers &= bit ? m : ~m;
+        const uint32_t splat = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+        const uint64_t m = ballot64((int32_t)splat < 0);
+        lo &= ~((uint32_t)m ^ splat);
+        hi &= ~((uint32_t)(m >> 32) ^ splat);
     }
-    return peers;
+    return ((uint64_t)hi << 32) | lo;
 }
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Reduce-then-scan pass, step 1: per-partition digit counts, digit-major (counts[d * parts + p]),
-// so that one exclusive scan of the whole array gives every (digit, partition) its output base.
+// Reduce-then-scan pass, step 1: per-partition digit counts, digit-major (counts[d * parts + p] for
+// the mask + 1 digits of the pass), so that one exclusive scan of the whole table gives every
+// (digit, partition) its output base.
 __global__ void __launch_bounds__(256) k_radix_upsweep(const uint32_t* __restrict__ keys, size_t n,
                                                        const uint32_t* __restrict__ n_dev, int shift, uint32_t mask,
                                                        uint32_t parts, uint32_t* __restrict__ counts) {
@@ -205,7 +212,7 @@ __global__ void __launch_bounds__(256) k_radix_upsweep(const uint32_t* __restric
         }
     }
     __syncthreads();
-    counts[(size_t)threadIdx.x * parts + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x <= mask) counts[(size_t)threadIdx.x * parts + blockIdx.x] = h[threadIdx.x];
 }
 
 // Step 3: rank each partition's items stably with wave64 ballots and scatter them through LDS in
@@ -225,7 +232,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     const uint32_t part = blockIdx.x;
     n = count_of(n, n_dev);
     if ((size_t)part * kSortTile >= n) return;
-    gbase[threadIdx.x] = offsets[(size_t)threadIdx.x * parts + part];
+    gbase[threadIdx.x] = threadIdx.x <= mask ? offsets[(size_t)threadIdx.x * parts + part] : 0u;
     __syncthreads();
     const size_t base = (size_t)part * kSortTile + (size_t)wave * kSortRounds * 64;
     uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
@@ -289,27 +296,42 @@ size_t radix_scratch_bytes(size_t n) {
     return align256(parts * kRadix * sizeof(uint32_t)) + scan_scratch_bytes(parts * kRadix);
 }
 
-int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
-                   hipStream_t s, const uint32_t* n_dev) {
-    int cur = 0;
-    if (n == 0 || bits <= 0) return cur;
-    // fewest 8-bit passes, digits spread evenly over them (fewer distinct digits per workgroup
-    // give longer runs of consecutive stores)
-    const int passes = (bits + 7) / 8;
-    const int dbits = (bits + passes - 1) / passes;
-    const uint32_t mask = (1u << dbits) - 1u;
+// fewest passes of at most 8 bits, digits spread evenly over them (fewer distinct digits per
+// workgroup give longer runs of consecutive stores)
+struct PassPlan {
+    int passes, dbits;
+    uint32_t mask;
+};
+static PassPlan plan_passes(int bits) {
+    PassPlan pl;
+    pl.passes = std::max(1, (bits + 7) / 8);
+    pl.dbits = (bits + pl.passes - 1) / pl.passes;
+    pl.mask = (1u << pl.dbits) - 1u;
+    return pl;
+}
+
+// one reduce-then-scan pass over n items (bound; n_dev the count on the device)
+static void radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
+                       size_t n, const uint32_t* n_dev, int shift, uint32_t mask, void* scratch, hipStream_t s) {
     const size_t parts = div_up(n, kSortTile);
     uint8_t* p = (uint8_t*)scratch;
     uint32_t* counts = (uint32_t*)p;
     p += align256(parts * kRadix * sizeof(uint32_t));
-    for (int pass = 0; pass < passes; ++pass) {
+    hipLaunchKernelGGL(k_radix_upsweep, dim3((unsigned)parts), dim3(256), 0, s, keys_in, n, n_dev, shift, mask,
+                       (uint32_t)parts, counts);
+    scan_exclusive_u32(counts, counts, parts * ((size_t)mask + 1), nullptr, p, s, nullptr);
+    hipLaunchKernelGGL(k_radix_downsweep, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in, vals_in,
+                       keys_out, vals_out, n, n_dev, shift, mask, (uint32_t)parts, (const uint32_t*)counts);
+}
+
+int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
+                   hipStream_t s, const uint32_t* n_dev) {
+    int cur = 0;
+    if (n == 0 || bits <= 0) return cur;
+    const PassPlan pl = plan_passes(bits);
+    for (int pass = 0; pass < pl.passes; ++pass) {
         const uint32_t* vin = (pass == 0 && identity_values) ? nullptr : vals[cur];
-        hipLaunchKernelGGL(k_radix_upsweep, dim3((unsigned)parts), dim3(256), 0, s, keys[cur], n, n_dev, dbits * pass,
-                           mask, (uint32_t)parts, counts);
-        scan_exclusive_u32(counts, counts, parts * kRadix, nullptr, p, s, nullptr);
-        hipLaunchKernelGGL(k_radix_downsweep, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys[cur], vin,
-                           keys[cur ^ 1], vals[cur ^ 1], n, n_dev, dbits * pass, mask, (uint32_t)parts,
-                           (const uint32_t*)counts);
+        radix_pass(keys[cur], vin, keys[cur ^ 1], vals[cur ^ 1], n, n_dev, pl.dbits * pass, pl.mask, scratch, s);
         cur ^= 1;
     }
     return cur;
@@ -321,76 +343,266 @@ int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, s
 
 __device__ __forceinline__ uint32_t rect_tiles(uint4 r) { return (r.y & 0xffffu) * (r.y >> 16); }
 
-// The one gather of the records' tile rectangles in depth order: pair counts, and the rectangles
-// themselves in that order so that pair emission reads them sequentially.
-__global__ void k_gather_tile_counts(const uint32_t* __restrict__ sorted_rec, const uint4* __restrict__ rect,
-                                     uint32_t n, const uint32_t* __restrict__ n_dev, uint32_t* __restrict__ counts,
-                                     uint4* __restrict__ sorted_rect) {
+// The one gather of the records' tile rectangles into depth order, so that pair emission reads
+// them sequentially.
+__global__ void k_gather_rects(const uint32_t* __restrict__ sorted_rec, const uint4* __restrict__ rect, uint32_t n,
+                               const uint32_t* __restrict__ n_dev, uint4* __restrict__ sorted_rect) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < (uint32_t)count_of(n, n_dev)) {
-        const uint4 r = rect[sorted_rec[i]];
-        counts[i] = rect_tiles(r);
-        sorted_rect[i] = r;
-    }
+    if (i < (uint32_t)count_of(n, n_dev)) sorted_rect[i] = rect[sorted_rec[i]];
 }
 
-// Load-balanced emission: a workgroup takes 256 consecutive records of the depth order; their
-// pairs are contiguous in the output, so the workgroup's lanes walk those pairs in order (each
-// store is coalesced across the wavefront) and find their record by binary search over the
-// workgroup's prefix sums in LDS. Pair j of a record with a w-tile-wide rectangle is tile
-// (tx0 + j mod w, ty0 + j / w), row-major, as a per-record loop would emit them.
-constexpr int kEmitThreads = 256;
+// Pair emission fused with the first pass of the stable sort by global tile id. A workgroup takes
+// a chunk of kEmitRecs consecutive records of the depth order; their pairs, in depth order and
+// row-major over each record's tile rectangle, are the chunk's items (the partition of the first
+// pass). Both kernels generate them alike: the chunk's rectangles and the exclusive prefix of
+// their tile counts are staged in LDS, and lane j of the chunk finds its record by binary search
+// over that prefix; pair t of a record whose rectangle is w tiles wide is tile (tx0 + t mod w,
+// ty0 + t / w). The upsweep counts their digits; the downsweep ranks them stably in batches of
+// kEmitBatch (wave64 ballots), stages each batch in LDS in digit order and writes it in runs. The
+// emitted pairs are never stored unsorted.
+constexpr int kEmitRecs = 512;
+constexpr int kEmitRounds = 16;
+constexpr int kEmitBatch = kSortWaves * kEmitRounds * 64;   // 4096
+// per wavefront, its 1024 pairs lane-major (lane l walks pairs 16 l .. 16 l + 15), padded to 17
+// words per lane so that neither the lane-major writes nor the round-major reads conflict
+constexpr int kEmitPad = kEmitRounds + 1;
+constexpr int kEmitStageWords = kSortWaves * 64 * kEmitPad;   // 4352 >= kEmitBatch
 
-__global__ void __launch_bounds__(kEmitThreads) k_emit_pairs(const uint32_t* __restrict__ sorted_rec,
-                                                             const uint4* __restrict__ sorted_rect,
-                                                             const uint32_t* __restrict__ pair_off, uint32_t n,
-                                                             uint32_t K, const uint32_t* __restrict__ counts_dev,
-                                                             uint32_t* __restrict__ keys,
-                                                             uint32_t* __restrict__ vals) {
-    __shared__ uint32_t s_off[kEmitThreads + 1];   // local exclusive offsets (+ total)
-    __shared__ uint32_t s_rec[kEmitThreads];
-    __shared__ uint32_t s_x[kEmitThreads];         // width in tiles
-    __shared__ uint32_t s_base[kEmitThreads];      // global tile id of the first covered tile
-    __shared__ uint32_t s_stride[kEmitThreads];    // tiles per row of the record's view
-    // counts_dev: (records, pairs) actually present, when the grid is sized by bounds
-    if (counts_dev) {
-        n = (uint32_t)count_of(n, counts_dev);
-        K = (uint32_t)count_of(K, counts_dev + 1);
-    }
-    const uint32_t i0 = blockIdx.x * kEmitThreads;
-    if (i0 >= n) return;
-    const uint32_t i = i0 + threadIdx.x;
-    const uint32_t base_out = pair_off[i0];
-    if (i < n) {
-        const uint32_t r = sorted_rec[i];
-        const uint4 rc = sorted_rect[i];
-        s_rec[threadIdx.x] = r;
-        s_x[threadIdx.x] = rc.y & 0xffffu;
-        s_base[threadIdx.x] = rc.x;
-        s_stride[threadIdx.x] = rc.z;
-        s_off[threadIdx.x] = pair_off[i] - base_out;
-    }
-    const uint32_t last = min(n - i0, (uint32_t)kEmitThreads);
-    if (threadIdx.x == 0) s_off[last] = (i0 + last < n ? pair_off[i0 + last] : K) - base_out;
-    __syncthreads();
-    const uint32_t total = s_off[last];
-    for (uint32_t j = threadIdx.x; j < total; j += kEmitThreads) {
-        // record k with s_off[k] <= j < s_off[k + 1]
-        uint32_t lo = 0, hi = last;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (s_off[mid] <= j) lo = mid;
-            else hi = mid;
+struct EmitStage {
+    uint32_t off[kEmitRecs + 1];   // exclusive prefix of the pair counts (+ total)
+    uint32_t base[kEmitRecs];      // global tile id of the first covered tile
+    uint32_t wdt[kEmitRecs];       // rectangle width in tiles
+    uint32_t stride[kEmitRecs];    // tiles per row of the record's view
+    uint32_t rec[kEmitRecs];
+};
+
+// Stages records [r0, r0 + cnt) of the depth order (cnt <= kEmitRecs); returns the chunk's pairs.
+__device__ __forceinline__ uint32_t emit_stage(const uint32_t* __restrict__ sorted_rec,
+                                               const uint4* __restrict__ sorted_rect, uint32_t r0, uint32_t cnt,
+                                               EmitStage& st, uint32_t* scan_tmp) {
+    constexpr int kPer = kEmitRecs / kSortThreads;   // consecutive records per thread
+    const uint32_t t = threadIdx.x;
+    uint32_t c[kPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const uint32_t i = kPer * t + (uint32_t)k;
+        c[k] = 0u;
+        if (i < cnt) {
+            const uint4 rc = sorted_rect[r0 + i];
+            c[k] = rect_tiles(rc);
+            st.base[i] = rc.x;
+            st.wdt[i] = rc.y & 0xffffu;
+            st.stride[i] = rc.z;
+            if (sorted_rec) st.rec[i] = sorted_rec[r0 + i];
         }
-        const uint32_t t = j - s_off[lo];
-        const uint32_t w = s_x[lo];
-        // t < 65536, so (t + 0.5) / w in float32 is never within rounding of an integer
+        sum += c[k];
+    }
+    uint32_t total;
+    uint32_t ex = block_exclusive_scan_256(sum, scan_tmp, &total);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        st.off[kPer * t + (uint32_t)k] = ex;
+        ex += c[k];
+    }
+    if (t == 0) st.off[kEmitRecs] = total;
+    __syncthreads();
+    return total;
+}
+
+// the staged record holding pair j of the chunk: the last one whose prefix is <= j (records
+// without pairs are passed over); a fixed number of steps, so that searches of several pairs
+// interleave
+__device__ __forceinline__ uint32_t emit_find(const EmitStage& st, uint32_t cnt, uint32_t j) {
+    uint32_t k = 0;
+#pragma unroll
+    for (uint32_t step = kEmitRecs / 2; step > 0; step >>= 1)
+        if (k + step < cnt && st.off[k + step] <= j) k += step;
+    return k;
+}
+
+
+// Walks the pairs of the staged chunk from pair j on, row-major over each rectangle.
+template <bool REC>
+struct EmitWalk {
+    uint32_t k, w, stride, left, col, rowkey, rec;
+    __device__ __forceinline__ void start(const EmitStage& st, uint32_t cnt, uint32_t j) {
+        k = emit_find(st, cnt, j);
+        if (REC) rec = st.rec[k];
+        w = st.wdt[k];
+        stride = st.stride[k];
+        left = st.off[k + 1] - j;
+        const uint32_t t = j - st.off[k];
+        // t < 65536 (tiles per view), so (t + 0.5) / w in float32 is never within rounding of an integer
         const uint32_t row = (uint32_t)floorf(((float)t + 0.5f) * __builtin_amdgcn_rcpf((float)w));
-        const uint32_t col = t - row * w;
-        const uint32_t o = base_out + j;
-        if (o >= K) break;
-        keys[o] = s_base[lo] + row * s_stride[lo] + col;
-        vals[o] = s_rec[lo];
+        col = t - row * w;
+        rowkey = st.base[k] + row * stride;
+    }
+    __device__ __forceinline__ uint32_t key() const { return rowkey + col; }
+    // to the next pair; the caller knows there is one
+    __device__ __forceinline__ void next(const EmitStage& st) {
+        if (--left == 0) {
+            // the next record: all its fields in one round trip to LDS (records without pairs,
+            // which the loop passes over, are rare)
+            ++k;
+            uint32_t o0 = st.off[k], o1 = st.off[k + 1];
+            uint32_t nb = st.base[k], nw = st.wdt[k], ns = st.stride[k], nr = REC ? st.rec[k] : 0u;
+            while (o1 == o0) {
+                ++k;
+                o1 = st.off[k + 1];
+                nb = st.base[k];
+                nw = st.wdt[k];
+                ns = st.stride[k];
+                if (REC) nr = st.rec[k];
+            }
+            rec = nr;
+            w = nw;
+            stride = ns;
+            left = o1 - o0;
+            rowkey = nb;
+            col = 0;
+        } else if (++col == w) {
+            col = 0;
+            rowkey += stride;
+        }
+    }
+};
+
+__global__ void __launch_bounds__(kSortThreads) k_emit_upsweep(const uint4* __restrict__ sorted_rect, uint32_t n,
+                                                               const uint32_t* __restrict__ n_dev, uint32_t mask,
+                                                               uint32_t chunks, uint32_t* __restrict__ counts) {
+    __shared__ EmitStage st;
+    __shared__ uint32_t h[kRadix];
+    __shared__ uint32_t scan_tmp[kRadix];
+    h[threadIdx.x] = 0;
+    n = (uint32_t)count_of(n, n_dev);
+    const uint32_t r0 = blockIdx.x * kEmitRecs;
+    if (r0 < n) {   // uniform over the workgroup
+        const uint32_t cnt = min(n - r0, (uint32_t)kEmitRecs);
+        const uint32_t total = emit_stage(nullptr, sorted_rect, r0, cnt, st, scan_tmp);
+        // each thread counts a contiguous run of pairs, walking the rectangles row-major
+        const uint32_t q = (total + kSortThreads - 1) / kSortThreads;
+        uint32_t j = threadIdx.x * q;
+        const uint32_t jend = min(j + q, total);
+        if (j < jend) {
+            EmitWalk<false> wk;
+            wk.start(st, cnt, j);
+            for (;;) {
+                atomicAdd(&h[wk.key() & mask], 1u);
+                if (++j == jend) break;
+                wk.next(st);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x <= mask) counts[(size_t)threadIdx.x * chunks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_emit_downsweep(
+    const uint32_t* __restrict__ sorted_rec, const uint4* __restrict__ sorted_rect, uint32_t n,
+    const uint32_t* __restrict__ n_dev, uint32_t mask, uint32_t chunks, const uint32_t* __restrict__ offsets,
+    uint32_t K, const uint32_t* __restrict__ K_dev, uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+    __shared__ EmitStage st;
+    __shared__ uint32_t wcount[kSortWaves][kRadix];
+    __shared__ uint32_t dstart[kRadix];
+    __shared__ uint32_t gbase[kRadix];
+    __shared__ uint32_t scan_tmp[kRadix];
+    // the lane-major pairs of each wavefront, then (after the ranking) the batch in digit order
+    __shared__ uint32_t skey[kEmitStageWords];
+    __shared__ uint32_t sval[kEmitStageWords];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    n = (uint32_t)count_of(n, n_dev);
+    K = (uint32_t)count_of(K, K_dev);
+    const uint32_t r0 = blockIdx.x * kEmitRecs;
+    if (r0 >= n) return;
+    const uint32_t cnt = min(n - r0, (uint32_t)kEmitRecs);
+    gbase[threadIdx.x] = threadIdx.x <= mask ? offsets[(size_t)threadIdx.x * chunks + blockIdx.x] : 0u;
+    const uint32_t total = emit_stage(sorted_rec, sorted_rect, r0, cnt, st, scan_tmp);
+    for (uint32_t b0 = 0; b0 < total; b0 += kEmitBatch) {
+        const uint32_t bn = min(total - b0, (uint32_t)kEmitBatch);
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) wcount[w][threadIdx.x] = 0u;
+        __syncthreads();
+        const uint32_t wbase = (uint32_t)wave * kEmitRounds * 64u;
+        uint32_t key[kEmitRounds], val[kEmitRounds], rank[kEmitRounds];
+        {
+            // lane l walks this wavefront's pairs 16 l .. 16 l + 15 (one search per lane) ...
+            uint32_t* tk = skey + wave * 64 * kEmitPad + lane * kEmitPad;
+            uint32_t* tv = sval + wave * 64 * kEmitPad + lane * kEmitPad;
+            const uint32_t j0 = wbase + (uint32_t)lane * kEmitRounds;
+            if (j0 < bn) {
+                EmitWalk<true> wk;
+                wk.start(st, cnt, b0 + j0);
+                const uint32_t m = min((uint32_t)kEmitRounds, bn - j0);
+                for (uint32_t i = 0;;) {
+                    tk[i] = wk.key();
+                    tv[i] = wk.rec;
+                    if (++i == m) break;
+                    wk.next(st);
+                }
+            }
+            wave_lds_sync();
+            // ... and round r takes pairs 64 r .. 64 r + 63 of the wavefront
+#pragma unroll
+            for (int r = 0; r < kEmitRounds; ++r) {
+                const uint32_t p = (uint32_t)r * 64u + (uint32_t)lane;
+                const uint32_t at = (uint32_t)wave * 64u * kEmitPad + (p / kEmitRounds) * kEmitPad + p % kEmitRounds;
+                key[r] = skey[at];
+                val[r] = sval[at];
+            }
+        }
+        // (the staging below reuses skey and sval after the barrier that follows the ranking)
+#pragma unroll
+        for (int r = 0; r < kEmitRounds; ++r) {
+            rank[r] = 0u;
+            if (wbase + (uint32_t)r * 64u >= bn) continue;   // uniform over the wavefront
+            const uint32_t j = wbase + (uint32_t)r * 64u + (uint32_t)lane;
+            const bool valid = j < bn;
+            const uint32_t d = key[r] & mask;
+            const uint64_t peers = digit_peers(d, valid);
+            const uint32_t below = (uint32_t)rank_below(peers);
+            const uint32_t before = wcount[wave][d];
+            rank[r] = before + below;
+            wave_lds_sync();
+            if (valid && below == 0) wcount[wave][d] = before + (uint32_t)__popcll(peers);
+            wave_lds_sync();
+        }
+        __syncthreads();
+        uint32_t run = 0;   // this batch's items of digit threadIdx.x
+        {
+            const int d = threadIdx.x;
+#pragma unroll
+            for (int w = 0; w < kSortWaves; ++w) {
+                const uint32_t c = wcount[w][d];
+                wcount[w][d] = run;
+                run += c;
+            }
+            uint32_t tot;
+            dstart[d] = block_exclusive_scan_256(run, scan_tmp, &tot);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kEmitRounds; ++r) {
+            const uint32_t j = wbase + (uint32_t)r * 64u + (uint32_t)lane;
+            if (j < bn) {
+                const uint32_t d = key[r] & mask;
+                const uint32_t pos = dstart[d] + wcount[wave][d] + rank[r];
+                skey[pos] = key[r];
+                sval[pos] = val[r];
+            }
+        }
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < bn; j += kSortThreads) {
+            const uint32_t k = skey[j];
+            const uint32_t d = k & mask;
+            const uint32_t dst = gbase[d] + (j - dstart[d]);
+            if (dst < K) {   // the pair count the buffers were sized by
+                keys_out[dst] = k;
+                vals_out[dst] = sval[j];
+            }
+        }
+        __syncthreads();
+        gbase[threadIdx.x] += run;
     }
 }
 
@@ -428,18 +640,42 @@ __global__ void k_export_keys(const uint32_t* __restrict__ tile_keys, const uint
     if (vals_out) vals_out[i] = rec.gid;
 }
 
-void launch_gather_tile_counts(const uint32_t* sorted_rec, const uint4* tile_rect, uint32_t n, uint32_t* counts,
-                               uint4* sorted_rect, hipStream_t s, const uint32_t* n_dev) {
-    if (!n) return;
-    hipLaunchKernelGGL(k_gather_tile_counts, dim3((n + 255) / 256), dim3(256), 0, s, sorted_rec, tile_rect, n,
-                       n_dev, counts, sorted_rect);
+size_t emit_sort_scratch_bytes(size_t n_rec, size_t K) {
+    const size_t chunks = std::max<size_t>(1, div_up(n_rec, kEmitRecs));
+    return std::max(radix_scratch_bytes(K), align256(chunks * kRadix * sizeof(uint32_t)) +
+                                                scan_scratch_bytes(chunks * kRadix));
 }
 
-void launch_emit_pairs(const uint32_t* sorted_rec, const uint4* sorted_rect, const uint32_t* pair_off, uint32_t n,
-                       uint32_t K, uint32_t* keys, uint32_t* vals, hipStream_t s, const uint32_t* counts_dev) {
-    if (!n || !K) return;
-    hipLaunchKernelGGL(k_emit_pairs, dim3((n + kEmitThreads - 1) / kEmitThreads), dim3(kEmitThreads), 0, s,
-                       sorted_rec, sorted_rect, pair_off, n, K, counts_dev, keys, vals);
+void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint4* tile_rect, uint4* sorted_rect, size_t n_rec,
+                           const uint32_t* n_rec_dev, uint32_t* keys, uint32_t* vals, size_t K,
+                           const uint32_t* K_dev, int bits, void* scratch, hipStream_t s) {
+    if (n_rec == 0 || K == 0) return;
+    hipLaunchKernelGGL(k_gather_rects, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, sorted_rec, tile_rect,
+                       (uint32_t)n_rec, n_rec_dev, sorted_rect);
+    const PassPlan pl = plan_passes(bits);
+    const size_t chunks = div_up(n_rec, kEmitRecs);
+    uint8_t* p = (uint8_t*)scratch;
+    uint32_t* counts = (uint32_t*)p;
+    p += align256(chunks * kRadix * sizeof(uint32_t));
+    hipLaunchKernelGGL(k_emit_upsweep, dim3((unsigned)chunks), dim3(kSortThreads), 0, s, (const uint4*)sorted_rect,
+                       (uint32_t)n_rec, n_rec_dev, pl.mask, (uint32_t)chunks, counts);
+    scan_exclusive_u32(counts, counts, chunks * ((size_t)pl.mask + 1), nullptr, p, s, nullptr);
+    hipLaunchKernelGGL(k_emit_downsweep, dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rec,
+                       (const uint4*)sorted_rect, (uint32_t)n_rec, n_rec_dev, pl.mask, (uint32_t)chunks,
+                       (const uint32_t*)counts, (uint32_t)K, K_dev, keys, vals);
+}
+
+int sort_pairs_rest(uint32_t* keys[2], uint32_t* vals[2], size_t K, const uint32_t* K_dev, int bits, void* scratch,
+                    hipStream_t s) {
+    int cur = 0;
+    if (K == 0) return cur;
+    const PassPlan pl = plan_passes(bits);
+    for (int pass = 1; pass < pl.passes; ++pass) {
+        radix_pass(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], K, K_dev, pl.dbits * pass, pl.mask, scratch,
+                   s);
+        cur ^= 1;
+    }
+    return cur;
 }
 
 void launch_ranges(const uint32_t* keys, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s,

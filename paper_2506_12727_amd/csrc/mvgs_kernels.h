@@ -73,14 +73,18 @@ void fill_u32_count(uint32_t* p, size_t n, const uint32_t* n_dev, uint32_t per, 
 void launch_capacity_clamp(const uint64_t* totals, uint64_t cap_v, uint64_t cap_k, uint32_t* eff, uint32_t* overflow,
                            hipStream_t s);
 
-// Pair emission in depth order: count per sorted record, then (global tile, record) pairs.
-// Pair counts of the records in depth order, and their tile rectangles gathered into that order.
-void launch_gather_tile_counts(const uint32_t* sorted_rec, const uint4* tile_rect, uint32_t n, uint32_t* counts,
-                               uint4* sorted_rect, hipStream_t s, const uint32_t* n_dev = nullptr);
-// counts_dev: null, or device (records, pairs) actually present when n and K are bounds
-void launch_emit_pairs(const uint32_t* sorted_rec, const uint4* sorted_rect, const uint32_t* pair_off, uint32_t n,
-                       uint32_t K, uint32_t* keys, uint32_t* vals, hipStream_t s,
-                       const uint32_t* counts_dev = nullptr);
+// Pairs of the depth-ordered records and their stable sort by global tile id (of `bits` bits):
+// the first pass gathers the records' tile rectangles into depth order (sorted_rect, [n_rec]) and
+// emits every (global tile, record) pair straight into its place after the first radix pass
+// (keys, vals: [K]); sort_pairs_rest runs the remaining passes from buffers 0 and returns the
+// index of the buffer holding the sorted pairs. n_rec and K are bounds when n_rec_dev / K_dev
+// (device) give the counts.
+size_t emit_sort_scratch_bytes(size_t n_rec, size_t K);
+void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint4* tile_rect, uint4* sorted_rect, size_t n_rec,
+                           const uint32_t* n_rec_dev, uint32_t* keys, uint32_t* vals, size_t K,
+                           const uint32_t* K_dev, int bits, void* scratch, hipStream_t s);
+int sort_pairs_rest(uint32_t* keys[2], uint32_t* vals[2], size_t K, const uint32_t* K_dev, int bits, void* scratch,
+                    hipStream_t s);
 void launch_ranges(const uint32_t* keys, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s,
                    const uint32_t* K_dev = nullptr);
 void launch_export_keys(const uint32_t* tile_keys, const uint32_t* vals, const BlendRec* recs,
