@@ -151,6 +151,42 @@ def test_statistics_accumulate_across_calls():
     r.release(fr)
 
 
+def test_backward_reuses_cleared_accumulators():
+    """Repeated backwards on one context (the per-record accumulators reused), a larger batch
+    (the buffer grows) and a smaller one afterwards all equal the same backward on a fresh
+    context."""
+    needs_gpu()
+    sc = scenes.make_scene(8000, 3, log_scale_mean=-3.2)
+    small = scenes.make_cameras([(61, 47), (130, 70)], seed=5)
+    big = scenes.make_cameras([(61, 47), (130, 70), (160, 96), (96, 128)], seed=6)
+    g = GaussianTensors.from_scene(sc)
+    r = Rasterizer()
+
+    def grads_of(rast, cams, seed):
+        imgs, fr = rast.forward(g, cams)
+        dl = [torch.from_numpy(np.random.default_rng(seed + v).standard_normal((3, c.height, c.width))
+                               .astype(np.float32)).cuda() for v, c in enumerate(cams)]
+        dz = dict(e1=torch.zeros(g.P, device="cuda"), e2=torch.zeros(g.P, device="cuda"),
+                  count=torch.zeros(g.P, dtype=torch.int32, device="cuda"))
+        out = rast.backward(g, fr, dl, densify=dz)
+        torch.cuda.synchronize()
+        rast.release(fr)
+        return {k: v.clone() for k, v in out.items()}, dz
+
+    for cams, seed in ((small, 1), (small, 2), (big, 3), (big, 4), (small, 5)):
+        got, dz = grads_of(r, cams, seed)
+        fresh = Rasterizer()
+        ref, dz_ref = grads_of(fresh, cams, seed)
+        fresh.close()
+        for n in ref:
+            compare_grad(n, got[n].cpu().numpy(), ref[n].cpu().numpy().astype(np.float64), rtol=1e-4, inf=1e-5,
+                         l2=1e-4)
+        assert torch.equal(dz["count"], dz_ref["count"])
+        compare_grad("e1", dz["e1"].cpu().numpy(), dz_ref["e1"].cpu().numpy().astype(np.float64), rtol=1e-4,
+                     inf=1e-5, l2=1e-4)
+    r.close()
+
+
 def test_batch_invariance_and_rerun_determinism():
     """A view rendered alone equals the same view rendered inside a batch, bit for bit, and two
     runs of the same batch give identical images and binning."""
