@@ -390,8 +390,9 @@ def train_bench(args, tile, ppl):
     """Training iterations (forward, fused loss, backward with the densification statistics, one
     Adam step) on the 300K-Gaussian SH-3 scene with a pool of 16 views of 1600x1064, as in the
     paper's training-time comparison: one view per iteration, four whole views, and four views
-    sharing one image plane by thread-efficient partial rendering. 0.8 L1 + 0.2 D-SSIM (the 3D
-    distance-aware D-SSIM for the partial batches); targets are renders of a second draw."""
+    sharing one image plane by thread-efficient partial rendering, each also as one HIP-graph
+    replay per iteration (Adam included). 0.8 L1 + 0.2 D-SSIM (the 3D distance-aware D-SSIM for
+    the partial batches); targets are renders of a second draw."""
     import torch
 
     from paper_2506_12727_amd import scenes
@@ -403,9 +404,13 @@ def train_bench(args, tile, ppl):
     gt = GaussianTensors.from_scene(scenes.make_scene(wl.P, wl.sh_degree, seed=7))
     out = {"scene": "300K Gaussians, SH 3", "views": 16, "size": [1600, 1064], "steps": args.train_steps,
            "loss": {"w_l1": 0.8, "w_dssim": 0.2}}
-    for name, B, partial in (("single_view", 1, False), ("multi_view", 4, False), ("partial", 4, True)):
+    modes = (("single_view", 1, False, False), ("multi_view", 4, False, False), ("partial", 4, True, False),
+             ("single_view_captured", 1, False, True), ("multi_view_captured", 4, False, True),
+             ("partial_captured", 4, True, True))
+    for name, B, partial, captured in modes:
         g = GaussianTensors.from_scene(wl.scene())
-        t = Trainer(g, gt, cams, views_per_step=B, partial=partial, densify_every=0, tile=tile, ppl=ppl, seed=44)
+        t = Trainer(g, gt, cams, views_per_step=B, partial=partial, densify_every=0, tile=tile, ppl=ppl, seed=44,
+                    captured=captured)
         for _ in range(3):
             t.step()
         torch.cuda.synchronize()
@@ -415,11 +420,32 @@ def train_bench(args, tile, ppl):
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t0) / args.train_steps
         out[name] = {"views_per_step": B, "ms_per_step": ms, "views_per_s": 1e3 * B / ms,
-                     "last_loss": float(loss.item())}
+                     "last_loss": float(loss.item()), "graph": captured}
         t.close()
         del t, g
     out["partial_over_single_time"] = out["partial"]["ms_per_step"] / out["single_view"]["ms_per_step"]
     out["multi_over_single_time"] = out["multi_view"]["ms_per_step"] / out["single_view"]["ms_per_step"]
+    # a small scene, where launches rather than kernels bound an eager iteration: the small
+    # workload's 16,384 Gaussians (SH 0) against a second draw, a pool of 16 views of 128x128
+    sm = scenes.WORKLOADS["small_16k_4x128"]
+    cams_s = scenes.make_cameras([(128, 128)] * 16, seed=43)
+    gt_s = GaussianTensors.from_scene(scenes.make_scene(sm.P, sm.sh_degree, seed=8))
+    small = {"scene": "16K Gaussians, SH 0", "views": 16, "size": [128, 128], "views_per_step": 4}
+    for name, captured in (("eager", False), ("captured", True)):
+        g = GaussianTensors.from_scene(sm.scene())
+        t = Trainer(g, gt_s, cams_s, views_per_step=4, densify_every=0, tile=(16, 16), seed=45, captured=captured)
+        for _ in range(3):
+            t.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.train_steps):
+            t.step()
+        torch.cuda.synchronize()
+        small[name] = 1e3 * (time.perf_counter() - t0) / args.train_steps
+        t.close()
+        del t, g
+    small["captured_speedup"] = small["eager"] / small["captured"]
+    out["small_scene_ms_per_step"] = small
     return out
 
 
@@ -438,8 +464,10 @@ def serve_bench(args, g, tile, ppl):
     n = args.serve_warmup + args.serve_requests
     arr, cams = scenes.make_requests(n, rate_hz=args.serve_rate)
     budget = int(args.serve_budget_gib * (1 << 30))
+    # pixels per lane chosen per batch by the library: requests range from one 256x256 view to
+    # batches of 1920x1080 views
     srv = Server(g, n_slots=args.serve_slots, budget_bytes=budget, max_batch=args.serve_batch, tile=tile,
-                 pixels_per_lane=ppl)
+                 pixels_per_lane=0)
     try:
         st = srv.run(arr, cams, measure_from=args.serve_warmup)
         n_sat = min(n, 600)
@@ -453,6 +481,7 @@ def serve_bench(args, g, tile, ppl):
            "mean_batch": st["mean_batch"], "slot_overlap": st["overlap"],
            "peak_budget_gib": st["peak_budget_bytes"] / (1 << 30), "budget_gib": args.serve_budget_gib,
            "refused_batches": st["refused_batches"], "slots": args.serve_slots, "max_batch": args.serve_batch,
+           "tile": list(tile), "pixels_per_lane": "per batch",
            "saturated": {"requests": sat["requests"], "views_per_s": sat["views_per_s"],
                          "pixels_per_s": sat["pixels_per_s"], "mean_batch": sat["mean_batch"],
                          "slot_overlap": sat["overlap"]},

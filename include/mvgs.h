@@ -98,7 +98,9 @@ typedef struct {
 
 /* Context options. tile_w, tile_h in {8, 16, 32} (0 selects 16). pixels_per_lane in {1, 2, 4}:
  * each lane of a blend wavefront owns that many pixels of its 8x8, 8x16 or 16x16 sub-tile; 2
- * needs tile_h >= 16, 4 needs tile_w and tile_h >= 16; 0 selects the largest the tile allows.
+ * needs tile_h >= 16, 4 needs tile_w and tile_h >= 16; 0 lets each forward choose: the largest
+ * the tile allows that still launches 4096 blend wavefronts (small frames take fewer pixels per
+ * lane and more wavefronts), the backward on its frame following it.
  * Results do not depend on these choices.
  * workspace_limit: 0 for none, else the most device bytes the context may hold (workspace,
  * upload staging and all its frames, as mvgs_memory_held counts them). A call that would grow
@@ -263,11 +265,19 @@ int mvgs_adapt_density(mvgs_context* ctx, void* stream, const mvgs_gaussians* g,
  * (statistics pointers unused). moments: device float [P, 11 + 3K, 2] (m, v interleaved; per
  * Gaussian the elements of means, scales, quats, opacity, SH in that order), zero before the
  * first step. The SH learning rate is lr_sh_dc for the first coefficient, lr_sh_rest for the
- * others. Launches one kernel, no synchronization (may be captured). */
+ * others. Launches one kernel, no synchronization (may be captured).
+ * step_dev: NULL, or a device int32 step counter. Then t is read on the device: the call adds 1 to
+ * *step_dev and takes the new value as t (prm->step is not used), so that a step captured into a
+ * graph counts its own replays; one more small kernel runs first. skip_dev: NULL, or a device word
+ * (with step_dev only): when it is non-zero at run time the call changes nothing, counter
+ * included; pass the frame's void word (mvgs_frame_void_word) so that a captured training step
+ * whose forward overflowed its capacities leaves the parameters alone. */
 typedef struct {
     float lr_means, lr_scales, lr_quats, lr_opacities, lr_sh_dc, lr_sh_rest;
     float beta1, beta2, eps;
     int32_t step;
+    int32_t* step_dev;
+    const uint32_t* skip_dev;
 } mvgs_adam_params;
 
 int mvgs_adam_step(mvgs_context* ctx, void* stream, int64_t P, int32_t sh_degree, const mvgs_gaussians_out* params,
@@ -318,6 +328,12 @@ int mvgs_frame_release(mvgs_context* ctx, mvgs_frame* frame);
  * Synchronizes the stream; not capturable. Returns MVGS_OK at once for frames not made in
  * capacity mode. */
 int mvgs_frame_check(mvgs_context* ctx, void* stream, mvgs_frame* frame);
+
+/* Capacity mode: the device word (owned by the frame, valid while it is held) that is non-zero
+ * once the frame's forward has run if the frame is void, for device-side decisions such as
+ * mvgs_adam_params.skip_dev. *word = NULL for frames not made in capacity mode (their errors are
+ * returned by the forward itself). */
+int mvgs_frame_void_word(const mvgs_frame* frame, const uint32_t** word);
 
 /* For a frame made by a forward captured into a graph: replace its cameras (same count and image
  * sizes; poses, intrinsics and background may change). Host-only: it rewrites the staging memory

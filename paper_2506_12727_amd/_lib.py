@@ -25,7 +25,8 @@ EXPORTED = ["mvgs_create", "mvgs_destroy", "mvgs_forward", "mvgs_loss", "mvgs_ba
             "mvgs_stage_name", "mvgs_frame_work", "mvgs_set_workspace_limit", "mvgs_memory_held",
             "mvgs_frame_workspace", "mvgs_forward_partial", "mvgs_subsample", "mvgs_frame_check",
             "mvgs_frame_set_cameras", "mvgs_loss_3d", "mvgs_export_depth", "mvgs_adapt_density",
-            "mvgs_adam_step", "mvgs_gather_rows", "mvgs_grad_moments", "mvgs_frame_merge"]
+            "mvgs_adam_step", "mvgs_gather_rows", "mvgs_grad_moments", "mvgs_frame_merge",
+            "mvgs_frame_void_word"]
 MVGS_PARTIAL_COMPACT = 0
 MVGS_PARTIAL_MASKED = 1
 MVGS_STAGE_COUNT = 10
@@ -70,7 +71,8 @@ class mvgs_gaussians_out(C.Structure):
 class mvgs_adam_params(C.Structure):
     _fields_ = [("lr_means", C.c_float), ("lr_scales", C.c_float), ("lr_quats", C.c_float),
                 ("lr_opacities", C.c_float), ("lr_sh_dc", C.c_float), ("lr_sh_rest", C.c_float),
-                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("step", C.c_int32)]
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("step", C.c_int32),
+                ("step_dev", C.c_void_p), ("skip_dev", C.c_void_p)]
 
 
 class MvgsError(RuntimeError):
@@ -150,6 +152,8 @@ def lib():
     L.mvgs_adam_step.argtypes = [vp, vp, i64, C.c_int32, C.POINTER(mvgs_gaussians_out), C.POINTER(mvgs_grads), vp,
                                  C.POINTER(mvgs_adam_params)]
     L.mvgs_adam_step.restype = C.c_int
+    L.mvgs_frame_void_word.argtypes = [vp, C.POINTER(vp)]
+    L.mvgs_frame_void_word.restype = C.c_int
     L.mvgs_gather_rows.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     L.mvgs_gather_rows.restype = C.c_int
     L.mvgs_grad_moments.argtypes = [vp, vp, i64, C.c_int32, C.POINTER(mvgs_grads), vp, vp]

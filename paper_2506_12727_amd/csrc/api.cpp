@@ -183,6 +183,7 @@ struct mvgs_frame {
     uint32_t n_tiles = 0, n_pixels = 0;
     int64_t P = 0;
     int sh_degree = 0;
+    int ppl = 1;   // pixels per lane of the full-tile blend kernels (the backward uses the forward's)
     uint32_t V = 0;
     uint64_t K = 0;
     int final_buf = 0;
@@ -214,10 +215,12 @@ struct mvgs_frame {
 struct mvgs_context {
     int device = 0;
     int tw = 16, th = 16, ppl = 2;
+    bool ppl_auto = false;   // pixels per lane chosen per frame (blend_auto_ppl)
     std::string err;
     std::vector<mvgs_frame*> frames;
     DevBuf nrec, ntiles, totals, scan_scratch, depth_key[2], rec_vals[2], tile_rect, sorted_rect;
     DevBuf sort_scratch, acc, loss_scratch, ssim_maps, loss3d_scratch, adc_n, adc_off, adc_act, moment_partials;
+    DevBuf adam_state;   // 3 words of a device-counted Adam step (allocated with the first device use)
     size_t limit = 0;  // 0: no workspace limit
     uint64_t cap_v = 0, cap_k = 0;  // capacity mode when non-zero
     bool capturing = false;         // the current call's stream is being captured into a graph
@@ -242,7 +245,7 @@ struct mvgs_context {
         DevBuf* bufs[] = {&nrec, &ntiles, &totals, &scan_scratch, &depth_key[0], &depth_key[1], &rec_vals[0],
                           &rec_vals[1], &tile_rect, &sorted_rect, &sort_scratch, &acc,
                           &loss_scratch, &ssim_maps, &loss3d_scratch, &adc_n, &adc_off, &adc_act,
-                          &moment_partials, &work};
+                          &moment_partials, &work, &adam_state};
         for (DevBuf* b : bufs) fn(*b);
         for (auto& sl : ring.slots) fn(sl.dev);
         for (mvgs_frame* f : frames) f->each_buffer(fn);
@@ -289,6 +292,8 @@ struct mvgs_context {
         hipError_t e = hipGetDevice(&device);
         if (e != hipSuccess) return e;
         e = hipHostMalloc((void**)&pinned_totals, 8 * sizeof(uint64_t), hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        e = ensure(adam_state, 256);
         if (e != hipSuccess) return e;
         device_used = true;
         return hipSuccess;
@@ -483,6 +488,7 @@ int mvgs_create(mvgs_context** out, const mvgs_options* opt) {
     if (limit < 0 || cap_v < 0 || cap_k < 0 || (cap_v == 0) != (cap_k == 0) || cap_v >= (1ll << 32) ||
         cap_k >= (1ll << 32))
         return MVGS_EINVAL;
+    const bool ppl_auto = ppl == 0;
     if (ppl == 0) ppl = blend_default_ppl(tw, th);
     if (!blend_supported(tw, th, ppl)) return MVGS_EINVAL;
     mvgs_context* ctx = new (std::nothrow) mvgs_context();
@@ -490,6 +496,7 @@ int mvgs_create(mvgs_context** out, const mvgs_options* opt) {
     ctx->tw = tw;
     ctx->th = th;
     ctx->ppl = ppl;
+    ctx->ppl_auto = ppl_auto;
     ctx->limit = (size_t)limit;
     ctx->cap_v = (uint64_t)cap_v;
     ctx->cap_k = (uint64_t)cap_k;
@@ -804,7 +811,8 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
         sa.images = a.images;
         launch_blend_fwd_sel(sa, s);
     } else {
-        launch_blend_fwd(a, tw, th, ctx->ppl, s);
+        f->ppl = ctx->ppl_auto ? blend_auto_ppl(tw, th, n_tiles) : ctx->ppl;
+        launch_blend_fwd(a, tw, th, f->ppl, s);
     }
     ctx->stage_end(mk, s);
     FCHK(hipGetLastError());
@@ -966,16 +974,17 @@ int mvgs_adam_step(mvgs_context* ctx, void* stream, int64_t P, int32_t sh_degree
     if (P > 0 && (!params->means || !params->scales || !params->quats || !params->opacities || !params->sh ||
                   !moments))
         return ctx->fail(MVGS_EINVAL, "a parameter or moment pointer is NULL");
-    if (prm->step < 1) return ctx->fail(MVGS_EINVAL, "step=%d must be >= 1", prm->step);
+    if (!prm->step_dev && prm->step < 1) return ctx->fail(MVGS_EINVAL, "step=%d must be >= 1", prm->step);
+    if (prm->skip_dev && !prm->step_dev) return ctx->fail(MVGS_EINVAL, "skip_dev needs step_dev");
     if (!(prm->beta1 >= 0.0f && prm->beta1 < 1.0f && prm->beta2 >= 0.0f && prm->beta2 < 1.0f && prm->eps >= 0.0f))
         return ctx->fail(MVGS_EINVAL, "betas must lie in [0, 1) and eps >= 0");
     const float lrs[6] = {prm->lr_means, prm->lr_scales, prm->lr_quats, prm->lr_opacities, prm->lr_sh_dc,
                           prm->lr_sh_rest};
     for (float l : lrs)
         if (!std::isfinite(l)) return ctx->fail(MVGS_EINVAL, "learning rates must be finite");
+    const int32_t t = prm->step_dev ? 1 : prm->step;   // (counted on the device: checked for t = 1)
     AdamArgs a{lrs[0], lrs[1], lrs[2], lrs[3], lrs[4], lrs[5], prm->beta1, prm->beta2, prm->eps,
-               (float)(1.0 - std::pow((double)prm->beta1, prm->step)),
-               (float)(1.0 - std::pow((double)prm->beta2, prm->step))};
+               (float)(1.0 - std::pow((double)prm->beta1, t)), (float)(1.0 - std::pow((double)prm->beta2, t))};
     if (!(a.bc1 > 0.0f) || !(a.bc2 > 0.0f)) return ctx->fail(MVGS_EINVAL, "a bias correction is zero");
     GradArgs gr{};
     gr.means = grads->means;
@@ -984,8 +993,13 @@ int mvgs_adam_step(mvgs_context* ctx, void* stream, int64_t P, int32_t sh_degree
     gr.opac = grads->opacities;
     gr.sh = grads->sh;
     HIPCHK(ctx, ctx->bind_device());
+    float* state = nullptr;
+    if (prm->step_dev) {
+        state = as<float>(ctx->adam_state);
+        launch_adam_count(prm->step_dev, prm->skip_dev, prm->beta1, prm->beta2, state, (hipStream_t)stream);
+    }
     launch_adam(params->means, params->scales, params->quats, params->opacities, params->sh, gr, moments, P, sh_degree,
-                a, (hipStream_t)stream);
+                a, (hipStream_t)stream, state);
     LAUNCHCHK(ctx, "adam step");
     return MVGS_OK;
 }
@@ -1122,7 +1136,7 @@ int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, cons
         sa.want_e1 = a.want_e1;
         launch_blend_bwd_sel(sa, s);
     } else {
-        launch_blend_bwd(a, ctx->tw, ctx->th, ctx->ppl, s);
+        launch_blend_bwd(a, ctx->tw, ctx->th, f->ppl, s);
     }
     ctx->stage_end(mk, s);
     GradArgs gr;
@@ -1205,6 +1219,12 @@ int mvgs_frame_check(mvgs_context* ctx, void* stream, mvgs_frame* frame) {
     frame->V = (uint32_t)V;
     frame->K = (uint32_t)K;
     frame->checked = true;
+    return MVGS_OK;
+}
+
+int mvgs_frame_void_word(const mvgs_frame* frame, const uint32_t** word) {
+    if (!frame || !word || !frame->in_use) return MVGS_EINVAL;
+    *word = frame_void(frame);
     return MVGS_OK;
 }
 

@@ -18,7 +18,13 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ means, float* 
                                               float* __restrict__ sh, const float* __restrict__ g_means,
                                               const float* __restrict__ g_scales, const float* __restrict__ g_quats,
                                               const float* __restrict__ g_opac, const float* __restrict__ g_sh,
-                                              float2* __restrict__ mom, int64_t P, int K, AdamArgs a) {
+                                              float2* __restrict__ mom, int64_t P, int K, AdamArgs a,
+                                              const float* __restrict__ state) {
+    if (state) {   // counted on the device
+        if (state[0] != 0.0f) return;
+        a.bc1 = state[1];
+        a.bc2 = state[2];
+    }
     const Idx D = (Idx)(11 + 3 * K);
     const Idx i = (Idx)blockIdx.x * 256u + (Idx)threadIdx.x;
     if ((int64_t)i >= P * (int64_t)D) return;
@@ -132,18 +138,35 @@ __global__ void __launch_bounds__(256) k_grad_moments_final(const double* __rest
     }
 }
 
+// The step counter of a replayed (graph-captured) Adam step: t = ++*step unless *skip, and the
+// bias corrections 1 - beta^t rounded from double, as the host computes them for a given step.
+__global__ void k_adam_count(int32_t* __restrict__ step, const uint32_t* __restrict__ skip, float beta1, float beta2,
+                             float* __restrict__ state) {
+    const bool sk = skip && *skip;
+    state[0] = sk ? 1.0f : 0.0f;
+    if (sk) return;
+    const int32_t t = *step + 1;
+    *step = t;
+    state[1] = (float)(1.0 - pow((double)beta1, (double)t));
+    state[2] = (float)(1.0 - pow((double)beta2, (double)t));
+}
+
+void launch_adam_count(int32_t* step, const uint32_t* skip, float beta1, float beta2, float* state, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam_count, dim3(1), dim3(1), 0, s, step, skip, beta1, beta2, state);
+}
+
 void launch_adam(float* means, float* scales, float* quats, float* opac, float* sh, const GradArgs& gr, float* mom,
-                 int64_t P, int sh_degree, const AdamArgs& a, hipStream_t s) {
+                 int64_t P, int sh_degree, const AdamArgs& a, hipStream_t s, const float* state) {
     const int K = (sh_degree + 1) * (sh_degree + 1);
     const int64_t n = P * (11 + 3 * K);
     if (!n) return;
     const dim3 grid((unsigned)((n + 255) / 256));
     if (n <= (int64_t(1) << 32) - 256)   // no index of the grid wraps
         hipLaunchKernelGGL(k_adam<uint32_t>, grid, dim3(256), 0, s, means, scales, quats, opac, sh, gr.means,
-                           gr.scales, gr.quats, gr.opac, gr.sh, reinterpret_cast<float2*>(mom), P, K, a);
+                           gr.scales, gr.quats, gr.opac, gr.sh, reinterpret_cast<float2*>(mom), P, K, a, state);
     else
         hipLaunchKernelGGL(k_adam<uint64_t>, grid, dim3(256), 0, s, means, scales, quats, opac, sh, gr.means,
-                           gr.scales, gr.quats, gr.opac, gr.sh, reinterpret_cast<float2*>(mom), P, K, a);
+                           gr.scales, gr.quats, gr.opac, gr.sh, reinterpret_cast<float2*>(mom), P, K, a, state);
 }
 
 void launch_gather_rows(const int32_t* src, int64_t n, int64_t width, const float* in, float* out, hipStream_t s) {

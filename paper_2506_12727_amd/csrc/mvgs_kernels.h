@@ -120,6 +120,8 @@ struct BlendBwdArgs {
 };
 bool blend_supported(int tw, int th, int ppl);
 int blend_default_ppl(int tw, int th);
+// pixels per lane for a frame of n_tiles tiles when the context leaves the choice to the library
+int blend_auto_ppl(int tw, int th, uint32_t n_tiles);
 void launch_frame_work(const DevCam* cams, int B, const uint2* ranges, const uint32_t* vals, const BlendRec* recs,
                        const uint32_t* n_last, uint32_t n_pixels, int tw, int th, uint64_t* out, hipStream_t s);
 void launch_blend_fwd(const BlendFwdArgs& a, int tw, int th, int ppl, hipStream_t s);
@@ -184,8 +186,13 @@ struct AdamArgs {
     float beta1, beta2, eps;
     float bc1, bc2;   // bias corrections 1 - beta^step
 };
+// state (device, 3 words) null: the bias corrections of `a`; else the step reads them from the
+// state launch_adam_count wrote, and does nothing when its first word is set
 void launch_adam(float* means, float* scales, float* quats, float* opac, float* sh, const GradArgs& gr, float* mom,
-                 int64_t P, int sh_degree, const AdamArgs& a, hipStream_t s);
+                 int64_t P, int sh_degree, const AdamArgs& a, hipStream_t s, const float* state = nullptr);
+// device step counter: unless *skip, ++*step and the bias corrections for it into state[1..2];
+// state[0] = skip
+void launch_adam_count(int32_t* step, const uint32_t* skip, float beta1, float beta2, float* state, hipStream_t s);
 void launch_gather_rows(const int32_t* src, int64_t n, int64_t width, const float* in, float* out, hipStream_t s);
 // the five gradient tensors (means, scales, quats, opacities, SH) as one vector: x[k] holds
 // elements [end[k-1], end[k]) of it

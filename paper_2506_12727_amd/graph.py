@@ -13,6 +13,11 @@ one size) share one image plane by the per-position keys in `keys` (int32 [H*W];
 draws new ones into it first unless `fresh_keys=False`, then the caller writes them), the
 targets are merged into `target_plane` by the same selection, and the loss is L1 + the 3D
 distance-aware D-SSIM of Sec. 5.1.2 on the plane (`plane`, its gradient `dl_plane`).
+
+With `optimizer` = dict(moments, lr, step[, beta1, beta2, eps]) the step ends with the Adam update
+of the Gaussians, its step number counted on the device in `step` (int32 [1]), and skipped when
+the forward overflowed its capacities. The warm-up call that sizes the buffers is then a full
+training step too.
 """
 from __future__ import annotations
 
@@ -36,9 +41,29 @@ def measure_capacity(g: GaussianTensors, cams, tile=(16, 16), ppl=0, headroom: f
     return (max(1, int(math.ceil(info["records"] * headroom))), max(1, int(math.ceil(info["pairs"] * headroom))))
 
 
+def measure_capacity_pool(g: GaussianTensors, cams, views_per_batch: int, tile=(16, 16), ppl=0,
+                          headroom: float = 1.25):
+    """Capacities that hold any batch of `views_per_batch` views of the pool `cams`: the records
+    and pairs of each view rendered alone, the largest ones summed, times `headroom`."""
+    r = Rasterizer(tile, ppl)
+    recs, pairs = [], []
+    try:
+        for c in cams:
+            _, fr = r.forward(g, [c])
+            info = fr.info()
+            r.release(fr)
+            recs.append(info["records"])
+            pairs.append(info["pairs"])
+    finally:
+        r.close()
+    top = lambda xs: sum(sorted(xs, reverse=True)[:views_per_batch])
+    return (max(1, int(math.ceil(top(recs) * headroom))), max(1, int(math.ceil(top(pairs) * headroom))))
+
+
 class CapturedStep:
     def __init__(self, g: GaussianTensors, cams, targets, w_l1=1.0, w_dssim=0.0, tile=(16, 16), ppl=0,
-                 capacity=None, densify: Optional[dict] = None, partial: bool = False, fresh_keys: bool = True):
+                 capacity=None, densify: Optional[dict] = None, partial: bool = False, fresh_keys: bool = True,
+                 optimizer: Optional[dict] = None):
         g.check()
         self.g, self.cams = g, list(cams)
         self.w_l1, self.w_dssim = float(w_l1), float(w_dssim)
@@ -66,6 +91,11 @@ class CapturedStep:
                           quats=torch.empty_like(g.quats), opacities=torch.empty_like(g.opacities),
                           sh=torch.empty_like(g.sh))
         self.densify = densify
+        self.optimizer = optimizer
+        if optimizer is not None:
+            st = optimizer["step"]
+            if st.dtype != torch.int32 or st.numel() != 1 or not st.is_cuda:
+                raise ValueError("optimizer['step'] must be an int32 [1] tensor on the GPU")
         # one step outside the capture sizes every buffer; its frame returns to the pool
         fr = self._step()
         fr.check()
@@ -89,6 +119,10 @@ class CapturedStep:
             _, fr = r.forward(self.g, self.cams, images=self.images)
             r.loss(self.cams, self.images, self.targets, self.w_l1, self.w_dssim, out=self.loss, grads=self.dl)
         r.backward(self.g, fr, self.dl, densify=self.densify, grads=self.grads)
+        if self.optimizer is not None:
+            o = self.optimizer
+            r.adam_step(self.g, self.grads, o["moments"], 0, o["lr"], o.get("beta1", 0.9), o.get("beta2", 0.999),
+                        o.get("eps", 1e-15), step_dev=o["step"], skip=fr)
         return fr
 
     def replay(self):

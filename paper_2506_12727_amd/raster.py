@@ -76,6 +76,13 @@ class Frame:
         (MVGS_EINVAL). No-op otherwise."""
         L.check(L.lib().mvgs_frame_check(self.rast.ctx, _stream(), self.handle), self.rast.ctx)
 
+    def void_word(self) -> Optional[int]:
+        """Device address of the word that is non-zero when this capacity-mode frame is void
+        (None for other frames)."""
+        w = C.c_void_p()
+        L.check(L.lib().mvgs_frame_void_word(self.handle, C.byref(w)))
+        return w.value
+
     def set_cameras(self, cams):
         """For a frame made under graph capture: the cameras the next replay renders (same sizes)."""
         L.check(L.lib().mvgs_frame_set_cameras(self.rast.ctx, self.handle, L.camera_array(cams), len(cams)),
@@ -318,10 +325,14 @@ class Rasterizer:
         return gr
 
     def adam_step(self, g: GaussianTensors, grads: dict, moments: torch.Tensor, step: int, lr: dict,
-                  beta1=0.9, beta2=0.999, eps=1e-15):
+                  beta1=0.9, beta2=0.999, eps=1e-15, step_dev: Optional[torch.Tensor] = None,
+                  skip: Optional["Frame"] = None):
         """One in-place Adam step of the activated parameters g (log-scale and opacity-logit
         coordinates for scales and opacities); moments: float32 [P, 11 + 3K, 2], zero at first.
-        lr: dict(means, scales, quats, opacities, sh_dc, sh_rest)."""
+        lr: dict(means, scales, quats, opacities, sh_dc, sh_rest). With step_dev (int32 [1] on the
+        GPU) the step number is counted on the device (incremented, then used; `step` is not),
+        and with `skip` (a capacity-mode frame) nothing changes when that frame is void: the form
+        a captured training step takes."""
         g.check()
         K = (g.sh_degree + 1) ** 2
         _check_grads(g, grads)
@@ -332,6 +343,12 @@ class Rasterizer:
                                  g.sh.data_ptr())
         prm = L.mvgs_adam_params(lr["means"], lr["scales"], lr["quats"], lr["opacities"], lr["sh_dc"], lr["sh_rest"],
                                  beta1, beta2, eps, int(step))
+        if step_dev is not None:
+            if step_dev.dtype != torch.int32 or step_dev.numel() != 1 or not step_dev.is_cuda:
+                raise ValueError("step_dev: expected an int32 [1] tensor on the GPU")
+            prm.step_dev = step_dev.data_ptr()
+        if skip is not None:
+            prm.skip_dev = skip.void_word()
         L.check(self.lib.mvgs_adam_step(self.ctx, _stream(), g.P, g.sh_degree, C.byref(o),
                                         C.byref(self._grads(grads)), moments.data_ptr(), C.byref(prm)), self.ctx)
 

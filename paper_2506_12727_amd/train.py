@@ -12,6 +12,14 @@ its outputs and clears the statistics. Targets are renders of a ground-truth sce
 problem has a known optimum. Every step of it runs in the library's kernels; torch holds memory
 and draws the random numbers (view order, sub-sampling keys, split normals).
 
+With `captured=True` (views of one size) an iteration is one replay of a HIP graph holding the
+whole step, Adam included (step number counted on the device): the host only writes the batch's
+poses, gathers its targets and replays. The capacities hold any batch of the pool with
+`headroom`; the host waits for each replay (the pose staging the graph reads is host memory) and
+checks it, and a step that overflowed, which changed nothing, is captured again with larger
+capacities and rerun. Density control runs eagerly and the next iteration captures anew. Sub-
+sampling keys are then drawn inside the graph from torch's default generator.
+
 `variance_views` and `variance_partial` estimate the variance of mini-batch gradients over given
 mini-batches (Sec. 3.2): the mean squared norm of the mini-batch gradients minus the squared
 norm of their mean, accumulated on the GPU in double precision.
@@ -23,6 +31,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 import torch
 
+from . import _lib as L
+from .graph import CapturedStep, measure_capacity_pool
 from .raster import GaussianTensors, Rasterizer
 
 # the 3DGS learning rates (the position rate for a scene extent of about 2)
@@ -49,7 +59,8 @@ class Trainer:
     def __init__(self, g: GaussianTensors, gt: GaussianTensors, cams: Sequence, views_per_step: int = 4,
                  partial: bool = False, w_l1: float = 0.8, w_dssim: float = 0.2, lr: Optional[dict] = None,
                  densify: Optional[dict] = None, densify_from: int = 100, densify_until: int = 1000,
-                 densify_every: int = 100, tile=(16, 16), ppl: int = 0, seed: int = 0):
+                 densify_every: int = 100, tile=(16, 16), ppl: int = 0, seed: int = 0, captured: bool = False,
+                 headroom: float = 1.3):
         g.check()
         gt.check()
         self.g = g
@@ -79,6 +90,15 @@ class Trainer:
         self.grads = _zeros_like_grads(g)
         self.it = 0
         self.n_densified = 0
+        self.tile, self.ppl = tile, ppl
+        self.captured, self.headroom = bool(captured), float(headroom)
+        self.cstep: Optional[CapturedStep] = None
+        self.recaptures = 0
+        if self.captured:
+            if len({(c.width, c.height) for c in self.cams}) != 1:
+                raise ValueError("a captured step keeps its image sizes: the views must have one size")
+            self.target_stack = torch.stack(self.targets)
+            self.step_dev = torch.zeros(1, dtype=torch.int32, device=self.dev)
 
     def _next_views(self) -> List[int]:
         if len(self.order) < self.B:
@@ -86,10 +106,50 @@ class Trainer:
         views, self.order = self.order[:self.B], self.order[self.B:]
         return [int(v) for v in views]
 
+    def _capture(self, cams, idx, capacity=None):
+        """Captures the step for the current Gaussians; its warm-up call is this iteration."""
+        if capacity is None:
+            capacity = measure_capacity_pool(self.g, self.cams, self.B, self.tile, self.ppl, self.headroom)
+        self.batch_targets = torch.index_select(self.target_stack, 0, idx)
+        self.step_dev.fill_(self.it)
+        self.cstep = CapturedStep(self.g, cams, list(self.batch_targets.unbind(0)), self.w_l1, self.w_dssim,
+                                  tile=self.tile, ppl=self.ppl, capacity=capacity, densify=self.stats,
+                                  partial=self.partial,
+                                  optimizer=dict(moments=self.moments, lr=self.lr, step=self.step_dev))
+
+    def _captured_step(self, views) -> torch.Tensor:
+        cams = [self.cams[v] for v in views]
+        idx = torch.as_tensor(views, dtype=torch.int64, device=self.dev)
+        if self.cstep is None:
+            self._capture(cams, idx)
+            return self.cstep.loss
+        self.cstep.set_cameras(cams)
+        torch.index_select(self.target_stack, 0, idx, out=self.batch_targets)
+        self.cstep.replay()
+        try:
+            self.cstep.check()
+        except L.MvgsError as e:
+            if e.status != L.MVGS_ECAPACITY:
+                raise
+            # the replay changed nothing: capture again with room for this batch, and rerun
+            cap = tuple(int(x * 1.5) for x in self.cstep.rast.capacity)
+            self.cstep.close()
+            self.cstep = None
+            self.recaptures += 1
+            self._capture(cams, idx, capacity=cap)
+        return self.cstep.loss
+
     def step(self) -> torch.Tensor:
         """One iteration; returns the loss as a device scalar."""
         r, g = self.rast, self.g
         views = self._next_views()
+        if self.captured:
+            loss = self._captured_step(views)
+            self.it += 1
+            if (self.densify_from <= self.it < self.densify_until and self.densify_every > 0
+                    and self.it % self.densify_every == 0):
+                self.densify()
+            return loss
         cams = [self.cams[v] for v in views]
         if self.partial:
             W, H = cams[0].width, cams[0].height
@@ -114,6 +174,10 @@ class Trainer:
 
     def densify(self):
         """Multi-view adaptive density control now, from the statistics gathered since the last."""
+        if self.cstep is not None:   # the captured step holds the old Gaussians
+            torch.cuda.synchronize()
+            self.cstep.close()
+            self.cstep = None
         g = self.g
         normals = torch.randn((g.P, 2, 3), device=self.dev, generator=self.gen)
         adc = dict(self.adc)
@@ -129,6 +193,9 @@ class Trainer:
         return [float(self.step().item()) for _ in range(n)]
 
     def close(self):
+        if self.cstep is not None:
+            self.cstep.close()
+            self.cstep = None
         self.rast.close()
 
 

@@ -57,6 +57,49 @@ def test_adam_matches_oracle():
     r.close()
 
 
+def test_adam_counted_on_the_device():
+    """Adam with its step number counted on the device equals the host-counted step, and a void
+    capacity-mode frame as skip word leaves parameters, moments and counter alone."""
+    needs_gpu()
+    P, deg = 700, 2
+    K = (deg + 1) ** 2
+    sc = scenes.make_scene(P, deg, seed=23, log_scale_mean=-3.0)
+    ga, gb = GaussianTensors.from_scene(sc), GaussianTensors.from_scene(sc)
+    ma = torch.zeros((P, 11 + 3 * K, 2), device="cuda")
+    mb = torch.zeros_like(ma)
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    rng = np.random.default_rng(24)
+    r = Rasterizer()
+    for t in (1, 2, 3, 4):
+        gr = dict(means=rng.normal(size=(P, 3)), scales=rng.normal(size=(P, 3)), quats=rng.normal(size=(P, 4)),
+                  opacities=rng.normal(size=P), sh=rng.normal(size=(P, K, 3)))
+        gr = {k: cuda(v.astype(np.float32)) for k, v in gr.items()}
+        r.adam_step(ga, gr, ma, t, LR)
+        r.adam_step(gb, gr, mb, 0, LR, step_dev=step)
+    torch.cuda.synchronize()
+    assert int(step.item()) == 4
+    for name in ("means", "scales", "quats", "opacities", "sh"):
+        a, b = getattr(ga, name), getattr(gb, name)
+        assert torch.allclose(a, b, rtol=1e-6, atol=1e-7), name
+    assert torch.allclose(ma, mb, rtol=1e-6, atol=1e-9)
+    # a void frame: records over a tiny capacity
+    cams = scenes.make_cameras([(64, 48)], seed=3)
+    small = Rasterizer(capacity=(1, 1))
+    _, fr = small.forward(ga, cams)
+    with pytest.raises(L.MvgsError):
+        fr.check()
+    before = {n: getattr(gb, n).clone() for n in ("means", "scales", "quats", "opacities", "sh")}
+    mb0 = mb.clone()
+    r.adam_step(gb, gr, mb, 0, LR, step_dev=step, skip=fr)
+    torch.cuda.synchronize()
+    assert int(step.item()) == 4 and torch.equal(mb, mb0)
+    for n, v in before.items():
+        assert torch.equal(getattr(gb, n), v), n
+    small.release(fr)
+    small.close()
+    r.close()
+
+
 def test_gather_rows_and_moments():
     needs_gpu()
     rng = np.random.default_rng(23)
@@ -194,3 +237,40 @@ def test_training_lowers_the_loss_and_densifies(partial):
         assert bool(torch.isfinite(getattr(t.g, name)).all()), name
     assert np.mean(losses[-10:]) < 0.8 * np.mean(losses[:10]), (losses[:10], losses[-10:])
     t.close()
+
+
+@pytest.mark.parametrize("partial", [False, True])
+def test_captured_training_matches_eager(partial):
+    """The training loop as one graph replay per iteration (Adam counted on the device, density
+    control between captures) follows the eager loop: the same first loss, losses that stay close
+    (float atomics make the runs drift apart slowly) and the same density control decisions on
+    the first round; it lowers the loss like the eager loop."""
+    needs_gpu()
+    lr = dict(means=1e-3, scales=5e-3, quats=1e-3, opacities=2e-2, sh_dc=1e-2, sh_rest=2e-3)
+    runs = {}
+    for captured in (False, True):
+        g, gt, cams = _problem()
+        t = Trainer(g, gt, cams, views_per_step=4, partial=partial, lr=lr, w_l1=0.8, w_dssim=0.2,
+                    densify=dict(split_threshold=1e-7, clone_threshold=1e-7), densify_from=20, densify_until=41,
+                    densify_every=20, seed=5, captured=captured)
+        P0 = t.g.P
+        losses = t.run(60)
+        runs[captured] = (losses, t.g.P, t.n_densified, P0)
+        for name in ("means", "scales", "quats", "opacities", "sh"):
+            assert bool(torch.isfinite(getattr(t.g, name)).all()), name
+        if captured:
+            assert t.cstep is not None and t.recaptures == 0
+        t.close()
+    le, P_e, nd_e, _ = runs[False]
+    lc, P_c, nd_c, _ = runs[True]
+    assert nd_c == nd_e == 2
+    assert all(np.isfinite(lc))
+    assert np.mean(lc[-10:]) < 0.85 * np.mean(lc[:10]), (lc[:10], lc[-10:])
+    if not partial:
+        # the same batches from the same parameters: the first loss agrees to rounding
+        assert abs(lc[0] - le[0]) <= 1e-6 * abs(le[0])
+        assert np.allclose(lc[:20], le[:20], rtol=2e-2), (lc[:20], le[:20])
+        assert abs(P_c - P_e) <= 0.02 * P_e
+    else:
+        # keys come from different generators: compare the trajectories on average
+        assert abs(np.mean(lc[-10:]) - np.mean(le[-10:])) <= 0.1 * np.mean(le[-10:])
