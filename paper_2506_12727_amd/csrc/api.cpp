@@ -524,6 +524,17 @@ void mvgs_destroy(mvgs_context* ctx) {
 
 namespace {
 
+// A lane's pixels share its walk over the tile's list, so more pixels per lane means fewer
+// wavefronts: fewer walks over the same lists, but also less latency hiding. Take the most
+// pixels per lane the tile allows that still launches kMinBlendWaves wavefronts (16 per CU); a
+// frame with fewer tiles than that takes one pixel per lane.
+constexpr uint64_t kMinBlendWaves = 4096;
+static int blend_auto_ppl(int tw, int th, uint32_t n_tiles) {
+    for (int ppl = blend_default_ppl(tw, th); ppl > 1; ppl >>= 1)
+        if ((uint64_t)n_tiles * (uint64_t)(tw * th / (64 * ppl)) >= kMinBlendWaves) return ppl;
+    return 1;
+}
+
 // Capacity-mode frames keep on the device (dtot, 64 bytes): the call's totals (u64 records, pairs,
 // error words, selection tasks) at [0, 32) and at [32, 44) the clamped record and pair counts and
 // the void word (bit 0 capacity overflow, bit 1 rejected selection, bit 2 tasks over their bound).

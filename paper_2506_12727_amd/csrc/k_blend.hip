@@ -275,17 +275,6 @@ int blend_default_ppl(int tw, int th) {
     return th >= 16 ? 2 : 1;
 }
 
-// A lane's pixels share its walk over the tile's list, so more pixels per lane means fewer
-// wavefronts: fewer walks over the same lists, but also less latency hiding. Take the most
-// pixels per lane the tile allows that still launches kMinBlendWaves wavefronts (16 per CU); a
-// frame with fewer tiles than that takes one pixel per lane.
-constexpr uint64_t kMinBlendWaves = 4096;
-int blend_auto_ppl(int tw, int th, uint32_t n_tiles) {
-    for (int ppl = blend_default_ppl(tw, th); ppl > 1; ppl >>= 1)
-        if ((uint64_t)n_tiles * (uint64_t)(tw * th / (64 * ppl)) >= kMinBlendWaves) return ppl;
-    return 1;
-}
-
 template <int W_, int H_, int P_>
 static void launch_fwd_t(const BlendFwdArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_blend_fwd<W_, H_, P_>), dim3(a.n_tiles), dim3(W_ * H_ / P_), 0, s, a.cams, a.B, a.n_tiles,

@@ -120,8 +120,6 @@ struct BlendBwdArgs {
 };
 bool blend_supported(int tw, int th, int ppl);
 int blend_default_ppl(int tw, int th);
-// pixels per lane for a frame of n_tiles tiles when the context leaves the choice to the library
-int blend_auto_ppl(int tw, int th, uint32_t n_tiles);
 void launch_frame_work(const DevCam* cams, int B, const uint2* ranges, const uint32_t* vals, const BlendRec* recs,
                        const uint32_t* n_last, uint32_t n_pixels, int tw, int th, uint64_t* out, hipStream_t s);
 void launch_blend_fwd(const BlendFwdArgs& a, int tw, int th, int ppl, hipStream_t s);
