@@ -322,7 +322,10 @@ int mvgs_frame_release(mvgs_context* ctx, mvgs_frame* frame);
 
 /* Capacity mode: wait for the frame's forward and report whether it fitted the capacities
  * (MVGS_ECAPACITY if not: its images and any backward on it are void; make a context with larger
- * capacities). A partial frame is also void, with MVGS_EINVAL, if its selection was rejected; if
+ * capacities). The depth sort of a capacity-mode forward orders the window of depth keys (whole
+ * 8-bit passes around them) that the last frame checked on this context had, or all 32 bits before
+ * any check; a forward whose keys leave that window is void too (MVGS_ECAPACITY, and the check
+ * moves the window to its keys: make the call again, or capture it again). A partial frame is also void, with MVGS_EINVAL, if its selection was rejected; if
  * its width * height pixels select a plane position in two views, MVGS_EINVAL says that its 3D
  * loss and merge are void. Sets the sizes mvgs_frame_info and mvgs_export_binning use.
  * Synchronizes the stream; not capturable. Returns MVGS_OK at once for frames not made in

@@ -223,6 +223,10 @@ struct mvgs_context {
     DevBuf adam_state;   // 3 words of a device-counted Adam step (allocated with the first device use)
     size_t limit = 0;  // 0: no workspace limit
     uint64_t cap_v = 0, cap_k = 0;  // capacity mode when non-zero
+    // capacity mode: the window of depth keys the depth sort orders, [dwin_base, dwin_base +
+    // 2^dwin_bits), set by mvgs_frame_check from the keys of the frames it checks
+    uint32_t dwin_base = 0;
+    int dwin_bits = 32;
     bool capturing = false;         // the current call's stream is being captured into a graph
     uint64_t* pinned_totals = nullptr;
     bool device_used = false;
@@ -536,8 +540,9 @@ static int blend_auto_ppl(int tw, int th, uint32_t n_tiles) {
 }
 
 // Capacity-mode frames keep on the device (dtot, 64 bytes): the call's totals (u64 records, pairs,
-// error words, selection tasks) at [0, 32) and at [32, 44) the clamped record and pair counts and
-// the void word (bit 0 capacity overflow, bit 1 rejected selection, bit 2 tasks over their bound).
+// error words, selection tasks) at [0, 32), at [32, 44) the clamped record and pair counts and
+// the void word (bit 0 capacity overflow, bit 1 rejected selection, bit 2 tasks over their bound,
+// bit 3 depth keys outside the sort window), and at [48, 56) the depth keys' (min, ~max).
 const uint32_t* frame_eff(const mvgs_frame* f) {
     return f->capacity ? reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(f->dtot.p) + 32) : nullptr;
 }
@@ -662,7 +667,12 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     // participation and sizes
     int mk = ctx->stage_begin(0, s);
     fill_u32(as<uint32_t>(ctx->nrec) + P, 1, 0u, s);
-    launch_count(ga, dcam, B, tw, th, as<uint32_t>(ctx->nrec), as<uint32_t>(ctx->ntiles), s);
+    // the range of the records' depth keys (totals[6]: min, ~max), read at the synchronization
+    // below so that the depth sort covers only the bits in which keys differ (capacity mode:
+    // checked against the context's window on the device)
+    uint32_t* key_range = reinterpret_cast<uint32_t*>(as<uint64_t>(ctx->totals) + 6);
+    fill_u32(key_range, 2, ~0u, s);
+    launch_count(ga, dcam, B, tw, th, as<uint32_t>(ctx->nrec), as<uint32_t>(ctx->ntiles), s, key_range);
     scan_exclusive_u32(as<uint32_t>(ctx->nrec), as<uint32_t>(f->rec_off), P + 1, as<uint64_t>(ctx->totals),
                        ctx->scan_scratch.p, s);
     reduce_sum_u32(as<uint32_t>(ctx->ntiles), P, as<uint64_t>(ctx->totals) + 1, nullptr, s);
@@ -690,11 +700,16 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     ctx->stage_end(mk, s);
     FCHK(hipGetLastError());
     uint64_t V64 = ctx->cap_v, K64 = ctx->cap_k;
+    uint32_t depth_base = 0;   // the depth sort orders key - depth_base on depth_bits bits
+    int depth_bits = 32;
     const uint32_t* eff = nullptr;   // capacity mode: device (records, pairs) of this call
     const uint32_t* ovf = nullptr;   // capacity mode: device overflow word
     if (cap) {
         uint32_t* e32 = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(f->dtot.p) + 32);
-        launch_capacity_clamp(as<uint64_t>(ctx->totals), ctx->cap_v, ctx->cap_k, e32, e32 + 2, s);
+        depth_base = ctx->dwin_base;
+        depth_bits = ctx->dwin_bits;
+        launch_capacity_clamp(as<uint64_t>(ctx->totals), ctx->cap_v, ctx->cap_k, e32, e32 + 2, s, key_range,
+                              depth_base, depth_bits, e32 + 4);
         if (sel) {
             // the grid of the selection kernels is the task bound; the count stays on the device
             launch_sel_void(sel_err, as<uint64_t>(ctx->totals) + 3, (uint32_t)task_cap, e32, e32 + 2, s);
@@ -710,10 +725,15 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
         f->V = 0;
         f->K = 0;
     } else {
-        FCHK(hipMemcpyAsync(ctx->pinned_totals, ctx->totals.p, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        FCHK(hipMemcpyAsync(ctx->pinned_totals, ctx->totals.p, 7 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
         FCHK(hipStreamSynchronize(s));
         V64 = ctx->pinned_totals[0];
         K64 = ctx->pinned_totals[1];
+        const uint32_t kmin = (uint32_t)ctx->pinned_totals[6], kmax = ~(uint32_t)(ctx->pinned_totals[6] >> 32);
+        if (V64 > 0 && kmin <= kmax) {
+            depth_base = kmin;
+            depth_bits = kmax > kmin ? 32 - __builtin_clz(kmax - kmin) : 1;
+        }
         if (sel) {
             const uint32_t e = (uint32_t)(ctx->pinned_totals[2] >> 32);
             f->partition = want_plane && !(e & kSelPlaneOverlap) &&
@@ -783,7 +803,7 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     mk = ctx->stage_begin(2, s);
     uint32_t* dk[2] = {as<uint32_t>(ctx->depth_key[0]), as<uint32_t>(ctx->depth_key[1])};
     uint32_t* dv[2] = {as<uint32_t>(ctx->rec_vals[0]), as<uint32_t>(ctx->rec_vals[1])};
-    const int dcur = radix_sort_u32(dk, dv, true, V, 32, ctx->sort_scratch.p, s, eff);
+    const int dcur = radix_sort_u32(dk, dv, true, V, depth_bits, ctx->sort_scratch.p, s, eff, depth_base);
     const uint32_t* sorted_rec = dv[dcur];
     ctx->stage_end(mk, s);
 
@@ -1197,10 +1217,30 @@ int mvgs_frame_check(mvgs_context* ctx, void* stream, mvgs_frame* frame) {
     if (!frame->capacity) return MVGS_OK;
     hipStream_t s = (hipStream_t)stream;
     if (ctx->begin(s)) return ctx->fail(MVGS_EINVAL, "mvgs_frame_check synchronizes and cannot be captured");
-    HIPCHK(ctx, hipMemcpyAsync(ctx->pinned_totals, frame->dtot.p, 48, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->pinned_totals, frame->dtot.p, 56, hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     const uint64_t V = ctx->pinned_totals[0], K = ctx->pinned_totals[1];
     const uint32_t* e32 = reinterpret_cast<const uint32_t*>(ctx->pinned_totals + 4);
+    // the depth-sort window of later forwards: around this frame's keys, whole 8-bit passes
+    const uint32_t kmin = e32[4], kmax = ~e32[5];
+    if (V > 0 && kmin <= kmax) {   // (the count kernel finds the range whatever else happened)
+        const uint32_t range = kmax - kmin;
+        const int need = range ? 32 - __builtin_clz(range) : 1;
+        const int bits = std::min(32, 8 * ((need + 7) / 8));
+        if (bits >= 32) {
+            ctx->dwin_base = 0;
+            ctx->dwin_bits = 32;
+        } else {
+            const uint32_t margin = (uint32_t)((((uint64_t)1 << bits) - 1 - range) / 2);
+            ctx->dwin_base = kmin >= margin ? kmin - margin : 0u;
+            ctx->dwin_bits = bits;
+        }
+    }
+    if (e32[2] & 8u) {
+        frame->checked = false;
+        return ctx->fail(MVGS_ECAPACITY, "the depth keys left the sort window that the call was made with; the "
+                                         "context's window now fits them: make the call again (capture again)");
+    }
     const uint32_t sel_e = frame->mode == kModeFull ? 0u : (uint32_t)(ctx->pinned_totals[2] >> 32);
     if (e32[2] & 2u) {
         frame->checked = false;

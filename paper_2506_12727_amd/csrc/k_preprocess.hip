@@ -24,22 +24,49 @@ __global__ void __launch_bounds__(256) k_count(const float* __restrict__ means, 
                                                const float* __restrict__ quats, const float* __restrict__ opac,
                                                int64_t P, const DevCam* __restrict__ cams, int B, int tile_w,
                                                int tile_h, uint32_t* __restrict__ nrec,
-                                               uint32_t* __restrict__ ntiles) {
+                                               uint32_t* __restrict__ ntiles, uint32_t* __restrict__ key_range) {
+    __shared__ uint32_t red[2][4];
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= P) return;
-    float mu[3], s[3], q[4], o;
-    load_gaussian(means, scales, quats, opac, g, mu, s, q, o);
-    uint32_t n = 0, nt = 0;
-    for (int v = 0; v < B; ++v) {
-        ProjState st;
-        const ProjOut p = project(mu, s, q, o, cams[v], st);
-        if (p.ok) {
-            n += 1;
-            nt += (uint32_t)((p.x1 / tile_w - p.x0 / tile_w + 1) * (p.y1 / tile_h - p.y0 / tile_h + 1));
+    uint32_t kmin = 0xffffffffu, kmax = 0u;   // depth keys of the participating records
+    if (g < P) {
+        float mu[3], s[3], q[4], o;
+        load_gaussian(means, scales, quats, opac, g, mu, s, q, o);
+        uint32_t n = 0, nt = 0;
+        for (int v = 0; v < B; ++v) {
+            ProjState st;
+            const ProjOut p = project(mu, s, q, o, cams[v], st);
+            if (p.ok) {
+                n += 1;
+                nt += (uint32_t)((p.x1 / tile_w - p.x0 / tile_w + 1) * (p.y1 / tile_h - p.y0 / tile_h + 1));
+                kmin = min(kmin, f2u(p.depth));
+                kmax = max(kmax, f2u(p.depth));
+            }
         }
+        nrec[g] = n;
+        ntiles[g] = nt;
     }
-    nrec[g] = n;
-    ntiles[g] = nt;
+    if (!key_range) return;   // (uniform over the workgroup)
+    // the workgroup's range; a global atomic only when it widens the range seen so far
+    for (int off = 32; off > 0; off >>= 1) {
+        kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off, 64));
+        kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off, 64));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = kmin;
+        red[1][w] = kmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (int)(blockDim.x + 63) >> 6;
+        for (int i = 1; i < nw; ++i) {
+            kmin = min(kmin, red[0][i]);
+            kmax = max(kmax, red[1][i]);
+        }
+        // the second word holds the complement of the maximum, so that both start at ~0
+        if (kmin < __atomic_load_n(key_range, __ATOMIC_RELAXED)) atomicMin(key_range, kmin);
+        if (~kmax < __atomic_load_n(key_range + 1, __ATOMIC_RELAXED)) atomicMin(key_range + 1, ~kmax);
+    }
 }
 
 // The per-record arrays beside the record itself: view, depth key and covered-tile rectangle
@@ -311,11 +338,11 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(
 // launchers
 // ---------------------------------------------------------------------------------------------
 void launch_count(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, uint32_t* nrec,
-                  uint32_t* ntiles, hipStream_t s) {
+                  uint32_t* ntiles, hipStream_t s, uint32_t* key_range) {
     const unsigned blocks = (unsigned)((ga.P + 255) / 256);
     if (!blocks) return;
     hipLaunchKernelGGL(k_count, dim3(blocks), dim3(256), 0, s, ga.means, ga.scales, ga.quats, ga.opac, ga.P, cams,
-                       B, tw, th, nrec, ntiles);
+                       B, tw, th, nrec, ntiles, key_range);
 }
 
 void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,

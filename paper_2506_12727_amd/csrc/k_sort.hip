@@ -195,8 +195,8 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 // the mask + 1 digits of the pass), so that one exclusive scan of the whole table gives every
 // (digit, partition) its output base.
 __global__ void __launch_bounds__(256) k_radix_upsweep(const uint32_t* __restrict__ keys, size_t n,
-                                                       const uint32_t* __restrict__ n_dev, int shift, uint32_t mask,
-                                                       uint32_t parts, uint32_t* __restrict__ counts) {
+                                                       const uint32_t* __restrict__ n_dev, uint32_t key_base, int shift,
+                                                       uint32_t mask, uint32_t parts, uint32_t* __restrict__ counts) {
     __shared__ uint32_t h[kRadix];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -206,15 +206,15 @@ __global__ void __launch_bounds__(256) k_radix_upsweep(const uint32_t* __restric
         const uint4* k4 = reinterpret_cast<const uint4*>(keys + base);
         for (int j = threadIdx.x; j < kSortTile / 4; j += 256) {
             const uint4 k = k4[j];
-            atomicAdd(&h[(k.x >> shift) & mask], 1u);
-            atomicAdd(&h[(k.y >> shift) & mask], 1u);
-            atomicAdd(&h[(k.z >> shift) & mask], 1u);
-            atomicAdd(&h[(k.w >> shift) & mask], 1u);
+            atomicAdd(&h[((k.x - key_base) >> shift) & mask], 1u);
+            atomicAdd(&h[((k.y - key_base) >> shift) & mask], 1u);
+            atomicAdd(&h[((k.z - key_base) >> shift) & mask], 1u);
+            atomicAdd(&h[((k.w - key_base) >> shift) & mask], 1u);
         }
     } else {
         for (int j = threadIdx.x; j < kSortTile; j += 256) {
             const size_t i = base + j;
-            if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+            if (i < n) atomicAdd(&h[((keys[i] - key_base) >> shift) & mask], 1u);
         }
     }
     __syncthreads();
@@ -225,8 +225,8 @@ __global__ void __launch_bounds__(256) k_radix_upsweep(const uint32_t* __restric
 // digit order to the bases the scan gave.
 __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, size_t n, const uint32_t* __restrict__ n_dev, int shift, uint32_t mask,
-    uint32_t parts, const uint32_t* __restrict__ offsets) {
+    uint32_t* __restrict__ vals_out, size_t n, const uint32_t* __restrict__ n_dev, uint32_t key_base, int shift,
+    uint32_t mask, uint32_t parts, const uint32_t* __restrict__ offsets) {
     __shared__ uint32_t wcount[kSortWaves][kRadix];
     __shared__ uint32_t dstart[kRadix];
     __shared__ uint32_t gbase[kRadix];
@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     for (int r = 0; r < kSortRounds; ++r) {
         const size_t i = base + (size_t)r * 64 + lane;
         const bool valid = i < n;
-        const uint32_t d = (key[r] >> shift) & mask;
+        const uint32_t d = ((key[r] - key_base) >> shift) & mask;
         const uint64_t peers = digit_peers(d, valid);
         const uint32_t below = (uint32_t)rank_below(peers);
         const uint32_t before = wcount[wave][d];
@@ -280,7 +280,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     for (int r = 0; r < kSortRounds; ++r) {
         const size_t i = base + (size_t)r * 64 + lane;
         if (i < n) {
-            const uint32_t d = (key[r] >> shift) & mask;
+            const uint32_t d = ((key[r] - key_base) >> shift) & mask;
             const uint32_t pos = dstart[d] + wcount[wave][d] + rank[r];
             skey[pos] = key[r];
             sval[pos] = val[r];
@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     const size_t tile_n = std::min<size_t>((size_t)kSortTile, n - (size_t)part * kSortTile);
     for (int j = threadIdx.x; j < (int)tile_n; j += kSortThreads) {
         const uint32_t k = skey[j];
-        const uint32_t d = (k >> shift) & mask;
+        const uint32_t d = ((k - key_base) >> shift) & mask;
         const size_t dst = (size_t)gbase[d] + (uint32_t)(j - dstart[d]);
         keys_out[dst] = k;
         vals_out[dst] = sval[j];
@@ -318,26 +318,28 @@ static PassPlan plan_passes(int bits) {
 
 // one reduce-then-scan pass over n items (bound; n_dev the count on the device)
 static void radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
-                       size_t n, const uint32_t* n_dev, int shift, uint32_t mask, void* scratch, hipStream_t s) {
+                       size_t n, const uint32_t* n_dev, uint32_t base, int shift, uint32_t mask, void* scratch,
+                       hipStream_t s) {
     const size_t parts = div_up(n, kSortTile);
     uint8_t* p = (uint8_t*)scratch;
     uint32_t* counts = (uint32_t*)p;
     p += align256(parts * kRadix * sizeof(uint32_t));
-    hipLaunchKernelGGL(k_radix_upsweep, dim3((unsigned)parts), dim3(256), 0, s, keys_in, n, n_dev, shift, mask,
-                       (uint32_t)parts, counts);
+    hipLaunchKernelGGL(k_radix_upsweep, dim3((unsigned)parts), dim3(256), 0, s, keys_in, n, n_dev, base, shift,
+                       mask, (uint32_t)parts, counts);
     scan_exclusive_u32(counts, counts, parts * ((size_t)mask + 1), nullptr, p, s, nullptr);
     hipLaunchKernelGGL(k_radix_downsweep, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in, vals_in,
-                       keys_out, vals_out, n, n_dev, shift, mask, (uint32_t)parts, (const uint32_t*)counts);
+                       keys_out, vals_out, n, n_dev, base, shift, mask, (uint32_t)parts, (const uint32_t*)counts);
 }
 
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
-                   hipStream_t s, const uint32_t* n_dev) {
+                   hipStream_t s, const uint32_t* n_dev, uint32_t key_base) {
     int cur = 0;
     if (n == 0 || bits <= 0) return cur;
     const PassPlan pl = plan_passes(bits);
     for (int pass = 0; pass < pl.passes; ++pass) {
         const uint32_t* vin = (pass == 0 && identity_values) ? nullptr : vals[cur];
-        radix_pass(keys[cur], vin, keys[cur ^ 1], vals[cur ^ 1], n, n_dev, pl.dbits * pass, pl.mask, scratch, s);
+        radix_pass(keys[cur], vin, keys[cur ^ 1], vals[cur ^ 1], n, n_dev, key_base, pl.dbits * pass, pl.mask, scratch,
+                   s);
         cur ^= 1;
     }
     return cur;
@@ -677,8 +679,8 @@ int sort_pairs_rest(uint32_t* keys[2], uint32_t* vals[2], size_t K, const uint32
     if (K == 0) return cur;
     const PassPlan pl = plan_passes(bits);
     for (int pass = 1; pass < pl.passes; ++pass) {
-        radix_pass(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], K, K_dev, pl.dbits * pass, pl.mask, scratch,
-                   s);
+        radix_pass(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], K, K_dev, 0u, pl.dbits * pass, pl.mask,
+                   scratch, s);
         cur ^= 1;
     }
     return cur;
@@ -719,19 +721,31 @@ void fill_u32_count(uint32_t* p, size_t n, const uint32_t* n_dev, uint32_t per, 
 // Capacity mode: the records and pairs of this call against the buffers' capacities. Within them,
 // eff = (V, K); beyond either, eff = (0, 0) and the overflow word is set, so every later kernel
 // does no work and stays inside its buffers.
+// Also: the depth keys of the records (key_range: min, ~max) must lie in the window
+// [key_base, key_base + 2^key_bits) the depth sort of this call orders (bit 3 otherwise); the
+// range is kept in range_out for the host.
 __global__ void k_capacity_clamp(const unsigned long long* __restrict__ totals, uint64_t cap_v, uint64_t cap_k,
-                                 uint32_t* __restrict__ eff, uint32_t* __restrict__ overflow) {
+                                 uint32_t* __restrict__ eff, uint32_t* __restrict__ overflow,
+                                 const uint32_t* __restrict__ key_range, uint32_t key_base, int key_bits,
+                                 uint32_t* __restrict__ range_out) {
     const uint64_t V = totals[0], K = totals[1];
-    const bool over = V > cap_v || K > cap_k;
-    eff[0] = over ? 0u : (uint32_t)V;
-    eff[1] = over ? 0u : (uint32_t)K;
-    overflow[0] = over ? 1u : 0u;
+    uint32_t bits = V > cap_v || K > cap_k ? 1u : 0u;
+    if (key_range) {
+        const uint32_t kmin = key_range[0], kmax = ~key_range[1];
+        range_out[0] = kmin;
+        range_out[1] = key_range[1];
+        if (V > 0 && key_bits < 32 && (kmin < key_base || ((kmax - key_base) >> key_bits) != 0u)) bits |= 8u;
+    }
+    eff[0] = bits ? 0u : (uint32_t)V;
+    eff[1] = bits ? 0u : (uint32_t)K;
+    overflow[0] = bits;
 }
 
 void launch_capacity_clamp(const uint64_t* totals, uint64_t cap_v, uint64_t cap_k, uint32_t* eff, uint32_t* overflow,
-                           hipStream_t s) {
+                           hipStream_t s, const uint32_t* key_range, uint32_t key_base, int key_bits,
+                           uint32_t* range_out) {
     hipLaunchKernelGGL(k_capacity_clamp, dim3(1), dim3(1), 0, s, (const unsigned long long*)totals, cap_v, cap_k, eff,
-                       overflow);
+                       overflow, key_range, key_base, key_bits, range_out);
 }
 
 }  // namespace mvgs

@@ -30,8 +30,10 @@ struct GradArgs {
 };
 
 // k_preprocess.hip
+// key_range: null, or 2 device words (min, ~max) that the depth keys of the participating records
+// are folded into with atomicMin (the caller sets both to ~0 first)
 void launch_count(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, uint32_t* nrec,
-                  uint32_t* ntiles, hipStream_t s);
+                  uint32_t* ntiles, hipStream_t s, uint32_t* key_range = nullptr);
 // overflow: null, or a device word that, when non-zero, makes the kernel write nothing
 void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,
                     BlendRec* recs, uint32_t* depth_key, uint4* tile_rect, uint16_t* rec_view, hipStream_t s,
@@ -58,20 +60,24 @@ void scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* t
 // Sum of n u32 values as u64 into *total64 (device).
 void reduce_sum_u32(const uint32_t* in, size_t n, uint64_t* total64, void* scratch, hipStream_t s);
 
-// Stable LSD radix sort of (key, value) u32 pairs on bits [0, bits), at most 8 bits per pass; a
-// pass reads the keys twice (count, scatter) and writes keys and values once. The input is in
-// keys[0] and vals[0] (or, with identity_values, the values are 0..n-1 and vals[0] is only
-// ping-pong space); passes alternate between buffers 0 and 1. Returns the index of the buffer
-// holding the result.
+// Stable LSD radix sort of (key, value) u32 pairs by key - key_base on bits [0, bits) (every key
+// must lie in [key_base, key_base + 2^bits)), at most 8 bits per pass; a pass reads the keys twice
+// (count, scatter) and writes keys and values once. The input is in keys[0] and vals[0] (or, with
+// identity_values, the values are 0..n-1 and vals[0] is only ping-pong space); passes alternate
+// between buffers 0 and 1. Returns the index of the buffer holding the result.
 size_t radix_scratch_bytes(size_t n);
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
-                   hipStream_t s, const uint32_t* n_dev = nullptr);
+                   hipStream_t s, const uint32_t* n_dev = nullptr, uint32_t key_base = 0);
 
 void fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 // per * min(*n_dev, n) values (all per * n when n_dev is null)
 void fill_u32_count(uint32_t* p, size_t n, const uint32_t* n_dev, uint32_t per, uint32_t v, hipStream_t s);
+// eff = the counts, or 0 and 0 with *overflow = 1 when they exceed the capacities; with key_range
+// (min, ~max of the depth keys) also 8 when the keys leave [key_base, key_base + 2^key_bits), and
+// the range copied to range_out
 void launch_capacity_clamp(const uint64_t* totals, uint64_t cap_v, uint64_t cap_k, uint32_t* eff, uint32_t* overflow,
-                           hipStream_t s);
+                           hipStream_t s, const uint32_t* key_range = nullptr, uint32_t key_base = 0,
+                           int key_bits = 32, uint32_t* range_out = nullptr);
 
 // Pairs of the depth-ordered records and their stable sort by global tile id (of `bits` bits):
 // the first pass gathers the records' tile rectangles into depth order (sorted_rect, [n_rec]) and

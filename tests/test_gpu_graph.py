@@ -170,3 +170,36 @@ def test_captured_step_replays_match_eager():
     step.close()
     other.close()
     eager.close()
+
+
+def test_depth_sort_window_is_checked():
+    """In capacity mode the depth sort orders the window of depth keys mvgs_frame_check saw last
+    (whole 8-bit passes around them); a replay whose keys leave it does nothing and is reported,
+    and a step captured again fits the new keys and matches the eager step."""
+    needs_gpu()
+    sc, cams = _batch()
+    g = GaussianTensors.from_scene(sc)
+    tg = [torch.from_numpy(t).cuda() for t in scenes.make_targets(cams)]
+    step = CapturedStep(g, cams, tg, 1.0, 0.0, tile=(16, 16))
+    far = scenes.make_cameras(SIZES, seed=2, radius=9.0)   # depths around 9: outside the window
+    step.set_cameras(far)
+    step.replay()
+    torch.cuda.synchronize()
+    with pytest.raises(L.MvgsError) as ei:
+        step.check()
+    assert ei.value.status == L.MVGS_ECAPACITY and "window" in str(ei.value)
+    assert all(float(t.abs().max()) == 0.0 for t in step.grads.values())
+    step.close()
+    step = CapturedStep(g, far, tg, 1.0, 0.0, tile=(16, 16))
+    step.replay()
+    torch.cuda.synchronize()
+    step.check()
+    eager = Rasterizer((16, 16))
+    imgs_e, loss_e, grads_e, _ = _eager_step(eager, g, far, tg, 1.0, 0.0)
+    for a, b in zip(step.images, imgs_e):
+        assert torch.equal(a, b)
+    for n in grads_e:
+        compare_grad(n, step.grads[n].cpu().numpy(), grads_e[n].cpu().numpy().astype(np.float64), rtol=1e-4,
+                     inf=1e-5, l2=1e-4)
+    step.close()
+    eager.close()
