@@ -27,7 +27,11 @@ METRIC = "fwd+bwd views/s, 1M Gaussians, 8-view batch vs 1-view loop; serve p50/
 HBM_PEAK_GBS = 8000.0
 # non-packed FP32 vector lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 ALU_PEAK_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# algorithmic lane operations per blended (pixel, Gaussian) pair
+# algorithmic lane operations per blended (pixel, Gaussian) pair. Forward: 2 subtractions and 5
+# multiply/fma for the power, 1 compare, 2 for exp2, 2 for alpha and its clamp, 1 fma for T, 1
+# compare, 1 weight, 3 fma for colour. Backward: the forward's 10 for power and alpha, 2 to recover
+# T, 3 colour gradients, 7 for dL/dalpha, 6 for the colour-behind update, 16 for the opacity, mean
+# and conic gradients, and 9 additions folding the pixel into the per-Gaussian sums.
 FWD_OPS_PER_STEP = 18
 BWD_OPS_PER_STEP = 57
 STAGES = ["count", "records", "depth_sort", "emit", "tile_sort", "ranges", "blend_fwd", "loss", "blend_bwd",
@@ -68,7 +72,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path runs on a single "
-              "MI355X; see DESIGN.md for how it would shard across GPUs).", file=sys.stderr)
+              "MI355X; across GPUs each would render its own views of a replicated scene and the "
+              "per-Gaussian gradients and statistics would be all-reduced).", file=sys.stderr)
         sys.exit(2)
     import ctypes as C
 
