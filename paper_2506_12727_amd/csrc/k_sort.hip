@@ -614,26 +614,23 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_downsweep(
     }
 }
 
-// [start, end) of each global tile's run in the sorted pair keys, by binary search
+// [start, end) of each global tile's run in the sorted pair keys, by binary search: a wavefront
+// finds where tiles t0 .. t0 + 63 start (one search per lane) and writes the ranges of the first
+// 63, the end of a run being the start of the next tile's
 __global__ void __launch_bounds__(256) k_ranges_search(const uint32_t* __restrict__ keys, uint32_t K,
                                                        const uint32_t* __restrict__ K_dev, uint32_t n_tiles,
                                                        uint2* __restrict__ ranges) {
-    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= n_tiles) return;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t t = (blockIdx.x * 4u + (threadIdx.x >> 6)) * 63u + lane;
     K = (uint32_t)count_of(K, K_dev);
-    uint32_t lo = 0, hi = K;  // first index with keys[i] >= t
+    uint32_t lo = 0, hi = K;   // first index with keys[i] >= t
     while (lo < hi) {
         const uint32_t mid = lo + ((hi - lo) >> 1);
         if (keys[mid] < t) lo = mid + 1;
         else hi = mid;
     }
-    uint32_t lo2 = lo, hi2 = K;  // first index with keys[i] > t
-    while (lo2 < hi2) {
-        const uint32_t mid = lo2 + ((hi2 - lo2) >> 1);
-        if (keys[mid] <= t) lo2 = mid + 1;
-        else hi2 = mid;
-    }
-    ranges[t] = lo2 > lo ? make_uint2(lo, lo2) : make_uint2(0u, 0u);
+    const uint32_t next = (uint32_t)__shfl_down((int)lo, 1, 64);
+    if (lane < 63u && t < n_tiles) ranges[t] = next > lo ? make_uint2(lo, next) : make_uint2(0u, 0u);
 }
 
 __global__ void k_export_keys(const uint32_t* __restrict__ tile_keys, const uint32_t* __restrict__ vals,
@@ -689,7 +686,7 @@ int sort_pairs_rest(uint32_t* keys[2], uint32_t* vals[2], size_t K, const uint32
 void launch_ranges(const uint32_t* keys, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s,
                    const uint32_t* K_dev) {
     if (!n_tiles) return;
-    hipLaunchKernelGGL(k_ranges_search, dim3((n_tiles + 255) / 256), dim3(256), 0, s, keys, K, K_dev, n_tiles,
+    hipLaunchKernelGGL(k_ranges_search, dim3((n_tiles + 251) / 252), dim3(256), 0, s, keys, K, K_dev, n_tiles,
                        ranges);
 }
 
@@ -713,9 +710,26 @@ __global__ void k_fill_u32_count(uint32_t* __restrict__ p, size_t n, const uint3
     if (i < (size_t)per * count_of(n, n_dev)) p[i] = v;
 }
 
+// the same with 16-byte stores (p 16-byte aligned): four values per thread
+__global__ void k_fill_u32x4_count(uint32_t* __restrict__ p, size_t n, const uint32_t* __restrict__ n_dev,
+                                   uint32_t per, uint32_t v) {
+    const size_t i = 4 * ((size_t)blockIdx.x * blockDim.x + threadIdx.x);
+    const size_t total = (size_t)per * count_of(n, n_dev);
+    if (i + 3 < total) {
+        *reinterpret_cast<uint4*>(p + i) = make_uint4(v, v, v, v);
+    } else {
+        for (size_t j = i; j < total; ++j) p[j] = v;
+    }
+}
+
 void fill_u32_count(uint32_t* p, size_t n, const uint32_t* n_dev, uint32_t per, uint32_t v, hipStream_t s) {
     if (!n || !per) return;
-    hipLaunchKernelGGL(k_fill_u32_count, dim3((unsigned)div_up(n * per, 256)), dim3(256), 0, s, p, n, n_dev, per, v);
+    if (((uintptr_t)p & 15u) == 0)
+        hipLaunchKernelGGL(k_fill_u32x4_count, dim3((unsigned)div_up(n * per, 1024)), dim3(256), 0, s, p, n, n_dev,
+                           per, v);
+    else
+        hipLaunchKernelGGL(k_fill_u32_count, dim3((unsigned)div_up(n * per, 256)), dim3(256), 0, s, p, n, n_dev, per,
+                           v);
 }
 
 // Capacity mode: the records and pairs of this call against the buffers' capacities. Within them,
