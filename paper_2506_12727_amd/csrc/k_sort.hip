@@ -77,11 +77,20 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t* __
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
 
+// block_off: the scanned block sums (the block's base is block_off[block]); or block_sums: the
+// block sums themselves, which the block adds up to its base (few blocks: one kernel less)
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t* in, uint32_t* out, size_t n,
                                                              const uint32_t* __restrict__ n_dev,
-                                                             const uint32_t* __restrict__ block_off) {
+                                                             const uint32_t* __restrict__ block_off,
+                                                             const uint32_t* __restrict__ block_sums) {
     __shared__ uint32_t lds[256];
     n = count_of(n, n_dev);
+    uint32_t off = block_off ? block_off[blockIdx.x] : 0u;
+    if (block_sums) {
+        uint32_t part = 0;
+        for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kScanThreads) part += block_sums[b];
+        (void)block_exclusive_scan_256(part, lds, &off);
+    }
     const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
     uint32_t vals[kScanItems];
     uint32_t s = 0;
@@ -91,7 +100,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t* in,
         s += vals[k];
     }
     uint32_t total;
-    uint32_t run = block_exclusive_scan_256(s, lds, &total) + (block_off ? block_off[blockIdx.x] : 0u);
+    uint32_t run = block_exclusive_scan_256(s, lds, &total) + off;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < n) out[base + k] = run;
@@ -151,15 +160,20 @@ static void scan_rec(const uint32_t* in, uint32_t* out, size_t n, const uint32_t
     const size_t blocks = div_up(n, kScanTile);
     if (blocks <= 1) {
         hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanThreads), 0, s, in, out, n, n_dev,
-                           (const uint32_t*)nullptr);
+                           (const uint32_t*)nullptr, (const uint32_t*)nullptr);
         return;
     }
     uint32_t* sums = (uint32_t*)scratch;
     uint8_t* next = scratch + ((blocks * sizeof(uint32_t) + 255) / 256) * 256;
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)blocks), dim3(kScanThreads), 0, s, in, n, n_dev, sums);
+    if (blocks <= 16 * kScanThreads) {   // each block adds up at most 16 sums per thread itself
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)blocks), dim3(kScanThreads), 0, s, in, out, n, n_dev,
+                           (const uint32_t*)nullptr, (const uint32_t*)sums);
+        return;
+    }
     scan_rec(sums, sums, blocks, nullptr, next, s);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)blocks), dim3(kScanThreads), 0, s, in, out, n, n_dev,
-                       (const uint32_t*)sums);
+                       (const uint32_t*)sums, (const uint32_t*)nullptr);
 }
 
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* total64, void* scratch,
