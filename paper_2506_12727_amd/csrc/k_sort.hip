@@ -365,13 +365,6 @@ int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, s
 
 __device__ __forceinline__ uint32_t rect_tiles(uint4 r) { return (r.y & 0xffffu) * (r.y >> 16); }
 
-// The one gather of the records' tile rectangles into depth order, so that pair emission reads
-// them sequentially.
-__global__ void k_gather_rects(const uint32_t* __restrict__ sorted_rec, const uint4* __restrict__ rect, uint32_t n,
-                               const uint32_t* __restrict__ n_dev, uint4* __restrict__ sorted_rect) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < (uint32_t)count_of(n, n_dev)) sorted_rect[i] = rect[sorted_rec[i]];
-}
 
 // Pair emission fused with the first pass of the stable sort by global tile id. A workgroup takes
 // a chunk of kEmitRecs consecutive records of the depth order; their pairs, in depth order and
@@ -399,9 +392,12 @@ struct EmitStage {
 };
 
 // Stages records [r0, r0 + cnt) of the depth order (cnt <= kEmitRecs); returns the chunk's pairs.
+// GATHER: the rectangles are fetched by record (tile_rect[sorted_rec[i]]) and written out in depth
+// order to sorted_rect; otherwise they are read from sorted_rect.
+template <bool GATHER>
 __device__ __forceinline__ uint32_t emit_stage(const uint32_t* __restrict__ sorted_rec,
-                                               const uint4* __restrict__ sorted_rect, uint32_t r0, uint32_t cnt,
-                                               EmitStage& st, uint32_t* scan_tmp) {
+                                               const uint4* __restrict__ tile_rect, uint4* __restrict__ sorted_rect,
+                                               uint32_t r0, uint32_t cnt, EmitStage& st, uint32_t* scan_tmp) {
     constexpr int kPer = kEmitRecs / kSortThreads;   // consecutive records per thread
     const uint32_t t = threadIdx.x;
     uint32_t c[kPer];
@@ -411,12 +407,20 @@ __device__ __forceinline__ uint32_t emit_stage(const uint32_t* __restrict__ sort
         const uint32_t i = kPer * t + (uint32_t)k;
         c[k] = 0u;
         if (i < cnt) {
-            const uint4 rc = sorted_rect[r0 + i];
+            uint4 rc;
+            if (GATHER) {
+                const uint32_t r = sorted_rec[r0 + i];
+                rc = tile_rect[r];
+                sorted_rect[r0 + i] = rc;
+                st.rec[i] = r;
+            } else {
+                rc = sorted_rect[r0 + i];
+                st.rec[i] = sorted_rec[r0 + i];
+            }
             c[k] = rect_tiles(rc);
             st.base[i] = rc.x;
             st.wdt[i] = rc.y & 0xffffu;
             st.stride[i] = rc.z;
-            if (sorted_rec) st.rec[i] = sorted_rec[r0 + i];
         }
         sum += c[k];
     }
@@ -490,7 +494,10 @@ struct EmitWalk {
     }
 };
 
-__global__ void __launch_bounds__(kSortThreads) k_emit_upsweep(const uint4* __restrict__ sorted_rect, uint32_t n,
+// The chunk's rectangles gathered into depth order (for the downsweep) and its digit counts.
+__global__ void __launch_bounds__(kSortThreads) k_emit_upsweep(const uint32_t* __restrict__ sorted_rec,
+                                                               const uint4* __restrict__ tile_rect,
+                                                               uint4* __restrict__ sorted_rect, uint32_t n,
                                                                const uint32_t* __restrict__ n_dev, uint32_t mask,
                                                                uint32_t chunks, uint32_t* __restrict__ counts) {
     __shared__ EmitStage st;
@@ -501,7 +508,7 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_upsweep(const uint4* __re
     const uint32_t r0 = blockIdx.x * kEmitRecs;
     if (r0 < n) {   // uniform over the workgroup
         const uint32_t cnt = min(n - r0, (uint32_t)kEmitRecs);
-        const uint32_t total = emit_stage(nullptr, sorted_rect, r0, cnt, st, scan_tmp);
+        const uint32_t total = emit_stage<true>(sorted_rec, tile_rect, sorted_rect, r0, cnt, st, scan_tmp);
         // each thread counts a contiguous run of pairs, walking the rectangles row-major
         const uint32_t q = (total + kSortThreads - 1) / kSortThreads;
         uint32_t j = threadIdx.x * q;
@@ -539,7 +546,8 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_downsweep(
     if (r0 >= n) return;
     const uint32_t cnt = min(n - r0, (uint32_t)kEmitRecs);
     gbase[threadIdx.x] = threadIdx.x <= mask ? offsets[(size_t)threadIdx.x * chunks + blockIdx.x] : 0u;
-    const uint32_t total = emit_stage(sorted_rec, sorted_rect, r0, cnt, st, scan_tmp);
+    const uint32_t total = emit_stage<false>(sorted_rec, nullptr, const_cast<uint4*>(sorted_rect), r0, cnt, st,
+                                             scan_tmp);
     for (uint32_t b0 = 0; b0 < total; b0 += kEmitBatch) {
         const uint32_t bn = min(total - b0, (uint32_t)kEmitBatch);
 #pragma unroll
@@ -669,15 +677,13 @@ void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint4* tile_rect, u
                            const uint32_t* n_rec_dev, uint32_t* keys, uint32_t* vals, size_t K,
                            const uint32_t* K_dev, int bits, void* scratch, hipStream_t s) {
     if (n_rec == 0 || K == 0) return;
-    hipLaunchKernelGGL(k_gather_rects, dim3((unsigned)div_up(n_rec, 256)), dim3(256), 0, s, sorted_rec, tile_rect,
-                       (uint32_t)n_rec, n_rec_dev, sorted_rect);
     const PassPlan pl = plan_passes(bits);
     const size_t chunks = div_up(n_rec, kEmitRecs);
     uint8_t* p = (uint8_t*)scratch;
     uint32_t* counts = (uint32_t*)p;
     p += align256(chunks * kRadix * sizeof(uint32_t));
-    hipLaunchKernelGGL(k_emit_upsweep, dim3((unsigned)chunks), dim3(kSortThreads), 0, s, (const uint4*)sorted_rect,
-                       (uint32_t)n_rec, n_rec_dev, pl.mask, (uint32_t)chunks, counts);
+    hipLaunchKernelGGL(k_emit_upsweep, dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rec, tile_rect,
+                       sorted_rect, (uint32_t)n_rec, n_rec_dev, pl.mask, (uint32_t)chunks, counts);
     scan_exclusive_u32(counts, counts, chunks * ((size_t)pl.mask + 1), nullptr, p, s, nullptr);
     hipLaunchKernelGGL(k_emit_downsweep, dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rec,
                        (const uint4*)sorted_rect, (uint32_t)n_rec, n_rec_dev, pl.mask, (uint32_t)chunks,
