@@ -60,6 +60,54 @@ def test_binning_bit_exact(case):
     r.release(fr)
 
 
+def _depth_case(kind):
+    """A camera looking along +z from z = -3 (depth = z + 3) over Gaussians all at z = 0 (every
+    depth key equal: the depth sort orders one bit, ties only), or spread from depth 0.3 to 500
+    (keys that differ in 27 bits: four passes)."""
+    sc = scenes.make_scene(3000, 1, seed=17, log_scale_mean=-3.0)
+    rng = np.random.default_rng(18)
+    if kind == "equal":
+        sc.means[:, 2] = 0.0
+    else:
+        sc.means[:, 2] = (np.exp(rng.uniform(np.log(0.3), np.log(500.0), size=len(sc.means))) - 3.0)
+        sc.means[:, :2] *= (sc.means[:, 2:3] + 3.0) / 3.0   # keep them in view
+    sc.means = sc.means.astype(np.float32)
+    f = 0.5 * 96 / np.tan(np.radians(30.0))
+    cams = [scenes.Camera(96, 80, float(np.float32(f)), float(np.float32(f)), 48.0, 40.0,
+                          np.eye(3, dtype=np.float32), np.array([0.0, 0.0, 3.0], np.float32))]
+    return sc, cams
+
+
+@pytest.mark.parametrize("kind", ["equal", "wide"])
+def test_depth_sort_key_range_edges(kind):
+    """The depth sort orders only the bits in which the records' depth keys differ (eager), or a
+    window of them (capacity mode, after a check): binning stays bit for bit the oracle's at both
+    ends of the range."""
+    needs_gpu()
+    sc, cams = _depth_case(kind)
+    ok, ov, orr = oracle.binning(sc, cams, (16, 16))
+    assert len(ok) > 100
+
+    def same(r, fr):
+        keys, vals, ranges = r.export_binning(fr)
+        assert np.array_equal(keys.cpu().numpy().view(np.uint64), ok)
+        assert np.array_equal(vals.cpu().numpy().view(np.uint32), ov)
+        assert np.array_equal(ranges.cpu().numpy().view(np.uint32), orr)
+
+    r, g, imgs, fr = run_forward(sc, cams, (16, 16))
+    same(r, fr)
+    r.release(fr)
+    info_r = oracle.count_pairs(sc, cams, (16, 16))
+    cap = Rasterizer((16, 16), capacity=(info_r[0] + 10, info_r[1] + 10))
+    for _ in range(2):   # the second call sorts the window the first call's check set
+        _, fc = cap.forward(g, cams)
+        fc.check()
+        same(cap, fc)
+        cap.release(fc)
+    cap.close()
+    r.close()
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_forward_images(case):
     needs_gpu()
