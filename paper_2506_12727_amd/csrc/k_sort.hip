@@ -370,11 +370,13 @@ __device__ __forceinline__ uint32_t rect_tiles(uint4 r) { return (r.y & 0xffffu)
 // a chunk of kEmitRecs consecutive records of the depth order; their pairs, in depth order and
 // row-major over each record's tile rectangle, are the chunk's items (the partition of the first
 // pass). Both kernels generate them alike: the chunk's rectangles and the exclusive prefix of
-// their tile counts are staged in LDS, and lane j of the chunk finds its record by binary search
-// over that prefix; pair t of a record whose rectangle is w tiles wide is tile (tx0 + t mod w,
-// ty0 + t / w). The upsweep counts their digits; the downsweep ranks them stably in batches of
-// kEmitBatch (wave64 ballots), stages each batch in LDS in digit order and writes it in runs. The
-// emitted pairs are never stored unsorted.
+// their tile counts are staged in LDS; a lane finds the record of the first pair of its run by
+// binary search over that prefix and walks on from there (pair t of a record whose rectangle is
+// w tiles wide is tile (tx0 + t mod w, ty0 + t / w)). The upsweep gathers the chunk's rectangles
+// into depth order for the downsweep and counts the digits of its pairs, a contiguous run per
+// thread; the downsweep, in batches of kEmitBatch, lets each lane walk 16 consecutive pairs, hands
+// them to the wave64 ballot ranking in round order through LDS, stages the batch in digit order
+// and writes it out in runs. The emitted pairs are never stored unsorted.
 constexpr int kEmitRecs = 512;
 constexpr int kEmitRounds = 16;
 constexpr int kEmitBatch = kSortWaves * kEmitRounds * 64;   // 4096
