@@ -6,7 +6,8 @@
 // sorted by their 32-bit depth key (one item per record), pairs are then emitted in that depth
 // order and sorted stably by their global tile id (view-major, so (view, tile) in one integer of
 // ceil(log2(total tiles)) bits). Ties in depth keep the (Gaussian, view) emission order of the
-// records, i.e. ascending Gaussian index within a view.
+// records, i.e. ascending Gaussian index within a view. The depth sort orders key - min over only
+// the bits in which the keys differ, and the first pass of the tile sort is fused with emission.
 //
 // Radix sort: LSD, digits of at most 8 bits spread evenly over the passes, 8192 items per
 // partition (4 wavefronts x 32 rounds x 64 lanes). Each pass reduces, scans, then scatters: one
