@@ -75,11 +75,12 @@ def _same_step(a, b):
                      inf=1e-5, l2=1e-4)
 
 
-def test_capacity_partial_matches_eager():
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 16)])
+def test_capacity_partial_matches_eager(tile):
     needs_gpu()
     g, cams, tg = _setup()
-    cap = Rasterizer((16, 16), capacity=measure_capacity(g, cams))
-    eager = Rasterizer((16, 16))
+    cap = Rasterizer(tile, capacity=measure_capacity(g, cams, tile))
+    eager = Rasterizer(tile)
     for seed in (1, 2):   # the second call reuses the buffers the first sized
         keys = _keys(seed)
         dz_e, dz_c = _stats(g.P), _stats(g.P)
