@@ -16,10 +16,13 @@
  *     (view, tile).
  *   - Sec. 3 / Sec. 5.1.2 (Eqs. 7-10): L1 and D-SSIM losses.
  *   - Sec. 5.2 (Eqs. 13-14): per-view screen-space error metrics E1 and E2.
- * All continuous arithmetic is double precision. The discrete decisions (who
- * participates, tile rectangles, sort keys, the per-pixel cut tests) are taken
- * in single precision by a fixed operation sequence (ora_geom32.c) because the
- * kernel takes them in single precision; the readings behind every constant are
+ * All continuous arithmetic is double precision. The binning decisions (who
+ * participates, tile rectangles, sort keys) are taken in single precision by a
+ * fixed operation sequence (ora_geom32.c) because the kernel takes them in
+ * single precision and binning is compared bit for bit. The per-pixel cut,
+ * clamp and stop tests are taken in double precision; a pixel where one of them
+ * lies within the kernel's single-precision error of its threshold is flagged
+ * (and excluded from the comparison). The readings behind every constant are
  * listed in the project's design notes.
  *
  * Parity status: every function here is pinned by CPU tests (closed forms,
@@ -67,9 +70,8 @@ typedef struct {
     uint32_t depth_bits;    /* IEEE bits of depth (monotone for depth > 0) */
     float mx, my;           /* projected mean, pixels */
     float ca, cb, cc;       /* conic = inverse dilated 2D covariance, [[ca,cb],[cb,cc]] */
-    float hca, nb, hcc;     /* -0.5*ca, -cb, -0.5*cc: the form the cut test uses */
-    float cut;              /* keep a pixel iff power >= cut */
-    float hi;               /* opacity*exp(power) is clamped to 0.99 iff power > hi */
+    float cut;              /* single-precision cut threshold, max(-4.5, -ln(255 o)): sizes the footprint */
+    float hi;               /* ln(0.99 / o) in single precision (reported only) */
     float radius;
     int32_t x0, x1, y0, y1; /* inclusive pixel box, clipped to the image */
 } ora_g32;
@@ -79,7 +81,6 @@ float ora_ln32(float x);
 void ora_geom32_eval(const float mu[3], const float s[3], const float q[4], float o,
                      const float R[9], const float t[3], float fx, float fy, float cx, float cy,
                      int32_t W, int32_t H, ora_g32* out);
-float ora_power32(const ora_g32* g, int32_t x, int32_t y);
 
 /* ora_sh.c */
 int ora_sh_count(int degree);

@@ -1,14 +1,17 @@
 /*
  * Single-precision decision geometry (oracle side). TEST INFRASTRUCTURE ONLY.
  *
- * The rasterizer's discrete decisions -- does a Gaussian take part in a view,
- * which tiles does it cover, what is its 32-bit depth key, does a pixel fall
- * inside its cut -- are functions of single-precision arithmetic in the kernel.
- * To compare them bit for bit, the oracle takes the same decisions in single
- * precision with the operation sequence written out below (every multiply and
- * add is its own rounding; fused multiply-adds appear only where fmaf() is
- * written; division and square root are IEEE). This file must be compiled
- * with -ffp-contract=off.
+ * The rasterizer's binning decisions -- does a Gaussian take part in a view,
+ * which tiles does it cover, what is its 32-bit depth key -- are functions of
+ * single-precision arithmetic in the kernel. To compare binning bit for bit,
+ * the oracle takes these decisions in single precision with the operation
+ * sequence written out below (every multiply and add is its own rounding;
+ * fused multiply-adds appear only where fmaf() is written; division and square
+ * root are IEEE). This file must be compiled with -ffp-contract=off. The
+ * per-pixel cut and clamp tests are not taken here: the walk decides them in
+ * double precision and flags the pixels where single precision could decide
+ * otherwise. The single-precision projected mean and conic computed here are
+ * also what the image-parity mode blends with (the kernel's geometry).
  *
  * Paper passages: Sec. 3 (covariance R S S^T R^T, EWA projection of mean and
  * covariance); Appendix "Rasterization in multi-view training" (frustum culling,
@@ -30,10 +33,11 @@
 static uint32_t f2u(float f) { uint32_t u; memcpy(&u, &f, 4); return u; }
 static float u2f(uint32_t u) { float f; memcpy(&f, &u, 4); return f; }
 
-/* Natural logarithm used for the opacity thresholds: x = 2^e m with m in
- * [sqrt(1/2), sqrt(2)], ln m = 2 atanh(s), s = (m-1)/(m+1), series to s^9.
- * It only has to be a fixed, accurate (~1e-7) function; both sides evaluate it
- * with this exact sequence. Non-positive or NaN input gives -inf. */
+/* Natural logarithm of the opacity threshold that sizes the footprint: x = 2^e m
+ * with m in [sqrt(1/2), sqrt(2)], ln m = 2 atanh(s), s = (m-1)/(m+1), series to
+ * s^9. It only has to be a fixed, accurate (~1e-7) function; because the
+ * footprint decides binning, both sides evaluate it with this exact sequence.
+ * Non-positive or NaN input gives -inf. */
 float ora_ln32(float x)
 {
     if (!(x > 0.0f)) return -INFINITY;
@@ -144,9 +148,6 @@ void ora_geom32_eval(const float mu[3], const float s[3], const float q[4], floa
     g->ca = c * idet;
     g->cb = -(b * idet);
     g->cc = a * idet;
-    g->hca = -0.5f * g->ca;
-    g->nb = -g->cb;
-    g->hcc = -0.5f * g->cc;
 
     /* opacity thresholds in the power domain */
     float lc = -ora_ln32(255.0f * o);
@@ -176,17 +177,4 @@ void ora_geom32_eval(const float mu[3], const float s[3], const float q[4], floa
     g->cut = cut;
     g->hi = ora_ln32(0.99f / o);
     g->participates = 1;
-}
-
-/* power = -0.5 (d^T conic d), d = pixel centre - projected mean, in the kernel's
- * single-precision operation order: dy (hcc dy + nb dx) + (hca dx) dx. */
-float ora_power32(const ora_g32* g, int32_t x, int32_t y)
-{
-    float px = (float)x + 0.5f;
-    float py = (float)y + 0.5f;
-    float dx = px - g->mx;
-    float dy = py - g->my;
-    float ax = (g->hca * dx) * dx;
-    float bx = g->nb * dx;
-    return fmaf(dy, fmaf(g->hcc, dy, bx), ax);
 }

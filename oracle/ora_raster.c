@@ -296,12 +296,35 @@ int64_t ora_binning(const ora_scene* s, const ora_cams* c, uint64_t* keys, uint3
 /* forward                                                                   */
 /* ------------------------------------------------------------------------- */
 
-/* What the pixel loop needs per Gaussian of one view. */
+/* What the pixel loop needs per Gaussian of one view: the geometry the walk decides and blends
+ * with (double projection, or the single-precision values in image-parity mode), and in double
+ * mode also the single-precision mean and conic, used only to size the flag margin. */
 typedef struct {
     double mx, my, ca, cb, cc, o, rgb[3];
     double z; /* camera-space depth */
+    double cut, hi; /* keep a pixel iff power >= cut; alpha clamped to 0.99 iff power > hi */
+    double cut_err; /* the kernel's error in cut: 0 when cut is the exact -4.5, else POW_LN */
+    double mx32, my32, ca32, cb32, cc32;
     int clamp_bits;
 } pix_g;
+
+/* Decision margins. The kernel decides the cut and clamp tests from a single-precision power and
+ * single-precision thresholds, and the stop test on its single-precision transmittance. The
+ * oracle decides in double and flags a pixel where a decision it takes lies within the kernel's
+ * possible error of the threshold:
+ *   power:      POW_REL * (|a dx^2|/2 + |b dx dy| + |c dy^2|/2), i.e. 16 single-precision
+ *               roundings of the power's terms (an evaluation in any order of its ~8 operations
+ *               rounds each term at most ~6 times), plus POW_LN where the threshold is a
+ *               logarithm (twice the error of the kernel's single-precision logarithm, which is
+ *               within 2e-6 of ln; the cut -4.5 itself is exact);
+ *   double mode: plus the power's change between the double and the single-precision projected
+ *               geometry at this pixel (the kernel's power is within the first margin of the
+ *               power of its single-precision geometry, which is within this change of the
+ *               double power);
+ *   stop:       `margin` relative to the 1e-4 threshold (plus, in double mode, the change of the
+ *               new transmittance between the two geometries). */
+#define POW_REL 9.5367431640625e-07 /* 2^-20 */
+#define POW_LN 4e-6
 
 static uint64_t mix64(uint64_t x)
 {
@@ -320,9 +343,11 @@ static void prepare_view(const ora_scene* s, const ora_cams* c, int v, int geom3
         proj64 p;
         project64_one(s, c, v, g, &p);
         pix_g* q = &pg[g];
+        q->mx32 = g32[g].mx; q->my32 = g32[g].my;
+        q->ca32 = g32[g].ca; q->cb32 = g32[g].cb; q->cc32 = g32[g].cc;
         if (geom32_mode) {
-            q->mx = g32[g].mx; q->my = g32[g].my;
-            q->ca = g32[g].ca; q->cb = g32[g].cb; q->cc = g32[g].cc;
+            q->mx = q->mx32; q->my = q->my32;
+            q->ca = q->ca32; q->cb = q->cb32; q->cc = q->cc32;
             q->z = g32[g].depth;
         } else {
             q->mx = p.mean2d[0]; q->my = p.mean2d[1];
@@ -330,6 +355,11 @@ static void prepare_view(const ora_scene* s, const ora_cams* c, int v, int geom3
             q->z = p.tc[2];
         }
         q->o = s->opac[g];
+        /* alpha >= 1/255 <=> power >= -ln(255 o); inside the 3-sigma ellipse <=> power >= -4.5 */
+        const double lc = -log(255.0 * q->o);
+        q->cut = lc > -4.5 ? lc : -4.5;
+        q->cut_err = lc > -4.5 ? POW_LN : 0.0;
+        q->hi = log(ALPHA_CLAMP / q->o);
         q->clamp_bits = 0;
         for (int k = 0; k < 3; ++k) {
             q->rgb[k] = p.rgb[k];
@@ -342,22 +372,39 @@ static void prepare_view(const ora_scene* s, const ora_cams* c, int v, int geom3
  * 2 = stop (this Gaussian would drop T below the threshold; not blended). */
 typedef struct {
     double alpha, G, T; /* alpha, exp(power), transmittance before this Gaussian */
+    double alpha_alt;   /* double mode: alpha from the single-precision geometry */
     int clamped;
     double dx, dy;
 } step_info;
 
-static int walk_step(const ora_g32* q32, const pix_g* q, int x, int y, double T, double margin, int* flag,
+/* Flag bits of a pixel: 1 = the stop test, 2 = a cut or clamp test lies within its margin. */
+static int walk_step(const pix_g* q, int x, int y, double T, double T_alt, int alt, double margin, int* flag,
                      step_info* st)
 {
-    float p32 = ora_power32(q32, x, y);
-    if (!(p32 >= q32->cut)) return 0;
     const double dx = (x + 0.5) - q->mx, dy = (y + 0.5) - q->my;
-    const double power = -0.5 * (q->ca * dx * dx + q->cc * dy * dy) - q->cb * dx * dy;
+    const double ta = q->ca * dx * dx, tb = q->cb * dx * dy, tc = q->cc * dy * dy;
+    const double power = -0.5 * (ta + tc) - tb;
+    double m = POW_REL * (0.5 * fabs(ta) + fabs(tb) + 0.5 * fabs(tc));
+    double p_alt = power;
+    if (alt) {
+        const double ex = (x + 0.5) - q->mx32, ey = (y + 0.5) - q->my32;
+        p_alt = -0.5 * (q->ca32 * ex * ex + q->cc32 * ey * ey) - q->cb32 * ex * ey;
+        m += fabs(p_alt - power);
+    }
+    if (fabs(power - q->cut) <= m + q->cut_err) *flag |= 2;
+    if (!(power >= q->cut)) return 0;
+    if (fabs(power - q->hi) <= m + POW_LN) *flag |= 2;
     const double G = exp(power);
-    const int clamped = p32 > q32->hi;
+    const int clamped = power > q->hi;
     const double alpha = clamped ? ALPHA_CLAMP : q->o * G;
     const double Tn = T * (1.0 - alpha);
-    if (fabs(Tn - T_STOP) <= margin * T_STOP) *flag |= 1;
+    double mt = margin * T_STOP;
+    st->alpha_alt = alpha;
+    if (alt) {
+        st->alpha_alt = clamped ? ALPHA_CLAMP : q->o * exp(p_alt);
+        mt += fabs(T_alt * (1.0 - st->alpha_alt) - Tn);
+    }
+    if (fabs(Tn - T_STOP) <= mt) *flag |= 1;
     st->alpha = alpha;
     st->G = G;
     st->T = T;
@@ -411,7 +458,7 @@ int ora_forward(const ora_scene* s, const ora_cams* c, int32_t geom32_mode, int3
         for (int y = 0; y < H; ++y) {
             for (int x = 0; x < W; ++x) {
                 const int64_t pix = (int64_t)y * W + x;
-                double T = 1.0, C[3] = {0, 0, 0}, Dz = 0.0;
+                double T = 1.0, T_alt = 1.0, C[3] = {0, 0, 0}, Dz = 0.0;
                 int flag = 0, n = 0;
                 uint64_t h = mix64((uint64_t)pix);
                 const uint32_t* list;
@@ -430,7 +477,7 @@ int ora_forward(const ora_scene* s, const ora_cams* c, int32_t geom32_mode, int3
                 for (int64_t i = 0; i < len; ++i) {
                     const uint32_t g = brute_force ? list[i] : plist[i].g;
                     step_info st;
-                    int r = walk_step(&g32[g], &pg[g], x, y, T, margin, &flag, &st);
+                    int r = walk_step(&pg[g], x, y, T, T_alt, !geom32_mode, margin, &flag, &st);
                     if (r == 0) continue;
                     if (r == 2) {
                         h = mix64(h ^ 0xdeadull);
@@ -439,6 +486,7 @@ int ora_forward(const ora_scene* s, const ora_cams* c, int32_t geom32_mode, int3
                     for (int k = 0; k < 3; ++k) C[k] += pg[g].rgb[k] * st.alpha * T;
                     Dz += pg[g].z * st.alpha * T;
                     T = T * (1.0 - st.alpha);
+                    T_alt = T_alt * (1.0 - st.alpha_alt);
                     ++n;
                     h = mix64(h ^ ((uint64_t)g << 2) ^ (uint64_t)st.clamped);
                 }
@@ -540,7 +588,7 @@ int ora_backward(const ora_scene* s, const ora_cams* c, int32_t geom32_mode, con
                     for (int64_t i = 0; i < len; ++i) {
                         const uint32_t g = vb.pairs[vb.start[tl] + i].g;
                         step_info st;
-                        int r = walk_step(&g32[g], &pg[g], x, y, T, 0.0, &flag, &st);
+                        int r = walk_step(&pg[g], x, y, T, T, 0, 0.0, &flag, &st);
                         if (r == 0) continue;
                         if (r == 2) break;
                         if (n == cap) {
@@ -737,17 +785,18 @@ int ora_render_pixels(const ora_scene* s, const ora_cams* c, int32_t v, int32_t 
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t k = 0; k < n; ++k) {
         const int x = xs[k], y = ys[k];
-        double T = 1.0, C[3] = {0, 0, 0}, Dz = 0.0;
+        double T = 1.0, T_alt = 1.0, C[3] = {0, 0, 0}, Dz = 0.0;
         int flag = 0;
         for (int64_t i = 0; i < n_order; ++i) {
             const uint32_t g = order[i];
             step_info st;
-            int r = walk_step(&g32[g], &pg[g], x, y, T, margin, &flag, &st);
+            int r = walk_step(&pg[g], x, y, T, T_alt, !geom32_mode, margin, &flag, &st);
             if (r == 0) continue;
             if (r == 2) break;
             for (int q = 0; q < 3; ++q) C[q] += pg[g].rgb[q] * st.alpha * T;
             Dz += pg[g].z * st.alpha * T;
             T = T * (1.0 - st.alpha);
+            T_alt = T_alt * (1.0 - st.alpha_alt);
         }
         for (int q = 0; q < 3; ++q) rgb[3 * k + q] = C[q] + T * bg[q];
         t_final[k] = T;

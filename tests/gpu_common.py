@@ -11,6 +11,8 @@ from paper_2506_12727_amd.raster import GaussianTensors, Rasterizer
 IMG_RTOL, IMG_ATOL = 1e-5, 1e-6
 GRAD_RTOL, GRAD_INF = 1e-3, 1e-4
 GRAD_L2 = 1e-3
+# at most this fraction of pixels may be flagged (a decision within the kernel's error of its threshold)
+FLAG_MAX = 1e-3
 
 
 def needs_gpu():
@@ -62,3 +64,23 @@ def compare_grad(name, gpu, ora, rtol=GRAD_RTOL, inf=GRAD_INF, l2=GRAD_L2, mask=
     assert not bad.any(), (f"{name}: {int(bad.sum())} of {bad.size} elements out of tolerance; worst "
                            f"{err.max():.3e} vs scale {scale:.3e}")
     return rel_l2
+
+
+def grad_flags(scene, cams, tile=(16, 16)):
+    """Per-view flags of the oracle's double-geometry walk (the one its gradients take): pixels where
+    a cut, clamp or stop decision lies within the kernel's possible error of its threshold."""
+    import oracle
+    return oracle.forward(scene, cams, tile, geom32_mode=False)["flags"]
+
+
+def flag_fraction(flags) -> float:
+    n = sum(int((f != 0).sum()) for f in flags)
+    return n / max(1, sum(f.size for f in flags))
+
+
+def zero_flagged(dl, flags):
+    """dL/dimage (GPU tensors [3,H,W], in place) set to zero at flagged pixels, so that they
+    contribute to neither side of a gradient comparison."""
+    for t, f in zip(dl, flags):
+        t.mul_(torch.from_numpy((f == 0).astype(np.float32)).to(t.device)[None])
+    return dl

@@ -1,10 +1,12 @@
 """Parity of the HIP path with the CPU oracle, through the C ABI.
 
 Binning (keys, values, ranges, counts) bit for bit; images and final transmittance within
-1e-5 relative + 1e-6 absolute outside pixels the oracle flags (the transmittance stop within
-1e-4 relative of its threshold, a decision single and double precision may take differently);
-loss and image gradients, parameter gradients and densification statistics within 1e-3
-relative (elementwise, plus 1e-4 of the largest magnitude; and 1e-3 in relative L2).
+1e-5 relative + 1e-6 absolute outside pixels the oracle flags (a cut, clamp or transmittance-stop
+decision, taken in double precision by the oracle, that lies within the kernel's single-precision
+error of its threshold; under 0.1% of pixels); loss and image gradients; parameter gradients and
+densification statistics against the oracle's double-precision geometry within 1e-3 relative
+(elementwise, plus 1e-4 of the largest magnitude; and 1e-3 in relative L2), with flagged pixels'
+image gradients zero on both sides.
 """
 import numpy as np
 import pytest
@@ -14,7 +16,8 @@ import oracle
 from paper_2506_12727_amd import scenes
 from paper_2506_12727_amd.raster import GaussianTensors, Rasterizer
 
-from gpu_common import compare_grad, compare_images, needs_gpu, run_forward, to_np
+from gpu_common import (FLAG_MAX, compare_grad, compare_images, flag_fraction, grad_flags, needs_gpu, run_forward,
+                        to_np, zero_flagged)
 
 pytestmark = pytest.mark.gpu
 
@@ -117,7 +120,8 @@ def test_forward_images(case):
     frac = compare_images(to_np(imgs), ref["images"], ref["flags"])
     tf = to_np(r.export_transmittance(fr))
     compare_images(tf, ref["t_final"], ref["flags"])
-    assert frac < 1e-3
+    print(f"{case}: flagged pixels {frac:.2e}")
+    assert frac < FLAG_MAX
     r.release(fr)
 
 
@@ -140,12 +144,15 @@ def test_loss_and_image_gradient(w):
 
 def _backward_case(sc, cams, tile, w_l1, w_dssim, densify, ppl=0):
     r, g, imgs, fr = run_forward(sc, cams, tile, ppl=ppl)
-    ref = oracle.forward(sc, cams, tile)
+    flags = grad_flags(sc, cams, tile)
+    frac = flag_fraction(flags)
+    print(f"gradient parity: flagged pixels {frac:.2e}")
+    assert frac < FLAG_MAX
     tg = [torch.from_numpy(a).cuda() for a in scenes.make_targets(cams)]
     _, dl = r.loss(cams, imgs, tg, w_l1, w_dssim)
-    # pixels whose stop decision may differ contribute to neither side
-    for t, f in zip(dl, ref["flags"]):
-        t.mul_(torch.from_numpy((f == 0).astype(np.float32)).cuda()[None])
+    # pixels where a decision of the double-precision walk may go the other way in the kernel
+    # contribute to neither side
+    zero_flagged(dl, flags)
     P = g.P
     dz = None
     if densify:
@@ -153,7 +160,7 @@ def _backward_case(sc, cams, tile, w_l1, w_dssim, densify, ppl=0):
                   count=torch.zeros(P, dtype=torch.int32, device="cuda"))
     grads = r.backward(g, fr, dl, densify=dz)
     torch.cuda.synchronize()
-    ob = oracle.backward(sc, cams, to_np(dl), tile)
+    ob = oracle.backward(sc, cams, to_np(dl), tile, geom32_mode=False)
     out = {}
     for n in ("means", "scales", "quats", "opacities", "sh"):
         out[n] = compare_grad(n, grads[n].cpu().numpy(), ob[n])
