@@ -124,6 +124,19 @@ typedef struct {
     int64_t workspace_limit;
     int64_t capacity_records;
     int64_t capacity_pairs;
+    /* Device memory of the context's workspace and frames: both NULL for hipMalloc / hipFree, or
+     * both set. alloc(bytes, alloc_ctx) returns at least `bytes` of device memory on the context's
+     * device, aligned to 256 bytes, or NULL (the call then fails with MVGS_ENOMEM); free(ptr,
+     * alloc_ctx) takes back a block alloc gave. The library calls them only from inside its own
+     * calls, on the thread and during the call that grows, replaces or (mvgs_destroy, after it has
+     * waited for the device) frees a buffer. free may be called while kernels that use the block
+     * are still queued on that call's stream: the allocator must not hand the block to other work
+     * before that work in stream order (a stream-ordered caching allocator, such as PyTorch's
+     * with the call's stream current, does this). The dedicated upload staging of calls recorded
+     * into a graph capture is allocated with hipMalloc / hipHostMalloc whatever these say. */
+    void* (*alloc)(size_t bytes, void* alloc_ctx);
+    void (*free)(void* ptr, void* alloc_ctx);
+    void* alloc_ctx;
 } mvgs_options;
 
 /* Create a context on the current HIP device. `opt` may be NULL (defaults).
@@ -152,6 +165,32 @@ void mvgs_destroy(mvgs_context* ctx);
  * context's limit (no frame is made then). */
 int mvgs_forward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_camera* cams, int32_t B,
                  float* const* images, mvgs_frame** frame);
+
+/* Participation pre-pass per view (the multi-view appendix decides which Gaussians take part in
+ * each view before any per-record memory is sized): for each of the B views, the number of
+ * participating Gaussians (its records) and of the (Gaussian, tile) pairs they cover with this
+ * context's tile shape, exactly as a forward of these cameras would count them. records, pairs:
+ * host arrays of B. Runs one kernel over the Gaussians on `stream` and synchronizes it (not
+ * capturable). Counts of a batch are the sums of its views' counts. */
+int mvgs_count_views(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_camera* cams, int32_t B,
+                     int64_t* records, int64_t* pairs);
+
+/* Admission bound: the device bytes this context would hold (as mvgs_memory_held counts them)
+ * after a forward of B views over P Gaussians whose participation pre-pass counted `records` and
+ * `pairs` (summed over the views; mvgs_count_views), followed by the work in `work`:
+ * MVGS_WORK_LOSS (mvgs_loss with w_dssim 0) or MVGS_WORK_LOSS_DSSIM (with D-SSIM), and
+ * MVGS_WORK_BACKWARD (mvgs_backward on the frame). It replays the growth of every buffer those
+ * calls would size, from the context's present buffers and frame pool, with the allocator's
+ * growth rule; host only, no device work. So with a workspace limit of at least *bytes, these
+ * calls, made next on this context with these cameras and Gaussians, are not refused. In capacity
+ * mode records and pairs are the context's capacities. MVGS_EINVAL for counts no batch can have;
+ * MVGS_ECAPACITY if records or pairs reach 2^32 (the forward would refuse them). */
+#define MVGS_WORK_FORWARD 0
+#define MVGS_WORK_LOSS 1
+#define MVGS_WORK_LOSS_DSSIM 2
+#define MVGS_WORK_BACKWARD 4
+int mvgs_workspace_bound(mvgs_context* ctx, const mvgs_camera* cams, int32_t B, int64_t P, int64_t records,
+                         int64_t pairs, int32_t work, int64_t* bytes);
 
 /* Partial rendering (paper Sec. 5.1.1, "Thread-efficient partial rendering", and Alg. 3): each view
  * renders only a selection of its pixels, the paper's index array. The selection is given per
@@ -317,7 +356,11 @@ int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, cons
                   const float* const* dl_dimages, mvgs_grads* grads, mvgs_densify* densify);
 
 /* Return a frame's memory to its context. The frame must not be in use by
- * work still pending on a stream other than the one it was created on. */
+ * work still pending on a stream other than the one it was created on. The
+ * handle is stale afterwards: every call given it returns MVGS_EINVAL, also
+ * after a later forward reuses the pooled frame object (a handle carries the
+ * object's 16-bit generation, which each release advances). Frames die with
+ * their context. */
 int mvgs_frame_release(mvgs_context* ctx, mvgs_frame* frame);
 
 /* Capacity mode: wait for the frame's forward and report whether it fitted the capacities
@@ -358,6 +401,12 @@ int mvgs_frame_workspace(const mvgs_frame* frame, int64_t* bytes);
 /* Sizes of a frame: participating (view, Gaussian) records, (Gaussian, tile)
  * pairs and tiles over all views. Any pointer may be NULL. */
 int mvgs_frame_info(const mvgs_frame* frame, int64_t* n_records, int64_t* n_pairs, int64_t* n_tiles);
+
+/* Radix passes the frame's forward ran (for rooflines): the depth sort of the records orders
+ * only the bits in which their depth keys differ (ceil(bits / 8) passes of even width); the tile
+ * sort of the pairs orders the bits of the batch's global tile ids, its first pass fused with pair
+ * emission (counted here). 0 for an empty sort. Either pointer may be NULL. */
+int mvgs_frame_sort_info(const mvgs_frame* frame, int32_t* depth_passes, int32_t* tile_passes);
 
 /* Test hook: copy a frame's binning to caller device buffers: keys [n_pairs]
  * (view<<48 | tile<<32 | depth bits), values [n_pairs] (Gaussian index), and

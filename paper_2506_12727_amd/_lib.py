@@ -26,10 +26,19 @@ EXPORTED = ["mvgs_create", "mvgs_destroy", "mvgs_forward", "mvgs_loss", "mvgs_ba
             "mvgs_frame_workspace", "mvgs_forward_partial", "mvgs_subsample", "mvgs_frame_check",
             "mvgs_frame_set_cameras", "mvgs_loss_3d", "mvgs_export_depth", "mvgs_adapt_density",
             "mvgs_adam_step", "mvgs_gather_rows", "mvgs_grad_moments", "mvgs_frame_merge",
-            "mvgs_frame_void_word"]
+            "mvgs_frame_void_word", "mvgs_count_views", "mvgs_workspace_bound",
+            "mvgs_frame_sort_info"]
 MVGS_PARTIAL_COMPACT = 0
 MVGS_PARTIAL_MASKED = 1
 MVGS_STAGE_COUNT = 10
+MVGS_WORK_FORWARD = 0
+MVGS_WORK_LOSS = 1
+MVGS_WORK_LOSS_DSSIM = 2
+MVGS_WORK_BACKWARD = 4
+
+# allocator callbacks of mvgs_options
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class mvgs_camera(C.Structure):
@@ -55,7 +64,7 @@ class mvgs_densify(C.Structure):
 class mvgs_options(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("pixels_per_lane", C.c_int32),
                 ("reserved0", C.c_int32), ("workspace_limit", C.c_int64), ("capacity_records", C.c_int64),
-                ("capacity_pairs", C.c_int64)]
+                ("capacity_pairs", C.c_int64), ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p)]
 
 
 class mvgs_adc_params(C.Structure):
@@ -144,6 +153,12 @@ def lib():
     L.mvgs_frame_set_cameras.restype = C.c_int
     L.mvgs_loss_3d.argtypes = [vp, vp, vp, vp, vp, f32, f32, vp, vp]
     L.mvgs_loss_3d.restype = C.c_int
+    L.mvgs_frame_sort_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+    L.mvgs_frame_sort_info.restype = C.c_int
+    L.mvgs_count_views.argtypes = [vp, vp, C.POINTER(mvgs_gaussians), C.POINTER(mvgs_camera), i32, vp, vp]
+    L.mvgs_count_views.restype = C.c_int
+    L.mvgs_workspace_bound.argtypes = [vp, C.POINTER(mvgs_camera), i32, i64, i64, i64, i32, C.POINTER(i64)]
+    L.mvgs_workspace_bound.restype = C.c_int
     L.mvgs_export_depth.argtypes = [vp, vp, vp, vp]
     L.mvgs_export_depth.restype = C.c_int
     L.mvgs_adapt_density.argtypes = [vp, vp, C.POINTER(mvgs_gaussians), vp, vp, vp, vp, C.POINTER(mvgs_adc_params),

@@ -17,31 +17,59 @@ using namespace mvgs;
 
 namespace {
 
+// Where device memory comes from: the caller's callbacks (mvgs_options.alloc / free), else
+// hipMalloc / hipFree.
+struct Allocator {
+    void* (*alloc)(size_t, void*) = nullptr;
+    void (*free)(void*, void*) = nullptr;
+    void* ctx = nullptr;
+};
+
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    const Allocator* al = nullptr;   // the owning context's allocator
 };
+
+hipError_t dev_alloc(const Allocator* al, void** p, size_t n) {
+    if (al && al->alloc) {
+        *p = al->alloc(n, al->ctx);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, n);
+}
+
+hipError_t dev_free(const Allocator* al, void* p) {
+    if (al && al->free) {
+        al->free(p, al->ctx);
+        return hipSuccess;
+    }
+    return hipFree(p);
+}
 
 // Capacity a grow-only buffer has after it is asked for `bytes`: unchanged if it already fits,
 // else at least a quarter more than before, in whole 4 KiB pages.
-size_t grown_capacity(const DevBuf& b, size_t bytes) {
-    if (bytes <= b.cap && b.p) return b.cap;
+size_t grown_capacity(size_t cap, size_t bytes) {
+    if (bytes <= cap && cap) return cap;
     size_t n = std::max<size_t>(bytes, 256);
-    n = std::max(n, b.cap + b.cap / 4);
+    n = std::max(n, cap + cap / 4);
     return (n + 4095) & ~(size_t)4095;
 }
+size_t grown_capacity(const DevBuf& b, size_t bytes) { return grown_capacity(b.p ? b.cap : 0, bytes); }
 
-// Grow-only device buffer. Growing frees the old allocation (hipFree waits for the device).
+// Grow-only device buffer. Growing frees the old allocation first: hipFree waits for the device;
+// a caller's free callback gets the block while work that used it may still be queued on the
+// call's stream (the contract of mvgs_options.free: reuse in stream order).
 hipError_t ensure(DevBuf& b, size_t bytes) {
     if (bytes <= b.cap && b.p) return hipSuccess;
     const size_t n = grown_capacity(b, bytes);
     if (b.p) {
-        hipError_t e = hipFree(b.p);
+        hipError_t e = dev_free(b.al, b.p);
         if (e != hipSuccess) return e;
         b.p = nullptr;
         b.cap = 0;
     }
-    hipError_t e = hipMalloc(&b.p, n);
+    hipError_t e = dev_alloc(b.al, &b.p, n);
     if (e != hipSuccess) {
         b.p = nullptr;
         return e;
@@ -51,7 +79,7 @@ hipError_t ensure(DevBuf& b, size_t bytes) {
 }
 
 void release(DevBuf& b) {
-    if (b.p) (void)hipFree(b.p);
+    if (b.p) (void)dev_free(b.al, b.p);
     b.p = nullptr;
     b.cap = 0;
 }
@@ -178,6 +206,7 @@ constexpr int kModeFull = -1;  // otherwise MVGS_PARTIAL_COMPACT or MVGS_PARTIAL
 struct mvgs_frame {
     mvgs_context* ctx = nullptr;
     bool in_use = false;
+    uint16_t gen = 0;   // generation of the handle: advanced at each release (see frame_handle)
     int B = 0;
     std::vector<DevCam> hcams;
     uint32_t n_tiles = 0, n_pixels = 0;
@@ -187,6 +216,7 @@ struct mvgs_frame {
     uint32_t V = 0;
     uint64_t K = 0;
     int final_buf = 0;
+    int depth_bits = 0, tile_bits = 0;   // key bits the depth and tile sorts ordered
     size_t need_bytes = 0;  // device bytes the forward that made this frame asked for
     // partial rendering: kModeFull renders every pixel; the others a selection (t_final and
     // n_last then hold one entry per selected pixel in thread-efficient mode)
@@ -214,6 +244,7 @@ struct mvgs_frame {
 
 struct mvgs_context {
     int device = 0;
+    Allocator alloc;   // every DevBuf of the context and of its frames points here
     int tw = 16, th = 16, ppl = 2;
     bool ppl_auto = false;   // pixels per lane chosen per frame (blend_auto_ppl)
     std::string err;
@@ -221,6 +252,7 @@ struct mvgs_context {
     DevBuf nrec, ntiles, totals, scan_scratch, depth_key[2], rec_vals[2], tile_rect, sorted_rect;
     DevBuf sort_scratch, acc, loss_scratch, ssim_maps, loss3d_scratch, adc_n, adc_off, adc_act, moment_partials;
     DevBuf adam_state;   // 3 words of a device-counted Adam step (allocated with the first device use)
+    DevBuf view_counts;  // per-view records and pairs of mvgs_count_views
     size_t limit = 0;  // 0: no workspace limit
     uint64_t cap_v = 0, cap_k = 0;  // capacity mode when non-zero
     // capacity mode: the window of depth keys the depth sort orders, [dwin_base, dwin_base +
@@ -249,7 +281,7 @@ struct mvgs_context {
         DevBuf* bufs[] = {&nrec, &ntiles, &totals, &scan_scratch, &depth_key[0], &depth_key[1], &rec_vals[0],
                           &rec_vals[1], &tile_rect, &sorted_rect, &sort_scratch, &acc,
                           &loss_scratch, &ssim_maps, &loss3d_scratch, &adc_n, &adc_off, &adc_act,
-                          &moment_partials, &work, &adam_state};
+                          &moment_partials, &work, &adam_state, &view_counts};
         for (DevBuf* b : bufs) fn(*b);
         for (auto& sl : ring.slots) fn(sl.dev);
         for (mvgs_frame* f : frames) f->each_buffer(fn);
@@ -443,6 +475,25 @@ void build_cams(const mvgs_camera* cams, int B, int tw, int th, std::vector<DevC
     }
 }
 
+// Frame handles. Frame objects are pooled per context and reused, so a raw pointer would let a
+// handle kept past mvgs_frame_release name whatever frame the object holds next. A handle is
+// therefore the object's address (below 2^48 in user space) with the object's 16-bit generation
+// in the top bits; releasing a frame advances its generation, and every call resolves the handle
+// through frame_of, which rejects a handle whose generation is not the object's current one (a
+// stale handle aliases a new frame only after exactly a multiple of 65,536 reuses of its object).
+constexpr uintptr_t kFrameAddrMask = ((uintptr_t)1 << 48) - 1;
+
+mvgs_frame* frame_handle(mvgs_frame* f) {
+    return reinterpret_cast<mvgs_frame*>(reinterpret_cast<uintptr_t>(f) | ((uintptr_t)f->gen << 48));
+}
+
+mvgs_frame* frame_of(const mvgs_frame* handle) {
+    const uintptr_t h = reinterpret_cast<uintptr_t>(handle);
+    mvgs_frame* f = reinterpret_cast<mvgs_frame*>(h & kFrameAddrMask);
+    if (!f || f->gen != (uint16_t)(h >> 48) || !f->in_use) return nullptr;
+    return f;
+}
+
 mvgs_frame* acquire_frame(mvgs_context* ctx) {
     for (mvgs_frame* f : ctx->frames)
         if (!f->in_use) {
@@ -451,6 +502,11 @@ mvgs_frame* acquire_frame(mvgs_context* ctx) {
         }
     mvgs_frame* f = new (std::nothrow) mvgs_frame();
     if (!f) return nullptr;
+    if (reinterpret_cast<uintptr_t>(f) & ~kFrameAddrMask) {   // no room for the generation
+        delete f;
+        return nullptr;
+    }
+    f->each_buffer([&](DevBuf& b) { b.al = &ctx->alloc; });
     f->ctx = ctx;
     f->in_use = true;
     ctx->frames.push_back(f);
@@ -488,6 +544,7 @@ int mvgs_create(mvgs_context** out, const mvgs_options* opt) {
         cap_v = opt->capacity_records;
         cap_k = opt->capacity_pairs;
         if (opt->reserved0) return MVGS_EINVAL;
+        if ((opt->alloc == nullptr) != (opt->free == nullptr)) return MVGS_EINVAL;
     }
     if (limit < 0 || cap_v < 0 || cap_k < 0 || (cap_v == 0) != (cap_k == 0) || cap_v >= (1ll << 32) ||
         cap_k >= (1ll << 32))
@@ -504,6 +561,12 @@ int mvgs_create(mvgs_context** out, const mvgs_options* opt) {
     ctx->limit = (size_t)limit;
     ctx->cap_v = (uint64_t)cap_v;
     ctx->cap_k = (uint64_t)cap_k;
+    if (opt) {
+        ctx->alloc.alloc = opt->alloc;
+        ctx->alloc.free = opt->free;
+        ctx->alloc.ctx = opt->alloc_ctx;
+    }
+    ctx->each_buffer([&](DevBuf& b) { b.al = &ctx->alloc; });
     // no HIP call here: device resources are created by the first call that needs them
     *out = ctx;
     return MVGS_OK;
@@ -579,6 +642,102 @@ struct SelIn {
     int mode;
 };
 
+// What a forward's buffers are sized by.
+struct FwdSizes {
+    int B = 0;
+    size_t P = 0;
+    uint32_t n_tiles = 0, n_pixels = 0;
+    bool cap = false;
+    const SelIn* sel = nullptr;
+    size_t task_cap = 0;     // tasks of thread-efficient partial rendering: one per segment + one per 64 pixels
+    size_t mask_words = 0;   // pixel bit mask of a selection
+    bool want_plane = false; // a selection over views of one size: plane mask of the merged image
+    size_t plane_words = 0;
+};
+
+FwdSizes fwd_sizes(const mvgs_camera* cams, int B, size_t P, uint32_t n_tiles, uint32_t n_pixels, bool cap,
+                   const SelIn* sel) {
+    FwdSizes z;
+    z.B = B;
+    z.P = P;
+    z.n_tiles = n_tiles;
+    z.n_pixels = n_pixels;
+    z.cap = cap;
+    z.sel = sel;
+    z.task_cap = sel ? (size_t)n_tiles + sel->n_sel / 64 + 1 : 0;
+    z.mask_words = ((size_t)n_pixels + 31) / 32;
+    bool same_size = true;
+    for (int v = 1; v < B; ++v)
+        same_size = same_size && cams[v].width == cams[0].width && cams[v].height == cams[0].height;
+    z.plane_words = ((size_t)cams[0].width * cams[0].height + 31) / 32;
+    z.want_plane = sel && same_size;
+    return z;
+}
+
+constexpr int kMaxNeed = 24;
+
+// Buffers a forward grows before the participation pre-pass (sized by P, tiles, pixels).
+int fwd_needs_pre(mvgs_context* ctx, mvgs_frame* f, const FwdSizes& z, Need* n) {
+    const SelIn* sel = z.sel;
+    const size_t P = z.P;
+    int k = 0;
+    n[k++] = {&f->cams, sizeof(DevCam) * z.B};
+    n[k++] = {&ctx->nrec, sizeof(uint32_t) * (P + 1)};
+    n[k++] = {&ctx->ntiles, sizeof(uint32_t) * (P + 1)};
+    n[k++] = {&ctx->totals, sizeof(uint64_t) * 8};
+    n[k++] = {&f->dtot, z.cap ? (size_t)64 : (size_t)0};
+    n[k++] = {&f->rec_off, sizeof(uint32_t) * (P + 1)};
+    n[k++] = {&ctx->scan_scratch, scan_scratch_bytes(std::max<size_t>(P + 1, z.n_tiles))};
+    n[k++] = {&f->sel_off, sel ? sizeof(uint32_t) * ((size_t)z.n_tiles + 1) : 0};
+    n[k++] = {&f->sel_pix, sel ? sizeof(uint32_t) * std::max<size_t>(sel->n_sel, 1) : 0};
+    n[k++] = {&f->mask, sel ? sizeof(uint32_t) * z.mask_words : 0};
+    n[k++] = {&f->task_n, sel ? sizeof(uint32_t) * z.n_tiles : 0};
+    n[k++] = {&f->task_off, sel ? sizeof(uint32_t) * z.n_tiles : 0};
+    n[k++] = {&f->tasks, sel ? sizeof(uint2) * z.task_cap : 0};
+    n[k++] = {&f->plane_mask, z.want_plane ? sizeof(uint32_t) * z.plane_words : 0};
+    return k;
+}
+
+// Buffers a forward grows once it knows V records and K pairs (exact, or the capacities).
+int fwd_needs_post(mvgs_context* ctx, mvgs_frame* f, const FwdSizes& z, uint32_t V, uint32_t K, Need* n) {
+    const SelIn* sel = z.sel;
+    const size_t V1 = std::max<uint32_t>(V, 1), K1 = std::max<uint32_t>(K, 1);
+    // per-pixel blend state: every pixel, or every selected pixel in thread-efficient mode
+    const bool compact = sel && sel->mode == MVGS_PARTIAL_COMPACT;
+    const size_t n_px_state = compact ? sel->n_sel : z.n_pixels;
+    int k = 0;
+    n[k++] = {&f->recs, sizeof(BlendRec) * V1};
+    n[k++] = {&f->rec_view, sizeof(uint16_t) * V1};
+    n[k++] = {&ctx->depth_key[0], sizeof(uint32_t) * V1};
+    n[k++] = {&ctx->depth_key[1], sizeof(uint32_t) * V1};
+    n[k++] = {&ctx->rec_vals[0], sizeof(uint32_t) * V1};
+    n[k++] = {&ctx->rec_vals[1], sizeof(uint32_t) * V1};
+    n[k++] = {&ctx->tile_rect, sizeof(uint4) * V1};
+    n[k++] = {&ctx->sorted_rect, sizeof(uint4) * V1};
+    n[k++] = {&f->keys[0], sizeof(uint32_t) * K1};
+    n[k++] = {&f->keys[1], sizeof(uint32_t) * K1};
+    n[k++] = {&f->vals[0], sizeof(uint32_t) * K1};
+    n[k++] = {&f->vals[1], sizeof(uint32_t) * K1};
+    n[k++] = {&f->ranges, sizeof(uint2) * std::max<uint32_t>(z.n_tiles, 1)};
+    n[k++] = {&f->t_final, sizeof(float) * std::max<size_t>(n_px_state, 1)};
+    n[k++] = {&f->n_last, sizeof(uint32_t) * std::max<size_t>(n_px_state, 1)};
+    n[k++] = {&f->depth, compact ? sizeof(float) * std::max<size_t>(sel->n_sel, 1) : (size_t)0};
+    n[k++] = {&ctx->sort_scratch, std::max(radix_scratch_bytes(V), emit_sort_scratch_bytes(V, K))};
+    return k;
+}
+
+// Buffers of the loss and of the backward.
+int loss_needs(mvgs_context* ctx, int B, uint32_t n_pixels, uint32_t max_hw, bool dssim, Need* n) {
+    int k = 0;
+    n[k++] = {&ctx->loss_scratch, loss_scratch_bytes(n_pixels, B)};
+    if (dssim) n[k++] = {&ctx->ssim_maps, ssim_map_bytes(max_hw)};
+    return k;
+}
+int backward_needs(mvgs_context* ctx, uint32_t V, Need* n) {
+    n[0] = {&ctx->acc, sizeof(float) * kAccStride * std::max<uint32_t>(V, 1)};
+    return 1;
+}
+
 int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_camera* cams, int32_t B,
                  float* const* images, mvgs_frame** frame, const SelIn* sel) {
     if (!ctx) return MVGS_EINVAL;
@@ -629,29 +788,11 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     } while (0)
 
     const bool fresh_totals = !ctx->totals.p;
-    // tasks of thread-efficient partial rendering: at most one per segment plus one per 64 pixels
-    const size_t task_cap = sel ? (size_t)n_tiles + sel->n_sel / 64 + 1 : 0;
-    const size_t mask_words = ((size_t)n_pixels + 31) / 32;
-    bool same_size = true;
-    for (int v = 1; v < B; ++v)
-        same_size = same_size && cams[v].width == cams[0].width && cams[v].height == cams[0].height;
-    const size_t plane_words = ((size_t)cams[0].width * cams[0].height + 31) / 32;
-    const bool want_plane = sel && same_size;
-    const Need need1[] = {{&f->cams, sizeof(DevCam) * B},
-                          {&ctx->nrec, sizeof(uint32_t) * (P + 1)},
-                          {&ctx->ntiles, sizeof(uint32_t) * (P + 1)},
-                          {&ctx->totals, sizeof(uint64_t) * 8},
-                          {&f->dtot, cap ? (size_t)64 : (size_t)0},
-                          {&f->rec_off, sizeof(uint32_t) * (P + 1)},
-                          {&ctx->scan_scratch, scan_scratch_bytes(std::max<size_t>(P + 1, n_tiles))},
-                          {&f->sel_off, sel ? sizeof(uint32_t) * ((size_t)n_tiles + 1) : 0},
-                          {&f->sel_pix, sel ? sizeof(uint32_t) * std::max<size_t>(sel->n_sel, 1) : 0},
-                          {&f->mask, sel ? sizeof(uint32_t) * mask_words : 0},
-                          {&f->task_n, sel ? sizeof(uint32_t) * n_tiles : 0},
-                          {&f->task_off, sel ? sizeof(uint32_t) * n_tiles : 0},
-                          {&f->tasks, sel ? sizeof(uint2) * task_cap : 0},
-                          {&f->plane_mask, want_plane ? sizeof(uint32_t) * plane_words : 0}};
-    const int n_need1 = 14;
+    const FwdSizes z = fwd_sizes(cams, B, (size_t)g->P, n_tiles, n_pixels, cap, sel);
+    const size_t task_cap = z.task_cap, mask_words = z.mask_words, plane_words = z.plane_words;
+    const bool want_plane = z.want_plane;
+    Need need1[kMaxNeed];
+    const int n_need1 = fwd_needs_pre(ctx, f, z, need1);
     st = grow_all(ctx, need1, n_need1);
     if (st) return bail(st);
     if (fresh_totals) fill_u32(as<uint32_t>(ctx->totals), 16, 0u, s);
@@ -765,30 +906,9 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     // kernels read the actual counts from eff)
     const uint32_t V = (uint32_t)V64, K = (uint32_t)K64;
 
-    // records and the depth sort
-    const size_t V1 = std::max<uint32_t>(V, 1), K1 = std::max<uint32_t>(K, 1);
-    // per-pixel blend state: every pixel, or every selected pixel in thread-efficient mode
-    const size_t n_px_state = (sel && sel->mode == MVGS_PARTIAL_COMPACT) ? sel->n_sel : n_pixels;
-    const Need need2[] = {{&f->recs, sizeof(BlendRec) * V1},
-                          {&f->rec_view, sizeof(uint16_t) * V1},
-                          {&ctx->depth_key[0], sizeof(uint32_t) * V1},
-                          {&ctx->depth_key[1], sizeof(uint32_t) * V1},
-                          {&ctx->rec_vals[0], sizeof(uint32_t) * V1},
-                          {&ctx->rec_vals[1], sizeof(uint32_t) * V1},
-                          {&ctx->tile_rect, sizeof(uint4) * V1},
-                          {&ctx->sorted_rect, sizeof(uint4) * V1},
-                          {&f->keys[0], sizeof(uint32_t) * K1},
-                          {&f->keys[1], sizeof(uint32_t) * K1},
-                          {&f->vals[0], sizeof(uint32_t) * K1},
-                          {&f->vals[1], sizeof(uint32_t) * K1},
-                          {&f->ranges, sizeof(uint2) * std::max<uint32_t>(n_tiles, 1)},
-                          {&f->t_final, sizeof(float) * std::max<size_t>(n_px_state, 1)},
-                          {&f->n_last, sizeof(uint32_t) * std::max<size_t>(n_px_state, 1)},
-                          {&f->depth, (sel && sel->mode == MVGS_PARTIAL_COMPACT)
-                                          ? sizeof(float) * std::max<size_t>(sel->n_sel, 1) : (size_t)0},
-                          {&ctx->sort_scratch,
-                           std::max(radix_scratch_bytes(V), emit_sort_scratch_bytes(V, K))}};
-    const int n_need2 = (int)(sizeof(need2) / sizeof(need2[0]));
+    // records, sorts, ranges and per-pixel state
+    Need need2[kMaxNeed];
+    const int n_need2 = fwd_needs_post(ctx, f, z, V, K, need2);
     st = grow_all(ctx, need2, n_need2);
     if (st) {
         (void)ctx->ring.seal(s);
@@ -811,6 +931,8 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     // global tile id, then the other passes
     mk = ctx->stage_begin(3, s);
     const int tile_bits = bits_for(n_tiles);
+    f->depth_bits = depth_bits;
+    f->tile_bits = tile_bits;
     emit_pairs_first_pass(sorted_rec, as<uint4>(ctx->tile_rect), as<uint4>(ctx->sorted_rect), V, eff,
                           as<uint32_t>(f->keys[0]), as<uint32_t>(f->vals[0]), K, eff ? eff + 1 : nullptr, tile_bits,
                           ctx->sort_scratch.p, s);
@@ -848,7 +970,7 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     ctx->stage_end(mk, s);
     FCHK(hipGetLastError());
     FCHK(ctx->ring.seal(s));
-    *frame = f;
+    *frame = frame_handle(f);
     return MVGS_OK;
 #undef FCHK
 }
@@ -872,6 +994,108 @@ int mvgs_forward_partial(mvgs_context* ctx, void* stream, const mvgs_gaussians* 
     if (!sel_offsets || (n_sel > 0 && !sel_pixels)) return ctx->fail(MVGS_EINVAL, "selection array is NULL");
     const SelIn sel{sel_offsets, sel_pixels, (uint32_t)n_sel, mode};
     return forward_impl(ctx, stream, g, cams, B, images, frame, &sel);
+}
+
+int mvgs_count_views(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_camera* cams, int32_t B,
+                     int64_t* records, int64_t* pairs) {
+    if (!ctx) return MVGS_EINVAL;
+    int st = validate_gaussians(ctx, g);
+    if (st) return st;
+    uint32_t n_tiles = 0, n_pixels = 0;
+    st = validate_cams(ctx, cams, B, ctx->tw, ctx->th, &n_tiles, &n_pixels);
+    if (st) return st;
+    if (!records || !pairs) return ctx->fail(MVGS_EINVAL, "records or pairs is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (ctx->begin(s)) return ctx->fail(MVGS_EINVAL, "mvgs_count_views synchronizes and cannot be captured");
+    HIPCHK(ctx, ctx->bind_device());
+    const Need need[] = {{&ctx->view_counts, sizeof(unsigned long long) * 2 * (size_t)B}};
+    st = grow_all(ctx, need, 1);
+    if (st) return st;
+    std::vector<DevCam> hc;
+    build_cams(cams, B, ctx->tw, ctx->th, hc);
+    void* dcams = nullptr;
+    HIPCHK(ctx, ctx->ring.put(hc.data(), sizeof(DevCam) * B, s, &dcams));
+    unsigned long long* dc = as<unsigned long long>(ctx->view_counts);
+    fill_u32(reinterpret_cast<uint32_t*>(dc), 4 * (size_t)B, 0u, s);
+    launch_count_views(gargs(g), (const DevCam*)dcams, B, ctx->tw, ctx->th, dc, s);
+    LAUNCHCHK(ctx, "participation pre-pass");
+    std::vector<unsigned long long> hv(2 * (size_t)B);
+    HIPCHK(ctx, hipMemcpyAsync(hv.data(), dc, sizeof(unsigned long long) * 2 * (size_t)B, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, ctx->ring.seal(s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    for (int v = 0; v < B; ++v) {
+        records[v] = (int64_t)hv[2 * (size_t)v];
+        pairs[v] = (int64_t)hv[2 * (size_t)v + 1];
+    }
+    return MVGS_OK;
+}
+
+int mvgs_workspace_bound(mvgs_context* ctx, const mvgs_camera* cams, int32_t B, int64_t P, int64_t records,
+                         int64_t pairs, int32_t work, int64_t* bytes) {
+    if (!ctx) return MVGS_EINVAL;
+    if (!bytes) return ctx->fail(MVGS_EINVAL, "bytes is NULL");
+    uint32_t n_tiles = 0, n_pixels = 0;
+    int st = validate_cams(ctx, cams, B, ctx->tw, ctx->th, &n_tiles, &n_pixels);
+    if (st) return st;
+    if (P < 0 || P >= (1ll << 31)) return ctx->fail(MVGS_EINVAL, "P=%lld outside [0, 2^31)", (long long)P);
+    if (records < 0 || records > P * (int64_t)B || pairs < 0)
+        return ctx->fail(MVGS_EINVAL, "records %lld or pairs %lld impossible for %lld Gaussians and %d views",
+                         (long long)records, (long long)pairs, (long long)P, B);
+    if (work & ~(MVGS_WORK_LOSS | MVGS_WORK_LOSS_DSSIM | MVGS_WORK_BACKWARD))
+        return ctx->fail(MVGS_EINVAL, "unknown work flags 0x%x", work);
+    const bool cap = ctx->cap_v > 0;
+    if (!cap && (records >= (1ll << 32) || pairs >= (1ll << 32)))
+        return ctx->fail(MVGS_ECAPACITY, "records %lld or pairs %lld reach 2^32", (long long)records, (long long)pairs);
+    const uint32_t V = cap ? (uint32_t)ctx->cap_v : (uint32_t)records;
+    const uint32_t K = cap ? (uint32_t)ctx->cap_k : (uint32_t)pairs;
+    // the frame the forward would take: the first free one of the pool, else a new (empty) one
+    mvgs_frame fresh;
+    mvgs_frame* f = &fresh;
+    for (mvgs_frame* q : ctx->frames)
+        if (!q->in_use) {
+            f = q;
+            break;
+        }
+    // replay the calls' growth in order on simulated capacities
+    std::vector<std::pair<const DevBuf*, size_t>> caps;
+    size_t held = ctx->held();
+    auto grow = [&](const DevBuf* b, size_t want) {
+        if (!want) return;
+        size_t c = b->p ? b->cap : 0;
+        auto it = std::find_if(caps.begin(), caps.end(), [&](const std::pair<const DevBuf*, size_t>& e) {
+            return e.first == b;
+        });
+        if (it != caps.end()) c = it->second;
+        const size_t n = grown_capacity(c, want);
+        if (n == c) return;
+        held += n - c;
+        if (it != caps.end()) it->second = n;
+        else caps.emplace_back(b, n);
+    };
+    auto grow_list = [&](const Need* n, int k) {
+        for (int i = 0; i < k; ++i) grow(n[i].buf, n[i].bytes);
+    };
+    int ring_next = ctx->ring.next;
+    auto ring_put = [&](size_t b) { grow(&ctx->ring.slots[ring_next].dev, b); ring_next = (ring_next + 1) % UploadRing::kSlots; };
+    if (!ctx->device_used) grow(&ctx->adam_state, 256);
+    const FwdSizes z = fwd_sizes(cams, B, (size_t)P, n_tiles, n_pixels, cap, nullptr);
+    Need n[kMaxNeed];
+    grow_list(n, fwd_needs_pre(ctx, f, z, n));
+    ring_put(sizeof(DevCam) * B);
+    ring_put(sizeof(float*) * B);
+    grow_list(n, fwd_needs_post(ctx, f, z, V, K, n));
+    if (work & (MVGS_WORK_LOSS | MVGS_WORK_LOSS_DSSIM)) {
+        uint32_t max_hw = 0;
+        for (int v = 0; v < B; ++v) max_hw = std::max(max_hw, (uint32_t)(cams[v].width * cams[v].height));
+        grow_list(n, loss_needs(ctx, B, n_pixels, max_hw, (work & MVGS_WORK_LOSS_DSSIM) != 0, n));
+        ring_put(sizeof(LossView) * B);
+    }
+    if (work & MVGS_WORK_BACKWARD) {
+        grow_list(n, backward_needs(ctx, V, n));
+        ring_put(sizeof(float*) * B);
+    }
+    *bytes = (int64_t)held;
+    return MVGS_OK;
 }
 
 int mvgs_subsample(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t B, const uint32_t* keys,
@@ -924,9 +1148,8 @@ int mvgs_loss(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t 
     if (ctx->begin(s) && !ctx->device_used)
         return ctx->fail(MVGS_EINVAL, "make the call once before capturing it");
     HIPCHK(ctx, ctx->bind_device());
-    const Need need[] = {{&ctx->loss_scratch, loss_scratch_bytes(n_pixels, B)},
-                         {&ctx->ssim_maps, w_dssim != 0.0f ? ssim_map_bytes(max_hw) : 0}};
-    st = grow_all(ctx, need, w_dssim != 0.0f ? 2 : 1);
+    Need need[2];
+    st = grow_all(ctx, need, loss_needs(ctx, B, n_pixels, max_hw, w_dssim != 0.0f, need));
     if (st) return st;
     void* dviews = nullptr;
     HIPCHK(ctx, ctx->ring.put(lv.data(), sizeof(LossView) * B, s, &dviews, ctx->capturing));
@@ -1047,19 +1270,21 @@ int mvgs_gather_rows(mvgs_context* ctx, void* stream, const int32_t* src, int64_
     return MVGS_OK;
 }
 
-int mvgs_grad_moments(mvgs_context* ctx, void* stream, int64_t P, int32_t sh_degree, const mvgs_grads* grads,
-                      double* sum, double* acc) {
-    if (!ctx) return MVGS_EINVAL;
+}  // extern "C"
+
+namespace {
+
+int check_moment_args(mvgs_context* ctx, int64_t P, int32_t sh_degree, const mvgs_grads* grads, const double* sum,
+                      const double* acc) {
     if (P < 0 || P >= (1ll << 31)) return ctx->fail(MVGS_EINVAL, "P=%lld outside [0, 2^31)", (long long)P);
     if (sh_degree < 0 || sh_degree > 3) return ctx->fail(MVGS_EINVAL, "sh_degree=%d outside [0, 3]", sh_degree);
     if (!grads_present(grads, P) || !acc || (P > 0 && !sum))
         return ctx->fail(MVGS_EINVAL, "grads, sum or acc is NULL");
-    HIPCHK(ctx, ctx->bind_device());
-    hipStream_t s = (hipStream_t)stream;
-    ctx->begin(s);
-    const Need need[] = {{&ctx->moment_partials, sizeof(double) * 2 * kMomentBlocks}};
-    int st = grow_all(ctx, need, 1);
-    if (st) return st;
+    return MVGS_OK;
+}
+
+// the five gradient tensors as one vector: means | scales | quats | opacities | SH
+GradSegments moment_segments(int64_t P, int32_t sh_degree, const mvgs_grads* grads) {
     const int64_t K = (int64_t)(sh_degree + 1) * (sh_degree + 1);
     GradSegments gs;
     const float* seg[5] = {grads->means, grads->scales, grads->quats, grads->opacities, grads->sh};
@@ -1070,13 +1295,32 @@ int mvgs_grad_moments(mvgs_context* ctx, void* stream, int64_t P, int32_t sh_deg
         at += P * width[k];
         gs.end[k] = at;
     }
-    launch_grad_moments(gs, sum, acc, as<double>(ctx->moment_partials), s);
+    return gs;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mvgs_grad_moments(mvgs_context* ctx, void* stream, int64_t P, int32_t sh_degree, const mvgs_grads* grads,
+                      double* sum, double* acc) {
+    if (!ctx) return MVGS_EINVAL;
+    int st = check_moment_args(ctx, P, sh_degree, grads, sum, acc);
+    if (st) return st;
+    HIPCHK(ctx, ctx->bind_device());
+    hipStream_t s = (hipStream_t)stream;
+    ctx->begin(s);
+    const Need need[] = {{&ctx->moment_partials, sizeof(double) * 2 * kMomentBlocks}};
+    st = grow_all(ctx, need, 1);
+    if (st) return st;
+    launch_grad_moments(moment_segments(P, sh_degree, grads), sum, acc, as<double>(ctx->moment_partials), s);
     LAUNCHCHK(ctx, "gradient moments");
     return MVGS_OK;
 }
 
 int mvgs_loss_3d(mvgs_context* ctx, void* stream, const mvgs_frame* frame, const float* image, const float* target,
                  float w_l1, float w_dssim, float* loss_dev, float* dl_dimage) {
+    frame = frame_of(frame);   // NULL for a released or stale handle
     if (!ctx) return MVGS_EINVAL;
     if (!frame || frame->ctx != ctx || !frame->in_use) return ctx->fail(MVGS_EINVAL, "frame is not live on this context");
     if (frame->mode != MVGS_PARTIAL_COMPACT || !frame->partition)
@@ -1101,6 +1345,7 @@ int mvgs_loss_3d(mvgs_context* ctx, void* stream, const mvgs_frame* frame, const
 }
 
 int mvgs_export_depth(mvgs_context* ctx, void* stream, const mvgs_frame* frame, float* const* depth) {
+    frame = frame_of(frame);   // NULL for a released or stale handle
     if (!ctx || !frame || frame->ctx != ctx || !frame->in_use || !depth) return MVGS_EINVAL;
     if (frame->mode != MVGS_PARTIAL_COMPACT)
         return ctx->fail(MVGS_EINVAL, "depth is rendered by thread-efficient partial frames only");
@@ -1120,6 +1365,7 @@ int mvgs_export_depth(mvgs_context* ctx, void* stream, const mvgs_frame* frame, 
 
 int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const mvgs_frame* frame,
                   const float* const* dl_dimages, mvgs_grads* grads, mvgs_densify* densify) {
+    frame = frame_of(frame);   // NULL for a released or stale handle
     if (!ctx) return MVGS_EINVAL;
     int st = validate_gaussians(ctx, g);
     if (st) return st;
@@ -1140,8 +1386,8 @@ int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, cons
     const uint32_t V = f->capacity ? (uint32_t)ctx->cap_v : f->V;
     const uint32_t* eff = frame_eff(f);
     const uint32_t* ovf = frame_void(f);
-    const Need need[] = {{&ctx->acc, sizeof(float) * kAccStride * std::max<uint32_t>(V, 1)}};
-    st = grow_all(ctx, need, 1);
+    Need need[1];
+    st = grow_all(ctx, need, backward_needs(ctx, V, need));
     if (st) return st;
     fill_u32_count(as<uint32_t>(ctx->acc), V, eff, kAccStride, 0u, s);
     void* dptrs = nullptr;
@@ -1189,8 +1435,10 @@ int mvgs_backward(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, cons
 }
 
 int mvgs_frame_release(mvgs_context* ctx, mvgs_frame* frame) {
+    frame = frame_of(frame);   // NULL for a released or stale handle
     if (!ctx || !frame || frame->ctx != ctx) return MVGS_EINVAL;
     frame->in_use = false;
+    ++frame->gen;
     return MVGS_OK;
 }
 
@@ -1207,12 +1455,14 @@ int mvgs_memory_held(mvgs_context* ctx, int64_t* bytes) {
 }
 
 int mvgs_frame_workspace(const mvgs_frame* frame, int64_t* bytes) {
+    frame = frame_of(frame);   // NULL for a released or stale handle
     if (!frame || !bytes) return MVGS_EINVAL;
     *bytes = (int64_t)frame->need_bytes;
     return MVGS_OK;
 }
 
 int mvgs_frame_check(mvgs_context* ctx, void* stream, mvgs_frame* frame) {
+    frame = frame_of(frame);   // NULL for a released or stale handle
     if (!ctx || !frame || frame->ctx != ctx || !frame->in_use) return MVGS_EINVAL;
     if (!frame->capacity) return MVGS_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -1274,12 +1524,14 @@ int mvgs_frame_check(mvgs_context* ctx, void* stream, mvgs_frame* frame) {
 }
 
 int mvgs_frame_void_word(const mvgs_frame* frame, const uint32_t** word) {
+    frame = frame_of(frame);   // NULL for a released or stale handle
     if (!frame || !word || !frame->in_use) return MVGS_EINVAL;
     *word = frame_void(frame);
     return MVGS_OK;
 }
 
 int mvgs_frame_set_cameras(mvgs_context* ctx, mvgs_frame* frame, const mvgs_camera* cams, int32_t B) {
+    frame = frame_of(frame);   // NULL for a released or stale handle
     if (!ctx || !frame || frame->ctx != ctx || !frame->in_use) return MVGS_EINVAL;
     if (!frame->cam_stage) return ctx->fail(MVGS_EINVAL, "the frame was not made under stream capture");
     if (!cams || B != frame->B) return ctx->fail(MVGS_EINVAL, "expected %d cameras", frame->B);
@@ -1295,6 +1547,7 @@ int mvgs_frame_set_cameras(mvgs_context* ctx, mvgs_frame* frame, const mvgs_came
 }
 
 int mvgs_frame_info(const mvgs_frame* frame, int64_t* n_records, int64_t* n_pairs, int64_t* n_tiles) {
+    frame = frame_of(frame);   // NULL for a released or stale handle
     if (!frame) return MVGS_EINVAL;
     if (n_records) *n_records = frame->V;
     if (n_pairs) *n_pairs = (int64_t)frame->K;
@@ -1302,8 +1555,22 @@ int mvgs_frame_info(const mvgs_frame* frame, int64_t* n_records, int64_t* n_pair
     return MVGS_OK;
 }
 
+int mvgs_frame_sort_info(const mvgs_frame* frame, int32_t* depth_passes, int32_t* tile_passes) {
+    frame = frame_of(frame);   // NULL for a released or stale handle
+    if (!frame) return MVGS_EINVAL;
+    // passes of ceil(bits / 8) even digits (k_sort.hip), none for an empty sort
+    auto passes = [](int bits, bool empty) { return empty || bits <= 0 ? 0 : std::max(1, (bits + 7) / 8); };
+    const bool cap = frame->capacity;
+    const bool no_rec = cap ? frame->ctx->cap_v == 0 : frame->V == 0;
+    const bool no_pair = cap ? frame->ctx->cap_k == 0 : frame->K == 0;
+    if (depth_passes) *depth_passes = passes(frame->depth_bits, no_rec);
+    if (tile_passes) *tile_passes = passes(frame->tile_bits, no_rec || no_pair);
+    return MVGS_OK;
+}
+
 int mvgs_export_binning(mvgs_context* ctx, void* stream, const mvgs_frame* frame, uint64_t* keys, uint32_t* values,
                         uint32_t* ranges) {
+    frame = frame_of(frame);   // NULL for a released or stale handle
     if (!ctx || !frame || frame->ctx != ctx || !frame->in_use) return MVGS_EINVAL;
     if (!frame->checked) return ctx->fail(MVGS_EINVAL, "call mvgs_frame_check on a capacity-mode frame first");
     hipStream_t s = (hipStream_t)stream;
@@ -1318,6 +1585,7 @@ int mvgs_export_binning(mvgs_context* ctx, void* stream, const mvgs_frame* frame
 }
 
 int mvgs_export_transmittance(mvgs_context* ctx, void* stream, const mvgs_frame* frame, float* const* t_final) {
+    frame = frame_of(frame);   // NULL for a released or stale handle
     if (!ctx || !frame || frame->ctx != ctx || !frame->in_use || !t_final) return MVGS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     mvgs_frame* f = const_cast<mvgs_frame*>(frame);
@@ -1343,6 +1611,7 @@ int mvgs_export_transmittance(mvgs_context* ctx, void* stream, const mvgs_frame*
 
 int mvgs_frame_merge(mvgs_context* ctx, void* stream, const mvgs_frame* frame, const float* const* planes,
                      int32_t channels, float* out) {
+    frame = frame_of(frame);   // NULL for a released or stale handle
     if (!ctx) return MVGS_EINVAL;
     if (!frame || frame->ctx != ctx || !frame->in_use) return ctx->fail(MVGS_EINVAL, "not a live frame");
     mvgs_frame* f = const_cast<mvgs_frame*>(frame);
@@ -1409,6 +1678,7 @@ int mvgs_profile_reset(mvgs_context* ctx) {
 }
 
 int mvgs_frame_work(mvgs_context* ctx, void* stream, const mvgs_frame* frame, uint64_t* work_dev) {
+    frame = frame_of(frame);   // NULL for a released or stale handle
     if (!ctx || !frame || frame->ctx != ctx || !frame->in_use || !work_dev) return MVGS_EINVAL;
     mvgs_frame* f = const_cast<mvgs_frame*>(frame);
     if (f->mode == MVGS_PARTIAL_COMPACT)

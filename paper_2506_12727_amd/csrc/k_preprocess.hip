@@ -69,6 +69,42 @@ __global__ void __launch_bounds__(256) k_count(const float* __restrict__ means, 
     }
 }
 
+// Participation pre-pass per view, for admission before anything is sized: the records (1 per
+// participating Gaussian) and covered tiles of each view, summed over the Gaussians. One thread per
+// Gaussian walks the views; per view a wavefront sum, then one 64-bit atomic per wavefront and
+// count (counts[2v] records, counts[2v+1] pairs).
+__global__ void __launch_bounds__(256) k_count_views(const float* __restrict__ means,
+                                                     const float* __restrict__ scales,
+                                                     const float* __restrict__ quats,
+                                                     const float* __restrict__ opac, int64_t P,
+                                                     const DevCam* __restrict__ cams, int B, int tile_w, int tile_h,
+                                                     unsigned long long* __restrict__ counts) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = g < P;
+    float mu[3] = {0.f, 0.f, 0.f}, s[3] = {0.f, 0.f, 0.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, o = 0.f;
+    if (live) load_gaussian(means, scales, quats, opac, g, mu, s, q, o);
+    for (int v = 0; v < B; ++v) {
+        uint32_t n = 0, nt = 0;
+        if (live) {
+            ProjState st;
+            const ProjOut p = project(mu, s, q, o, cams[v], st);
+            if (p.ok) {
+                n = 1;
+                nt = (uint32_t)((p.x1 / tile_w - p.x0 / tile_w + 1) * (p.y1 / tile_h - p.y0 / tile_h + 1));
+            }
+        }
+        // at most 64 x 65,536 tiles per wavefront: the sums fit 32 bits
+        for (int off = 32; off > 0; off >>= 1) {
+            n += (uint32_t)__shfl_xor((int)n, off, 64);
+            nt += (uint32_t)__shfl_xor((int)nt, off, 64);
+        }
+        if ((threadIdx.x & 63) == 0 && n) {
+            atomicAdd(counts + 2 * v, (unsigned long long)n);
+            atomicAdd(counts + 2 * v + 1, (unsigned long long)nt);
+        }
+    }
+}
+
 // The per-record arrays beside the record itself: view, depth key and covered-tile rectangle
 // (first global tile id, width | height << 16, the view's tiles per row).
 __device__ __forceinline__ void record_side(const BlendRec& r, const DevCam* __restrict__ cams, int tile_w,
@@ -343,6 +379,14 @@ void launch_count(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int
     if (!blocks) return;
     hipLaunchKernelGGL(k_count, dim3(blocks), dim3(256), 0, s, ga.means, ga.scales, ga.quats, ga.opac, ga.P, cams,
                        B, tw, th, nrec, ntiles, key_range);
+}
+
+void launch_count_views(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th,
+                        unsigned long long* counts, hipStream_t s) {
+    const unsigned blocks = (unsigned)((ga.P + 255) / 256);
+    if (!blocks) return;
+    hipLaunchKernelGGL(k_count_views, dim3(blocks), dim3(256), 0, s, ga.means, ga.scales, ga.quats, ga.opac, ga.P,
+                       cams, B, tw, th, counts);
 }
 
 void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,

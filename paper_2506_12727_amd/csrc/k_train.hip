@@ -178,9 +178,13 @@ void launch_gather_rows(const int32_t* src, int64_t n, int64_t width, const floa
         hipLaunchKernelGGL(k_gather_rows<uint64_t>, grid, dim3(256), 0, s, src, n, width, in, out);
 }
 
+size_t moment_blocks(int64_t n) {
+    return (size_t)std::max<int64_t>(1, std::min<int64_t>((n + 2047) / 2048, kMomentBlocks));
+}
+
 void launch_grad_moments(const GradSegments& g, double* sum, double* acc, double* partials, hipStream_t s) {
     const int64_t n = g.end[4];
-    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 2047) / 2048, kMomentBlocks));
+    const int blocks = (int)moment_blocks(n);
     if (n) hipLaunchKernelGGL(k_grad_moments, dim3((unsigned)blocks), dim3(256), 0, s, g, sum, partials);
     hipLaunchKernelGGL(k_grad_moments_final, dim3(1), dim3(256), 0, s, partials, n ? blocks : 0, acc);
 }

@@ -35,6 +35,9 @@ struct GradArgs {
 void launch_count(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, uint32_t* nrec,
                   uint32_t* ntiles, hipStream_t s, uint32_t* key_range = nullptr);
 // overflow: null, or a device word that, when non-zero, makes the kernel write nothing
+// per-view participating records and covered tiles (counts [B][2], accumulated with +=)
+void launch_count_views(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th,
+                        unsigned long long* counts, hipStream_t s);
 void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,
                     BlendRec* recs, uint32_t* depth_key, uint4* tile_rect, uint16_t* rec_view, hipStream_t s,
                     const uint32_t* overflow = nullptr);
@@ -205,6 +208,7 @@ struct GradSegments {
     int64_t end[5];
 };
 constexpr int kMomentBlocks = 1024;   // workgroups of the moment pass (2 double partials each)
+size_t moment_blocks(int64_t n);       // workgroups the moment pass uses for n elements
 void launch_grad_moments(const GradSegments& g, double* sum, double* acc, double* partials, hipStream_t s);
 
 // k_loss3d.hip: L1 + 3D distance-aware D-SSIM on the merged plane of a thread-efficient partial

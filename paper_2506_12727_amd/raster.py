@@ -98,17 +98,52 @@ class Frame:
     def info(self):
         V, K, T = C.c_int64(), C.c_int64(), C.c_int64()
         L.check(L.lib().mvgs_frame_info(self.handle, C.byref(V), C.byref(K), C.byref(T)))
-        return dict(records=V.value, pairs=K.value, tiles=T.value)
+        dp, tp = C.c_int32(), C.c_int32()
+        L.check(L.lib().mvgs_frame_sort_info(self.handle, C.byref(dp), C.byref(tp)))
+        return dict(records=V.value, pairs=K.value, tiles=T.value, depth_passes=dp.value, tile_passes=tp.value)
 
     def release(self):
         if not self.released:
             self.rast.release(self)
 
+    def __del__(self):
+        # a frame dropped without release (e.g. an autograd graph freed before its backward)
+        # returns its memory to the context, if the context still exists
+        try:
+            if not self.released and self.rast.ctx:
+                self.rast.release(self)
+        except Exception:
+            pass
+
+
+class TorchAllocator:
+    """Device memory of a library context from PyTorch's caching allocator (mvgs_options.alloc /
+    free): blocks are taken on the calling thread's current stream, which is the stream of the
+    library call that asks for them, and given back to the cache in that stream's order."""
+
+    def __init__(self, device=None):
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.alloc_fn = L.ALLOC_FN(self._alloc)
+        self.free_fn = L.FREE_FN(self._free)
+
+    def _alloc(self, nbytes, _ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), self.device)
+        except Exception:   # out of memory: the library returns MVGS_ENOMEM
+            return None
+
+    def _free(self, ptr, _ctx):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:
+            pass
+
 
 class Rasterizer:
-    def __init__(self, tile=(16, 16), pixels_per_lane=0, workspace_limit=0, capacity=None):
+    def __init__(self, tile=(16, 16), pixels_per_lane=0, workspace_limit=0, capacity=None, torch_allocator=True):
         """capacity: None, or (records, pairs) for capacity mode (no host synchronization in the
-        forward; capturable into a HIP graph)."""
+        forward; capturable into a HIP graph). torch_allocator: the context's workspace and frames
+        come from PyTorch's caching allocator (else hipMalloc)."""
         self.lib = L.lib()
         opt = L.mvgs_options()
         opt.tile_w, opt.tile_h = int(tile[0]), int(tile[1])
@@ -116,10 +151,33 @@ class Rasterizer:
         opt.workspace_limit = int(workspace_limit)
         if capacity is not None:
             opt.capacity_records, opt.capacity_pairs = int(capacity[0]), int(capacity[1])
+        self.allocator = TorchAllocator() if torch_allocator else None
+        if self.allocator is not None:
+            opt.alloc, opt.free = self.allocator.alloc_fn, self.allocator.free_fn
         self.capacity = capacity
         self.ctx = C.c_void_p()
         L.check(self.lib.mvgs_create(C.byref(self.ctx), C.byref(opt)))
         self.tile = (opt.tile_w, opt.tile_h)
+
+    def count_views(self, g: GaussianTensors, cams):
+        """Participation pre-pass: per view, (participating Gaussians, covered (Gaussian, tile)
+        pairs) as int64 arrays; one synchronization of the current stream."""
+        import numpy as np
+        g.check()
+        B = len(cams)
+        rec = np.zeros(B, np.int64)
+        pairs = np.zeros(B, np.int64)
+        L.check(self.lib.mvgs_count_views(self.ctx, _stream(), C.byref(self._gauss(g)), L.camera_array(cams), B,
+                                          rec.ctypes.data, pairs.ctypes.data), self.ctx)
+        return rec, pairs
+
+    def workspace_bound(self, cams, P: int, records: int, pairs: int, work: int = L.MVGS_WORK_FORWARD) -> int:
+        """Device bytes this context would hold after a forward of `cams` (with the loss and backward
+        of `work`) whose views count `records` and `pairs` in total (host only)."""
+        b = C.c_int64()
+        L.check(self.lib.mvgs_workspace_bound(self.ctx, L.camera_array(cams), len(cams), int(P), int(records),
+                                              int(pairs), int(work), C.byref(b)), self.ctx)
+        return int(b.value)
 
     def set_workspace_limit(self, nbytes: int):
         """Most device bytes this context may hold from now on (0: no limit)."""
@@ -210,6 +268,8 @@ class Rasterizer:
     def backward(self, g: GaussianTensors, frame: Frame, dl_dimages, densify=None, grads=None):
         """Parameter gradients (overwritten) and, if `densify` = dict(e1, e2, count) tensors, the
         densification statistics (accumulated)."""
+        if frame.released:
+            raise ValueError("the frame was released: render again for another backward")
         g.check()
         if grads is None:
             grads = dict(means=torch.empty_like(g.means), scales=torch.empty_like(g.scales),
@@ -389,31 +449,53 @@ class MVGSRasterize(torch.autograd.Function):
     """images = rasterize(means, scales, quats, opacities, sh) for a fixed camera batch.
 
     The backward recomputes blend state from the frame's final transmittance and last contributor;
-    if `densify` (dict of e1, e2, count tensors) is given, the statistics are accumulated into it."""
+    if `densify` (dict of e1, e2, count tensors) is given, the statistics are accumulated into it.
+    Frame lifetime: a forward that no backward can follow (grad mode off, or no parameter requires
+    grad) releases its frame at once; otherwise the backward releases it, so one forward takes one
+    backward (a second raises), and a graph freed without a backward releases it when the frame
+    object is collected. A capacity-mode forward outside graph capture is checked (an overflow
+    raises instead of giving background images and zero gradients)."""
 
     @staticmethod
-    def forward(ctx, rast: Rasterizer, cams, sh_degree: int, densify, means, scales, quats, opacities, sh):
+    def forward(ctx, rast: Rasterizer, cams, sh_degree: int, densify, keep: bool, means, scales, quats, opacities,
+                sh):
         g = GaussianTensors(means.contiguous(), scales.contiguous(), quats.contiguous(), opacities.contiguous(),
                             sh.contiguous(), sh_degree)
         images, frame = rast.forward(g, cams)
+        if rast.capacity is not None and not torch.cuda.is_current_stream_capturing():
+            try:
+                frame.check()
+            except Exception:
+                rast.release(frame)
+                raise
+        if not keep:
+            rast.release(frame)
         ctx.rast, ctx.frame, ctx.sh_degree, ctx.densify = rast, frame, sh_degree, densify
         ctx.save_for_backward(g.means, g.scales, g.quats, g.opacities, g.sh)
         return tuple(images)
 
     @staticmethod
     def backward(ctx, *grad_images):
+        if ctx.frame.released:
+            raise RuntimeError("rasterize: this forward's frame was already released (its backward ran once, or "
+                               "it was rendered without grad); render again for another backward")
         means, scales, quats, opacities, sh = ctx.saved_tensors
         g = GaussianTensors(means, scales, quats, opacities, sh, ctx.sh_degree)
-        dl = [gi if gi is not None else torch.zeros((3, c.height, c.width), device=means.device)
+        dl = [gi.contiguous() if gi is not None else torch.zeros((3, c.height, c.width), device=means.device)
               for gi, c in zip(grad_images, ctx.frame.cams)]
-        grads = ctx.rast.backward(g, ctx.frame, dl, densify=ctx.densify)
-        ctx.rast.release(ctx.frame)
-        return (None, None, None, None, grads["means"], grads["scales"], grads["quats"], grads["opacities"],
+        try:
+            grads = ctx.rast.backward(g, ctx.frame, dl, densify=ctx.densify)
+        finally:
+            ctx.rast.release(ctx.frame)
+        return (None, None, None, None, None, grads["means"], grads["scales"], grads["quats"], grads["opacities"],
                 grads["sh"])
 
 
 def rasterize(rast: Rasterizer, cams, g: GaussianTensors, densify=None):
-    return MVGSRasterize.apply(rast, cams, g.sh_degree, densify, g.means, g.scales, g.quats, g.opacities, g.sh)
+    """Differentiable render of every view of `cams`: a tuple of [3,H,W] images."""
+    params = (g.means, g.scales, g.quats, g.opacities, g.sh)
+    keep = torch.is_grad_enabled() and any(t.requires_grad for t in params)
+    return MVGSRasterize.apply(rast, cams, g.sh_degree, densify, keep, *params)
 
 
 class FusedLoss(torch.autograd.Function):

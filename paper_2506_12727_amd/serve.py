@@ -8,12 +8,14 @@ overlap on the device. Every view of a batch is rendered by one forward call (mu
 of the multi-view appendix); a view's image does not depend on what else is in its batch.
 
 Admission (class Admission) keeps the server's per-request device memory under a byte budget:
-the workspace every slot context holds plus the output images of requests in flight. A batch is
-the longest prefix of the queue (in arrival order, at most `max_batch` views) whose estimated
-workspace and images fit in what the budget leaves; the slot's context gets that reservation as
-its workspace limit, which the library enforces before it allocates. A batch the library refuses
-goes back to the head of the queue with a larger estimate. The per-pixel workspace estimate
-learns from the exact workspace each finished batch reports.
+the memory every slot context holds plus the output images of requests in flight. As the
+multi-view appendix sizes memory from the participating Gaussians before allocating, every queued
+request gets its participation counts (records and covered tile pairs, mvgs_count_views, one
+pre-pass over the waiting requests at a time), and a batch's memory is the exact bound the library
+computes from them for the slot's context (mvgs_workspace_bound). A batch is the longest prefix of
+the queue (in arrival order, at most `max_batch` views) whose bound and images fit in what the
+budget leaves; the slot's context gets that bound as its workspace limit, which the library
+enforces before it allocates, and which the forward then cannot exceed.
 """
 from __future__ import annotations
 
@@ -22,7 +24,7 @@ import threading
 import time
 from collections import deque
 from dataclasses import dataclass
-from typing import List, Optional, Sequence
+from typing import Callable, List, Optional, Sequence
 
 import numpy as np
 
@@ -40,6 +42,8 @@ class Request:
     batch: int = -1
     image: Optional[object] = None  # [3,H,W] float32 on the GPU when images are kept
     error: Optional[str] = None
+    records: int = -1               # participation pre-pass: participating Gaussians (-1: not counted)
+    pairs: int = -1                 # and covered (Gaussian, tile) pairs
 
     @property
     def pixels(self) -> int:
@@ -53,92 +57,59 @@ class Request:
 class Admission:
     """Byte accounting and batch formation against the budget (host logic only).
 
-    held[s]      bytes slot s's context holds (its buffers only grow until the slot is recycled)
-    reserved[s]  what slot s may hold while it runs a batch (>= held[s]); == held[s] when idle
-    images       bytes of output images of requests in flight
+    bound(slot, reqs)  bytes slot `slot`'s context would hold after rendering `reqs` as one batch
+    held[s]            bytes slot s's context holds (its buffers only grow until it is recycled)
+    reserved[s]        what slot s may hold while it runs a batch (>= held[s]); == held[s] when idle
+    images             bytes of output images of requests in flight
     """
 
-    def __init__(self, budget: int, n_slots: int, max_batch: int, fixed_bytes: int = 0, view_bytes: int = 0,
-                 bytes_per_pixel: float = 256.0, slack: float = 1.3, miss_growth: float = 1.5):
+    def __init__(self, budget: int, n_slots: int, max_batch: int, bound: Callable[[int, Sequence[Request]], int]):
         if budget <= 0 or n_slots < 1 or max_batch < 1:
             raise ValueError("budget, n_slots and max_batch must be positive")
         self.budget = int(budget)
         self.max_batch = int(max_batch)
-        self.fixed = int(fixed_bytes)
-        self.view_bytes = int(view_bytes)
-        self.bpp = float(bytes_per_pixel)
-        self.slack = float(slack)            # the context's allocator grows buffers with headroom
-        self.miss_growth = float(miss_growth)
+        self.bound = bound
         self.held = [0] * n_slots
         self.reserved = [0] * n_slots
         self.images = 0
         self.peak = 0
         self.misses = 0
-        self.gen = 0                        # bumped whenever the estimate is raised after a refusal
-        self.taken_gen = [0] * n_slots      # estimate generation each slot's batch was admitted with
 
     def used(self) -> int:
         return sum(self.reserved) + self.images
-
-    def workspace_estimate(self, views: int, pixels: int) -> int:
-        """Workspace of a batch: a part per batch, a bound per view (records, one per Gaussian that
-        takes part, at most P) and a learned part per pixel (pairs and per-pixel blend state)."""
-        return int(self.fixed + self.view_bytes * views + self.bpp * pixels)
-
-    def _need(self, slot: int, views: int, pixels: int, image_bytes: int) -> int:
-        return max(self.held[slot], int(self.slack * self.workspace_estimate(views, pixels))) + image_bytes
-
-    def fits_alone(self, req: Request) -> bool:
-        """Whether the request could run with every other slot empty."""
-        return int(self.slack * self.workspace_estimate(1, req.pixels)) + req.image_bytes <= self.budget
 
     def take(self, slot: int, queue: deque) -> List[Request]:
         """Pop the longest admissible prefix of `queue` for an idle `slot` and reserve its memory.
         Returns [] when not even the head fits."""
         avail = self.budget - (self.used() - self.reserved[slot])
-        n = pix = img = 0
-        for r in queue:
-            if n == self.max_batch or self._need(slot, n + 1, pix + r.pixels, img + r.image_bytes) > avail:
+        n = img = 0
+        need = 0
+        items = list(queue)[:self.max_batch]
+        for k in range(1, len(items) + 1):
+            img_k = img + items[k - 1].image_bytes
+            need_k = max(self.held[slot], int(self.bound(slot, items[:k])))
+            if need_k + img_k > avail:
                 break
-            n += 1
-            pix += r.pixels
-            img += r.image_bytes
+            n, img, need = k, img_k, need_k
         if n == 0:
             return []
         batch = [queue.popleft() for _ in range(n)]
-        self.taken_gen[slot] = self.gen
-        self.reserved[slot] = max(self.held[slot], int(self.slack * self.workspace_estimate(n, pix)))
+        self.reserved[slot] = need
         self.images += img
         self.peak = max(self.peak, self.used())
         return batch
 
-    def take_forced(self, slot: int, queue: deque) -> List[Request]:
-        """The head alone, reserving everything the budget has left (used when every slot is idle
-        and holds nothing, yet the estimate says the head does not fit: the library decides)."""
-        r = queue.popleft()
-        self.taken_gen[slot] = self.gen
-        self.reserved[slot] = max(self.held[slot], self.budget - (self.used() - self.reserved[slot]) - r.image_bytes)
-        self.images += r.image_bytes
-        self.peak = max(self.peak, self.used())
-        return [r]
-
-    def finish(self, slot: int, batch: Sequence[Request], held_after: int, workspace: Optional[int]):
-        """The batch is done: its images leave the in-flight count (the caller owns them now), the
-        reservation falls back to what the context holds, and the estimate learns."""
+    def finish(self, slot: int, batch: Sequence[Request], held_after: int):
+        """The batch is done: its images leave the in-flight count (the caller owns them now) and the
+        reservation falls back to what the context holds."""
         self.images -= sum(r.image_bytes for r in batch)
         self.held[slot] = self.reserved[slot] = int(held_after)
-        pix = sum(r.pixels for r in batch)
-        if workspace is not None and pix > 0:
-            self.bpp = max(self.bpp, (workspace - self.fixed - self.view_bytes * len(batch)) / pix)
 
     def refused(self, slot: int, batch: Sequence[Request], held_after: int):
-        """The library refused the batch under its reservation: release, and estimate higher unless
-        the estimate was already raised since this batch was admitted."""
+        """The library refused a batch under its reservation (the bound should make this never
+        happen; counted)."""
         self.images -= sum(r.image_bytes for r in batch)
         self.held[slot] = self.reserved[slot] = int(held_after)
-        if self.taken_gen[slot] == self.gen:
-            self.bpp *= self.miss_growth
-            self.gen += 1
         self.misses += 1
 
     def recycled(self, slot: int):
@@ -155,7 +126,6 @@ class _Slot:
         self.stream = torch.cuda.Stream()          # default priority
         self.batch: Optional[List[Request]] = None
         self.limit = 0
-        self.forced = False   # the batch was admitted with the whole remaining budget
         self.busy_intervals = []
         self.thread = threading.Thread(target=self._loop, name=f"mvgs-slot-{index}", daemon=True)
         self.thread.start()
@@ -176,14 +146,13 @@ class _Slot:
                 imgs, fr = self.rast.forward(srv.g, cams, imgs)
             except L.MvgsError as e:
                 if e.status == L.MVGS_ECAPACITY:
-                    return None, None
+                    return None
                 raise
-            ws = fr.workspace()
             self.rast.release(fr)   # the frame's buffers are reused only by later work on this stream
             ev = torch.cuda.Event()
             ev.record(self.stream)
         ev.synchronize()
-        return imgs, ws
+        return imgs
 
     def _loop(self):
         srv = self.server
@@ -193,14 +162,14 @@ class _Slot:
                     srv.cond.wait()
                 if srv.stopping:
                     return
-                batch, limit, forced = self.batch, self.limit, self.forced
+                batch, limit = self.batch, self.limit
             t0 = srv.clock()
             try:
-                imgs, ws = self._render(batch, limit)
+                imgs = self._render(batch, limit)
                 held = self.rast.memory_held()
                 err = None
             except Exception as e:  # surfaced by Server.run
-                imgs, ws, held, err = None, None, 0, e
+                imgs, held, err = None, 0, e
             t1 = srv.clock()
             with srv.cond:
                 self.busy_intervals.append((t0, t1))
@@ -208,15 +177,9 @@ class _Slot:
                     srv.error = err
                 elif imgs is None:
                     srv.adm.refused(self.index, batch, held)
-                    if forced:
-                        # refused with every byte the budget has: the request cannot be served
-                        for r in batch:
-                            r.error = "request exceeds the memory budget"
-                            srv.rejected.append(r)
-                    else:
-                        srv.queue.extendleft(reversed(batch))
+                    srv.queue.extendleft(reversed(batch))
                 else:
-                    srv.adm.finish(self.index, batch, held, ws)
+                    srv.adm.finish(self.index, batch, held)
                     for r, im in zip(batch, imgs):
                         r.t_start, r.t_done, r.slot = t0, t1, self.index
                         r.image = im if srv.keep_images else None
@@ -225,27 +188,21 @@ class _Slot:
                 srv.cond.notify_all()
 
 
-# Device bytes per participating (view, Gaussian) record in a forward: the 64-byte blend record, its
-# view (2), depth keys and record indices double-buffered (16), tile rectangle in record and in depth
-# order (32), pair count and offset (8).
-RECORD_BYTES = 122
-
-
 class Server:
     """Continuous-batching render server over a resident scene (GaussianTensors on the GPU)."""
 
     def __init__(self, g, n_slots: int = 4, budget_bytes: int = 16 << 30, max_batch: int = 8,
-                 tile=(16, 16), pixels_per_lane: int = 0, keep_images: bool = False,
-                 bytes_per_pixel: float = 64.0):
+                 tile=(16, 16), pixels_per_lane: int = 0, keep_images: bool = False):
         import torch
+        from .raster import Rasterizer
         g.check()
         self.g, self.device = g, g.means.device
         self.tile, self.ppl = tuple(tile), int(pixels_per_lane)
         self.keep_images = keep_images
-        # per batch: Gaussian-sized counters and offsets, upload staging, page rounding; per view: at
-        # most P records of RECORD_BYTES each
-        self.adm = Admission(budget_bytes, n_slots, max_batch, fixed_bytes=16 * (g.P + 1) + (256 << 10),
-                             view_bytes=RECORD_BYTES * g.P, bytes_per_pixel=bytes_per_pixel)
+        self.adm = Admission(budget_bytes, n_slots, max_batch, self._bound)
+        # participation pre-pass of queued requests, on its own context and stream
+        self.counter = Rasterizer(self.tile, self.ppl)
+        self.count_stream = torch.cuda.Stream()    # default priority
         self.cond = threading.Condition()
         self.queue: deque = deque()
         self.done: List[Request] = []
@@ -268,11 +225,29 @@ class Server:
         for s in self.slots:
             s.thread.join()
             s.rast.close()
+        self.counter.close()
+
+    def _bound(self, slot: int, reqs: Sequence[Request]) -> int:
+        """Exact bytes slot `slot`'s context would hold after rendering `reqs` as one batch."""
+        return self.slots[slot].rast.workspace_bound([r.cam for r in reqs], self.g.P, sum(r.records for r in reqs),
+                                                     sum(r.pairs for r in reqs))
+
+    def _count(self):
+        """Participation counts of every queued request that has none (one pre-pass)."""
+        import torch
+        todo = [r for r in self.queue if r.records < 0]
+        if not todo:
+            return
+        with torch.cuda.stream(self.count_stream):
+            rec, pairs = self.counter.count_views(self.g, [r.cam for r in todo])
+        for r, a, b in zip(todo, rec, pairs):
+            r.records, r.pairs = int(a), int(b)
 
     def _idle(self):
         return [s for s in self.slots if s.batch is None]
 
     def _dispatch(self):
+        self._count()
         while self.queue:
             idle = sorted(self._idle(), key=lambda s: -self.adm.held[s.index])
             if not idle:
@@ -281,28 +256,30 @@ class Server:
             for s in idle:
                 batch = self.adm.take(s.index, self.queue)
                 if batch:
-                    self._launch(s, batch, forced=False)
+                    self._launch(s, batch)
                     launched = True
                     break
             if launched:
                 continue
             if len(idle) < len(self.slots):
                 return   # wait for a busy slot to finish
-            # every slot idle, yet the head does not fit the estimate: free idle contexts' memory,
-            # then let the library decide with the whole budget
+            # every slot idle, yet the head does not fit: free idle contexts' memory; a request that
+            # does not fit an empty context within the whole budget cannot be served
             big = idle[0]
             if self.adm.held[big.index] > 0:
                 big.recycle()
                 self.adm.recycled(big.index)
                 self.recycles += 1
                 continue
-            self._launch(big, self.adm.take_forced(big.index, self.queue), forced=True)
+            r = self.queue.popleft()
+            r.error = "request exceeds the memory budget"
+            self.rejected.append(r)
 
-    def _launch(self, s, batch, forced):
+    def _launch(self, s, batch):
         for r in batch:
             r.batch = len(self.batches)
         self.batches.append((s.index, len(batch)))
-        s.batch, s.limit, s.forced = batch, self.adm.reserved[s.index], forced
+        s.batch, s.limit = batch, self.adm.reserved[s.index]
         self.cond.notify_all()
 
     def run(self, arrivals: Sequence[float], cams: Sequence, measure_from: int = 0) -> dict:

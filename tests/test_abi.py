@@ -218,3 +218,74 @@ def test_adapt_density_validation(ctx):
     assert call(prm=L.mvgs_adc_params(float("nan"), 2e-4, 0.01, 0.005)) == L.MVGS_EINVAL
     assert call(prm=L.mvgs_adc_params(2e-4, 2e-4, -1.0, 0.005)) == L.MVGS_EINVAL and "finite" in _err(ctx)
     assert lib.mvgs_adapt_density(None, None, None, None, None, None, None, None, None, None, 0, None) == L.MVGS_EINVAL
+
+
+def test_create_rejects_half_an_allocator():
+    lib = L.lib()
+    keep = L.ALLOC_FN(lambda n, c: None)
+    o = L.mvgs_options()
+    o.alloc = keep
+    h = C.c_void_p()
+    assert lib.mvgs_create(C.byref(h), C.byref(o)) == L.MVGS_EINVAL
+    keep2 = L.FREE_FN(lambda p, c: None)
+    o2 = L.mvgs_options()
+    o2.free = keep2
+    assert lib.mvgs_create(C.byref(h), C.byref(o2)) == L.MVGS_EINVAL
+
+
+def _bound(lib, ctx, cams, P, rec, pairs, work=0):
+    b = C.c_int64(-1)
+    st = lib.mvgs_workspace_bound(ctx, L.camera_array(cams), len(cams), P, rec, pairs, work, C.byref(b))
+    return st, b.value
+
+
+def test_workspace_bound_is_host_only_and_monotone(ctx):
+    """mvgs_workspace_bound does no device work: on a fresh context it is the sum of the grown sizes
+    of every buffer the calls would make; it rises with records, pairs, views and the work asked for."""
+    lib = L.lib()
+    cams = scenes.make_cameras([(320, 180), (640, 480)])
+    P = 100_000
+    st, base = _bound(lib, ctx, cams, P, 1000, 5000)
+    assert st == L.MVGS_OK and base > 0
+    # records: at least a 64-byte blend record, view, keys, values and rectangles each
+    assert _bound(lib, ctx, cams, P, 101_000, 5000)[1] - base >= 100_000 * (64 + 2 + 4 * 4 + 16 * 2)
+    # pairs: keys and values, double-buffered
+    assert _bound(lib, ctx, cams, P, 1000, 1_005_000)[1] - base >= 1_000_000 * 16
+    assert _bound(lib, ctx, cams[:1], P, 1000, 5000)[1] < base
+    l1 = _bound(lib, ctx, cams, P, 1000, 5000, L.MVGS_WORK_LOSS)[1]
+    ds = _bound(lib, ctx, cams, P, 1000, 5000, L.MVGS_WORK_LOSS_DSSIM)[1]
+    bw = _bound(lib, ctx, cams, P, 1000, 5000, L.MVGS_WORK_LOSS_DSSIM | L.MVGS_WORK_BACKWARD)[1]
+    assert base < l1 < ds < bw
+    # the backward adds 48 bytes of accumulators per record
+    assert bw - ds >= 1000 * 48
+    # the context holds nothing: the bound allocated nothing
+    held = C.c_int64(-1)
+    assert lib.mvgs_memory_held(ctx, C.byref(held)) == L.MVGS_OK and held.value == 0
+
+
+def test_workspace_bound_rejects_impossible_counts(ctx):
+    lib = L.lib()
+    cams = scenes.make_cameras([(64, 64)])
+    assert _bound(lib, ctx, cams, 100, 101, 5)[0] == L.MVGS_EINVAL     # more records than Gaussians x views
+    assert _bound(lib, ctx, cams, 100, -1, 5)[0] == L.MVGS_EINVAL
+    assert _bound(lib, ctx, cams, 100, 10, -5)[0] == L.MVGS_EINVAL
+    assert _bound(lib, ctx, cams, 100, 10, 5, 8)[0] == L.MVGS_EINVAL   # unknown work flag
+    assert _bound(lib, ctx, cams, 100, 10, 1 << 32)[0] == L.MVGS_ECAPACITY
+    assert _bound(lib, ctx, [], 100, 0, 0)[0] == L.MVGS_EINVAL
+    b = C.c_int64()
+    assert lib.mvgs_workspace_bound(ctx, L.camera_array(cams), 1, 100, 1, 1, 0, None) == L.MVGS_EINVAL
+    assert lib.mvgs_workspace_bound(None, L.camera_array(cams), 1, 100, 1, 1, 0, C.byref(b)) == L.MVGS_EINVAL
+
+
+def test_count_views_validates_before_the_device(ctx):
+    lib = L.lib()
+    cams = scenes.make_cameras([(64, 64)])
+    rec = np.zeros(1, np.int64)
+    pairs = np.zeros(1, np.int64)
+    g = L.mvgs_gaussians()
+    g.P, g.sh_degree = 10, 5
+    assert lib.mvgs_count_views(ctx, None, C.byref(g), L.camera_array(cams), 1, rec.ctypes.data,
+                                pairs.ctypes.data) == L.MVGS_EINVAL
+    g.sh_degree = 0
+    assert lib.mvgs_count_views(ctx, None, C.byref(g), L.camera_array(cams), 1, rec.ctypes.data,
+                                pairs.ctypes.data) == L.MVGS_EINVAL   # NULL parameter pointers

@@ -49,8 +49,9 @@ def test_serving_results_equal_alone_renders():
 
 
 def test_serving_under_a_tight_budget():
-    """A budget that admits about two requests at a time and an estimate that starts far too low:
-    the library refuses batches, they return to the queue, and every result is still exact."""
+    """A budget that admits about two requests at a time: batches are sized by the library's exact
+    bound from each request's participation counts, so none is refused, the budget holds, and every
+    result is still exact."""
     needs_gpu()
     sc = scenes.make_scene(20000, 3, log_scale_mean=-3.5)
     g = GaussianTensors.from_scene(sc)
@@ -59,11 +60,11 @@ def test_serving_under_a_tight_budget():
     r = Rasterizer((16, 16))
     big = max(cams, key=lambda c: c.width * c.height)
     _, fr = r.forward(g, [big])
-    ws = fr.workspace()
     r.release(fr)
+    ws = r.memory_held()
     r.close()
-    budget = int(4 * ws)
-    srv = Server(g, n_slots=2, budget_bytes=budget, max_batch=4, keep_images=True, bytes_per_pixel=1.0)
+    budget = int(3 * ws)
+    srv = Server(g, n_slots=2, budget_bytes=budget, max_batch=4, keep_images=True)
     try:
         st = srv.run(arr, cams)
         reqs = sorted(srv.done, key=lambda q: q.rid)
@@ -71,7 +72,43 @@ def test_serving_under_a_tight_budget():
     finally:
         srv.close()
     assert st["requests"] == 24 and st["rejected"] == 0, st
-    assert st["refused_batches"] >= 1
+    assert st["refused_batches"] == 0, st
     assert st["peak_budget_bytes"] <= budget
     assert held <= budget
     _alone_equal(g, reqs, (16, 16))
+
+
+def test_workspace_bound_is_exact():
+    """mvgs_count_views gives each view's participation counts as the forward counts them, and
+    mvgs_workspace_bound from them is exactly what the context holds after the forward (and after
+    the loss and backward), on a fresh context and on one that already holds buffers."""
+    needs_gpu()
+    from paper_2506_12727_amd import _lib as L
+    sc = scenes.make_scene(20000, 3, log_scale_mean=-3.5)
+    g = GaussianTensors.from_scene(sc)
+    cams = scenes.make_cameras([(160, 120), (320, 180), (96, 200)])
+    r = Rasterizer((16, 16))
+    rec, pairs = r.count_views(g, cams)
+    for v in range(len(cams)):
+        _, fr = r.forward(g, [cams[v]])
+        info = fr.info()
+        assert (info["records"], info["pairs"]) == (rec[v], pairs[v])
+        r.release(fr)
+    r.close()
+    r = Rasterizer((16, 16))   # a fresh context: the first bound counts every buffer
+    try:
+        for work in (L.MVGS_WORK_FORWARD, L.MVGS_WORK_LOSS | L.MVGS_WORK_BACKWARD,
+                     L.MVGS_WORK_LOSS_DSSIM | L.MVGS_WORK_BACKWARD):
+            for sub in (cams[:1], cams, cams[1:]):
+                idx = [cams.index(c) for c in sub]
+                want = r.workspace_bound(sub, g.P, int(rec[idx].sum()), int(pairs[idx].sum()), work)
+                imgs, fr = r.forward(g, sub)
+                if work:
+                    tg = [torch.zeros_like(i) for i in imgs]
+                    _, dl = r.loss(sub, imgs, tg, 1.0, 0.2 if work & L.MVGS_WORK_LOSS_DSSIM else 0.0)
+                    r.backward(g, fr, dl)
+                torch.cuda.synchronize()
+                assert r.memory_held() == want, (work, len(sub))
+                r.release(fr)
+    finally:
+        r.close()
