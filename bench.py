@@ -63,41 +63,37 @@ def parse():
     ap.add_argument("--variance-batches", type=int, default=24)
     ap.add_argument("--no-train", action="store_true", help="skip the training-iteration comparison")
     ap.add_argument("--train-steps", type=int, default=20)
+    ap.add_argument("--no-configs", action="store_true", help="skip the other workloads of the benchmark set")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path runs on a single "
-              "MI355X; across GPUs each would render its own views of a replicated scene and the "
-              "per-Gaussian gradients and statistics would be all-reduced).", file=sys.stderr)
-        sys.exit(2)
+def measure(name, args, steps, warmup, tile_arg="auto", ppl_arg=0, with_loop=True, with_graph=True, keep=False):
+    """Forward + loss + backward steps of one workload: the autotuned launch shape, eager steps with
+    per-stage HIP-event times recorded on the library's stream, the frame's sizes and blend work,
+    the same step replayed as one HIP graph, and the one-view-per-call loop on the same GPU."""
     import ctypes as C
 
-    import numpy as np
     import torch
 
     from paper_2506_12727_amd import _lib as L
     from paper_2506_12727_amd import scenes
     from paper_2506_12727_amd.raster import GaussianTensors, Rasterizer
 
-    torch.cuda.set_device(0)
-    wl = scenes.WORKLOADS[args.workload]
+    wl = scenes.WORKLOADS[name]
     scene = wl.scene()
     cams = wl.cameras()
     B = len(cams)
     g = GaussianTensors.from_scene(scene)
     tg = [torch.from_numpy(t).cuda() for t in scenes.make_targets(cams)]
     tuned = None
-    if args.tile == "auto":
+    if tile_arg == "auto":
         from paper_2506_12727_amd.tune import autotune
         tile, ppl, times = autotune(g, cams, tg, wl.w_l1, wl.w_dssim)
         tuned = {f"{t[0]}x{t[1]}/{p}": round(1e3 * v, 3) for (t, p), v in times.items()}
     else:
-        tile, ppl = tuple(int(x) for x in args.tile.split("x")), args.ppl
+        tile, ppl = tuple(int(x) for x in tile_arg.split("x")), ppl_arg
     rast = Rasterizer(tile, ppl)
     lib = L.lib()
     imgs = [torch.empty((3, c.height, c.width), device="cuda") for c in cams]
@@ -126,21 +122,14 @@ def main():
         for v in range(B):
             rast.release(step([v]))
 
-    if args.copy_mib:
-        src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         batched()
     torch.cuda.synchronize()
     lib.mvgs_profile_reset(rast.ctx)
     lib.mvgs_profile_enable(rast.ctx, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         batched()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -150,10 +139,10 @@ def main():
     L.check(lib.mvgs_profile_read(rast.ctx, ms, calls), rast.ctx)
     stage_ms = {STAGES[i]: ms[i] / max(calls[i], 1) for i in range(L.MVGS_STAGE_COUNT)}
     elapsed = t1 - t0
-    ms_step = 1e3 * elapsed / args.steps
-    views_s = B * args.steps / elapsed
+    ms_step = 1e3 * elapsed / steps
+    views_s = B * steps / elapsed
 
-    # frame sizes and walk work of one batched forward (outside the timed region)
+    # frame sizes, sort passes and walk work of one batched forward (outside the timed region)
     _, fr = rast.forward(g, cams, images=imgs)
     info = fr.info()
     work = torch.zeros(2, dtype=torch.int64, device="cuda")
@@ -165,42 +154,121 @@ def main():
 
     # the same step captured into a HIP graph (capacity mode: no host synchronization in the step)
     graph_res = None
-    if not args.no_graph:
+    if with_graph:
         from paper_2506_12727_amd.graph import CapturedStep
         capacity = (int(info["records"] * 1.02) + 1024, int(info["pairs"] * 1.02) + 4096)
         gstep = CapturedStep(g, cams, tg, wl.w_l1, wl.w_dssim, tile=tile, ppl=ppl, capacity=capacity, densify=dz)
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             gstep.replay()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             gstep.replay()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         gstep.check()
-        graph_res = {"ms_per_step": 1e3 * (t1 - t0) / args.steps, "views_per_s": B * args.steps / (t1 - t0),
+        graph_res = {"ms_per_step": 1e3 * (t1 - t0) / steps, "views_per_s": B * steps / (t1 - t0),
                      "capacity": {"records": capacity[0], "pairs": capacity[1]}}
         gstep.close()
 
     loop_res = None
-    if not args.no_loop:
-        for _ in range(max(1, args.warmup)):
+    if with_loop:
+        for _ in range(max(1, warmup)):
             loop()
         torch.cuda.synchronize()
-        lsteps = max(3, args.steps // 2)
+        lsteps = max(3, steps // 2)
         t0 = time.perf_counter()
         for _ in range(lsteps):
             loop()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         lv = B * lsteps / (t1 - t0)
-        loop_res = {"value": lv, "unit": "views/s", "ms_per_step": 1e3 * (t1 - t0) / lsteps,
-                    "batched_speedup": views_s / lv}
+        loop_res = {"value": lv, "unit": "views/s", "ms_per_step": 1e3 * (t1 - t0) / lsteps}
+    rast.close()
 
-    # roofline of the dominant kernel
-    dom = max(("blend_fwd", "blend_bwd", "tile_sort", "depth_sort", "emit", "records", "preprocess_bwd"),
-              key=lambda k: stage_ms[k])
-    roof = roofline(dom, stage_ms[dom], info, blended, g, B, cams, measured_traffic(dom, wl.name, tile, ppl))
+    traffic = {k: measured_traffic(k, wl.name, tile, ppl) for k in STAGES}
+    roofs = {k: roofline(k, stage_ms[k], info, blended, g, cams, wl, traffic[k]) for k in STAGES}
+    dom = max(STAGES, key=lambda k: stage_ms[k])
+    value, ms_value, src = views_s, ms_step, "eager calls"
+    if graph_res is not None:
+        value, ms_value, src = graph_res["views_per_s"], graph_res["ms_per_step"], "hip graph replay"
+    if loop_res is not None:
+        loop_res["batched_speedup"] = value / loop_res["value"]
+    total_px = sum(c.width * c.height for c in cams)
+    res = {
+        "workload": wl.name, "gaussians": g.P, "sh_degree": wl.sh_degree, "views": B,
+        "sizes": [[c.width, c.height] for c in cams], "tile": list(tile), "pixels_per_lane": ppl,
+        "autotune_ms_per_step": tuned, "loss": {"w_l1": wl.w_l1, "w_dssim": wl.w_dssim}, "densify": wl.densify,
+        "views_per_s": value, "ms_per_step": ms_value, "value_source": src,
+        "gaussian_pixels_per_s": g.P * total_px / (ms_value / 1e3),
+        "eager": {"ms_per_step": ms_step, "views_per_s": views_s},
+        "graph": graph_res,
+        "one_view_loop": loop_res,
+        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "frame": {"records": info["records"], "pairs": info["pairs"], "tiles": info["tiles"],
+                  "depth_sort_passes": info["depth_passes"], "tile_sort_passes": info["tile_passes"],
+                  "walk_steps": steps_walk, "blended_pairs": blended},
+        "stage_rooflines": roofs,
+        "roofline": roofs[dom],
+    }
+    if keep:
+        res["_state"] = (wl, scene, cams, tg, g, tile, ppl)
+    return res
+
+
+def copy_peak_gbs(mib=2048, reps=5):
+    """HBM bandwidth of a plain device-to-device copy (read + write), best of `reps`, timed with HIP
+    events: the measured ceiling next to the 8 TB/s specification."""
+    import torch
+    src = torch.empty(mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    best = None
+    for _ in range(reps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        t = a.elapsed_time(b) / 1e3
+        best = t if best is None else min(best, t)
+    del src, dst
+    return 2.0 * (mib << 20) / best / 1e9
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path runs on a single "
+              "MI355X; across GPUs each would render its own views of a replicated scene and the "
+              "per-Gaussian gradients and statistics would be all-reduced).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    torch.cuda.set_device(0)
+    if args.copy_mib:
+        src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    main_res = measure(args.workload, args, args.steps, args.warmup, args.tile, args.ppl, with_loop=not args.no_loop,
+                       with_graph=not args.no_graph, keep=True)
+    wl, scene, cams, tg, g, tile, ppl = main_res.pop("_state")
+    B = len(cams)
+
+    # the other workloads of the benchmark set, same measurement with fewer steps
+    others = {}
+    if not args.no_configs:
+        for name in ("small_16k_4x128", "train_300k_4x1600x1064_dssim", "large_3m_16x1280x840"):
+            if name == args.workload:
+                continue
+            r = measure(name, args, max(5, args.steps // 2), 2, "auto", 0, with_loop=True, with_graph=True)
+            others[name] = {k: r[k] for k in ("views", "gaussians", "tile", "pixels_per_lane", "views_per_s",
+                                              "ms_per_step", "value_source", "gaussian_pixels_per_s", "eager",
+                                              "graph", "one_view_loop", "stages_ms", "frame", "roofline",
+                                              "stage_rooflines", "loss", "densify")}
+            torch.cuda.empty_cache()
 
     partial = None
     if not args.no_partial:
@@ -211,49 +279,42 @@ def main():
 
     serve = None
     if args.serve_requests > 0:
-        rast.close()
-        del imgs, dl, grads
         torch.cuda.synchronize()
         serve = serve_bench(args, g if (wl.P, wl.sh_degree) == (1_000_000, 3) and wl.log_scale_mean == -4.0 else None,
                             tile, ppl)
+    copy_gbs = copy_peak_gbs()
 
     cpu = None if args.no_cpu else cpu_baseline(scene, cams, tg, wl, (16, 16), args.cpu_views)
-    total_px = sum(c.width * c.height for c in cams)
-    # the headline is the graph-replayed step when it ran (same work; no host gaps between kernels)
-    value, ms_value = views_s, ms_step
-    if graph_res is not None:
-        value, ms_value = graph_res["views_per_s"], graph_res["ms_per_step"]
-    if loop_res is not None:
-        loop_res["batched_speedup"] = value / loop_res["value"]
+    roof = dict(main_res["roofline"])
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": main_res["views_per_s"],
         "unit": "views/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_value,
+        "ms_per_step": main_res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "gaussians": g.P, "sh_degree": wl.sh_degree, "views": B,
-                   "sizes": [[c.width, c.height] for c in cams], "tile": list(tile),
-                   "pixels_per_lane": ppl, "autotune_ms_per_step": tuned,
+                   "sizes": main_res["sizes"], "tile": list(tile), "pixels_per_lane": ppl,
+                   "autotune_ms_per_step": main_res["autotune_ms_per_step"],
                    "loss": {"w_l1": wl.w_l1, "w_dssim": wl.w_dssim}, "densify": wl.densify},
-        "gaussian_pixels_per_s": g.P * total_px / (ms_value / 1e3),
-        "value_source": "hip graph replay" if graph_res is not None else "eager calls",
-        "eager": {"ms_per_step": ms_step, "views_per_s": views_s},
-        "graph": graph_res,
-        "one_view_loop": loop_res,
-        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "frame": {"records": info["records"], "pairs": info["pairs"], "tiles": info["tiles"],
-                  "walk_steps": steps_walk, "blended_pairs": blended},
-        "blend_rooflines": {k: roofline(k, stage_ms[k], info, blended, g, B, cams,
-                                        measured_traffic(k, wl.name, tile, ppl))
-                            for k in ("blend_fwd", "blend_bwd")},
+        "gaussian_pixels_per_s": main_res["gaussian_pixels_per_s"],
+        "value_source": main_res["value_source"],
+        "eager": main_res["eager"],
+        "graph": main_res["graph"],
+        "one_view_loop": main_res["one_view_loop"],
+        "stages_ms": main_res["stages_ms"],
+        "frame": main_res["frame"],
+        "stage_rooflines": main_res["stage_rooflines"],
         "roofline": roof,
+        "hbm_peak": {"spec_GBps": HBM_PEAK_GBS, "copy_kernel_GBps": copy_gbs,
+                     "copy_over_spec": copy_gbs / HBM_PEAK_GBS},
+        "configs": others,
         "partial": partial,
         "grad_variance": variance,
         "training": training,
@@ -513,51 +574,94 @@ def measured_traffic(stage, workload, tile, ppl):
     return rec["bytes_per_launch"].get(stage)
 
 
-def roofline(stage, ms, info, blended, g, B, cams, traffic=None):
-    """Achieved vs peak for one stage; algorithmic bytes or lane operations per launch; traffic is
-    the measured HBM bytes per launch when known."""
-    K, V = info["pairs"], info["records"]
-    npx = sum(c.width * c.height for c in cams)
+def stage_bytes(stage, info, g, cams, wl):
+    """Algorithmic HBM bytes of one launch of an HBM-bound stage: what it must read and write once.
+    K pairs, V records, P Gaussians with Kc = (degree + 1)^2 SH coefficients, N pixels."""
+    K, V, T = info["pairs"], info["records"], info["tiles"]
+    P, Kc = g.P, (g.sh_degree + 1) ** 2
+    N = sum(c.width * c.height for c in cams)
+    par = 44 + 12 * Kc            # mean, scale, quaternion, opacity, SH (float32)
+    return {
+        # geometry parameters in; records and covered tiles per Gaussian out
+        "count": 44.0 * P + 8.0 * P,
+        # parameters and record offsets in; 64 B record, 2 B view, 4 B depth key, 16 B tile rectangle out
+        "records": (par + 4.0) * P + 86.0 * V,
+        # one read and one write of the 4 B key and 4 B value per record and pass
+        "depth_sort": 16.0 * V * info["depth_passes"],
+        # each record's tile rectangle and id in depth order read once; 8 B per pair written
+        "emit": 20.0 * V + 8.0 * K,
+        # the passes after the one fused with emission
+        "tile_sort": 16.0 * K * max(info["tile_passes"] - 1, 0),
+        # the key at each tile boundary read, 8 B per tile written
+        "ranges": 12.0 * T,
+        # image and target read, gradient written per pixel-channel; with D-SSIM also the four
+        # separable window passes' maps (28 + 32 + 24 + 24 B per pixel-channel)
+        "loss": 3.0 * N * (12.0 + (108.0 if wl.w_dssim else 0.0)),
+        # parameters in and gradients out, record offsets; per record the 64 B record and 48 B of sums
+        "preprocess_bwd": 2.0 * par * P + 4.0 * P + (12.0 * P if wl.densify else 0.0) + 112.0 * V,
+    }[stage]
+
+
+def roofline(stage, ms, info, blended, g, cams, wl, traffic=None):
+    """Achieved vs peak for one stage: lane operations per blended pair for the blend kernels
+    (VALU-bound), algorithmic bytes per launch for the others; traffic is the measured HBM bytes
+    per launch when known."""
     sec = ms / 1e3
     if stage in ("blend_fwd", "blend_bwd"):
         per = FWD_OPS_PER_STEP if stage == "blend_fwd" else BWD_OPS_PER_STEP
-        ach = blended * per / sec / 1e12
+        ach = blended * per / sec / 1e12 if sec > 0 else 0.0
         return {"kernel": stage, "bound": "alu", "achieved": ach, "peak": ALU_PEAK_TLANEOPS, "unit": "Tlane-op/s",
                 "frac": ach / ALU_PEAK_TLANEOPS, "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE, WRITE_SIZE, calibrated)",
-                "traffic_TBps": None if traffic is None else traffic / sec / 1e12,
+                "traffic_TBps": None if traffic is None or sec <= 0 else traffic / sec / 1e12,
                 "units": {"blended_pairs": blended, "ops_per_pair": per}}
-    # HBM-bound stages: one read and one write of what the stage must move
-    per = {
-        "tile_sort": 2 * 16.0 * K,              # two 8-bit passes, each reads and writes 8 B per pair
-        "depth_sort": 4 * 16.0 * V,
-        "emit": 8.0 * K + 12.0 * V,
-        "records": (56 + 4 * 3 * (g.sh_degree + 1) ** 2) * g.P + 80.0 * V,
-        "preprocess_bwd": (56 + 12 * (g.sh_degree + 1) ** 2) * g.P + 112.0 * V,
-    }
-    byts = per[stage]
-    ach = byts / sec / 1e9
+    byts = stage_bytes(stage, info, g, cams, wl)
+    ach = byts / sec / 1e9 if sec > 0 else 0.0
     return {"kernel": stage, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None, "units": {"bytes": byts}}
+            "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "ms": ms, "units": {"bytes": byts}}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline(scene, cams, tg, wl, tile, nviews):
-    """The oracle (FP64, OpenMP) on a bounded sample: the first `nviews` views of the workload
-    with the full scene, forward + loss + backward. Value in views/s."""
-    import numpy as np
-
+    """The oracle (FP64, OpenMP over the host's threads) on a bounded sample: the first `nviews`
+    views of the workload with the full scene, forward + loss + backward, in views/s; and the
+    oracle on one thread over the smallest view of the workload."""
     import oracle
     sub = cams[:nviews]
     tgs = [t.cpu().numpy() for t in tg[:nviews]]
-    t0 = time.perf_counter()
-    f = oracle.forward(scene, sub, tile)
-    _, gl = oracle.loss(sub, f["images"], tgs, wl.w_l1, wl.w_dssim)
-    oracle.backward(scene, sub, gl, tile)
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+
+    def run(views, targets):
+        t0 = time.perf_counter()
+        f = oracle.forward(scene, views, tile)
+        _, gl = oracle.loss(views, f["images"], targets, wl.w_l1, wl.w_dssim)
+        oracle.backward(scene, views, gl, tile)
+        return time.perf_counter() - t0
+
+    threads = oracle.max_threads()
+    dt = run(sub, tgs)
+    small = min(range(len(cams)), key=lambda v: cams[v].width * cams[v].height)
+    oracle.set_threads(1)
+    try:
+        dt1 = run([cams[small]], [tg[small].cpu().numpy()])
+    finally:
+        oracle.set_threads(threads)
+    c1 = cams[small]
     return {"value": nviews / dt, "unit": "views/s", "cores": threads, "kind": "oracle",
             "sample": f"{nviews} view(s) {sub[0].width}x{sub[0].height} of {wl.name}, all {scene.P} Gaussians, "
-                      f"forward+loss+backward, {dt:.1f} s"}
+                      f"forward+loss+backward, {dt:.1f} s on {threads} threads",
+            "one_thread": {"value": 1.0 / dt1, "unit": "views/s", "cores": 1,
+                           "sample": f"view {small} ({c1.width}x{c1.height}) of {wl.name}, all {scene.P} Gaussians, "
+                                     f"forward+loss+backward, {dt1:.1f} s"},
+            "host": {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": _cpu_model()}}
 
 
 if __name__ == "__main__":

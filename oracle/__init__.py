@@ -66,6 +66,9 @@ def lib():
         L.ora_ssim_map.argtypes = [i32, i32, vp, vp, vp]
         L.ora_sh_basis.argtypes = [C.c_int, vp, vp, vp]
         L.ora_sh_count.restype = C.c_int
+        L.ora_set_threads.argtypes = [i32]
+        L.ora_set_threads.restype = None
+        L.ora_max_threads.restype = i32
         _LIB = L
     return _LIB
 
@@ -113,6 +116,15 @@ class OCams:
     def total_tiles(self) -> int:
         return sum(((w + self.tile[0] - 1) // self.tile[0]) * ((h + self.tile[1] - 1) // self.tile[1])
                    for (w, h) in self.sizes)
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().ora_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().ora_max_threads())
 
 
 def ln32(x: float) -> float:

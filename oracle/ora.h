@@ -106,6 +106,8 @@ int ora_render_pixels(const ora_scene* s, const ora_cams* c, int32_t v, int32_t 
 int ora_count_pairs(const ora_scene* s, const ora_cams* c, int64_t* records, int64_t* pairs);
 int ora_project64(const ora_scene* s, const ora_cams* c, int32_t v, double* mean2d, double* cov2d,
                   double* rgb, double* depth);
+void ora_set_threads(int32_t n);
+int32_t ora_max_threads(void);
 
 /* ora_loss.c */
 int ora_loss(const ora_cams* c, const double* const* img, const double* const* tgt, double w_l1,

@@ -829,3 +829,22 @@ int ora_count_pairs(const ora_scene* s, const ora_cams* c, int64_t* records, int
     *pairs = np;
     return 0;
 }
+
+/* Threads the oracle's parallel loops use (the CPU baseline times it on one thread too). */
+void ora_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int32_t ora_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
