@@ -46,6 +46,7 @@ extern "C" {
 #define MVGS_ENOMEM (-2)    /* device or host allocation failed */
 #define MVGS_ECAPACITY (-3) /* a size limit of the format was exceeded (see mvgs_forward) */
 #define MVGS_EHIP (-4)      /* a HIP runtime call failed; mvgs_last_error has the text */
+#define MVGS_ERETRY (-5)    /* capacity mode: the depth keys left the sort window; make the call again */
 
 #define MVGS_MAX_VIEWS 65535
 #define MVGS_MAX_TILES_PER_VIEW 65536
@@ -367,8 +368,9 @@ int mvgs_frame_release(mvgs_context* ctx, mvgs_frame* frame);
  * (MVGS_ECAPACITY if not: its images and any backward on it are void; make a context with larger
  * capacities). The depth sort of a capacity-mode forward orders the window of depth keys (whole
  * 8-bit passes around them) that the last frame checked on this context had, or all 32 bits before
- * any check; a forward whose keys leave that window is void too (MVGS_ECAPACITY, and the check
- * moves the window to its keys: make the call again, or capture it again). A partial frame is also void, with MVGS_EINVAL, if its selection was rejected; if
+ * any check; a forward whose keys leave that window is void too: MVGS_ERETRY, and the check
+ * moves the window to its keys, so the same call (or the same capture, with the same capacities)
+ * made again succeeds. A partial frame is also void, with MVGS_EINVAL, if its selection was rejected; if
  * its width * height pixels select a plane position in two views, MVGS_EINVAL says that its 3D
  * loss and merge are void. Sets the sizes mvgs_frame_info and mvgs_export_binning use.
  * Synchronizes the stream; not capturable. Returns MVGS_OK at once for frames not made in

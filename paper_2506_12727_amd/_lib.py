@@ -16,6 +16,7 @@ MVGS_EINVAL = -1
 MVGS_ENOMEM = -2
 MVGS_ECAPACITY = -3
 MVGS_EHIP = -4
+MVGS_ERETRY = -5
 MVGS_MAX_VIEWS = 65535
 MVGS_MAX_TILES_PER_VIEW = 65536
 

@@ -525,6 +525,7 @@ const char* mvgs_status_string(int status) {
         case MVGS_ENOMEM: return "out of memory";
         case MVGS_ECAPACITY: return "size limit exceeded";
         case MVGS_EHIP: return "HIP runtime error";
+        case MVGS_ERETRY: return "make the call again";
         default: return "unknown status";
     }
 }
@@ -1488,8 +1489,8 @@ int mvgs_frame_check(mvgs_context* ctx, void* stream, mvgs_frame* frame) {
     }
     if (e32[2] & 8u) {
         frame->checked = false;
-        return ctx->fail(MVGS_ECAPACITY, "the depth keys left the sort window that the call was made with; the "
-                                         "context's window now fits them: make the call again (capture again)");
+        return ctx->fail(MVGS_ERETRY, "the depth keys left the sort window that the call was made with; the "
+                                      "context's window now fits them: make the call again (capture again)");
     }
     const uint32_t sel_e = frame->mode == kModeFull ? 0u : (uint32_t)(ctx->pinned_totals[2] >> 32);
     if (e32[2] & 2u) {

@@ -129,10 +129,14 @@ class Trainer:
         try:
             self.cstep.check()
         except L.MvgsError as e:
-            if e.status != L.MVGS_ECAPACITY:
+            if e.status not in (L.MVGS_ECAPACITY, L.MVGS_ERETRY):
                 raise
-            # the replay changed nothing: capture again with room for this batch, and rerun
-            cap = tuple(int(x * 1.5) for x in self.cstep.rast.capacity)
+            # the replay changed nothing: capture again and rerun, with room for this batch after an
+            # overflow, with the same capacities after a depth-window miss (the check moved the
+            # window to this batch's keys)
+            cap = self.cstep.rast.capacity
+            if e.status == L.MVGS_ECAPACITY:
+                cap = tuple(int(x * 1.5) for x in cap)
             self.cstep.close()
             self.cstep = None
             self.recaptures += 1

@@ -30,7 +30,7 @@ def test_header_declarations_are_exported():
 
 def test_status_strings():
     lib = L.lib()
-    for code in (L.MVGS_OK, L.MVGS_EINVAL, L.MVGS_ENOMEM, L.MVGS_ECAPACITY, L.MVGS_EHIP):
+    for code in (L.MVGS_OK, L.MVGS_EINVAL, L.MVGS_ENOMEM, L.MVGS_ECAPACITY, L.MVGS_EHIP, L.MVGS_ERETRY):
         assert lib.mvgs_status_string(code)
     assert lib.mvgs_status_string(-99) == b"unknown status"
 

@@ -187,7 +187,7 @@ def test_depth_sort_window_is_checked():
     torch.cuda.synchronize()
     with pytest.raises(L.MvgsError) as ei:
         step.check()
-    assert ei.value.status == L.MVGS_ECAPACITY and "window" in str(ei.value)
+    assert ei.value.status == L.MVGS_ERETRY and "window" in str(ei.value)
     assert all(float(t.abs().max()) == 0.0 for t in step.grads.values())
     step.close()
     step = CapturedStep(g, far, tg, 1.0, 0.0, tile=(16, 16))
