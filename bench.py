@@ -90,7 +90,7 @@ def measure(name, args, steps, warmup, tile_arg="auto", ppl_arg=0, with_loop=Tru
     tuned = None
     if tile_arg == "auto":
         from paper_2506_12727_amd.tune import autotune
-        tile, ppl, times = autotune(g, cams, tg, wl.w_l1, wl.w_dssim)
+        tile, ppl, times = autotune(g, cams, tg, wl.w_l1, wl.w_dssim, cache=False)
         tuned = {f"{t[0]}x{t[1]}/{p}": round(1e3 * v, 3) for (t, p), v in times.items()}
     else:
         tile, ppl = tuple(int(x) for x in tile_arg.split("x")), ppl_arg
