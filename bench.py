@@ -597,8 +597,9 @@ def stage_bytes(stage, info, g, cams, wl):
         # image and target read, gradient written per pixel-channel; with D-SSIM also the four
         # separable window passes' maps (28 + 32 + 24 + 24 B per pixel-channel)
         "loss": 3.0 * N * (12.0 + (108.0 if wl.w_dssim else 0.0)),
-        # parameters in and gradients out, record offsets; per record the 64 B record and 48 B of sums
-        "preprocess_bwd": 2.0 * par * P + 4.0 * P + (12.0 * P if wl.densify else 0.0) + 112.0 * V,
+        # parameters in and gradients out, record offsets, statistics read and written; per record
+        # its 48 B of sums and its 2 B view
+        "preprocess_bwd": 2.0 * par * P + 4.0 * P + (24.0 * P if wl.densify else 0.0) + 50.0 * V,
     }[stage]
 
 
