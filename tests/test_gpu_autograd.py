@@ -99,6 +99,11 @@ def test_frame_lifetime():
     r = Rasterizer((16, 16))
     g = _leaves(sc)
     fused_loss(r, cams, rasterize(r, cams, g), tg).backward()   # sizes the context's buffers
+    # the upload ring takes its slots in turn (4 KiB each at first use): fill all of them so that
+    # what is held below is workspace and frames only
+    with torch.no_grad():
+        for _ in range(16):
+            rasterize(r, cams, g)
     torch.cuda.synchronize()
     held = r.memory_held()
     # forwards no backward can follow release their frame at once

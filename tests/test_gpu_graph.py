@@ -50,7 +50,12 @@ def test_capacity_mode_matches_eager():
     for _ in range(2):   # the second call reuses the buffers sized by the first
         imgs_c, fc = cap.forward(g, cams)
         fc.check()
-        assert fc.info() == info
+        ic = fc.info()
+        # the depth sort of a capacity-mode forward orders the context's key window (all 32 bits
+        # until a check has seen the keys), the eager one only the bits in which this call's keys
+        # differ: more passes, the same order
+        assert ic.pop("depth_passes") >= info["depth_passes"]
+        assert ic == {k: v for k, v in info.items() if k != "depth_passes"}
         for a, b in zip(imgs_c, imgs_e):
             assert torch.equal(a, b)
         kc, vc, rc = cap.export_binning(fc)
