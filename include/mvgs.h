@@ -242,6 +242,24 @@ int mvgs_subsample(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int
 int mvgs_loss(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t B, const float* const* images,
               const float* const* targets, float w_l1, float w_dssim, float* loss_dev, float* const* dl_dimages);
 
+/* Bytes of device scratch memory mvgs_loss_noalloc may use (per GPU). */
+#define MVGS_NOALLOC_SCRATCH_BYTES (32 * 1024 * 1024)
+
+/* mvgs_loss for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same arguments, kernels and results (the
+ * loss and dL/dI bit for bit mvgs_loss's), but every intermediate lives in a fixed
+ * MVGS_NOALLOC_SCRATCH_BYTES array that the library holds on each GPU it runs on until the process
+ * ends; the call allocates nothing, neither in the context nor on the host (no staging: the view
+ * table is written by a kernel from its arguments). Limits: B <= 64 views, and the scratch must
+ * hold the partial sums of every pixel (about 1/16 byte per pixel) plus, with w_dssim != 0, 96 bytes
+ * per pixel of the largest view (e.g. 640x480 fits, 1280x720 does not); beyond them the call returns
+ * MVGS_ECAPACITY and enqueues nothing. Every call on one GPU shares that GPU's array: calls that may
+ * overlap on the device (other streams, other threads, other contexts) race and must be ordered by
+ * the caller. The first call on a device looks the array up (no allocation). */
+int mvgs_loss_noalloc(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t B,
+                      const float* const* images, const float* const* targets, float w_l1, float w_dssim,
+                      float* loss_dev, float* const* dl_dimages);
+
 /* L1 + 3D distance-aware D-SSIM (paper Sec. 5.1.2, Eqs. 7-11) on the merged image plane of a
  * thread-efficient partial frame whose selection covers the views' common image plane once (as
  * mvgs_subsample makes). Pixel (x, y) of the plane was rendered from one view; its surface point is

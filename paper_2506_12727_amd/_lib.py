@@ -19,6 +19,7 @@ MVGS_EHIP = -4
 MVGS_ERETRY = -5
 MVGS_MAX_VIEWS = 65535
 MVGS_MAX_TILES_PER_VIEW = 65536
+MVGS_NOALLOC_SCRATCH_BYTES = 32 * 1024 * 1024
 
 EXPORTED = ["mvgs_create", "mvgs_destroy", "mvgs_forward", "mvgs_loss", "mvgs_backward", "mvgs_frame_release",
             "mvgs_frame_info", "mvgs_export_binning", "mvgs_export_transmittance", "mvgs_status_string",
@@ -28,7 +29,7 @@ EXPORTED = ["mvgs_create", "mvgs_destroy", "mvgs_forward", "mvgs_loss", "mvgs_ba
             "mvgs_frame_set_cameras", "mvgs_loss_3d", "mvgs_export_depth", "mvgs_adapt_density",
             "mvgs_adam_step", "mvgs_gather_rows", "mvgs_grad_moments", "mvgs_frame_merge",
             "mvgs_frame_void_word", "mvgs_count_views", "mvgs_workspace_bound",
-            "mvgs_frame_sort_info"]
+            "mvgs_frame_sort_info", "mvgs_loss_noalloc"]
 MVGS_PARTIAL_COMPACT = 0
 MVGS_PARTIAL_MASKED = 1
 MVGS_STAGE_COUNT = 10
@@ -112,6 +113,8 @@ def lib():
     L.mvgs_forward.restype = C.c_int
     L.mvgs_loss.argtypes = [vp, vp, C.POINTER(mvgs_camera), i32, vp, vp, f32, f32, vp, vp]
     L.mvgs_loss.restype = C.c_int
+    L.mvgs_loss_noalloc.argtypes = [vp, vp, C.POINTER(mvgs_camera), i32, vp, vp, f32, f32, vp, vp]
+    L.mvgs_loss_noalloc.restype = C.c_int
     L.mvgs_backward.argtypes = [vp, vp, C.POINTER(mvgs_gaussians), vp, vp, C.POINTER(mvgs_grads),
                                 C.POINTER(mvgs_densify)]
     L.mvgs_backward.restype = C.c_int

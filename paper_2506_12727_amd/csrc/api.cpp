@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1160,6 +1161,86 @@ int mvgs_loss(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t 
     ctx->stage_end(mk, s);
     LAUNCHCHK(ctx, "loss kernels");
     HIPCHK(ctx, ctx->ring.seal(s));
+    return MVGS_OK;
+}
+
+// Device memory of mvgs_loss_noalloc: a fixed array in the library's code object, one copy on each
+// GPU, held until the process ends. Host code never passes `scratch` itself (on the host the name
+// stands for a host-side shadow, not the device array): each device's address is looked up once
+// with hipGetSymbolAddress and that address is used everywhere.
+static __device__ __align__(256) unsigned char scratch[MVGS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// the current device's copy of `scratch` (looked up at the first call on that device)
+hipError_t scratch_for_current_device(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+int mvgs_loss_noalloc(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t B, const float* const* images,
+                      const float* const* targets, float w_l1, float w_dssim, float* loss_dev,
+                      float* const* dl_dimages) {
+    if (!ctx) return MVGS_EINVAL;
+    uint32_t n_tiles = 0, n_pixels = 0;
+    int st = validate_cams(ctx, cams, B, ctx->tw, ctx->th, &n_tiles, &n_pixels);
+    if (st) return st;
+    if (!images || !targets || !dl_dimages || !loss_dev) return ctx->fail(MVGS_EINVAL, "a loss buffer is NULL");
+    if (!std::isfinite(w_l1) || !std::isfinite(w_dssim)) return ctx->fail(MVGS_EINVAL, "loss weights must be finite");
+    if (B > kLossArgViews)
+        return ctx->fail(MVGS_ECAPACITY, "mvgs_loss_noalloc takes at most %d views (B=%d)", kLossArgViews, B);
+    std::vector<LossView> lv(B);
+    uint32_t pb = 0, max_hw = 0;
+    for (int v = 0; v < B; ++v) {
+        if (!images[v] || !targets[v] || !dl_dimages[v]) return ctx->fail(MVGS_EINVAL, "view %d: NULL image", v);
+        lv[v].img = images[v];
+        lv[v].tgt = targets[v];
+        lv[v].grad = dl_dimages[v];
+        lv[v].W = cams[v].width;
+        lv[v].H = cams[v].height;
+        lv[v].pix_base = pb;
+        lv[v].pad = 0;
+        const uint32_t hw = (uint32_t)(cams[v].width * cams[v].height);
+        pb += hw;
+        max_hw = std::max(max_hw, hw);
+    }
+    // scratch layout: view table, loss partials, then (D-SSIM) the per-view maps
+    const auto up256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t views_b = up256(sizeof(LossView) * (size_t)B);
+    const size_t part_b = up256(loss_scratch_bytes(n_pixels, B));
+    const size_t maps_b = w_dssim != 0.0f ? ssim_map_bytes(max_hw) : 0;
+    const size_t need = views_b + part_b + maps_b;
+    if (need > (size_t)MVGS_NOALLOC_SCRATCH_BYTES)
+        return ctx->fail(MVGS_ECAPACITY,
+                         "mvgs_loss_noalloc: %zu scratch bytes needed (%u pixels, largest view %u pixels%s), "
+                         "above its %d-byte maximum",
+                         need, n_pixels, max_hw, w_dssim != 0.0f ? ", D-SSIM" : "", MVGS_NOALLOC_SCRATCH_BYTES);
+    void* base = nullptr;
+    HIPCHK(ctx, scratch_for_current_device(&base));
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t* p = (uint8_t*)base;
+    LossView* dviews = (LossView*)p;
+    // every partial, chunk sum and map is written before it is read: nothing to clear
+    launch_put_loss_views(lv.data(), B, dviews, s);
+    launch_loss(dviews, lv.data(), B, n_pixels, w_l1, w_dssim, loss_dev, p + views_b,
+                maps_b ? p + views_b + part_b : nullptr, s);
+    LAUNCHCHK(ctx, "loss kernels");
     return MVGS_OK;
 }
 

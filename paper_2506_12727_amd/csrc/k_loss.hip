@@ -278,6 +278,22 @@ size_t loss_scratch_bytes(uint32_t total_pixels, int B) {
 
 size_t ssim_map_bytes(uint32_t max_view_pixels) { return (size_t)max_view_pixels * 3 * 8 * sizeof(float); }
 
+// The view table written by a kernel from its arguments (no host staging buffer, so the launch also
+// works where the caller may not allocate).
+struct LossViewArgs {
+    LossView v[kLossArgViews];
+};
+
+__global__ void k_put_loss_views(LossViewArgs a, int B, LossView* __restrict__ dst) {
+    if ((int)threadIdx.x < B) dst[threadIdx.x] = a.v[threadIdx.x];
+}
+
+void launch_put_loss_views(const LossView* views, int B, LossView* dst, hipStream_t s) {
+    LossViewArgs a{};
+    for (int v = 0; v < B && v < kLossArgViews; ++v) a.v[v] = views[v];
+    hipLaunchKernelGGL(k_put_loss_views, dim3(1), dim3(64), 0, s, a, B, dst);
+}
+
 void launch_loss(const LossView* views_dev, const LossView* views_host, int B, uint32_t total_pixels, float w_l1,
                  float w_dssim, float* loss_out, void* scratch, void* maps, hipStream_t s) {
     const double N = 3.0 * (double)total_pixels;

@@ -230,6 +230,9 @@ struct LossView {
 };
 size_t loss_scratch_bytes(uint32_t total_pixels, int B);
 size_t ssim_map_bytes(uint32_t max_view_pixels);
+// at most this many views per launch_put_loss_views (kernel-argument table; one wavefront)
+constexpr int kLossArgViews = 64;
+void launch_put_loss_views(const LossView* views, int B, LossView* dst, hipStream_t s);
 void launch_loss(const LossView* views_dev, const LossView* views_host, int B, uint32_t total_pixels, float w_l1,
                  float w_dssim, float* loss_out, void* scratch, void* maps, hipStream_t s);
 

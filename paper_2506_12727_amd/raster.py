@@ -250,18 +250,20 @@ class Rasterizer:
         L.check(st, self.ctx)
         return images, Frame(self, fr, cams)
 
-    def loss(self, cams, images, targets, w_l1=1.0, w_dssim=0.0, out=None, grads=None):
-        """Fused L1 + D-SSIM: returns (loss [1] tensor on the GPU, list of dL/dimage)."""
+    def loss(self, cams, images, targets, w_l1=1.0, w_dssim=0.0, out=None, grads=None, noalloc=False):
+        """Fused L1 + D-SSIM: returns (loss [1] tensor on the GPU, list of dL/dimage). noalloc: through
+        mvgs_loss_noalloc (the library's fixed per-GPU scratch; give out and grads to allocate
+        nothing here either)."""
         dev = images[0].device
         if out is None:
             out = torch.empty(1, dtype=torch.float32, device=dev)
         if grads is None:
             grads = [torch.empty_like(t) for t in images]
         ca = L.camera_array(cams)
-        st = self.lib.mvgs_loss(self.ctx, _stream(), ca, len(cams),
-                                L.ptr_array([t.data_ptr() for t in images]),
-                                L.ptr_array([t.data_ptr() for t in targets]), float(w_l1), float(w_dssim),
-                                out.data_ptr(), L.ptr_array([t.data_ptr() for t in grads]))
+        fn = self.lib.mvgs_loss_noalloc if noalloc else self.lib.mvgs_loss
+        st = fn(self.ctx, _stream(), ca, len(cams), L.ptr_array([t.data_ptr() for t in images]),
+                L.ptr_array([t.data_ptr() for t in targets]), float(w_l1), float(w_dssim), out.data_ptr(),
+                L.ptr_array([t.data_ptr() for t in grads]))
         L.check(st, self.ctx)
         return out, grads
 

@@ -112,6 +112,18 @@ def test_loss_and_backward_validation(ctx):
     assert lib.mvgs_loss(ctx, None, ca, 0, p, p, 1.0, 0.0, 0x3000, p) == L.MVGS_EINVAL
     assert lib.mvgs_loss(ctx, None, ca, 1, None, p, 1.0, 0.0, 0x3000, p) == L.MVGS_EINVAL
     assert lib.mvgs_loss(ctx, None, ca, 1, p, p, float("nan"), 0.0, 0x3000, p) == L.MVGS_EINVAL
+    # the no-alloc variant validates alike and refuses, before any device work, what its fixed
+    # scratch cannot hold: more than 64 views, or D-SSIM maps of a view above ~340K pixels
+    assert lib.mvgs_loss_noalloc(ctx, None, ca, 0, p, p, 1.0, 0.0, 0x3000, p) == L.MVGS_EINVAL
+    assert lib.mvgs_loss_noalloc(ctx, None, ca, 1, None, p, 1.0, 0.0, 0x3000, p) == L.MVGS_EINVAL
+    assert lib.mvgs_loss_noalloc(ctx, None, ca, 1, p, p, 1.0, 0.0, None, p) == L.MVGS_EINVAL
+    many = scenes.make_cameras([(16, 16)] * 65)
+    p65 = L.ptr_array([0x2000] * 65)
+    assert lib.mvgs_loss_noalloc(ctx, None, L.camera_array(many), 65, p65, p65, 1.0, 0.0, 0x3000,
+                                 p65) == L.MVGS_ECAPACITY
+    hd = scenes.make_cameras([(1280, 720)])
+    assert lib.mvgs_loss_noalloc(ctx, None, L.camera_array(hd), 1, p, p, 0.8, 0.2, 0x3000, p) == L.MVGS_ECAPACITY
+    assert "scratch" in _err(ctx)
     gr = L.mvgs_grads()
     assert lib.mvgs_backward(ctx, None, C.byref(_gauss()), None, p, C.byref(gr), None) == L.MVGS_EINVAL
     assert lib.mvgs_frame_release(ctx, None) == L.MVGS_EINVAL
