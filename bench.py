@@ -34,6 +34,11 @@ ALU_PEAK_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # and conic gradients, and 9 additions folding the pixel into the per-Gaussian sums.
 FWD_OPS_PER_STEP = 18
 BWD_OPS_PER_STEP = 57
+# algorithmic lane operations per pixel-channel of the fused L1 + D-SSIM loss (separable 11-tap
+# window, fused multiply-adds counted once): the five moments along x (2 multiplies and 5 fma per
+# tap: 77) and along y (55), SSIM and its three derivative maps (38), the maps along x and y (66),
+# and the gradient with its L1 term (8). The halo the 32x32 output tiles recompute is not counted.
+SSIM_OPS_PER_PIXEL_CHANNEL = 244
 STAGES = ["count", "records", "depth_sort", "emit", "tile_sort", "ranges", "blend_fwd", "loss", "blend_bwd",
           "preprocess_bwd"]
 
@@ -584,19 +589,19 @@ def stage_bytes(stage, info, g, cams, wl):
     return {
         # geometry parameters in; records and covered tiles per Gaussian out
         "count": 44.0 * P + 8.0 * P,
-        # parameters and record offsets in; 64 B record, 2 B view, 4 B depth key, 16 B tile rectangle out
-        "records": (par + 4.0) * P + 86.0 * V,
-        # one read and one write of the 4 B key and 4 B value per record and pass
-        "depth_sort": 16.0 * V * info["depth_passes"],
+        # parameters and record offsets in; 64 B record, 2 B view, 4 B depth key, 8 B tile rectangle out
+        "records": (par + 4.0) * P + 78.0 * V,
+        # one read and one write of the 4 B key, 4 B value and 8 B tile rectangle per record and pass
+        "depth_sort": 32.0 * V * info["depth_passes"],
         # each record's tile rectangle and id in depth order read once; 8 B per pair written
-        "emit": 20.0 * V + 8.0 * K,
+        "emit": 12.0 * V + 8.0 * K,
         # the passes after the one fused with emission
         "tile_sort": 16.0 * K * max(info["tile_passes"] - 1, 0),
         # the key at each tile boundary read, 8 B per tile written
         "ranges": 12.0 * T,
-        # image and target read, gradient written per pixel-channel; with D-SSIM also the four
-        # separable window passes' maps (28 + 32 + 24 + 24 B per pixel-channel)
-        "loss": 3.0 * N * (12.0 + (108.0 if wl.w_dssim else 0.0)),
+        # image and target read, gradient written per pixel-channel (L1 only: with D-SSIM the
+        # fused kernel is bound by its arithmetic, see roofline)
+        "loss": 3.0 * N * 12.0,
         # parameters in and gradients out, record offsets, statistics read and written; per record
         # its 48 B of sums and its 2 B view
         "preprocess_bwd": 2.0 * par * P + 4.0 * P + (24.0 * P if wl.densify else 0.0) + 50.0 * V,
@@ -616,6 +621,13 @@ def roofline(stage, ms, info, blended, g, cams, wl, traffic=None):
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE, WRITE_SIZE, calibrated)",
                 "traffic_TBps": None if traffic is None or sec <= 0 else traffic / sec / 1e12,
                 "units": {"blended_pairs": blended, "ops_per_pair": per}}
+    if stage == "loss" and wl.w_dssim:
+        n_pc = 3.0 * sum(c.width * c.height for c in cams)
+        ach = n_pc * SSIM_OPS_PER_PIXEL_CHANNEL / sec / 1e12 if sec > 0 else 0.0
+        return {"kernel": stage, "bound": "alu", "achieved": ach, "peak": ALU_PEAK_TLANEOPS, "unit": "Tlane-op/s",
+                "frac": ach / ALU_PEAK_TLANEOPS, "traffic": traffic, "ms": ms,
+                "units": {"pixel_channels": n_pc, "ops_per_pixel_channel": SSIM_OPS_PER_PIXEL_CHANNEL,
+                          "hbm_bytes": stage_bytes(stage, info, g, cams, wl)}}
     byts = stage_bytes(stage, info, g, cams, wl)
     ach = byts / sec / 1e9 if sec > 0 else 0.0
     return {"kernel": stage, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",

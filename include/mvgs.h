@@ -251,9 +251,8 @@ int mvgs_loss(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t 
  * MVGS_NOALLOC_SCRATCH_BYTES array that the library holds on each GPU it runs on until the process
  * ends; the call allocates nothing, neither in the context nor on the host (no staging: the view
  * table is written by a kernel from its arguments). Limits: B <= 64 views, and the scratch must
- * hold the partial sums of every pixel (about 1/16 byte per pixel) plus, with w_dssim != 0, 96 bytes
- * per pixel of the largest view (e.g. 640x480 fits, 1280x720 does not); beyond them the call returns
- * MVGS_ECAPACITY and enqueues nothing. Every call on one GPU shares that GPU's array: calls that may
+ * hold the partial sums (1/256 byte per pixel with L1 only; 24 bytes per 32x32 tile with
+ * D-SSIM, so about 1.4G pixels); beyond them the call returns MVGS_ECAPACITY and enqueues nothing. Every call on one GPU shares that GPU's array: calls that may
  * overlap on the device (other streams, other threads, other contexts) race and must be ordered by
  * the caller. The first call on a device looks the array up (no allocation). */
 int mvgs_loss_noalloc(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t B,

@@ -251,7 +251,7 @@ struct mvgs_context {
     std::string err;
     std::vector<mvgs_frame*> frames;
     DevBuf nrec, ntiles, totals, scan_scratch, depth_key[2], rec_vals[2], tile_rect, sorted_rect;
-    DevBuf sort_scratch, acc, loss_scratch, ssim_maps, loss3d_scratch, adc_n, adc_off, adc_act, moment_partials;
+    DevBuf sort_scratch, acc, loss_scratch, loss3d_scratch, adc_n, adc_off, adc_act, moment_partials;
     DevBuf adam_state;   // 3 words of a device-counted Adam step (allocated with the first device use)
     DevBuf view_counts;  // per-view records and pairs of mvgs_count_views
     size_t limit = 0;  // 0: no workspace limit
@@ -281,7 +281,7 @@ struct mvgs_context {
     void each_buffer(Fn fn) {
         DevBuf* bufs[] = {&nrec, &ntiles, &totals, &scan_scratch, &depth_key[0], &depth_key[1], &rec_vals[0],
                           &rec_vals[1], &tile_rect, &sorted_rect, &sort_scratch, &acc,
-                          &loss_scratch, &ssim_maps, &loss3d_scratch, &adc_n, &adc_off, &adc_act,
+                          &loss_scratch, &loss3d_scratch, &adc_n, &adc_off, &adc_act,
                           &moment_partials, &work, &adam_state, &view_counts};
         for (DevBuf* b : bufs) fn(*b);
         for (auto& sl : ring.slots) fn(sl.dev);
@@ -714,8 +714,8 @@ int fwd_needs_post(mvgs_context* ctx, mvgs_frame* f, const FwdSizes& z, uint32_t
     n[k++] = {&ctx->depth_key[1], sizeof(uint32_t) * V1};
     n[k++] = {&ctx->rec_vals[0], sizeof(uint32_t) * V1};
     n[k++] = {&ctx->rec_vals[1], sizeof(uint32_t) * V1};
-    n[k++] = {&ctx->tile_rect, sizeof(uint4) * V1};
-    n[k++] = {&ctx->sorted_rect, sizeof(uint4) * V1};
+    n[k++] = {&ctx->tile_rect, sizeof(uint2) * V1};
+    n[k++] = {&ctx->sorted_rect, sizeof(uint2) * V1};
     n[k++] = {&f->keys[0], sizeof(uint32_t) * K1};
     n[k++] = {&f->keys[1], sizeof(uint32_t) * K1};
     n[k++] = {&f->vals[0], sizeof(uint32_t) * K1};
@@ -729,11 +729,14 @@ int fwd_needs_post(mvgs_context* ctx, mvgs_frame* f, const FwdSizes& z, uint32_t
 }
 
 // Buffers of the loss and of the backward.
-int loss_needs(mvgs_context* ctx, int B, uint32_t n_pixels, uint32_t max_hw, bool dssim, Need* n) {
-    int k = 0;
-    n[k++] = {&ctx->loss_scratch, loss_scratch_bytes(n_pixels, B)};
-    if (dssim) n[k++] = {&ctx->ssim_maps, ssim_map_bytes(max_hw)};
-    return k;
+uint64_t ssim_tiles_of(const mvgs_camera* cams, int B) {
+    uint64_t n = 0;
+    for (int v = 0; v < B; ++v) n += ssim_tiles(cams[v].width, cams[v].height);
+    return n;
+}
+int loss_needs(mvgs_context* ctx, const mvgs_camera* cams, int B, uint32_t n_pixels, bool dssim, Need* n) {
+    n[0] = {&ctx->loss_scratch, loss_scratch_bytes(n_pixels, dssim ? ssim_tiles_of(cams, B) : 0)};
+    return 1;
 }
 int backward_needs(mvgs_context* ctx, uint32_t V, Need* n) {
     n[0] = {&ctx->acc, sizeof(float) * kAccStride * std::max<uint32_t>(V, 1)};
@@ -920,12 +923,14 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
 
     mk = ctx->stage_begin(1, s);
     launch_records(ga, dcam, B, tw, th, as<uint32_t>(f->rec_off), as<BlendRec>(f->recs),
-                   as<uint32_t>(ctx->depth_key[0]), as<uint4>(ctx->tile_rect), as<uint16_t>(f->rec_view), s, ovf);
+                   as<uint32_t>(ctx->depth_key[0]), as<uint2>(ctx->tile_rect), as<uint16_t>(f->rec_view), s, ovf);
     ctx->stage_end(mk, s);
     mk = ctx->stage_begin(2, s);
     uint32_t* dk[2] = {as<uint32_t>(ctx->depth_key[0]), as<uint32_t>(ctx->depth_key[1])};
     uint32_t* dv[2] = {as<uint32_t>(ctx->rec_vals[0]), as<uint32_t>(ctx->rec_vals[1])};
-    const int dcur = radix_sort_u32(dk, dv, true, V, depth_bits, ctx->sort_scratch.p, s, eff, depth_base);
+    // the records' tile rectangles travel with their depth keys
+    uint2* rect[2] = {as<uint2>(ctx->tile_rect), as<uint2>(ctx->sorted_rect)};
+    const int dcur = radix_sort_u32(dk, dv, true, V, depth_bits, ctx->sort_scratch.p, s, eff, depth_base, rect);
     const uint32_t* sorted_rec = dv[dcur];
     ctx->stage_end(mk, s);
 
@@ -935,9 +940,8 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     const int tile_bits = bits_for(n_tiles);
     f->depth_bits = depth_bits;
     f->tile_bits = tile_bits;
-    emit_pairs_first_pass(sorted_rec, as<uint4>(ctx->tile_rect), as<uint4>(ctx->sorted_rect), V, eff,
-                          as<uint32_t>(f->keys[0]), as<uint32_t>(f->vals[0]), K, eff ? eff + 1 : nullptr, tile_bits,
-                          ctx->sort_scratch.p, s);
+    emit_pairs_first_pass(sorted_rec, rect[dcur], dcam, B, V, eff, as<uint32_t>(f->keys[0]), as<uint32_t>(f->vals[0]),
+                          K, eff ? eff + 1 : nullptr, tile_bits, ctx->sort_scratch.p, s);
     ctx->stage_end(mk, s);
     mk = ctx->stage_begin(4, s);
     uint32_t* pk[2] = {as<uint32_t>(f->keys[0]), as<uint32_t>(f->keys[1])};
@@ -1087,9 +1091,7 @@ int mvgs_workspace_bound(mvgs_context* ctx, const mvgs_camera* cams, int32_t B, 
     ring_put(sizeof(float*) * B);
     grow_list(n, fwd_needs_post(ctx, f, z, V, K, n));
     if (work & (MVGS_WORK_LOSS | MVGS_WORK_LOSS_DSSIM)) {
-        uint32_t max_hw = 0;
-        for (int v = 0; v < B; ++v) max_hw = std::max(max_hw, (uint32_t)(cams[v].width * cams[v].height));
-        grow_list(n, loss_needs(ctx, B, n_pixels, max_hw, (work & MVGS_WORK_LOSS_DSSIM) != 0, n));
+        grow_list(n, loss_needs(ctx, cams, B, n_pixels, (work & MVGS_WORK_LOSS_DSSIM) != 0, n));
         ring_put(sizeof(LossView) * B);
     }
     if (work & MVGS_WORK_BACKWARD) {
@@ -1132,7 +1134,7 @@ int mvgs_loss(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t 
     if (!images || !targets || !dl_dimages || !loss_dev) return ctx->fail(MVGS_EINVAL, "a loss buffer is NULL");
     if (!std::isfinite(w_l1) || !std::isfinite(w_dssim)) return ctx->fail(MVGS_EINVAL, "loss weights must be finite");
     std::vector<LossView> lv(B);
-    uint32_t pb = 0, max_hw = 0;
+    uint32_t pb = 0;
     for (int v = 0; v < B; ++v) {
         if (!images[v] || !targets[v] || !dl_dimages[v]) return ctx->fail(MVGS_EINVAL, "view %d: NULL image", v);
         lv[v].img = images[v];
@@ -1144,20 +1146,18 @@ int mvgs_loss(mvgs_context* ctx, void* stream, const mvgs_camera* cams, int32_t 
         lv[v].pad = 0;
         const uint32_t hw = (uint32_t)(cams[v].width * cams[v].height);
         pb += hw;
-        max_hw = std::max(max_hw, hw);
     }
     hipStream_t s = (hipStream_t)stream;
     if (ctx->begin(s) && !ctx->device_used)
         return ctx->fail(MVGS_EINVAL, "make the call once before capturing it");
     HIPCHK(ctx, ctx->bind_device());
     Need need[2];
-    st = grow_all(ctx, need, loss_needs(ctx, B, n_pixels, max_hw, w_dssim != 0.0f, need));
+    st = grow_all(ctx, need, loss_needs(ctx, cams, B, n_pixels, w_dssim != 0.0f, need));
     if (st) return st;
     void* dviews = nullptr;
     HIPCHK(ctx, ctx->ring.put(lv.data(), sizeof(LossView) * B, s, &dviews, ctx->capturing));
     const int mk = ctx->stage_begin(7, s);
-    launch_loss((const LossView*)dviews, lv.data(), B, n_pixels, w_l1, w_dssim, loss_dev, ctx->loss_scratch.p,
-                ctx->ssim_maps.p, s);
+    launch_loss((const LossView*)dviews, lv.data(), B, n_pixels, w_l1, w_dssim, loss_dev, ctx->loss_scratch.p, s);
     ctx->stage_end(mk, s);
     LAUNCHCHK(ctx, "loss kernels");
     HIPCHK(ctx, ctx->ring.seal(s));
@@ -1206,7 +1206,7 @@ int mvgs_loss_noalloc(mvgs_context* ctx, void* stream, const mvgs_camera* cams, 
     if (B > kLossArgViews)
         return ctx->fail(MVGS_ECAPACITY, "mvgs_loss_noalloc takes at most %d views (B=%d)", kLossArgViews, B);
     std::vector<LossView> lv(B);
-    uint32_t pb = 0, max_hw = 0;
+    uint32_t pb = 0;
     for (int v = 0; v < B; ++v) {
         if (!images[v] || !targets[v] || !dl_dimages[v]) return ctx->fail(MVGS_EINVAL, "view %d: NULL image", v);
         lv[v].img = images[v];
@@ -1218,28 +1218,23 @@ int mvgs_loss_noalloc(mvgs_context* ctx, void* stream, const mvgs_camera* cams, 
         lv[v].pad = 0;
         const uint32_t hw = (uint32_t)(cams[v].width * cams[v].height);
         pb += hw;
-        max_hw = std::max(max_hw, hw);
     }
-    // scratch layout: view table, loss partials, then (D-SSIM) the per-view maps
+    // scratch layout: view table, then the loss partials
     const auto up256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t views_b = up256(sizeof(LossView) * (size_t)B);
-    const size_t part_b = up256(loss_scratch_bytes(n_pixels, B));
-    const size_t maps_b = w_dssim != 0.0f ? ssim_map_bytes(max_hw) : 0;
-    const size_t need = views_b + part_b + maps_b;
+    const size_t need = views_b + loss_scratch_bytes(n_pixels, w_dssim != 0.0f ? ssim_tiles_of(cams, B) : 0);
     if (need > (size_t)MVGS_NOALLOC_SCRATCH_BYTES)
         return ctx->fail(MVGS_ECAPACITY,
-                         "mvgs_loss_noalloc: %zu scratch bytes needed (%u pixels, largest view %u pixels%s), "
-                         "above its %d-byte maximum",
-                         need, n_pixels, max_hw, w_dssim != 0.0f ? ", D-SSIM" : "", MVGS_NOALLOC_SCRATCH_BYTES);
+                         "mvgs_loss_noalloc: %zu scratch bytes needed (%u pixels%s), above its %d-byte maximum", need,
+                         n_pixels, w_dssim != 0.0f ? ", D-SSIM" : "", MVGS_NOALLOC_SCRATCH_BYTES);
     void* base = nullptr;
     HIPCHK(ctx, scratch_for_current_device(&base));
     hipStream_t s = (hipStream_t)stream;
     uint8_t* p = (uint8_t*)base;
     LossView* dviews = (LossView*)p;
-    // every partial, chunk sum and map is written before it is read: nothing to clear
+    // every partial and chunk sum is written before it is read: nothing to clear
     launch_put_loss_views(lv.data(), B, dviews, s);
-    launch_loss(dviews, lv.data(), B, n_pixels, w_l1, w_dssim, loss_dev, p + views_b,
-                maps_b ? p + views_b + part_b : nullptr, s);
+    launch_loss(dviews, lv.data(), B, n_pixels, w_l1, w_dssim, loss_dev, p + views_b, s);
     LAUNCHCHK(ctx, "loss kernels");
     return MVGS_OK;
 }

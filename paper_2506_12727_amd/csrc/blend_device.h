@@ -17,16 +17,6 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
     return x * q + (x < rem ? x : rem) + k;
 }
 
-__device__ __forceinline__ int find_view(const DevCam* __restrict__ cams, int B, uint32_t tile) {
-    int lo = 0, hi = B;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (cams[mid].tile_base <= tile) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ bool box_misses(uint32_t bx, uint32_t by, int sx0, int sx1, int sy0, int sy1) {
     return (int)(bx & 0xffffu) > sx1 || (int)(bx >> 16) < sx0 || (int)(by & 0xffffu) > sy1 || (int)(by >> 16) < sy0;
 }

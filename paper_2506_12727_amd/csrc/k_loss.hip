@@ -7,6 +7,7 @@
 //   w(q - p) [dS/dmu1(p) + 2 I(q) dS/dE[I^2](p) + T(q) dS/dE[IT](p)],
 // which is the same separable convolution applied to three per-pixel derivative maps.
 // Partial sums are reduced in a fixed order, so the loss is deterministic.
+#include <algorithm>
 #include <cmath>
 
 #include "mvgs_kernels.h"
@@ -76,128 +77,199 @@ __global__ void __launch_bounds__(kLossThreads) k_l1(const LossView* __restrict_
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-// Horizontal pass: 5 windowed sums (I, T, I^2, T^2, IT) along x. Grid (blocks, 3 channels).
-__global__ void __launch_bounds__(kLossThreads) k_ssim_h(const float* __restrict__ img, const float* __restrict__ tgt,
-                                                         int W, int H, Win11 win, float* __restrict__ out) {
-    const int ch = blockIdx.y;
-    const size_t hw = (size_t)W * H;
-    const uint32_t p = blockIdx.x * kLossThreads + threadIdx.x;
-    if (p >= hw) return;
-    const int y = (int)(p / (uint32_t)W), x = (int)(p - (uint32_t)y * W);
-    const float* a = img + ch * hw + (size_t)y * W;
-    const float* b = tgt + ch * hw + (size_t)y * W;
-    float m0 = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0;
-#pragma unroll
-    for (int k = 0; k < 11; ++k) {
-        const int xx = x + k - 5;
-        if (xx < 0 || xx >= W) continue;
-        const float u = a[xx], v = b[xx], w = win.w[k];
-        m0 += w * u;
-        m1 += w * v;
-        m2 += w * u * u;
-        m3 += w * v * v;
-        m4 += w * u * v;
-    }
-    float* o = out + (size_t)ch * 5 * hw;
-    o[p] = m0;
-    o[hw + p] = m1;
-    o[2 * hw + p] = m2;
-    o[3 * hw + p] = m3;
-    o[4 * hw + p] = m4;
-}
+// D-SSIM with L1, fused: one workgroup per 32x32 output tile of one channel of one view. The
+// gradient at q needs the derivative maps over q's 11x11 window, and those need the moments over
+// their own windows, so the workgroup stages the 52x52 input neighbourhood of I and T in LDS and
+// keeps every intermediate there: the five moments along x (52 rows x 42 columns), then along y
+// with SSIM and its three derivative maps on the 42x42 neighbourhood of the tile (zero outside the
+// image: the sums run over image pixels only), then the derivative maps convolved along x and y.
+// Each thread slides the 11-tap window (fused multiply-adds) over a run of consecutive outputs held
+// in registers. HBM sees I and T read once (plus the halo, mostly from L2) and the gradient
+// written once.
+constexpr int kSsimTile = 32;
+constexpr int kSsimA = kSsimTile + 10;   // derivative-map neighbourhood
+constexpr int kSsimI = kSsimTile + 20;   // input neighbourhood
+constexpr int kSsimThreads = 256;
 
-// Vertical pass: moments -> SSIM (one partial sum per block) and the three derivative maps,
-// pre-multiplied by dL/dSSIM = -w_dssim / N.
-__global__ void __launch_bounds__(kLossThreads) k_ssim_v(const float* __restrict__ hsum, int W, int H, Win11 win,
-                                                         float dscale, float* __restrict__ dmaps,
-                                                         float* __restrict__ partial) {
-    __shared__ float red[kLossThreads];
+struct SsimLds {
+    union {
+        float in[2][kSsimI][kSsimI];   // I and T
+        float abc[3][kSsimA][kSsimA];  // derivative maps (after the moments along x)
+    } u;
+    union {
+        float hs[5][kSsimI][kSsimA];   // moments along x
+        float hb[3][kSsimA][kSsimTile];  // derivative maps along x
+    } v;
+    float red[2][kSsimThreads / 64];
+};
+
+__global__ void __launch_bounds__(kSsimThreads) k_ssim_fused(const float* __restrict__ img,
+                                                             const float* __restrict__ tgt,
+                                                             float* __restrict__ grad, int W, int H, int tiles_x,
+                                                             Win11 win, float l1scale, float dscale,
+                                                             float* __restrict__ partial, uint32_t part_base,
+                                                             uint32_t n_parts) {
+    __shared__ SsimLds L;
     const int ch = blockIdx.y;
+    const int t = threadIdx.x;
+    const int ty = (int)blockIdx.x / tiles_x, tx = (int)blockIdx.x - ty * tiles_x;
+    const int x0 = tx * kSsimTile, y0 = ty * kSsimTile;
     const size_t hw = (size_t)W * H;
-    const uint32_t p = blockIdx.x * kLossThreads + threadIdx.x;
-    float S = 0.0f;
-    if (p < hw) {
-        const int y = (int)(p / (uint32_t)W), x = (int)(p - (uint32_t)y * W);
-        const float* h = hsum + (size_t)ch * 5 * hw;
-        float m[5] = {0, 0, 0, 0, 0};
-#pragma unroll
-        for (int k = 0; k < 11; ++k) {
-            const int yy = y + k - 5;
-            if (yy < 0 || yy >= H) continue;
-            const size_t q = (size_t)yy * W + x;
-            const float w = win.w[k];
-#pragma unroll
-            for (int j = 0; j < 5; ++j) m[j] += w * h[j * hw + q];
-        }
-        const float mu1 = m[0], mu2 = m[1];
-        const float s11 = m[2] - mu1 * mu1, s22 = m[3] - mu2 * mu2, s12 = m[4] - mu1 * mu2;
-        const float A1 = 2.0f * mu1 * mu2 + kC1, A2 = 2.0f * s12 + kC2;
-        const float B1 = mu1 * mu1 + mu2 * mu2 + kC1, B2 = s11 + s22 + kC2;
-        const float iB = 1.0f / (B1 * B2);
-        S = A1 * A2 * iB;
-        const float d_mu1 = 2.0f * mu2 * (A2 - A1) * iB - 2.0f * mu1 * S * (1.0f / B1 - 1.0f / B2);
-        const float d_m11 = -S / B2;
-        const float d_m12 = 2.0f * A1 * iB;
-        float* d = dmaps + (size_t)ch * 3 * hw;
-        d[p] = dscale * d_mu1;
-        d[hw + p] = dscale * d_m11;
-        d[2 * hw + p] = dscale * d_m12;
+    const float* a = img + ch * hw;
+    const float* b = tgt + ch * hw;
+    float* gout = grad + ch * hw;
+    // 1. I and T over rows y0 - 10 .. y0 + 41 and columns x0 - 10 .. x0 + 41 (zero outside)
+    for (int e = t; e < kSsimI * kSsimI; e += kSsimThreads) {
+        const int r = e / kSsimI, c = e - r * kSsimI;
+        const int y = y0 - 10 + r, x = x0 - 10 + c;
+        const bool in = x >= 0 && x < W && y >= 0 && y < H;
+        const size_t q = (size_t)y * W + x;
+        L.u.in[0][r][c] = in ? a[q] : 0.0f;
+        L.u.in[1][r][c] = in ? b[q] : 0.0f;
     }
-    red[threadIdx.x] = S;
     __syncthreads();
-    for (int off = kLossThreads / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
+    // 2. moments along x: row r, columns j .. j + 6 of the 42 (a run of 7 per task)
+    for (int task = t; task < kSsimI * 6; task += kSsimThreads) {
+        const int r = task / 6, j0 = (task - r * 6) * 7;
+        float u[17], v[17];
+#pragma unroll
+        for (int k = 0; k < 17; ++k) {
+            u[k] = L.u.in[0][r][j0 + k];
+            v[k] = L.u.in[1][r][j0 + k];
+        }
+#pragma unroll
+        for (int jj = 0; jj < 7; ++jj) {
+            float m0 = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0;
+#pragma unroll
+            for (int k = 0; k < 11; ++k) {
+                const float uu = u[jj + k], vv = v[jj + k], w = win.w[k];
+                const float wu = w * uu, wv = w * vv;
+                m0 = __builtin_fmaf(w, uu, m0);
+                m1 = __builtin_fmaf(w, vv, m1);
+                m2 = __builtin_fmaf(wu, uu, m2);
+                m3 = __builtin_fmaf(wv, vv, m3);
+                m4 = __builtin_fmaf(wu, vv, m4);
+            }
+            L.v.hs[0][r][j0 + jj] = m0;
+            L.v.hs[1][r][j0 + jj] = m1;
+            L.v.hs[2][r][j0 + jj] = m2;
+            L.v.hs[3][r][j0 + jj] = m3;
+            L.v.hs[4][r][j0 + jj] = m4;
+        }
     }
-    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
-}
-
-// Backward horizontal pass over the three derivative maps.
-__global__ void __launch_bounds__(kLossThreads) k_ssim_bh(const float* __restrict__ dmaps, int W, int H, Win11 win,
-                                                          float* __restrict__ out) {
-    const int ch = blockIdx.y;
-    const size_t hw = (size_t)W * H;
-    const uint32_t p = blockIdx.x * kLossThreads + threadIdx.x;
-    if (p >= hw) return;
-    const int y = (int)(p / (uint32_t)W), x = (int)(p - (uint32_t)y * W);
-    const float* d = dmaps + (size_t)ch * 3 * hw + (size_t)y * W;
-    float s[3] = {0, 0, 0};
+    __syncthreads();
+    // 3. moments along y, SSIM and its derivative maps at the 42x42 positions p = (x0 - 5 + j,
+    // y0 - 5 + i): column j, rows i .. i + 6 per task; SSIM summed over the tile's own pixels
+    float ssim_sum = 0.0f;
+    float mom[5][7];
+    int j = 0, i0 = 0;
+    const bool task3 = t < kSsimA * 6;
+    if (task3) {
+        j = t / 6;
+        i0 = (t - j * 6) * 7;
 #pragma unroll
-    for (int k = 0; k < 11; ++k) {
-        const int xx = x + k - 5;
-        if (xx < 0 || xx >= W) continue;
-        const float w = win.w[k];
+        for (int m = 0; m < 5; ++m) {
+            float h[17];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) s[j] += w * d[j * hw + xx];
+            for (int k = 0; k < 17; ++k) h[k] = L.v.hs[m][i0 + k][j];
+#pragma unroll
+            for (int ii = 0; ii < 7; ++ii) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int k = 0; k < 11; ++k) acc = __builtin_fmaf(win.w[k], h[ii + k], acc);
+                mom[m][ii] = acc;
+            }
+        }
+        // (the inputs are no longer read: the derivative maps take their place)
+        const int px = x0 - 5 + j;
+        const bool own_col = j >= 5 && j < 5 + kSsimTile && px < W;
+#pragma unroll
+        for (int ii = 0; ii < 7; ++ii) {
+            const int i = i0 + ii, py = y0 - 5 + i;
+            float dm0 = 0.0f, dm1 = 0.0f, dm2 = 0.0f;
+            if (px >= 0 && px < W && py >= 0 && py < H) {
+                const float mu1 = mom[0][ii], mu2 = mom[1][ii];
+                const float s11 = mom[2][ii] - mu1 * mu1, s22 = mom[3][ii] - mu2 * mu2, s12 = mom[4][ii] - mu1 * mu2;
+                const float A1 = 2.0f * mu1 * mu2 + kC1, A2 = 2.0f * s12 + kC2;
+                const float B1 = mu1 * mu1 + mu2 * mu2 + kC1, B2 = s11 + s22 + kC2;
+                const float iB = 1.0f / (B1 * B2);
+                const float S = A1 * A2 * iB;
+                dm0 = dscale * (2.0f * mu2 * (A2 - A1) * iB - 2.0f * mu1 * S * (1.0f / B1 - 1.0f / B2));
+                dm1 = dscale * (-S / B2);
+                dm2 = dscale * (2.0f * A1 * iB);
+                if (own_col && i >= 5 && i < 5 + kSsimTile) ssim_sum += S;
+            }
+            L.u.abc[0][i][j] = dm0;
+            L.u.abc[1][i][j] = dm1;
+            L.u.abc[2][i][j] = dm2;
+        }
     }
-    float* o = out + (size_t)ch * 3 * hw;
+    __syncthreads();
+    // 4. derivative maps along x: row i, output columns jq .. jq + 7 of the 32
+    if (t < kSsimA * 4) {
+        const int i = t >> 2, jq0 = (t & 3) * 8;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) o[j * hw + p] = s[j];
-}
-
-// Backward vertical pass and combination into the image gradient (added to the L1 part).
-__global__ void __launch_bounds__(kLossThreads) k_ssim_bv(const float* __restrict__ hmaps,
-                                                          const float* __restrict__ img,
-                                                          const float* __restrict__ tgt, int W, int H, Win11 win,
-                                                          float* __restrict__ grad) {
-    const int ch = blockIdx.y;
-    const size_t hw = (size_t)W * H;
-    const uint32_t p = blockIdx.x * kLossThreads + threadIdx.x;
-    if (p >= hw) return;
-    const int y = (int)(p / (uint32_t)W), x = (int)(p - (uint32_t)y * W);
-    const float* h = hmaps + (size_t)ch * 3 * hw;
-    float s[3] = {0, 0, 0};
+        for (int c = 0; c < 3; ++c) {
+            float h[18];
 #pragma unroll
-    for (int k = 0; k < 11; ++k) {
-        const int yy = y + k - 5;
-        if (yy < 0 || yy >= H) continue;
-        const size_t q = (size_t)yy * W + x;
-        const float w = win.w[k];
+            for (int k = 0; k < 18; ++k) h[k] = L.u.abc[c][i][jq0 + k];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) s[j] += w * h[j * hw + q];
+            for (int jj = 0; jj < 8; ++jj) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int k = 0; k < 11; ++k) acc = __builtin_fmaf(win.w[k], h[jj + k], acc);
+                L.v.hb[c][i][jq0 + jj] = acc;
+            }
+        }
     }
-    const size_t i = ch * hw + p;
-    grad[i] += s[0] + 2.0f * img[i] * s[1] + tgt[i] * s[2];
+    __syncthreads();
+    // 5. along y, and the gradient dL/dI(q) = L1 term + s0 + 2 I s1 + T s2: column jq, rows
+    // iq .. iq + 3 of the 32
+    float l1_sum = 0.0f;
+    {
+        const int jq = t & 31, iq0 = (t >> 5) * 4;
+        float s[3][4];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float h[14];
+#pragma unroll
+            for (int k = 0; k < 14; ++k) h[k] = L.v.hb[c][iq0 + k][jq];
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int k = 0; k < 11; ++k) acc = __builtin_fmaf(win.w[k], h[ii + k], acc);
+                s[c][ii] = acc;
+            }
+        }
+        const int x = x0 + jq;
+        if (x < W) {
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii) {
+                const int y = y0 + iq0 + ii;
+                if (y < H) {
+                    const size_t q = (size_t)y * W + x;
+                    const float I = a[q], T = b[q], d = I - T;
+                    l1_sum += fabsf(d);
+                    gout[q] = l1_sign(d, l1scale) + (s[0][ii] + 2.0f * I * s[1][ii] + T * s[2][ii]);
+                }
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        l1_sum += __shfl_down(l1_sum, o, 64);
+        ssim_sum += __shfl_down(ssim_sum, o, 64);
+    }
+    if ((t & 63) == 0) {
+        L.red[0][t >> 6] = l1_sum;
+        L.red[1][t >> 6] = ssim_sum;
+    }
+    __syncthreads();
+    if (t == 0) {
+        const uint32_t k = part_base + blockIdx.y * gridDim.x + blockIdx.x;
+        partial[k] = L.red[0][0] + L.red[0][1] + L.red[0][2] + L.red[0][3];
+        partial[n_parts + k] = L.red[1][0] + L.red[1][1] + L.red[1][2] + L.red[1][3];
+    }
 }
 
 // Deterministic reduction in two stages. First, each workgroup adds kReduceChunk consecutive
@@ -267,16 +339,17 @@ static Win11 gaussian_window() {
     return w;
 }
 
-size_t loss_scratch_bytes(uint32_t total_pixels, int B) {
-    // partials (l1 + ssim) then, per view in turn, 8 maps per channel of the largest view
-    (void)B;
-    const size_t n_l1 = (total_pixels + kLossThreads - 1) / kLossThreads;
-    const size_t n_part = n_l1 + 3 * (size_t)total_pixels / kLossThreads + 3 * (size_t)B;
-    // float partials, then (8-byte aligned) two doubles per reduction chunk
-    return (n_part + 64) * sizeof(float) + 2 * sizeof(double) * (n_part / kReduceChunk + 2);
+uint32_t ssim_tiles(int W, int H) {
+    return (uint32_t)((W + kSsimTile - 1) / kSsimTile) * (uint32_t)((H + kSsimTile - 1) / kSsimTile);
 }
 
-size_t ssim_map_bytes(uint32_t max_view_pixels) { return (size_t)max_view_pixels * 3 * 8 * sizeof(float); }
+size_t loss_scratch_bytes(uint32_t total_pixels, uint64_t ssim_tiles_total) {
+    // float partials (L1 blocks, or an L1 and an SSIM sum per channel tile), then (8-byte aligned)
+    // two doubles per reduction chunk
+    const size_t n_l1 = (total_pixels + 4 * kLossThreads - 1) / (4 * kLossThreads);
+    const size_t n_part = std::max<size_t>(n_l1, 6 * (size_t)ssim_tiles_total);
+    return (n_part + 64) * sizeof(float) + 2 * sizeof(double) * (n_part / kReduceChunk + 2);
+}
 
 // The view table written by a kernel from its arguments (no host staging buffer, so the launch also
 // works where the caller may not allocate).
@@ -295,35 +368,32 @@ void launch_put_loss_views(const LossView* views, int B, LossView* dst, hipStrea
 }
 
 void launch_loss(const LossView* views_dev, const LossView* views_host, int B, uint32_t total_pixels, float w_l1,
-                 float w_dssim, float* loss_out, void* scratch, void* maps, hipStream_t s) {
+                 float w_dssim, float* loss_out, void* scratch, hipStream_t s) {
     const double N = 3.0 * (double)total_pixels;
     float* partial = (float*)scratch;
-    const uint32_t n_l1 = (total_pixels + 4 * kLossThreads - 1) / (4 * kLossThreads);
-    hipLaunchKernelGGL(k_l1, dim3(n_l1), dim3(kLossThreads), 0, s, views_dev, B, total_pixels, (float)(w_l1 / N),
-                       partial);
-    float* sp = partial + n_l1;
-    uint32_t n_s = 0;
-    if (w_dssim != 0.0f) {
+    uint32_t n_l1, n_part;
+    if (w_dssim == 0.0f) {
+        n_l1 = n_part = (total_pixels + 4 * kLossThreads - 1) / (4 * kLossThreads);
+        hipLaunchKernelGGL(k_l1, dim3(n_l1), dim3(kLossThreads), 0, s, views_dev, B, total_pixels,
+                           (float)(w_l1 / N), partial);
+    } else {
+        // one L1 and one SSIM partial per (view, channel, tile), L1 ones first
+        uint32_t n_s = 0;
+        for (int v = 0; v < B; ++v) n_s += 3 * ssim_tiles(views_host[v].W, views_host[v].H);
         const Win11 win = gaussian_window();
+        uint32_t base = 0;
         for (int v = 0; v < B; ++v) {
             const LossView& lv = views_host[v];
-            const uint32_t hw = (uint32_t)lv.W * (uint32_t)lv.H;
-            const uint32_t nb = (hw + kLossThreads - 1) / kLossThreads;
-            float* hsum = (float*)maps;                       // 5 maps x 3 channels
-            float* dm = hsum + (size_t)15 * hw;                // 3 maps x 3 channels
-            hipLaunchKernelGGL(k_ssim_h, dim3(nb, 3), dim3(kLossThreads), 0, s, lv.img, lv.tgt, lv.W, lv.H, win,
-                               hsum);
-            hipLaunchKernelGGL(k_ssim_v, dim3(nb, 3), dim3(kLossThreads), 0, s, (const float*)hsum, lv.W, lv.H, win,
-                               (float)(-(double)w_dssim / N), dm, sp + n_s);
-            n_s += 3 * nb;
-            float* hb = hsum;  // the moment maps are no longer needed
-            hipLaunchKernelGGL(k_ssim_bh, dim3(nb, 3), dim3(kLossThreads), 0, s, (const float*)dm, lv.W, lv.H, win,
-                               hb);
-            hipLaunchKernelGGL(k_ssim_bv, dim3(nb, 3), dim3(kLossThreads), 0, s, (const float*)hb, lv.img, lv.tgt,
-                               lv.W, lv.H, win, lv.grad);
+            const uint32_t nt = ssim_tiles(lv.W, lv.H);
+            const int tiles_x = (lv.W + kSsimTile - 1) / kSsimTile;
+            hipLaunchKernelGGL(k_ssim_fused, dim3(nt, 3), dim3(kSsimThreads), 0, s, lv.img, lv.tgt, lv.grad, lv.W,
+                               lv.H, tiles_x, win, (float)(w_l1 / N), (float)(-(double)w_dssim / N), partial, base,
+                               n_s);
+            base += 3 * nt;
         }
+        n_l1 = n_s;
+        n_part = 2 * n_s;
     }
-    const uint32_t n_part = n_l1 + n_s;
     const uint32_t n_chunks = (n_part + kReduceChunk - 1) / kReduceChunk;
     double* chunks = reinterpret_cast<double*>(((uintptr_t)(partial + n_part) + 7) & ~(uintptr_t)7);
     hipLaunchKernelGGL(k_loss_reduce, dim3(n_chunks), dim3(256), 0, s, (const float*)partial, n_l1, n_part, chunks);

@@ -106,18 +106,17 @@ __global__ void __launch_bounds__(256) k_count_views(const float* __restrict__ m
 }
 
 // The per-record arrays beside the record itself: view, depth key and covered-tile rectangle
-// (first global tile id, width | height << 16, the view's tiles per row).
+// (first global tile id, width | height << 16; the view's tiles per row follow from the id).
 __device__ __forceinline__ void record_side(const BlendRec& r, const DevCam* __restrict__ cams, int tile_w,
                                             int tile_h, uint32_t i, uint32_t* __restrict__ depth_key,
-                                            uint4* __restrict__ tile_rect, uint16_t* __restrict__ rec_view) {
+                                            uint2* __restrict__ tile_rect, uint16_t* __restrict__ rec_view) {
     const DevCam& c = cams[r.view];
     const uint32_t x0 = r.boxx & 0xffffu, x1 = r.boxx >> 16, y0 = r.boxy & 0xffffu, y1 = r.boxy >> 16;
     const uint32_t tx0 = x0 / (uint32_t)tile_w, ty0 = y0 / (uint32_t)tile_h;
     const uint32_t tw_n = x1 / (uint32_t)tile_w - tx0 + 1, th_n = y1 / (uint32_t)tile_h - ty0 + 1;
     rec_view[i] = (uint16_t)r.view;
     depth_key[i] = r.depth_bits;
-    tile_rect[i] = make_uint4(c.tile_base + ty0 * (uint32_t)c.tiles_x + tx0, tw_n | (th_n << 16), (uint32_t)c.tiles_x,
-                              0u);
+    tile_rect[i] = make_uint2(c.tile_base + ty0 * (uint32_t)c.tiles_x + tx0, tw_n | (th_n << 16));
 }
 
 // Records of every participating (view, Gaussian), written in (Gaussian, view) order at
@@ -134,7 +133,7 @@ __global__ void __launch_bounds__(64) k_records(const float* __restrict__ means,
                                                 const float* __restrict__ sh, int64_t P,
                                                 const DevCam* __restrict__ cams, int B, int tile_w, int tile_h,
                                                 const uint32_t* __restrict__ rec_off, BlendRec* __restrict__ recs,
-                                                uint32_t* __restrict__ depth_key, uint4* __restrict__ tile_rect,
+                                                uint32_t* __restrict__ depth_key, uint2* __restrict__ tile_rect,
                                                 uint16_t* __restrict__ rec_view,
                                                 const uint32_t* __restrict__ overflow) {
     __shared__ BlendRec stage[kRecStage];
@@ -390,7 +389,7 @@ void launch_count_views(const GaussianArgs& ga, const DevCam* cams, int B, int t
 }
 
 void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,
-                    BlendRec* recs, uint32_t* depth_key, uint4* tile_rect, uint16_t* rec_view, hipStream_t s,
+                    BlendRec* recs, uint32_t* depth_key, uint2* tile_rect, uint16_t* rec_view, hipStream_t s,
                     const uint32_t* overflow) {
     const unsigned blocks = (unsigned)((ga.P + 63) / 64);
     if (!blocks) return;

@@ -237,17 +237,27 @@ __global__ void __launch_bounds__(256) k_radix_upsweep(const uint32_t* __restric
 }
 
 // Step 3: rank each partition's items stably with wave64 ballots and scatter them through LDS in
-// digit order to the bases the scan gave.
+// digit order to the bases the scan gave. PAY: an 8-byte payload per item follows its key, staged
+// through the same LDS after the keys and values are out (the digits of the staged order kept
+// aside for it).
+template <bool PAY>
 __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, size_t n, const uint32_t* __restrict__ n_dev, uint32_t key_base, int shift,
-    uint32_t mask, uint32_t parts, const uint32_t* __restrict__ offsets) {
+    uint32_t* __restrict__ vals_out, const uint2* __restrict__ pay_in, uint2* __restrict__ pay_out, size_t n,
+    const uint32_t* __restrict__ n_dev, uint32_t key_base, int shift, uint32_t mask, uint32_t parts,
+    const uint32_t* __restrict__ offsets) {
     __shared__ uint32_t wcount[kSortWaves][kRadix];
     __shared__ uint32_t dstart[kRadix];
     __shared__ uint32_t gbase[kRadix];
     __shared__ uint32_t scan_tmp[kRadix];
-    __shared__ uint32_t skey[kSortTile];
-    __shared__ uint32_t sval[kSortTile];
+    __shared__ union {
+        struct {
+            uint32_t k[kSortTile];
+            uint32_t v[kSortTile];
+        } kv;
+        uint2 p[kSortTile];
+    } stg;
+    __shared__ uint8_t sdig[PAY ? kSortTile : 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortThreads) (&wcount[0][0])[d] = 0;
     const uint32_t part = blockIdx.x;
@@ -297,18 +307,45 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
         if (i < n) {
             const uint32_t d = ((key[r] - key_base) >> shift) & mask;
             const uint32_t pos = dstart[d] + wcount[wave][d] + rank[r];
-            skey[pos] = key[r];
-            sval[pos] = val[r];
+            stg.kv.k[pos] = key[r];
+            stg.kv.v[pos] = val[r];
+            if (PAY) sdig[pos] = (uint8_t)d;
+            rank[r] = pos;
         }
     }
     __syncthreads();
     const size_t tile_n = std::min<size_t>((size_t)kSortTile, n - (size_t)part * kSortTile);
     for (int j = threadIdx.x; j < (int)tile_n; j += kSortThreads) {
-        const uint32_t k = skey[j];
+        const uint32_t k = stg.kv.k[j];
         const uint32_t d = ((k - key_base) >> shift) & mask;
         const size_t dst = (size_t)gbase[d] + (uint32_t)(j - dstart[d]);
         keys_out[dst] = k;
-        vals_out[dst] = sval[j];
+        vals_out[dst] = stg.kv.v[j];
+    }
+    if (PAY) {
+        __syncthreads();   // the keys and values are out of the staging area
+        // eight loads in flight at a time (all 32 at once would double the registers the kernel
+        // needs and halve its occupancy)
+#pragma unroll
+        for (int r0 = 0; r0 < kSortRounds; r0 += 8) {
+            uint2 pv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const size_t i = base + (size_t)(r0 + q) * 64 + lane;
+                pv[q] = i < n ? pay_in[i] : make_uint2(0u, 0u);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const size_t i = base + (size_t)(r0 + q) * 64 + lane;
+                if (i < n) stg.p[rank[r0 + q]] = pv[q];
+            }
+            asm volatile("" ::: "memory");
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < (int)tile_n; j += kSortThreads) {
+            const uint32_t d = sdig[j];
+            pay_out[(size_t)gbase[d] + (uint32_t)(j - dstart[d])] = stg.p[j];
+        }
     }
 }
 
@@ -334,7 +371,7 @@ static PassPlan plan_passes(int bits) {
 // one reduce-then-scan pass over n items (bound; n_dev the count on the device)
 static void radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
                        size_t n, const uint32_t* n_dev, uint32_t base, int shift, uint32_t mask, void* scratch,
-                       hipStream_t s) {
+                       hipStream_t s, const uint2* pay_in = nullptr, uint2* pay_out = nullptr) {
     const size_t parts = div_up(n, kSortTile);
     uint8_t* p = (uint8_t*)scratch;
     uint32_t* counts = (uint32_t*)p;
@@ -342,19 +379,25 @@ static void radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
     hipLaunchKernelGGL(k_radix_upsweep, dim3((unsigned)parts), dim3(256), 0, s, keys_in, n, n_dev, base, shift,
                        mask, (uint32_t)parts, counts);
     scan_exclusive_u32(counts, counts, parts * ((size_t)mask + 1), nullptr, p, s, nullptr);
-    hipLaunchKernelGGL(k_radix_downsweep, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in, vals_in,
-                       keys_out, vals_out, n, n_dev, base, shift, mask, (uint32_t)parts, (const uint32_t*)counts);
+    if (pay_in)
+        hipLaunchKernelGGL(k_radix_downsweep<true>, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in, vals_in,
+                           keys_out, vals_out, pay_in, pay_out, n, n_dev, base, shift, mask, (uint32_t)parts,
+                           (const uint32_t*)counts);
+    else
+        hipLaunchKernelGGL(k_radix_downsweep<false>, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in,
+                           vals_in, keys_out, vals_out, nullptr, nullptr, n, n_dev, base, shift, mask, (uint32_t)parts,
+                           (const uint32_t*)counts);
 }
 
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
-                   hipStream_t s, const uint32_t* n_dev, uint32_t key_base) {
+                   hipStream_t s, const uint32_t* n_dev, uint32_t key_base, uint2* pay[2]) {
     int cur = 0;
     if (n == 0 || bits <= 0) return cur;
     const PassPlan pl = plan_passes(bits);
     for (int pass = 0; pass < pl.passes; ++pass) {
         const uint32_t* vin = (pass == 0 && identity_values) ? nullptr : vals[cur];
         radix_pass(keys[cur], vin, keys[cur ^ 1], vals[cur ^ 1], n, n_dev, key_base, pl.dbits * pass, pl.mask, scratch,
-                   s);
+                   s, pay ? pay[cur] : nullptr, pay ? pay[cur ^ 1] : nullptr);
         cur ^= 1;
     }
     return cur;
@@ -364,20 +407,20 @@ int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, s
 // binning
 // ---------------------------------------------------------------------------------------------
 
-__device__ __forceinline__ uint32_t rect_tiles(uint4 r) { return (r.y & 0xffffu) * (r.y >> 16); }
+__device__ __forceinline__ uint32_t rect_tiles(uint2 r) { return (r.y & 0xffffu) * (r.y >> 16); }
 
 
 // Pair emission fused with the first pass of the stable sort by global tile id. A workgroup takes
 // a chunk of kEmitRecs consecutive records of the depth order; their pairs, in depth order and
 // row-major over each record's tile rectangle, are the chunk's items (the partition of the first
-// pass). Both kernels generate them alike: the chunk's rectangles and the exclusive prefix of
-// their tile counts are staged in LDS; a lane finds the record of the first pair of its run by
-// binary search over that prefix and walks on from there (pair t of a record whose rectangle is
-// w tiles wide is tile (tx0 + t mod w, ty0 + t / w)). The upsweep gathers the chunk's rectangles
-// into depth order for the downsweep and counts the digits of its pairs, a contiguous run per
-// thread; the downsweep, in batches of kEmitBatch, lets each lane walk 16 consecutive pairs, hands
-// them to the wave64 ballot ranking in round order through LDS, stages the batch in digit order
-// and writes it out in runs. The emitted pairs are never stored unsorted.
+// pass). Both kernels generate them alike: the chunk's rectangles (carried through the depth sort,
+// so read in order) and the exclusive prefix of their tile counts are staged in LDS; a lane finds
+// the record of the first pair of its run by binary search over that prefix and walks on from
+// there (pair t of a record whose rectangle is w tiles wide is tile (tx0 + t mod w, ty0 + t / w)).
+// The upsweep counts the digits of the chunk's pairs, a contiguous run per thread; the downsweep,
+// in batches of kEmitBatch, lets each lane walk 16 consecutive pairs, hands them to the wave64
+// ballot ranking in round order through LDS, stages the batch in digit order and writes it out in
+// runs. The emitted pairs are never stored unsorted.
 constexpr int kEmitRecs = 512;
 constexpr int kEmitRounds = 16;
 constexpr int kEmitBatch = kSortWaves * kEmitRounds * 64;   // 4096
@@ -395,12 +438,10 @@ struct EmitStage {
 };
 
 // Stages records [r0, r0 + cnt) of the depth order (cnt <= kEmitRecs); returns the chunk's pairs.
-// GATHER: the rectangles are fetched by record (tile_rect[sorted_rec[i]]) and written out in depth
-// order to sorted_rect; otherwise they are read from sorted_rect.
-template <bool GATHER>
 __device__ __forceinline__ uint32_t emit_stage(const uint32_t* __restrict__ sorted_rec,
-                                               const uint4* __restrict__ tile_rect, uint4* __restrict__ sorted_rect,
-                                               uint32_t r0, uint32_t cnt, EmitStage& st, uint32_t* scan_tmp) {
+                                               const uint2* __restrict__ sorted_rect,
+                                               const DevCam* __restrict__ cams, int B, uint32_t r0, uint32_t cnt,
+                                               EmitStage& st, uint32_t* scan_tmp) {
     constexpr int kPer = kEmitRecs / kSortThreads;   // consecutive records per thread
     const uint32_t t = threadIdx.x;
     uint32_t c[kPer];
@@ -410,20 +451,12 @@ __device__ __forceinline__ uint32_t emit_stage(const uint32_t* __restrict__ sort
         const uint32_t i = kPer * t + (uint32_t)k;
         c[k] = 0u;
         if (i < cnt) {
-            uint4 rc;
-            if (GATHER) {
-                const uint32_t r = sorted_rec[r0 + i];
-                rc = tile_rect[r];
-                sorted_rect[r0 + i] = rc;
-                st.rec[i] = r;
-            } else {
-                rc = sorted_rect[r0 + i];
-                st.rec[i] = sorted_rec[r0 + i];
-            }
+            const uint2 rc = sorted_rect[r0 + i];
+            st.rec[i] = sorted_rec[r0 + i];
             c[k] = rect_tiles(rc);
             st.base[i] = rc.x;
             st.wdt[i] = rc.y & 0xffffu;
-            st.stride[i] = rc.z;
+            st.stride[i] = (uint32_t)cams[find_view(cams, B, rc.x)].tiles_x;
         }
         sum += c[k];
     }
@@ -497,10 +530,10 @@ struct EmitWalk {
     }
 };
 
-// The chunk's rectangles gathered into depth order (for the downsweep) and its digit counts.
+// The digit counts of the chunk's pairs.
 __global__ void __launch_bounds__(kSortThreads) k_emit_upsweep(const uint32_t* __restrict__ sorted_rec,
-                                                               const uint4* __restrict__ tile_rect,
-                                                               uint4* __restrict__ sorted_rect, uint32_t n,
+                                                               const uint2* __restrict__ sorted_rect,
+                                                               const DevCam* __restrict__ cams, int B, uint32_t n,
                                                                const uint32_t* __restrict__ n_dev, uint32_t mask,
                                                                uint32_t chunks, uint32_t* __restrict__ counts) {
     __shared__ EmitStage st;
@@ -511,7 +544,7 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_upsweep(const uint32_t* _
     const uint32_t r0 = blockIdx.x * kEmitRecs;
     if (r0 < n) {   // uniform over the workgroup
         const uint32_t cnt = min(n - r0, (uint32_t)kEmitRecs);
-        const uint32_t total = emit_stage<true>(sorted_rec, tile_rect, sorted_rect, r0, cnt, st, scan_tmp);
+        const uint32_t total = emit_stage(sorted_rec, sorted_rect, cams, B, r0, cnt, st, scan_tmp);
         // each thread counts a contiguous run of pairs, walking the rectangles row-major
         const uint32_t q = (total + kSortThreads - 1) / kSortThreads;
         uint32_t j = threadIdx.x * q;
@@ -531,8 +564,9 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_upsweep(const uint32_t* _
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_emit_downsweep(
-    const uint32_t* __restrict__ sorted_rec, const uint4* __restrict__ sorted_rect, uint32_t n,
-    const uint32_t* __restrict__ n_dev, uint32_t mask, uint32_t chunks, const uint32_t* __restrict__ offsets,
+    const uint32_t* __restrict__ sorted_rec, const uint2* __restrict__ sorted_rect, const DevCam* __restrict__ cams,
+    int B, uint32_t n, const uint32_t* __restrict__ n_dev, uint32_t mask, uint32_t chunks,
+    const uint32_t* __restrict__ offsets,
     uint32_t K, const uint32_t* __restrict__ K_dev, uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
     __shared__ EmitStage st;
     __shared__ uint32_t wcount[kSortWaves][kRadix];
@@ -549,8 +583,7 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_downsweep(
     if (r0 >= n) return;
     const uint32_t cnt = min(n - r0, (uint32_t)kEmitRecs);
     gbase[threadIdx.x] = threadIdx.x <= mask ? offsets[(size_t)threadIdx.x * chunks + blockIdx.x] : 0u;
-    const uint32_t total = emit_stage<false>(sorted_rec, nullptr, const_cast<uint4*>(sorted_rect), r0, cnt, st,
-                                             scan_tmp);
+    const uint32_t total = emit_stage(sorted_rec, sorted_rect, cams, B, r0, cnt, st, scan_tmp);
     for (uint32_t b0 = 0; b0 < total; b0 += kEmitBatch) {
         const uint32_t bn = min(total - b0, (uint32_t)kEmitBatch);
 #pragma unroll
@@ -676,8 +709,8 @@ size_t emit_sort_scratch_bytes(size_t n_rec, size_t K) {
                                                 scan_scratch_bytes(chunks * kRadix));
 }
 
-void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint4* tile_rect, uint4* sorted_rect, size_t n_rec,
-                           const uint32_t* n_rec_dev, uint32_t* keys, uint32_t* vals, size_t K,
+void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint2* sorted_rect, const DevCam* cams, int B,
+                           size_t n_rec, const uint32_t* n_rec_dev, uint32_t* keys, uint32_t* vals, size_t K,
                            const uint32_t* K_dev, int bits, void* scratch, hipStream_t s) {
     if (n_rec == 0 || K == 0) return;
     const PassPlan pl = plan_passes(bits);
@@ -685,11 +718,11 @@ void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint4* tile_rect, u
     uint8_t* p = (uint8_t*)scratch;
     uint32_t* counts = (uint32_t*)p;
     p += align256(chunks * kRadix * sizeof(uint32_t));
-    hipLaunchKernelGGL(k_emit_upsweep, dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rec, tile_rect,
-                       sorted_rect, (uint32_t)n_rec, n_rec_dev, pl.mask, (uint32_t)chunks, counts);
+    hipLaunchKernelGGL(k_emit_upsweep, dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rec, sorted_rect,
+                       cams, B, (uint32_t)n_rec, n_rec_dev, pl.mask, (uint32_t)chunks, counts);
     scan_exclusive_u32(counts, counts, chunks * ((size_t)pl.mask + 1), nullptr, p, s, nullptr);
-    hipLaunchKernelGGL(k_emit_downsweep, dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rec,
-                       (const uint4*)sorted_rect, (uint32_t)n_rec, n_rec_dev, pl.mask, (uint32_t)chunks,
+    hipLaunchKernelGGL(k_emit_downsweep, dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rec, sorted_rect,
+                       cams, B, (uint32_t)n_rec, n_rec_dev, pl.mask, (uint32_t)chunks,
                        (const uint32_t*)counts, (uint32_t)K, K_dev, keys, vals);
 }
 

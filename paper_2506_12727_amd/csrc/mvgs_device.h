@@ -37,6 +37,17 @@ struct DevCam {
     uint32_t pix_base;       // offset of this view's first pixel in per-pixel arrays
 };
 
+// the view holding global tile id `tile` (views in increasing tile_base)
+__device__ __forceinline__ int find_view(const DevCam* __restrict__ cams, int B, uint32_t tile) {
+    int lo = 0, hi = B;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cams[mid].tile_base <= tile) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // Blend record of one participating (view, Gaussian): 64 bytes, four dwordx4.
 struct alignas(16) BlendRec {
     uint32_t boxx;   // x0 | x1 << 16 (inclusive pixel box)

@@ -39,7 +39,7 @@ void launch_count(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int
 void launch_count_views(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th,
                         unsigned long long* counts, hipStream_t s);
 void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,
-                    BlendRec* recs, uint32_t* depth_key, uint4* tile_rect, uint16_t* rec_view, hipStream_t s,
+                    BlendRec* recs, uint32_t* depth_key, uint2* tile_rect, uint16_t* rec_view, hipStream_t s,
                     const uint32_t* overflow = nullptr);
 // overflow: as above; when set, every Gaussian is treated as taking part in no view
 void launch_preprocess_bwd(const GaussianArgs& ga, const DevCam* cams, const uint32_t* rec_off,
@@ -67,10 +67,11 @@ void reduce_sum_u32(const uint32_t* in, size_t n, uint64_t* total64, void* scrat
 // must lie in [key_base, key_base + 2^bits)), at most 8 bits per pass; a pass reads the keys twice
 // (count, scatter) and writes keys and values once. The input is in keys[0] and vals[0] (or, with
 // identity_values, the values are 0..n-1 and vals[0] is only ping-pong space); passes alternate
-// between buffers 0 and 1. Returns the index of the buffer holding the result.
+// between buffers 0 and 1. With pay, an 8-byte payload per item (input in pay[0]) travels with
+// its key the same way. Returns the index of the buffer holding the result.
 size_t radix_scratch_bytes(size_t n);
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
-                   hipStream_t s, const uint32_t* n_dev = nullptr, uint32_t key_base = 0);
+                   hipStream_t s, const uint32_t* n_dev = nullptr, uint32_t key_base = 0, uint2* pay[2] = nullptr);
 
 void fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 // per * min(*n_dev, n) values (all per * n when n_dev is null)
@@ -83,14 +84,14 @@ void launch_capacity_clamp(const uint64_t* totals, uint64_t cap_v, uint64_t cap_
                            int key_bits = 32, uint32_t* range_out = nullptr);
 
 // Pairs of the depth-ordered records and their stable sort by global tile id (of `bits` bits):
-// the first pass gathers the records' tile rectangles into depth order (sorted_rect, [n_rec]) and
-// emits every (global tile, record) pair straight into its place after the first radix pass
-// (keys, vals: [K]); sort_pairs_rest runs the remaining passes from buffers 0 and returns the
-// index of the buffer holding the sorted pairs. n_rec and K are bounds when n_rec_dev / K_dev
-// (device) give the counts.
+// from the records and their tile rectangles in depth order (sorted_rec, sorted_rect: [n_rec],
+// the rectangles carried through the depth sort), every (global tile, record) pair is emitted
+// straight into its place after the first radix pass (keys, vals: [K]); sort_pairs_rest runs the
+// remaining passes from buffers 0 and returns the index of the buffer holding the sorted pairs.
+// n_rec and K are bounds when n_rec_dev / K_dev (device) give the counts.
 size_t emit_sort_scratch_bytes(size_t n_rec, size_t K);
-void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint4* tile_rect, uint4* sorted_rect, size_t n_rec,
-                           const uint32_t* n_rec_dev, uint32_t* keys, uint32_t* vals, size_t K,
+void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint2* sorted_rect, const DevCam* cams, int B,
+                           size_t n_rec, const uint32_t* n_rec_dev, uint32_t* keys, uint32_t* vals, size_t K,
                            const uint32_t* K_dev, int bits, void* scratch, hipStream_t s);
 int sort_pairs_rest(uint32_t* keys[2], uint32_t* vals[2], size_t K, const uint32_t* K_dev, int bits, void* scratch,
                     hipStream_t s);
@@ -228,12 +229,14 @@ struct LossView {
     uint32_t pix_base;
     uint32_t pad;
 };
-size_t loss_scratch_bytes(uint32_t total_pixels, int B);
-size_t ssim_map_bytes(uint32_t max_view_pixels);
+// D-SSIM output tiles (per channel) of a W x H view
+uint32_t ssim_tiles(int W, int H);
+// partial sums of the loss kernels over total_pixels pixels whose views hold ssim_tiles_total tiles
+size_t loss_scratch_bytes(uint32_t total_pixels, uint64_t ssim_tiles_total);
 // at most this many views per launch_put_loss_views (kernel-argument table; one wavefront)
 constexpr int kLossArgViews = 64;
 void launch_put_loss_views(const LossView* views, int B, LossView* dst, hipStream_t s);
 void launch_loss(const LossView* views_dev, const LossView* views_host, int B, uint32_t total_pixels, float w_l1,
-                 float w_dssim, float* loss_out, void* scratch, void* maps, hipStream_t s);
+                 float w_dssim, float* loss_out, void* scratch, hipStream_t s);
 
 }  // namespace mvgs

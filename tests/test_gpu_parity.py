@@ -128,7 +128,8 @@ def test_forward_images(case):
 @pytest.mark.parametrize("w", [(1.0, 0.0), (0.8, 0.2), (0.0, 1.0)])
 def test_loss_and_image_gradient(w):
     needs_gpu()
-    cams = scenes.make_cameras([(61, 47), (40, 90), (16, 16)])
+    # ragged views spanning several 32x32 loss tiles, views smaller than one tile, 1x1 and 1-wide
+    cams = scenes.make_cameras([(61, 47), (40, 90), (16, 16), (97, 70), (1, 1), (1, 37), (5, 3), (64, 32)])
     rng = np.random.default_rng(7)
     imgs = [rng.uniform(size=(3, c.height, c.width)).astype(np.float32) for c in cams]
     tg = scenes.make_targets(cams)

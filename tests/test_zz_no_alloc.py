@@ -31,7 +31,7 @@ def _call(fn, r, cams, imgs, tgts, w_l1, w_dssim, out, grads):
 
 # (first batch, second smaller batch, w_l1, w_dssim)
 CASES = [([(1920, 1080), (1280, 720), (980, 545)], [(640, 480), (33, 17)], 1.0, 0.0),
-         ([(640, 480), (320, 240), (161, 97)], [(200, 120)], 0.8, 0.2)]
+         ([(1600, 1064), (320, 240), (161, 97)], [(200, 120)], 0.8, 0.2)]
 
 
 @pytest.mark.parametrize("first,second,w_l1,w_dssim", CASES)
@@ -62,15 +62,19 @@ def test_noalloc_loss_refuses_what_its_scratch_cannot_hold():
     needs_gpu()
     lib = L.lib()
     r = Rasterizer((16, 16))
-    cams, imgs, tgts = _batch([(1280, 720)], seed=7)
+    cams, imgs, tgts = _batch([(8, 8)] * 65, seed=7)   # one view more than the kernel-argument table
     out = torch.full((1,), 123.0, device="cuda")
-    grads = [torch.full_like(imgs[0], 5.0)]
+    grads = [torch.full_like(t, 5.0) for t in imgs]
     assert _call(lib.mvgs_loss_noalloc, r, cams, imgs, tgts, 0.8, 0.2, out, grads) == L.MVGS_ECAPACITY
     torch.cuda.synchronize()
-    assert float(out) == 123.0 and bool((grads[0] == 5.0).all())   # nothing was enqueued
-    # the same view with L1 only fits
-    assert _call(lib.mvgs_loss_noalloc, r, cams, imgs, tgts, 1.0, 0.0, out, grads) == L.MVGS_OK
-    want_out, want_g = r.loss(cams, imgs, tgts, 1.0, 0.0)
-    torch.cuda.synchronize()
-    assert torch.equal(out, want_out) and torch.equal(grads[0], want_g[0])
+    assert float(out) == 123.0 and all(bool((g == 5.0).all()) for g in grads)   # nothing was enqueued
+    # 64 of them fit, and a full-HD view with D-SSIM fits too
+    for sizes in ([(8, 8)] * 64, [(1920, 1080)]):
+        cams, imgs, tgts = _batch(sizes, seed=8)
+        out = torch.empty(1, device="cuda")
+        grads = [torch.empty_like(t) for t in imgs]
+        assert _call(lib.mvgs_loss_noalloc, r, cams, imgs, tgts, 0.8, 0.2, out, grads) == L.MVGS_OK
+        want_out, want_g = r.loss(cams, imgs, tgts, 0.8, 0.2)
+        torch.cuda.synchronize()
+        assert torch.equal(out, want_out) and all(torch.equal(a, b) for a, b in zip(grads, want_g))
     r.close()
