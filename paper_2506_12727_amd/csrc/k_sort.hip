@@ -411,7 +411,8 @@ __device__ __forceinline__ uint32_t rect_tiles(uint2 r) { return (r.y & 0xffffu)
 
 
 // Pair emission fused with the first pass of the stable sort by global tile id. A workgroup takes
-// a chunk of kEmitRecs consecutive records of the depth order; their pairs, in depth order and
+// a chunk of RECS consecutive records of the depth order (512, or 1,024 when records cover fewer
+// than four tiles on average, so that a chunk's pairs still fill most of a batch); their pairs, in depth order and
 // row-major over each record's tile rectangle, are the chunk's items (the partition of the first
 // pass). Both kernels generate them alike: the chunk's rectangles (carried through the depth sort,
 // so read in order) and the exclusive prefix of their tile counts are staged in LDS; a lane finds
@@ -421,7 +422,8 @@ __device__ __forceinline__ uint32_t rect_tiles(uint2 r) { return (r.y & 0xffffu)
 // in batches of kEmitBatch, lets each lane walk 16 consecutive pairs, hands them to the wave64
 // ballot ranking in round order through LDS, stages the batch in digit order and writes it out in
 // runs. The emitted pairs are never stored unsorted.
-constexpr int kEmitRecs = 512;
+constexpr int kEmitRecs = 512;        // the smaller chunk (it bounds the count table)
+constexpr int kEmitRecsSmall = 1024;  // chunk of records that cover few tiles each
 constexpr int kEmitRounds = 16;
 constexpr int kEmitBatch = kSortWaves * kEmitRounds * 64;   // 4096
 // per wavefront, its 1024 pairs lane-major (lane l walks pairs 16 l .. 16 l + 15), padded to 17
@@ -429,21 +431,60 @@ constexpr int kEmitBatch = kSortWaves * kEmitRounds * 64;   // 4096
 constexpr int kEmitPad = kEmitRounds + 1;
 constexpr int kEmitStageWords = kSortWaves * 64 * kEmitPad;   // 4352 >= kEmitBatch
 
+// views whose first tile id and tiles per row are staged in LDS for the rectangles' view lookup
+// (a batch of more views searches the camera array in global memory). Sized so that the
+// downsweep's LDS (allocated in 512-byte granules) still lets three workgroups share a CU: 256
+// views made it 2 KB larger and cost a third of its occupancy (317 -> 458 us on the 1M batch).
+constexpr int kEmitViews = 128;
+
+template <int RECS>
 struct EmitStage {
-    uint32_t off[kEmitRecs + 1];   // exclusive prefix of the pair counts (+ total)
-    uint32_t base[kEmitRecs];      // global tile id of the first covered tile
-    uint32_t wdt[kEmitRecs];       // rectangle width in tiles
-    uint32_t stride[kEmitRecs];    // tiles per row of the record's view
-    uint32_t rec[kEmitRecs];
+    uint32_t off[RECS + 1];   // exclusive prefix of the pair counts (+ total)
+    uint32_t base[RECS];      // global tile id of the first covered tile
+    uint32_t wdt[RECS];       // rectangle width in tiles
+    uint32_t stride[RECS];    // tiles per row of the record's view
+    uint32_t rec[RECS];
+    uint32_t vbase[kEmitViews];    // the views' first tile ids
+    uint32_t vtx[kEmitViews];      // and tiles per row
 };
 
-// Stages records [r0, r0 + cnt) of the depth order (cnt <= kEmitRecs); returns the chunk's pairs.
+// tiles per row of the view holding global tile id `tile`
+template <int RECS>
+__device__ __forceinline__ uint32_t emit_stride(const EmitStage<RECS>& st, const DevCam* __restrict__ cams, int B,
+                                                uint32_t tile) {
+    if (B > kEmitViews) return (uint32_t)cams[find_view(cams, B, tile)].tiles_x;
+    int lo = 0, hi = B;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (st.vbase[mid] <= tile) lo = mid;
+        else hi = mid;
+    }
+    return st.vtx[lo];
+}
+
+// Stages records [r0, r0 + cnt) of the depth order (cnt <= RECS); returns the chunk's pairs.
+template <int RECS>
 __device__ __forceinline__ uint32_t emit_stage(const uint32_t* __restrict__ sorted_rec,
                                                const uint2* __restrict__ sorted_rect,
                                                const DevCam* __restrict__ cams, int B, uint32_t r0, uint32_t cnt,
-                                               EmitStage& st, uint32_t* scan_tmp) {
-    constexpr int kPer = kEmitRecs / kSortThreads;   // consecutive records per thread
+                                               EmitStage<RECS>& st, uint32_t* scan_tmp) {
+    constexpr int kPer = RECS / kSortThreads;   // consecutive records per thread
     const uint32_t t = threadIdx.x;
+    if ((int)t < B && t < (uint32_t)kEmitViews) {
+        st.vbase[t] = cams[t].tile_base;
+        st.vtx[t] = (uint32_t)cams[t].tiles_x;
+    }
+    uint2 rc[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const uint32_t i = kPer * t + (uint32_t)k;
+        rc[k] = make_uint2(0u, 0u);
+        if (i < cnt) {
+            rc[k] = sorted_rect[r0 + i];
+            st.rec[i] = sorted_rec[r0 + i];
+        }
+    }
+    __syncthreads();   // the view table
     uint32_t c[kPer];
     uint32_t sum = 0;
 #pragma unroll
@@ -451,12 +492,10 @@ __device__ __forceinline__ uint32_t emit_stage(const uint32_t* __restrict__ sort
         const uint32_t i = kPer * t + (uint32_t)k;
         c[k] = 0u;
         if (i < cnt) {
-            const uint2 rc = sorted_rect[r0 + i];
-            st.rec[i] = sorted_rec[r0 + i];
-            c[k] = rect_tiles(rc);
-            st.base[i] = rc.x;
-            st.wdt[i] = rc.y & 0xffffu;
-            st.stride[i] = (uint32_t)cams[find_view(cams, B, rc.x)].tiles_x;
+            c[k] = rect_tiles(rc[k]);
+            st.base[i] = rc[k].x;
+            st.wdt[i] = rc[k].y & 0xffffu;
+            st.stride[i] = emit_stride(st, cams, B, rc[k].x);
         }
         sum += c[k];
     }
@@ -467,7 +506,7 @@ __device__ __forceinline__ uint32_t emit_stage(const uint32_t* __restrict__ sort
         st.off[kPer * t + (uint32_t)k] = ex;
         ex += c[k];
     }
-    if (t == 0) st.off[kEmitRecs] = total;
+    if (t == 0) st.off[RECS] = total;
     __syncthreads();
     return total;
 }
@@ -475,20 +514,21 @@ __device__ __forceinline__ uint32_t emit_stage(const uint32_t* __restrict__ sort
 // the staged record holding pair j of the chunk: the last one whose prefix is <= j (records
 // without pairs are passed over); a fixed number of steps, so that searches of several pairs
 // interleave
-__device__ __forceinline__ uint32_t emit_find(const EmitStage& st, uint32_t cnt, uint32_t j) {
+template <int RECS>
+__device__ __forceinline__ uint32_t emit_find(const EmitStage<RECS>& st, uint32_t cnt, uint32_t j) {
     uint32_t k = 0;
 #pragma unroll
-    for (uint32_t step = kEmitRecs / 2; step > 0; step >>= 1)
+    for (uint32_t step = RECS / 2; step > 0; step >>= 1)
         if (k + step < cnt && st.off[k + step] <= j) k += step;
     return k;
 }
 
 
 // Walks the pairs of the staged chunk from pair j on, row-major over each rectangle.
-template <bool REC>
+template <bool REC, int RECS>
 struct EmitWalk {
     uint32_t k, w, stride, left, col, rowkey, rec;
-    __device__ __forceinline__ void start(const EmitStage& st, uint32_t cnt, uint32_t j) {
+    __device__ __forceinline__ void start(const EmitStage<RECS>& st, uint32_t cnt, uint32_t j) {
         k = emit_find(st, cnt, j);
         if (REC) rec = st.rec[k];
         w = st.wdt[k];
@@ -502,7 +542,7 @@ struct EmitWalk {
     }
     __device__ __forceinline__ uint32_t key() const { return rowkey + col; }
     // to the next pair; the caller knows there is one
-    __device__ __forceinline__ void next(const EmitStage& st) {
+    __device__ __forceinline__ void next(const EmitStage<RECS>& st) {
         if (--left == 0) {
             // the next record: all its fields in one round trip to LDS (records without pairs,
             // which the loop passes over, are rare)
@@ -531,26 +571,27 @@ struct EmitWalk {
 };
 
 // The digit counts of the chunk's pairs.
+template <int RECS>
 __global__ void __launch_bounds__(kSortThreads) k_emit_upsweep(const uint32_t* __restrict__ sorted_rec,
                                                                const uint2* __restrict__ sorted_rect,
                                                                const DevCam* __restrict__ cams, int B, uint32_t n,
                                                                const uint32_t* __restrict__ n_dev, uint32_t mask,
                                                                uint32_t chunks, uint32_t* __restrict__ counts) {
-    __shared__ EmitStage st;
+    __shared__ EmitStage<RECS> st;
     __shared__ uint32_t h[kRadix];
     __shared__ uint32_t scan_tmp[kRadix];
     h[threadIdx.x] = 0;
     n = (uint32_t)count_of(n, n_dev);
-    const uint32_t r0 = blockIdx.x * kEmitRecs;
+    const uint32_t r0 = blockIdx.x * RECS;
     if (r0 < n) {   // uniform over the workgroup
-        const uint32_t cnt = min(n - r0, (uint32_t)kEmitRecs);
+        const uint32_t cnt = min(n - r0, (uint32_t)RECS);
         const uint32_t total = emit_stage(sorted_rec, sorted_rect, cams, B, r0, cnt, st, scan_tmp);
         // each thread counts a contiguous run of pairs, walking the rectangles row-major
         const uint32_t q = (total + kSortThreads - 1) / kSortThreads;
         uint32_t j = threadIdx.x * q;
         const uint32_t jend = min(j + q, total);
         if (j < jend) {
-            EmitWalk<false> wk;
+            EmitWalk<false, RECS> wk;
             wk.start(st, cnt, j);
             for (;;) {
                 atomicAdd(&h[wk.key() & mask], 1u);
@@ -563,12 +604,13 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_upsweep(const uint32_t* _
     if (threadIdx.x <= mask) counts[(size_t)threadIdx.x * chunks + blockIdx.x] = h[threadIdx.x];
 }
 
+template <int RECS>
 __global__ void __launch_bounds__(kSortThreads) k_emit_downsweep(
     const uint32_t* __restrict__ sorted_rec, const uint2* __restrict__ sorted_rect, const DevCam* __restrict__ cams,
     int B, uint32_t n, const uint32_t* __restrict__ n_dev, uint32_t mask, uint32_t chunks,
     const uint32_t* __restrict__ offsets,
     uint32_t K, const uint32_t* __restrict__ K_dev, uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
-    __shared__ EmitStage st;
+    __shared__ EmitStage<RECS> st;
     __shared__ uint32_t wcount[kSortWaves][kRadix];
     __shared__ uint32_t dstart[kRadix];
     __shared__ uint32_t gbase[kRadix];
@@ -579,9 +621,9 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_downsweep(
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     n = (uint32_t)count_of(n, n_dev);
     K = (uint32_t)count_of(K, K_dev);
-    const uint32_t r0 = blockIdx.x * kEmitRecs;
+    const uint32_t r0 = blockIdx.x * RECS;
     if (r0 >= n) return;
-    const uint32_t cnt = min(n - r0, (uint32_t)kEmitRecs);
+    const uint32_t cnt = min(n - r0, (uint32_t)RECS);
     gbase[threadIdx.x] = threadIdx.x <= mask ? offsets[(size_t)threadIdx.x * chunks + blockIdx.x] : 0u;
     const uint32_t total = emit_stage(sorted_rec, sorted_rect, cams, B, r0, cnt, st, scan_tmp);
     for (uint32_t b0 = 0; b0 < total; b0 += kEmitBatch) {
@@ -597,7 +639,7 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_downsweep(
             uint32_t* tv = sval + wave * 64 * kEmitPad + lane * kEmitPad;
             const uint32_t j0 = wbase + (uint32_t)lane * kEmitRounds;
             if (j0 < bn) {
-                EmitWalk<true> wk;
+                EmitWalk<true, RECS> wk;
                 wk.start(st, cnt, b0 + j0);
                 const uint32_t m = min((uint32_t)kEmitRounds, bn - j0);
                 for (uint32_t i = 0;;) {
@@ -713,15 +755,20 @@ void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint2* sorted_rect,
                            size_t n_rec, const uint32_t* n_rec_dev, uint32_t* keys, uint32_t* vals, size_t K,
                            const uint32_t* K_dev, int bits, void* scratch, hipStream_t s) {
     if (n_rec == 0 || K == 0) return;
+    // records covering fewer than four tiles on average: chunks of twice the records
+    const bool small_rects = K < 4 * (size_t)n_rec;
     const PassPlan pl = plan_passes(bits);
-    const size_t chunks = div_up(n_rec, kEmitRecs);
+    const int recs = small_rects ? kEmitRecsSmall : kEmitRecs;
+    const size_t chunks = div_up(n_rec, (size_t)recs);
     uint8_t* p = (uint8_t*)scratch;
     uint32_t* counts = (uint32_t*)p;
     p += align256(chunks * kRadix * sizeof(uint32_t));
-    hipLaunchKernelGGL(k_emit_upsweep, dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rec, sorted_rect,
-                       cams, B, (uint32_t)n_rec, n_rec_dev, pl.mask, (uint32_t)chunks, counts);
+    hipLaunchKernelGGL(small_rects ? k_emit_upsweep<kEmitRecsSmall> : k_emit_upsweep<kEmitRecs>,
+                       dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rec, sorted_rect, cams, B,
+                       (uint32_t)n_rec, n_rec_dev, pl.mask, (uint32_t)chunks, counts);
     scan_exclusive_u32(counts, counts, chunks * ((size_t)pl.mask + 1), nullptr, p, s, nullptr);
-    hipLaunchKernelGGL(k_emit_downsweep, dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rec, sorted_rect,
+    hipLaunchKernelGGL(small_rects ? k_emit_downsweep<kEmitRecsSmall> : k_emit_downsweep<kEmitRecs>,
+                       dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rec, sorted_rect,
                        cams, B, (uint32_t)n_rec, n_rec_dev, pl.mask, (uint32_t)chunks,
                        (const uint32_t*)counts, (uint32_t)K, K_dev, keys, vals);
 }
