@@ -72,7 +72,7 @@ def parse():
     ap.add_argument("--train-only", action="store_true",
                     help="run only the training-iteration comparison and print its JSON (for profiling)")
     ap.add_argument("--copy-mib", type=int, default=0,
-                    help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
+                    help="first run one plain device copy of this many MiB (a reference dispatch for the HBM byte counters)")
     return ap.parse_args()
 
 
