@@ -262,6 +262,8 @@ struct mvgs_context {
     int dwin_bits = 32;
     bool capturing = false;         // the current call's stream is being captured into a graph
     uint64_t* pinned_totals = nullptr;
+    uint64_t* pinned_counts = nullptr;   // readback of mvgs_count_views (grown as needed)
+    size_t pinned_counts_n = 0;
     bool device_used = false;
     UploadRing ring;
 
@@ -586,6 +588,7 @@ void mvgs_destroy(mvgs_context* ctx) {
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->pinned_totals) (void)hipHostFree(ctx->pinned_totals);
+    if (ctx->pinned_counts) (void)hipHostFree(ctx->pinned_counts);
     delete ctx;
 }
 
@@ -1014,7 +1017,9 @@ int mvgs_count_views(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, c
     hipStream_t s = (hipStream_t)stream;
     if (ctx->begin(s)) return ctx->fail(MVGS_EINVAL, "mvgs_count_views synchronizes and cannot be captured");
     HIPCHK(ctx, ctx->bind_device());
-    const Need need[] = {{&ctx->view_counts, sizeof(unsigned long long) * 2 * (size_t)B}};
+    // the counts, then the per-workgroup partials of the pre-pass
+    const size_t counts_b = (sizeof(unsigned long long) * 2 * (size_t)B + 255) & ~(size_t)255;
+    const Need need[] = {{&ctx->view_counts, counts_b + count_views_scratch_bytes(g->P, B)}};
     st = grow_all(ctx, need, 1);
     if (st) return st;
     std::vector<DevCam> hc;
@@ -1022,11 +1027,21 @@ int mvgs_count_views(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, c
     void* dcams = nullptr;
     HIPCHK(ctx, ctx->ring.put(hc.data(), sizeof(DevCam) * B, s, &dcams));
     unsigned long long* dc = as<unsigned long long>(ctx->view_counts);
-    fill_u32(reinterpret_cast<uint32_t*>(dc), 4 * (size_t)B, 0u, s);
-    launch_count_views(gargs(g), (const DevCam*)dcams, B, ctx->tw, ctx->th, dc, s);
+    launch_count_views(gargs(g), (const DevCam*)dcams, B, ctx->tw, ctx->th, dc,
+                       reinterpret_cast<unsigned long long*>(static_cast<uint8_t*>(ctx->view_counts.p) + counts_b), s);
     LAUNCHCHK(ctx, "participation pre-pass");
-    std::vector<unsigned long long> hv(2 * (size_t)B);
-    HIPCHK(ctx, hipMemcpyAsync(hv.data(), dc, sizeof(unsigned long long) * 2 * (size_t)B, hipMemcpyDeviceToHost, s));
+    // read back through pinned memory (a pageable destination costs a staged copy)
+    if (ctx->pinned_counts_n < 2 * (size_t)B) {
+        if (ctx->pinned_counts) HIPCHK(ctx, hipHostFree(ctx->pinned_counts));
+        ctx->pinned_counts = nullptr;
+        ctx->pinned_counts_n = 0;
+        const size_t n = std::max<size_t>(2 * (size_t)B, 64);
+        HIPCHK(ctx, hipHostMalloc((void**)&ctx->pinned_counts, n * sizeof(uint64_t), hipHostMallocDefault));
+        ctx->pinned_counts_n = n;
+    }
+    const uint64_t* hv = ctx->pinned_counts;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->pinned_counts, dc, sizeof(unsigned long long) * 2 * (size_t)B,
+                               hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, ctx->ring.seal(s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     for (int v = 0; v < B; ++v) {

@@ -5,6 +5,8 @@
 // One thread per Gaussian loops over all views of the batch, so each Gaussian's
 // parameters are read from HBM once per step whatever the number of views; the
 // cameras are uniform across the wave and come in through the scalar cache.
+#include <algorithm>
+
 #include "mvgs_kernels.h"
 
 namespace mvgs {
@@ -71,16 +73,20 @@ __global__ void __launch_bounds__(256) k_count(const float* __restrict__ means, 
 
 // Participation pre-pass per view, for admission before anything is sized: the records (1 per
 // participating Gaussian) and covered tiles of each view, summed over the Gaussians. One thread per
-// Gaussian walks the views; per view a wavefront sum, then one 64-bit atomic per wavefront and
-// count (counts[2v] records, counts[2v+1] pairs).
+// Gaussian walks the views; per view a wavefront sum, the workgroup's four wavefront sums added in
+// LDS, and one partial per workgroup, view and count (partial[(2 v + c) * blocks + block]); a
+// second kernel adds each row of partials. (One 64-bit atomic per wavefront into the same two
+// words per view serialised on one L2 channel: 0.4 ms for 1M Gaussians.)
 __global__ void __launch_bounds__(256) k_count_views(const float* __restrict__ means,
                                                      const float* __restrict__ scales,
                                                      const float* __restrict__ quats,
                                                      const float* __restrict__ opac, int64_t P,
                                                      const DevCam* __restrict__ cams, int B, int tile_w, int tile_h,
-                                                     unsigned long long* __restrict__ counts) {
+                                                     unsigned long long* __restrict__ partial) {
+    __shared__ uint32_t red[2][4];
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = g < P;
+    const int wave = threadIdx.x >> 6;
     float mu[3] = {0.f, 0.f, 0.f}, s[3] = {0.f, 0.f, 0.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, o = 0.f;
     if (live) load_gaussian(means, scales, quats, opac, g, mu, s, q, o);
     for (int v = 0; v < B; ++v) {
@@ -93,16 +99,36 @@ __global__ void __launch_bounds__(256) k_count_views(const float* __restrict__ m
                 nt = (uint32_t)((p.x1 / tile_w - p.x0 / tile_w + 1) * (p.y1 / tile_h - p.y0 / tile_h + 1));
             }
         }
-        // at most 64 x 65,536 tiles per wavefront: the sums fit 32 bits
+        // at most 256 x 65,536 tiles per workgroup: the sums fit 32 bits
         for (int off = 32; off > 0; off >>= 1) {
             n += (uint32_t)__shfl_xor((int)n, off, 64);
             nt += (uint32_t)__shfl_xor((int)nt, off, 64);
         }
-        if ((threadIdx.x & 63) == 0 && n) {
-            atomicAdd(counts + 2 * v, (unsigned long long)n);
-            atomicAdd(counts + 2 * v + 1, (unsigned long long)nt);
+        if ((threadIdx.x & 63) == 0) {
+            red[0][wave] = n;
+            red[1][wave] = nt;
         }
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            const uint32_t* r = red[threadIdx.x];
+            partial[(size_t)(2 * v + threadIdx.x) * gridDim.x + blockIdx.x] =
+                (unsigned long long)r[0] + r[1] + r[2] + r[3];
+        }
+        __syncthreads();
     }
+}
+
+// counts[k] = sum of row k of the partials (rows of `blocks` values), one workgroup per row
+__global__ void __launch_bounds__(256) k_sum_rows_u64(const unsigned long long* __restrict__ partial,
+                                                      uint32_t blocks, unsigned long long* __restrict__ counts) {
+    __shared__ unsigned long long red[4];
+    const unsigned long long* row = partial + (size_t)blockIdx.x * blocks;
+    unsigned long long s = 0;
+    for (uint32_t i = threadIdx.x; i < blocks; i += 256) s += row[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) counts[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 // The per-record arrays beside the record itself: view, depth key and covered-tile rectangle
@@ -380,12 +406,25 @@ void launch_count(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int
                        B, tw, th, nrec, ntiles, key_range);
 }
 
+__global__ void k_fill_u64_small(unsigned long long* __restrict__ p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
+}
+
+size_t count_views_scratch_bytes(int64_t P, int B) {
+    return sizeof(unsigned long long) * 2 * (size_t)B * (size_t)std::max<int64_t>((P + 255) / 256, 1);
+}
+
 void launch_count_views(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th,
-                        unsigned long long* counts, hipStream_t s) {
+                        unsigned long long* counts, unsigned long long* scratch, hipStream_t s) {
     const unsigned blocks = (unsigned)((ga.P + 255) / 256);
-    if (!blocks) return;
+    if (!blocks) {
+        hipLaunchKernelGGL(k_fill_u64_small, dim3(1), dim3(64), 0, s, counts, 2 * B);
+        return;
+    }
     hipLaunchKernelGGL(k_count_views, dim3(blocks), dim3(256), 0, s, ga.means, ga.scales, ga.quats, ga.opac, ga.P,
-                       cams, B, tw, th, counts);
+                       cams, B, tw, th, scratch);
+    hipLaunchKernelGGL(k_sum_rows_u64, dim3(2 * B), dim3(256), 0, s, (const unsigned long long*)scratch, blocks,
+                       counts);
 }
 
 void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,

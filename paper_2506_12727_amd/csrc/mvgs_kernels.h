@@ -35,9 +35,11 @@ struct GradArgs {
 void launch_count(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, uint32_t* nrec,
                   uint32_t* ntiles, hipStream_t s, uint32_t* key_range = nullptr);
 // overflow: null, or a device word that, when non-zero, makes the kernel write nothing
-// per-view participating records and covered tiles (counts [B][2], accumulated with +=)
+// per-view participating records and covered tiles (counts [B][2], written), through per-workgroup
+// partials in scratch (count_views_scratch_bytes)
+size_t count_views_scratch_bytes(int64_t P, int B);
 void launch_count_views(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th,
-                        unsigned long long* counts, hipStream_t s);
+                        unsigned long long* counts, unsigned long long* scratch, hipStream_t s);
 void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,
                     BlendRec* recs, uint32_t* depth_key, uint2* tile_rect, uint16_t* rec_view, hipStream_t s,
                     const uint32_t* overflow = nullptr);
