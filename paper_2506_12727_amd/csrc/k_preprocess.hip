@@ -33,10 +33,12 @@ __global__ void __launch_bounds__(256) k_count(const float* __restrict__ means, 
     if (g < P) {
         float mu[3], s[3], q[4], o;
         load_gaussian(means, scales, quats, opac, g, mu, s, q, o);
+        GaussGeom geo;
+        gauss_geom(s, q, o, geo);
         uint32_t n = 0, nt = 0;
         for (int v = 0; v < B; ++v) {
             ProjState st;
-            const ProjOut p = project(mu, s, q, o, cams[v], st);
+            const ProjOut p = project(mu, geo, cams[v], st);
             if (p.ok) {
                 n += 1;
                 nt += (uint32_t)((p.x1 / tile_w - p.x0 / tile_w + 1) * (p.y1 / tile_h - p.y0 / tile_h + 1));
@@ -89,11 +91,13 @@ __global__ void __launch_bounds__(256) k_count_views(const float* __restrict__ m
     const int wave = threadIdx.x >> 6;
     float mu[3] = {0.f, 0.f, 0.f}, s[3] = {0.f, 0.f, 0.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, o = 0.f;
     if (live) load_gaussian(means, scales, quats, opac, g, mu, s, q, o);
+    GaussGeom geo;
+    gauss_geom(s, q, o, geo);
     for (int v = 0; v < B; ++v) {
         uint32_t n = 0, nt = 0;
         if (live) {
             ProjState st;
-            const ProjOut p = project(mu, s, q, o, cams[v], st);
+            const ProjOut p = project(mu, geo, cams[v], st);
             if (p.ok) {
                 n = 1;
                 nt = (uint32_t)((p.x1 / tile_w - p.x0 / tile_w + 1) * (p.y1 / tile_h - p.y0 / tile_h + 1));
@@ -178,12 +182,14 @@ __global__ void __launch_bounds__(64) k_records(const float* __restrict__ means,
         for (int k = 0; k < K; ++k)
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) coef[k][ch] = sh[(g * K + k) * 3 + ch];
+        GaussGeom geo;
+        gauss_geom(s, q, o, geo);
         uint32_t out = rec_off[g];
         const uint32_t out_end = rec_off[g + 1];
         for (int v = 0; v < B && out < out_end; ++v) {
             const DevCam& c = cams[v];
             ProjState st;
-            const ProjOut p = project(mu, s, q, o, c, st);
+            const ProjOut p = project(mu, geo, c, st);
             if (!p.ok) continue;
             float dx = mu[0] - c.campos[0], dy = mu[1] - c.campos[1], dz = mu[2] - c.campos[2];
             const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
@@ -252,6 +258,8 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(
     float dmu[3] = {0, 0, 0}, ds[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dop = 0.0f;
     float se1 = 0.0f, se2 = 0.0f;
     const uint32_t r0 = rec_off[g], r1 = (overflow && *overflow) ? r0 : rec_off[g + 1];
+    GaussGeom geo;
+    gauss_geom(s, q, o, geo);
     for (uint32_t ri = r0; ri < r1; ++ri) {
         const uint32_t v = rec_view[ri];
         const DevCam& c = cams[v];
@@ -262,7 +270,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(
         const float gcc = a1.x, gop = a1.y, gr = a1.z, gg = a1.w;
         const float gb = a2.x, ge1 = a2.y;
         ProjState st;
-        (void)project(mu, s, q, o, c, st);
+        (void)project(mu, geo, c, st);
         dop += gop;
         // statistics (NDC = pixel gradient times (W/2, H/2))
         const float nx = gmx * 0.5f * (float)c.W, ny = gmy * 0.5f * (float)c.H;

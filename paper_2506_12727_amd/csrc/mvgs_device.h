@@ -111,10 +111,57 @@ struct ProjOut {
     int32_t x0, x1, y0, y1;
 };
 
-// EWA projection of one Gaussian into one camera (paper Sec. 3), in the fixed
-// operation order described at the top of this file.
-__device__ __forceinline__ ProjOut project(const float mu[3], const float s[3], const float q[4], float o,
-                                           const DevCam& c, ProjState& st) {
+// The view-independent part of the projection (paper Sec. 3): normalised quaternion, its
+// rotation, Sigma = R S S^T R^T, and the cut and clamp thresholds of the opacity. Computed once
+// per Gaussian; project() below then works view by view. The operations are those of the fixed
+// order described at the top of this file, only not repeated per view.
+struct GaussGeom {
+    bool ok;                          // the quaternion is not degenerate
+    float qw, qx, qy, qz, qinv;
+    float rot[9];
+    float S[6];                       // Sigma: xx xy xz yy yz zz
+    float cut, hi;
+};
+
+__device__ __forceinline__ void gauss_geom(const float s[3], const float q[4], float o, GaussGeom& g) {
+    const float n2 = __builtin_fmaf(q[0], q[0], __builtin_fmaf(q[1], q[1], __builtin_fmaf(q[2], q[2], q[3] * q[3])));
+    g.ok = n2 > 0.0f;
+    const float inv = 1.0f / sqrtf(n2);
+    g.qinv = inv;
+    const float qw = q[0] * inv, qx = q[1] * inv, qy = q[2] * inv, qz = q[3] * inv;
+    g.qw = qw; g.qx = qx; g.qy = qy; g.qz = qz;
+    const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
+    const float xy = qx * qy, xz = qx * qz, yz = qy * qz;
+    const float wx = qw * qx, wy = qw * qy, wz = qw * qz;
+    float* r = g.rot;
+    r[0] = 1.0f - 2.0f * (yy + zz);
+    r[1] = 2.0f * (xy - wz);
+    r[2] = 2.0f * (xz + wy);
+    r[3] = 2.0f * (xy + wz);
+    r[4] = 1.0f - 2.0f * (xx + zz);
+    r[5] = 2.0f * (yz - wx);
+    r[6] = 2.0f * (xz - wy);
+    r[7] = 2.0f * (yz + wx);
+    r[8] = 1.0f - 2.0f * (xx + yy);
+    float M[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) M[3 * i + j] = r[3 * i + j] * s[j];
+    g.S[0] = __builtin_fmaf(M[0], M[0], __builtin_fmaf(M[1], M[1], M[2] * M[2]));
+    g.S[1] = __builtin_fmaf(M[0], M[3], __builtin_fmaf(M[1], M[4], M[2] * M[5]));
+    g.S[2] = __builtin_fmaf(M[0], M[6], __builtin_fmaf(M[1], M[7], M[2] * M[8]));
+    g.S[3] = __builtin_fmaf(M[3], M[3], __builtin_fmaf(M[4], M[4], M[5] * M[5]));
+    g.S[4] = __builtin_fmaf(M[3], M[6], __builtin_fmaf(M[4], M[7], M[5] * M[8]));
+    g.S[5] = __builtin_fmaf(M[6], M[6], __builtin_fmaf(M[7], M[7], M[8] * M[8]));
+    const float lc = -ln_threshold(kAlphaMin * o);
+    g.cut = (lc > kPowerFloor) ? lc : kPowerFloor;
+    g.hi = ln_threshold(kAlphaMax / o);
+}
+
+// EWA projection of one Gaussian (its view-independent part in g) into one camera (paper Sec. 3),
+// in the fixed operation order described at the top of this file.
+__device__ __forceinline__ ProjOut project(const float mu[3], const GaussGeom& g, const DevCam& c, ProjState& st) {
     ProjOut out;
     out.ok = false;
     const float tx = __builtin_fmaf(c.R[0], mu[0], __builtin_fmaf(c.R[1], mu[1], __builtin_fmaf(c.R[2], mu[2], c.t[0])));
@@ -130,37 +177,12 @@ __device__ __forceinline__ ProjOut project(const float mu[3], const float s[3], 
     out.mx = __builtin_fmaf(u, iz, c.cx);
     out.my = __builtin_fmaf(w, iz, c.cy);
 
-    const float n2 = __builtin_fmaf(q[0], q[0], __builtin_fmaf(q[1], q[1], __builtin_fmaf(q[2], q[2], q[3] * q[3])));
-    if (!(n2 > 0.0f)) return out;
-    const float inv = 1.0f / sqrtf(n2);
-    st.qinv = inv;
-    const float qw = q[0] * inv, qx = q[1] * inv, qy = q[2] * inv, qz = q[3] * inv;
-    st.qw = qw; st.qx = qx; st.qy = qy; st.qz = qz;
-    const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
-    const float xy = qx * qy, xz = qx * qz, yz = qy * qz;
-    const float wx = qw * qx, wy = qw * qy, wz = qw * qz;
-    float* r = st.rot;
-    r[0] = 1.0f - 2.0f * (yy + zz);
-    r[1] = 2.0f * (xy - wz);
-    r[2] = 2.0f * (xz + wy);
-    r[3] = 2.0f * (xy + wz);
-    r[4] = 1.0f - 2.0f * (xx + zz);
-    r[5] = 2.0f * (yz - wx);
-    r[6] = 2.0f * (xz - wy);
-    r[7] = 2.0f * (yz + wx);
-    r[8] = 1.0f - 2.0f * (xx + yy);
-
-    float M[9];
+    if (!g.ok) return out;
+    st.qinv = g.qinv;
+    st.qw = g.qw; st.qx = g.qx; st.qy = g.qy; st.qz = g.qz;
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) M[3 * i + j] = r[3 * i + j] * s[j];
-    const float S00 = __builtin_fmaf(M[0], M[0], __builtin_fmaf(M[1], M[1], M[2] * M[2]));
-    const float S01 = __builtin_fmaf(M[0], M[3], __builtin_fmaf(M[1], M[4], M[2] * M[5]));
-    const float S02 = __builtin_fmaf(M[0], M[6], __builtin_fmaf(M[1], M[7], M[2] * M[8]));
-    const float S11 = __builtin_fmaf(M[3], M[3], __builtin_fmaf(M[4], M[4], M[5] * M[5]));
-    const float S12 = __builtin_fmaf(M[3], M[6], __builtin_fmaf(M[4], M[7], M[5] * M[8]));
-    const float S22 = __builtin_fmaf(M[6], M[6], __builtin_fmaf(M[7], M[7], M[8] * M[8]));
+    for (int k = 0; k < 9; ++k) st.rot[k] = g.rot[k];
+    const float S00 = g.S[0], S01 = g.S[1], S02 = g.S[2], S11 = g.S[3], S12 = g.S[4], S22 = g.S[5];
     st.S[0] = S00; st.S[1] = S01; st.S[2] = S02; st.S[3] = S11; st.S[4] = S12; st.S[5] = S22;
     const float Sm[9] = {S00, S01, S02, S01, S11, S12, S02, S12, S22};
 
@@ -195,9 +217,8 @@ __device__ __forceinline__ ProjOut project(const float mu[3], const float s[3], 
     out.nb = -cb;
     out.hcc = -0.5f * cc;
 
-    const float lc = -ln_threshold(kAlphaMin * o);
-    out.cut = (lc > kPowerFloor) ? lc : kPowerFloor;
-    out.hi = ln_threshold(kAlphaMax / o);
+    out.cut = g.cut;
+    out.hi = g.hi;
 
     // footprint: per-axis half-extents of the cut ellipse {d : -0.5 d^T conic d >= cut},
     // sqrt(-2 cut Sigma'_xx) and sqrt(-2 cut Sigma'_yy), in whole pixels
@@ -219,6 +240,14 @@ __device__ __forceinline__ ProjOut project(const float mu[3], const float s[3], 
     out.y1 = (int32_t)y1;
     out.ok = true;
     return out;
+}
+
+// The projection of one Gaussian into one camera from its parameters.
+__device__ __forceinline__ ProjOut project(const float mu[3], const float s[3], const float q[4], float o,
+                                           const DevCam& c, ProjState& st) {
+    GaussGeom g;
+    gauss_geom(s, q, o, g);
+    return project(mu, g, c, st);
 }
 
 // power = -0.5 d^T conic d at pixel (px, py), d = pixel centre - mean: the cut test's operand,
