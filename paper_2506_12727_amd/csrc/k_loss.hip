@@ -97,7 +97,7 @@ struct SsimLds {
         float abc[3][kSsimA][kSsimA];  // derivative maps (after the moments along x)
     } u;
     union {
-        float hs[5][kSsimI][kSsimA];   // moments along x
+        float hs[2][kSsimI][kSsimA];   // moments along x (two at a time)
         float hb[3][kSsimA][kSsimTile];  // derivative maps along x
     } v;
     float red[2][kSsimThreads / 64];
@@ -128,58 +128,70 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_fused(const float* __rest
         L.u.in[1][r][c] = in ? b[q] : 0.0f;
     }
     __syncthreads();
-    // 2. moments along x: row r, columns j .. j + 6 of the 42 (a run of 7 per task)
-    for (int task = t; task < kSsimI * 6; task += kSsimThreads) {
-        const int r = task / 6, j0 = (task - r * 6) * 7;
-        float u[17], v[17];
-#pragma unroll
-        for (int k = 0; k < 17; ++k) {
-            u[k] = L.u.in[0][r][j0 + k];
-            v[k] = L.u.in[1][r][j0 + k];
-        }
-#pragma unroll
-        for (int jj = 0; jj < 7; ++jj) {
-            float m0 = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0;
-#pragma unroll
-            for (int k = 0; k < 11; ++k) {
-                const float uu = u[jj + k], vv = v[jj + k], w = win.w[k];
-                const float wu = w * uu, wv = w * vv;
-                m0 = __builtin_fmaf(w, uu, m0);
-                m1 = __builtin_fmaf(w, vv, m1);
-                m2 = __builtin_fmaf(wu, uu, m2);
-                m3 = __builtin_fmaf(wv, vv, m3);
-                m4 = __builtin_fmaf(wu, vv, m4);
-            }
-            L.v.hs[0][r][j0 + jj] = m0;
-            L.v.hs[1][r][j0 + jj] = m1;
-            L.v.hs[2][r][j0 + jj] = m2;
-            L.v.hs[3][r][j0 + jj] = m3;
-            L.v.hs[4][r][j0 + jj] = m4;
-        }
-    }
-    __syncthreads();
-    // 3. moments along y, SSIM and its derivative maps at the 42x42 positions p = (x0 - 5 + j,
-    // y0 - 5 + i): column j, rows i .. i + 6 per task; SSIM summed over the tile's own pixels
-    float ssim_sum = 0.0f;
+    // 2.-3. the five moments along x (row r, columns j .. j + 6 of the 42 per task) and then along
+    // y (column j, rows i .. i + 6 per task) at the 42x42 positions p = (x0 - 5 + j, y0 - 5 + i),
+    // in three rounds (I and T; I^2 and T^2; I T) so that the moments along x take two maps of LDS
+    // instead of five: the workgroup then fits four times per CU instead of twice
     float mom[5][7];
     int j = 0, i0 = 0;
     const bool task3 = t < kSsimA * 6;
     if (task3) {
         j = t / 6;
         i0 = (t - j * 6) * 7;
+    }
 #pragma unroll
-        for (int m = 0; m < 5; ++m) {
-            float h[17];
+    for (int round = 0; round < 3; ++round) {
+        for (int task = t; task < kSsimI * 6; task += kSsimThreads) {
+            const int r = task / 6, j0 = (task - r * 6) * 7;
+            float u[17], v[17];
 #pragma unroll
-            for (int k = 0; k < 17; ++k) h[k] = L.v.hs[m][i0 + k][j];
+            for (int k = 0; k < 17; ++k) {
+                u[k] = L.u.in[0][r][j0 + k];
+                v[k] = L.u.in[1][r][j0 + k];
+            }
 #pragma unroll
-            for (int ii = 0; ii < 7; ++ii) {
-                float acc = 0.0f;
+            for (int jj = 0; jj < 7; ++jj) {
+                float m0 = 0, m1 = 0;
 #pragma unroll
-                for (int k = 0; k < 11; ++k) acc = __builtin_fmaf(win.w[k], h[ii + k], acc);
-                mom[m][ii] = acc;
+                for (int k = 0; k < 11; ++k) {
+                    const float uu = u[jj + k], vv = v[jj + k], w = win.w[k];
+                    if (round == 0) {
+                        m0 = __builtin_fmaf(w, uu, m0);
+                        m1 = __builtin_fmaf(w, vv, m1);
+                    } else if (round == 1) {
+                        const float wu = w * uu, wv = w * vv;
+                        m0 = __builtin_fmaf(wu, uu, m0);
+                        m1 = __builtin_fmaf(wv, vv, m1);
+                    } else {
+                        const float wu = w * uu;
+                        m0 = __builtin_fmaf(wu, vv, m0);
+                    }
+                }
+                L.v.hs[0][r][j0 + jj] = m0;
+                if (round < 2) L.v.hs[1][r][j0 + jj] = m1;
             }
         }
+        __syncthreads();
+        if (task3) {
+#pragma unroll
+            for (int m = 0; m < (round < 2 ? 2 : 1); ++m) {
+                float h[17];
+#pragma unroll
+                for (int k = 0; k < 17; ++k) h[k] = L.v.hs[m][i0 + k][j];
+#pragma unroll
+                for (int ii = 0; ii < 7; ++ii) {
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < 11; ++k) acc = __builtin_fmaf(win.w[k], h[ii + k], acc);
+                    mom[2 * round + m][ii] = acc;
+                }
+            }
+        }
+        __syncthreads();   // (the maps are overwritten by the next round; after the last, the inputs are free)
+    }
+    // SSIM and its derivative maps; SSIM summed over the tile's own pixels
+    float ssim_sum = 0.0f;
+    if (task3) {
         // (the inputs are no longer read: the derivative maps take their place)
         const int px = x0 - 5 + j;
         const bool own_col = j >= 5 && j < 5 + kSsimTile && px < W;

@@ -42,6 +42,10 @@ CASES = {
     "ragged_16x32_ppl4": lambda: _ragged(1, -3.1) + ((16, 32), 4),
     "ragged_32x32_ppl4": lambda: _ragged(3, -2.8) + ((32, 32), 4),
     "ragged_8x32_ppl2": lambda: _ragged(3, -3.0) + ((8, 32), 2),
+    # more views than the emission's LDS table of view tile bases holds (its global-memory search),
+    # with records that cover few tiles each (the 1,024-record emission chunks)
+    "many_views": lambda: (scenes.make_scene(3000, 1, log_scale_mean=-3.6),
+                           scenes.make_cameras([(24, 20), (17, 31)] * 70, seed=23), (16, 16), 0),
 }
 
 
