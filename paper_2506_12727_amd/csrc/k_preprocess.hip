@@ -418,8 +418,12 @@ __global__ void k_fill_u64_small(unsigned long long* __restrict__ p, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
 }
 
+// views per launch of the pre-pass (bounds its scratch to 2 x 64 partials per workgroup)
+constexpr int kCountViewsChunk = 64;
+
 size_t count_views_scratch_bytes(int64_t P, int B) {
-    return sizeof(unsigned long long) * 2 * (size_t)B * (size_t)std::max<int64_t>((P + 255) / 256, 1);
+    return sizeof(unsigned long long) * 2 * (size_t)std::min(B, kCountViewsChunk) *
+           (size_t)std::max<int64_t>((P + 255) / 256, 1);
 }
 
 void launch_count_views(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th,
@@ -429,10 +433,13 @@ void launch_count_views(const GaussianArgs& ga, const DevCam* cams, int B, int t
         hipLaunchKernelGGL(k_fill_u64_small, dim3(1), dim3(64), 0, s, counts, 2 * B);
         return;
     }
-    hipLaunchKernelGGL(k_count_views, dim3(blocks), dim3(256), 0, s, ga.means, ga.scales, ga.quats, ga.opac, ga.P,
-                       cams, B, tw, th, scratch);
-    hipLaunchKernelGGL(k_sum_rows_u64, dim3(2 * B), dim3(256), 0, s, (const unsigned long long*)scratch, blocks,
-                       counts);
+    for (int v0 = 0; v0 < B; v0 += kCountViewsChunk) {
+        const int nb = std::min(kCountViewsChunk, B - v0);
+        hipLaunchKernelGGL(k_count_views, dim3(blocks), dim3(256), 0, s, ga.means, ga.scales, ga.quats, ga.opac,
+                           ga.P, cams + v0, nb, tw, th, scratch);
+        hipLaunchKernelGGL(k_sum_rows_u64, dim3(2 * nb), dim3(256), 0, s, (const unsigned long long*)scratch, blocks,
+                           counts + 2 * (size_t)v0);
+    }
 }
 
 void launch_records(const GaussianArgs& ga, const DevCam* cams, int B, int tw, int th, const uint32_t* rec_off,

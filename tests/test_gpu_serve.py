@@ -3,6 +3,7 @@ with it and while other slots render, equals the same view rendered alone, bit f
 budget holds; slots overlap."""
 import math
 
+import numpy as np
 import pytest
 import torch
 
@@ -89,6 +90,10 @@ def test_workspace_bound_is_exact():
     cams = scenes.make_cameras([(160, 120), (320, 180), (96, 200)])
     r = Rasterizer((16, 16))
     rec, pairs = r.count_views(g, cams)
+    # more views than one launch of the pre-pass takes (64): the same counts view by view
+    many = cams * 23
+    rec_m, pairs_m = r.count_views(g, many)
+    assert np.array_equal(rec_m, np.tile(rec, 23)) and np.array_equal(pairs_m, np.tile(pairs, 23))
     for v in range(len(cams)):
         _, fr = r.forward(g, [cams[v]])
         info = fr.info()
