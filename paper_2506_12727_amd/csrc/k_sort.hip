@@ -10,7 +10,7 @@
 // the bits in which the keys differ, and the first pass of the tile sort is fused with emission.
 //
 // Radix sort: LSD, digits of at most 8 bits spread evenly over the passes, 8192 items per
-// partition (4 wavefronts x 32 rounds x 64 lanes). Each pass reduces, scans, then scatters: one
+// partition (8 wavefronts x 16 rounds x 64 lanes in the scatter). Each pass reduces, scans, then scatters: one
 // workgroup per partition counts its digits (LDS counters) into a digit-major table, one exclusive
 // scan of that table gives every (digit, partition) its output base, and one workgroup per
 // partition ranks its items stably with wave64 ballots, stages them in LDS in digit order and
@@ -32,6 +32,10 @@ constexpr int kSortRounds = 32;
 constexpr int kSortThreads = kSortWaves * 64;
 constexpr int kSortTile = kSortWaves * kSortRounds * 64;  // 8192
 constexpr int kRadix = 256;
+// wavefronts of the downsweeps: 8 x 16 rounds over the same 8192-item partition fit four waves
+// per SIMD (4 x 32 rounds: two); the payload's digit bytes share the count table's LDS
+constexpr int kPlainWaves = 8;
+constexpr int kPayWaves = 8;
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -43,10 +47,13 @@ __global__ void k_fill_u64(uint64_t* __restrict__ p, size_t n, uint64_t v) {
     if (i < n) p[i] = v;
 }
 
-// exclusive scan of 256 values held one per thread (a workgroup of 256): each wavefront scans its
-// 64 values with shuffles, then the four wavefront totals are combined through LDS (lds: at least
-// 4 words). Returns the exclusive prefix and sets *total; lds may be reused on return.
-__device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_t* lds, uint32_t* total) {
+// exclusive scan of one value per thread over a workgroup of THREADS (a multiple of 64): each
+// wavefront scans its 64 values with shuffles, then the wavefront totals are combined through LDS
+// (lds: at least THREADS / 64 words). Returns the exclusive prefix and sets *total; lds may be
+// reused on return.
+template <int THREADS>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds, uint32_t* total) {
+    constexpr int WAVES = THREADS / 64;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     uint32_t x = v;
 #pragma unroll
@@ -56,11 +63,20 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_
     }
     if (lane == 63) lds[wave] = x;
     __syncthreads();
-    const uint32_t w0 = lds[0], w1 = lds[1], w2 = lds[2], w3 = lds[3];
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        const uint32_t c = lds[w];
+        before += w < wave ? c : 0u;
+        all += c;
+    }
     __syncthreads();
-    *total = w0 + w1 + w2 + w3;
-    const uint32_t before = (wave > 0 ? w0 : 0u) + (wave > 1 ? w1 : 0u) + (wave > 2 ? w2 : 0u);
+    *total = all;
     return before + x - v;
+}
+
+__device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_t* lds, uint32_t* total) {
+    return block_exclusive_scan<256>(v, lds, total);
 }
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t* __restrict__ in, size_t n,
@@ -188,14 +204,15 @@ void scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint64_t* t
 // radix sort
 // ---------------------------------------------------------------------------------------------
 
-// lanes of this wave holding the same 8-bit digit (among `valid` lanes): per bit, the lane's bit
+// lanes of this wave holding the same digit of nbits <= 8 bits (among `valid` lanes): per bit, the lane's bit
 // spread over a word (0 or ~0) is both the ballot's predicate and the mask that keeps the ballot
 // or its complement, so the update is one three-input logic op per half of the peer mask
-__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int nbits) {
     const uint64_t v = ballot64(valid);
     uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
+        if (b >= nbits) break;   // uniform: one ballot per bit of the pass's digit
         const uint32_t splat = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
         const uint64_t m = ballot64((int32_t)splat < 0);
         lo &= ~((uint32_t)m ^ splat);
@@ -240,13 +257,21 @@ __global__ void __launch_bounds__(256) k_radix_upsweep(const uint32_t* __restric
 // digit order to the bases the scan gave. PAY: an 8-byte payload per item follows its key, staged
 // through the same LDS after the keys and values are out (the digits of the staged order kept
 // aside for it).
-template <bool PAY>
-__global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
+template <bool PAY, int WAVES>
+__global__ void __launch_bounds__(WAVES * 64) k_radix_downsweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const uint2* __restrict__ pay_in, uint2* __restrict__ pay_out, size_t n,
     const uint32_t* __restrict__ n_dev, uint32_t key_base, int shift, uint32_t mask, uint32_t parts,
     const uint32_t* __restrict__ offsets) {
-    __shared__ uint32_t wcount[kSortWaves][kRadix];
+    constexpr int ROUNDS = kSortTile / (WAVES * 64);
+    constexpr int THREADS = WAVES * 64;
+    // the per-wavefront digit counts; once the items are staged, PAY keeps the digit of every
+    // staged position in the same bytes
+    __shared__ union {
+        uint32_t wcount[WAVES][kRadix];
+        uint8_t sdig[kSortTile];
+    } cd;
+    auto& wcount = cd.wcount;
     __shared__ uint32_t dstart[kRadix];
     __shared__ uint32_t gbase[kRadix];
     __shared__ uint32_t scan_tmp[kRadix];
@@ -257,29 +282,29 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
         } kv;
         uint2 p[kSortTile];
     } stg;
-    __shared__ uint8_t sdig[PAY ? kSortTile : 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortThreads) (&wcount[0][0])[d] = 0;
+    const int nbits = 32 - __builtin_clz(mask | 1u);   // bits of this pass's digit
+    for (int d = threadIdx.x; d < WAVES * kRadix; d += THREADS) (&wcount[0][0])[d] = 0;
     const uint32_t part = blockIdx.x;
     n = count_of(n, n_dev);
     if ((size_t)part * kSortTile >= n) return;
-    gbase[threadIdx.x] = threadIdx.x <= mask ? offsets[(size_t)threadIdx.x * parts + part] : 0u;
+    if (threadIdx.x < kRadix) gbase[threadIdx.x] = threadIdx.x <= mask ? offsets[(size_t)threadIdx.x * parts + part] : 0u;
     __syncthreads();
-    const size_t base = (size_t)part * kSortTile + (size_t)wave * kSortRounds * 64;
-    uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
+    const size_t base = (size_t)part * kSortTile + (size_t)wave * ROUNDS * 64;
+    uint32_t key[ROUNDS], val[ROUNDS], rank[ROUNDS];
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
+    for (int r = 0; r < ROUNDS; ++r) {
         const size_t i = base + (size_t)r * 64 + lane;
         const bool valid = i < n;
         key[r] = valid ? keys_in[i] : 0xffffffffu;
         val[r] = valid ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
     }
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
+    for (int r = 0; r < ROUNDS; ++r) {
         const size_t i = base + (size_t)r * 64 + lane;
         const bool valid = i < n;
         const uint32_t d = ((key[r] - key_base) >> shift) & mask;
-        const uint64_t peers = digit_peers(d, valid);
+        const uint64_t peers = digit_peers(d, valid, nbits);
         const uint32_t below = (uint32_t)rank_below(peers);
         const uint32_t before = wcount[wave][d];
         rank[r] = before + below;
@@ -289,33 +314,43 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     }
     __syncthreads();
     {
+        // digit d = threadIdx.x (threads past the 256 digits join the scan with 0)
         const int d = threadIdx.x;
         uint32_t run = 0;
+        if (d < kRadix) {
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) {
-            const uint32_t c = wcount[w][d];
-            wcount[w][d] = run;
-            run += c;
+            for (int w = 0; w < WAVES; ++w) {
+                const uint32_t c = wcount[w][d];
+                wcount[w][d] = run;
+                run += c;
+            }
         }
         uint32_t total;
-        dstart[d] = block_exclusive_scan_256(run, scan_tmp, &total);
+        const uint32_t ex = block_exclusive_scan<THREADS>(run, scan_tmp, &total);
+        if (d < kRadix) dstart[d] = ex;
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
+    for (int r = 0; r < ROUNDS; ++r) {
         const size_t i = base + (size_t)r * 64 + lane;
         if (i < n) {
             const uint32_t d = ((key[r] - key_base) >> shift) & mask;
             const uint32_t pos = dstart[d] + wcount[wave][d] + rank[r];
             stg.kv.k[pos] = key[r];
             stg.kv.v[pos] = val[r];
-            if (PAY) sdig[pos] = (uint8_t)d;
             rank[r] = pos;
         }
     }
-    __syncthreads();
+    __syncthreads();   // (the counts are read for the last time above)
+    if (PAY) {
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            const size_t i = base + (size_t)r * 64 + lane;
+            if (i < n) cd.sdig[rank[r]] = (uint8_t)(((key[r] - key_base) >> shift) & mask);
+        }
+    }
     const size_t tile_n = std::min<size_t>((size_t)kSortTile, n - (size_t)part * kSortTile);
-    for (int j = threadIdx.x; j < (int)tile_n; j += kSortThreads) {
+    for (int j = threadIdx.x; j < (int)tile_n; j += THREADS) {
         const uint32_t k = stg.kv.k[j];
         const uint32_t d = ((k - key_base) >> shift) & mask;
         const size_t dst = (size_t)gbase[d] + (uint32_t)(j - dstart[d]);
@@ -324,10 +359,10 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     }
     if (PAY) {
         __syncthreads();   // the keys and values are out of the staging area
-        // eight loads in flight at a time (all 32 at once would double the registers the kernel
-        // needs and halve its occupancy)
+        // eight loads in flight at a time (all of them at once would raise the registers the kernel
+        // needs and lower its occupancy)
 #pragma unroll
-        for (int r0 = 0; r0 < kSortRounds; r0 += 8) {
+        for (int r0 = 0; r0 < ROUNDS; r0 += 8) {
             uint2 pv[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -342,8 +377,8 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
             asm volatile("" ::: "memory");
         }
         __syncthreads();
-        for (int j = threadIdx.x; j < (int)tile_n; j += kSortThreads) {
-            const uint32_t d = sdig[j];
+        for (int j = threadIdx.x; j < (int)tile_n; j += THREADS) {
+            const uint32_t d = cd.sdig[j];
             pay_out[(size_t)gbase[d] + (uint32_t)(j - dstart[d])] = stg.p[j];
         }
     }
@@ -368,6 +403,12 @@ static PassPlan plan_passes(int bits) {
     return pl;
 }
 
+// The tile sort: the first pass (fused with emission) takes the low tile bits, the passes after
+// it the rest, in even digits of at most 8 bits. (Uneven splits of the 14 bits of 9,996 tiles
+// were slower: emission + second pass 0.708 ms with 6 + 8 bits and 0.746 ms with 8 + 6, against
+// 0.697 ms with 7 + 7.)
+static int tile_first_bits(int bits) { return plan_passes(bits).dbits; }
+
 // one reduce-then-scan pass over n items (bound; n_dev the count on the device)
 static void radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
                        size_t n, const uint32_t* n_dev, uint32_t base, int shift, uint32_t mask, void* scratch,
@@ -380,13 +421,13 @@ static void radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
                        mask, (uint32_t)parts, counts);
     scan_exclusive_u32(counts, counts, parts * ((size_t)mask + 1), nullptr, p, s, nullptr);
     if (pay_in)
-        hipLaunchKernelGGL(k_radix_downsweep<true>, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in, vals_in,
-                           keys_out, vals_out, pay_in, pay_out, n, n_dev, base, shift, mask, (uint32_t)parts,
-                           (const uint32_t*)counts);
+        hipLaunchKernelGGL((k_radix_downsweep<true, kPayWaves>), dim3((unsigned)parts), dim3(kPayWaves * 64), 0, s,
+                           keys_in, vals_in, keys_out, vals_out, pay_in, pay_out, n, n_dev, base, shift, mask,
+                           (uint32_t)parts, (const uint32_t*)counts);
     else
-        hipLaunchKernelGGL(k_radix_downsweep<false>, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in,
-                           vals_in, keys_out, vals_out, nullptr, nullptr, n, n_dev, base, shift, mask, (uint32_t)parts,
-                           (const uint32_t*)counts);
+        hipLaunchKernelGGL((k_radix_downsweep<false, kPlainWaves>), dim3((unsigned)parts), dim3(kPlainWaves * 64), 0,
+                           s, keys_in, vals_in, keys_out, vals_out, nullptr, nullptr, n, n_dev, base, shift, mask,
+                           (uint32_t)parts, (const uint32_t*)counts);
 }
 
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
@@ -419,17 +460,23 @@ __device__ __forceinline__ uint32_t rect_tiles(uint2 r) { return (r.y & 0xffffu)
 // the record of the first pair of its run by binary search over that prefix and walks on from
 // there (pair t of a record whose rectangle is w tiles wide is tile (tx0 + t mod w, ty0 + t / w)).
 // The upsweep counts the digits of the chunk's pairs, a contiguous run per thread; the downsweep,
-// in batches of kEmitBatch, lets each lane walk 16 consecutive pairs, hands them to the wave64
+// in batches of kEmitBatch, lets each lane walk kEmitRounds consecutive pairs, hands them to the wave64
 // ballot ranking in round order through LDS, stages the batch in digit order and writes it out in
 // runs. The emitted pairs are never stored unsorted.
 constexpr int kEmitRecs = 512;        // the smaller chunk (it bounds the count table)
 constexpr int kEmitRecsSmall = 1024;  // chunk of records that cover few tiles each
-constexpr int kEmitRounds = 16;
-constexpr int kEmitBatch = kSortWaves * kEmitRounds * 64;   // 4096
-// per wavefront, its 1024 pairs lane-major (lane l walks pairs 16 l .. 16 l + 15), padded to 17
-// words per lane so that neither the lane-major writes nor the round-major reads conflict
+// the downsweep: 4 wavefronts, each ranking 16 rounds of 64 pairs per batch (8 wavefronts of 8
+// rounds fit four waves per SIMD instead of three but were slower: 0.423 against 0.407 ms on 54.7M
+// pairs, twice the searches per batch)
+constexpr int kEmitWaves = 4;
+constexpr int kEmitThreads = kEmitWaves * 64;
+constexpr int kEmitBatch = 4096;
+constexpr int kEmitRounds = kEmitBatch / kEmitThreads;
+// per wavefront, its pairs lane-major (lane l walks pairs R l .. R l + R - 1, R = kEmitRounds),
+// padded to R + 1 words per lane so that neither the lane-major writes nor the round-major reads
+// conflict
 constexpr int kEmitPad = kEmitRounds + 1;
-constexpr int kEmitStageWords = kSortWaves * 64 * kEmitPad;   // 4352 >= kEmitBatch
+constexpr int kEmitStageWords = kEmitWaves * 64 * kEmitPad;   // >= kEmitBatch
 
 // views whose first tile id and tiles per row are staged in LDS for the rectangles' view lookup
 // (a batch of more views searches the camera array in global memory). Sized so that the
@@ -463,12 +510,12 @@ __device__ __forceinline__ uint32_t emit_stride(const EmitStage<RECS>& st, const
 }
 
 // Stages records [r0, r0 + cnt) of the depth order (cnt <= RECS); returns the chunk's pairs.
-template <int RECS>
+template <int RECS, int THREADS>
 __device__ __forceinline__ uint32_t emit_stage(const uint32_t* __restrict__ sorted_rec,
                                                const uint2* __restrict__ sorted_rect,
                                                const DevCam* __restrict__ cams, int B, uint32_t r0, uint32_t cnt,
                                                EmitStage<RECS>& st, uint32_t* scan_tmp) {
-    constexpr int kPer = RECS / kSortThreads;   // consecutive records per thread
+    constexpr int kPer = RECS / THREADS;   // consecutive records per thread
     const uint32_t t = threadIdx.x;
     if ((int)t < B && t < (uint32_t)kEmitViews) {
         st.vbase[t] = cams[t].tile_base;
@@ -500,7 +547,7 @@ __device__ __forceinline__ uint32_t emit_stage(const uint32_t* __restrict__ sort
         sum += c[k];
     }
     uint32_t total;
-    uint32_t ex = block_exclusive_scan_256(sum, scan_tmp, &total);
+    uint32_t ex = block_exclusive_scan<THREADS>(sum, scan_tmp, &total);
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         st.off[kPer * t + (uint32_t)k] = ex;
@@ -585,7 +632,7 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_upsweep(const uint32_t* _
     const uint32_t r0 = blockIdx.x * RECS;
     if (r0 < n) {   // uniform over the workgroup
         const uint32_t cnt = min(n - r0, (uint32_t)RECS);
-        const uint32_t total = emit_stage(sorted_rec, sorted_rect, cams, B, r0, cnt, st, scan_tmp);
+        const uint32_t total = emit_stage<RECS, kSortThreads>(sorted_rec, sorted_rect, cams, B, r0, cnt, st, scan_tmp);
         // each thread counts a contiguous run of pairs, walking the rectangles row-major
         const uint32_t q = (total + kSortThreads - 1) / kSortThreads;
         uint32_t j = threadIdx.x * q;
@@ -605,13 +652,13 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_upsweep(const uint32_t* _
 }
 
 template <int RECS>
-__global__ void __launch_bounds__(kSortThreads) k_emit_downsweep(
+__global__ void __launch_bounds__(kEmitThreads) k_emit_downsweep(
     const uint32_t* __restrict__ sorted_rec, const uint2* __restrict__ sorted_rect, const DevCam* __restrict__ cams,
     int B, uint32_t n, const uint32_t* __restrict__ n_dev, uint32_t mask, uint32_t chunks,
     const uint32_t* __restrict__ offsets,
     uint32_t K, const uint32_t* __restrict__ K_dev, uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
     __shared__ EmitStage<RECS> st;
-    __shared__ uint32_t wcount[kSortWaves][kRadix];
+    __shared__ uint32_t wcount[kEmitWaves][kRadix];
     __shared__ uint32_t dstart[kRadix];
     __shared__ uint32_t gbase[kRadix];
     __shared__ uint32_t scan_tmp[kRadix];
@@ -619,22 +666,23 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_downsweep(
     __shared__ uint32_t skey[kEmitStageWords];
     __shared__ uint32_t sval[kEmitStageWords];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nbits = 32 - __builtin_clz(mask | 1u);   // bits of this pass's digit
     n = (uint32_t)count_of(n, n_dev);
     K = (uint32_t)count_of(K, K_dev);
     const uint32_t r0 = blockIdx.x * RECS;
     if (r0 >= n) return;
     const uint32_t cnt = min(n - r0, (uint32_t)RECS);
-    gbase[threadIdx.x] = threadIdx.x <= mask ? offsets[(size_t)threadIdx.x * chunks + blockIdx.x] : 0u;
-    const uint32_t total = emit_stage(sorted_rec, sorted_rect, cams, B, r0, cnt, st, scan_tmp);
+    if (threadIdx.x < kRadix)
+        gbase[threadIdx.x] = threadIdx.x <= mask ? offsets[(size_t)threadIdx.x * chunks + blockIdx.x] : 0u;
+    const uint32_t total = emit_stage<RECS, kEmitThreads>(sorted_rec, sorted_rect, cams, B, r0, cnt, st, scan_tmp);
     for (uint32_t b0 = 0; b0 < total; b0 += kEmitBatch) {
         const uint32_t bn = min(total - b0, (uint32_t)kEmitBatch);
-#pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) wcount[w][threadIdx.x] = 0u;
+        for (int i = threadIdx.x; i < kEmitWaves * kRadix; i += kEmitThreads) (&wcount[0][0])[i] = 0u;
         __syncthreads();
         const uint32_t wbase = (uint32_t)wave * kEmitRounds * 64u;
         uint32_t key[kEmitRounds], val[kEmitRounds], rank[kEmitRounds];
         {
-            // lane l walks this wavefront's pairs 16 l .. 16 l + 15 (one search per lane) ...
+            // lane l walks this wavefront's pairs R l .. R l + R - 1 (R = kEmitRounds; one search per lane) ...
             uint32_t* tk = skey + wave * 64 * kEmitPad + lane * kEmitPad;
             uint32_t* tv = sval + wave * 64 * kEmitPad + lane * kEmitPad;
             const uint32_t j0 = wbase + (uint32_t)lane * kEmitRounds;
@@ -667,7 +715,7 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_downsweep(
             const uint32_t j = wbase + (uint32_t)r * 64u + (uint32_t)lane;
             const bool valid = j < bn;
             const uint32_t d = key[r] & mask;
-            const uint64_t peers = digit_peers(d, valid);
+            const uint64_t peers = digit_peers(d, valid, nbits);
             const uint32_t below = (uint32_t)rank_below(peers);
             const uint32_t before = wcount[wave][d];
             rank[r] = before + below;
@@ -676,17 +724,20 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_downsweep(
             wave_lds_sync();
         }
         __syncthreads();
-        uint32_t run = 0;   // this batch's items of digit threadIdx.x
+        uint32_t run = 0;   // this batch's items of digit threadIdx.x (threads past the digits: 0)
         {
             const int d = threadIdx.x;
+            if (d < kRadix) {
 #pragma unroll
-            for (int w = 0; w < kSortWaves; ++w) {
-                const uint32_t c = wcount[w][d];
-                wcount[w][d] = run;
-                run += c;
+                for (int w = 0; w < kEmitWaves; ++w) {
+                    const uint32_t c = wcount[w][d];
+                    wcount[w][d] = run;
+                    run += c;
+                }
             }
             uint32_t tot;
-            dstart[d] = block_exclusive_scan_256(run, scan_tmp, &tot);
+            const uint32_t ex = block_exclusive_scan<kEmitThreads>(run, scan_tmp, &tot);
+            if (d < kRadix) dstart[d] = ex;
         }
         __syncthreads();
 #pragma unroll
@@ -700,7 +751,7 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_downsweep(
             }
         }
         __syncthreads();
-        for (uint32_t j = threadIdx.x; j < bn; j += kSortThreads) {
+        for (uint32_t j = threadIdx.x; j < bn; j += kEmitThreads) {
             const uint32_t k = skey[j];
             const uint32_t d = k & mask;
             const uint32_t dst = gbase[d] + (j - dstart[d]);
@@ -710,7 +761,7 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_downsweep(
             }
         }
         __syncthreads();
-        gbase[threadIdx.x] += run;
+        if (threadIdx.x < kRadix) gbase[threadIdx.x] += run;
     }
 }
 
@@ -757,7 +808,7 @@ void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint2* sorted_rect,
     if (n_rec == 0 || K == 0) return;
     // records covering fewer than four tiles on average: chunks of twice the records
     const bool small_rects = K < 4 * (size_t)n_rec;
-    const PassPlan pl = plan_passes(bits);
+    const uint32_t first_mask = (1u << tile_first_bits(bits)) - 1u;
     const int recs = small_rects ? kEmitRecsSmall : kEmitRecs;
     const size_t chunks = div_up(n_rec, (size_t)recs);
     uint8_t* p = (uint8_t*)scratch;
@@ -765,11 +816,11 @@ void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint2* sorted_rect,
     p += align256(chunks * kRadix * sizeof(uint32_t));
     hipLaunchKernelGGL(small_rects ? k_emit_upsweep<kEmitRecsSmall> : k_emit_upsweep<kEmitRecs>,
                        dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rec, sorted_rect, cams, B,
-                       (uint32_t)n_rec, n_rec_dev, pl.mask, (uint32_t)chunks, counts);
-    scan_exclusive_u32(counts, counts, chunks * ((size_t)pl.mask + 1), nullptr, p, s, nullptr);
+                       (uint32_t)n_rec, n_rec_dev, first_mask, (uint32_t)chunks, counts);
+    scan_exclusive_u32(counts, counts, chunks * ((size_t)first_mask + 1), nullptr, p, s, nullptr);
     hipLaunchKernelGGL(small_rects ? k_emit_downsweep<kEmitRecsSmall> : k_emit_downsweep<kEmitRecs>,
-                       dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rec, sorted_rect,
-                       cams, B, (uint32_t)n_rec, n_rec_dev, pl.mask, (uint32_t)chunks,
+                       dim3((unsigned)chunks), dim3(kEmitThreads), 0, s, sorted_rec, sorted_rect,
+                       cams, B, (uint32_t)n_rec, n_rec_dev, first_mask, (uint32_t)chunks,
                        (const uint32_t*)counts, (uint32_t)K, K_dev, keys, vals);
 }
 
@@ -777,10 +828,12 @@ int sort_pairs_rest(uint32_t* keys[2], uint32_t* vals[2], size_t K, const uint32
                     hipStream_t s) {
     int cur = 0;
     if (K == 0) return cur;
-    const PassPlan pl = plan_passes(bits);
-    for (int pass = 1; pass < pl.passes; ++pass) {
-        radix_pass(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], K, K_dev, 0u, pl.dbits * pass, pl.mask,
-                   scratch, s);
+    const int first = tile_first_bits(bits);
+    if (first >= bits) return cur;
+    const PassPlan pl = plan_passes(bits - first);
+    for (int pass = 0; pass < pl.passes; ++pass) {
+        radix_pass(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], K, K_dev, 0u, first + pl.dbits * pass,
+                   pl.mask, scratch, s);
         cur ^= 1;
     }
     return cur;
