@@ -112,6 +112,33 @@ __device__ __forceinline__ uint64_t window_mask(const uint32_t* __restrict__ val
     return ballot64(keep);
 }
 
+// Bounding rectangle [ax0, ax1] x [ay0, ay1] of the pixels of a wavefront's SW-wide sub-tile (at
+// sx0, sy0; lane l owns column l % SW and rows l / SW + (64 / SW) k, k < PPL) whose bit is set in
+// the ballots m[k] (pixel k of each lane); at least one bit must be set. Scalar work only: the
+// walks shrink the rectangle their candidates are culled against to the pixels that can still
+// take a Gaussian (live in the forward, before their last contributor in the backward), so a
+// candidate that reaches only stopped or finished pixels is not loaded.
+template <int PPL, int SW>
+__device__ __forceinline__ void active_rect(const uint64_t (&m)[PPL], int sx0, int sy0, int& ax0, int& ax1, int& ay0,
+                                            int& ay1) {
+    constexpr int ROWS = 64 / SW;
+    constexpr uint64_t kCols = (1ull << SW) - 1ull;
+    uint64_t cols = 0;
+    uint32_t rows = 0;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k)
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const uint64_t c = (m[k] >> (r * SW)) & kCols;
+            cols |= c;
+            rows |= (c != 0ull ? 1u : 0u) << (r + ROWS * k);
+        }
+    ax0 = sx0 + __builtin_ctzll(cols);
+    ax1 = sx0 + 63 - __builtin_clzll(cols);
+    ay0 = sy0 + __builtin_ctz(rows);
+    ay1 = sy0 + 31 - __builtin_clz(rows);
+}
+
 // T carries the pixel's state in its sign: a stopped (or unselected) pixel holds -T, so one
 // comparison tells a live pixel and no separate flag has to be kept per candidate. Transmittance
 // is |T| (at least 1e-4 while live).
@@ -350,8 +377,10 @@ __device__ __forceinline__ void walk_forward(FwdPix (&st)[PPL], float px, const 
 
 // Reverse walk of one wavefront from list position hi_end down to rg.x (Eq. 1 differentiated):
 // per Gaussian, the lanes' contributions are summed over the wavefront and added to the record's
-// accumulators with one atomic instruction.
-template <bool E1, int PPL>
+// accumulators with one atomic instruction. SW > 0: the lanes' pixels form an SW-wide sub-tile
+// (see active_rect) and each window of candidates is culled against the pixels whose last
+// contributor lies above it; SW = 0: against the fixed rectangle [sx0, sx1] x [sy0, sy1].
+template <bool E1, int PPL, int SW = 0>
 __device__ __forceinline__ void walk_backward(BwdPix (&st)[PPL], float px, uint32_t hi_end, uint2 rg,
                                               const uint32_t* __restrict__ vals, const BlendRec* __restrict__ recs,
                                               int lane, int sx0, int sx1, int sy0, int sy1, float half_w,
@@ -360,8 +389,23 @@ __device__ __forceinline__ void walk_backward(BwdPix (&st)[PPL], float px, uint3
 
     for (uint32_t top = hi_end; top > rg.x;) {
         const uint32_t base = top - rg.x > 64u ? top - 64u : rg.x;
+        int ax0 = sx0, ax1 = sx1, ay0 = sy0, ay1 = sy1;
+        if constexpr (SW > 0) {
+            uint64_t am[PPL];
+            uint64_t any = 0;
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                am[k] = ballot64(st[k].last > base);
+                any |= am[k];
+            }
+            if (any == 0) {   // no pixel takes a Gaussian at or above base
+                top = base;
+                continue;
+            }
+            active_rect<PPL, SW>(am, sx0, sy0, ax0, ax1, ay0, ay1);
+        }
         uint32_t rl;
-        uint64_t m = window_mask(vals, recs, base, top, lane, sx0, sx1, sy0, sy1, rl);
+        uint64_t m = window_mask(vals, recs, base, top, lane, ax0, ax1, ay0, ay1, rl);
         top = base;
         while (m) {
             // highest list position first; up to four records per round trip

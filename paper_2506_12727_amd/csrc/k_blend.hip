@@ -93,12 +93,19 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_fwd(const DevCam* __res
     // The walk of walk_forward, written out here: with the call, the compiler optimises the loop
     // apart from this kernel and the kernel runs out of scalar registers.
     for (uint32_t base = wt.rg.x; base < wt.rg.y; base += 64) {
-        bool live = false;
+        uint64_t lm[PPL];
+        uint64_t any = 0;
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) live |= pix_live(st[k]);
-        if (ballot64(live) == 0) break;
+        for (int k = 0; k < PPL; ++k) {
+            lm[k] = ballot64(pix_live(st[k]));
+            any |= lm[k];
+        }
+        if (any == 0) break;
+        // candidates are culled against the pixels still live
+        int ax0, ax1, ay0, ay1;
+        active_rect<PPL, ST::SW>(lm, wt.sx0, wt.sy0, ax0, ax1, ay0, ay1);
         uint32_t rl;
-        uint64_t m = window_mask(vals, recs, base, wt.rg.y, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1, rl);
+        uint64_t m = window_mask(vals, recs, base, wt.rg.y, lane, ax0, ax1, ay0, ay1, rl);
         while (m) {
             // up to four records per round trip through the scalar cache
             const int j0 = __builtin_ctzll(m);
@@ -194,7 +201,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_bwd(const DevCam* __res
         }
     }
     const uint32_t hi_end = __builtin_amdgcn_readfirstlane(wave_max_u32(lane_last));
-    walk_backward<E1, PPL>(st, px, hi_end, wt.rg, vals, recs, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1, half_w, half_h,
+    walk_backward<E1, PPL, ST::SW>(st, px, hi_end, wt.rg, vals, recs, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1, half_w, half_h,
                            acc);
 }
 
