@@ -591,6 +591,7 @@ def stage_bytes(stage, info, g, cams, wl):
     """Algorithmic HBM bytes of one launch of an HBM-bound stage: what it must read and write once.
     K pairs, V records, P Gaussians with Kc = (degree + 1)^2 SH coefficients, N pixels."""
     K, V, T = info["pairs"], info["records"], info["tiles"]
+    kb = 2.0 if T <= 65536 else 4.0   # bytes per pair key: 16-bit tile ids up to 65,536 tiles
     P, Kc = g.P, (g.sh_degree + 1) ** 2
     N = sum(c.width * c.height for c in cams)
     par = 44 + 12 * Kc            # mean, scale, quaternion, opacity, SH (float32)
@@ -601,12 +602,12 @@ def stage_bytes(stage, info, g, cams, wl):
         "records": (par + 4.0) * P + 78.0 * V,
         # one read and one write of the 4 B key, 4 B value and 8 B tile rectangle per record and pass
         "depth_sort": 32.0 * V * info["depth_passes"],
-        # each record's tile rectangle and id in depth order read once; 8 B per pair written
-        "emit": 12.0 * V + 8.0 * K,
-        # the passes after the one fused with emission
-        "tile_sort": 16.0 * K * max(info["tile_passes"] - 1, 0),
+        # each record's tile rectangle and id in depth order read once; key and 4 B value per pair written
+        "emit": 12.0 * V + (kb + 4.0) * K,
+        # the passes after the one fused with emission: key and value read and written
+        "tile_sort": 2.0 * (kb + 4.0) * K * max(info["tile_passes"] - 1, 0),
         # the key at each tile boundary read, 8 B per tile written
-        "ranges": 12.0 * T,
+        "ranges": (kb + 8.0) * T,
         # image and target read, gradient written per pixel-channel (L1 only: with D-SSIM the
         # fused kernel is bound by its arithmetic, see roofline)
         "loss": 3.0 * N * 12.0,

@@ -217,6 +217,7 @@ struct mvgs_frame {
     uint32_t V = 0;
     uint64_t K = 0;
     int final_buf = 0;
+    bool key16 = false;   // the pair keys are 16-bit tile ids (at most 65,536 tiles)
     int depth_bits = 0, tile_bits = 0;   // key bits the depth and tile sorts ordered
     size_t need_bytes = 0;  // device bytes the forward that made this frame asked for
     // partial rendering: kModeFull renders every pixel; the others a selection (t_final and
@@ -943,16 +944,17 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     const int tile_bits = bits_for(n_tiles);
     f->depth_bits = depth_bits;
     f->tile_bits = tile_bits;
-    emit_pairs_first_pass(sorted_rec, rect[dcur], dcam, B, V, eff, as<uint32_t>(f->keys[0]), as<uint32_t>(f->vals[0]),
+    f->key16 = tile_bits <= 16;
+    emit_pairs_first_pass(sorted_rec, rect[dcur], dcam, B, V, eff, f->keys[0].p, f->key16, as<uint32_t>(f->vals[0]),
                           K, eff ? eff + 1 : nullptr, tile_bits, ctx->sort_scratch.p, s);
     ctx->stage_end(mk, s);
     mk = ctx->stage_begin(4, s);
-    uint32_t* pk[2] = {as<uint32_t>(f->keys[0]), as<uint32_t>(f->keys[1])};
+    void* pk[2] = {f->keys[0].p, f->keys[1].p};
     uint32_t* pv[2] = {as<uint32_t>(f->vals[0]), as<uint32_t>(f->vals[1])};
-    f->final_buf = sort_pairs_rest(pk, pv, K, eff ? eff + 1 : nullptr, tile_bits, ctx->sort_scratch.p, s);
+    f->final_buf = sort_pairs_rest(pk, f->key16, pv, K, eff ? eff + 1 : nullptr, tile_bits, ctx->sort_scratch.p, s);
     ctx->stage_end(mk, s);
     mk = ctx->stage_begin(5, s);
-    launch_ranges(pk[f->final_buf], K, n_tiles, as<uint2>(f->ranges), s, eff ? eff + 1 : nullptr);
+    launch_ranges(pk[f->final_buf], f->key16, K, n_tiles, as<uint2>(f->ranges), s, eff ? eff + 1 : nullptr);
     ctx->stage_end(mk, s);
 
     // blend every pixel of every view
@@ -1668,7 +1670,7 @@ int mvgs_export_binning(mvgs_context* ctx, void* stream, const mvgs_frame* frame
     hipStream_t s = (hipStream_t)stream;
     mvgs_frame* f = const_cast<mvgs_frame*>(frame);
     if (keys || values)
-        launch_export_keys(as<uint32_t>(f->keys[f->final_buf]), as<uint32_t>(f->vals[f->final_buf]),
+        launch_export_keys(f->keys[f->final_buf].p, f->key16, as<uint32_t>(f->vals[f->final_buf]),
                            as<BlendRec>(f->recs), as<DevCam>(f->cams), f->B, (uint32_t)f->K, keys, values, s);
     if (ranges && f->n_tiles)
         HIPCHK(ctx, hipMemcpyAsync(ranges, f->ranges.p, sizeof(uint2) * f->n_tiles, hipMemcpyDeviceToDevice, s));

@@ -225,8 +225,9 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Reduce-then-scan pass, step 1: per-partition digit counts, digit-major (counts[d * parts + p] for
 // the mask + 1 digits of the pass), so that one exclusive scan of the whole table gives every
-// (digit, partition) its output base.
-__global__ void __launch_bounds__(256) k_radix_upsweep(const uint32_t* __restrict__ keys, size_t n,
+// (digit, partition) its output base. KT: 32- or 16-bit keys.
+template <typename KT>
+__global__ void __launch_bounds__(256) k_radix_upsweep(const KT* __restrict__ keys, size_t n,
                                                        const uint32_t* __restrict__ n_dev, uint32_t key_base, int shift,
                                                        uint32_t mask, uint32_t parts, uint32_t* __restrict__ counts) {
     __shared__ uint32_t h[kRadix];
@@ -235,18 +236,26 @@ __global__ void __launch_bounds__(256) k_radix_upsweep(const uint32_t* __restric
     n = count_of(n, n_dev);
     const size_t base = (size_t)blockIdx.x * kSortTile;
     if (base + kSortTile <= n) {
+        // 16 bytes per load: four 32-bit or eight 16-bit keys
+        constexpr int kPer = 16 / (int)sizeof(KT);
         const uint4* k4 = reinterpret_cast<const uint4*>(keys + base);
-        for (int j = threadIdx.x; j < kSortTile / 4; j += 256) {
+        for (int j = threadIdx.x; j < kSortTile / kPer; j += 256) {
             const uint4 k = k4[j];
-            atomicAdd(&h[((k.x - key_base) >> shift) & mask], 1u);
-            atomicAdd(&h[((k.y - key_base) >> shift) & mask], 1u);
-            atomicAdd(&h[((k.z - key_base) >> shift) & mask], 1u);
-            atomicAdd(&h[((k.w - key_base) >> shift) & mask], 1u);
+            const uint32_t w[4] = {k.x, k.y, k.z, k.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (sizeof(KT) == 4) {
+                    atomicAdd(&h[((w[e] - key_base) >> shift) & mask], 1u);
+                } else {
+                    atomicAdd(&h[(((w[e] & 0xffffu) - key_base) >> shift) & mask], 1u);
+                    atomicAdd(&h[(((w[e] >> 16) - key_base) >> shift) & mask], 1u);
+                }
+            }
         }
     } else {
         for (int j = threadIdx.x; j < kSortTile; j += 256) {
             const size_t i = base + j;
-            if (i < n) atomicAdd(&h[((keys[i] - key_base) >> shift) & mask], 1u);
+            if (i < n) atomicAdd(&h[(((uint32_t)keys[i] - key_base) >> shift) & mask], 1u);
         }
     }
     __syncthreads();
@@ -256,10 +265,10 @@ __global__ void __launch_bounds__(256) k_radix_upsweep(const uint32_t* __restric
 // Step 3: rank each partition's items stably with wave64 ballots and scatter them through LDS in
 // digit order to the bases the scan gave. PAY: an 8-byte payload per item follows its key, staged
 // through the same LDS after the keys and values are out (the digits of the staged order kept
-// aside for it).
-template <bool PAY, int WAVES>
+// aside for it). KT: 32- or 16-bit keys (staged as 32 bits).
+template <bool PAY, int WAVES, typename KT>
 __global__ void __launch_bounds__(WAVES * 64) k_radix_downsweep(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
+    const KT* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, KT* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const uint2* __restrict__ pay_in, uint2* __restrict__ pay_out, size_t n,
     const uint32_t* __restrict__ n_dev, uint32_t key_base, int shift, uint32_t mask, uint32_t parts,
     const uint32_t* __restrict__ offsets) {
@@ -296,7 +305,7 @@ __global__ void __launch_bounds__(WAVES * 64) k_radix_downsweep(
     for (int r = 0; r < ROUNDS; ++r) {
         const size_t i = base + (size_t)r * 64 + lane;
         const bool valid = i < n;
-        key[r] = valid ? keys_in[i] : 0xffffffffu;
+        key[r] = valid ? (uint32_t)keys_in[i] : 0xffffffffu;
         val[r] = valid ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
     }
 #pragma unroll
@@ -354,7 +363,7 @@ __global__ void __launch_bounds__(WAVES * 64) k_radix_downsweep(
         const uint32_t k = stg.kv.k[j];
         const uint32_t d = ((k - key_base) >> shift) & mask;
         const size_t dst = (size_t)gbase[d] + (uint32_t)(j - dstart[d]);
-        keys_out[dst] = k;
+        keys_out[dst] = (KT)k;
         vals_out[dst] = stg.kv.v[j];
     }
     if (PAY) {
@@ -410,23 +419,24 @@ static PassPlan plan_passes(int bits) {
 static int tile_first_bits(int bits) { return plan_passes(bits).dbits; }
 
 // one reduce-then-scan pass over n items (bound; n_dev the count on the device)
-static void radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
-                       size_t n, const uint32_t* n_dev, uint32_t base, int shift, uint32_t mask, void* scratch,
-                       hipStream_t s, const uint2* pay_in = nullptr, uint2* pay_out = nullptr) {
+template <typename KT>
+static void radix_pass(const KT* keys_in, const uint32_t* vals_in, KT* keys_out, uint32_t* vals_out, size_t n,
+                       const uint32_t* n_dev, uint32_t base, int shift, uint32_t mask, void* scratch, hipStream_t s,
+                       const uint2* pay_in = nullptr, uint2* pay_out = nullptr) {
     const size_t parts = div_up(n, kSortTile);
     uint8_t* p = (uint8_t*)scratch;
     uint32_t* counts = (uint32_t*)p;
     p += align256(parts * kRadix * sizeof(uint32_t));
-    hipLaunchKernelGGL(k_radix_upsweep, dim3((unsigned)parts), dim3(256), 0, s, keys_in, n, n_dev, base, shift,
+    hipLaunchKernelGGL(k_radix_upsweep<KT>, dim3((unsigned)parts), dim3(256), 0, s, keys_in, n, n_dev, base, shift,
                        mask, (uint32_t)parts, counts);
     scan_exclusive_u32(counts, counts, parts * ((size_t)mask + 1), nullptr, p, s, nullptr);
     if (pay_in)
-        hipLaunchKernelGGL((k_radix_downsweep<true, kPayWaves>), dim3((unsigned)parts), dim3(kPayWaves * 64), 0, s,
-                           keys_in, vals_in, keys_out, vals_out, pay_in, pay_out, n, n_dev, base, shift, mask,
+        hipLaunchKernelGGL((k_radix_downsweep<true, kPayWaves, KT>), dim3((unsigned)parts), dim3(kPayWaves * 64), 0,
+                           s, keys_in, vals_in, keys_out, vals_out, pay_in, pay_out, n, n_dev, base, shift, mask,
                            (uint32_t)parts, (const uint32_t*)counts);
     else
-        hipLaunchKernelGGL((k_radix_downsweep<false, kPlainWaves>), dim3((unsigned)parts), dim3(kPlainWaves * 64), 0,
-                           s, keys_in, vals_in, keys_out, vals_out, nullptr, nullptr, n, n_dev, base, shift, mask,
+        hipLaunchKernelGGL((k_radix_downsweep<false, kPlainWaves, KT>), dim3((unsigned)parts), dim3(kPlainWaves * 64),
+                           0, s, keys_in, vals_in, keys_out, vals_out, nullptr, nullptr, n, n_dev, base, shift, mask,
                            (uint32_t)parts, (const uint32_t*)counts);
 }
 
@@ -437,7 +447,7 @@ int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, s
     const PassPlan pl = plan_passes(bits);
     for (int pass = 0; pass < pl.passes; ++pass) {
         const uint32_t* vin = (pass == 0 && identity_values) ? nullptr : vals[cur];
-        radix_pass(keys[cur], vin, keys[cur ^ 1], vals[cur ^ 1], n, n_dev, key_base, pl.dbits * pass, pl.mask, scratch,
+        radix_pass<uint32_t>(keys[cur], vin, keys[cur ^ 1], vals[cur ^ 1], n, n_dev, key_base, pl.dbits * pass, pl.mask, scratch,
                    s, pay ? pay[cur] : nullptr, pay ? pay[cur ^ 1] : nullptr);
         cur ^= 1;
     }
@@ -651,12 +661,12 @@ __global__ void __launch_bounds__(kSortThreads) k_emit_upsweep(const uint32_t* _
     if (threadIdx.x <= mask) counts[(size_t)threadIdx.x * chunks + blockIdx.x] = h[threadIdx.x];
 }
 
-template <int RECS>
+template <int RECS, typename KT>
 __global__ void __launch_bounds__(kEmitThreads) k_emit_downsweep(
     const uint32_t* __restrict__ sorted_rec, const uint2* __restrict__ sorted_rect, const DevCam* __restrict__ cams,
     int B, uint32_t n, const uint32_t* __restrict__ n_dev, uint32_t mask, uint32_t chunks,
     const uint32_t* __restrict__ offsets,
-    uint32_t K, const uint32_t* __restrict__ K_dev, uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+    uint32_t K, const uint32_t* __restrict__ K_dev, KT* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
     __shared__ EmitStage<RECS> st;
     __shared__ uint32_t wcount[kEmitWaves][kRadix];
     __shared__ uint32_t dstart[kRadix];
@@ -756,7 +766,7 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_downsweep(
             const uint32_t d = k & mask;
             const uint32_t dst = gbase[d] + (j - dstart[d]);
             if (dst < K) {   // the pair count the buffers were sized by
-                keys_out[dst] = k;
+                keys_out[dst] = (KT)k;
                 vals_out[dst] = sval[j];
             }
         }
@@ -768,7 +778,8 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_downsweep(
 // [start, end) of each global tile's run in the sorted pair keys, by binary search: a wavefront
 // finds where tiles t0 .. t0 + 63 start (one search per lane) and writes the ranges of the first
 // 63, the end of a run being the start of the next tile's
-__global__ void __launch_bounds__(256) k_ranges_search(const uint32_t* __restrict__ keys, uint32_t K,
+template <typename KT>
+__global__ void __launch_bounds__(256) k_ranges_search(const KT* __restrict__ keys, uint32_t K,
                                                        const uint32_t* __restrict__ K_dev, uint32_t n_tiles,
                                                        uint2* __restrict__ ranges) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -777,21 +788,22 @@ __global__ void __launch_bounds__(256) k_ranges_search(const uint32_t* __restric
     uint32_t lo = 0, hi = K;   // first index with keys[i] >= t
     while (lo < hi) {
         const uint32_t mid = lo + ((hi - lo) >> 1);
-        if (keys[mid] < t) lo = mid + 1;
+        if ((uint32_t)keys[mid] < t) lo = mid + 1;
         else hi = mid;
     }
     const uint32_t next = (uint32_t)__shfl_down((int)lo, 1, 64);
     if (lane < 63u && t < n_tiles) ranges[t] = next > lo ? make_uint2(lo, next) : make_uint2(0u, 0u);
 }
 
-__global__ void k_export_keys(const uint32_t* __restrict__ tile_keys, const uint32_t* __restrict__ vals,
+template <typename KT>
+__global__ void k_export_keys(const KT* __restrict__ tile_keys, const uint32_t* __restrict__ vals,
                               const BlendRec* __restrict__ recs, const DevCam* __restrict__ cams, uint32_t K,
                               uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= K) return;
     const uint32_t r = vals[i];
     const BlendRec& rec = recs[r];
-    const uint32_t local = tile_keys[i] - cams[rec.view].tile_base;
+    const uint32_t local = (uint32_t)tile_keys[i] - cams[rec.view].tile_base;
     if (keys_out) keys_out[i] = ((uint64_t)rec.view << 48) | ((uint64_t)local << 32) | (uint64_t)rec.depth_bits;
     if (vals_out) vals_out[i] = rec.gid;
 }
@@ -803,7 +815,7 @@ size_t emit_sort_scratch_bytes(size_t n_rec, size_t K) {
 }
 
 void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint2* sorted_rect, const DevCam* cams, int B,
-                           size_t n_rec, const uint32_t* n_rec_dev, uint32_t* keys, uint32_t* vals, size_t K,
+                           size_t n_rec, const uint32_t* n_rec_dev, void* keys, bool key16, uint32_t* vals, size_t K,
                            const uint32_t* K_dev, int bits, void* scratch, hipStream_t s) {
     if (n_rec == 0 || K == 0) return;
     // records covering fewer than four tiles on average: chunks of twice the records
@@ -818,41 +830,66 @@ void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint2* sorted_rect,
                        dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rec, sorted_rect, cams, B,
                        (uint32_t)n_rec, n_rec_dev, first_mask, (uint32_t)chunks, counts);
     scan_exclusive_u32(counts, counts, chunks * ((size_t)first_mask + 1), nullptr, p, s, nullptr);
-    hipLaunchKernelGGL(small_rects ? k_emit_downsweep<kEmitRecsSmall> : k_emit_downsweep<kEmitRecs>,
-                       dim3((unsigned)chunks), dim3(kEmitThreads), 0, s, sorted_rec, sorted_rect,
-                       cams, B, (uint32_t)n_rec, n_rec_dev, first_mask, (uint32_t)chunks,
-                       (const uint32_t*)counts, (uint32_t)K, K_dev, keys, vals);
+    if (key16)
+        hipLaunchKernelGGL((small_rects ? k_emit_downsweep<kEmitRecsSmall, uint16_t> : k_emit_downsweep<kEmitRecs, uint16_t>),
+                           dim3((unsigned)chunks), dim3(kEmitThreads), 0, s, sorted_rec, sorted_rect, cams, B,
+                           (uint32_t)n_rec, n_rec_dev, first_mask, (uint32_t)chunks, (const uint32_t*)counts,
+                           (uint32_t)K, K_dev, (uint16_t*)keys, vals);
+    else
+        hipLaunchKernelGGL((small_rects ? k_emit_downsweep<kEmitRecsSmall, uint32_t> : k_emit_downsweep<kEmitRecs, uint32_t>),
+                           dim3((unsigned)chunks), dim3(kEmitThreads), 0, s, sorted_rec, sorted_rect, cams, B,
+                           (uint32_t)n_rec, n_rec_dev, first_mask, (uint32_t)chunks, (const uint32_t*)counts,
+                           (uint32_t)K, K_dev, (uint32_t*)keys, vals);
 }
 
-int sort_pairs_rest(uint32_t* keys[2], uint32_t* vals[2], size_t K, const uint32_t* K_dev, int bits, void* scratch,
-                    hipStream_t s) {
+template <typename KT>
+static int sort_pairs_rest_t(KT* keys[2], uint32_t* vals[2], size_t K, const uint32_t* K_dev, int bits, void* scratch,
+                             hipStream_t s) {
     int cur = 0;
     if (K == 0) return cur;
     const int first = tile_first_bits(bits);
     if (first >= bits) return cur;
     const PassPlan pl = plan_passes(bits - first);
     for (int pass = 0; pass < pl.passes; ++pass) {
-        radix_pass(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], K, K_dev, 0u, first + pl.dbits * pass,
-                   pl.mask, scratch, s);
+        radix_pass<KT>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], K, K_dev, 0u, first + pl.dbits * pass,
+                       pl.mask, scratch, s);
         cur ^= 1;
     }
     return cur;
 }
 
-void launch_ranges(const uint32_t* keys, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s,
-                   const uint32_t* K_dev) {
-    if (!n_tiles) return;
-    hipLaunchKernelGGL(k_ranges_search, dim3((n_tiles + 251) / 252), dim3(256), 0, s, keys, K, K_dev, n_tiles,
-                       ranges);
+int sort_pairs_rest(void* keys[2], bool key16, uint32_t* vals[2], size_t K, const uint32_t* K_dev, int bits,
+                    void* scratch, hipStream_t s) {
+    if (key16) {
+        uint16_t* k[2] = {(uint16_t*)keys[0], (uint16_t*)keys[1]};
+        return sort_pairs_rest_t<uint16_t>(k, vals, K, K_dev, bits, scratch, s);
+    }
+    uint32_t* k[2] = {(uint32_t*)keys[0], (uint32_t*)keys[1]};
+    return sort_pairs_rest_t<uint32_t>(k, vals, K, K_dev, bits, scratch, s);
 }
 
-void launch_export_keys(const uint32_t* tile_keys, const uint32_t* vals, const BlendRec* recs,
+void launch_ranges(const void* keys, bool key16, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s,
+                   const uint32_t* K_dev) {
+    if (!n_tiles) return;
+    if (key16)
+        hipLaunchKernelGGL(k_ranges_search<uint16_t>, dim3((n_tiles + 251) / 252), dim3(256), 0, s,
+                           (const uint16_t*)keys, K, K_dev, n_tiles, ranges);
+    else
+        hipLaunchKernelGGL(k_ranges_search<uint32_t>, dim3((n_tiles + 251) / 252), dim3(256), 0, s,
+                           (const uint32_t*)keys, K, K_dev, n_tiles, ranges);
+}
+
+void launch_export_keys(const void* tile_keys, bool key16, const uint32_t* vals, const BlendRec* recs,
                         const DevCam* cams, int B, uint32_t K, uint64_t* keys_out, uint32_t* vals_out,
                         hipStream_t s) {
     (void)B;
     if (!K) return;
-    hipLaunchKernelGGL(k_export_keys, dim3((K + 255) / 256), dim3(256), 0, s, tile_keys, vals, recs, cams, K,
-                       keys_out, vals_out);
+    if (key16)
+        hipLaunchKernelGGL(k_export_keys<uint16_t>, dim3((K + 255) / 256), dim3(256), 0, s,
+                           (const uint16_t*)tile_keys, vals, recs, cams, K, keys_out, vals_out);
+    else
+        hipLaunchKernelGGL(k_export_keys<uint32_t>, dim3((K + 255) / 256), dim3(256), 0, s,
+                           (const uint32_t*)tile_keys, vals, recs, cams, K, keys_out, vals_out);
 }
 
 void fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {

@@ -90,16 +90,17 @@ void launch_capacity_clamp(const uint64_t* totals, uint64_t cap_v, uint64_t cap_
 // the rectangles carried through the depth sort), every (global tile, record) pair is emitted
 // straight into its place after the first radix pass (keys, vals: [K]); sort_pairs_rest runs the
 // remaining passes from buffers 0 and returns the index of the buffer holding the sorted pairs.
-// n_rec and K are bounds when n_rec_dev / K_dev (device) give the counts.
+// n_rec and K are bounds when n_rec_dev / K_dev (device) give the counts. key16: the tile ids fit
+// in 16 bits (at most 65,536 tiles) and the key buffers hold uint16_t, else uint32_t.
 size_t emit_sort_scratch_bytes(size_t n_rec, size_t K);
 void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint2* sorted_rect, const DevCam* cams, int B,
-                           size_t n_rec, const uint32_t* n_rec_dev, uint32_t* keys, uint32_t* vals, size_t K,
+                           size_t n_rec, const uint32_t* n_rec_dev, void* keys, bool key16, uint32_t* vals, size_t K,
                            const uint32_t* K_dev, int bits, void* scratch, hipStream_t s);
-int sort_pairs_rest(uint32_t* keys[2], uint32_t* vals[2], size_t K, const uint32_t* K_dev, int bits, void* scratch,
-                    hipStream_t s);
-void launch_ranges(const uint32_t* keys, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s,
+int sort_pairs_rest(void* keys[2], bool key16, uint32_t* vals[2], size_t K, const uint32_t* K_dev, int bits,
+                    void* scratch, hipStream_t s);
+void launch_ranges(const void* keys, bool key16, uint32_t K, uint32_t n_tiles, uint2* ranges, hipStream_t s,
                    const uint32_t* K_dev = nullptr);
-void launch_export_keys(const uint32_t* tile_keys, const uint32_t* vals, const BlendRec* recs,
+void launch_export_keys(const void* tile_keys, bool key16, const uint32_t* vals, const BlendRec* recs,
                         const DevCam* cams, int B, uint32_t K, uint64_t* keys_out, uint32_t* vals_out,
                         hipStream_t s);
 

@@ -322,3 +322,27 @@ def test_maximum_tiles_per_view():
     ok_ = fl == 0
     assert np.all(np.abs(got - rgb)[ok_] <= 1e-5 * np.abs(rgb)[ok_] + 1e-6)
     r.release(fr)
+
+
+def test_more_tiles_than_16_bit_ids():
+    """Two 2048 x 2048 views at 8x8 tiles: 131,072 tiles in the batch, so the pair keys are 32-bit
+    tile ids (17 bits, three tile-sort passes); at most 65,536 tiles they are 16-bit."""
+    needs_gpu()
+    sc = scenes.make_scene(3000, 0, log_scale_mean=-3.2)
+    cams = [scenes.make_camera(2048, 2048, (0.0, 0.3, -2.5)), scenes.make_camera(2048, 2048, (0.4, -0.2, -2.7))]
+    r, g, imgs, fr = run_forward(sc, cams, (8, 8))
+    assert fr.info()["tiles"] == 131072
+    keys, vals, ranges = r.export_binning(fr)
+    ok, ov, orr = oracle.binning(sc, cams, (8, 8))
+    assert len(ok) > 0
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), ok)
+    assert np.array_equal(vals.cpu().numpy().view(np.uint32), ov)
+    assert np.array_equal(ranges.cpu().numpy().view(np.uint32), orr)
+    rng = np.random.default_rng(5)
+    for v in range(2):
+        xs, ys = rng.integers(0, 2048, 300), rng.integers(0, 2048, 300)
+        rgb, tf, fl = oracle.render_pixels(sc, cams, v, xs, ys)
+        got = imgs[v].cpu().numpy().astype(np.float64)[:, ys, xs].T
+        ok_ = fl == 0
+        assert np.all(np.abs(got - rgb)[ok_] <= 1e-5 * np.abs(rgb)[ok_] + 1e-6)
+    r.release(fr)
