@@ -10,13 +10,14 @@
 // the bits in which the keys differ, and the first pass of the tile sort is fused with emission.
 //
 // Radix sort: LSD, digits of at most 8 bits spread evenly over the passes, 8192 items per
-// partition (8 wavefronts x 16 rounds x 64 lanes in the scatter). Each pass reduces, scans, then scatters: one
-// workgroup per partition counts its digits (LDS counters) into a digit-major table, one exclusive
-// scan of that table gives every (digit, partition) its output base, and one workgroup per
-// partition ranks its items stably with wave64 ballots, stages them in LDS in digit order and
-// writes them out in contiguous runs. Nothing waits on another workgroup. (A single-sweep pass
-// with decoupled look-back was measured slower on this chip: its device-scope look-back latency
-// across the XCDs cost more than the extra read of the keys.)
+// partition (8 wavefronts x 16 rounds x 64 lanes in the scatter). Each pass reduces, scans, then
+// scatters: one workgroup per partition counts its digits (LDS counters) into a digit-major
+// table, one exclusive scan of that table gives every (digit, partition) its output base, and one
+// workgroup per partition ranks its items stably with wave64 ballots, stages them in LDS in digit
+// order and writes them out in contiguous runs. Nothing waits on another workgroup. (A
+// single-sweep pass with decoupled look-back was measured slower on this chip: its device-scope
+// look-back latency across the XCDs cost more than the extra read of the keys.) The tile ids of
+// the pairs are 16-bit keys while a batch has at most 65,536 tiles, 32-bit above.
 #include <algorithm>
 
 #include "mvgs_kernels.h"
@@ -447,8 +448,8 @@ int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, s
     const PassPlan pl = plan_passes(bits);
     for (int pass = 0; pass < pl.passes; ++pass) {
         const uint32_t* vin = (pass == 0 && identity_values) ? nullptr : vals[cur];
-        radix_pass<uint32_t>(keys[cur], vin, keys[cur ^ 1], vals[cur ^ 1], n, n_dev, key_base, pl.dbits * pass, pl.mask, scratch,
-                   s, pay ? pay[cur] : nullptr, pay ? pay[cur ^ 1] : nullptr);
+        radix_pass<uint32_t>(keys[cur], vin, keys[cur ^ 1], vals[cur ^ 1], n, n_dev, key_base, pl.dbits * pass,
+                             pl.mask, scratch, s, pay ? pay[cur] : nullptr, pay ? pay[cur ^ 1] : nullptr);
         cur ^= 1;
     }
     return cur;
@@ -831,15 +832,15 @@ void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint2* sorted_rect,
                        (uint32_t)n_rec, n_rec_dev, first_mask, (uint32_t)chunks, counts);
     scan_exclusive_u32(counts, counts, chunks * ((size_t)first_mask + 1), nullptr, p, s, nullptr);
     if (key16)
-        hipLaunchKernelGGL((small_rects ? k_emit_downsweep<kEmitRecsSmall, uint16_t> : k_emit_downsweep<kEmitRecs, uint16_t>),
-                           dim3((unsigned)chunks), dim3(kEmitThreads), 0, s, sorted_rec, sorted_rect, cams, B,
-                           (uint32_t)n_rec, n_rec_dev, first_mask, (uint32_t)chunks, (const uint32_t*)counts,
-                           (uint32_t)K, K_dev, (uint16_t*)keys, vals);
+        hipLaunchKernelGGL(
+            (small_rects ? k_emit_downsweep<kEmitRecsSmall, uint16_t> : k_emit_downsweep<kEmitRecs, uint16_t>),
+            dim3((unsigned)chunks), dim3(kEmitThreads), 0, s, sorted_rec, sorted_rect, cams, B, (uint32_t)n_rec,
+            n_rec_dev, first_mask, (uint32_t)chunks, (const uint32_t*)counts, (uint32_t)K, K_dev, (uint16_t*)keys, vals);
     else
-        hipLaunchKernelGGL((small_rects ? k_emit_downsweep<kEmitRecsSmall, uint32_t> : k_emit_downsweep<kEmitRecs, uint32_t>),
-                           dim3((unsigned)chunks), dim3(kEmitThreads), 0, s, sorted_rec, sorted_rect, cams, B,
-                           (uint32_t)n_rec, n_rec_dev, first_mask, (uint32_t)chunks, (const uint32_t*)counts,
-                           (uint32_t)K, K_dev, (uint32_t*)keys, vals);
+        hipLaunchKernelGGL(
+            (small_rects ? k_emit_downsweep<kEmitRecsSmall, uint32_t> : k_emit_downsweep<kEmitRecs, uint32_t>),
+            dim3((unsigned)chunks), dim3(kEmitThreads), 0, s, sorted_rec, sorted_rect, cams, B, (uint32_t)n_rec,
+            n_rec_dev, first_mask, (uint32_t)chunks, (const uint32_t*)counts, (uint32_t)K, K_dev, (uint32_t*)keys, vals);
 }
 
 template <typename KT>
