@@ -201,8 +201,8 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_bwd(const DevCam* __res
         }
     }
     const uint32_t hi_end = __builtin_amdgcn_readfirstlane(wave_max_u32(lane_last));
-    walk_backward<E1, PPL, ST::SW>(st, px, hi_end, wt.rg, vals, recs, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1, half_w,
-                                   half_h, acc);
+    walk_backward<E1, PPL, ST::SW>(st, px, hi_end, wt.rg, vals, recs, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1, half_w, half_h,
+                           acc);
 }
 
 // Work of a frame's walks, one thread per pixel: out[0] += list entries from the start of the pixel's
