@@ -668,6 +668,11 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_downsweep(
     int B, uint32_t n, const uint32_t* __restrict__ n_dev, uint32_t mask, uint32_t chunks,
     const uint32_t* __restrict__ offsets,
     uint32_t K, const uint32_t* __restrict__ K_dev, KT* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+    // 16-bit tile ids: a pair is staged as one word, tile id << 10 | the record's index in the
+    // chunk (RECS <= 1024), and its record id looked up at write-out; half the LDS of a key and a
+    // value word, so four workgroups share a CU instead of three
+    constexpr bool PACK = sizeof(KT) == 2;
+    static_assert(!PACK || RECS <= 1024, "packed pairs hold a 10-bit record index");
     __shared__ EmitStage<RECS> st;
     __shared__ uint32_t wcount[kEmitWaves][kRadix];
     __shared__ uint32_t dstart[kRadix];
@@ -675,9 +680,10 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_downsweep(
     __shared__ uint32_t scan_tmp[kRadix];
     // the lane-major pairs of each wavefront, then (after the ranking) the batch in digit order
     __shared__ uint32_t skey[kEmitStageWords];
-    __shared__ uint32_t sval[kEmitStageWords];
+    __shared__ uint32_t sval[PACK ? 1 : kEmitStageWords];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nbits = 32 - __builtin_clz(mask | 1u);   // bits of this pass's digit
+    const int kshift = PACK ? 10 : 0;   // staged word >> kshift = tile id
     n = (uint32_t)count_of(n, n_dev);
     K = (uint32_t)count_of(K, K_dev);
     const uint32_t r0 = blockIdx.x * RECS;
@@ -695,15 +701,19 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_downsweep(
         {
             // lane l walks this wavefront's pairs R l .. R l + R - 1 (R = kEmitRounds; one search per lane) ...
             uint32_t* tk = skey + wave * 64 * kEmitPad + lane * kEmitPad;
-            uint32_t* tv = sval + wave * 64 * kEmitPad + lane * kEmitPad;
+            uint32_t* tv = sval + (PACK ? 0 : wave * 64 * kEmitPad + lane * kEmitPad);
             const uint32_t j0 = wbase + (uint32_t)lane * kEmitRounds;
             if (j0 < bn) {
-                EmitWalk<true, RECS> wk;
+                EmitWalk<!PACK, RECS> wk;
                 wk.start(st, cnt, b0 + j0);
                 const uint32_t m = min((uint32_t)kEmitRounds, bn - j0);
                 for (uint32_t i = 0;;) {
-                    tk[i] = wk.key();
-                    tv[i] = wk.rec;
+                    if (PACK) {
+                        tk[i] = (wk.key() << 10) | wk.k;
+                    } else {
+                        tk[i] = wk.key();
+                        tv[i] = wk.rec;
+                    }
                     if (++i == m) break;
                     wk.next(st);
                 }
@@ -715,7 +725,7 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_downsweep(
                 const uint32_t p = (uint32_t)r * 64u + (uint32_t)lane;
                 const uint32_t at = (uint32_t)wave * 64u * kEmitPad + (p / kEmitRounds) * kEmitPad + p % kEmitRounds;
                 key[r] = skey[at];
-                val[r] = sval[at];
+                val[r] = PACK ? 0u : sval[at];
             }
         }
         // (the staging below reuses skey and sval after the barrier that follows the ranking)
@@ -725,7 +735,7 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_downsweep(
             if (wbase + (uint32_t)r * 64u >= bn) continue;   // uniform over the wavefront
             const uint32_t j = wbase + (uint32_t)r * 64u + (uint32_t)lane;
             const bool valid = j < bn;
-            const uint32_t d = key[r] & mask;
+            const uint32_t d = (key[r] >> kshift) & mask;
             const uint64_t peers = digit_peers(d, valid, nbits);
             const uint32_t below = (uint32_t)rank_below(peers);
             const uint32_t before = wcount[wave][d];
@@ -755,20 +765,21 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_downsweep(
         for (int r = 0; r < kEmitRounds; ++r) {
             const uint32_t j = wbase + (uint32_t)r * 64u + (uint32_t)lane;
             if (j < bn) {
-                const uint32_t d = key[r] & mask;
+                const uint32_t d = (key[r] >> kshift) & mask;
                 const uint32_t pos = dstart[d] + wcount[wave][d] + rank[r];
                 skey[pos] = key[r];
-                sval[pos] = val[r];
+                if (!PACK) sval[pos] = val[r];
             }
         }
         __syncthreads();
         for (uint32_t j = threadIdx.x; j < bn; j += kEmitThreads) {
-            const uint32_t k = skey[j];
+            const uint32_t w = skey[j];
+            const uint32_t k = w >> kshift;
             const uint32_t d = k & mask;
             const uint32_t dst = gbase[d] + (j - dstart[d]);
             if (dst < K) {   // the pair count the buffers were sized by
                 keys_out[dst] = (KT)k;
-                vals_out[dst] = sval[j];
+                vals_out[dst] = PACK ? st.rec[w & 1023u] : sval[j];
             }
         }
         __syncthreads();
