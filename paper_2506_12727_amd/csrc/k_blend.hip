@@ -91,7 +91,9 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_fwd(const DevCam* __res
         st[k] = FwdPix{sel ? 1.0f : -1.0f, 0.0f, 0.0f, 0.0f, sel ? 0u : kUnselected, 0.0f};
     }
     // The walk of walk_forward, written out here: with the call, the compiler optimises the loop
-    // apart from this kernel and the kernel runs out of scalar registers.
+    // apart from this kernel and the kernel runs out of scalar registers. The next window's loads
+    // are issued before the current window's candidates are blended.
+    WindowPre nxt = window_load(vals, recs, wt.rg.x, wt.rg.y, lane);
     for (uint32_t base = wt.rg.x; base < wt.rg.y; base += 64) {
         uint64_t lm[PPL];
         uint64_t any = 0;
@@ -104,8 +106,10 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_fwd(const DevCam* __res
         // candidates are culled against the pixels still live
         int ax0, ax1, ay0, ay1;
         active_rect<PPL, ST::SW>(lm, wt.sx0, wt.sy0, ax0, ax1, ay0, ay1);
-        uint32_t rl;
-        uint64_t m = window_mask(vals, recs, base, wt.rg.y, lane, ax0, ax1, ay0, ay1, rl);
+        const WindowPre cur = nxt;
+        const uint32_t rl = cur.rl;
+        uint64_t m = window_test(cur, recs, ax0, ax1, ay0, ay1);
+        if (base + 64u < wt.rg.y) nxt = window_load(vals, recs, base + 64u, wt.rg.y, lane);
         while (m) {
             // up to four records per round trip through the scalar cache
             const int j0 = __builtin_ctzll(m);
