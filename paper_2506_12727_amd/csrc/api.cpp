@@ -934,7 +934,9 @@ int forward_impl(mvgs_context* ctx, void* stream, const mvgs_gaussians* g, const
     uint32_t* dv[2] = {as<uint32_t>(ctx->rec_vals[0]), as<uint32_t>(ctx->rec_vals[1])};
     // the records' tile rectangles travel with their depth keys
     uint2* rect[2] = {as<uint2>(ctx->tile_rect), as<uint2>(ctx->sorted_rect)};
-    const int dcur = radix_sort_u32(dk, dv, true, V, depth_bits, ctx->sort_scratch.p, s, eff, depth_base, rect);
+    // (only the order is used: the last pass writes no keys)
+    const int dcur =
+        radix_sort_u32(dk, dv, true, V, depth_bits, ctx->sort_scratch.p, s, eff, depth_base, rect, false);
     const uint32_t* sorted_rec = dv[dcur];
     ctx->stage_end(mk, s);
 

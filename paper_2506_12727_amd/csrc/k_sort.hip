@@ -364,7 +364,7 @@ __global__ void __launch_bounds__(WAVES * 64) k_radix_downsweep(
         const uint32_t k = stg.kv.k[j];
         const uint32_t d = ((k - key_base) >> shift) & mask;
         const size_t dst = (size_t)gbase[d] + (uint32_t)(j - dstart[d]);
-        keys_out[dst] = (KT)k;
+        if (keys_out) keys_out[dst] = (KT)k;   // null: the keys are not needed after this pass
         vals_out[dst] = stg.kv.v[j];
     }
     if (PAY) {
@@ -442,14 +442,15 @@ static void radix_pass(const KT* keys_in, const uint32_t* vals_in, KT* keys_out,
 }
 
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
-                   hipStream_t s, const uint32_t* n_dev, uint32_t key_base, uint2* pay[2]) {
+                   hipStream_t s, const uint32_t* n_dev, uint32_t key_base, uint2* pay[2], bool sorted_keys) {
     int cur = 0;
     if (n == 0 || bits <= 0) return cur;
     const PassPlan pl = plan_passes(bits);
     for (int pass = 0; pass < pl.passes; ++pass) {
         const uint32_t* vin = (pass == 0 && identity_values) ? nullptr : vals[cur];
-        radix_pass<uint32_t>(keys[cur], vin, keys[cur ^ 1], vals[cur ^ 1], n, n_dev, key_base, pl.dbits * pass,
-                             pl.mask, scratch, s, pay ? pay[cur] : nullptr, pay ? pay[cur ^ 1] : nullptr);
+        uint32_t* kout = (pass + 1 == pl.passes && !sorted_keys) ? nullptr : keys[cur ^ 1];
+        radix_pass<uint32_t>(keys[cur], vin, kout, vals[cur ^ 1], n, n_dev, key_base, pl.dbits * pass, pl.mask,
+                             scratch, s, pay ? pay[cur] : nullptr, pay ? pay[cur ^ 1] : nullptr);
         cur ^= 1;
     }
     return cur;

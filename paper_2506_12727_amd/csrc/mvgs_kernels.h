@@ -70,10 +70,12 @@ void reduce_sum_u32(const uint32_t* in, size_t n, uint64_t* total64, void* scrat
 // (count, scatter) and writes keys and values once. The input is in keys[0] and vals[0] (or, with
 // identity_values, the values are 0..n-1 and vals[0] is only ping-pong space); passes alternate
 // between buffers 0 and 1. With pay, an 8-byte payload per item (input in pay[0]) travels with
-// its key the same way. Returns the index of the buffer holding the result.
+// its key the same way. Returns the index of the buffer holding the result; with sorted_keys
+// false the last pass writes no keys (only the order of the values and payloads is wanted).
 size_t radix_scratch_bytes(size_t n);
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], bool identity_values, size_t n, int bits, void* scratch,
-                   hipStream_t s, const uint32_t* n_dev = nullptr, uint32_t key_base = 0, uint2* pay[2] = nullptr);
+                   hipStream_t s, const uint32_t* n_dev = nullptr, uint32_t key_base = 0, uint2* pay[2] = nullptr,
+                   bool sorted_keys = true);
 
 void fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 // per * min(*n_dev, n) values (all per * n when n_dev is null)
