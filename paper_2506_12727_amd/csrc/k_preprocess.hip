@@ -154,8 +154,45 @@ __device__ __forceinline__ void record_side(const BlendRec& r, const DevCam* __r
 // wavefront per workgroup: its 64 Gaussians own one contiguous run of records, which is staged in
 // LDS while the lanes project view after view and then written out by consecutive lanes (each
 // lane's own records lie a Gaussian's worth of views apart, so direct stores would leave lines
-// half written); a run longer than the stage is written directly.
+// half written). A run a little longer than the stage goes through it in two windows: the second
+// repeats, for the lanes whose records straddle the two, the participation tests of the views
+// before it, and evaluates colours and assembles only its own records. A run longer still (many
+// views per Gaussian) is written directly: with two windows of about half the lanes each, the
+// wavefront's serial time would double.
 constexpr uint32_t kRecStage = 512;   // records (32 KiB)
+
+// The record of a participating (view, Gaussian): its projection p, colour from the SH
+// coefficients along the view direction (clamped at 0), opacity o.
+template <int D>
+__device__ __forceinline__ BlendRec make_record(const ProjOut& p, const float (&mu)[3], float o,
+                                                const float (&coef)[(D + 1) * (D + 1)][3], const DevCam& c,
+                                                uint32_t g, uint32_t v) {
+    constexpr int K = (D + 1) * (D + 1);
+    float dx = mu[0] - c.campos[0], dy = mu[1] - c.campos[1], dz = mu[2] - c.campos[2];
+    const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= il; dy *= il; dz *= il;
+    float Y[16];
+    sh_basis<D>(dx, dy, dz, Y);
+    float rgb[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float a = 0.5f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) a = __builtin_fmaf(coef[k][ch], Y[k], a);
+        rgb[ch] = a > 0.0f ? a : 0.0f;
+    }
+    BlendRec r;
+    r.boxx = (uint32_t)p.x0 | ((uint32_t)p.x1 << 16);
+    r.boxy = (uint32_t)p.y0 | ((uint32_t)p.y1 << 16);
+    r.mx = p.mx; r.my = p.my;
+    r.hca = p.hca; r.nb = p.nb; r.hcc = p.hcc; r.o = o;
+    r.cut = p.cut; r.hi = p.hi; r.r = rgb[0]; r.g = rgb[1];
+    r.b = rgb[2];
+    r.gid = g;
+    r.view = v;
+    r.depth_bits = f2u(p.depth);
+    return r;
+}
 
 template <int D>
 __global__ void __launch_bounds__(64) k_records(const float* __restrict__ means, const float* __restrict__ scales,
@@ -172,64 +209,60 @@ __global__ void __launch_bounds__(64) k_records(const float* __restrict__ means,
     const int64_t g0 = (int64_t)blockIdx.x * 64;
     const int64_t g1 = g0 + 64 < P ? g0 + 64 : P;
     const uint32_t base = rec_off[g0], n_run = rec_off[g1] - base;
-    const bool staged = n_run <= kRecStage;
     const int64_t g = g0 + threadIdx.x;
-    if (g < P) {
-        float mu[3], s[3], q[4], o;
+    const bool here = g < P;
+    float mu[3] = {0.0f, 0.0f, 0.0f}, s[3] = {0.0f, 0.0f, 0.0f}, q[4] = {1.0f, 0.0f, 0.0f, 0.0f}, o = 0.0f;
+    float coef[K][3];
+    uint32_t out0 = 0, out_end = 0;
+    if (here) {
         load_gaussian(means, scales, quats, opac, g, mu, s, q, o);
-        float coef[K][3];
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) coef[k][ch] = sh[(g * K + k) * 3 + ch];
-        GaussGeom geo;
-        gauss_geom(s, q, o, geo);
-        uint32_t out = rec_off[g];
-        const uint32_t out_end = rec_off[g + 1];
+        out0 = rec_off[g];
+        out_end = rec_off[g + 1];
+    }
+    GaussGeom geo;
+    gauss_geom(s, q, o, geo);
+    const bool staged = n_run <= kRecStage + kRecStage / 4;   // uniform over the workgroup
+    if (!staged) {
+        if (!here) return;
+        uint32_t out = out0;
         for (int v = 0; v < B && out < out_end; ++v) {
             const DevCam& c = cams[v];
             ProjState st;
             const ProjOut p = project(mu, geo, c, st);
             if (!p.ok) continue;
-            float dx = mu[0] - c.campos[0], dy = mu[1] - c.campos[1], dz = mu[2] - c.campos[2];
-            const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-            dx *= il; dy *= il; dz *= il;
-            float Y[16];
-            sh_basis<D>(dx, dy, dz, Y);
-            float rgb[3];
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                float a = 0.5f;
-#pragma unroll
-                for (int k = 0; k < K; ++k) a = __builtin_fmaf(coef[k][ch], Y[k], a);
-                rgb[ch] = a > 0.0f ? a : 0.0f;
-            }
-            BlendRec r;
-            r.boxx = (uint32_t)p.x0 | ((uint32_t)p.x1 << 16);
-            r.boxy = (uint32_t)p.y0 | ((uint32_t)p.y1 << 16);
-            r.mx = p.mx; r.my = p.my;
-            r.hca = p.hca; r.nb = p.nb; r.hcc = p.hcc; r.o = o;
-            r.cut = p.cut; r.hi = p.hi; r.r = rgb[0]; r.g = rgb[1];
-            r.b = rgb[2];
-            r.gid = (uint32_t)g;
-            r.view = (uint32_t)v;
-            r.depth_bits = f2u(p.depth);
-            if (staged) {
-                stage[out - base] = r;
-            } else {
-                recs[out] = r;
-                record_side(r, cams, tile_w, tile_h, out, depth_key, tile_rect, rec_view);
-            }
+            const BlendRec r = make_record<D>(p, mu, o, coef, c, (uint32_t)g, (uint32_t)v);
+            recs[out] = r;
+            record_side(r, cams, tile_w, tile_h, out, depth_key, tile_rect, rec_view);
             ++out;
         }
+        return;
     }
-    if (!staged) return;
-    __syncthreads();
-    const uint4* src = reinterpret_cast<const uint4*>(stage);
-    uint4* dst = reinterpret_cast<uint4*>(recs + base);
-    for (uint32_t i = threadIdx.x; i < 4 * n_run; i += 64) dst[i] = src[i];
-    for (uint32_t i = threadIdx.x; i < n_run; i += 64)
-        record_side(stage[i], cams, tile_w, tile_h, base + i, depth_key, tile_rect, rec_view);
+    for (uint32_t w0 = 0; w0 < n_run; w0 += kRecStage) {
+        const uint32_t lo = base + w0, hi = base + min(n_run, w0 + kRecStage);
+        if (here && out0 < hi && out_end > lo) {
+            uint32_t out = out0;
+            for (int v = 0; v < B && out < out_end && out < hi; ++v) {
+                const DevCam& c = cams[v];
+                ProjState st;
+                const ProjOut p = project(mu, geo, c, st);
+                if (!p.ok) continue;
+                if (out >= lo) stage[out - lo] = make_record<D>(p, mu, o, coef, c, (uint32_t)g, (uint32_t)v);
+                ++out;
+            }
+        }
+        __syncthreads();
+        const uint32_t n = hi - lo;
+        const uint4* src = reinterpret_cast<const uint4*>(stage);
+        uint4* dst = reinterpret_cast<uint4*>(recs + lo);
+        for (uint32_t i = threadIdx.x; i < 4 * n; i += 64) dst[i] = src[i];
+        for (uint32_t i = threadIdx.x; i < n; i += 64)
+            record_side(stage[i], cams, tile_w, tile_h, lo + i, depth_key, tile_rect, rec_view);
+        __syncthreads();   // the stage is reused by the next window
+    }
 }
 
 // Backward chain per Gaussian over its records (2D gradients -> parameters), summed over
