@@ -20,9 +20,11 @@ import torch
 
 from .raster import GaussianTensors, Rasterizer
 
+# one pixel per lane (more wavefronts per tile) wins on small frames, whose few tiles leave
+# most of the chip idle at 2 or 4
 CANDIDATES: List[Tuple[Tuple[int, int], int]] = [
     ((16, 16), 2), ((16, 16), 4), ((32, 16), 4), ((16, 32), 4), ((32, 32), 4), ((32, 32), 2),
-    ((32, 16), 2), ((16, 32), 2),
+    ((32, 16), 2), ((16, 32), 2), ((16, 16), 1), ((8, 8), 1),
 ]
 
 CACHE_ENV = "MVGS_TUNE_CACHE"
