@@ -21,6 +21,13 @@ __device__ __forceinline__ void load_gaussian(const float* __restrict__ means, c
     o = opac[g];
 }
 
+// Tiles covered by the inclusive pixel range [a, b] (0 <= a <= b) of tiles `tile` pixels wide, a
+// power of two (8, 16 or 32): a shift, where an integer division would take a long VALU sequence.
+__device__ __forceinline__ int tile_span(int a, int b, int tile) {
+    const int sh = __builtin_ctz((unsigned)tile);
+    return (b >> sh) - (a >> sh) + 1;
+}
+
 // Number of participating views and of covered tiles (summed over views) per Gaussian.
 __global__ void __launch_bounds__(256) k_count(const float* __restrict__ means, const float* __restrict__ scales,
                                                const float* __restrict__ quats, const float* __restrict__ opac,
@@ -41,7 +48,7 @@ __global__ void __launch_bounds__(256) k_count(const float* __restrict__ means, 
             const ProjOut p = project(mu, geo, cams[v], st);
             if (p.ok) {
                 n += 1;
-                nt += (uint32_t)((p.x1 / tile_w - p.x0 / tile_w + 1) * (p.y1 / tile_h - p.y0 / tile_h + 1));
+                nt += (uint32_t)(tile_span(p.x0, p.x1, tile_w) * tile_span(p.y0, p.y1, tile_h));
                 kmin = min(kmin, f2u(p.depth));
                 kmax = max(kmax, f2u(p.depth));
             }
@@ -100,7 +107,7 @@ __global__ void __launch_bounds__(256) k_count_views(const float* __restrict__ m
             const ProjOut p = project(mu, geo, cams[v], st);
             if (p.ok) {
                 n = 1;
-                nt = (uint32_t)((p.x1 / tile_w - p.x0 / tile_w + 1) * (p.y1 / tile_h - p.y0 / tile_h + 1));
+                nt = (uint32_t)(tile_span(p.x0, p.x1, tile_w) * tile_span(p.y0, p.y1, tile_h));
             }
         }
         // at most 256 x 65,536 tiles per workgroup: the sums fit 32 bits
@@ -142,8 +149,9 @@ __device__ __forceinline__ void record_side(const BlendRec& r, const DevCam* __r
                                             uint2* __restrict__ tile_rect, uint16_t* __restrict__ rec_view) {
     const DevCam& c = cams[r.view];
     const uint32_t x0 = r.boxx & 0xffffu, x1 = r.boxx >> 16, y0 = r.boxy & 0xffffu, y1 = r.boxy >> 16;
-    const uint32_t tx0 = x0 / (uint32_t)tile_w, ty0 = y0 / (uint32_t)tile_h;
-    const uint32_t tw_n = x1 / (uint32_t)tile_w - tx0 + 1, th_n = y1 / (uint32_t)tile_h - ty0 + 1;
+    const uint32_t sw = (uint32_t)__builtin_ctz((unsigned)tile_w), shh = (uint32_t)__builtin_ctz((unsigned)tile_h);
+    const uint32_t tx0 = x0 >> sw, ty0 = y0 >> shh;   // tiles are 8, 16 or 32 pixels
+    const uint32_t tw_n = (x1 >> sw) - tx0 + 1, th_n = (y1 >> shh) - ty0 + 1;
     rec_view[i] = (uint16_t)r.view;
     depth_key[i] = r.depth_bits;
     tile_rect[i] = make_uint2(c.tile_base + ty0 * (uint32_t)c.tiles_x + tx0, tw_n | (th_n << 16));
