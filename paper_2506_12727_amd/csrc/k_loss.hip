@@ -141,34 +141,37 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_fused(const float* __rest
     }
 #pragma unroll
     for (int round = 0; round < 3; ++round) {
-        for (int task = t; task < kSsimI * 6; task += kSsimThreads) {
-            const int r = task / 6, j0 = (task - r * 6) * 7;
-            float u[17], v[17];
+        // one task per thread: row r, output columns j0 .. j0 + n - 1 (groups of 11, 11, 10, 10 of
+        // the 42), the products I^2, T^2 or I T formed once per input
+        if (t < kSsimI * 4) {
+            const int r = t >> 2, g = t & 3;
+            const int j0 = g < 2 ? 11 * g : 22 + 10 * (g - 2);
+            const int n = g < 2 ? 11 : 10;
+            float u[21], v[21];
 #pragma unroll
-            for (int k = 0; k < 17; ++k) {
-                u[k] = L.u.in[0][r][j0 + k];
-                v[k] = L.u.in[1][r][j0 + k];
+            for (int k = 0; k < 21; ++k) {
+                const bool ok = k < n + 10;
+                u[k] = ok ? L.u.in[0][r][j0 + k] : 0.0f;
+                v[k] = ok ? L.u.in[1][r][j0 + k] : 0.0f;
+                if (round == 1) {
+                    u[k] = u[k] * u[k];
+                    v[k] = v[k] * v[k];
+                } else if (round == 2) {
+                    u[k] = u[k] * v[k];
+                }
             }
 #pragma unroll
-            for (int jj = 0; jj < 7; ++jj) {
+            for (int jj = 0; jj < 11; ++jj) {
                 float m0 = 0, m1 = 0;
 #pragma unroll
                 for (int k = 0; k < 11; ++k) {
-                    const float uu = u[jj + k], vv = v[jj + k], w = win.w[k];
-                    if (round == 0) {
-                        m0 = __builtin_fmaf(w, uu, m0);
-                        m1 = __builtin_fmaf(w, vv, m1);
-                    } else if (round == 1) {
-                        const float wu = w * uu, wv = w * vv;
-                        m0 = __builtin_fmaf(wu, uu, m0);
-                        m1 = __builtin_fmaf(wv, vv, m1);
-                    } else {
-                        const float wu = w * uu;
-                        m0 = __builtin_fmaf(wu, vv, m0);
-                    }
+                    m0 = __builtin_fmaf(win.w[k], u[jj + k], m0);
+                    if (round < 2) m1 = __builtin_fmaf(win.w[k], v[jj + k], m1);
                 }
-                L.v.hs[0][r][j0 + jj] = m0;
-                if (round < 2) L.v.hs[1][r][j0 + jj] = m1;
+                if (jj < n) {
+                    L.v.hs[0][r][j0 + jj] = m0;
+                    if (round < 2) L.v.hs[1][r][j0 + jj] = m1;
+                }
             }
         }
         __syncthreads();
@@ -217,20 +220,23 @@ __global__ void __launch_bounds__(kSsimThreads) k_ssim_fused(const float* __rest
         }
     }
     __syncthreads();
-    // 4. derivative maps along x: row i, output columns jq .. jq + 7 of the 32
-    if (t < kSsimA * 4) {
-        const int i = t >> 2, jq0 = (t & 3) * 8;
+    // 4. derivative maps along x: row i, output columns jq0 .. jq0 + n - 1 of the 32 (groups of
+    // 6, 6, 5, 5, 5, 5: 252 tasks, one per thread)
+    if (t < kSsimA * 6) {
+        const int i = t / 6, g = t - i * 6;
+        const int jq0 = g < 2 ? 6 * g : 12 + 5 * (g - 2);
+        const int n = g < 2 ? 6 : 5;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            float h[18];
+            float h[16];
 #pragma unroll
-            for (int k = 0; k < 18; ++k) h[k] = L.u.abc[c][i][jq0 + k];
+            for (int k = 0; k < 16; ++k) h[k] = k < n + 10 ? L.u.abc[c][i][jq0 + k] : 0.0f;
 #pragma unroll
-            for (int jj = 0; jj < 8; ++jj) {
+            for (int jj = 0; jj < 6; ++jj) {
                 float acc = 0.0f;
 #pragma unroll
                 for (int k = 0; k < 11; ++k) acc = __builtin_fmaf(win.w[k], h[jj + k], acc);
-                L.v.hb[c][i][jq0 + jj] = acc;
+                if (jj < n) L.v.hb[c][i][jq0 + jj] = acc;
             }
         }
     }
