@@ -507,18 +507,18 @@ struct EmitStage {
     uint32_t vtx[kEmitViews];      // and tiles per row
 };
 
-// tiles per row of the view holding global tile id `tile`
-template <int RECS>
-__device__ __forceinline__ uint32_t emit_stride(const EmitStage<RECS>& st, const DevCam* __restrict__ cams, int B,
-                                                uint32_t tile) {
+// tiles per row of the view holding global tile id `tile` (vbase, vtx: the LDS table of the first
+// kEmitViews views)
+__device__ __forceinline__ uint32_t emit_stride(const uint32_t* vbase, const uint32_t* vtx,
+                                                const DevCam* __restrict__ cams, int B, uint32_t tile) {
     if (B > kEmitViews) return (uint32_t)cams[find_view(cams, B, tile)].tiles_x;
     int lo = 0, hi = B;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (st.vbase[mid] <= tile) lo = mid;
+        if (vbase[mid] <= tile) lo = mid;
         else hi = mid;
     }
-    return st.vtx[lo];
+    return vtx[lo];
 }
 
 // Stages records [r0, r0 + cnt) of the depth order (cnt <= RECS); returns the chunk's pairs.
@@ -554,7 +554,7 @@ __device__ __forceinline__ uint32_t emit_stage(const uint32_t* __restrict__ sort
             c[k] = rect_tiles(rc[k]);
             st.base[i] = rc[k].x;
             st.wdt[i] = rc[k].y & 0xffffu;
-            st.stride[i] = emit_stride(st, cams, B, rc[k].x);
+            st.stride[i] = emit_stride(st.vbase, st.vtx, cams, B, rc[k].x);
         }
         sum += c[k];
     }
@@ -629,38 +629,63 @@ struct EmitWalk {
     }
 };
 
-// The digit counts of the chunk's pairs.
+// The digit counts of the chunk's pairs, without generating them: a row of a record's tile
+// rectangle is a run of consecutive tile ids, so its digits (the low bits of the ids) are a cyclic
+// run of consecutive digits. Each thread takes whole records and adds each row to a difference
+// array over the digits (a run as long as the digit range adds to every digit once); a scan of
+// the differences gives the counts.
 template <int RECS>
 __global__ void __launch_bounds__(kSortThreads) k_emit_upsweep(const uint32_t* __restrict__ sorted_rec,
                                                                const uint2* __restrict__ sorted_rect,
                                                                const DevCam* __restrict__ cams, int B, uint32_t n,
                                                                const uint32_t* __restrict__ n_dev, uint32_t mask,
                                                                uint32_t chunks, uint32_t* __restrict__ counts) {
-    __shared__ EmitStage<RECS> st;
-    __shared__ uint32_t h[kRadix];
+    (void)sorted_rec;
+    __shared__ uint32_t vbase[kEmitViews], vtx[kEmitViews];
+    __shared__ int diff[kRadix + 1];
     __shared__ uint32_t scan_tmp[kRadix];
-    h[threadIdx.x] = 0;
+    __shared__ uint32_t full;
+    const uint32_t t = threadIdx.x;
+    diff[t] = 0;
+    if (t == 0) {
+        diff[kRadix] = 0;
+        full = 0u;
+    }
+    if ((int)t < B && t < (uint32_t)kEmitViews) {
+        vbase[t] = cams[t].tile_base;
+        vtx[t] = (uint32_t)cams[t].tiles_x;
+    }
     n = (uint32_t)count_of(n, n_dev);
     const uint32_t r0 = blockIdx.x * RECS;
-    if (r0 < n) {   // uniform over the workgroup
-        const uint32_t cnt = min(n - r0, (uint32_t)RECS);
-        const uint32_t total = emit_stage<RECS, kSortThreads>(sorted_rec, sorted_rect, cams, B, r0, cnt, st, scan_tmp);
-        // each thread counts a contiguous run of pairs, walking the rectangles row-major
-        const uint32_t q = (total + kSortThreads - 1) / kSortThreads;
-        uint32_t j = threadIdx.x * q;
-        const uint32_t jend = min(j + q, total);
-        if (j < jend) {
-            EmitWalk<false, RECS> wk;
-            wk.start(st, cnt, j);
-            for (;;) {
-                atomicAdd(&h[wk.key() & mask], 1u);
-                if (++j == jend) break;
-                wk.next(st);
+    const uint32_t cnt = r0 < n ? min(n - r0, (uint32_t)RECS) : 0u;
+    const uint32_t R = mask + 1u;   // digits of the pass (a power of two)
+    __syncthreads();
+    uint32_t cycles = 0;   // whole runs through all R digits
+    for (uint32_t i = t; i < cnt; i += kSortThreads) {
+        const uint2 rc = sorted_rect[r0 + i];
+        const uint32_t w = rc.y & 0xffffu, h = rc.y >> 16;
+        if (w == 0u || h == 0u) continue;
+        const uint32_t stride = emit_stride(vbase, vtx, cams, B, rc.x);
+        cycles += h * (w / R);
+        const uint32_t m = w & mask;   // the partial run of each row
+        if (m == 0u) continue;
+        for (uint32_t row = 0; row < h; ++row) {
+            const uint32_t d0 = (rc.x + row * stride) & mask, e = d0 + m;
+            atomicAdd(&diff[d0], 1);
+            if (e <= R) {
+                atomicAdd(&diff[e], -1);
+            } else {
+                atomicAdd(&diff[0], 1);
+                atomicAdd(&diff[e - R], -1);
             }
         }
     }
+    if (cycles) atomicAdd(&full, cycles);
     __syncthreads();
-    if (threadIdx.x <= mask) counts[(size_t)threadIdx.x * chunks + blockIdx.x] = h[threadIdx.x];
+    uint32_t total;
+    const uint32_t v = t < R ? (uint32_t)diff[t] : 0u;
+    const uint32_t c = block_exclusive_scan_256(v, scan_tmp, &total) + v + full;   // inclusive
+    if (t <= mask) counts[(size_t)t * chunks + blockIdx.x] = c;
 }
 
 template <int RECS, typename KT>
