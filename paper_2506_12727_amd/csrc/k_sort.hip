@@ -500,8 +500,8 @@ template <int RECS>
 struct EmitStage {
     uint32_t off[RECS + 1];   // exclusive prefix of the pair counts (+ total)
     uint32_t base[RECS];      // global tile id of the first covered tile
-    uint32_t wdt[RECS];       // rectangle width in tiles
-    uint32_t stride[RECS];    // tiles per row of the record's view
+    uint32_t ws[RECS];        // (rectangle width - 1) | (tiles per row of its view - 1) << 16
+                              // (both at most 65,536: tiles per view)
     uint32_t rec[RECS];
     uint32_t vbase[kEmitViews];    // the views' first tile ids
     uint32_t vtx[kEmitViews];      // and tiles per row
@@ -553,8 +553,7 @@ __device__ __forceinline__ uint32_t emit_stage(const uint32_t* __restrict__ sort
         if (i < cnt) {
             c[k] = rect_tiles(rc[k]);
             st.base[i] = rc[k].x;
-            st.wdt[i] = rc[k].y & 0xffffu;
-            st.stride[i] = emit_stride(st.vbase, st.vtx, cams, B, rc[k].x);
+            st.ws[i] = ((rc[k].y & 0xffffu) - 1u) | ((emit_stride(st.vbase, st.vtx, cams, B, rc[k].x) - 1u) << 16);
         }
         sum += c[k];
     }
@@ -590,8 +589,9 @@ struct EmitWalk {
     __device__ __forceinline__ void start(const EmitStage<RECS>& st, uint32_t cnt, uint32_t j) {
         k = emit_find(st, cnt, j);
         if (REC) rec = st.rec[k];
-        w = st.wdt[k];
-        stride = st.stride[k];
+        const uint32_t ws = st.ws[k];
+        w = (ws & 0xffffu) + 1u;
+        stride = (ws >> 16) + 1u;
         left = st.off[k + 1] - j;
         const uint32_t t = j - st.off[k];
         // t < 65536 (tiles per view), so (t + 0.5) / w in float32 is never within rounding of an integer
@@ -607,18 +607,17 @@ struct EmitWalk {
             // which the loop passes over, are rare)
             ++k;
             uint32_t o0 = st.off[k], o1 = st.off[k + 1];
-            uint32_t nb = st.base[k], nw = st.wdt[k], ns = st.stride[k], nr = REC ? st.rec[k] : 0u;
+            uint32_t nb = st.base[k], nws = st.ws[k], nr = REC ? st.rec[k] : 0u;
             while (o1 == o0) {
                 ++k;
                 o1 = st.off[k + 1];
                 nb = st.base[k];
-                nw = st.wdt[k];
-                ns = st.stride[k];
+                nws = st.ws[k];
                 if (REC) nr = st.rec[k];
             }
             rec = nr;
-            w = nw;
-            stride = ns;
+            w = (nws & 0xffffu) + 1u;
+            stride = (nws >> 16) + 1u;
             left = o1 - o0;
             rowkey = nb;
             col = 0;
@@ -700,7 +699,8 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_downsweep(
     constexpr bool PACK = sizeof(KT) == 2;
     static_assert(!PACK || RECS <= 1024, "packed pairs hold a 10-bit record index");
     __shared__ EmitStage<RECS> st;
-    __shared__ uint32_t wcount[kEmitWaves][kRadix];
+    // per wavefront and digit: its items in the batch, then their offset (at most kEmitBatch)
+    __shared__ uint16_t wcount[kEmitWaves][kRadix];
     __shared__ uint32_t dstart[kRadix];
     __shared__ uint32_t gbase[kRadix];
     __shared__ uint32_t scan_tmp[kRadix];
@@ -767,7 +767,7 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_downsweep(
             const uint32_t before = wcount[wave][d];
             rank[r] = before + below;
             wave_lds_sync();
-            if (valid && below == 0) wcount[wave][d] = before + (uint32_t)__popcll(peers);
+            if (valid && below == 0) wcount[wave][d] = (uint16_t)(before + (uint32_t)__popcll(peers));
             wave_lds_sync();
         }
         __syncthreads();
@@ -778,7 +778,7 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_downsweep(
 #pragma unroll
                 for (int w = 0; w < kEmitWaves; ++w) {
                     const uint32_t c = wcount[w][d];
-                    wcount[w][d] = run;
+                    wcount[w][d] = (uint16_t)run;
                     run += c;
                 }
             }
