@@ -634,12 +634,10 @@ struct EmitWalk {
 // array over the digits (a run as long as the digit range adds to every digit once); a scan of
 // the differences gives the counts.
 template <int RECS>
-__global__ void __launch_bounds__(kSortThreads) k_emit_upsweep(const uint32_t* __restrict__ sorted_rec,
-                                                               const uint2* __restrict__ sorted_rect,
+__global__ void __launch_bounds__(kSortThreads) k_emit_upsweep(const uint2* __restrict__ sorted_rect,
                                                                const DevCam* __restrict__ cams, int B, uint32_t n,
                                                                const uint32_t* __restrict__ n_dev, uint32_t mask,
                                                                uint32_t chunks, uint32_t* __restrict__ counts) {
-    (void)sorted_rec;
     __shared__ uint32_t vbase[kEmitViews], vtx[kEmitViews];
     __shared__ int diff[kRadix + 1];
     __shared__ uint32_t scan_tmp[kRadix];
@@ -865,8 +863,8 @@ void emit_pairs_first_pass(const uint32_t* sorted_rec, const uint2* sorted_rect,
     uint32_t* counts = (uint32_t*)p;
     p += align256(chunks * kRadix * sizeof(uint32_t));
     hipLaunchKernelGGL(small_rects ? k_emit_upsweep<kEmitRecsSmall> : k_emit_upsweep<kEmitRecs>,
-                       dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rec, sorted_rect, cams, B,
-                       (uint32_t)n_rec, n_rec_dev, first_mask, (uint32_t)chunks, counts);
+                       dim3((unsigned)chunks), dim3(kSortThreads), 0, s, sorted_rect, cams, B, (uint32_t)n_rec,
+                       n_rec_dev, first_mask, (uint32_t)chunks, counts);
     scan_exclusive_u32(counts, counts, chunks * ((size_t)first_mask + 1), nullptr, p, s, nullptr);
     if (key16)
         hipLaunchKernelGGL(
