@@ -46,6 +46,13 @@ CASES = {
     # with records that cover few tiles each (the 1,024-record emission chunks)
     "many_views": lambda: (scenes.make_scene(3000, 1, log_scale_mean=-3.6),
                            scenes.make_cameras([(24, 20), (17, 31)] * 70, seed=23), (16, 16), 0),
+    # about 9 records per Gaussian: the records of 64 Gaussians just exceed the 512-record LDS stage
+    # of the records kernel (46 of 47 runs go through it in two windows)
+    "nine_views": lambda: (scenes.make_scene(3000, 1, log_scale_mean=-3.0),
+                           scenes.make_cameras([(64, 48)] * 9, seed=31), (16, 16), 0),
+    # 12 records per Gaussian: every run of 64 Gaussians (762-768 records) is written directly
+    "twelve_views": lambda: (scenes.make_scene(3008, 1, log_scale_mean=-2.6),
+                             scenes.make_cameras([(64, 48)] * 12, seed=5), (16, 16), 0),
 }
 
 
