@@ -82,6 +82,28 @@ def test_capacity_mode_matches_eager():
     eager.release(fe)
 
 
+def test_capacity_mode_matches_eager_above_16_bit_tile_ids():
+    """131,072 tiles (two 2048 x 2048 views at 8x8): 32-bit pair keys in both modes."""
+    needs_gpu()
+    sc = scenes.make_scene(3000, 0, log_scale_mean=-3.2)
+    cams = [scenes.make_camera(2048, 2048, (0.0, 0.3, -2.5)), scenes.make_camera(2048, 2048, (0.4, -0.2, -2.7))]
+    g = GaussianTensors.from_scene(sc)
+    eager = Rasterizer((8, 8))
+    imgs_e, fe = eager.forward(g, cams)
+    info = fe.info()
+    assert info["tiles"] == 131072
+    ke, ve, re_ = eager.export_binning(fe)
+    cap = Rasterizer((8, 8), capacity=(info["records"] + 999, info["pairs"] + 4999))
+    imgs_c, fc = cap.forward(g, cams)
+    fc.check()
+    for a, b in zip(imgs_c, imgs_e):
+        assert torch.equal(a, b)
+    kc, vc, rc = cap.export_binning(fc)
+    assert torch.equal(kc, ke) and torch.equal(vc, ve) and torch.equal(rc, re_)
+    cap.release(fc)
+    eager.release(fe)
+
+
 def test_capacity_overflow_is_reported_and_harmless():
     needs_gpu()
     sc, cams = _batch()
