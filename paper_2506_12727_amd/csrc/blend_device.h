@@ -8,8 +8,6 @@
 namespace mvgs {
 
 
-constexpr float kLog2e = 1.4426950408889634f;
-
 // Contiguous tile runs per XCD: block b is dispatched to XCD b % 8.
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
     const uint32_t x = b & 7u, k = b >> 3;
@@ -21,7 +19,8 @@ __device__ __forceinline__ bool box_misses(uint32_t bx, uint32_t by, int sx0, in
     return (int)(bx & 0xffffu) > sx1 || (int)(bx >> 16) < sx0 || (int)(by & 0xffffu) > sy1 || (int)(by >> 16) < sy0;
 }
 
-__device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
+// a record's exponent is in base 2 already (BlendRec)
+__device__ __forceinline__ float weight_of(float power2) { return __builtin_amdgcn_exp2f(power2); }
 
 // Wavefront-uniform copy of the fields the walks use.
 struct RecS {
@@ -184,7 +183,7 @@ __device__ __forceinline__ void blend_step(FwdPix& st, const RecS& q, const Powe
     if (!pix_live(st)) return;
     const float power = power_y(t, py, q.my, q.hcc);
     if (power >= q.cut) {
-        const float alpha = (power > q.hi) ? kAlphaMax : q.o * fast_exp(power);
+        const float alpha = (power > q.hi) ? kAlphaMax : q.o * weight_of(power);
         const float Tn = __builtin_fmaf(-st.T, alpha, st.T);
         if (Tn < kTStop) {
             st.T = -st.T;
@@ -217,11 +216,12 @@ struct BwdPix {
 };
 
 // Per-lane sums of one Gaussian's gradient contributions over the lane's pixels. Without E1 the
-// mean and conic terms are gathered as s0 = sum dpow, s1 = sum dpow dy, s2 = sum dpow dy^2 (the
-// lane's pixels share dx) and expanded once per lane in unblend_step.
+// field o first holds s0 = sum dpow, with dpow = dalpha alpha = w (dC . (c - behind)) for an
+// unclamped pixel, and s1 = sum dpow dy, s2 = sum dpow dy^2 (the lane's pixels share dx);
+// unblend_step expands them once, the opacity gradient sum dalpha G being s0 / o.
 struct BwdSum {
     float mx, my, ca, cb, cc, o, r, g, b, e1;
-    float s0, s1, s2;
+    float s1, s2;
     bool contrib;
 };
 
@@ -234,23 +234,25 @@ __device__ __forceinline__ void unblend_pixel(BwdPix& st, BwdSum& a, const RecS&
     if (!(power >= q.cut)) return;
     a.contrib = true;
     const bool clamped = power > q.hi;
-    const float G = fast_exp(power);
+    const float G = weight_of(power);
     const float alpha = clamped ? kAlphaMax : q.o * G;
     st.T = st.T * __builtin_amdgcn_rcpf(1.0f - alpha);   // transmittance in front of this Gaussian
     const float w = alpha * st.T;
     a.r = __builtin_fmaf(st.dC0, w, a.r);
     a.g = __builtin_fmaf(st.dC1, w, a.g);
     a.b = __builtin_fmaf(st.dC2, w, a.b);
-    const float dalpha = st.T * (st.dC0 * (q.r - st.Rb0) + st.dC1 * (q.g - st.Rb1) + st.dC2 * (q.b - st.Rb2));
+    // fused: the build keeps contraction off, so the dot product is written with explicit FMAs
+    const float dot = __builtin_fmaf(st.dC0, q.r - st.Rb0, __builtin_fmaf(st.dC1, q.g - st.Rb1, st.dC2 * (q.b - st.Rb2)));
     st.Rb0 = __builtin_fmaf(q.r - st.Rb0, alpha, st.Rb0);
     st.Rb1 = __builtin_fmaf(q.g - st.Rb1, alpha, st.Rb1);
     st.Rb2 = __builtin_fmaf(q.b - st.Rb2, alpha, st.Rb2);
     if (clamped) return;
-    a.o = __builtin_fmaf(dalpha, G, a.o);
-    const float dpow = dalpha * alpha;
     if (E1) {
-        // the per-pixel positional gradient is needed for its norm
-        const float ca = -2.0f * q.hca, cbq = -q.nb, cc = -2.0f * q.hcc;
+        const float dalpha = st.T * dot;
+        a.o = __builtin_fmaf(dalpha, G, a.o);
+        const float dpow = dalpha * alpha;
+        // the per-pixel positional gradient is needed for its norm (natural-log conic terms)
+        const float ca = (-2.0f * kLn2) * q.hca, cbq = -kLn2 * q.nb, cc = (-2.0f * kLn2) * q.hcc;
         const float gx = dpow * (ca * dx + cbq * dy);
         const float gy = dpow * (cbq * dx + cc * dy);
         a.mx += gx;
@@ -261,8 +263,9 @@ __device__ __forceinline__ void unblend_pixel(BwdPix& st, BwdSum& a, const RecS&
         const float nx = gx * half_w, ny = gy * half_h;
         a.e1 += sqrtf(nx * nx + ny * ny);
     } else {
+        const float dpow = w * dot;
         const float dpy = dpow * dy;
-        a.s0 += dpow;
+        a.o += dpow;
         a.s1 += dpy;
         a.s2 = __builtin_fmaf(dpy, dy, a.s2);
     }
@@ -327,21 +330,24 @@ template <bool E1, int PPL>
 __device__ __forceinline__ void unblend_step(BwdPix (&st)[PPL], const RecS& q, uint32_t r, uint32_t pos, float px,
                                              float half_w, float half_h, int lane, uint32_t bperm32,
                                              float* __restrict__ acc) {
-    BwdSum a{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false};
+    BwdSum a{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false};
     const PowerX t = power_x(px, q.mx, q.hca, q.nb);
 #pragma unroll
     for (int k = 0; k < PPL; ++k) unblend_pixel<E1>(st[k], a, q, pos, t, half_w, half_h);
     if (ballot64(a.contrib) == 0) return;
     if (!E1) {
         // sum over the lane's pixels of dpow (ca dx + cb dy, cb dx + cc dy) and -dpow (dx^2 / 2,
-        // dx dy, dy^2 / 2), with ca = -2 hca, cb = -nb, cc = -2 hcc
+        // dx dy, dy^2 / 2), with ca = -2 hca, cb = -nb, cc = -2 hcc in natural-log units (the
+        // record's base-2 terms times ln 2)
         const float dx = t.dx;
-        const float cadx = -2.0f * q.hca * dx, cbdx = -q.nb * dx;
-        a.mx = __builtin_fmaf(cadx, a.s0, -q.nb * a.s1);
-        a.my = __builtin_fmaf(cbdx, a.s0, -2.0f * q.hcc * a.s1);
-        a.ca = -0.5f * dx * dx * a.s0;
-        a.cb = -dx * a.s1;
-        a.cc = -0.5f * a.s2;
+        const float s0 = a.o, s1 = a.s1, s2 = a.s2;
+        a.o = s0 * __builtin_amdgcn_rcpf(q.o);
+        const float ca = (-2.0f * kLn2) * q.hca, cb = -kLn2 * q.nb, cc = (-2.0f * kLn2) * q.hcc;
+        a.mx = __builtin_fmaf(ca * dx, s0, cb * s1);
+        a.my = __builtin_fmaf(cb * dx, s0, cc * s1);
+        a.ca = -0.5f * dx * dx * s0;
+        a.cb = -dx * s1;
+        a.cc = -0.5f * s2;
     }
     const float v[10] = {a.mx, a.my, a.ca, a.cb, a.cc, a.o, a.r, a.g, a.b, E1 ? a.e1 : 0.0f};
     int k;

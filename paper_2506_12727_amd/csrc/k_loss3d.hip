@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(256) k_points3d(const DevCam* __restrict__ cam
 // without a point keeps only itself, a neighbour without a point has no weight.
 constexpr int kT = 16, kHalo = kT + 2 * kWin, kHN = kHalo * kHalo;
 constexpr float kNoPoint = -1.0f, kOutside = -2.0f;
-constexpr double kLog2e = 1.4426950408889634;
+constexpr double kLog2eD = 1.4426950408889634;
 
 struct HaloPoints {
     double px[kHN], py[kHN], pz[kHN];
@@ -79,7 +79,7 @@ __device__ __forceinline__ void stage_points(const double4* __restrict__ pts, in
         float k = kOutside;
         if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
             p = pts[(size_t)gy * W + gx];
-            k = p.w > 0.0 ? (float)(kLog2e / (2.0 * p.w * p.w)) : kNoPoint;
+            k = p.w > 0.0 ? (float)(kLog2eD / (2.0 * p.w * p.w)) : kNoPoint;
         }
         h.px[i] = p.x;
         h.py[i] = p.y;

@@ -48,13 +48,17 @@ __device__ __forceinline__ int find_view(const DevCam* __restrict__ cams, int B,
     return lo;
 }
 
-// Blend record of one participating (view, Gaussian): 64 bytes, four dwordx4.
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+// Blend record of one participating (view, Gaussian): 64 bytes, four dwordx4. The exponent is
+// held in base 2 (every term times log2 e), so that a pixel's weight is one exp2 of its power.
 struct alignas(16) BlendRec {
     uint32_t boxx;   // x0 | x1 << 16 (inclusive pixel box)
     uint32_t boxy;   // y0 | y1 << 16
     float mx, my;    // projected mean (pixels)
-    float hca, nb, hcc, o;   // -0.5*conic_xx, -conic_xy, -0.5*conic_yy, opacity
-    float cut, hi, r, g;     // cut threshold, clamp threshold, colour
+    float hca, nb, hcc, o;   // log2 e times (-0.5*conic_xx, -conic_xy, -0.5*conic_yy); opacity
+    float cut, hi, r, g;     // cut and clamp thresholds on that base-2 power; colour
     float b;
     uint32_t gid;    // Gaussian index
     uint32_t view;
