@@ -308,15 +308,17 @@ typedef struct {
     int clamp_bits;
 } pix_g;
 
-/* Decision margins. The kernel decides the cut and clamp tests from a single-precision power and
- * single-precision thresholds, and the stop test on its single-precision transmittance. The
- * oracle decides in double and flags a pixel where a decision it takes lies within the kernel's
- * possible error of the threshold:
+/* Decision margins. The kernel decides the cut test from a single-precision power and threshold
+ * (both may carry one more rounding from a change of the logarithm's base), the clamp from the
+ * single-precision product o exp(power) against 0.99, and the stop test on its single-precision
+ * transmittance. The oracle decides in double and flags a pixel where a decision it takes lies
+ * within the kernel's possible error of the threshold:
  *   power:      POW_REL * (|a dx^2|/2 + |b dx dy| + |c dy^2|/2), i.e. 16 single-precision
  *               roundings of the power's terms (an evaluation in any order of its ~8 operations
  *               rounds each term at most ~6 times), plus POW_LN where the threshold is a
  *               logarithm (twice the error of the kernel's single-precision logarithm, which is
- *               within 2e-6 of ln; the cut -4.5 itself is exact);
+ *               within 2e-6 of ln; the cut -4.5 itself is exact) and for the clamp (an
+ *               exponential and a product in single precision: a few 1e-7 of power);
  *   double mode: plus the power's change between the double and the single-precision projected
  *               geometry at this pixel (the kernel's power is within the first margin of the
  *               power of its single-precision geometry, which is within this change of the

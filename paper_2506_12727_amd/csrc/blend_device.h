@@ -24,14 +24,14 @@ __device__ __forceinline__ float weight_of(float power2) { return __builtin_amdg
 
 // Wavefront-uniform copy of the fields the walks use.
 struct RecS {
-    float mx, my, hca, nb, hcc, o, cut, hi, r, g, b, z;
+    float mx, my, hca, nb, hcc, o, cut, r, g, b, z;
 };
 
 __device__ __forceinline__ RecS load_rec(const BlendRec* __restrict__ recs, uint32_t r) {
     const BlendRec* R = recs + r;
     RecS s;
     s.mx = R->mx; s.my = R->my; s.hca = R->hca; s.nb = R->nb; s.hcc = R->hcc; s.o = R->o;
-    s.cut = R->cut; s.hi = R->hi; s.r = R->r; s.g = R->g; s.b = R->b;
+    s.cut = R->cut; s.r = R->r; s.g = R->g; s.b = R->b;
     s.z = __uint_as_float(R->depth_bits);
     return s;
 }
@@ -183,7 +183,7 @@ __device__ __forceinline__ void blend_step(FwdPix& st, const RecS& q, const Powe
     if (!pix_live(st)) return;
     const float power = power_y(t, py, q.my, q.hcc);
     if (power >= q.cut) {
-        const float alpha = (power > q.hi) ? kAlphaMax : q.o * weight_of(power);
+        const float alpha = fminf(q.o * weight_of(power), kAlphaMax);
         const float Tn = __builtin_fmaf(-st.T, alpha, st.T);
         if (Tn < kTStop) {
             st.T = -st.T;
@@ -233,9 +233,10 @@ __device__ __forceinline__ void unblend_pixel(BwdPix& st, BwdSum& a, const RecS&
     const float power = power_dy(t, dy, q.hcc);
     if (!(power >= q.cut)) return;
     a.contrib = true;
-    const bool clamped = power > q.hi;
     const float G = weight_of(power);
-    const float alpha = clamped ? kAlphaMax : q.o * G;
+    const float oG = q.o * G;
+    const bool clamped = oG > kAlphaMax;   // the forward's min(o G, kAlphaMax), decided alike
+    const float alpha = clamped ? kAlphaMax : oG;
     st.T = st.T * __builtin_amdgcn_rcpf(1.0f - alpha);   // transmittance in front of this Gaussian
     const float w = alpha * st.T;
     a.r = __builtin_fmaf(st.dC0, w, a.r);

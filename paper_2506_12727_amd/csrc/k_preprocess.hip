@@ -194,7 +194,7 @@ __device__ __forceinline__ BlendRec make_record(const ProjOut& p, const float (&
     r.boxy = (uint32_t)p.y0 | ((uint32_t)p.y1 << 16);
     r.mx = p.mx; r.my = p.my;
     r.hca = p.hca * kLog2e; r.nb = p.nb * kLog2e; r.hcc = p.hcc * kLog2e; r.o = o;
-    r.cut = p.cut * kLog2e; r.hi = p.hi * kLog2e; r.r = rgb[0]; r.g = rgb[1];
+    r.cut = p.cut * kLog2e; r.unused = 0.0f; r.r = rgb[0]; r.g = rgb[1];
     r.b = rgb[2];
     r.gid = g;
     r.view = v;

@@ -58,7 +58,7 @@ struct alignas(16) BlendRec {
     uint32_t boxy;   // y0 | y1 << 16
     float mx, my;    // projected mean (pixels)
     float hca, nb, hcc, o;   // log2 e times (-0.5*conic_xx, -conic_xy, -0.5*conic_yy); opacity
-    float cut, hi, r, g;     // cut and clamp thresholds on that base-2 power; colour
+    float cut, unused, r, g; // cut threshold on that base-2 power (the clamp is min(o G, 0.99)); colour
     float b;
     uint32_t gid;    // Gaussian index
     uint32_t view;
@@ -111,12 +111,12 @@ struct ProjState {
 struct ProjOut {
     bool ok;
     float mx, my, depth;
-    float hca, nb, hcc, cut, hi;
+    float hca, nb, hcc, cut;
     int32_t x0, x1, y0, y1;
 };
 
 // The view-independent part of the projection (paper Sec. 3): normalised quaternion, its
-// rotation, Sigma = R S S^T R^T, and the cut and clamp thresholds of the opacity. Computed once
+// rotation, Sigma = R S S^T R^T, and the cut threshold of the opacity. Computed once
 // per Gaussian; project() below then works view by view. The operations are those of the fixed
 // order described at the top of this file, only not repeated per view.
 struct GaussGeom {
@@ -124,7 +124,7 @@ struct GaussGeom {
     float qw, qx, qy, qz, qinv;
     float rot[9];
     float S[6];                       // Sigma: xx xy xz yy yz zz
-    float cut, hi;
+    float cut;
 };
 
 __device__ __forceinline__ void gauss_geom(const float s[3], const float q[4], float o, GaussGeom& g) {
@@ -160,7 +160,6 @@ __device__ __forceinline__ void gauss_geom(const float s[3], const float q[4], f
     g.S[5] = __builtin_fmaf(M[6], M[6], __builtin_fmaf(M[7], M[7], M[8] * M[8]));
     const float lc = -ln_threshold(kAlphaMin * o);
     g.cut = (lc > kPowerFloor) ? lc : kPowerFloor;
-    g.hi = ln_threshold(kAlphaMax / o);
 }
 
 // EWA projection of one Gaussian (its view-independent part in g) into one camera (paper Sec. 3),
@@ -222,7 +221,6 @@ __device__ __forceinline__ ProjOut project(const float mu[3], const GaussGeom& g
     out.hcc = -0.5f * cc;
 
     out.cut = g.cut;
-    out.hi = g.hi;
 
     // footprint: per-axis half-extents of the cut ellipse {d : -0.5 d^T conic d >= cut},
     // sqrt(-2 cut Sigma'_xx) and sqrt(-2 cut Sigma'_yy), in whole pixels
