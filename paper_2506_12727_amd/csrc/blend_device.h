@@ -225,10 +225,12 @@ struct BwdSum {
     bool contrib;
 };
 
-template <bool E1>
+// CHECK = false: the caller knows pos < st.last for every pixel that can contribute (a pixel
+// without contributors holds T = 0 and dC = 0, so it adds nothing).
+template <bool E1, bool CHECK>
 __device__ __forceinline__ void unblend_pixel(BwdPix& st, BwdSum& a, const RecS& q, uint32_t pos, const PowerX& t,
                                               float half_w, float half_h) {
-    if (pos >= st.last) return;
+    if (CHECK && pos >= st.last) return;
     const float dx = t.dx, dy = st.py - q.my;
     const float power = power_dy(t, dy, q.hcc);
     if (!(power >= q.cut)) return;
@@ -327,14 +329,14 @@ __device__ __forceinline__ float wave_sum10(const float (&v)[10], int lane, uint
 
 // One Gaussian of the reverse walk for all of this lane's pixels, summed over the wavefront and
 // added to the record's accumulators with one atomic instruction.
-template <bool E1, int PPL>
+template <bool E1, int PPL, bool CHECK>
 __device__ __forceinline__ void unblend_step(BwdPix (&st)[PPL], const RecS& q, uint32_t r, uint32_t pos, float px,
                                              float half_w, float half_h, int lane, uint32_t bperm32,
                                              float* __restrict__ acc) {
     BwdSum a{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false};
     const PowerX t = power_x(px, q.mx, q.hca, q.nb);
 #pragma unroll
-    for (int k = 0; k < PPL; ++k) unblend_pixel<E1>(st[k], a, q, pos, t, half_w, half_h);
+    for (int k = 0; k < PPL; ++k) unblend_pixel<E1, CHECK>(st[k], a, q, pos, t, half_w, half_h);
     if (ballot64(a.contrib) == 0) return;
     if (!E1) {
         // sum over the lane's pixels of dpow (ca dx + cb dy, cb dx + cc dy) and -dpow (dx^2 / 2,
@@ -409,13 +411,47 @@ __device__ __forceinline__ void walk_forward(FwdPix (&st)[PPL], float px, const 
     }
 }
 
+// The surviving candidates m of one window (list positions base + j), highest position first, up
+// to four records per round trip through the scalar cache.
+template <bool E1, int PPL, bool CHECK>
+__device__ __forceinline__ void unblend_window(BwdPix (&st)[PPL], float px, uint64_t m, uint32_t rl, uint32_t base,
+                                               const BlendRec* __restrict__ recs, int lane, uint32_t bperm32,
+                                               float half_w, float half_h, float* __restrict__ acc) {
+    while (m) {
+        const int j0 = 63 - __builtin_clzll(m);
+        m &= ~(1ull << j0);
+        const int j1 = m ? 63 - __builtin_clzll(m) : j0;
+        if (m) m &= ~(1ull << j1);
+        const bool h1 = j1 != j0;
+        const int j2 = m ? 63 - __builtin_clzll(m) : j0;
+        if (m) m &= ~(1ull << j2);
+        const bool h2 = j2 != j0;
+        const int j3 = m ? 63 - __builtin_clzll(m) : j0;
+        if (m) m &= ~(1ull << j3);
+        const bool h3 = j3 != j0;
+        const uint32_t r0 = readlane_u32(rl, j0), r1 = readlane_u32(rl, j1);
+        const uint32_t r2 = readlane_u32(rl, j2), r3 = readlane_u32(rl, j3);
+        const RecS q0 = load_rec(recs, r0);
+        const RecS q1 = load_rec(recs, r1);
+        const RecS q2 = load_rec(recs, r2);
+        const RecS q3 = load_rec(recs, r3);
+        unblend_step<E1, PPL, CHECK>(st, q0, r0, base + (uint32_t)j0, px, half_w, half_h, lane, bperm32, acc);
+        if (h1) unblend_step<E1, PPL, CHECK>(st, q1, r1, base + (uint32_t)j1, px, half_w, half_h, lane, bperm32, acc);
+        if (h2) unblend_step<E1, PPL, CHECK>(st, q2, r2, base + (uint32_t)j2, px, half_w, half_h, lane, bperm32, acc);
+        if (h3) unblend_step<E1, PPL, CHECK>(st, q3, r3, base + (uint32_t)j3, px, half_w, half_h, lane, bperm32, acc);
+    }
+}
+
 // Reverse walk of one wavefront from list position hi_end down to rg.x (Eq. 1 differentiated):
 // per Gaussian, the lanes' contributions are summed over the wavefront and added to the record's
 // accumulators with one atomic instruction. SW > 0: the lanes' pixels form an SW-wide sub-tile
 // (see active_rect) and each window of candidates is culled against the pixels whose last
 // contributor lies above it; SW = 0: against the fixed rectangle [sx0, sx1] x [sy0, sy1].
+// lo_end: every pixel of the wavefront either has its last contributor at or above lo_end or
+// has none (and then T = 0, dC = 0); without E1, windows below it skip the per-pixel position
+// test. 0 keeps the test everywhere.
 template <bool E1, int PPL, int SW = 0>
-__device__ __forceinline__ void walk_backward(BwdPix (&st)[PPL], float px, uint32_t hi_end, uint2 rg,
+__device__ __forceinline__ void walk_backward(BwdPix (&st)[PPL], float px, uint32_t hi_end, uint32_t lo_end, uint2 rg,
                                               const uint32_t* __restrict__ vals, const BlendRec* __restrict__ recs,
                                               int lane, int sx0, int sx1, int sy0, int sy1, float half_w,
                                               float half_h, float* __restrict__ acc) {
@@ -439,32 +475,12 @@ __device__ __forceinline__ void walk_backward(BwdPix (&st)[PPL], float px, uint3
             active_rect<PPL, SW>(am, sx0, sy0, ax0, ax1, ay0, ay1);
         }
         uint32_t rl;
-        uint64_t m = window_mask(vals, recs, base, top, lane, ax0, ax1, ay0, ay1, rl);
+        const uint64_t m = window_mask(vals, recs, base, top, lane, ax0, ax1, ay0, ay1, rl);
+        if (!E1 && top <= lo_end)   // with E1 the second copy of the loop costs occupancy
+            unblend_window<E1, PPL, false>(st, px, m, rl, base, recs, lane, bperm32, half_w, half_h, acc);
+        else
+            unblend_window<E1, PPL, true>(st, px, m, rl, base, recs, lane, bperm32, half_w, half_h, acc);
         top = base;
-        while (m) {
-            // highest list position first; up to four records per round trip
-            const int j0 = 63 - __builtin_clzll(m);
-            m &= ~(1ull << j0);
-            const int j1 = m ? 63 - __builtin_clzll(m) : j0;
-            if (m) m &= ~(1ull << j1);
-            const bool h1 = j1 != j0;
-            const int j2 = m ? 63 - __builtin_clzll(m) : j0;
-            if (m) m &= ~(1ull << j2);
-            const bool h2 = j2 != j0;
-            const int j3 = m ? 63 - __builtin_clzll(m) : j0;
-            if (m) m &= ~(1ull << j3);
-            const bool h3 = j3 != j0;
-            const uint32_t r0 = readlane_u32(rl, j0), r1 = readlane_u32(rl, j1);
-            const uint32_t r2 = readlane_u32(rl, j2), r3 = readlane_u32(rl, j3);
-            const RecS q0 = load_rec(recs, r0);
-            const RecS q1 = load_rec(recs, r1);
-            const RecS q2 = load_rec(recs, r2);
-            const RecS q3 = load_rec(recs, r3);
-            unblend_step<E1, PPL>(st, q0, r0, base + (uint32_t)j0, px, half_w, half_h, lane, bperm32, acc);
-            if (h1) unblend_step<E1, PPL>(st, q1, r1, base + (uint32_t)j1, px, half_w, half_h, lane, bperm32, acc);
-            if (h2) unblend_step<E1, PPL>(st, q2, r2, base + (uint32_t)j2, px, half_w, half_h, lane, bperm32, acc);
-            if (h3) unblend_step<E1, PPL>(st, q3, r3, base + (uint32_t)j3, px, half_w, half_h, lane, bperm32, acc);
-        }
     }
 }
 

@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_bwd(const DevCam* __res
     const size_t hw = (size_t)c.W * c.H;
     const float* g = dl_dimg[wt.v];
     BwdPix st[PPL];
-    uint32_t lane_last = 0;
+    uint32_t lane_last = 0, lane_first = ~0u;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int y = wt.sy0 + (lane / ST::SW) + ST::ROWS * k;
@@ -203,10 +203,14 @@ __global__ void __launch_bounds__(TW * TH / PPL) k_blend_bwd(const DevCam* __res
             st[k].last = n_last[c.pix_base + pix];
             lane_last = max(lane_last, st[k].last);
         }
+        // a pixel without contributors is made inert, so the walk may skip its position test
+        if (st[k].last == 0u) st[k].T = st[k].dC0 = st[k].dC1 = st[k].dC2 = 0.0f;
+        lane_first = min(lane_first, st[k].last == 0u ? ~0u : st[k].last);
     }
     const uint32_t hi_end = __builtin_amdgcn_readfirstlane(wave_max_u32(lane_last));
-    walk_backward<E1, PPL, ST::SW>(st, px, hi_end, wt.rg, vals, recs, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1, half_w, half_h,
-                           acc);
+    const uint32_t lo_end = __builtin_amdgcn_readfirstlane(~wave_max_u32(~lane_first));
+    walk_backward<E1, PPL, ST::SW>(st, px, hi_end, lo_end, wt.rg, vals, recs, lane, wt.sx0, wt.sx1, wt.sy0, wt.sy1,
+                                   half_w, half_h, acc);
 }
 
 // Work of a frame's walks, one thread per pixel: out[0] += list entries from the start of the pixel's

@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(64) k_blend_bwd_sel(const DevCam* __restrict__
         st[0].last = last_sel[w.i];
     }
     const uint32_t hi_end = __builtin_amdgcn_readfirstlane(wave_max_u32(st[0].last));
-    walk_backward<E1, 1>(st, px, hi_end, w.rg, vals, recs, lane, w.bx0, w.bx1, w.by0, w.by1, 0.5f * (float)c.W,
+    walk_backward<E1, 1>(st, px, hi_end, 0u, w.rg, vals, recs, lane, w.bx0, w.bx1, w.by0, w.by1, 0.5f * (float)c.W,
                          0.5f * (float)c.H, acc);
 }
 
