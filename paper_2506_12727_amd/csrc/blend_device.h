@@ -176,13 +176,12 @@ struct FwdPix {
 
 __device__ __forceinline__ bool pix_live(const FwdPix& st) { return st.T > 0.0f; }
 
-// One Gaussian of Eq. 1 for one pixel (skipped when the pixel has stopped or the cut test fails;
-// the branches cost less than computing every step for every lane).
+// One Gaussian of Eq. 1 for one pixel (skipped when the pixel has stopped or the cut test fails:
+// the power is computed for every lane and both tests share one branch).
 template <bool DEPTH>
 __device__ __forceinline__ void blend_step(FwdPix& st, const RecS& q, const PowerX& t, float py, uint32_t pos) {
-    if (!pix_live(st)) return;
     const float power = power_y(t, py, q.my, q.hcc);
-    if (power >= q.cut) {
+    if (pix_live(st) & (power >= q.cut)) {
         const float alpha = fminf(q.o * weight_of(power), kAlphaMax);
         const float Tn = __builtin_fmaf(-st.T, alpha, st.T);
         if (Tn < kTStop) {
@@ -230,10 +229,9 @@ struct BwdSum {
 template <bool E1, bool CHECK>
 __device__ __forceinline__ void unblend_pixel(BwdPix& st, BwdSum& a, const RecS& q, uint32_t pos, const PowerX& t,
                                               float half_w, float half_h) {
-    if (CHECK && pos >= st.last) return;
     const float dx = t.dx, dy = st.py - q.my;
     const float power = power_dy(t, dy, q.hcc);
-    if (!(power >= q.cut)) return;
+    if (!((!CHECK | (pos < st.last)) & (power >= q.cut))) return;   // one branch for both tests
     a.contrib = true;
     const float G = weight_of(power);
     const float oG = q.o * G;
